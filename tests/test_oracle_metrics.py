@@ -1,0 +1,45 @@
+"""Pins for the accuracy measures (Sec. 5.5)."""
+import numpy as np
+import pytest
+
+from conftest import golden_path
+from oracle import metrics as M
+
+
+def _risk_rows():
+    rows = []
+    for line in open(golden_path("resampling_risk.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        a, b, r = [p.strip() for p in line.split("|")]
+        rows.append((int(a), int(b), float(r)))
+    return rows
+
+
+@pytest.mark.parametrize("v1,v2,printed", _risk_rows())
+def test_resampling_risk_reproduces_printed_values(v1, v2, printed):
+    vc = min(v1, v2)  # nested rejection sets
+    assert round(100 * M.resampling_risk(v1, v2, vc), 2) == printed
+
+
+def test_risk_disjoint_and_equal():
+    assert M.resampling_risk(10, 10, 10) == 0.0
+    assert M.resampling_risk(10, 5, 0) == 1.0
+
+
+def test_kl_self_zero_and_positive():
+    rng = np.random.default_rng(0)
+    a = rng.normal(size=5000)
+    assert M.kl_divergence(a, a) == 0.0
+    assert M.kl_divergence(a, a + 0.5) > 0.05
+
+
+def test_threshold_order_statistic():
+    m = np.arange(1, 101, dtype=float)[::-1]  # 100 .. 1
+    # alpha = 0.05, L = 100: m_(100 - 5) = 95
+    assert M.threshold(m, 0.05) == 95.0
+    assert M.threshold(m, 0.0) == 100.0
+    p = M.corrected_pvalue(m, np.array([95.0, 95.5, 100.0, 0.0]))
+    np.testing.assert_allclose(p, [0.06, 0.05, 0.01, 1.0])
+    rej = M.rejected(m, np.array([95.0, 95.5, 101.0]), 0.05)
+    assert list(rej) == [False, True, True]
