@@ -1,0 +1,240 @@
+/*
+ * rpt.h -- C ABI of librpt: RapidPT permutation testing on MI355X (gfx950).
+ *
+ * The library computes the voxel-wise maximum null distribution of a
+ * two-sample permutation test, either exactly (NaivePT, Alg. 1 of
+ * Gutierrez-Barragan et al., "Accelerating Permutation Testing in Voxel-wise
+ * Analysis through Subspace Tracking") or by RapidPT (Alg. 2): a low-rank
+ * basis U of the permutation testing matrix T is learnt from l fully computed
+ * columns by subspace tracking on sub-sampled entries, and every further
+ * column is completed from ceil(eta v) sampled t statistics, a residual
+ * noise draw and a maximum -- without ever forming T.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Every array argument is DEVICE memory owned by the caller.  The library
+ *   never allocates, frees, or reads device memory on the host; scratch space
+ *   comes from the caller's workspace `ws` of at least the size returned by
+ *   the matching *_workspace() query (256-byte aligned).
+ * - Work is enqueued on `stream` (a hipStream_t; NULL = the default stream)
+ *   and is asynchronous: outputs are valid after the stream is synchronised.
+ *   No entry point synchronises, so every call can be captured in a HIP graph.
+ * - Arguments are validated synchronously; violations return an error code
+ *   and enqueue nothing.  Numeric failures that can only be seen on the device
+ *   (a sampled Gram matrix that is not positive definite) are reported
+ *   LAPACK-style in a caller-provided `info` array.
+ * - Data layout: X is v x n row-major (row k = voxel k, column j = subject j)
+ *   with leading dimension ldx >= n, FP32.  Columns 0..n1-1 of X are the
+ *   observed group 1 (X = [X^1 X^2], Alg. 1).  Relabellings are L x n uint8
+ *   rows with exactly n1 entries equal to 1 (= group 1) and the rest 0.
+ *   T is logically L x v (row i = the t map of relabelling i).
+ * - The t statistic is Eq. 2 with sigma_g read as the unbiased group variance
+ *   (Welch form; equal to the pooled Student t when n1 = n2), positive when
+ *   group 1 has the larger mean.  Voxels with zero spread give t = 0.
+ * - Thread safety: calls are independent except through their arguments; two
+ *   calls may run concurrently on different streams with distinct workspaces.
+ */
+#ifndef RPT_H
+#define RPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  RPT_OK = 0,
+  RPT_ERR_INVALID_ARG = -1,     /* a size, pointer or enum is out of range  */
+  RPT_ERR_UNDERDETERMINED = -2, /* sampled set smaller than the rank r      */
+  RPT_ERR_NOT_SPD = -3,         /* (device info code) Gram not positive def. */
+  RPT_ERR_WORKSPACE = -4,       /* ws NULL, misaligned or too small         */
+  RPT_ERR_HIP = -5,             /* a HIP launch failed; see rpt_last_hip_error */
+  RPT_ERR_UNSUPPORTED = -6      /* valid request this build does not handle  */
+} rpt_status;
+
+/* Arithmetic of the dense contractions (indicator GEMM of NaivePT and the
+ * training columns). */
+typedef enum {
+  RPT_FP32 = 0,       /* FP32 MFMA on FP32 data                               */
+  RPT_SPLIT_BF16 = 1  /* data split x = hi + lo into two BF16 halves, both    */
+                      /* multiplied by the exact 0/1 indicator, FP32 accumulate */
+} rpt_precision;
+
+typedef enum {
+  RPT_TAIL_SIGNED = 0, /* m_i = max_k t_ik            (Alg. 1)               */
+  RPT_TAIL_ABS = 1     /* m_i = max_k |t_ik|          (two-sided testing)     */
+} rpt_tail;
+
+typedef enum {
+  RPT_MU_MEAN_GAP = 0, /* mu = mean_i [max T_ex[:,i] - max(U w_i + s_i)]       */
+  RPT_MU_LITERAL = 1,  /* mu = sup_i max(T_ex[:,i] - U W_ex[:,i])  (Alg. 2)    */
+  RPT_MU_ZERO = 2
+} rpt_mu_rule;
+
+/* Noise streams of the counter-based generator (Philox4x32-10 + Box-Muller):
+ * z(seed, stream, i, k) uses key (seed mod 2^32, seed >> 32) and counter
+ * (k >> 2, i, stream, study); words 0,1 give voxels 4q, 4q+1 (cos, sin), words
+ * 2,3 give 4q+2, 4q+3.  Each word x maps to u = ((x >> 8) + 0.5) 2^-24. */
+#define RPT_STREAM_RECOVERY 2
+#define RPT_STREAM_TRAINING 4
+
+const char* rpt_status_string(int status);
+/* The last HIP error code seen by a call that returned RPT_ERR_HIP (per thread). */
+int rpt_last_hip_error(void);
+/* Library version, major*10000 + minor*100 + patch. */
+int rpt_version(void);
+
+/* -------------------------------------------------------------------------
+ * NaivePT -- Alg. 1 (Sec. 2.1).
+ *
+ * For each of the L relabellings, computes the t statistic at all v voxels and
+ * writes its maximum to max_out[i] (signed or absolute, `tail`).  Group sums
+ * are formed as a GEMM of the per-voxel standardised data with the 0/1
+ * relabelling indicator on the matrix cores (`prec`).
+ *
+ *   X        v x n FP32, leading dimension ldx >= n            (in)
+ *   labels   L x n uint8 relabellings, exactly n1 ones per row (in)
+ *   max_out  L FP32                                            (out)
+ *   T_out    NULL, or L x v FP32: the full permutation testing matrix,
+ *            row i = t map of relabelling i (for tests and training)   (out)
+ * Requirements: v >= 1, 4 <= n <= 1024, 2 <= n1 <= n-2, L >= 0.
+ * n1 != n - n1 (unbalanced designs) needs prec == RPT_FP32.
+ * ------------------------------------------------------------------------- */
+size_t rpt_naive_workspace(int64_t v, int32_t n, int64_t L, int prec);
+rpt_status rpt_naive_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
+                             const uint8_t* labels, int64_t L, int tail, int prec,
+                             float* max_out, float* T_out,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Sampled t statistics -- the test() step of RapidPT recovery (Alg. 2).
+ *
+ * y[i*k + q] = t statistic of voxel omega[i*k + q] under relabelling i.
+ *   omega  L x k int32 voxel indices in [0, v), k >= 1      (in)
+ *   y      L x k FP32                                       (out)
+ * ------------------------------------------------------------------------- */
+size_t rpt_sampled_tstat_workspace(int64_t v, int32_t n);
+rpt_status rpt_sampled_tstat(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
+                             const uint8_t* labels, int64_t L,
+                             const int32_t* omega, int32_t k, float* y,
+                             void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Complete -- the masked least-squares fit of Alg. 2 (Sec. 4.2).
+ *
+ * For each column i: w_i = argmin_w || U[omega_i, :] w - y_i ||_2, solved from
+ * the normal equations (Gram matrix of the sampled basis rows, FP64 Cholesky).
+ *   U      v x r FP32 row-major (row k = voxel k)              (in)
+ *   omega  L x k int32, k >= r                                 (in)
+ *   y      L x k FP32 sampled values                           (in)
+ *   W      L x r FP32, row i = w_i                              (out)
+ *   resid  NULL or L x k FP32: y - U[omega] w                   (out)
+ *   info   L int32: 0 = ok, j > 0 = leading minor j not positive (out)
+ * Requirements: 1 <= r <= 128, r <= k.
+ * ------------------------------------------------------------------------- */
+size_t rpt_complete_workspace(int64_t L, int32_t r);
+rpt_status rpt_complete(const float* U, int64_t v, int32_t r,
+                        const int32_t* omega, int32_t k, const float* y, int64_t L,
+                        float* W, float* resid, int32_t* info,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Subspace training -- the TRAINING half of Alg. 2 (Sec. 4.1).
+ *
+ * 1. T_ex: the t maps of the l training relabellings (the same contraction as
+ *    NaivePT); train_max[i] = max_k T_ex[i, k] (exact maxima).
+ * 2. U <- orthonormalised U0 (Q factor with positive diagonal R).
+ * 3. `passes` passes over the l columns in mini-batches of `batch` columns:
+ *    each visit of column i in pass p samples omega_train[(p*l + i)*k ..+k),
+ *    fits w by Complete, forms the residual e on the sampled entries, and the
+ *    batch moves U by gamma * sum_i e_i w_i^T / |w_i|^2 (the first-order form
+ *    of GROUSE's greedy geodesic step) followed by re-orthonormalisation.
+ * 4. sigma = sample std (N-1) of the Complete residuals of every training
+ *    column on a fresh sampled set omega_sm (l x k); mu by `mu_rule`, with the
+ *    mean-gap rule drawing the noise on stream RPT_STREAM_TRAINING.
+ *
+ *   U0           v x r FP32 Gaussian (or any full-rank) start       (in)
+ *   omega_train  (passes*l) x k int32                               (in)
+ *   omega_sm     l x k int32                                        (in)
+ *   U_out        v x r FP32 orthonormal basis                       (out)
+ *   sigma_mu     2 FP32 on the device: {sigma, mu}                  (out)
+ *   train_max    l FP32                                             (out)
+ *   T_ex_out     NULL or l x v FP32                                 (out)
+ *   info         l int32 (Complete status of the last visit)        (out)
+ * Requirements: as NaivePT and Complete; balanced designs (n1 = n - n1);
+ * 1 <= batch <= l; gamma > 0.
+ * ------------------------------------------------------------------------- */
+size_t rpt_train_workspace(int64_t v, int32_t n, int32_t ell, int32_t r, int32_t k, int prec);
+rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
+                              const uint8_t* train_labels, int32_t ell,
+                              const float* U0, int32_t r,
+                              const int32_t* omega_train, int32_t k, int32_t passes,
+                              int32_t batch, float gamma,
+                              const int32_t* omega_sm, uint64_t seed, int mu_rule, int prec,
+                              float* U_out, float* sigma_mu, float* train_max, float* T_ex_out,
+                              int32_t* info, void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Recovery -- the RECOVERY half of Alg. 2 (Sec. 4.2).
+ *
+ * For each recovered column j (global column index col0 + j): t at the sampled
+ * voxels omega_j, w_j = Complete(U, omega_j, t), s ~ N^v(0, sigma^2) from the
+ * counter-based generator on stream RPT_STREAM_RECOVERY, and
+ *     max_out[j] = max_k ( (U w_j)_k + s_k ) + mu.
+ * U W is never written out: a BF16 matrix-core pass bounds every voxel's
+ * reconstructed value, and only voxels that can still attain the maximum
+ * (within the proven noise bound |z| < 5.8872 and the pass's error bound) are
+ * recomputed in FP32 with their noise draw.
+ *
+ *   U         v x r FP32 (orthonormal basis from training)          (in)
+ *   sigma_mu  2 FP32 on the device {sigma, mu}                      (in)
+ *   omega     L_rec x k int32                                       (in)
+ *   max_out   L_rec FP32                                            (out)
+ *   W_out     NULL or L_rec x r FP32 (the fitted coefficients)      (out)
+ *   info      L_rec int32 (as rpt_complete)                         (out)
+ * Requirements: balanced designs; 1 <= r <= 128; r <= k.
+ * ------------------------------------------------------------------------- */
+size_t rpt_recover_workspace(int64_t v, int32_t n, int64_t L_rec, int32_t r, int32_t k);
+rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
+                               const uint8_t* labels, int64_t L_rec, int64_t col0,
+                               const float* U, int32_t r, const float* sigma_mu,
+                               const int32_t* omega, int32_t k, uint64_t seed,
+                               float* max_out, float* W_out, int32_t* info,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Orthonormalisation used by training: U <- U R^{-1}, with R^T R = U^T U
+ * (Cholesky-QR, Gram and Cholesky in FP64, applied twice).  In place.
+ *   U  v x r FP32 (in/out).  Requirements: 1 <= r <= 128, v >= r.
+ * ------------------------------------------------------------------------- */
+size_t rpt_reorth_workspace(int64_t v, int32_t r);
+rpt_status rpt_reorth(float* U, int64_t v, int32_t r, int32_t* info,
+                      void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Masked completion loss of Eq. 1 and its gradient.
+ *
+ *   f = 1/2 sum_b sum_{k in Omega_b} (t_bk - U[k,:] W[:,b])^2
+ * Sampled sets are CSR: omega_ptr[B+1] (int64, omega_ptr[0] = 0), omega_idx
+ * [nnz] voxel indices (distinct within a row), t_vals[nnz].
+ *   U       v x r FP32 row-major        W   r x B FP32 row-major
+ *   loss    1 FP64 on the device (out)   resid  nnz FP32 = t - U W (out)
+ *   dU      v x r FP32, fully overwritten (zero outside sampled rows) (out)
+ *   dW      r x B FP32 (out)
+ * ------------------------------------------------------------------------- */
+rpt_status rpt_masked_loss_fwd(const float* U, int64_t v, int32_t r, const float* W, int32_t B,
+                               const int64_t* omega_ptr, const int32_t* omega_idx,
+                               const float* t_vals, int64_t nnz,
+                               double* loss, float* resid, void* stream);
+rpt_status rpt_masked_loss_bwd(const float* U, int64_t v, int32_t r, const float* W, int32_t B,
+                               const int64_t* omega_ptr, const int32_t* omega_idx,
+                               const float* resid, int64_t nnz,
+                               float* dU, float* dW, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RPT_H */

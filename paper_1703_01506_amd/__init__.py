@@ -1,0 +1,26 @@
+"""RapidPT permutation testing on MI355X (gfx950).
+
+The compute lives in librpt.so (hand-written HIP kernels behind a C ABI, see
+include/rpt.h); this package is a thin torch binding.  Importing it loads the
+library and fails loudly if it has not been built
+(``python paper_1703_01506_amd/build.py``).
+"""
+from . import _lib
+from .api import (  # noqa: F401
+    complete,
+    masked_loss_bwd,
+    masked_loss_fwd,
+    naive_maxnull,
+    rapidpt_maxnull,
+    recover_maxnull,
+    reorth,
+    sampled_tstat,
+    train_subspace,
+)
+
+_lib.load()
+
+__all__ = [
+    "naive_maxnull", "sampled_tstat", "complete", "reorth", "train_subspace", "recover_maxnull",
+    "rapidpt_maxnull", "masked_loss_fwd", "masked_loss_bwd",
+]

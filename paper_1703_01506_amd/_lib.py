@@ -1,0 +1,73 @@
+"""ctypes loader for librpt.so: symbol table and status handling only."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "librpt.so")
+
+_p = C.c_void_p
+_i32 = C.c_int32
+_i64 = C.c_int64
+_u64 = C.c_uint64
+_f32 = C.c_float
+_sz = C.c_size_t
+_int = C.c_int
+
+# name -> (restype, argtypes); mirrors include/rpt.h
+SIGNATURES = {
+    "rpt_status_string": (C.c_char_p, [_int]),
+    "rpt_last_hip_error": (_int, []),
+    "rpt_version": (_int, []),
+    "rpt_naive_workspace": (_sz, [_i64, _i32, _i64, _int]),
+    "rpt_naive_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _int, _int, _p, _p, _p, _sz, _p]),
+    "rpt_sampled_tstat_workspace": (_sz, [_i64, _i32]),
+    "rpt_sampled_tstat": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _p, _i32, _p, _p, _sz, _p]),
+    "rpt_complete_workspace": (_sz, [_i64, _i32]),
+    "rpt_complete": (_int, [_p, _i64, _i32, _p, _i32, _p, _i64, _p, _p, _p, _p, _sz, _p]),
+    "rpt_train_workspace": (_sz, [_i64, _i32, _i32, _i32, _i32, _int]),
+    "rpt_train_subspace": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i32, _p, _i32, _p, _i32, _i32, _i32, _f32,
+                                  _p, _u64, _int, _int, _p, _p, _p, _p, _p, _p, _sz, _p]),
+    "rpt_recover_workspace": (_sz, [_i64, _i32, _i64, _i32, _i32]),
+    "rpt_recover_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _i64, _p, _i32, _p, _p, _i32, _u64,
+                                   _p, _p, _p, _p, _sz, _p]),
+    "rpt_reorth_workspace": (_sz, [_i64, _i32]),
+    "rpt_reorth": (_int, [_p, _i64, _i32, _p, _p, _sz, _p]),
+    "rpt_masked_loss_fwd": (_int, [_p, _i64, _i32, _p, _i32, _p, _p, _p, _i64, _p, _p, _p]),
+    "rpt_masked_loss_bwd": (_int, [_p, _i64, _i32, _p, _i32, _p, _p, _p, _i64, _p, _p, _p]),
+}
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load librpt.so (once).  Raises if the library has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"librpt.so not found at {path}; build it with `python paper_1703_01506_amd/build.py`")
+    lib = C.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+class RPTError(RuntimeError):
+    def __init__(self, code: int, what: str):
+        lib = load()
+        msg = lib.rpt_status_string(code).decode()
+        if code == -5:
+            msg += f" (hipError {lib.rpt_last_hip_error()})"
+        super().__init__(f"{what}: {msg} [{code}]")
+        self.code = code
+
+
+def check(code: int, what: str) -> None:
+    if code != 0:
+        raise RPTError(code, what)

@@ -1,0 +1,220 @@
+"""Torch-facing wrappers of librpt's C ABI.
+
+Argument marshalling only: tensors must already live on the GPU; every step of
+the computation runs in librpt's HIP kernels on torch's current stream.  Scratch
+workspaces are allocated through torch's caching allocator and passed in.
+Functions raise RPTError (a RuntimeError) with the library's status string.
+"""
+from __future__ import annotations
+
+import torch
+
+from . import _lib
+
+PREC = {"fp32": 0, "split_bf16": 1}
+TAIL = {"signed": 0, "abs": 1}
+MU_RULE = {"mean_gap": 0, "literal": 1, "zero": 2}
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    # torch's allocator returns blocks aligned to at least 512 bytes
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)
+
+
+def _dev(t: torch.Tensor, dtype, name: str, ndim: int | None = None):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError(f"{name} must have {ndim} dimensions")
+    return t
+
+
+def _data(X: torch.Tensor):
+    _dev(X, torch.float32, "X", 2)
+    if X.stride(1) != 1:
+        raise ValueError("X must have unit stride along subjects")
+    return X.shape[0], X.shape[1], X.stride(0)
+
+
+def naive_maxnull(X: torch.Tensor, labels: torch.Tensor, n1: int | None = None, tail: str = "signed",
+                  prec: str = "split_bf16", return_T: bool = False):
+    """NaivePT (Alg. 1).  X (v, n) float32, labels (L, n) uint8 with n1 ones per
+    row.  Returns max (L,) float32, and T (L, v) if return_T."""
+    lib = _lib.load()
+    v, n, ldx = _data(X)
+    labels = _dev(labels, torch.uint8, "labels", 2).contiguous()
+    L = labels.shape[0]
+    if labels.shape[1] != n:
+        raise ValueError("labels must have n columns")
+    n1 = n // 2 if n1 is None else int(n1)
+    dev = X.device
+    out = torch.empty(L, dtype=torch.float32, device=dev)
+    T = torch.empty((L, v), dtype=torch.float32, device=dev) if return_T else None
+    nb = lib.rpt_naive_workspace(v, n, L, PREC[prec])
+    ws = _workspace(nb, dev)
+    rc = lib.rpt_naive_maxnull(_ptr(X), v, n, ldx, n1, _ptr(labels), L, TAIL[tail], PREC[prec],
+                               _ptr(out), _ptr(T), _ptr(ws), ws.numel(), _stream(dev))
+    _lib.check(rc, "rpt_naive_maxnull")
+    return (out, T) if return_T else out
+
+
+def sampled_tstat(X: torch.Tensor, labels: torch.Tensor, omega: torch.Tensor, n1: int | None = None):
+    """t statistics at sampled voxels: y[i, q] = t(voxel omega[i, q], labels[i])."""
+    lib = _lib.load()
+    v, n, ldx = _data(X)
+    labels = _dev(labels, torch.uint8, "labels", 2).contiguous()
+    omega = _dev(omega, torch.int32, "omega", 2).contiguous()
+    L, k = omega.shape
+    if labels.shape[0] != L:
+        raise ValueError("labels and omega must have the same number of rows")
+    n1 = n // 2 if n1 is None else int(n1)
+    y = torch.empty((L, k), dtype=torch.float32, device=X.device)
+    ws = _workspace(lib.rpt_sampled_tstat_workspace(v, n), X.device)
+    rc = lib.rpt_sampled_tstat(_ptr(X), v, n, ldx, n1, _ptr(labels), L, _ptr(omega), k, _ptr(y),
+                               _ptr(ws), ws.numel(), _stream(X.device))
+    _lib.check(rc, "rpt_sampled_tstat")
+    return y
+
+
+def complete(U: torch.Tensor, omega: torch.Tensor, y: torch.Tensor, return_resid: bool = False):
+    """Masked least squares per row: W[i] = argmin |U[omega[i]] w - y[i]|.
+    Returns (W (L, r), info (L,) int32[, resid (L, k)])."""
+    lib = _lib.load()
+    U = _dev(U, torch.float32, "U", 2).contiguous()
+    omega = _dev(omega, torch.int32, "omega", 2).contiguous()
+    y = _dev(y, torch.float32, "y", 2).contiguous()
+    v, r = U.shape
+    L, k = omega.shape
+    dev = U.device
+    W = torch.empty((L, r), dtype=torch.float32, device=dev)
+    info = torch.empty(L, dtype=torch.int32, device=dev)
+    resid = torch.empty((L, k), dtype=torch.float32, device=dev) if return_resid else None
+    ws = _workspace(lib.rpt_complete_workspace(L, r), dev)
+    rc = lib.rpt_complete(_ptr(U), v, r, _ptr(omega), k, _ptr(y), L, _ptr(W), _ptr(resid), _ptr(info),
+                          _ptr(ws), ws.numel(), _stream(dev))
+    _lib.check(rc, "rpt_complete")
+    return (W, info, resid) if return_resid else (W, info)
+
+
+def reorth(U: torch.Tensor):
+    """In-place orthonormalisation U <- U R^{-1} (Cholesky-QR2, FP64).  Returns info (1,)."""
+    lib = _lib.load()
+    U = _dev(U, torch.float32, "U", 2)
+    if not U.is_contiguous():
+        raise ValueError("U must be contiguous")
+    v, r = U.shape
+    info = torch.empty(1, dtype=torch.int32, device=U.device)
+    ws = _workspace(lib.rpt_reorth_workspace(v, r), U.device)
+    rc = lib.rpt_reorth(_ptr(U), v, r, _ptr(info), _ptr(ws), ws.numel(), _stream(U.device))
+    _lib.check(rc, "rpt_reorth")
+    return info
+
+
+def train_subspace(X, train_labels, U0, omega_train, omega_sm, passes: int, seed: int,
+                   batch: int | None = None, gamma: float = 1.0, mu_rule: str = "mean_gap",
+                   prec: str = "split_bf16", n1: int | None = None, return_T: bool = False):
+    """Training half of Alg. 2.  Returns a dict with U (v, r), sigma_mu (2,),
+    train_max (l,), info (l,) and optionally T_ex (l, v)."""
+    lib = _lib.load()
+    v, n, ldx = _data(X)
+    train_labels = _dev(train_labels, torch.uint8, "train_labels", 2).contiguous()
+    U0 = _dev(U0, torch.float32, "U0", 2).contiguous()
+    omega_train = _dev(omega_train, torch.int32, "omega_train", 2).contiguous()
+    omega_sm = _dev(omega_sm, torch.int32, "omega_sm", 2).contiguous()
+    ell = train_labels.shape[0]
+    r = U0.shape[1]
+    k = omega_sm.shape[1]
+    if omega_train.shape != (passes * ell, k) or omega_sm.shape[0] != ell or U0.shape[0] != v:
+        raise ValueError("inconsistent shapes")
+    batch = ell if batch is None else int(batch)
+    n1 = n // 2 if n1 is None else int(n1)
+    dev = X.device
+    U = torch.empty((v, r), dtype=torch.float32, device=dev)
+    sm = torch.empty(2, dtype=torch.float32, device=dev)
+    tmax = torch.empty(ell, dtype=torch.float32, device=dev)
+    info = torch.empty(ell, dtype=torch.int32, device=dev)
+    T = torch.empty((ell, v), dtype=torch.float32, device=dev) if return_T else None
+    ws = _workspace(lib.rpt_train_workspace(v, n, ell, r, k, PREC[prec]), dev)
+    rc = lib.rpt_train_subspace(_ptr(X), v, n, ldx, n1, _ptr(train_labels), ell, _ptr(U0), r,
+                                _ptr(omega_train), k, passes, batch, float(gamma), _ptr(omega_sm),
+                                int(seed), MU_RULE[mu_rule], PREC[prec], _ptr(U), _ptr(sm), _ptr(tmax),
+                                _ptr(T), _ptr(info), _ptr(ws), ws.numel(), _stream(dev))
+    _lib.check(rc, "rpt_train_subspace")
+    out = {"U": U, "sigma_mu": sm, "train_max": tmax, "info": info}
+    if return_T:
+        out["T_ex"] = T
+    return out
+
+
+def recover_maxnull(X, labels, U, sigma_mu, omega, seed: int, col0: int = 0, n1: int | None = None,
+                    return_W: bool = False):
+    """Recovery half of Alg. 2.  Returns (max (L,), info (L,)[, W (L, r)])."""
+    lib = _lib.load()
+    v, n, ldx = _data(X)
+    labels = _dev(labels, torch.uint8, "labels", 2).contiguous()
+    U = _dev(U, torch.float32, "U", 2).contiguous()
+    sigma_mu = _dev(sigma_mu, torch.float32, "sigma_mu", 1).contiguous()
+    omega = _dev(omega, torch.int32, "omega", 2).contiguous()
+    L, k = omega.shape
+    r = U.shape[1]
+    n1 = n // 2 if n1 is None else int(n1)
+    dev = X.device
+    out = torch.empty(L, dtype=torch.float32, device=dev)
+    info = torch.empty(L, dtype=torch.int32, device=dev)
+    W = torch.empty((L, r), dtype=torch.float32, device=dev) if return_W else None
+    ws = _workspace(lib.rpt_recover_workspace(v, n, L, r, k), dev)
+    rc = lib.rpt_recover_maxnull(_ptr(X), v, n, ldx, n1, _ptr(labels), L, int(col0), _ptr(U), r,
+                                 _ptr(sigma_mu), _ptr(omega), k, int(seed), _ptr(out), _ptr(W), _ptr(info),
+                                 _ptr(ws), ws.numel(), _stream(dev))
+    _lib.check(rc, "rpt_recover_maxnull")
+    return (out, info, W) if return_W else (out, info)
+
+
+def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omega_rec, passes: int, seed: int,
+                    batch: int | None = None, gamma: float = 1.0, mu_rule: str = "mean_gap",
+                    prec: str = "split_bf16"):
+    """Alg. 2 end to end: the l exact training maxima followed by the recovered
+    ones.  Returns (h (L,), train dict, recovery info)."""
+    tr = train_subspace(X, train_labels, U0, omega_train, omega_sm, passes, seed, batch, gamma, mu_rule, prec)
+    rec, info = recover_maxnull(X, rec_labels, tr["U"], tr["sigma_mu"], omega_rec, seed,
+                                col0=train_labels.shape[0])
+    return torch.cat([tr["train_max"], rec]), tr, info
+
+
+def masked_loss_fwd(U, W, omega_ptr, omega_idx, t_vals):
+    """f = 1/2 sum (t - U W)^2 over the CSR sampled entries.  Returns
+    (loss (1,) float64 on the device, resid (nnz,) float32)."""
+    lib = _lib.load()
+    v, r = U.shape
+    B = W.shape[1]
+    nnz = omega_idx.numel()
+    loss = torch.empty(1, dtype=torch.float64, device=U.device)
+    resid = torch.empty(nnz, dtype=torch.float32, device=U.device)
+    rc = lib.rpt_masked_loss_fwd(_ptr(U), v, r, _ptr(W), B, _ptr(omega_ptr), _ptr(omega_idx), _ptr(t_vals), nnz,
+                                 _ptr(loss), _ptr(resid), _stream(U.device))
+    _lib.check(rc, "rpt_masked_loss_fwd")
+    return loss, resid
+
+
+def masked_loss_bwd(U, W, omega_ptr, omega_idx, resid):
+    """Gradient of the masked loss: (dU (v, r), dW (r, B))."""
+    lib = _lib.load()
+    v, r = U.shape
+    B = W.shape[1]
+    nnz = omega_idx.numel()
+    dU = torch.empty_like(U)
+    dW = torch.empty_like(W)
+    rc = lib.rpt_masked_loss_bwd(_ptr(U), v, r, _ptr(W), B, _ptr(omega_ptr), _ptr(omega_idx), _ptr(resid), nnz,
+                                 _ptr(dU), _ptr(dW), _stream(U.device))
+    _lib.check(rc, "rpt_masked_loss_bwd")
+    return dU, dW

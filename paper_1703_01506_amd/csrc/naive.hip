@@ -1,0 +1,412 @@
+// K1 -- NaivePT (Alg. 1): group sums as a 0/1-indicator x X contraction on the
+// matrix cores, fused with the t epilogue and the column maximum.
+//
+// Output element (relabelling i, voxel k) of the contraction is
+//     a_ik = sum_j I[i, j] x_kj,     I[i, j] = 1 if subject j is in group 1.
+// Rows of the MFMA tile are relabellings (operand A = indicator, held in
+// registers for the whole workgroup lifetime), columns are voxels (operand B =
+// the prepared data, streamed from the K-blocked layout so that one wave's
+// fragment load is a single contiguous 1 KB block).  With the 32x32 MFMA
+// output layout each lane owns one voxel column, so the per-voxel epilogue
+// constants are per-lane scalars and the running maximum over voxels is kept
+// per accumulator register; one cross-lane reduction per workgroup finishes
+// it.
+//
+// Balanced designs (n1 = n/2): one contraction, epilogue u = a * rinv + c,
+// partial maxima of u, t = t(max u) in the finalize kernel (see prep.hip).
+// Unbalanced designs: a second contraction with the squared data gives the
+// group-1 sums of squares and the epilogue evaluates Eq. 2 per element.
+//
+// Split-BF16: x = hi + lo with hi = bf16(x), lo = bf16(x - hi).  Each K step
+// of 16 subjects issues two MFMAs with the same (exact) indicator fragment,
+// one on the hi fragment and one on the lo fragment, accumulating both halves
+// in FP32; sharing the indicator fragment halves its register footprint.
+//
+// Grid: workgroups = perm groups (4 waves x PT tiles x 32 relabellings) x
+// voxel chunks.  Block ids are remapped so that every perm group of one voxel
+// chunk lands on the same XCD (dispatch is round-robin over the 8 XCDs), so a
+// chunk's data is fetched into one L2 only.
+#include "rpt_internal.h"
+
+namespace rpt {
+
+namespace {
+
+struct NaiveArgs {
+  const uint16_t* kb16;
+  const float* kb32;
+  const float* kb32sq;
+  const float2* cst;
+  const float2* cstg;
+  const uint8_t* labels;
+  int64_t vpad, v, vt, L;
+  int n, n1, tpc, pg, abs_tail, store;
+  float fs, tm;
+  float* partial;
+  float* T_out;
+};
+
+__device__ __forceinline__ void block_coords(const NaiveArgs& a, int pt, int& chunk, int64_t& pbase) {
+  const int b = blockIdx.x, xcd = b & 7, j = b >> 3;
+  const int pg = j % a.pg;
+  chunk = xcd + 8 * (j / a.pg);
+  const int wave = threadIdx.x >> 6;
+  pbase = static_cast<int64_t>(pg) * (4 * pt * 32) + static_cast<int64_t>(wave) * (pt * 32);
+}
+
+
+// ----------------------------------------------------------------------------
+// split-BF16, balanced.  K step s covers subjects 16s..16s+15; the same
+// indicator fragment multiplies the hi fragment and the lo fragment.
+template <int KS, int PT, bool ABS, bool STORE>
+__global__ __launch_bounds__(kBlock) void naive_split_kernel(NaiveArgs a) {
+  const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
+  int chunk;
+  int64_t pbase;
+  block_coords(a, PT, chunk, pbase);
+
+  // indicator fragments: lane supplies A[row = col][subject 16s + 8h + 0..7]
+  u32x4 A[PT][KS];
+#pragma unroll
+  for (int p = 0; p < PT; ++p) {
+    const int64_t perm = pbase + p * 32 + col;
+    const bool valid = perm < a.L;
+    const uint8_t* lab = a.labels + (valid ? perm : 0) * a.n;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      unsigned w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j0 = 16 * s + 8 * h + 2 * q;
+        const unsigned b0 = (valid && j0 < a.n && lab[j0]) ? 0x3F80u : 0u;
+        const unsigned b1 = (valid && j0 + 1 < a.n && lab[j0 + 1]) ? 0x3F80u : 0u;
+        w[q] = b0 | (b1 << 16);
+      }
+      A[p][s] = u32x4{w[0], w[1], w[2], w[3]};
+    }
+  }
+
+  const float init = ABS ? 0.0f : -INFINITY;
+  float rm[PT][16];
+#pragma unroll
+  for (int p = 0; p < PT; ++p)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) rm[p][e] = init;
+
+  const int64_t t0 = static_cast<int64_t>(chunk) * a.tpc;
+  const int64_t t1 = t0 + a.tpc < a.vt ? t0 + a.tpc : a.vt;
+  const size_t kstride = static_cast<size_t>(a.vpad) * 32;  // uint16 per K step
+
+  u32x4 Bc[2 * KS], Bn[2 * KS];
+  float2 cc = make_float2(0.f, 0.f), cn = cc;
+  auto load = [&](u32x4* B, float2& c2, int64_t t) {
+    const int64_t vox = t * 32 + col;
+    const uint16_t* bp = a.kb16 + static_cast<size_t>(vox) * 32 + h * 8;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      B[2 * s] = *reinterpret_cast<const u32x4*>(bp + s * kstride);
+      B[2 * s + 1] = *reinterpret_cast<const u32x4*>(bp + s * kstride + 16);
+    }
+    c2 = a.cst[vox];
+  };
+  auto body = [&](const u32x4* B, float2 c2, int64_t t) {
+    f32x16 acc[PT];
+#pragma unroll
+    for (int p = 0; p < PT; ++p) acc[p] = f32x16{};
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int p = 0; p < PT; ++p) {
+        acc[p] = mfma_bf16(A[p][s], B[2 * s], acc[p]);
+        acc[p] = mfma_bf16(A[p][s], B[2 * s + 1], acc[p]);
+      }
+#pragma unroll
+    for (int p = 0; p < PT; ++p)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const float u = fmaf(acc[p][e], c2.x, c2.y);
+        rm[p][e] = fmaxf(rm[p][e], ABS ? fabsf(u) : u);
+      }
+    if (STORE) {
+      const int64_t vox = t * 32 + col;
+#pragma unroll
+      for (int p = 0; p < PT; ++p)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int64_t perm = pbase + p * 32 + mfma_row(e, h);
+          if (perm < a.L && vox < a.v)
+            a.T_out[perm * a.v + vox] = t_from_u_f(fmaf(acc[p][e], c2.x, c2.y), a.fs, a.tm);
+        }
+    }
+  };
+
+  if (t0 < t1) load(Bc, cc, t0);
+  for (int64_t t = t0; t < t1; t += 2) {
+    if (t + 1 < t1) load(Bn, cn, t + 1);
+    body(Bc, cc, t);
+    if (t + 1 >= t1) break;
+    if (t + 2 < t1) load(Bc, cc, t + 2);
+    body(Bn, cn, t + 1);
+  }
+
+#pragma unroll
+  for (int p = 0; p < PT; ++p)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      float x = rm[p][e];
+#pragma unroll
+      for (int off = 1; off < 32; off <<= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
+      rm[p][e] = x;
+    }
+  if (col == 0) {
+#pragma unroll
+    for (int p = 0; p < PT; ++p)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t perm = pbase + p * 32 + mfma_row(e, h);
+        if (perm < a.L) a.partial[static_cast<int64_t>(chunk) * a.L + perm] = rm[p][e];
+      }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// FP32 (balanced, or unbalanced with a second contraction of the squares)
+template <int KSB, int PT, bool UNBAL>
+__global__ __launch_bounds__(kBlock) void naive_f32_kernel(NaiveArgs a) {
+  const int lane = threadIdx.x & 63, h = lane >> 5, col = lane & 31;
+  int chunk;
+  int64_t pbase;
+  block_coords(a, PT, chunk, pbase);
+
+  // lane supplies A[row = col][subject 8s + 2q + h], q = 0..3
+  f32x4 A[PT][KSB];
+#pragma unroll
+  for (int p = 0; p < PT; ++p) {
+    const int64_t perm = pbase + p * 32 + col;
+    const bool valid = perm < a.L;
+    const uint8_t* lab = a.labels + (valid ? perm : 0) * a.n;
+#pragma unroll
+    for (int s = 0; s < KSB; ++s) {
+      float f[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j = 8 * s + 2 * q + h;
+        f[q] = (valid && j < a.n && lab[j]) ? 1.0f : 0.0f;
+      }
+      A[p][s] = f32x4{f[0], f[1], f[2], f[3]};
+    }
+  }
+
+  const float init = a.abs_tail ? 0.0f : -INFINITY;
+  float rm[PT][16];
+#pragma unroll
+  for (int p = 0; p < PT; ++p)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) rm[p][e] = init;
+
+  const int64_t t0 = static_cast<int64_t>(chunk) * a.tpc;
+  const int64_t t1 = t0 + a.tpc < a.vt ? t0 + a.tpc : a.vt;
+  const size_t kstride = static_cast<size_t>(a.vpad) * 8;
+  const int n1 = a.n1, n2 = a.n - a.n1;
+  const float rn1 = 1.0f / n1, rn2 = 1.0f / n2, rd1 = 1.0f / (n1 - 1), rd2 = 1.0f / (n2 - 1);
+
+  for (int64_t t = t0; t < t1; ++t) {
+    const int64_t vox = t * 32 + col;
+    const float* bp = a.kb32 + static_cast<size_t>(vox) * 8 + h * 4;
+    f32x16 acc[PT], acc2[PT];
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      acc[p] = f32x16{};
+      if (UNBAL) acc2[p] = f32x16{};
+    }
+#pragma unroll
+    for (int s = 0; s < KSB; ++s) {
+      const f32x4 B = *reinterpret_cast<const f32x4*>(bp + s * kstride);
+      f32x4 B2;
+      if (UNBAL) B2 = *reinterpret_cast<const f32x4*>(a.kb32sq + static_cast<size_t>(vox) * 8 + h * 4 + s * kstride);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int p = 0; p < PT; ++p) {
+          acc[p] = mfma_f32(A[p][s][q], B[q], acc[p]);
+          if (UNBAL) acc2[p] = mfma_f32(A[p][s][q], B2[q], acc2[p]);
+        }
+    }
+    if (!UNBAL) {
+      const float2 c2 = a.cst[vox];
+#pragma unroll
+      for (int p = 0; p < PT; ++p)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const float u = fmaf(acc[p][e], c2.x, c2.y);
+          rm[p][e] = fmaxf(rm[p][e], a.abs_tail ? fabsf(u) : u);
+          if (a.store) {
+            const int64_t perm = pbase + p * 32 + mfma_row(e, h);
+            if (perm < a.L && vox < a.v) a.T_out[perm * a.v + vox] = t_from_u_f(u, a.fs, a.tm);
+          }
+        }
+    } else {
+      const float2 sq = a.cstg[vox];
+      const bool vvalid = vox < a.v;
+#pragma unroll
+      for (int p = 0; p < PT; ++p)
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const float S1 = acc[p][e], Q1 = acc2[p][e];
+          const float S2 = sq.x - S1, Q2 = sq.y - Q1;
+          const float m1 = S1 * rn1, m2 = S2 * rn2;
+          const float v1 = fmaxf((Q1 - S1 * m1) * rd1, 0.0f), v2 = fmaxf((Q2 - S2 * m2) * rd2, 0.0f);
+          const float den2 = v1 * rn1 + v2 * rn2;
+          const float t = den2 > 0.0f ? (m1 - m2) * rsqrtf(den2) : 0.0f;
+          if (vvalid) rm[p][e] = fmaxf(rm[p][e], a.abs_tail ? fabsf(t) : t);
+          if (a.store) {
+            const int64_t perm = pbase + p * 32 + mfma_row(e, h);
+            if (perm < a.L && vvalid) a.T_out[perm * a.v + vox] = t;
+          }
+        }
+    }
+  }
+
+#pragma unroll
+  for (int p = 0; p < PT; ++p)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      float x = rm[p][e];
+#pragma unroll
+      for (int off = 1; off < 32; off <<= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
+      rm[p][e] = x;
+    }
+  if (col == 0) {
+#pragma unroll
+    for (int p = 0; p < PT; ++p)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t perm = pbase + p * 32 + mfma_row(e, h);
+        if (perm < a.L) a.partial[static_cast<int64_t>(chunk) * a.L + perm] = rm[p][e];
+      }
+  }
+}
+
+__global__ void naive_finalize_kernel(const float* __restrict__ partial, int nc, int64_t L, int m, int apply_t,
+                                      float* __restrict__ max_out) {
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= L) return;
+  float u = partial[i];
+  for (int c = 1; c < nc; ++c) u = fmaxf(u, partial[static_cast<int64_t>(c) * L + i]);
+  max_out[i] = apply_t ? static_cast<float>(t_from_u(static_cast<double>(u), m)) : u;
+}
+
+template <int PT, int KS>
+void* split_ptr(int abs_tail, int store) {
+  if (store) return abs_tail ? reinterpret_cast<void*>(&naive_split_kernel<KS, PT, true, true>)
+                             : reinterpret_cast<void*>(&naive_split_kernel<KS, PT, false, true>);
+  return abs_tail ? reinterpret_cast<void*>(&naive_split_kernel<KS, PT, true, false>)
+                  : reinterpret_cast<void*>(&naive_split_kernel<KS, PT, false, false>);
+}
+template <int PT, int KSB, bool U>
+void* f32_ptr() { return reinterpret_cast<void*>(&naive_f32_kernel<KSB, PT, U>); }
+
+template <int PT>
+void* pick_split(int ks, int at, int st) {
+  switch (ks) {
+    case 1: return split_ptr<PT, 1>(at, st); case 2: return split_ptr<PT, 2>(at, st);
+    case 3: return split_ptr<PT, 3>(at, st); case 4: return split_ptr<PT, 4>(at, st);
+    case 5: return split_ptr<PT, 5>(at, st); case 6: return split_ptr<PT, 6>(at, st);
+    case 7: return split_ptr<PT, 7>(at, st); case 8: return split_ptr<PT, 8>(at, st);
+    default: return nullptr;
+  }
+}
+template <int PT, bool U>
+void* pick_f32(int ks) {
+  switch (ks) {
+    case 1: return f32_ptr<PT, 1, U>();   case 2: return f32_ptr<PT, 2, U>();
+    case 3: return f32_ptr<PT, 3, U>();   case 4: return f32_ptr<PT, 4, U>();
+    case 5: return f32_ptr<PT, 5, U>();   case 6: return f32_ptr<PT, 6, U>();
+    case 7: return f32_ptr<PT, 7, U>();   case 8: return f32_ptr<PT, 8, U>();
+    case 9: return f32_ptr<PT, 9, U>();   case 10: return f32_ptr<PT, 10, U>();
+    case 11: return f32_ptr<PT, 11, U>(); case 12: return f32_ptr<PT, 12, U>();
+    case 13: return f32_ptr<PT, 13, U>(); case 14: return f32_ptr<PT, 14, U>();
+    case 15: return f32_ptr<PT, 15, U>(); case 16: return f32_ptr<PT, 16, U>();
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+NaivePlan naive_plan(int64_t v, int64_t L, int n, int prec, bool store) {
+  NaivePlan pl;
+  (void)n;
+  // split max-only path: 4 relabelling tiles per wave fit the register file
+  // without spills; the T-writing path and the FP32 path use 2.
+  pl.pt = (prec == RPT_SPLIT_BF16 && !store) ? 4 : 2;
+  pl.vt = round_up(v, 32) / 32;
+  const int64_t group = 4 * pl.pt * 32;
+  pl.pg = static_cast<int>(ceil_div(L > 0 ? L : 1, group));
+  int64_t nc = round_up(ceil_div(1280, pl.pg), 8);
+  const int64_t ncmax = round_up(pl.vt, 8);
+  if (nc > ncmax) nc = ncmax;
+  if (nc < 8) nc = 8;
+  pl.nc = static_cast<int>(nc);
+  pl.tpc = static_cast<int>(ceil_div(pl.vt, nc));
+  return pl;
+}
+
+size_t naive_bytes(int64_t v, int n, int64_t L, int prec) {
+  // the larger of the two plans (max-only / T-writing)
+  int64_t nc = 0;
+  for (int st = 0; st < 2; ++st) {
+    NaivePlan pl = naive_plan(v, L, n, prec, st != 0);
+    if (pl.nc > nc) nc = pl.nc;
+  }
+  return round_up(nc * (L > 0 ? L : 1) * 4, 256);
+}
+
+rpt_status naive_launch(const PrepX& p, const NaivePlan& pl, const uint8_t* labels, int64_t L, int tail, int prec,
+                        float* partial, float* T_out, float* max_out, hipStream_t s) {
+  if (L == 0) return RPT_OK;
+  NaiveArgs a;
+  a.kb16 = p.kb16;
+  a.kb32 = p.kb32;
+  a.kb32sq = p.kb32sq;
+  a.cst = p.cst;
+  a.cstg = p.cstg;
+  a.labels = labels;
+  a.vpad = p.vpad;
+  a.v = p.v;
+  a.vt = pl.vt;
+  a.L = L;
+  a.n = p.n;
+  a.n1 = p.n1;
+  a.tpc = pl.tpc;
+  a.pg = pl.pg;
+  a.abs_tail = tail == RPT_TAIL_ABS;
+  a.store = T_out != nullptr;
+  const int m = p.n / 2;
+  a.fs = static_cast<float>(2.0 * sqrt((m - 1.0) / m));
+  a.tm = static_cast<float>(2.0 / m);
+  a.partial = partial;
+  a.T_out = T_out;
+  const bool unbal = 2 * p.n1 != p.n;
+  void* fn = nullptr;
+  if (prec == RPT_SPLIT_BF16) {
+    fn = pl.pt == 4 ? pick_split<4>(p.ksteps, a.abs_tail, a.store) : pick_split<2>(p.ksteps, a.abs_tail, a.store);
+  } else {
+    fn = unbal ? pick_f32<2, true>(p.ksteps) : pick_f32<2, false>(p.ksteps);
+  }
+  if (!fn) return RPT_ERR_UNSUPPORTED;
+  const unsigned blocks = static_cast<unsigned>(pl.pg) * static_cast<unsigned>(pl.nc);
+  void* args[] = {&a};
+  hipError_t e = hipLaunchKernel(fn, dim3(blocks), dim3(kBlock), args, 0, s);
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return RPT_ERR_HIP;
+  }
+  if (max_out) {
+    hipLaunchKernelGGL(naive_finalize_kernel, dim3(static_cast<unsigned>(ceil_div(L, kBlock))), dim3(kBlock), 0, s,
+                       partial, pl.nc, L, m, unbal ? 0 : 1, max_out);
+    RPT_CHECK_LAUNCH();
+  }
+  return RPT_OK;
+}
+
+}  // namespace rpt

@@ -1,0 +1,175 @@
+// Internal declarations of librpt (HIP, gfx950).  Not part of the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "rpt.h"
+
+namespace rpt {
+
+typedef __attribute__((ext_vector_type(8))) __bf16 bf16x8;
+typedef __attribute__((ext_vector_type(16))) float f32x16;
+typedef __attribute__((ext_vector_type(4))) float f32x4;
+typedef __attribute__((ext_vector_type(4))) unsigned u32x4;
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;          // 4 waves per workgroup
+constexpr float kZBound = 5.8872f;   // > sqrt(50 ln 2): largest |z| of the noise map
+
+// ---------------------------------------------------------------------------
+// error reporting
+void set_hip_error(hipError_t e);
+
+#define RPT_CHECK_LAUNCH()                              \
+  do {                                                  \
+    hipError_t e_ = hipGetLastError();                  \
+    if (e_ != hipSuccess) {                             \
+      ::rpt::set_hip_error(e_);                         \
+      return RPT_ERR_HIP;                               \
+    }                                                   \
+  } while (0)
+
+#define RPT_TRY(expr)                      \
+  do {                                     \
+    rpt_status s_ = (expr);                \
+    if (s_ != RPT_OK) return s_;           \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// workspace carving: every piece 256-byte aligned.  With base == nullptr the
+// carver only measures.
+struct Carver {
+  char* base;
+  size_t off = 0;
+  explicit Carver(void* b) : base(static_cast<char*>(b)) {}
+  template <class T>
+  T* take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += bytes;
+    return p;
+  }
+};
+
+inline int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t round_up(int64_t a, int64_t b) { return ceil_div(a, b) * b; }
+
+// ---------------------------------------------------------------------------
+// device helpers
+__device__ __forceinline__ uint16_t f2bf(float x) {
+  // round to nearest even; inputs are finite
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return static_cast<uint16_t>(u >> 16);
+}
+__device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(static_cast<uint32_t>(h) << 16); }
+
+__device__ __forceinline__ f32x16 mfma_bf16(const u32x4& a, const u32x4& b, const f32x16& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                  c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x16 mfma_f32(float a, float b, const f32x16& c) {
+  return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
+}
+
+// Row of the 32x32 MFMA output held by accumulator register e of a lane in
+// half h (= lane / 32); the column is lane % 32.
+__device__ __forceinline__ int mfma_row(int e, int h) { return 8 * (e >> 2) + 4 * h + (e & 3); }
+
+__device__ __forceinline__ float wave_max(float x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
+  return x;
+}
+__device__ __forceinline__ double wave_sum_d(double x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+__device__ __forceinline__ float wave_sum(float x) {
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// ordered-int encoding so that unsigned atomicMax orders floats
+__device__ __forceinline__ unsigned float_to_ordered(float f) {
+  unsigned u = __float_as_uint(f);
+  return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ordered_to_float(unsigned u) {
+  return __uint_as_float((u & 0x80000000u) ? (u & 0x7FFFFFFFu) : ~u);
+}
+
+// ---------------------------------------------------------------------------
+// Balanced-design t from the scaled group contrast u (see prep.hip):
+// t = 2u sqrt((m-1)/m) / sqrt(1 - 2u^2/m), m = n/2.  Monotone in u.
+__host__ __device__ inline double t_from_u(double u, int m) {
+  double d = 1.0 - 2.0 * u * u / m;
+  double num = 2.0 * u * sqrt((m - 1.0) / m);
+  if (d <= 0.0) return u == 0.0 ? 0.0 : (u > 0 ? INFINITY : -INFINITY);
+  return num / sqrt(d);
+}
+__device__ __forceinline__ float t_from_u_f(float u, float fs, float tm) {
+  // fs = 2 sqrt((m-1)/m), tm = 2/m
+  float d = fmaxf(fmaf(-tm * u, u, 1.0f), 0.0f);
+  return u == 0.0f ? 0.0f : u * fs * rsqrtf(d);
+}
+
+// ---------------------------------------------------------------------------
+// Prepared data of one X (see prep.hip for the layouts).
+struct PrepX {
+  int64_t v = 0, vpad = 0;   // vpad = v rounded up to 32 voxels
+  int n = 0, n1 = 0;
+  int ksteps = 0;            // split: 16-wide K blocks; f32: 8-subject blocks
+  uint16_t* kb16 = nullptr;  // split: [ksteps][vpad][2][16] bf16 (hi block, lo block)
+  float* kb32 = nullptr;     // f32:   [ksteps][vpad][2][4]   (subject 8s+2q+h)
+  float* kb32sq = nullptr;   // f32 unbalanced: same layout, squared values
+  float* rows = nullptr;     // [vpad][ldn] standardised rows (sampled t)
+  int ldn = 0;
+  float2* cst = nullptr;     // [vpad] balanced epilogue (rinv, -h*rinv)
+  float2* cstg = nullptr;    // [vpad] unbalanced epilogue (S, Q)
+};
+
+enum PrepFlags { kPrepSplit = 1, kPrepF32 = 2, kPrepRows = 4, kPrepUnbal = 8 };
+
+size_t prep_bytes(int64_t v, int n, int flags);
+PrepX prep_carve(Carver& c, int64_t v, int n, int n1, int flags);
+rpt_status prep_launch(const PrepX& p, const float* X, int64_t ldx, int tail, int flags, hipStream_t s);
+
+// NaivePT contraction; writes per-(chunk, perm) maxima or T rows.
+struct NaivePlan {
+  int pt = 4;       // perm tiles (32 perms) per wave
+  int pg = 0;       // perm groups
+  int nc = 0;       // voxel chunks (multiple of 8)
+  int tpc = 0;      // voxel tiles per chunk
+  int64_t vt = 0;   // voxel tiles
+};
+NaivePlan naive_plan(int64_t v, int64_t L, int n, int prec, bool store);
+size_t naive_bytes(int64_t v, int n, int64_t L, int prec);
+rpt_status naive_launch(const PrepX& p, const NaivePlan& plan, const uint8_t* labels, int64_t L, int tail,
+                        int prec, float* partial, float* T_out, float* max_out, hipStream_t s);
+
+// Sampled t statistics (K2).
+rpt_status sampled_launch(const PrepX& p, const uint8_t* labels, int64_t L, const int32_t* omega, int k,
+                          const float* Tsrc, float* y, hipStream_t s);
+
+// Complete (Gram + FP64 Cholesky + solve).
+size_t complete_bytes(int64_t L, int r);
+rpt_status complete_launch(const float* U, int64_t v, int r, const int32_t* omega, int k, const float* y,
+                           int64_t L, float* W, float* resid, int32_t* info, void* ws, hipStream_t s);
+
+// Reconstruction filter + exact refine with noise (K7).
+size_t recon_bytes(int64_t v, int64_t L, int r);
+rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_t L, int64_t col0,
+                        uint64_t seed, int stream_id, const float* sigma_mu, float* out_max,
+                        const float* Tmax_for_gap, float* gap_out, void* ws, hipStream_t s);
+
+// Orthonormalisation (Cholesky-QR2).
+size_t reorth_bytes(int64_t v, int r);
+rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hipStream_t s);
+
+}  // namespace rpt

@@ -1,0 +1,64 @@
+"""CPU-side checks of the C ABI: the library loads, exports every symbol that
+include/rpt.h declares, and rejects invalid arguments synchronously (before any
+device work, so these run without a GPU)."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from conftest import ROOT
+
+LIB = os.path.join(ROOT, "paper_1703_01506_amd", "librpt.so")
+HEADER = os.path.join(ROOT, "include", "rpt.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rpt_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("librpt.so is not built (python paper_1703_01506_amd/build.py)")
+    from paper_1703_01506_amd import _lib
+    return _lib.load()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 17
+    for name in names:
+        assert hasattr(lib, name), name
+    from paper_1703_01506_amd._lib import SIGNATURES
+    assert sorted(SIGNATURES) == names
+
+
+def test_status_strings(lib):
+    assert lib.rpt_status_string(0) == b"ok"
+    assert b"workspace" in lib.rpt_status_string(-4)
+    assert lib.rpt_version() >= 100
+
+
+def test_naive_argument_validation(lib):
+    dummy = C.c_void_p(256)  # never dereferenced: validation fails first
+    ws_need = lib.rpt_naive_workspace(1000, 20, 50, 1)
+    assert ws_need > 0
+    # n1 out of range
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 1, dummy, 50, 0, 1, dummy, None, dummy, ws_need, None) == -1
+    # ldx < n
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 10, 10, dummy, 50, 0, 1, dummy, None, dummy, ws_need, None) == -1
+    # bad tail / precision
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 7, 1, dummy, None, dummy, ws_need, None) == -1
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 0, 9, dummy, None, dummy, ws_need, None) == -1
+    # unbalanced split-BF16 is not provided
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 8, dummy, 50, 0, 1, dummy, None, dummy, ws_need, None) == -6
+    # workspace too small / misaligned
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 0, 1, dummy, None, dummy, ws_need - 1,
+                                 None) == -4
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 0, 1, dummy, None, C.c_void_p(257), ws_need,
+                                 None) == -4
+    # L == 0 is a valid no-op
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 0, 0, 1, dummy, None, dummy, ws_need, None) == 0
