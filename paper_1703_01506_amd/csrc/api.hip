@@ -78,45 +78,224 @@ rpt_status rpt_naive_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, 
 }  // extern "C"
 
 // ---------------------------------------------------------------------------
-// entry points whose kernels are added in later files; kept as explicit
-// UNSUPPORTED stubs until then so that the exported symbol set matches rpt.h
+// sampled t statistics
+size_t rpt_sampled_tstat_workspace(int64_t v, int32_t n) {
+  if (v < 1 || n < 4) return 0;
+  return prep_bytes(v, n, kPrepRows | kPrepUnbal);
+}
+
+rpt_status rpt_sampled_tstat(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* labels,
+                             int64_t L, const int32_t* omega, int32_t k, float* y, void* ws, size_t ws_bytes,
+                             void* stream) {
+  if (!design_ok(v, n, ldx, n1) || L < 0 || k < 0) return RPT_ERR_INVALID_ARG;
+  if (L > 0 && k > 0 && (!X || !labels || !omega || !y)) return RPT_ERR_INVALID_ARG;
+  if (!ws_ok(ws, ws_bytes, rpt_sampled_tstat_workspace(v, n))) return RPT_ERR_WORKSPACE;
+  if (L == 0 || k == 0) return RPT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int flags = kPrepRows | (2 * n1 != n ? kPrepUnbal : 0);
+  Carver c(ws);
+  PrepX p = prep_carve(c, v, n, n1, flags | kPrepUnbal);
+  if (!(flags & kPrepUnbal)) p.cstg = nullptr;
+  RPT_TRY(prep_launch(p, X, ldx, RPT_TAIL_SIGNED, flags, s));
+  return sampled_launch(p, labels, L, omega, k, nullptr, y, s);
+}
+
+// ---------------------------------------------------------------------------
+// Complete
+size_t rpt_complete_workspace(int64_t L, int32_t r) {
+  (void)L;
+  (void)r;
+  return 0;
+}
+
+rpt_status rpt_complete(const float* U, int64_t v, int32_t r, const int32_t* omega, int32_t k, const float* y,
+                        int64_t L, float* W, float* resid, int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+  (void)ws;
+  (void)ws_bytes;
+  if (v < 1 || r < 1 || r > 128 || L < 0 || k < 1 || r > v) return RPT_ERR_INVALID_ARG;
+  if (k < r) return RPT_ERR_UNDERDETERMINED;
+  if (L > 0 && (!U || !omega || !y || !W || !info)) return RPT_ERR_INVALID_ARG;
+  return complete_run(U, v, r, omega, k, y, nullptr, 0, nullptr, L, W, resid, info, nullptr,
+                      static_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------------------
+// re-orthonormalisation: two Cholesky-QR passes
+size_t rpt_reorth_workspace(int64_t v, int32_t r) {
+  if (v < 1 || r < 1) return 0;
+  return reorth_bytes(v, r);
+}
+
+rpt_status rpt_reorth(float* U, int64_t v, int32_t r, int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+  if (!U || v < 1 || r < 1 || r > 128 || v < r) return RPT_ERR_INVALID_ARG;
+  if (!ws_ok(ws, ws_bytes, rpt_reorth_workspace(v, r))) return RPT_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  RPT_TRY(reorth_launch(U, v, r, info, ws, s));
+  return reorth_launch(U, v, r, info, ws, s);
+}
+
+// ---------------------------------------------------------------------------
+// training
+namespace rpt {
+namespace {
+struct TrainWs {
+  PrepX p;
+  float* partial;
+  float* T;
+  float* W;
+  float* resid;
+  float* wnorm2;
+  int32_t* info;
+  double* sums;
+  float* gap;
+  void* reorth_ws;
+  void* recon_ws;
+};
+TrainWs train_carve(void* ws, int64_t v, int n, int n1, int ell, int r, int k, int prec, size_t* total) {
+  Carver c(ws);
+  TrainWs t;
+  t.p = prep_carve(c, v, n, n1, naive_flags(prec, false));
+  const NaivePlan pl = naive_plan(v, ell, n, prec, true);
+  t.partial = c.take<float>(static_cast<size_t>(pl.nc) * ell);
+  t.T = c.take<float>(static_cast<size_t>(ell) * v);
+  t.W = c.take<float>(static_cast<size_t>(ell) * r);
+  t.resid = c.take<float>(static_cast<size_t>(ell) * k);
+  t.wnorm2 = c.take<float>(ell);
+  t.info = c.take<int32_t>(ell);
+  t.sums = c.take<double>(4);
+  t.gap = c.take<float>(ell);
+  t.reorth_ws = c.take<char>(reorth_bytes(v, r));
+  t.recon_ws = c.take<char>(recon_bytes(v, ell, r));
+  if (total) *total = c.off;
+  return t;
+}
+}  // namespace
+}  // namespace rpt
+
 extern "C" {
-__attribute__((weak)) size_t rpt_sampled_tstat_workspace(int64_t, int32_t) { return 0; }
-__attribute__((weak)) rpt_status rpt_sampled_tstat(const float*, int64_t, int32_t, int64_t, int32_t, const uint8_t*,
-                                                   int64_t, const int32_t*, int32_t, float*, void*, size_t, void*) {
-  return RPT_ERR_UNSUPPORTED;
+
+size_t rpt_train_workspace(int64_t v, int32_t n, int32_t ell, int32_t r, int32_t k, int prec) {
+  if (v < 1 || n < 4 || ell < 1 || r < 1 || k < 1) return 0;
+  size_t total = 0;
+  train_carve(nullptr, v, n, n / 2, ell, r, k, prec, &total);
+  return total;
 }
-__attribute__((weak)) size_t rpt_complete_workspace(int64_t, int32_t) { return 0; }
-__attribute__((weak)) rpt_status rpt_complete(const float*, int64_t, int32_t, const int32_t*, int32_t, const float*,
-                                              int64_t, float*, float*, int32_t*, void*, size_t, void*) {
-  return RPT_ERR_UNSUPPORTED;
+
+rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
+                              const uint8_t* train_labels, int32_t ell, const float* U0, int32_t r,
+                              const int32_t* omega_train, int32_t k, int32_t passes, int32_t batch, float gamma,
+                              const int32_t* omega_sm, uint64_t seed, int mu_rule, int prec, float* U_out,
+                              float* sigma_mu, float* train_max, float* T_ex_out, int32_t* info, void* ws,
+                              size_t ws_bytes, void* stream) {
+  if (!design_ok(v, n, ldx, n1) || 2 * n1 != n) return design_ok(v, n, ldx, n1) ? RPT_ERR_UNSUPPORTED
+                                                                               : RPT_ERR_INVALID_ARG;
+  if (ell < 1 || r < 1 || r > 128 || r > v || k < 1 || k > v || passes < 0 || batch < 1 || batch > ell ||
+      !(gamma > 0.0f))
+    return RPT_ERR_INVALID_ARG;
+  if (k < r) return RPT_ERR_UNDERDETERMINED;
+  if (mu_rule != RPT_MU_MEAN_GAP && mu_rule != RPT_MU_LITERAL && mu_rule != RPT_MU_ZERO) return RPT_ERR_INVALID_ARG;
+  if (prec != RPT_FP32 && prec != RPT_SPLIT_BF16) return RPT_ERR_INVALID_ARG;
+  if (!X || !train_labels || !U0 || (passes > 0 && !omega_train) || !omega_sm || !U_out || !sigma_mu ||
+      !train_max || !info)
+    return RPT_ERR_INVALID_ARG;
+  if (!ws_ok(ws, ws_bytes, rpt_train_workspace(v, n, ell, r, k, prec))) return RPT_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  TrainWs t = train_carve(ws, v, n, n1, ell, r, k, prec, nullptr);
+  float* T = T_ex_out ? T_ex_out : t.T;
+  // 1. training columns T_ex and their exact maxima
+  const int flags = naive_flags(prec, false);
+  RPT_TRY(prep_launch(t.p, X, ldx, RPT_TAIL_SIGNED, flags, s));
+  const NaivePlan pl = naive_plan(v, ell, n, prec, true);
+  RPT_TRY(naive_launch(t.p, pl, train_labels, ell, RPT_TAIL_SIGNED, prec, t.partial, T, train_max, s));
+  // 2. U <- Rand. Orth.
+  if (hipMemcpyAsync(U_out, U0, sizeof(float) * static_cast<size_t>(v) * r, hipMemcpyDeviceToDevice, s) !=
+      hipSuccess) {
+    set_hip_error(hipGetLastError());
+    return RPT_ERR_HIP;
+  }
+  RPT_TRY(reorth_launch(U_out, v, r, t.info, t.reorth_ws, s));
+  RPT_TRY(reorth_launch(U_out, v, r, t.info, t.reorth_ws, s));
+  // 3. tracking passes
+  for (int pp = 0; pp < passes; ++pp) {
+    for (int b0 = 0; b0 < ell; b0 += batch) {
+      const int nb = b0 + batch <= ell ? batch : ell - b0;
+      const int32_t* om = omega_train + (static_cast<int64_t>(pp) * ell + b0) * k;
+      RPT_TRY(complete_run(U_out, v, r, om, k, nullptr, T + static_cast<int64_t>(b0) * v, v, nullptr, nb, t.W,
+                           t.resid, t.info, t.wnorm2, s));
+      RPT_TRY(track_update_launch(U_out, v, r, om, k, t.resid, t.W, t.wnorm2, t.info, nb, gamma, s));
+      RPT_TRY(reorth_launch(U_out, v, r, t.info + ell - 1, t.reorth_ws, s));
+    }
+  }
+  // 4. sigma from fresh sampled sets with the final U
+  RPT_TRY(complete_run(U_out, v, r, omega_sm, k, nullptr, T, v, nullptr, ell, t.W, t.resid, info, t.wnorm2, s));
+  RPT_TRY(sigma_launch(t.resid, static_cast<int64_t>(ell) * k, t.sums, sigma_mu, s));
+  // 5. mu
+  if (mu_rule == RPT_MU_MEAN_GAP) {
+    RPT_TRY(recon_launch(U_out, v, r, t.W, ell, 0, seed, RPT_STREAM_TRAINING, sigma_mu, nullptr, train_max, t.gap,
+                         t.recon_ws, s));
+    RPT_TRY(mu_launch(t.gap, ell, mu_rule, sigma_mu, s));
+  } else if (mu_rule == RPT_MU_LITERAL) {
+    RPT_TRY(literal_resid_launch(T, U_out, t.W, v, r, ell, t.gap, s));
+    RPT_TRY(mu_launch(t.gap, ell, mu_rule, sigma_mu, s));
+  } else {
+    RPT_TRY(mu_launch(t.gap, 0, mu_rule, sigma_mu, s));
+  }
+  return RPT_OK;
 }
-__attribute__((weak)) size_t rpt_train_workspace(int64_t, int32_t, int32_t, int32_t, int32_t, int) { return 0; }
-__attribute__((weak)) rpt_status rpt_train_subspace(const float*, int64_t, int32_t, int64_t, int32_t, const uint8_t*,
-                                                    int32_t, const float*, int32_t, const int32_t*, int32_t, int32_t,
-                                                    int32_t, float, const int32_t*, uint64_t, int, int, float*,
-                                                    float*, float*, float*, int32_t*, void*, size_t, void*) {
-  return RPT_ERR_UNSUPPORTED;
+
+// ---------------------------------------------------------------------------
+// recovery
+size_t rpt_recover_workspace(int64_t v, int32_t n, int64_t L_rec, int32_t r, int32_t k) {
+  if (v < 1 || n < 4 || L_rec < 0 || r < 1 || k < 1) return 0;
+  Carver c(nullptr);
+  prep_carve(c, v, n, n / 2, kPrepRows);
+  c.take<float>(static_cast<size_t>(L_rec > 0 ? L_rec : 1) * k);
+  c.take<float>(static_cast<size_t>(L_rec > 0 ? L_rec : 1) * r);
+  c.take<char>(recon_bytes(v, L_rec, r));
+  return c.off;
 }
-__attribute__((weak)) size_t rpt_recover_workspace(int64_t, int32_t, int64_t, int32_t, int32_t) { return 0; }
-__attribute__((weak)) rpt_status rpt_recover_maxnull(const float*, int64_t, int32_t, int64_t, int32_t, const uint8_t*,
-                                                     int64_t, int64_t, const float*, int32_t, const float*,
-                                                     const int32_t*, int32_t, uint64_t, float*, float*, int32_t*,
-                                                     void*, size_t, void*) {
-  return RPT_ERR_UNSUPPORTED;
+
+rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* labels,
+                               int64_t L_rec, int64_t col0, const float* U, int32_t r, const float* sigma_mu,
+                               const int32_t* omega, int32_t k, uint64_t seed, float* max_out, float* W_out,
+                               int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+  if (!design_ok(v, n, ldx, n1)) return RPT_ERR_INVALID_ARG;
+  if (2 * n1 != n) return RPT_ERR_UNSUPPORTED;
+  if (L_rec < 0 || col0 < 0 || r < 1 || r > 128 || r > v || k < 1 || k > v) return RPT_ERR_INVALID_ARG;
+  if (k < r) return RPT_ERR_UNDERDETERMINED;
+  if (L_rec > 0 && (!X || !labels || !U || !sigma_mu || !omega || !max_out || !info)) return RPT_ERR_INVALID_ARG;
+  if (!ws_ok(ws, ws_bytes, rpt_recover_workspace(v, n, L_rec, r, k))) return RPT_ERR_WORKSPACE;
+  if (L_rec == 0) return RPT_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  Carver c(ws);
+  PrepX p = prep_carve(c, v, n, n1, kPrepRows);
+  float* y = c.take<float>(static_cast<size_t>(L_rec) * k);
+  float* Wt = c.take<float>(static_cast<size_t>(L_rec) * r);
+  void* rws = c.take<char>(recon_bytes(v, L_rec, r));
+  float* W = W_out ? W_out : Wt;
+  RPT_TRY(prep_launch(p, X, ldx, RPT_TAIL_SIGNED, kPrepRows, s));
+  RPT_TRY(sampled_launch(p, labels, L_rec, omega, k, nullptr, y, s));
+  RPT_TRY(complete_run(U, v, r, omega, k, y, nullptr, 0, nullptr, L_rec, W, nullptr, info, nullptr, s));
+  return recon_launch(U, v, r, W, L_rec, col0, seed, RPT_STREAM_RECOVERY, sigma_mu, max_out, nullptr, nullptr, rws,
+                      s);
 }
-__attribute__((weak)) size_t rpt_reorth_workspace(int64_t, int32_t) { return 0; }
-__attribute__((weak)) rpt_status rpt_reorth(float*, int64_t, int32_t, int32_t*, void*, size_t, void*) {
-  return RPT_ERR_UNSUPPORTED;
+
+// ---------------------------------------------------------------------------
+// masked loss
+rpt_status rpt_masked_loss_fwd(const float* U, int64_t v, int32_t r, const float* W, int32_t B,
+                               const int64_t* omega_ptr, const int32_t* omega_idx, const float* t_vals, int64_t nnz,
+                               double* loss, float* resid, void* stream) {
+  if (v < 1 || r < 1 || B < 0 || nnz < 0 || !loss) return RPT_ERR_INVALID_ARG;
+  if (B > 0 && (!U || !W || !omega_ptr || (nnz > 0 && (!omega_idx || !t_vals)))) return RPT_ERR_INVALID_ARG;
+  return loss_fwd_launch(U, v, r, W, B, omega_ptr, omega_idx, t_vals, loss, resid, static_cast<hipStream_t>(stream));
 }
-__attribute__((weak)) rpt_status rpt_masked_loss_fwd(const float*, int64_t, int32_t, const float*, int32_t,
-                                                     const int64_t*, const int32_t*, const float*, int64_t, double*,
-                                                     float*, void*) {
-  return RPT_ERR_UNSUPPORTED;
+
+rpt_status rpt_masked_loss_bwd(const float* U, int64_t v, int32_t r, const float* W, int32_t B,
+                               const int64_t* omega_ptr, const int32_t* omega_idx, const float* resid, int64_t nnz,
+                               float* dU, float* dW, void* stream) {
+  if (v < 1 || r < 1 || B < 0 || nnz < 0 || !dU || (B > 0 && !dW)) return RPT_ERR_INVALID_ARG;
+  if (B > 0 && (!U || !W || !omega_ptr || (nnz > 0 && (!omega_idx || !resid)))) return RPT_ERR_INVALID_ARG;
+  return loss_bwd_launch(U, v, r, W, B, omega_ptr, omega_idx, resid, dU, dW, static_cast<hipStream_t>(stream));
 }
-__attribute__((weak)) rpt_status rpt_masked_loss_bwd(const float*, int64_t, int32_t, const float*, int32_t,
-                                                     const int64_t*, const int32_t*, const float*, int64_t, float*,
-                                                     float*, void*) {
-  return RPT_ERR_UNSUPPORTED;
-}
+
 }  // extern "C"

@@ -1,0 +1,243 @@
+// K3 + K4 -- Complete (Alg. 2): per column i, the masked least-squares fit
+//     w_i = argmin_w | U[omega_i, :] w - y_i |_2
+// from the normal equations G w = b, G = U_O^T U_O, b = U_O^T y.
+//
+// One workgroup per column.  The sampled basis rows are gathered 32 at a time
+// (coalesced: a row is r contiguous floats) into LDS, transposed and split
+// into BF16 hi/lo halves; G accumulates on the matrix cores as
+// hi.hi + hi.lo + lo.hi (the split product keeps about 16 significant bits per
+// term, FP32 accumulation).  b accumulates from the FP32 values in FP64.
+// G is then moved to LDS in FP64 (packed lower triangle) and factored by a
+// right-looking Cholesky in FP64; two triangular solves in one wave give w.
+// A non-positive pivot at step j sets info[i] = j + 1 and w_i = 0.
+// Optionally the residual y - U_O w is written (FP32 dot products).
+#include "rpt_internal.h"
+
+namespace rpt {
+
+namespace {
+
+constexpr int kRMax = 128;           // basis rank handled in LDS
+constexpr int kChunk = 32;           // sampled rows per LDS stage
+constexpr int kStageLd = 40;         // bf16 per staged column (32 + pad)
+
+struct CompleteArgs {
+  const float* U;
+  int64_t v;
+  int r;
+  const int32_t* omega;
+  int k;
+  const float* y;       // [L][k]  (or nullptr when yT is used)
+  const float* Trows;   // alternative source: y[i][q] = Trows[trow(i) * ldT + omega[i][q]]
+  int64_t ldT;
+  const int32_t* trow;  // row of Trows for column i (nullptr: row i)
+  int64_t L;
+  float* W;             // [L][r]
+  float* resid;         // [L][k] or nullptr
+  int32_t* info;        // [L]
+  float* wnorm2;        // [L] |w|^2 (or nullptr)
+};
+
+__device__ __forceinline__ int tri(int i, int c) { return (i * (i + 1)) / 2 + c; }
+
+__device__ __forceinline__ float y_at(const CompleteArgs& a, int64_t i, int q) {
+  if (a.y) return a.y[i * a.k + q];
+  const int64_t row = a.trow ? a.trow[i] : i;
+  const int64_t vox = a.omega[i * a.k + q];
+  return (vox >= 0 && vox < a.ldT) ? a.Trows[row * a.ldT + vox] : 0.0f;
+}
+
+template <int RT>
+__global__ __launch_bounds__(kBlock) void complete_kernel(CompleteArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  // stage: UT_hi[kRMax][kStageLd] bf16, UT_lo[...], ybuf[kChunk] f32
+  uint16_t* uth = reinterpret_cast<uint16_t*>(smem);
+  uint16_t* utl = uth + kRMax * kStageLd;
+  float* ybuf = reinterpret_cast<float*>(utl + kRMax * kStageLd);
+  // factor phase (aliases the stage): G64 packed lower [r(r+1)/2], diag[r], rhs[r]
+  double* G64 = reinterpret_cast<double*>(smem);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, col = lane & 31;
+  const int r = a.r, k = a.k;
+  const int64_t i = blockIdx.x;
+  const int32_t* om = a.omega + i * k;
+
+  f32x16 acc[RT];
+#pragma unroll
+  for (int t = 0; t < RT; ++t) acc[t] = f32x16{};
+  // b: thread t owns column ac = t & 127 for rows of parity t >> 7
+  const int ac = tid & (kRMax - 1), par = tid >> 7;
+  double bacc = 0.0;
+
+  for (int c0 = 0; c0 < k; c0 += kChunk) {
+    __syncthreads();
+    if (tid < kChunk) ybuf[tid] = (c0 + tid < k) ? y_at(a, i, c0 + tid) : 0.0f;
+    __syncthreads();
+#pragma unroll 4
+    for (int kk = par; kk < kChunk; kk += 2) {
+      float x = 0.0f;
+      if (c0 + kk < k && ac < r) {
+        const int64_t row = om[c0 + kk];
+        if (row >= 0 && row < a.v) x = a.U[row * r + ac];  // out-of-range index: row treated as zero
+      }
+      const uint16_t hi = f2bf(x);
+      uth[ac * kStageLd + kk] = hi;
+      utl[ac * kStageLd + kk] = f2bf(x - bf2f(hi));
+      bacc += static_cast<double>(x) * ybuf[kk];
+    }
+    __syncthreads();
+    if (wave < RT) {
+#pragma unroll
+      for (int s = 0; s < kChunk / 16; ++s) {
+        const int ko = 16 * s + 8 * h;
+        const u32x4 ah = *reinterpret_cast<const u32x4*>(uth + (wave * 32 + col) * kStageLd + ko);
+        const u32x4 al = *reinterpret_cast<const u32x4*>(utl + (wave * 32 + col) * kStageLd + ko);
+#pragma unroll
+        for (int t = 0; t < RT; ++t) {
+          const u32x4 bh = *reinterpret_cast<const u32x4*>(uth + (t * 32 + col) * kStageLd + ko);
+          const u32x4 bl = *reinterpret_cast<const u32x4*>(utl + (t * 32 + col) * kStageLd + ko);
+          acc[t] = mfma_bf16(ah, bh, acc[t]);
+          acc[t] = mfma_bf16(ah, bl, acc[t]);
+          acc[t] = mfma_bf16(al, bh, acc[t]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+  // G (lower triangle) to LDS in FP64; b reduced over the two row parities
+  const int ntri = r * (r + 1) / 2;
+  double* diag = G64 + ntri;
+  double* rhs = diag + kRMax;
+  double* bpart = rhs + kRMax;  // [2][kRMax]
+  if (wave < RT) {
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int row = wave * 32 + mfma_row(e, h), cc = t * 32 + col;
+        if (row < r && cc <= row) G64[tri(row, cc)] = static_cast<double>(acc[t][e]);
+      }
+  }
+  bpart[par * kRMax + ac] = bacc;
+  __syncthreads();
+  if (tid < r) rhs[tid] = bpart[tid] + bpart[kRMax + tid];
+
+  // right-looking Cholesky, FP64
+  __shared__ int fail;
+  if (tid == 0) fail = 0;
+  for (int j = 0; j < r; ++j) {
+    __syncthreads();
+    const double piv = G64[tri(j, j)];
+    if (!(piv > 0.0)) {
+      if (tid == 0) fail = j + 1;
+      break;
+    }
+    const double d = sqrt(piv);
+    const double dinv = 1.0 / d;
+    for (int ii = j + 1 + tid; ii < r; ii += kBlock) G64[tri(ii, j)] *= dinv;
+    if (tid == 0) diag[j] = d;
+    __syncthreads();
+    const int m = r - j - 1;
+    for (int t = tid; t < m * m; t += kBlock) {
+      const int ii = j + 1 + t / m, cc = j + 1 + t % m;
+      if (cc <= ii) G64[tri(ii, cc)] -= G64[tri(ii, j)] * G64[tri(cc, j)];
+    }
+  }
+  __syncthreads();
+  const int failed = fail;
+  float* Wi = a.W + i * r;
+  if (failed) {
+    for (int c = tid; c < r; c += kBlock) Wi[c] = 0.0f;
+    if (tid == 0) {
+      a.info[i] = failed;
+      if (a.wnorm2) a.wnorm2[i] = 0.0f;
+    }
+    if (a.resid)
+      for (int q = tid; q < k; q += kBlock) a.resid[i * k + q] = y_at(a, i, q);
+    return;
+  }
+  // triangular solves in wave 0: lane owns rows lane and lane + 64
+  if (wave == 0) {
+    double z0 = lane < r ? rhs[lane] : 0.0, z1 = lane + 64 < r ? rhs[lane + 64] : 0.0;
+    for (int j = 0; j < r; ++j) {  // L z = b
+      const double own = (j < 64) ? z0 : z1;
+      const double zj = __shfl(own, j & 63, 64) / diag[j];
+      if (lane == (j & 63)) {
+        if (j < 64) z0 = zj; else z1 = zj;
+      }
+      if (lane > j && lane < r) z0 -= G64[tri(lane, j)] * zj;
+      if (lane + 64 > j && lane + 64 < r) z1 -= G64[tri(lane + 64, j)] * zj;
+    }
+    for (int j = r - 1; j >= 0; --j) {  // L^T w = z
+      const double own = (j < 64) ? z0 : z1;
+      const double wj = __shfl(own, j & 63, 64) / diag[j];
+      if (lane == (j & 63)) {
+        if (j < 64) z0 = wj; else z1 = wj;
+      }
+      if (lane < j) z0 -= G64[tri(j, lane)] * wj;
+      if (lane + 64 < j) z1 -= G64[tri(j, lane + 64)] * wj;
+    }
+    double nrm = 0.0;
+    if (lane < r) {
+      Wi[lane] = static_cast<float>(z0);
+      rhs[lane] = z0;
+      nrm += z0 * z0;
+    }
+    if (lane + 64 < r) {
+      Wi[lane + 64] = static_cast<float>(z1);
+      rhs[lane + 64] = z1;
+      nrm += z1 * z1;
+    }
+    nrm = wave_sum_d(nrm);
+    if (lane == 0) {
+      a.info[i] = 0;
+      if (a.wnorm2) a.wnorm2[i] = static_cast<float>(nrm);
+    }
+  }
+  if (a.resid) {
+    __syncthreads();
+    for (int q = tid; q < k; q += kBlock) {
+      const int64_t row = om[q];
+      double s = 0.0;
+      if (row >= 0 && row < a.v) {
+        const float* u = a.U + row * r;
+        for (int c = 0; c < r; ++c) s += static_cast<double>(u[c]) * rhs[c];
+      }
+      a.resid[i * k + q] = static_cast<float>(y_at(a, i, q) - s);
+    }
+  }
+}
+
+size_t smem_bytes(int r) {
+  const size_t stage = 2 * kRMax * kStageLd * sizeof(uint16_t) + kChunk * sizeof(float);
+  const size_t factor = (static_cast<size_t>(r) * (r + 1) / 2 + 4 * kRMax) * sizeof(double);
+  return stage > factor ? stage : factor;
+}
+
+}  // namespace
+
+rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, int k, const float* y,
+                        const float* Trows, int64_t ldT, const int32_t* trow, int64_t L, float* W, float* resid,
+                        int32_t* info, float* wnorm2, hipStream_t s) {
+  if (L == 0) return RPT_OK;
+  if (r < 1 || r > kRMax) return RPT_ERR_UNSUPPORTED;
+  CompleteArgs a{U, v, r, omega, k, y, Trows, ldT, trow, L, W, resid, info, wnorm2};
+  const int RT = (r + 31) / 32;
+  void* fn = nullptr;
+  switch (RT) {
+    case 1: fn = reinterpret_cast<void*>(&complete_kernel<1>); break;
+    case 2: fn = reinterpret_cast<void*>(&complete_kernel<2>); break;
+    case 3: fn = reinterpret_cast<void*>(&complete_kernel<3>); break;
+    default: fn = reinterpret_cast<void*>(&complete_kernel<4>); break;
+  }
+  const size_t sm = smem_bytes(r);
+  void* args[] = {&a};
+  hipError_t e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(L)), dim3(kBlock), args, sm, s);
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return RPT_ERR_HIP;
+  }
+  return RPT_OK;
+}
+
+}  // namespace rpt

@@ -28,125 +28,141 @@ namespace rpt {
 
 namespace {
 
-__global__ void prep_kernel(const float* __restrict__ X, int64_t v, int n, int64_t ldx, PrepX p, int tail,
-                            int flags) {
-  const int64_t k = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (k >= p.vpad) return;
+constexpr int kPrepTile = 64;     // voxels per workgroup
+constexpr int kPrepNMax = 128;    // subjects held in LDS
+
+// One workgroup prepares 64 voxel rows: a coalesced load of the rows into LDS,
+// FP64 row statistics with 4 threads per row, then coalesced writes of every
+// output layout.
+__global__ __launch_bounds__(kBlock) void prep_kernel(const float* __restrict__ X, int64_t v, int n, int64_t ldx,
+                                                     PrepX p, int tail, int flags) {
+  __shared__ float xs[kPrepTile][kPrepNMax + 1];
+  const int tid = threadIdx.x;
+  const int64_t v0 = static_cast<int64_t>(blockIdx.x) * kPrepTile;
   const bool split = (flags & kPrepSplit) != 0;
-  if (k >= v) {
-    if (p.kb16) {
-      for (int s = 0; s < p.ksteps; ++s) {
-        u32x4* d = reinterpret_cast<u32x4*>(p.kb16 + (static_cast<size_t>(s) * p.vpad + k) * 32);
-        d[0] = u32x4{0, 0, 0, 0};
-        d[1] = u32x4{0, 0, 0, 0};
-        d[2] = u32x4{0, 0, 0, 0};
-        d[3] = u32x4{0, 0, 0, 0};
-      }
-    }
-    if (p.kb32) {
-      for (int s = 0; s < p.ksteps; ++s) {
-        f32x4* d = reinterpret_cast<f32x4*>(p.kb32 + (static_cast<size_t>(s) * p.vpad + k) * 8);
-        d[0] = f32x4{0, 0, 0, 0};
-        d[1] = f32x4{0, 0, 0, 0};
-        if (p.kb32sq) {
-          f32x4* d2 = reinterpret_cast<f32x4*>(p.kb32sq + (static_cast<size_t>(s) * p.vpad + k) * 8);
-          d2[0] = f32x4{0, 0, 0, 0};
-          d2[1] = f32x4{0, 0, 0, 0};
-        }
-      }
-    }
-    if (p.rows)
-      for (int j = 0; j < p.ldn; ++j) p.rows[k * p.ldn + j] = 0.0f;
-    if (p.cst) p.cst[k] = make_float2(0.0f, tail == RPT_TAIL_ABS ? 0.0f : -INFINITY);
-    if (p.cstg) p.cstg[k] = make_float2(0.0f, 0.0f);
-    return;
+
+  for (int idx = tid; idx < kPrepTile * n; idx += kBlock) {
+    const int r = idx / n, j = idx - r * n;
+    const int64_t vox = v0 + r;
+    xs[r][j] = vox < v ? X[vox * ldx + j] : 0.0f;
   }
-  const float* x = X + k * ldx;
+  __syncthreads();
+
+  // statistics: thread group of 4 per row (lanes 4r..4r+3 of the block)
+  const int r = tid >> 2, q = tid & 3;
+  const int64_t vox = v0 + r;
   double s0 = 0.0;
-  for (int j = 0; j < n; ++j) s0 += x[j];
+  for (int j = q; j < n; j += 4) s0 += xs[r][j];
+  s0 += __shfl_xor(s0, 1, 64);
+  s0 += __shfl_xor(s0, 2, 64);
   const double mean = s0 / n;
   double ss = 0.0;
-  for (int j = 0; j < n; ++j) {
-    double d = x[j] - mean;
+  for (int j = q; j < n; j += 4) {
+    const double d = xs[r][j] - mean;
     ss += d * d;
   }
-  const double sc = ss > 0.0 ? sqrt((n - 1.0) / ss) : 0.0;
-  auto xs = [&](int j) -> float { return static_cast<float>((x[j] - mean) * sc); };
-  auto stored = [&](int j) -> float {
-    float f = xs(j);
-    if (!split) return f;
-    uint16_t hi = f2bf(f);
-    uint16_t lo = f2bf(f - bf2f(hi));
-    return bf2f(hi) + bf2f(lo);
-  };
+  ss += __shfl_xor(ss, 1, 64);
+  ss += __shfl_xor(ss, 2, 64);
+  const double sc = (ss > 0.0 && vox < v) ? sqrt((n - 1.0) / ss) : 0.0;
+  // standardise in place (each thread its own entries)
   double S = 0.0;
-  for (int j = 0; j < n; ++j) S += stored(j);
+  for (int j = q; j < n; j += 4) {
+    const float f = static_cast<float>((xs[r][j] - mean) * sc);
+    xs[r][j] = f;
+    float st = f;
+    if (split) {
+      const uint16_t hi = f2bf(f);
+      st = bf2f(hi) + bf2f(f2bf(f - bf2f(hi)));
+    }
+    S += st;
+  }
+  S += __shfl_xor(S, 1, 64);
+  S += __shfl_xor(S, 2, 64);
   const double mu = S / n;
   double Qc = 0.0, Q = 0.0;
-  for (int j = 0; j < n; ++j) {
-    double st = stored(j);
+  for (int j = q; j < n; j += 4) {
+    const float f = xs[r][j];
+    float st = f;
+    if (split) {
+      const uint16_t hi = f2bf(f);
+      st = bf2f(hi) + bf2f(f2bf(f - bf2f(hi)));
+    }
     Qc += (st - mu) * (st - mu);
-    Q += st * st;
+    Q += static_cast<double>(st) * st;
   }
-  if (p.kb16) {
-    for (int s = 0; s < p.ksteps; ++s) {
-      uint32_t whi[8], wlo[8];
-#pragma unroll
-      for (int e2 = 0; e2 < 8; ++e2) {
-        uint32_t phi = 0, plo = 0;
-#pragma unroll
-        for (int hlf = 0; hlf < 2; ++hlf) {
-          const int j = 16 * s + 2 * e2 + hlf;
-          uint16_t vh = 0, vl = 0;
-          if (j < n) {
-            const float f = xs(j);
-            vh = f2bf(f);
-            vl = f2bf(f - bf2f(vh));
-          }
-          phi |= static_cast<uint32_t>(vh) << (16 * hlf);
-          plo |= static_cast<uint32_t>(vl) << (16 * hlf);
-        }
-        whi[e2] = phi;
-        wlo[e2] = plo;
+  Qc += __shfl_xor(Qc, 1, 64);
+  Qc += __shfl_xor(Qc, 2, 64);
+  Q += __shfl_xor(Q, 1, 64);
+  Q += __shfl_xor(Q, 2, 64);
+  if (q == 0 && vox < p.vpad) {
+    if (vox < v) {
+      if (p.cst) {
+        const double rinv = Qc > 0.0 ? 1.0 / sqrt(Qc) : 0.0;
+        p.cst[vox] = make_float2(static_cast<float>(rinv), static_cast<float>(-0.5 * S * rinv));
       }
-      u32x4* d = reinterpret_cast<u32x4*>(p.kb16 + (static_cast<size_t>(s) * p.vpad + k) * 32);
-      d[0] = u32x4{whi[0], whi[1], whi[2], whi[3]};
-      d[1] = u32x4{whi[4], whi[5], whi[6], whi[7]};
-      d[2] = u32x4{wlo[0], wlo[1], wlo[2], wlo[3]};
-      d[3] = u32x4{wlo[4], wlo[5], wlo[6], wlo[7]};
+      if (p.cstg) p.cstg[vox] = make_float2(static_cast<float>(S), static_cast<float>(Q));
+    } else {
+      // padding voxels never win a maximum
+      if (p.cst) p.cst[vox] = make_float2(0.0f, tail == RPT_TAIL_ABS ? 0.0f : -INFINITY);
+      if (p.cstg) p.cstg[vox] = make_float2(0.0f, 0.0f);
+    }
+  }
+  __syncthreads();
+
+  const int nv = static_cast<int>((p.vpad - v0) < kPrepTile ? (p.vpad - v0) : kPrepTile);
+  if (p.kb16) {
+    // per K step: 64 voxels x (hi 16 | lo 16) bf16 = 256 chunks of 16 bytes
+    const int rr = tid >> 2, c = tid & 3;
+    for (int s = 0; s < p.ksteps; ++s) {
+      if (rr < nv) {
+        uint32_t w[4];
+#pragma unroll
+        for (int e2 = 0; e2 < 4; ++e2) {
+          uint32_t pr = 0;
+#pragma unroll
+          for (int hl = 0; hl < 2; ++hl) {
+            const int j = 16 * s + 8 * (c & 1) + 2 * e2 + hl;
+            uint16_t val = 0;
+            if (j < n) {
+              const float f = xs[rr][j];
+              const uint16_t hi = f2bf(f);
+              val = (c < 2) ? hi : f2bf(f - bf2f(hi));
+            }
+            pr |= static_cast<uint32_t>(val) << (16 * hl);
+          }
+          w[e2] = pr;
+        }
+        u32x4* d = reinterpret_cast<u32x4*>(p.kb16 + (static_cast<size_t>(s) * p.vpad + v0 + rr) * 32 + 8 * c);
+        *d = u32x4{w[0], w[1], w[2], w[3]};
+      }
     }
   }
   if (p.kb32) {
+    // per K block: 64 voxels x 8 floats = 128 chunks of 16 bytes
     for (int s = 0; s < p.ksteps; ++s) {
-      float f[8], f2[8];
+      for (int ch = tid; ch < 2 * kPrepTile; ch += kBlock) {
+        const int rr = ch >> 1, hh = ch & 1;
+        if (rr >= nv) continue;
+        float f[4], f2[4];
 #pragma unroll
-      for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          int subj = 8 * s + 2 * q + hh;
-          float val = subj < n ? xs(subj) : 0.0f;
-          f[hh * 4 + q] = val;
-          f2[hh * 4 + q] = val * val;
+        for (int qq = 0; qq < 4; ++qq) {
+          const int j = 8 * s + 2 * qq + hh;
+          f[qq] = j < n ? xs[rr][j] : 0.0f;
+          f2[qq] = f[qq] * f[qq];
         }
-      f32x4* d = reinterpret_cast<f32x4*>(p.kb32 + (static_cast<size_t>(s) * p.vpad + k) * 8);
-      d[0] = f32x4{f[0], f[1], f[2], f[3]};
-      d[1] = f32x4{f[4], f[5], f[6], f[7]};
-      if (p.kb32sq) {
-        f32x4* d2 = reinterpret_cast<f32x4*>(p.kb32sq + (static_cast<size_t>(s) * p.vpad + k) * 8);
-        d2[0] = f32x4{f2[0], f2[1], f2[2], f2[3]};
-        d2[1] = f32x4{f2[4], f2[5], f2[6], f2[7]};
+        const size_t off = (static_cast<size_t>(s) * p.vpad + v0 + rr) * 8 + 4 * hh;
+        *reinterpret_cast<f32x4*>(p.kb32 + off) = f32x4{f[0], f[1], f[2], f[3]};
+        if (p.kb32sq) *reinterpret_cast<f32x4*>(p.kb32sq + off) = f32x4{f2[0], f2[1], f2[2], f2[3]};
       }
     }
   }
   if (p.rows) {
-    float* r = p.rows + k * p.ldn;
-    for (int j = 0; j < p.ldn; ++j) r[j] = j < n ? xs(j) : 0.0f;
+    const int ld = p.ldn;
+    for (int idx = tid; idx < nv * ld; idx += kBlock) {
+      const int rr = idx / ld, j = idx - rr * ld;
+      p.rows[(v0 + rr) * ld + j] = j < n ? xs[rr][j] : 0.0f;
+    }
   }
-  if (p.cst) {
-    const double rinv = Qc > 0.0 ? 1.0 / sqrt(Qc) : 0.0;
-    p.cst[k] = make_float2(static_cast<float>(rinv), static_cast<float>(-0.5 * S * rinv));
-  }
-  if (p.cstg) p.cstg[k] = make_float2(static_cast<float>(S), static_cast<float>(Q));
 }
 
 }  // namespace
@@ -181,7 +197,8 @@ PrepX prep_carve(Carver& c, int64_t v, int n, int n1, int flags) {
 }
 
 rpt_status prep_launch(const PrepX& p, const float* X, int64_t ldx, int tail, int flags, hipStream_t s) {
-  const int64_t blocks = ceil_div(p.vpad, kBlock);
+  if (p.n > kPrepNMax) return RPT_ERR_UNSUPPORTED;
+  const int64_t blocks = ceil_div(p.vpad, kPrepTile);
   hipLaunchKernelGGL(prep_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, X, p.v, p.n, ldx, p,
                      tail, flags);
   RPT_CHECK_LAUNCH();

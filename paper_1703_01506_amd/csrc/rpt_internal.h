@@ -157,10 +157,11 @@ rpt_status naive_launch(const PrepX& p, const NaivePlan& plan, const uint8_t* la
 rpt_status sampled_launch(const PrepX& p, const uint8_t* labels, int64_t L, const int32_t* omega, int k,
                           const float* Tsrc, float* y, hipStream_t s);
 
-// Complete (Gram + FP64 Cholesky + solve).
-size_t complete_bytes(int64_t L, int r);
-rpt_status complete_launch(const float* U, int64_t v, int r, const int32_t* omega, int k, const float* y,
-                           int64_t L, float* W, float* resid, int32_t* info, void* ws, hipStream_t s);
+// Complete (Gram + FP64 Cholesky + solve).  The sampled values come either from
+// y ([L][k]) or, when y is null, from rows of T: y[i][q] = Trows[i * ldT + omega[i][q]].
+rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, int k, const float* y,
+                        const float* Trows, int64_t ldT, const int32_t* trow, int64_t L, float* W, float* resid,
+                        int32_t* info, float* wnorm2, hipStream_t s);
 
 // Reconstruction filter + exact refine with noise (K7).
 size_t recon_bytes(int64_t v, int64_t L, int r);
@@ -168,8 +169,23 @@ rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_
                         uint64_t seed, int stream_id, const float* sigma_mu, float* out_max,
                         const float* Tmax_for_gap, float* gap_out, void* ws, hipStream_t s);
 
-// Orthonormalisation (Cholesky-QR2).
+// Orthonormalisation (one Cholesky-QR pass).
 size_t reorth_bytes(int64_t v, int r);
 rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hipStream_t s);
+
+// Training helpers (train.hip).
+rpt_status track_update_launch(float* U, int64_t v, int r, const int32_t* omega, int k, const float* resid,
+                               const float* W, const float* wnorm2, const int32_t* info, int64_t B, float gamma,
+                               hipStream_t s);
+rpt_status sigma_launch(const float* resid, int64_t n, double* sums, float* sigma_mu, hipStream_t s);
+rpt_status mu_launch(const float* vals, int n, int rule, float* sigma_mu, hipStream_t s);
+rpt_status literal_resid_launch(const float* T, const float* U, const float* W, int64_t v, int r, int64_t ell,
+                                float* out, hipStream_t s);
+
+// Masked loss (masked_loss.hip).
+rpt_status loss_fwd_launch(const float* U, int64_t v, int r, const float* W, int B, const int64_t* ptr, const int32_t* idx,
+                           const float* t, double* loss, float* resid, hipStream_t s);
+rpt_status loss_bwd_launch(const float* U, int64_t v, int r, const float* W, int B, const int64_t* ptr,
+                           const int32_t* idx, const float* e, float* dU, float* dW, hipStream_t s);
 
 }  // namespace rpt

@@ -97,7 +97,7 @@ def test_naive_tiny_edge_cases():
         labels = S.relabellings(L, n, n // 2, seed=8)
         ref = OT.naive_maxnull(X.astype(np.float64), labels)
         for prec in ("fp32", "split_bf16"):
-            assert_t_close(_run(torch, X, labels, n // 2, "signed", prec), ref, prec, f"max n={n} v={v}")
+            assert_t_close(_run(torch, X, labels, n // 2, "signed", prec), ref, prec, f"max n={n} v={v}", m=n // 2)
 
 
 @pytest.mark.parametrize("prec", ["split_bf16", "fp32"])

@@ -1,0 +1,221 @@
+"""GPU parity: RapidPT steps (Alg. 2) through the C ABI against the FP64 oracle.
+
+Every case feeds the same seeded inputs (relabellings, sampled sets, Gaussian
+start matrix) to both sides; the noise is drawn on both sides from the same
+counter-based generator."""
+import numpy as np
+import pytest
+
+import rpt_synth as S
+from gpu_util import announce, assert_t_close, torch_cuda
+from oracle import metrics as OM
+from oracle import philox as PH
+from oracle import rapidpt as OR
+from oracle import tstat as OT
+
+pytestmark = pytest.mark.gpu
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def test_sampled_tstat_balanced_and_unbalanced():
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    for (n, n1) in [(40, 20), (30, 11)]:
+        announce(f"sampled n={n} n1={n1}")
+        rng = np.random.default_rng(n)
+        v, L, k = 5003, 37, 301
+        X = (rng.normal(size=(v, n)) * 0.2 + 0.5).astype(np.float32)
+        labels = S.relabellings(L, n, n1, seed=3)
+        om = S.omega_sets(L, v, k, seed=4)
+        y = rpt.sampled_tstat(_dev(torch, X), _dev(torch, labels), _dev(torch, om), n1=n1).cpu().numpy()
+        X64 = X.astype(np.float64)
+        ref = np.stack([OT.tstat(X64[om[i]], labels[i] == 1) for i in range(L)])
+        assert_t_close(y, ref, "fp32", "y")
+
+
+@pytest.mark.parametrize("r,k", [(7, 40), (32, 100), (100, 875), (128, 300)])
+def test_complete_least_squares(r, k):
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce(f"complete r={r} k={k}")
+    rng = np.random.default_rng(r)
+    v, L = 6000, 23
+    U = OR.orthonormalize(rng.normal(size=(v, r)))
+    om = S.omega_sets(L, v, k, seed=5)
+    y = rng.normal(size=(L, k))
+    W, info, resid = rpt.complete(_dev(torch, U.astype(np.float32)), _dev(torch, om),
+                                  _dev(torch, y.astype(np.float32)), return_resid=True)
+    W = W.cpu().numpy()
+    resid = resid.cpu().numpy()
+    assert (info.cpu().numpy() == 0).all()
+    U32 = U.astype(np.float32).astype(np.float64)
+    for i in range(L):
+        wref = OR.complete(U32, om[i], y[i].astype(np.float32).astype(np.float64))
+        assert np.linalg.norm(W[i] - wref) <= 1e-4 * np.linalg.norm(wref)
+        eref = y[i] - U32[om[i]] @ wref
+        assert np.linalg.norm(resid[i] - eref) <= 1e-4 * np.linalg.norm(y[i])
+
+
+def test_complete_reports_rank_deficiency():
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce("complete singular")
+    rng = np.random.default_rng(1)
+    v, r, k = 500, 8, 20
+    U = OR.orthonormalize(rng.normal(size=(v, r))).astype(np.float32)
+    U[:100] = 0.0                       # sampled rows all zero: G = 0
+    om = np.stack([np.arange(20), np.arange(20, 40)]).astype(np.int32)
+    om[1] = np.sort(rng.choice(np.arange(100, 500), 20, replace=False))
+    y = rng.normal(size=(2, k)).astype(np.float32)
+    W, info = rpt.complete(_dev(torch, U), _dev(torch, om), _dev(torch, y))
+    info = info.cpu().numpy()
+    assert info[0] >= 1 and info[1] == 0
+    assert (W.cpu().numpy()[0] == 0).all()
+
+
+@pytest.mark.parametrize("v,r", [(5000, 64), (250_000, 100), (1000, 128), (37, 5)])
+def test_reorth_is_positive_qr(v, r):
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce(f"reorth v={v} r={r}")
+    A = S.gaussian_matrix(v, r, seed=7).astype(np.float32)
+    Ud = _dev(torch, A.copy())
+    info = rpt.reorth(Ud)
+    U = Ud.cpu().numpy().astype(np.float64)
+    assert int(info.cpu().numpy()[0]) == 0
+    np.testing.assert_allclose(U.T @ U, np.eye(r), atol=2e-5)
+    Q = OR.orthonormalize(A.astype(np.float64))
+    assert np.abs(U - Q).max() <= 2e-5 * max(1.0, np.abs(Q).max() * np.sqrt(v / r))
+
+
+def _recover_case(torch, X, labels, U, sigma, mu, om, seed, col0, idx=None):
+    import paper_1703_01506_amd as rpt
+    sm = torch.tensor([sigma, mu], dtype=torch.float32, device="cuda")
+    got, info, W = rpt.recover_maxnull(_dev(torch, X), _dev(torch, labels), _dev(torch, U.astype(np.float32)), sm,
+                                       _dev(torch, om), seed, col0=col0, return_W=True)
+    got = got.cpu().numpy()
+    assert (info.cpu().numpy() == 0).all()
+    X64 = X.astype(np.float64)
+    U64 = U.astype(np.float32).astype(np.float64)
+    idx = range(labels.shape[0]) if idx is None else idx
+    ref = np.array([OR.recover_column(X64, labels[j] == 1, U64, float(np.float32(sigma)), float(np.float32(mu)),
+                                      om[j], seed, col0 + j)[0] for j in idx])
+    return got[list(idx)], ref
+
+
+def test_recover_small_with_noise():
+    torch = torch_cuda()
+    announce("recover small")
+    rng = np.random.default_rng(21)
+    n, v, L, r, k = 20, 4001, 70, 19, 120
+    X = rng.normal(size=(v, n)).astype(np.float32)
+    labels = S.relabellings(L, n, n // 2, seed=22)
+    U = OR.orthonormalize(rng.normal(size=(v, r)))
+    om = S.omega_sets(L, v, k, seed=23)
+    for sigma, mu in [(0.0, 0.0), (0.05, 0.3), (0.8, -0.2)]:
+        got, ref = _recover_case(torch, X, labels, U, sigma, mu, om, seed=2017, col0=300)
+        np.testing.assert_allclose(got, ref, atol=2e-4, rtol=0)
+
+
+def test_recover_full_size_sampled():
+    """v = 250,000 smoothed volume, n = 100, r = 100, |Omega| = 875 (0.35%),
+    9,700 recovered columns as in the benchmark; 6 columns recomputed by the
+    oracle one by one (full-length noise draw and maximum)."""
+    torch = torch_cuda()
+    announce("recover full size")
+    X = S.smoothed_volumes(100, 250_000, seed=1703)
+    labels = S.relabellings(9_700, 100, 50, seed=77)
+    U = OR.orthonormalize(S.gaussian_matrix(250_000, 100, seed=3))
+    om = S.omega_sets(9_700, 250_000, 875, seed=2017)
+    idx = [0, 1, 4_321, 7_000, 9_698, 9_699]
+    got, ref = _recover_case(torch, X, labels, U, 0.0123, 0.2, om, seed=2017, col0=300, idx=idx)
+    np.testing.assert_allclose(got, ref, atol=5e-4, rtol=0)
+
+
+def _train_inputs(n=20, v=3001, ell=30, r=12, k=150, passes=3, seed=31):
+    X, _ = S.iid_volumes(n, v, n // 2, signal_frac=0.02, shift=0.5, seed=seed)
+    X = X.astype(np.float32)
+    tl = S.relabellings(ell, n, n // 2, seed=seed + 1)
+    U0 = S.gaussian_matrix(v, r, seed=seed + 2).astype(np.float32)
+    omt = S.omega_sets(passes * ell, v, k, seed=seed + 3)
+    oms = S.omega_sets(ell, v, k, seed=seed + 4)
+    return X, tl, U0, omt, oms
+
+
+@pytest.mark.parametrize("batch", [30, 7])
+def test_train_subspace_matches_oracle(batch):
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce(f"train batch={batch}")
+    passes, seed = 3, 2017
+    X, tl, U0, omt, oms = _train_inputs(passes=passes)
+    out = rpt.train_subspace(_dev(torch, X), _dev(torch, tl), _dev(torch, U0), _dev(torch, omt), _dev(torch, oms),
+                             passes=passes, seed=seed, batch=batch, prec="fp32", return_T=True)
+    U = out["U"].cpu().numpy().astype(np.float64)
+    sigma, mu = [float(x) for x in out["sigma_mu"].cpu().numpy()]
+    T_ex = OT.tmatrix(X.astype(np.float64), tl)
+    assert_t_close(out["T_ex"].cpu().numpy(), T_ex, "fp32", "T_ex")
+    assert_t_close(out["train_max"].cpu().numpy(), T_ex.max(axis=1), "fp32", "train_max")
+    Uo = OR.train_subspace(T_ex, U0.astype(np.float64), omt, passes, batch=batch)
+    so, muo, _ = OR.sigma_mu(T_ex, Uo, oms, seed)
+    np.testing.assert_allclose(U.T @ U, np.eye(U.shape[1]), atol=5e-5)
+    assert np.abs(U @ U.T - Uo @ Uo.T).max() < 2e-4
+    assert abs(sigma - so) <= 1e-3 * so
+    assert abs(mu - muo) <= 2e-3
+
+
+def test_rapidpt_end_to_end_gates():
+    """Alg. 2 end to end on the simulated design (n = 20, v = 10,000, 2% of
+    voxels shifted by 0.5): l = 100 training columns, 6 passes, eta = 2%
+    (200 sampled voxels), L = 1,000.  Gates: KL(oracle || GPU) < 1e-3 and the
+    alpha = 0.05 threshold within 1%."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce("rapidpt end to end")
+    n, v, L, ell, r, passes, seed = 20, 10_000, 1_000, 100, 19, 6, 2017
+    k = S.omega_count(v, 20_000)
+    X, _ = S.iid_volumes(n, v, n // 2, signal_frac=0.02, shift=0.5, seed=1703)
+    X = X.astype(np.float32)
+    labels = S.relabellings(L, n, n // 2, seed=1506)
+    U0 = S.gaussian_matrix(v, r, seed=3).astype(np.float32)
+    omt = S.omega_sets(passes * ell, v, k, seed=41)
+    oms = S.omega_sets(ell, v, k, seed=42)
+    omr = S.omega_sets(L - ell, v, k, seed=43)
+    h, tr, info = rpt.rapidpt_maxnull(_dev(torch, X), _dev(torch, labels[:ell]), _dev(torch, labels[ell:]),
+                                      _dev(torch, U0), _dev(torch, omt), _dev(torch, oms), _dev(torch, omr),
+                                      passes=passes, seed=seed, prec="fp32")
+    h = h.cpu().numpy()
+    assert (info.cpu().numpy() == 0).all()
+    href, Uo, so, muo = OR.rapidpt_maxnull(X.astype(np.float64), labels[:ell], labels[ell:], U0.astype(np.float64),
+                                           omt, oms, omr, passes, seed)
+    assert OM.kl_divergence(href, h) < 1e-3
+    t_ref, t_gpu = OM.threshold(href, 0.05), OM.threshold(h, 0.05)
+    assert abs(t_gpu - t_ref) <= 0.01 * abs(t_ref)
+    np.testing.assert_allclose(h, href, atol=5e-3, rtol=0)
+
+
+def test_masked_loss_forward_backward():
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    from oracle import masked_loss as OL
+    announce("masked loss")
+    rng = np.random.default_rng(51)
+    v, r, B = 2003, 40, 13
+    sizes = rng.integers(5, 60, size=B)
+    ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    idx = np.concatenate([np.sort(rng.choice(v, s_, replace=False)) for s_ in sizes]).astype(np.int32)
+    U = rng.normal(size=(v, r)).astype(np.float32) * 0.05
+    W = rng.normal(size=(r, B)).astype(np.float32)
+    t = rng.normal(size=ptr[-1]).astype(np.float32)
+    Ud, Wd = _dev(torch, U), _dev(torch, W)
+    loss, resid = rpt.masked_loss_fwd(Ud, Wd, _dev(torch, ptr), _dev(torch, idx), _dev(torch, t))
+    dU, dW = rpt.masked_loss_bwd(Ud, Wd, _dev(torch, ptr), _dev(torch, idx), resid)
+    U64, W64 = U.astype(np.float64), W.astype(np.float64)
+    fref = OL.loss(U64, W64, ptr, idx, t)
+    gU, gW = OL.grad(U64, W64, ptr, idx, t)
+    assert abs(float(loss.cpu().numpy()[0]) - fref) <= 1e-5 * fref
+    assert np.linalg.norm(dU.cpu().numpy() - gU) <= 1e-5 * np.linalg.norm(gU)
+    assert np.linalg.norm(dW.cpu().numpy() - gW) <= 1e-5 * np.linalg.norm(gW)
