@@ -74,9 +74,10 @@ typedef enum {
 } rpt_mu_rule;
 
 /* Noise streams of the counter-based generator (Philox4x32-10 + Box-Muller):
- * z(seed, stream, i, k) uses key (seed mod 2^32, seed >> 32) and counter
- * (k >> 2, i, stream, study); words 0,1 give voxels 4q, 4q+1 (cos, sin), words
- * 2,3 give 4q+2, 4q+3.  Each word x maps to u = ((x >> 8) + 0.5) 2^-24. */
+ * z(seed, stream, i, k) for column i and voxel k uses key (seed mod 2^32,
+ * seed >> 32) and counter (k, i >> 2, stream, study); words 0,1 give columns
+ * 4q, 4q+1 (cos, sin), words 2,3 give 4q+2, 4q+3.  Each word x maps to
+ * u = ((x >> 8) + 0.5) 2^-24 (so |z| < 5.8872). */
 #define RPT_STREAM_RECOVERY 2
 #define RPT_STREAM_TRAINING 4
 
@@ -85,6 +86,20 @@ const char* rpt_status_string(int status);
 int rpt_last_hip_error(void);
 /* Library version, major*10000 + minor*100 + patch. */
 int rpt_version(void);
+
+/* Per-stage timing, for profiling (off by default).  While enabled, each
+ * kernel stage of every call records a pair of HIP events on the caller's
+ * stream ("prep", "naive_contract", "sampled_t", "complete", "recon_fused",
+ * "recon_filter", "recon_refine", "reorth", "track_update", "sigma", ...).
+ * rpt_timing_query waits for the recorded events of one stage and returns the
+ * summed elapsed time in ms and the number of records (0 = found, -1 = no
+ * records, -2 = HIP error).  rpt_timing_stages writes the recorded stage
+ * names, comma separated, into buf and returns the full length.  Enabling
+ * timing is not meant for calls under HIP graph capture. */
+void rpt_timing_enable(int on);
+void rpt_timing_reset(void);
+int rpt_timing_query(const char* stage, double* total_ms, int64_t* count);
+int rpt_timing_stages(char* buf, size_t len);
 
 /* -------------------------------------------------------------------------
  * NaivePT -- Alg. 1 (Sec. 2.1).
@@ -99,7 +114,7 @@ int rpt_version(void);
  *   max_out  L FP32                                            (out)
  *   T_out    NULL, or L x v FP32: the full permutation testing matrix,
  *            row i = t map of relabelling i (for tests and training)   (out)
- * Requirements: v >= 1, 4 <= n <= 1024, 2 <= n1 <= n-2, L >= 0.
+ * Requirements: v >= 1, 4 <= n <= 128, 2 <= n1 <= n-2, L >= 0.
  * n1 != n - n1 (unbalanced designs) needs prec == RPT_FP32.
  * ------------------------------------------------------------------------- */
 size_t rpt_naive_workspace(int64_t v, int32_t n, int64_t L, int prec);

@@ -15,10 +15,11 @@ library and this oracle produce the same draw for the same (column, voxel):
 * Box-Muller (Box & Muller, 1958): from (u_a, u_b), z = sqrt(-2 ln u_a) times
   cos(2 pi u_b), and the sine for the second normal.
 
-Noise layout: key = (seed mod 2^32, seed >> 32); counter = (k >> 2, i, stream,
-study) for voxel k of column i.  Words (x0, x1) give the normals of voxels
-k = 4q and 4q+1 (cos, then sin), words (x2, x3) those of 4q+2 and 4q+3.
-Since u >= 2^-25, |z| <= sqrt(50 ln 2) < 5.8872 for every draw.
+Noise layout: key = (seed mod 2^32, seed >> 32); counter = (k, i >> 2, stream,
+study) for voxel k of column i, so one call serves four consecutive columns at
+one voxel.  Words (x0, x1) give the normals of columns i = 4q and 4q+1 (cos,
+then sin), words (x2, x3) those of 4q+2 and 4q+3.  Since u >= 2^-25,
+|z| <= sqrt(50 ln 2) < 5.8872 for every draw.
 
 Pins (tests/test_oracle_philox.py): the published Random123 known-answer
 vectors for Philox4x32-10, the uniform map's range, moments and a
@@ -69,15 +70,13 @@ def uniform_from_word(x) -> np.ndarray:
 
 def normals(seed: int, stream: int, i: int, k, study: int = 0) -> np.ndarray:
     """z(seed, stream, i, k) for an array of voxel indices k (int)."""
-    k = np.asarray(k, dtype=np.int64)
-    q = (k >> 2).astype(np.uint64)
+    k = np.asarray(k, dtype=np.int64).astype(np.uint64)
+    i = int(i)
     key = (int(seed) & 0xFFFFFFFF, (int(seed) >> 32) & 0xFFFFFFFF)
-    w = philox4x32_10((q, np.uint64(i), np.uint64(stream), np.uint64(study)), key)
+    w = philox4x32_10((k, np.uint64(i >> 2), np.uint64(stream), np.uint64(study)), key)
     u = uniform_from_word(w)                      # (4, ...)
-    lane = (k & 3)
-    first = lane < 2                             # words 0,1 or words 2,3
-    ua = np.where(first, u[0], u[2])
-    ub = np.where(first, u[1], u[3])
+    sel = i & 3
+    ua, ub = (u[0], u[1]) if sel < 2 else (u[2], u[3])
     rad = np.sqrt(-2.0 * np.log(ua))
     ang = 2.0 * np.pi * ub
-    return np.where((lane & 1) == 0, rad * np.cos(ang), rad * np.sin(ang))
+    return rad * np.cos(ang) if (sel & 1) == 0 else rad * np.sin(ang)

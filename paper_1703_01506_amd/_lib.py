@@ -20,6 +20,10 @@ SIGNATURES = {
     "rpt_status_string": (C.c_char_p, [_int]),
     "rpt_last_hip_error": (_int, []),
     "rpt_version": (_int, []),
+    "rpt_timing_enable": (None, [_int]),
+    "rpt_timing_reset": (None, []),
+    "rpt_timing_query": (_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
+    "rpt_timing_stages": (_int, [C.c_char_p, _sz]),
     "rpt_naive_workspace": (_sz, [_i64, _i32, _i64, _int]),
     "rpt_naive_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _int, _int, _p, _p, _p, _sz, _p]),
     "rpt_sampled_tstat_workspace": (_sz, [_i64, _i32]),

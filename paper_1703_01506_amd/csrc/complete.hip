@@ -11,6 +11,7 @@
 // right-looking Cholesky in FP64; two triangular solves in one wave give w.
 // A non-positive pivot at step j sets info[i] = j + 1 and w_i = 0.
 // Optionally the residual y - U_O w is written (FP32 dot products).
+#include "lds_linalg.h"
 #include "rpt_internal.h"
 
 namespace rpt {
@@ -18,8 +19,8 @@ namespace rpt {
 namespace {
 
 constexpr int kRMax = 128;           // basis rank handled in LDS
-constexpr int kChunk = 32;           // sampled rows per LDS stage
-constexpr int kStageLd = 40;         // bf16 per staged column (32 + pad)
+constexpr int kChunk = 64;           // sampled rows per LDS stage
+constexpr int kStageLd = 72;         // bf16 per staged column (64 + pad: conflict-free 16-byte reads)
 
 struct CompleteArgs {
   const float* U;
@@ -27,7 +28,7 @@ struct CompleteArgs {
   int r;
   const int32_t* omega;
   int k;
-  const float* y;       // [L][k]  (or nullptr when yT is used)
+  const float* y;       // [L][k]  (or nullptr when Trows is used)
   const float* Trows;   // alternative source: y[i][q] = Trows[trow(i) * ldT + omega[i][q]]
   int64_t ldT;
   const int32_t* trow;  // row of Trows for column i (nullptr: row i)
@@ -37,8 +38,6 @@ struct CompleteArgs {
   int32_t* info;        // [L]
   float* wnorm2;        // [L] |w|^2 (or nullptr)
 };
-
-__device__ __forceinline__ int tri(int i, int c) { return (i * (i + 1)) / 2 + c; }
 
 __device__ __forceinline__ float y_at(const CompleteArgs& a, int64_t i, int q) {
   if (a.y) return a.y[i * a.k + q];
@@ -50,11 +49,12 @@ __device__ __forceinline__ float y_at(const CompleteArgs& a, int64_t i, int q) {
 template <int RT>
 __global__ __launch_bounds__(kBlock) void complete_kernel(CompleteArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  // stage: UT_hi[kRMax][kStageLd] bf16, UT_lo[...], ybuf[kChunk] f32
+  // stage: UT_hi[kRMax][kStageLd] bf16, UT_lo[...], ybuf[kChunk] f32, ibuf[kChunk] i32
   uint16_t* uth = reinterpret_cast<uint16_t*>(smem);
   uint16_t* utl = uth + kRMax * kStageLd;
   float* ybuf = reinterpret_cast<float*>(utl + kRMax * kStageLd);
-  // factor phase (aliases the stage): G64 packed lower [r(r+1)/2], diag[r], rhs[r]
+  int* ibuf = reinterpret_cast<int*>(ybuf + kChunk);
+  // factor phase (aliases the stage): G64 packed lower [r(r+1)/2], diag[kRMax], rhs[kRMax], bpart[2][kRMax]
   double* G64 = reinterpret_cast<double*>(smem);
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, col = lane & 31;
@@ -65,25 +65,33 @@ __global__ __launch_bounds__(kBlock) void complete_kernel(CompleteArgs a) {
   f32x16 acc[RT];
 #pragma unroll
   for (int t = 0; t < RT; ++t) acc[t] = f32x16{};
-  // b: thread t owns column ac = t & 127 for rows of parity t >> 7
+  // thread t gathers column ac = t & 127 of the rows of parity t >> 7; b
+  // accumulates from the FP32 values in FP64
   const int ac = tid & (kRMax - 1), par = tid >> 7;
   double bacc = 0.0;
 
   for (int c0 = 0; c0 < k; c0 += kChunk) {
     __syncthreads();
-    if (tid < kChunk) ybuf[tid] = (c0 + tid < k) ? y_at(a, i, c0 + tid) : 0.0f;
+    if (tid < kChunk) {
+      const bool in = c0 + tid < k;
+      const int64_t row = in ? om[c0 + tid] : -1;
+      ibuf[tid] = (row >= 0 && row < a.v) ? static_cast<int>(row) : -1;  // out-of-range: zero row
+      ybuf[tid] = in ? y_at(a, i, c0 + tid) : 0.0f;
+    }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = par; kk < kChunk; kk += 2) {
-      float x = 0.0f;
-      if (c0 + kk < k && ac < r) {
-        const int64_t row = om[c0 + kk];
-        if (row >= 0 && row < a.v) x = a.U[row * r + ac];  // out-of-range index: row treated as zero
-      }
-      const uint16_t hi = f2bf(x);
+    float x[kChunk / 2];
+#pragma unroll
+    for (int m = 0; m < kChunk / 2; ++m) {
+      const int row = ibuf[par + 2 * m];
+      x[m] = (row >= 0 && ac < r) ? a.U[static_cast<int64_t>(row) * r + ac] : 0.0f;
+    }
+#pragma unroll
+    for (int m = 0; m < kChunk / 2; ++m) {
+      const int kk = par + 2 * m;
+      const uint16_t hi = f2bf(x[m]);
       uth[ac * kStageLd + kk] = hi;
-      utl[ac * kStageLd + kk] = f2bf(x - bf2f(hi));
-      bacc += static_cast<double>(x) * ybuf[kk];
+      utl[ac * kStageLd + kk] = f2bf(x[m] - bf2f(hi));
+      bacc += static_cast<double>(x[m]) * ybuf[kk];
     }
     __syncthreads();
     if (wave < RT) {
@@ -115,36 +123,14 @@ __global__ __launch_bounds__(kBlock) void complete_kernel(CompleteArgs a) {
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int row = wave * 32 + mfma_row(e, h), cc = t * 32 + col;
-        if (row < r && cc <= row) G64[tri(row, cc)] = static_cast<double>(acc[t][e]);
+        if (row < r && cc <= row) G64[ptri(row, cc)] = static_cast<double>(acc[t][e]);
       }
   }
   bpart[par * kRMax + ac] = bacc;
   __syncthreads();
   if (tid < r) rhs[tid] = bpart[tid] + bpart[kRMax + tid];
 
-  // right-looking Cholesky, FP64
-  __shared__ int fail;
-  if (tid == 0) fail = 0;
-  for (int j = 0; j < r; ++j) {
-    __syncthreads();
-    const double piv = G64[tri(j, j)];
-    if (!(piv > 0.0)) {
-      if (tid == 0) fail = j + 1;
-      break;
-    }
-    const double d = sqrt(piv);
-    const double dinv = 1.0 / d;
-    for (int ii = j + 1 + tid; ii < r; ii += kBlock) G64[tri(ii, j)] *= dinv;
-    if (tid == 0) diag[j] = d;
-    __syncthreads();
-    const int m = r - j - 1;
-    for (int t = tid; t < m * m; t += kBlock) {
-      const int ii = j + 1 + t / m, cc = j + 1 + t % m;
-      if (cc <= ii) G64[tri(ii, cc)] -= G64[tri(ii, j)] * G64[tri(cc, j)];
-    }
-  }
-  __syncthreads();
-  const int failed = fail;
+  const int failed = lds_cholesky(G64, diag, r);
   float* Wi = a.W + i * r;
   if (failed) {
     for (int c = tid; c < r; c += kBlock) Wi[c] = 0.0f;
@@ -156,27 +142,9 @@ __global__ __launch_bounds__(kBlock) void complete_kernel(CompleteArgs a) {
       for (int q = tid; q < k; q += kBlock) a.resid[i * k + q] = y_at(a, i, q);
     return;
   }
-  // triangular solves in wave 0: lane owns rows lane and lane + 64
   if (wave == 0) {
-    double z0 = lane < r ? rhs[lane] : 0.0, z1 = lane + 64 < r ? rhs[lane + 64] : 0.0;
-    for (int j = 0; j < r; ++j) {  // L z = b
-      const double own = (j < 64) ? z0 : z1;
-      const double zj = __shfl(own, j & 63, 64) / diag[j];
-      if (lane == (j & 63)) {
-        if (j < 64) z0 = zj; else z1 = zj;
-      }
-      if (lane > j && lane < r) z0 -= G64[tri(lane, j)] * zj;
-      if (lane + 64 > j && lane + 64 < r) z1 -= G64[tri(lane + 64, j)] * zj;
-    }
-    for (int j = r - 1; j >= 0; --j) {  // L^T w = z
-      const double own = (j < 64) ? z0 : z1;
-      const double wj = __shfl(own, j & 63, 64) / diag[j];
-      if (lane == (j & 63)) {
-        if (j < 64) z0 = wj; else z1 = wj;
-      }
-      if (lane < j) z0 -= G64[tri(j, lane)] * wj;
-      if (lane + 64 < j) z1 -= G64[tri(j, lane + 64)] * wj;
-    }
+    double z0, z1;
+    wave_chol_solve(G64, diag, rhs, r, z0, z1);
     double nrm = 0.0;
     if (lane < r) {
       Wi[lane] = static_cast<float>(z0);
@@ -209,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void complete_kernel(CompleteArgs a) {
 }
 
 size_t smem_bytes(int r) {
-  const size_t stage = 2 * kRMax * kStageLd * sizeof(uint16_t) + kChunk * sizeof(float);
+  const size_t stage = 2 * kRMax * kStageLd * sizeof(uint16_t) + kChunk * (sizeof(float) + sizeof(int));
   const size_t factor = (static_cast<size_t>(r) * (r + 1) / 2 + 4 * kRMax) * sizeof(double);
   return stage > factor ? stage : factor;
 }
@@ -231,7 +199,13 @@ rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, 
     default: fn = reinterpret_cast<void*>(&complete_kernel<4>); break;
   }
   const size_t sm = smem_bytes(r);
+  static bool attr_set[4] = {false, false, false, false};
+  if (!attr_set[RT - 1]) {
+    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem_bytes(kRMax)));
+    attr_set[RT - 1] = true;
+  }
   void* args[] = {&a};
+  RPT_STAGE("complete", s);
   hipError_t e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(L)), dim3(kBlock), args, sm, s);
   if (e != hipSuccess) {
     set_hip_error(e);

@@ -81,6 +81,7 @@ rpt_status loss_fwd_launch(const float* U, int64_t v, int r, const float* W, int
   hipLaunchKernelGGL(zero_loss_kernel, dim3(1), dim3(1), 0, s, loss);
   RPT_CHECK_LAUNCH();
   if (B == 0) return RPT_OK;
+  RPT_STAGE("masked_loss_fwd", s);
   hipLaunchKernelGGL(loss_fwd_kernel, dim3(B), dim3(kBlock), 0, s, U, v, r, W, B, ptr, idx, t, loss, resid);
   RPT_CHECK_LAUNCH();
   return RPT_OK;
@@ -94,6 +95,7 @@ rpt_status loss_bwd_launch(const float* U, int64_t v, int r, const float* W, int
   hipLaunchKernelGGL(fill_zero_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, dU, n);
   RPT_CHECK_LAUNCH();
   if (B == 0) return RPT_OK;
+  RPT_STAGE("masked_loss_bwd", s);
   hipLaunchKernelGGL(loss_bwd_kernel, dim3(B), dim3(kBlock), 0, s, U, v, r, W, B, ptr, idx, e, dU, dW);
   RPT_CHECK_LAUNCH();
   return RPT_OK;

@@ -396,12 +396,17 @@ rpt_status naive_launch(const PrepX& p, const NaivePlan& pl, const uint8_t* labe
   if (!fn) return RPT_ERR_UNSUPPORTED;
   const unsigned blocks = static_cast<unsigned>(pl.pg) * static_cast<unsigned>(pl.nc);
   void* args[] = {&a};
-  hipError_t e = hipLaunchKernel(fn, dim3(blocks), dim3(kBlock), args, 0, s);
+  hipError_t e;
+  {
+    RPT_STAGE(a.store ? "naive_contract_store" : "naive_contract", s);
+    e = hipLaunchKernel(fn, dim3(blocks), dim3(kBlock), args, 0, s);
+  }
   if (e != hipSuccess) {
     set_hip_error(e);
     return RPT_ERR_HIP;
   }
   if (max_out) {
+    RPT_STAGE("naive_finalize", s);
     hipLaunchKernelGGL(naive_finalize_kernel, dim3(static_cast<unsigned>(ceil_div(L, kBlock))), dim3(kBlock), 0, s,
                        partial, pl.nc, L, m, unbal ? 0 : 1, max_out);
     RPT_CHECK_LAUNCH();

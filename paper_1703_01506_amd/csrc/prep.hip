@@ -199,6 +199,7 @@ PrepX prep_carve(Carver& c, int64_t v, int n, int n1, int flags) {
 rpt_status prep_launch(const PrepX& p, const float* X, int64_t ldx, int tail, int flags, hipStream_t s) {
   if (p.n > kPrepNMax) return RPT_ERR_UNSUPPORTED;
   const int64_t blocks = ceil_div(p.vpad, kPrepTile);
+  RPT_STAGE("prep", s);
   hipLaunchKernelGGL(prep_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, X, p.v, p.n, ldx, p,
                      tail, flags);
   RPT_CHECK_LAUNCH();

@@ -34,8 +34,10 @@ __device__ __forceinline__ void philox4x32_10(unsigned c[4], unsigned k0, unsign
       k0 += 0x9E3779B9u;
       k1 += 0xBB67AE85u;
     }
-    const unsigned lo0 = 0xD2511F53u * c[0], hi0 = __umulhi(0xD2511F53u, c[0]);
-    const unsigned lo1 = 0xCD9E8D57u * c[2], hi1 = __umulhi(0xCD9E8D57u, c[2]);
+    const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c[0];
+    const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c[2];
+    const unsigned lo0 = static_cast<unsigned>(p0), hi0 = static_cast<unsigned>(p0 >> 32);
+    const unsigned lo1 = static_cast<unsigned>(p1), hi1 = static_cast<unsigned>(p1 >> 32);
     const unsigned n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
     c[0] = n0;
     c[1] = lo1;
@@ -44,54 +46,76 @@ __device__ __forceinline__ void philox4x32_10(unsigned c[4], unsigned k0, unsign
   }
 }
 
+// Box-Muller on the hardware transcendental units: v_log_f32 is log2,
+// v_sin_f32 / v_cos_f32 take their argument in revolutions (sin(2 pi x)), the
+// exact form the transform needs; u lies in (0, 1).
+__device__ __forceinline__ float bm_radius(unsigned x) {
+  const float u = (static_cast<float>(x >> 8) + 0.5f) * 5.9604644775390625e-08f;  // 2^-24
+  return __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u));  // -2 ln 2 log2(u)
+}
+__device__ __forceinline__ float bm_turns(unsigned x) {
+  return (static_cast<float>(x >> 8) + 0.5f) * 5.9604644775390625e-08f;
+}
+
+// z(seed, stream, col, vox): counter (vox, col >> 2, stream, study); column
+// col & 3 selects the word pair (0,1) or (2,3) and cos or sin.
 __device__ __forceinline__ float noise_z(uint64_t seed, unsigned stream, unsigned col, int64_t vox, unsigned study) {
-  unsigned c[4] = {static_cast<unsigned>(vox >> 2), col, stream, study};
+  unsigned c[4] = {static_cast<unsigned>(vox), col >> 2, stream, study};
   philox4x32_10(c, static_cast<unsigned>(seed), static_cast<unsigned>(seed >> 32));
-  const int lane4 = static_cast<int>(vox & 3);
+  const int lane4 = static_cast<int>(col & 3);
   const unsigned xa = lane4 < 2 ? c[0] : c[2];
   const unsigned xb = lane4 < 2 ? c[1] : c[3];
-  const float ua = (static_cast<float>(xa >> 8) + 0.5f) * 5.9604644775390625e-08f;  // 2^-24
-  const float ub = (static_cast<float>(xb >> 8) + 0.5f) * 5.9604644775390625e-08f;
-  const float rad = sqrtf(-2.0f * logf(ua));
-  float sn, cs;
-  sincospif(2.0f * ub, &sn, &cs);
-  return rad * ((lane4 & 1) ? sn : cs);
+  const float t = bm_turns(xb);
+  return bm_radius(xa) * ((lane4 & 1) ? __builtin_amdgcn_sinf(t) : __builtin_amdgcn_cosf(t));
 }
 
 // ---------------------------------------------------------------- U preparation
-// ukb [ks][vpad][16] bf16 of U (zero past r and past v); umax >= max_k |U_k|_2
+// ukb [ks][vpad][2][16] bf16: hi(U[k][16s+e]) then lo(...), zero past r and v;
+// umax >= max_k |U_k|_2
 __global__ void recon_init_kernel(unsigned* umax_bits) { *umax_bits = 0u; }
 
 __global__ __launch_bounds__(kBlock) void recon_prep_u_kernel(const float* __restrict__ U, int64_t v, int r,
                                                              int64_t vpad, int ks, uint16_t* __restrict__ ukb,
                                                              unsigned* umax_bits) {
-  // thread per voxel; for a fixed K block consecutive threads write
-  // consecutive 32-byte segments
   const int64_t vox = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   float nrm = 0.0f;
   if (vox < vpad) {
     const float* u = U + vox * r;
     for (int s = 0; s < ks; ++s) {
-      uint32_t w[8];
+      uint32_t wh[8], wl[8];
 #pragma unroll
       for (int e2 = 0; e2 < 8; ++e2) {
-        uint32_t pr = 0;
+        uint32_t ph = 0, pl = 0;
 #pragma unroll
         for (int hl = 0; hl < 2; ++hl) {
           const int c = 16 * s + 2 * e2 + hl;
           const float x = (vox < v && c < r) ? u[c] : 0.0f;
           nrm = fmaf(x, x, nrm);
-          pr |= static_cast<uint32_t>(f2bf(x)) << (16 * hl);
+          const uint16_t hi = f2bf(x);
+          ph |= static_cast<uint32_t>(hi) << (16 * hl);
+          pl |= static_cast<uint32_t>(f2bf(x - bf2f(hi))) << (16 * hl);
         }
-        w[e2] = pr;
+        wh[e2] = ph;
+        wl[e2] = pl;
       }
-      u32x4* d = reinterpret_cast<u32x4*>(ukb + (static_cast<size_t>(s) * vpad + vox) * 16);
-      d[0] = u32x4{w[0], w[1], w[2], w[3]};
-      d[1] = u32x4{w[4], w[5], w[6], w[7]};
+      u32x4* d = reinterpret_cast<u32x4*>(ukb + (static_cast<size_t>(s) * vpad + vox) * 32);
+      d[0] = u32x4{wh[0], wh[1], wh[2], wh[3]};
+      d[1] = u32x4{wh[4], wh[5], wh[6], wh[7]};
+      d[2] = u32x4{wl[0], wl[1], wl[2], wl[3]};
+      d[3] = u32x4{wl[4], wl[5], wl[6], wl[7]};
     }
   }
   nrm = wave_max(nrm);
   if ((threadIdx.x & 63) == 0) atomicMax(umax_bits, __float_as_uint(sqrtf(nrm) * 1.000001f));
+}
+
+// Path choice made on the device (sigma is a device value): exact pruning pays
+// off only when the candidate band 2 Z sigma is narrow; otherwise every voxel
+// needs its noise draw and the fused kernel draws them alongside the
+// contraction.  Both paths compute the same maximum.
+constexpr float kPruneBand = 0.5f;
+__global__ void recon_decide_kernel(const float* sigma_mu, int* path) {
+  *path = (2.0f * kZBound * sigma_mu[0] <= kPruneBand) ? 1 : 0;
 }
 
 // ---------------------------------------------------------------- filter
@@ -102,10 +126,12 @@ struct FilterArgs {
   int64_t v, vpad, vt, L;
   int tpc, pg, nc;
   float* smax;  // [L][nc * 32]
+  const int* path;
 };
 
 template <int KS, int PT>
 __global__ __launch_bounds__(kBlock) void recon_filter_kernel(FilterArgs a) {
+  if (*a.path != 1) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, col = lane & 31;
   const int b = blockIdx.x, xcd = b & 7, j = b >> 3;
   const int pg = j % a.pg;
@@ -140,10 +166,10 @@ __global__ __launch_bounds__(kBlock) void recon_filter_kernel(FilterArgs a) {
 
   const int64_t t0 = static_cast<int64_t>(chunk) * a.tpc;
   const int64_t t1 = t0 + a.tpc < a.vt ? t0 + a.tpc : a.vt;
-  const size_t kstride = static_cast<size_t>(a.vpad) * 16;
+  const size_t kstride = static_cast<size_t>(a.vpad) * 32;
   u32x4 Bc[KS], Bn[KS];
   auto load = [&](u32x4* B, int64_t t) {
-    const uint16_t* bp = a.ukb + static_cast<size_t>(t * 32 + col) * 16 + h * 8;
+    const uint16_t* bp = a.ukb + static_cast<size_t>(t * 32 + col) * 32 + h * 8;
 #pragma unroll
     for (int s = 0; s < KS; ++s) B[s] = *reinterpret_cast<const u32x4*>(bp + s * kstride);
   };
@@ -189,6 +215,7 @@ __global__ __launch_bounds__(kBlock) void recon_filter_kernel(FilterArgs a) {
 
 // ---------------------------------------------------------------- refine
 struct RefineArgs {
+  const int* path;
   const float* U;
   const float* W;
   int64_t v, vt, L;
@@ -206,6 +233,7 @@ struct RefineArgs {
 };
 
 __global__ __launch_bounds__(kBlock) void recon_refine_kernel(RefineArgs a) {
+  if (*a.path != 1) return;
   __shared__ float wsh[4][kRMaxRefine];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 4 + wave;
@@ -258,6 +286,181 @@ __global__ __launch_bounds__(kBlock) void recon_refine_kernel(RefineArgs a) {
   }
 }
 
+// ---------------------------------------------------------------- fused path
+// Reconstruction on the matrix cores as hi.hi + hi.lo + lo.hi (W and U split
+// into BF16 halves, FP32 accumulation), the noise of every element, and the
+// running maximum, in one pass.  Accumulator registers 4m..4m+3 of a lane hold
+// four consecutive columns 4q..4q+3 at one voxel: exactly the four normals of
+// one Philox call at counter (voxel, q, stream, 0).
+struct FusedArgs {
+  const uint16_t* ukb;
+  const float* W;
+  int r;
+  int64_t v, vpad, vt, L;
+  int tpc, pg, nc;
+  int64_t col0;
+  uint64_t seed;
+  unsigned stream;
+  const float* sigma_mu;
+  const int* path;
+  float* partial;  // [nc][L]
+};
+
+__device__ __forceinline__ void box_muller4(const unsigned c[4], float z[4]) {
+  const float r1 = bm_radius(c[0]), r2 = bm_radius(c[2]);
+  const float t1 = bm_turns(c[1]), t2 = bm_turns(c[3]);
+  z[0] = r1 * __builtin_amdgcn_cosf(t1);
+  z[1] = r1 * __builtin_amdgcn_sinf(t1);
+  z[2] = r2 * __builtin_amdgcn_cosf(t2);
+  z[3] = r2 * __builtin_amdgcn_sinf(t2);
+}
+
+template <int KS, int PT, bool ALIGNED>
+__global__ __launch_bounds__(kBlock) void recon_fused_kernel(FusedArgs a) {
+  if (*a.path != 0) return;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, col = lane & 31;
+  const int b = blockIdx.x, xcd = b & 7, j = b >> 3;
+  const int pg = j % a.pg;
+  const int chunk = xcd + 8 * (j / a.pg);
+  const int64_t pbase = static_cast<int64_t>(pg) * (4 * PT * 32) + static_cast<int64_t>(wave) * (PT * 32);
+  const float sigma = a.sigma_mu[0];
+  const unsigned k0 = static_cast<unsigned>(a.seed), k1 = static_cast<unsigned>(a.seed >> 32);
+
+  u32x4 Ah[PT][KS], Al[PT][KS];
+#pragma unroll
+  for (int p = 0; p < PT; ++p) {
+    const int64_t perm = pbase + p * 32 + col;
+    const bool valid = perm < a.L;
+    const float* wr = a.W + (valid ? perm : 0) * a.r;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      unsigned wh[4], wl[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        uint32_t ph = 0, pl = 0;
+#pragma unroll
+        for (int hl = 0; hl < 2; ++hl) {
+          const int c = 16 * s + 8 * h + 2 * q + hl;
+          const float x = (valid && c < a.r) ? wr[c] : 0.0f;
+          const uint16_t hi = f2bf(x);
+          ph |= static_cast<uint32_t>(hi) << (16 * hl);
+          pl |= static_cast<uint32_t>(f2bf(x - bf2f(hi))) << (16 * hl);
+        }
+        wh[q] = ph;
+        wl[q] = pl;
+      }
+      Ah[p][s] = u32x4{wh[0], wh[1], wh[2], wh[3]};
+      Al[p][s] = u32x4{wl[0], wl[1], wl[2], wl[3]};
+    }
+  }
+  float rm[PT][16];
+#pragma unroll
+  for (int p = 0; p < PT; ++p)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) rm[p][e] = -INFINITY;
+
+  const int64_t t0 = static_cast<int64_t>(chunk) * a.tpc;
+  const int64_t t1 = t0 + a.tpc < a.vt ? t0 + a.tpc : a.vt;
+  const size_t kstride = static_cast<size_t>(a.vpad) * 32;
+  u32x4 Bc[2 * KS], Bn[2 * KS];
+  auto load = [&](u32x4* B, int64_t t) {
+    const uint16_t* bp = a.ukb + static_cast<size_t>(t * 32 + col) * 32 + h * 8;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      B[2 * s] = *reinterpret_cast<const u32x4*>(bp + s * kstride);
+      B[2 * s + 1] = *reinterpret_cast<const u32x4*>(bp + s * kstride + 16);
+    }
+  };
+  auto body = [&](const u32x4* B, int64_t t) {
+    f32x16 acc[PT];
+#pragma unroll
+    for (int p = 0; p < PT; ++p) acc[p] = f32x16{};
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int p = 0; p < PT; ++p) {
+        acc[p] = mfma_bf16(Ah[p][s], B[2 * s], acc[p]);
+        acc[p] = mfma_bf16(Ah[p][s], B[2 * s + 1], acc[p]);
+        acc[p] = mfma_bf16(Al[p][s], B[2 * s], acc[p]);
+      }
+    const int64_t vox = t * 32 + col;
+    const bool ok = vox < a.v;
+#pragma unroll
+    for (int p = 0; p < PT; ++p)
+#pragma unroll
+      for (int m = 0; m < 4; ++m) {
+        const int64_t g = a.col0 + pbase + p * 32 + 8 * m + 4 * h;  // column of register 4m
+        float z[4];
+        if (ALIGNED) {
+          unsigned c[4] = {static_cast<unsigned>(vox), static_cast<unsigned>(g >> 2), a.stream, 0u};
+          philox4x32_10(c, k0, k1);
+          box_muller4(c, z);
+        } else {
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) z[jj] = noise_z(a.seed, a.stream, static_cast<unsigned>(g + jj), vox, 0u);
+        }
+#pragma unroll
+        for (int jj = 0; jj < 4; ++jj) {
+          const float val = fmaf(sigma, z[jj], acc[p][4 * m + jj]);
+          rm[p][4 * m + jj] = ok ? fmaxf(rm[p][4 * m + jj], val) : rm[p][4 * m + jj];
+        }
+      }
+  };
+  if (t0 < t1) load(Bc, t0);
+  for (int64_t t = t0; t < t1; t += 2) {
+    if (t + 1 < t1) load(Bn, t + 1);
+    body(Bc, t);
+    if (t + 1 >= t1) break;
+    if (t + 2 < t1) load(Bc, t + 2);
+    body(Bn, t + 1);
+  }
+#pragma unroll
+  for (int p = 0; p < PT; ++p)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      float x = rm[p][e];
+#pragma unroll
+      for (int off = 1; off < 32; off <<= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
+      rm[p][e] = x;
+    }
+  if (col == 0) {
+#pragma unroll
+    for (int p = 0; p < PT; ++p)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t perm = pbase + p * 32 + mfma_row(e, h);
+        if (perm < a.L) a.partial[static_cast<int64_t>(chunk) * a.L + perm] = rm[p][e];
+      }
+  }
+}
+
+__global__ void recon_fused_finalize_kernel(const float* __restrict__ partial, int nc, int64_t L,
+                                            const float* sigma_mu, const int* path, float* out,
+                                            const float* tmax, float* gap) {
+  if (*path != 0) return;
+  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  if (i >= L) return;
+  float m = partial[i];
+  for (int c = 1; c < nc; ++c) m = fmaxf(m, partial[static_cast<int64_t>(c) * L + i]);
+  if (out) out[i] = m + sigma_mu[1];
+  if (gap) gap[i] = tmax[i] - m;
+}
+
+template <int PT, bool AL>
+void* pick_fused(int ks) {
+  switch (ks) {
+    case 1: return reinterpret_cast<void*>(&recon_fused_kernel<1, PT, AL>);
+    case 2: return reinterpret_cast<void*>(&recon_fused_kernel<2, PT, AL>);
+    case 3: return reinterpret_cast<void*>(&recon_fused_kernel<3, PT, AL>);
+    case 4: return reinterpret_cast<void*>(&recon_fused_kernel<4, PT, AL>);
+    case 5: return reinterpret_cast<void*>(&recon_fused_kernel<5, PT, AL>);
+    case 6: return reinterpret_cast<void*>(&recon_fused_kernel<6, PT, AL>);
+    case 7: return reinterpret_cast<void*>(&recon_fused_kernel<7, PT, AL>);
+    case 8: return reinterpret_cast<void*>(&recon_fused_kernel<8, PT, AL>);
+    default: return nullptr;
+  }
+}
+
 template <int PT>
 void* pick_filter(int ks) {
   switch (ks) {
@@ -278,10 +481,10 @@ struct ReconPlan {
   int64_t vpad, vt;
 };
 
-ReconPlan recon_plan(int64_t v, int64_t L, int r) {
+ReconPlan recon_plan(int64_t v, int64_t L, int r, int pt) {
   ReconPlan pl;
   pl.ks = static_cast<int>(ceil_div(r, 16));
-  pl.pt = 4;
+  pl.pt = pt;
   pl.vpad = round_up(v, 32);
   pl.vt = pl.vpad / 32;
   const int64_t group = 4 * pl.pt * 32;
@@ -295,11 +498,17 @@ ReconPlan recon_plan(int64_t v, int64_t L, int r) {
   return pl;
 }
 
-void recon_carve(Carver& c, int64_t v, int64_t L, int r, uint16_t** ukb, float** smax, unsigned** umax) {
-  const ReconPlan pl = recon_plan(v, L, r);
-  *ukb = c.take<uint16_t>(static_cast<size_t>(pl.ks) * pl.vpad * 16);
-  *smax = c.take<float>(static_cast<size_t>(L > 0 ? L : 1) * pl.nc * 32);
+constexpr int kFilterPT = 4, kFusedPT = 2;
+
+void recon_carve(Carver& c, int64_t v, int64_t L, int r, uint16_t** ukb, float** smax, float** partial,
+                 unsigned** umax, int** path) {
+  const ReconPlan pf = recon_plan(v, L, r, kFilterPT);
+  const ReconPlan pu = recon_plan(v, L, r, kFusedPT);
+  *ukb = c.take<uint16_t>(static_cast<size_t>(pf.ks) * pf.vpad * 32);
+  *smax = c.take<float>(static_cast<size_t>(L > 0 ? L : 1) * pf.nc * 32);
+  *partial = c.take<float>(static_cast<size_t>(L > 0 ? L : 1) * pu.nc);
   *umax = c.take<unsigned>(64);
+  *path = c.take<int>(64);
 }
 
 }  // namespace
@@ -307,9 +516,10 @@ void recon_carve(Carver& c, int64_t v, int64_t L, int r, uint16_t** ukb, float**
 size_t recon_bytes(int64_t v, int64_t L, int r) {
   Carver c(nullptr);
   uint16_t* a;
-  float* b;
+  float *b, *b2;
   unsigned* d;
-  recon_carve(c, v, L, r, &a, &b, &d);
+  int* e;
+  recon_carve(c, v, L, r, &a, &b, &b2, &d, &e);
   return c.off;
 }
 
@@ -320,27 +530,56 @@ rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_
   if (r < 1 || r > kRMaxRefine) return RPT_ERR_UNSUPPORTED;
   Carver c(ws);
   uint16_t* ukb;
-  float* smax;
+  float *smax, *partial;
   unsigned* umax;
-  recon_carve(c, v, L, r, &ukb, &smax, &umax);
-  const ReconPlan pl = recon_plan(v, L, r);
+  int* path;
+  recon_carve(c, v, L, r, &ukb, &smax, &partial, &umax, &path);
+  const ReconPlan pl = recon_plan(v, L, r, kFilterPT);
+  const ReconPlan pu = recon_plan(v, L, r, kFusedPT);
 
+  RPT_STAGE("recon_total", s);
   hipLaunchKernelGGL(recon_init_kernel, dim3(1), dim3(1), 0, s, umax);
+  RPT_CHECK_LAUNCH();
+  hipLaunchKernelGGL(recon_decide_kernel, dim3(1), dim3(1), 0, s, sigma_mu, path);
   RPT_CHECK_LAUNCH();
   hipLaunchKernelGGL(recon_prep_u_kernel, dim3(static_cast<unsigned>(ceil_div(pl.vpad, kBlock))), dim3(kBlock), 0, s,
                      U, v, r, pl.vpad, pl.ks, ukb, umax);
   RPT_CHECK_LAUNCH();
 
-  FilterArgs fa{ukb, W, r, pl.ks, v, pl.vpad, pl.vt, L, pl.tpc, pl.pg, pl.nc, smax};
-  void* fn = pick_filter<4>(pl.ks);
+  // fused path (runs when the device decided path 0)
+  FusedArgs ua{ukb, W, r, v, pu.vpad, pu.vt, L, pu.tpc, pu.pg, pu.nc, col0, seed,
+               static_cast<unsigned>(stream_id), sigma_mu, path, partial};
+  void* ufn = (col0 % 4 == 0) ? pick_fused<kFusedPT, true>(pu.ks) : pick_fused<kFusedPT, false>(pu.ks);
+  if (!ufn) return RPT_ERR_UNSUPPORTED;
+  void* uargs[] = {&ua};
+  hipError_t e;
+  {
+    RPT_STAGE("recon_fused", s);
+    e = hipLaunchKernel(ufn, dim3(static_cast<unsigned>(pu.pg) * pu.nc), dim3(kBlock), uargs, 0, s);
+  }
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return RPT_ERR_HIP;
+  }
+  hipLaunchKernelGGL(recon_fused_finalize_kernel, dim3(static_cast<unsigned>(ceil_div(L, kBlock))), dim3(kBlock), 0,
+                     s, partial, pu.nc, L, sigma_mu, path, out_max, Tmax_for_gap, gap_out);
+  RPT_CHECK_LAUNCH();
+
+  // exact-pruning path (runs when the device decided path 1)
+  FilterArgs fa{ukb, W, r, pl.ks, v, pl.vpad, pl.vt, L, pl.tpc, pl.pg, pl.nc, smax, path};
+  void* fn = pick_filter<kFilterPT>(pl.ks);
   if (!fn) return RPT_ERR_UNSUPPORTED;
   void* args[] = {&fa};
-  hipError_t e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(pl.pg) * pl.nc), dim3(kBlock), args, 0, s);
+  {
+    RPT_STAGE("recon_filter", s);
+    e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(pl.pg) * pl.nc), dim3(kBlock), args, 0, s);
+  }
   if (e != hipSuccess) {
     set_hip_error(e);
     return RPT_ERR_HIP;
   }
   RefineArgs ra;
+  ra.path = path;
   ra.U = U;
   ra.W = W;
   ra.v = v;
@@ -362,6 +601,7 @@ rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_
   ra.out = out_max;
   ra.tmax = Tmax_for_gap;
   ra.gap = gap_out;
+  RPT_STAGE("recon_refine", s);
   hipLaunchKernelGGL(recon_refine_kernel, dim3(static_cast<unsigned>(ceil_div(L, 4))), dim3(kBlock), 0, s, ra);
   RPT_CHECK_LAUNCH();
   return RPT_OK;

@@ -39,6 +39,25 @@ void set_hip_error(hipError_t e);
   } while (0)
 
 // ---------------------------------------------------------------------------
+// per-stage timing (timing.hip): records HIP events around a kernel stage on
+// the stage's stream when timing is enabled through the C ABI.
+class StageScope {
+ public:
+  StageScope(const char* name, hipStream_t s);
+  ~StageScope();
+  StageScope(const StageScope&) = delete;
+  StageScope& operator=(const StageScope&) = delete;
+
+ private:
+  const char* name_;
+  hipStream_t s_;
+  hipEvent_t start_;
+};
+#define RPT_CAT2(a, b) a##b
+#define RPT_CAT(a, b) RPT_CAT2(a, b)
+#define RPT_STAGE(name, stream) ::rpt::StageScope RPT_CAT(rpt_stage_, __LINE__)(name, stream)
+
+// ---------------------------------------------------------------------------
 // workspace carving: every piece 256-byte aligned.  With base == nullptr the
 // carver only measures.
 struct Carver {

@@ -89,6 +89,7 @@ rpt_status sampled_launch(const PrepX& p, const uint8_t* labels, int64_t L, cons
   const int m = p.n / 2;
   a.fs = static_cast<float>(2.0 * sqrt((m - 1.0) / m));
   a.tm = static_cast<float>(2.0 / m);
+  RPT_STAGE("sampled_t", s);
   hipLaunchKernelGGL(sampled_kernel, dim3(static_cast<unsigned>(L)), dim3(kBlock), 0, s, a);
   RPT_CHECK_LAUNCH();
   return RPT_OK;

@@ -13,6 +13,7 @@
 // * sigma: sample standard deviation of the sampled-entry residuals (FP64).
 // * mu: mean of the per-column gaps (mean-gap rule) or the literal maximum
 //   residual of Alg. 2.
+#include "lds_linalg.h"
 #include "rpt_internal.h"
 
 namespace rpt {
@@ -20,8 +21,8 @@ namespace rpt {
 namespace {
 
 constexpr int kR = 128;          // rank bound
-constexpr int kStage = 32;       // rows per LDS stage
-constexpr int kLd = 40;          // bf16 per staged column
+constexpr int kStage = 64;       // rows per LDS stage
+constexpr int kLd = 72;          // bf16 per staged column (64 + pad)
 
 // ---------------------------------------------------------------- Gram partials
 template <int RT>
@@ -37,14 +38,19 @@ __global__ __launch_bounds__(kBlock) void gram_partial_kernel(const float* __res
   for (int t = 0; t < RT; ++t) acc[t] = f32x16{};
   const int ac = tid & (kR - 1), par = tid >> 7;
   for (int64_t c0 = r0; c0 < r1; c0 += kStage) {
+    float x[kStage / 2];
+#pragma unroll
+    for (int m = 0; m < kStage / 2; ++m) {
+      const int64_t row = c0 + par + 2 * m;
+      x[m] = (row < r1 && ac < r) ? U[row * r + ac] : 0.0f;
+    }
     __syncthreads();
-#pragma unroll 4
-    for (int kk = par; kk < kStage; kk += 2) {
-      float x = 0.0f;
-      if (c0 + kk < r1 && ac < r) x = U[(c0 + kk) * r + ac];
-      const uint16_t hi = f2bf(x);
+#pragma unroll
+    for (int m = 0; m < kStage / 2; ++m) {
+      const int kk = par + 2 * m;
+      const uint16_t hi = f2bf(x[m]);
       uth[ac * kLd + kk] = hi;
-      utl[ac * kLd + kk] = f2bf(x - bf2f(hi));
+      utl[ac * kLd + kk] = f2bf(x[m] - bf2f(hi));
     }
     __syncthreads();
     if (wave < RT) {
@@ -76,75 +82,51 @@ __global__ __launch_bounds__(kBlock) void gram_partial_kernel(const float* __res
   }
 }
 
-// Sum the partials in FP64, factor G = L L^T (packed lower triangle in LDS),
-// and write R^{-1} = L^{-T} transposed (RinvT[c][j] = Rinv[j][c] = Linv[c][j])
-// split into BF16 hi/lo.  Linv is built column by column in the FP64 scratch
-// `li` (r x r).  One workgroup.
-__device__ __forceinline__ int ptri(int i, int c) { return (i * (i + 1)) / 2 + c; }
+// G = sum of the partials, in FP64 (one thread per entry, coalesced)
+__global__ __launch_bounds__(kBlock) void gram_reduce_kernel(const float* __restrict__ part, int nblk, int r,
+                                                            double* __restrict__ G) {
+  const int idx = blockIdx.x * kBlock + threadIdx.x;
+  if (idx >= r * r) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += part[static_cast<int64_t>(b) * r * r + idx];
+  G[idx] = s;
+}
 
-__global__ __launch_bounds__(kBlock) void chol_rinv_kernel(const float* __restrict__ part, int nblk, int r,
-                                                          double* __restrict__ li, uint16_t* __restrict__ rinvT_hi,
+// Factor G = L L^T (FP64, LDS) and write R^{-1} = L^{-T} transposed
+// (RinvT[c][j] = Rinv[j][c] = Linv[c][j]) split into BF16 hi/lo.  A failed
+// factorisation writes the identity (U is left unchanged) and info = j + 1.
+__global__ __launch_bounds__(kBlock) void chol_rinv_kernel(const double* __restrict__ Gfull, int r,
+                                                          uint16_t* __restrict__ rinvT_hi,
                                                           uint16_t* __restrict__ rinvT_lo, int32_t* info) {
-  extern __shared__ double G[];  // packed lower, r(r+1)/2
-  __shared__ int fail;
-  const int tid = threadIdx.x;
+  extern __shared__ __align__(16) unsigned char sm[];
   const int ntri = r * (r + 1) / 2;
-  for (int idx = tid; idx < r * r; idx += kBlock) {
-    const int ii = idx / r, cc = idx - ii * r;
-    if (cc > ii) continue;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += part[static_cast<int64_t>(b) * r * r + idx];
-    G[ptri(ii, cc)] = s;
+  double* G = reinterpret_cast<double*>(sm);
+  double* diag = G + ntri;
+  float* Li = reinterpret_cast<float*>(diag + kR);  // [r][kR]
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < ntri; idx += kBlock) {
+    // invert ptri: row i with i(i+1)/2 <= idx
+    int i = static_cast<int>((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
+    while ((i + 1) * (i + 2) / 2 <= idx) ++i;
+    while (i * (i + 1) / 2 > idx) --i;
+    const int c = idx - i * (i + 1) / 2;
+    G[idx] = Gfull[i * r + c];
   }
-  (void)ntri;
-  if (tid == 0) fail = 0;
-  for (int j = 0; j < r; ++j) {
-    __syncthreads();
-    const double piv = G[ptri(j, j)];
-    if (!(piv > 0.0)) {
-      if (tid == 0) fail = j + 1;
-      break;
-    }
-    const double d = sqrt(piv), dinv = 1.0 / d;
-    __syncthreads();
-    if (tid == 0) G[ptri(j, j)] = d;
-    for (int ii = j + 1 + tid; ii < r; ii += kBlock) G[ptri(ii, j)] *= dinv;
-    __syncthreads();
-    const int m = r - j - 1;
-    for (int t = tid; t < m * m; t += kBlock) {
-      const int ii = j + 1 + t / m, cc = j + 1 + t % m;
-      if (cc <= ii) G[ptri(ii, cc)] -= G[ptri(ii, j)] * G[ptri(cc, j)];
-    }
-  }
-  __syncthreads();
-  const int failed = fail;
-  // Linv (lower): column c by forward substitution, one thread per column
-  for (int c = tid; c < r; c += kBlock) {
-    for (int ii = 0; ii < r; ++ii) {
-      double s;
-      if (failed) {
-        s = (ii == c) ? 1.0 : 0.0;  // leave U unchanged
-      } else if (ii < c) {
-        s = 0.0;
-      } else {
-        s = (ii == c) ? 1.0 : 0.0;
-        for (int jj = c; jj < ii; ++jj) s -= G[ptri(ii, jj)] * li[jj * r + c];
-        s /= G[ptri(ii, ii)];
-      }
-      li[ii * r + c] = s;
-    }
-  }
-  __threadfence_block();
+  const int failed = lds_cholesky(G, diag, r);
+  if (!failed) lds_tri_inverse(G, diag, r, Li, kR);
   __syncthreads();
   for (int idx = tid; idx < kR * kR; idx += kBlock) {
     const int c = idx / kR, j = idx - c * kR;
-    const float x = (c < r && j < r) ? static_cast<float>(li[c * r + j]) : 0.0f;
+    float x = 0.0f;
+    if (c < r && j < r) x = failed ? (c == j ? 1.0f : 0.0f) : Li[c * kR + j];
     const uint16_t hi = f2bf(x);
     rinvT_hi[idx] = hi;
     rinvT_lo[idx] = f2bf(x - bf2f(hi));
   }
   if (tid == 0 && info) *info = failed;
 }
+
+size_t chol_smem(int r) { return (static_cast<size_t>(r) * (r + 1) / 2 + kR) * sizeof(double) + r * kR * sizeof(float); }
 
 // U <- U R^{-1}, in place; one wave per 32-row tile.
 template <int KS>
@@ -158,19 +140,33 @@ __global__ __launch_bounds__(kBlock) void apply_rinv_kernel(float* __restrict__ 
   // A fragments: lane supplies U[v0 + col][16s + 8h + 0..7] (hi, lo)
   u32x4 Ah[KS], Al[KS];
   const int64_t vox = v0 + col;
+  const bool vec = (r & 3) == 0;
 #pragma unroll
   for (int s = 0; s < KS; ++s) {
+    const int cb = 16 * s + 8 * h;
+    float x[8];
+    if (vec && vox < v && cb + 8 <= r) {
+      const f32x4 p0 = *reinterpret_cast<const f32x4*>(U + vox * r + cb);
+      const f32x4 p1 = *reinterpret_cast<const f32x4*>(U + vox * r + cb + 4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        x[e] = p0[e];
+        x[4 + e] = p1[e];
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < 8; ++e) x[e] = (vox < v && cb + e < r) ? U[vox * r + cb + e] : 0.0f;
+    }
     unsigned wh[4], wl[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       uint32_t ph = 0, pl = 0;
 #pragma unroll
       for (int hl = 0; hl < 2; ++hl) {
-        const int c = 16 * s + 8 * h + 2 * q + hl;
-        const float x = (vox < v && c < r) ? U[vox * r + c] : 0.0f;
-        const uint16_t hi = f2bf(x);
+        const float xv = x[2 * q + hl];
+        const uint16_t hi = f2bf(xv);
         ph |= static_cast<uint32_t>(hi) << (16 * hl);
-        pl |= static_cast<uint32_t>(f2bf(x - bf2f(hi))) << (16 * hl);
+        pl |= static_cast<uint32_t>(f2bf(xv - bf2f(hi))) << (16 * hl);
       }
       wh[q] = ph;
       wl[q] = pl;
@@ -297,7 +293,7 @@ __global__ __launch_bounds__(kBlock) void literal_resid_max_kernel(const float* 
 }
 
 int gram_blocks(int64_t v) {
-  int64_t nb = ceil_div(v, 1024);
+  int64_t nb = ceil_div(v, 256);
   if (nb > 512) nb = 512;
   if (nb < 1) nb = 1;
   return static_cast<int>(nb);
@@ -319,11 +315,12 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
   Carver c(ws);
   const int nb = gram_blocks(v);
   float* part = c.take<float>(static_cast<size_t>(nb) * r * r);
-  double* li = c.take<double>(static_cast<size_t>(r) * r);
+  double* gfull = c.take<double>(static_cast<size_t>(r) * r);
   uint16_t* rth = c.take<uint16_t>(static_cast<size_t>(kR) * kR);
   uint16_t* rtl = c.take<uint16_t>(static_cast<size_t>(kR) * kR);
   const int RT = (r + 31) / 32;
   const int64_t rpb = round_up(ceil_div(v, nb), kStage);
+  RPT_STAGE("reorth", s);
   switch (RT) {
     case 1: hipLaunchKernelGGL(gram_partial_kernel<1>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
     case 2: hipLaunchKernelGGL(gram_partial_kernel<2>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
@@ -331,8 +328,16 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
     default: hipLaunchKernelGGL(gram_partial_kernel<4>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
   }
   RPT_CHECK_LAUNCH();
-  const size_t sm = static_cast<size_t>(r) * (r + 1) / 2 * sizeof(double);
-  hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(kBlock), sm, s, part, nb, r, li, rth, rtl, info);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(static_cast<unsigned>(ceil_div(static_cast<int64_t>(r) * r, kBlock))),
+                     dim3(kBlock), 0, s, part, nb, r, gfull);
+  RPT_CHECK_LAUNCH();
+  static bool attr_set = false;
+  if (!attr_set) {
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_rinv_kernel),
+                              hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(chol_smem(kR)));
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(kBlock), chol_smem(r), s, gfull, r, rth, rtl, info);
   RPT_CHECK_LAUNCH();
   const unsigned blocks = static_cast<unsigned>(ceil_div(ceil_div(v, 32), 4));
   const int KS = static_cast<int>(ceil_div(r, 16));
@@ -354,6 +359,7 @@ rpt_status track_update_launch(float* U, int64_t v, int r, const int32_t* omega,
                                const float* W, const float* wnorm2, const int32_t* info, int64_t B, float gamma,
                                hipStream_t s) {
   if (B == 0) return RPT_OK;
+  RPT_STAGE("track_update", s);
   hipLaunchKernelGGL(track_update_kernel, dim3(static_cast<unsigned>(B)), dim3(kBlock), 0, s, U, v, r, omega, k, resid,
                      W, wnorm2, info, gamma);
   RPT_CHECK_LAUNCH();
@@ -361,6 +367,7 @@ rpt_status track_update_launch(float* U, int64_t v, int r, const int32_t* omega,
 }
 
 rpt_status sigma_launch(const float* resid, int64_t n, double* sums, float* sigma_mu, hipStream_t s) {
+  RPT_STAGE("sigma", s);
   hipLaunchKernelGGL(zero_doubles_kernel, dim3(1), dim3(64), 0, s, sums, 2);
   RPT_CHECK_LAUNCH();
   int64_t blocks = ceil_div(n, kBlock);

@@ -115,23 +115,28 @@ def test_recover_small_with_noise():
     labels = S.relabellings(L, n, n // 2, seed=22)
     U = OR.orthonormalize(rng.normal(size=(v, r)))
     om = S.omega_sets(L, v, k, seed=23)
-    for sigma, mu in [(0.0, 0.0), (0.05, 0.3), (0.8, -0.2)]:
-        got, ref = _recover_case(torch, X, labels, U, sigma, mu, om, seed=2017, col0=300)
+    # sigma = 0 takes the exact-pruning path, the larger values the fused path;
+    # col0 = 301 exercises the per-element noise draw of unaligned columns
+    for sigma, mu, col0 in [(0.0, 0.0, 300), (0.01, 0.1, 300), (0.05, 0.3, 300), (0.8, -0.2, 300),
+                            (0.8, -0.2, 301)]:
+        got, ref = _recover_case(torch, X, labels, U, sigma, mu, om, seed=2017, col0=col0)
         np.testing.assert_allclose(got, ref, atol=2e-4, rtol=0)
 
 
-def test_recover_full_size_sampled():
+@pytest.mark.parametrize("sigma", [0.0123, 0.9])
+def test_recover_full_size_sampled(sigma):
     """v = 250,000 smoothed volume, n = 100, r = 100, |Omega| = 875 (0.35%),
     9,700 recovered columns as in the benchmark; 6 columns recomputed by the
-    oracle one by one (full-length noise draw and maximum)."""
+    oracle one by one (full-length noise draw and maximum).  The small sigma
+    takes the exact-pruning path, the large one the fused path."""
     torch = torch_cuda()
-    announce("recover full size")
+    announce(f"recover full size sigma={sigma}")
     X = S.smoothed_volumes(100, 250_000, seed=1703)
     labels = S.relabellings(9_700, 100, 50, seed=77)
     U = OR.orthonormalize(S.gaussian_matrix(250_000, 100, seed=3))
     om = S.omega_sets(9_700, 250_000, 875, seed=2017)
     idx = [0, 1, 4_321, 7_000, 9_698, 9_699]
-    got, ref = _recover_case(torch, X, labels, U, 0.0123, 0.2, om, seed=2017, col0=300, idx=idx)
+    got, ref = _recover_case(torch, X, labels, U, sigma, 0.2, om, seed=2017, col0=300, idx=idx)
     np.testing.assert_allclose(got, ref, atol=5e-4, rtol=0)
 
 

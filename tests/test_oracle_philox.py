@@ -30,6 +30,19 @@ def test_vectorised_matches_scalar():
         assert z[j] == PH.normals(123456789012345, PH.STREAM_RECOVERY, 17, np.array([k]))[0]
 
 
+def test_layout_four_columns_per_call():
+    """One Philox call at counter (k, i >> 2, stream, study) feeds columns
+    4q..4q+3 at voxel k, as cos/sin pairs of words (0,1) and (2,3)."""
+    seed, k, q = 99, 12345, 7
+    w = PH.philox4x32_10((k, q, PH.STREAM_RECOVERY, 0), (seed, 0))
+    u = PH.uniform_from_word(w)
+    r1, r2 = np.sqrt(-2 * np.log(u[0])), np.sqrt(-2 * np.log(u[2]))
+    expect = [r1 * np.cos(2 * np.pi * u[1]), r1 * np.sin(2 * np.pi * u[1]),
+              r2 * np.cos(2 * np.pi * u[3]), r2 * np.sin(2 * np.pi * u[3])]
+    got = [PH.normals(seed, PH.STREAM_RECOVERY, 4 * q + j, np.array([k]))[0] for j in range(4)]
+    np.testing.assert_allclose(got, expect, rtol=1e-15)
+
+
 def test_uniform_map_range():
     u = PH.uniform_from_word(np.array([0, 255, 256, 0xFFFFFFFF], dtype=np.uint64))
     assert u[0] == 0.5 * 2.0 ** -24 and u[1] == u[0]
