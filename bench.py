@@ -32,6 +32,9 @@ sys.path.insert(0, ROOT)
 METRIC = "max-null permutations/s, n=100 v=250k: RapidPT vs NaivePT on GPU, KL<1e-3"
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak
 PEAK_HBM_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rapidpt_step_n100_v250k_hbm_traffic.md")
+STAGE_KERNEL = {"complete": "complete_kernel", "recon_fused": "recon_fused_kernel",
+                "naive_contract": "naive_split_kernel", "sampled_t": "sampled_kernel"}
 
 
 def log(msg):
@@ -79,7 +82,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--passes", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     a = ap.parse_args()
+    if a.copy_calibration:
+        import torch
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        x.fill_(1.0)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}))
+        return
     if a.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU layout is "
               "described in DESIGN.md and not built", file=sys.stderr)
@@ -145,17 +160,18 @@ def main():
     log(f"naivept {naive_ms:.3f} ms/step")
 
     # roofline of the dominant kernel stage of the RapidPT step
-    per = {s: (q[0] / q[1], q[1] / a.steps) for s, q in stages.items() if q and not s.endswith("_total")}
     tot = {s: q[0] / a.steps for s, q in stages.items() if q and not s.endswith("_total")}
+    launches = {s: q[1] / a.steps for s, q in stages.items() if q and not s.endswith("_total")}
     dom = max(tot, key=tot.get)
     kc = nstages.get("naive_contract")
     naive_avg_ms = kc[0] / kc[1]
     naive_flops = 2.0 * 2.0 * v * n * L          # hi and lo halves, 2 flops per MAC
     naive_roof = {"bound": "mfma", "achieved": naive_flops / (naive_avg_ms * 1e-3) / 1e12,
-                  "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s"}
+                  "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "kernel": "naive_contract",
+                  "avg_launch_ms": naive_avg_ms}
     naive_roof["frac"] = naive_roof["achieved"] / naive_roof["peak"]
-    naive_roof["traffic"] = None
-    roof = roofline_for(dom, per[dom][0], v, n, L, ell, r, k, P)
+    naive_roof["traffic"] = None   # counters were taken on the T-storing training launch, not this one
+    roof = roofline_for(dom, tot[dom], launches[dom], v, n, L, ell, r, k, P)
 
     from oracle import metrics as OM
     hn, nvn = h.cpu().numpy(), nv.cpu().numpy()
@@ -181,41 +197,71 @@ def main():
                     "roofline": naive_roof},
         "rapidpt_vs_naivept": value / (L / (nwall / a.steps)),
         "stages_ms_per_step": {s: round(t, 4) for s, t in sorted(tot.items(), key=lambda kv: -kv[1])},
+        "naivept_stages_ms_per_step": {s: round(q[0] / a.steps, 4) for s, q in nstages.items() if q},
         "rapidpt_quality": quality,
     }
     print(json.dumps(out), flush=True)
 
 
-def roofline_for(stage, avg_ms, v, n, L, ell, r, k, P):
-    """Algorithmic work of one launch of a stage and the matching peak."""
-    sec = avg_ms * 1e-3
+def measured_traffic(stage):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy's
+    reading) from the committed counter summary, or None when the kernel's
+    source has changed since the counters were taken."""
+    import hashlib
+    kern = STAGE_KERNEL.get(stage)
+    if kern is None or not os.path.exists(TRAFFIC_FILE):
+        return None
+    txt = open(TRAFFIC_FILE).read()
+    blk = txt.split("```json", 1)[-1].split("```", 1)[0]
+    try:
+        rec = json.loads(blk).get(kern)
+    except ValueError:
+        return None
+    if rec is None:
+        return None
+    src = os.path.join(ROOT, rec["source"])
+    if hashlib.sha256(open(src, "rb").read()).hexdigest()[:16] != rec["source_sha256_16"]:
+        return None
+    return rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+
+
+def roofline_for(stage, ms_per_step, launches_per_step, v, n, L, ell, r, k, P):
+    """Algorithmic work of a stage per launch (total per step / launches) over
+    its average launch duration, against the matching MI355X peak."""
+    avg_s = ms_per_step * 1e-3 / launches_per_step
     Lr = L - ell
-    if stage == "recon_fused":
-        # contraction U W for the recovered columns: 2 flops per MAC, counted once
-        # per split pass (hi.hi + hi.lo + lo.hi)
-        flops = 3 * 2.0 * v * r * Lr
-        ach = flops / sec / 1e12
-        return {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_BF16_TFLOPS, "traffic": None, "kernel": stage}
-    if stage == "naive_contract_store":
-        flops = 2.0 * 2.0 * v * n * ell
-        ach = flops / sec / 1e12
-        return {"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                "frac": ach / PEAK_BF16_TFLOPS, "traffic": None, "kernel": stage}
+    out = {"kernel": stage, "avg_launch_ms": avg_s * 1e3, "launches_per_step": launches_per_step,
+           "traffic": measured_traffic(stage), "traffic_unit": "bytes per launch"}
     if stage == "complete":
-        # sampled basis rows gathered once per column: k rows of r FP32 values
-        launches_cols = Lr  # per launch column count varies; report the recovery launch
-        byts = 4.0 * k * r * launches_cols
-        ach = byts / sec / 1e9
-        return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": None, "kernel": stage}
+        # columns solved per step: P passes over l, the sigma/mu pass, the recovery;
+        # each gathers k basis rows (4r bytes), k indices and k values, writes r coefficients
+        cols = P * ell + ell + Lr
+        byts = cols * (4.0 * k * r + 8.0 * k + 4.0 * r) / launches_per_step
+        ach = byts / avg_s / 1e9
+        out.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": ach / PEAK_HBM_GBS, "algorithmic_bytes_per_launch": byts})
+        return out
+    if stage == "recon_fused":
+        # U W for the training (mean gap) and recovered columns, 3 split passes, 2 flops per MAC
+        flops = 3 * 2.0 * v * r * (ell + Lr) / launches_per_step
+        ach = flops / avg_s / 1e12
+        out.update({"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                    "frac": ach / PEAK_BF16_TFLOPS, "algorithmic_flops_per_launch": flops})
+        return out
     if stage == "reorth":
-        byts = 3 * 4.0 * v * r   # read U twice (Gram, apply), write once
-        ach = byts / sec / 1e9
-        return {"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                "frac": ach / PEAK_HBM_GBS, "traffic": None, "kernel": stage}
-    return {"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None,
-            "traffic": None, "kernel": stage}
+        byts = 3 * 4.0 * v * r   # read U twice (Gram, apply), write it once
+        ach = byts / avg_s / 1e9
+        out.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": ach / PEAK_HBM_GBS, "algorithmic_bytes_per_launch": byts})
+        return out
+    if stage == "track_update":
+        byts = 2 * 4.0 * k * r * ell   # read-modify-write of the sampled basis rows
+        ach = byts / avg_s / 1e9
+        out.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": ach / PEAK_HBM_GBS, "algorithmic_bytes_per_launch": byts})
+        return out
+    out.update({"bound": "hbm", "achieved": None, "peak": PEAK_HBM_GBS, "unit": "GB/s", "frac": None})
+    return out
 
 
 if __name__ == "__main__":

@@ -21,6 +21,7 @@ namespace {
 constexpr int kRMax = 128;           // basis rank handled in LDS
 constexpr int kChunk = 64;           // sampled rows per LDS stage
 constexpr int kStageLd = 72;         // bf16 per staged column (64 + pad: conflict-free 16-byte reads)
+constexpr int kIdxBlk = 1024;        // sampled indices / values staged in LDS at a time
 
 struct CompleteArgs {
   const float* U;
@@ -49,11 +50,11 @@ __device__ __forceinline__ float y_at(const CompleteArgs& a, int64_t i, int q) {
 template <int RT>
 __global__ __launch_bounds__(kBlock) void complete_kernel(CompleteArgs a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  // stage: UT_hi[kRMax][kStageLd] bf16, UT_lo[...], ybuf[kChunk] f32, ibuf[kChunk] i32
+  // stage: UT_hi[kRMax][kStageLd] bf16, UT_lo[...], ybuf[kIdxBlk] f32, ibuf[kIdxBlk] i32
   uint16_t* uth = reinterpret_cast<uint16_t*>(smem);
   uint16_t* utl = uth + kRMax * kStageLd;
   float* ybuf = reinterpret_cast<float*>(utl + kRMax * kStageLd);
-  int* ibuf = reinterpret_cast<int*>(ybuf + kChunk);
+  int* ibuf = reinterpret_cast<int*>(ybuf + kIdxBlk);
   // factor phase (aliases the stage): G64 packed lower [r(r+1)/2], diag[kRMax], rhs[kRMax], bpart[2][kRMax]
   double* G64 = reinterpret_cast<double*>(smem);
 
@@ -70,43 +71,54 @@ __global__ __launch_bounds__(kBlock) void complete_kernel(CompleteArgs a) {
   const int ac = tid & (kRMax - 1), par = tid >> 7;
   double bacc = 0.0;
 
-  for (int c0 = 0; c0 < k; c0 += kChunk) {
+  // indices and sampled values are staged in LDS a block at a time; inside a
+  // block the basis rows of chunk c+1 are loaded while the matrix cores work
+  // on chunk c
+  float x[kChunk / 2];
+  for (int b0 = 0; b0 < k; b0 += kIdxBlk) {
+    const int nb = k - b0 < kIdxBlk ? k - b0 : kIdxBlk;
     __syncthreads();
-    if (tid < kChunk) {
-      const bool in = c0 + tid < k;
-      const int64_t row = in ? om[c0 + tid] : -1;
-      ibuf[tid] = (row >= 0 && row < a.v) ? static_cast<int>(row) : -1;  // out-of-range: zero row
-      ybuf[tid] = in ? y_at(a, i, c0 + tid) : 0.0f;
+    for (int t = tid; t < kIdxBlk; t += kBlock) {
+      const bool in = t < nb;
+      const int64_t row = in ? om[b0 + t] : -1;
+      ibuf[t] = (row >= 0 && row < a.v) ? static_cast<int>(row) : -1;  // out-of-range: zero row
+      ybuf[t] = in ? y_at(a, i, b0 + t) : 0.0f;
     }
     __syncthreads();
-    float x[kChunk / 2];
+    auto gather = [&](int c0) {
 #pragma unroll
-    for (int m = 0; m < kChunk / 2; ++m) {
-      const int row = ibuf[par + 2 * m];
-      x[m] = (row >= 0 && ac < r) ? a.U[static_cast<int64_t>(row) * r + ac] : 0.0f;
-    }
+      for (int m = 0; m < kChunk / 2; ++m) {
+        const int row = ibuf[c0 + par + 2 * m];
+        x[m] = (row >= 0 && ac < r) ? a.U[static_cast<int64_t>(row) * r + ac] : 0.0f;
+      }
+    };
+    gather(0);
+    for (int c0 = 0; c0 < nb; c0 += kChunk) {
+      __syncthreads();  // the previous chunk's MFMA reads of the stage are done
 #pragma unroll
-    for (int m = 0; m < kChunk / 2; ++m) {
-      const int kk = par + 2 * m;
-      const uint16_t hi = f2bf(x[m]);
-      uth[ac * kStageLd + kk] = hi;
-      utl[ac * kStageLd + kk] = f2bf(x[m] - bf2f(hi));
-      bacc += static_cast<double>(x[m]) * ybuf[kk];
-    }
-    __syncthreads();
-    if (wave < RT) {
+      for (int m = 0; m < kChunk / 2; ++m) {
+        const int kk = par + 2 * m;
+        const uint16_t hi = f2bf(x[m]);
+        uth[ac * kStageLd + kk] = hi;
+        utl[ac * kStageLd + kk] = f2bf(x[m] - bf2f(hi));
+        bacc += static_cast<double>(x[m]) * ybuf[c0 + kk];
+      }
+      if (c0 + kChunk < nb) gather(c0 + kChunk);
+      __syncthreads();
+      if (wave < RT) {
 #pragma unroll
-      for (int s = 0; s < kChunk / 16; ++s) {
-        const int ko = 16 * s + 8 * h;
-        const u32x4 ah = *reinterpret_cast<const u32x4*>(uth + (wave * 32 + col) * kStageLd + ko);
-        const u32x4 al = *reinterpret_cast<const u32x4*>(utl + (wave * 32 + col) * kStageLd + ko);
+        for (int s = 0; s < kChunk / 16; ++s) {
+          const int ko = 16 * s + 8 * h;
+          const u32x4 ah = *reinterpret_cast<const u32x4*>(uth + (wave * 32 + col) * kStageLd + ko);
+          const u32x4 al = *reinterpret_cast<const u32x4*>(utl + (wave * 32 + col) * kStageLd + ko);
 #pragma unroll
-        for (int t = 0; t < RT; ++t) {
-          const u32x4 bh = *reinterpret_cast<const u32x4*>(uth + (t * 32 + col) * kStageLd + ko);
-          const u32x4 bl = *reinterpret_cast<const u32x4*>(utl + (t * 32 + col) * kStageLd + ko);
-          acc[t] = mfma_bf16(ah, bh, acc[t]);
-          acc[t] = mfma_bf16(ah, bl, acc[t]);
-          acc[t] = mfma_bf16(al, bh, acc[t]);
+          for (int t = 0; t < RT; ++t) {
+            const u32x4 bh = *reinterpret_cast<const u32x4*>(uth + (t * 32 + col) * kStageLd + ko);
+            const u32x4 bl = *reinterpret_cast<const u32x4*>(utl + (t * 32 + col) * kStageLd + ko);
+            acc[t] = mfma_bf16(ah, bh, acc[t]);
+            acc[t] = mfma_bf16(ah, bl, acc[t]);
+            acc[t] = mfma_bf16(al, bh, acc[t]);
+          }
         }
       }
     }
@@ -115,7 +127,8 @@ __global__ __launch_bounds__(kBlock) void complete_kernel(CompleteArgs a) {
   // G (lower triangle) to LDS in FP64; b reduced over the two row parities
   const int ntri = r * (r + 1) / 2;
   double* diag = G64 + ntri;
-  double* rhs = diag + kRMax;
+  double* dinv = diag + kRMax;
+  double* rhs = dinv + kRMax;
   double* bpart = rhs + kRMax;  // [2][kRMax]
   if (wave < RT) {
 #pragma unroll
@@ -130,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void complete_kernel(CompleteArgs a) {
   __syncthreads();
   if (tid < r) rhs[tid] = bpart[tid] + bpart[kRMax + tid];
 
-  const int failed = lds_cholesky(G64, diag, r);
+  const int failed = lds_cholesky(G64, diag, dinv, r);
   float* Wi = a.W + i * r;
   if (failed) {
     for (int c = tid; c < r; c += kBlock) Wi[c] = 0.0f;
@@ -144,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void complete_kernel(CompleteArgs a) {
   }
   if (wave == 0) {
     double z0, z1;
-    wave_chol_solve(G64, diag, rhs, r, z0, z1);
+    wave_chol_solve(G64, dinv, rhs, r, z0, z1);
     double nrm = 0.0;
     if (lane < r) {
       Wi[lane] = static_cast<float>(z0);
@@ -166,19 +179,26 @@ __global__ __launch_bounds__(kBlock) void complete_kernel(CompleteArgs a) {
     __syncthreads();
     for (int q = tid; q < k; q += kBlock) {
       const int64_t row = om[q];
-      double s = 0.0;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
       if (row >= 0 && row < a.v) {
         const float* u = a.U + row * r;
-        for (int c = 0; c < r; ++c) s += static_cast<double>(u[c]) * rhs[c];
+        int c = 0;
+        for (; c + 4 <= r; c += 4) {
+          s0 += static_cast<double>(u[c]) * rhs[c];
+          s1 += static_cast<double>(u[c + 1]) * rhs[c + 1];
+          s2 += static_cast<double>(u[c + 2]) * rhs[c + 2];
+          s3 += static_cast<double>(u[c + 3]) * rhs[c + 3];
+        }
+        for (; c < r; ++c) s0 += static_cast<double>(u[c]) * rhs[c];
       }
-      a.resid[i * k + q] = static_cast<float>(y_at(a, i, q) - s);
+      a.resid[i * k + q] = static_cast<float>(y_at(a, i, q) - ((s0 + s1) + (s2 + s3)));
     }
   }
 }
 
 size_t smem_bytes(int r) {
-  const size_t stage = 2 * kRMax * kStageLd * sizeof(uint16_t) + kChunk * (sizeof(float) + sizeof(int));
-  const size_t factor = (static_cast<size_t>(r) * (r + 1) / 2 + 4 * kRMax) * sizeof(double);
+  const size_t stage = 2 * kRMax * kStageLd * sizeof(uint16_t) + kIdxBlk * (sizeof(float) + sizeof(int));
+  const size_t factor = (static_cast<size_t>(r) * (r + 1) / 2 + 5 * kRMax) * sizeof(double);
   return stage > factor ? stage : factor;
 }
 

@@ -82,14 +82,19 @@ __global__ __launch_bounds__(kBlock) void gram_partial_kernel(const float* __res
   }
 }
 
-// G = sum of the partials, in FP64 (one thread per entry, coalesced)
+// G = sum of the partials, in FP64: a workgroup owns 64 entries, its four
+// waves sum interleaved quarters of the partials, LDS combines them.
 __global__ __launch_bounds__(kBlock) void gram_reduce_kernel(const float* __restrict__ part, int nblk, int r,
                                                             double* __restrict__ G) {
-  const int idx = blockIdx.x * kBlock + threadIdx.x;
-  if (idx >= r * r) return;
+  __shared__ double red[4][64];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int idx = blockIdx.x * 64 + lane;
   double s = 0.0;
-  for (int b = 0; b < nblk; ++b) s += part[static_cast<int64_t>(b) * r * r + idx];
-  G[idx] = s;
+  if (idx < r * r)
+    for (int b = wave; b < nblk; b += 4) s += part[static_cast<int64_t>(b) * r * r + idx];
+  red[wave][lane] = s;
+  __syncthreads();
+  if (wave == 0 && idx < r * r) G[idx] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
 }
 
 // Factor G = L L^T (FP64, LDS) and write R^{-1} = L^{-T} transposed
@@ -102,7 +107,8 @@ __global__ __launch_bounds__(kBlock) void chol_rinv_kernel(const double* __restr
   const int ntri = r * (r + 1) / 2;
   double* G = reinterpret_cast<double*>(sm);
   double* diag = G + ntri;
-  float* Li = reinterpret_cast<float*>(diag + kR);  // [r][kR]
+  double* dinv = diag + kR;
+  float* Li = reinterpret_cast<float*>(dinv + kR);  // [r][kR]
   const int tid = threadIdx.x;
   for (int idx = tid; idx < ntri; idx += kBlock) {
     // invert ptri: row i with i(i+1)/2 <= idx
@@ -112,8 +118,8 @@ __global__ __launch_bounds__(kBlock) void chol_rinv_kernel(const double* __restr
     const int c = idx - i * (i + 1) / 2;
     G[idx] = Gfull[i * r + c];
   }
-  const int failed = lds_cholesky(G, diag, r);
-  if (!failed) lds_tri_inverse(G, diag, r, Li, kR);
+  const int failed = lds_cholesky(G, diag, dinv, r);
+  if (!failed) lds_tri_inverse(G, dinv, r, Li, kR);
   __syncthreads();
   for (int idx = tid; idx < kR * kR; idx += kBlock) {
     const int c = idx / kR, j = idx - c * kR;
@@ -126,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void chol_rinv_kernel(const double* __restr
   if (tid == 0 && info) *info = failed;
 }
 
-size_t chol_smem(int r) { return (static_cast<size_t>(r) * (r + 1) / 2 + kR) * sizeof(double) + r * kR * sizeof(float); }
+size_t chol_smem(int r) { return (static_cast<size_t>(r) * (r + 1) / 2 + 2 * kR) * sizeof(double) + r * kR * sizeof(float); }
 
 // U <- U R^{-1}, in place; one wave per 32-row tile.
 template <int KS>
@@ -294,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void literal_resid_max_kernel(const float* 
 
 int gram_blocks(int64_t v) {
   int64_t nb = ceil_div(v, 256);
-  if (nb > 512) nb = 512;
+  if (nb > 256) nb = 256;
   if (nb < 1) nb = 1;
   return static_cast<int>(nb);
 }
@@ -328,7 +334,7 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
     default: hipLaunchKernelGGL(gram_partial_kernel<4>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
   }
   RPT_CHECK_LAUNCH();
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(static_cast<unsigned>(ceil_div(static_cast<int64_t>(r) * r, kBlock))),
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(static_cast<unsigned>(ceil_div(static_cast<int64_t>(r) * r, 64))),
                      dim3(kBlock), 0, s, part, nb, r, gfull);
   RPT_CHECK_LAUNCH();
   static bool attr_set = false;
