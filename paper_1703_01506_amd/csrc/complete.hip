@@ -2,15 +2,17 @@
 //     w_i = argmin_w | U[omega_i, :] w - y_i |_2
 // from the normal equations G w = b, G = U_O^T U_O, b = U_O^T y.
 //
-// One workgroup per column.  The sampled basis rows are gathered 32 at a time
-// (coalesced: a row is r contiguous floats) into LDS, transposed and split
-// into BF16 hi/lo halves; G accumulates on the matrix cores as
-// hi.hi + hi.lo + lo.hi (the split product keeps about 16 significant bits per
-// term, FP32 accumulation).  b accumulates from the FP32 values in FP64.
-// G is then moved to LDS in FP64 (packed lower triangle) and factored by a
-// right-looking Cholesky in FP64; two triangular solves in one wave give w.
-// A non-positive pivot at step j sets info[i] = j + 1 and w_i = 0.
-// Optionally the residual y - U_O w is written (FP32 dot products).
+// One workgroup (4 waves) per column.  The sampled rows are split between the
+// waves in groups of 32; every lane loads its MFMA fragments straight from
+// the basis (for a fixed sampled row, 16 lanes read 16 consecutive floats),
+// splits them into BF16 hi/lo halves and accumulates the lower-triangular
+// 16 x 16 tiles of G on the matrix cores as hi.hi + hi.lo + lo.hi (about 16
+// significant bits per term, FP32 accumulation); b accumulates in FP64 from
+// the FP32 values.  The per-wave partial tiles are summed into a packed FP64
+// lower triangle in LDS with b^T appended as row r, so that the blocked
+// Cholesky of that trapezoid leaves z = L^{-1} b in row r; one blocked back
+// substitution gives w.  A non-positive pivot j sets info[i] = j + 1 and
+// w_i = 0.  Optionally the residual y - U_O w is written.
 #include "lds_linalg.h"
 #include "rpt_internal.h"
 
@@ -18,10 +20,10 @@ namespace rpt {
 
 namespace {
 
-constexpr int kRMax = 128;           // basis rank handled in LDS
-constexpr int kChunk = 64;           // sampled rows per LDS stage
-constexpr int kStageLd = 72;         // bf16 per staged column (64 + pad: conflict-free 16-byte reads)
-constexpr int kIdxBlk = 1024;        // sampled indices / values staged in LDS at a time
+constexpr int kRMax = 128;  // basis rank handled in LDS
+constexpr int kNW = 4;      // waves per workgroup
+constexpr int kNT = 64 * kNW;
+constexpr int kIdx = 1024;  // sampled indices / values staged in LDS at a time
 
 struct CompleteArgs {
   const float* U;
@@ -47,128 +49,139 @@ __device__ __forceinline__ float y_at(const CompleteArgs& a, int64_t i, int q) {
   return (vox >= 0 && vox < a.ldT) ? a.Trows[row * a.ldT + vox] : 0.0f;
 }
 
-template <int RT>
-__global__ __launch_bounds__(kBlock) void complete_kernel(CompleteArgs a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  // stage: UT_hi[kRMax][kStageLd] bf16, UT_lo[...], ybuf[kIdxBlk] f32, ibuf[kIdxBlk] i32
-  uint16_t* uth = reinterpret_cast<uint16_t*>(smem);
-  uint16_t* utl = uth + kRMax * kStageLd;
-  float* ybuf = reinterpret_cast<float*>(utl + kRMax * kStageLd);
-  int* ibuf = reinterpret_cast<int*>(ybuf + kIdxBlk);
-  // factor phase (aliases the stage): G64 packed lower [r(r+1)/2], diag[kRMax], rhs[kRMax], bpart[2][kRMax]
-  double* G64 = reinterpret_cast<double*>(smem);
+// LDS layout (doubles first): G packed (r + 1)(r + 2)/2 rounded to even,
+// P [kCb][kPanelLd], dinv [kRMax], w [kRMax], then ibuf [kIdx] int, ybuf [kIdx] float
+__host__ __device__ inline int gsize(int r) { return (((r + 1) * (r + 2) / 2) + 1) & ~1; }
+size_t smem_bytes(int r) {
+  return (static_cast<size_t>(gsize(r)) + kCb * kPanelLd + 2 * kRMax) * sizeof(double) +
+         kIdx * (sizeof(int) + sizeof(float));
+}
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, col = lane & 31;
+template <int RB>
+__global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(CompleteArgs a) {
+  constexpr int NTILE = RB * (RB + 1) / 2;
+  extern __shared__ __align__(16) unsigned char smem[];
   const int r = a.r, k = a.k;
+  double* G = reinterpret_cast<double*>(smem);
+  double* P = G + gsize(r);
+  double* dinv = P + kCb * kPanelLd;
+  double* wv = dinv + kRMax;
+  int* ibuf = reinterpret_cast<int*>(wv + kRMax);
+  float* ybuf = reinterpret_cast<float*>(ibuf + kIdx);
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, c16 = lane & 15, kq = lane >> 4;
   const int64_t i = blockIdx.x;
   const int32_t* om = a.omega + i * k;
+  const int nrows = r + 1, ntri = nrows * (nrows + 1) / 2;
+  for (int t = tid; t < ntri; t += kNT) G[t] = 0.0;
 
-  f32x16 acc[RT];
+  f32x4 acc[NTILE];
 #pragma unroll
-  for (int t = 0; t < RT; ++t) acc[t] = f32x16{};
-  // thread t gathers column ac = t & 127 of the rows of parity t >> 7; b
-  // accumulates from the FP32 values in FP64
-  const int ac = tid & (kRMax - 1), par = tid >> 7;
-  double bacc = 0.0;
+  for (int t = 0; t < NTILE; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  double bacc[RB];
+#pragma unroll
+  for (int b = 0; b < RB; ++b) bacc[b] = 0.0;
 
-  // indices and sampled values are staged in LDS a block at a time; inside a
-  // block the basis rows of chunk c+1 are loaded while the matrix cores work
-  // on chunk c
-  float x[kChunk / 2];
-  for (int b0 = 0; b0 < k; b0 += kIdxBlk) {
-    const int nb = k - b0 < kIdxBlk ? k - b0 : kIdxBlk;
-    __syncthreads();
-    for (int t = tid; t < kIdxBlk; t += kBlock) {
+  float x[RB][8];
+  for (int b0 = 0; b0 < k; b0 += kIdx) {
+    const int nb = k - b0 < kIdx ? k - b0 : kIdx;
+    const int ngr = (nb + 31) >> 5;
+    __syncthreads();  // previous index block fully consumed (and G cleared)
+    for (int t = tid; t < ngr * 32; t += kNT) {
       const bool in = t < nb;
       const int64_t row = in ? om[b0 + t] : -1;
-      ibuf[t] = (row >= 0 && row < a.v) ? static_cast<int>(row) : -1;  // out-of-range: zero row
+      ibuf[t] = (row >= 0 && row < a.v) ? static_cast<int>(row) : -1;  // out of range: zero row
       ybuf[t] = in ? y_at(a, i, b0 + t) : 0.0f;
     }
     __syncthreads();
-    auto gather = [&](int c0) {
+    auto load = [&](int g) {
 #pragma unroll
-      for (int m = 0; m < kChunk / 2; ++m) {
-        const int row = ibuf[c0 + par + 2 * m];
-        x[m] = (row >= 0 && ac < r) ? a.U[static_cast<int64_t>(row) * r + ac] : 0.0f;
-      }
-    };
-    gather(0);
-    for (int c0 = 0; c0 < nb; c0 += kChunk) {
-      __syncthreads();  // the previous chunk's MFMA reads of the stage are done
+      for (int j = 0; j < 8; ++j) {
+        const int row = ibuf[32 * g + 8 * kq + j];
+        const float* u = a.U + static_cast<int64_t>(row) * r;
 #pragma unroll
-      for (int m = 0; m < kChunk / 2; ++m) {
-        const int kk = par + 2 * m;
-        const uint16_t hi = f2bf(x[m]);
-        uth[ac * kStageLd + kk] = hi;
-        utl[ac * kStageLd + kk] = f2bf(x[m] - bf2f(hi));
-        bacc += static_cast<double>(x[m]) * ybuf[c0 + kk];
-      }
-      if (c0 + kChunk < nb) gather(c0 + kChunk);
-      __syncthreads();
-      if (wave < RT) {
-#pragma unroll
-        for (int s = 0; s < kChunk / 16; ++s) {
-          const int ko = 16 * s + 8 * h;
-          const u32x4 ah = *reinterpret_cast<const u32x4*>(uth + (wave * 32 + col) * kStageLd + ko);
-          const u32x4 al = *reinterpret_cast<const u32x4*>(utl + (wave * 32 + col) * kStageLd + ko);
-#pragma unroll
-          for (int t = 0; t < RT; ++t) {
-            const u32x4 bh = *reinterpret_cast<const u32x4*>(uth + (t * 32 + col) * kStageLd + ko);
-            const u32x4 bl = *reinterpret_cast<const u32x4*>(utl + (t * 32 + col) * kStageLd + ko);
-            acc[t] = mfma_bf16(ah, bh, acc[t]);
-            acc[t] = mfma_bf16(ah, bl, acc[t]);
-            acc[t] = mfma_bf16(al, bh, acc[t]);
-          }
+        for (int b = 0; b < RB; ++b) {
+          const int c = 16 * b + c16;
+          x[b][j] = (row >= 0 && c < r) ? u[c] : 0.0f;
         }
       }
+    };
+    // no register prefetch of the next group: x and the hi/lo fragments are
+    // never live together (the other waves of the SIMD cover the latency)
+    for (int g = wave; g < ngr; g += kNW) {
+      load(g);
+      u32x4 hi[RB], lo[RB];
+      float yv[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) yv[j] = ybuf[32 * g + 8 * kq + j];
+#pragma unroll
+      for (int b = 0; b < RB; ++b) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) {
+          const uint16_t h0 = f2bf(x[b][j]), h1 = f2bf(x[b][j + 1]);
+          hi[b][j >> 1] = pack_bf2(h0, h1);
+          lo[b][j >> 1] = pack_bf2(f2bf(x[b][j] - bf2f(h0)), f2bf(x[b][j + 1] - bf2f(h1)));
+          s = fma(static_cast<double>(x[b][j]), static_cast<double>(yv[j]), s);
+          s = fma(static_cast<double>(x[b][j + 1]), static_cast<double>(yv[j + 1]), s);
+        }
+        bacc[b] += s;
+      }
+      int t = 0;
+#pragma unroll
+      for (int bi = 0; bi < RB; ++bi)
+#pragma unroll
+        for (int bj = 0; bj <= bi; ++bj) {
+          acc[t] = mfma16_bf16(hi[bi], hi[bj], acc[t]);
+          acc[t] = mfma16_bf16(hi[bi], lo[bj], acc[t]);
+          acc[t] = mfma16_bf16(lo[bi], hi[bj], acc[t]);
+          ++t;
+        }
+    }
+  }
+  // partial tiles and b of every wave summed into the packed FP64 trapezoid
+  {
+    int t = 0;
+#pragma unroll
+    for (int bi = 0; bi < RB; ++bi)
+#pragma unroll
+      for (int bj = 0; bj <= bi; ++bj) {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int row = 16 * bi + 4 * kq + e, col = 16 * bj + c16;
+          if (row < r && col <= row) atomicAdd(&G[ptri(row, col)], static_cast<double>(acc[t][e]));
+        }
+        ++t;
+      }
+#pragma unroll
+    for (int b = 0; b < RB; ++b) {
+      double s = bacc[b];
+      s += __shfl_xor(s, 16, 64);
+      s += __shfl_xor(s, 32, 64);
+      const int c = 16 * b + c16;
+      if (kq == 0 && c < r) atomicAdd(&G[ptri(r, c)], s);
     }
   }
   __syncthreads();
-  // G (lower triangle) to LDS in FP64; b reduced over the two row parities
-  const int ntri = r * (r + 1) / 2;
-  double* diag = G64 + ntri;
-  double* dinv = diag + kRMax;
-  double* rhs = dinv + kRMax;
-  double* bpart = rhs + kRMax;  // [2][kRMax]
-  if (wave < RT) {
-#pragma unroll
-    for (int t = 0; t < RT; ++t)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = wave * 32 + mfma_row(e, h), cc = t * 32 + col;
-        if (row < r && cc <= row) G64[ptri(row, cc)] = static_cast<double>(acc[t][e]);
-      }
-  }
-  bpart[par * kRMax + ac] = bacc;
-  __syncthreads();
-  if (tid < r) rhs[tid] = bpart[tid] + bpart[kRMax + tid];
 
-  const int failed = lds_cholesky(G64, diag, dinv, r);
+  const int failed = lds_cholesky_blocked<(RB >= 8 ? 3 : 2)>(G, dinv, P, r, nrows);
   float* Wi = a.W + i * r;
   if (failed) {
-    for (int c = tid; c < r; c += kBlock) Wi[c] = 0.0f;
+    for (int c = tid; c < r; c += kNT) Wi[c] = 0.0f;
     if (tid == 0) {
       a.info[i] = failed;
       if (a.wnorm2) a.wnorm2[i] = 0.0f;
     }
     if (a.resid)
-      for (int q = tid; q < k; q += kBlock) a.resid[i * k + q] = y_at(a, i, q);
+      for (int q = tid; q < k; q += kNT) a.resid[i * k + q] = y_at(a, i, q);
     return;
   }
+  for (int c = tid; c < r; c += kNT) wv[c] = G[ptri(r, c)];
+  lds_chol_backsolve(G, dinv, wv, r);
+  for (int c = tid; c < r; c += kNT) Wi[c] = static_cast<float>(wv[c]);
   if (wave == 0) {
-    double z0, z1;
-    wave_chol_solve(G64, dinv, rhs, r, z0, z1);
     double nrm = 0.0;
-    if (lane < r) {
-      Wi[lane] = static_cast<float>(z0);
-      rhs[lane] = z0;
-      nrm += z0 * z0;
-    }
-    if (lane + 64 < r) {
-      Wi[lane + 64] = static_cast<float>(z1);
-      rhs[lane + 64] = z1;
-      nrm += z1 * z1;
-    }
+    for (int c = lane; c < r; c += 64) nrm = fma(wv[c], wv[c], nrm);
     nrm = wave_sum_d(nrm);
     if (lane == 0) {
       a.info[i] = 0;
@@ -176,30 +189,31 @@ __global__ __launch_bounds__(kBlock) void complete_kernel(CompleteArgs a) {
     }
   }
   if (a.resid) {
+    // one sampled row per thread: every load of the row is independent, so a
+    // thread's whole row is in flight at once
     __syncthreads();
-    for (int q = tid; q < k; q += kBlock) {
+    const bool vec = (r & 3) == 0 && (reinterpret_cast<uintptr_t>(a.U) & 15) == 0;
+    for (int q = tid; q < k; q += kNT) {
       const int64_t row = om[q];
+      const float yq = y_at(a, i, q);
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
       if (row >= 0 && row < a.v) {
         const float* u = a.U + row * r;
-        int c = 0;
-        for (; c + 4 <= r; c += 4) {
-          s0 += static_cast<double>(u[c]) * rhs[c];
-          s1 += static_cast<double>(u[c + 1]) * rhs[c + 1];
-          s2 += static_cast<double>(u[c + 2]) * rhs[c + 2];
-          s3 += static_cast<double>(u[c + 3]) * rhs[c + 3];
+        if (vec) {
+          for (int c = 0; c < r; c += 4) {
+            const f32x4 x4 = *reinterpret_cast<const f32x4*>(u + c);
+            s0 = fma(static_cast<double>(x4[0]), wv[c], s0);
+            s1 = fma(static_cast<double>(x4[1]), wv[c + 1], s1);
+            s2 = fma(static_cast<double>(x4[2]), wv[c + 2], s2);
+            s3 = fma(static_cast<double>(x4[3]), wv[c + 3], s3);
+          }
+        } else {
+          for (int c = 0; c < r; ++c) s0 = fma(static_cast<double>(u[c]), wv[c], s0);
         }
-        for (; c < r; ++c) s0 += static_cast<double>(u[c]) * rhs[c];
       }
-      a.resid[i * k + q] = static_cast<float>(y_at(a, i, q) - ((s0 + s1) + (s2 + s3)));
+      a.resid[i * k + q] = static_cast<float>(yq - ((s0 + s1) + (s2 + s3)));
     }
   }
-}
-
-size_t smem_bytes(int r) {
-  const size_t stage = 2 * kRMax * kStageLd * sizeof(uint16_t) + kIdxBlk * (sizeof(float) + sizeof(int));
-  const size_t factor = (static_cast<size_t>(r) * (r + 1) / 2 + 5 * kRMax) * sizeof(double);
-  return stage > factor ? stage : factor;
 }
 
 }  // namespace
@@ -210,23 +224,20 @@ rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, 
   if (L == 0) return RPT_OK;
   if (r < 1 || r > kRMax) return RPT_ERR_UNSUPPORTED;
   CompleteArgs a{U, v, r, omega, k, y, Trows, ldT, trow, L, W, resid, info, wnorm2};
-  const int RT = (r + 31) / 32;
-  void* fn = nullptr;
-  switch (RT) {
-    case 1: fn = reinterpret_cast<void*>(&complete_kernel<1>); break;
-    case 2: fn = reinterpret_cast<void*>(&complete_kernel<2>); break;
-    case 3: fn = reinterpret_cast<void*>(&complete_kernel<3>); break;
-    default: fn = reinterpret_cast<void*>(&complete_kernel<4>); break;
-  }
-  const size_t sm = smem_bytes(r);
-  static bool attr_set[4] = {false, false, false, false};
-  if (!attr_set[RT - 1]) {
+  const int RB = (r + 15) / 16;
+  void* fns[8] = {reinterpret_cast<void*>(&complete_kernel<1>), reinterpret_cast<void*>(&complete_kernel<2>),
+                  reinterpret_cast<void*>(&complete_kernel<3>), reinterpret_cast<void*>(&complete_kernel<4>),
+                  reinterpret_cast<void*>(&complete_kernel<5>), reinterpret_cast<void*>(&complete_kernel<6>),
+                  reinterpret_cast<void*>(&complete_kernel<7>), reinterpret_cast<void*>(&complete_kernel<8>)};
+  void* fn = fns[RB - 1];
+  static bool attr_set[8] = {};
+  if (!attr_set[RB - 1]) {
     (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem_bytes(kRMax)));
-    attr_set[RT - 1] = true;
+    attr_set[RB - 1] = true;
   }
   void* args[] = {&a};
   RPT_STAGE("complete", s);
-  hipError_t e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(L)), dim3(kBlock), args, sm, s);
+  hipError_t e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(L)), dim3(kNT), args, smem_bytes(r), s);
   if (e != hipSuccess) {
     set_hip_error(e);
     return RPT_ERR_HIP;

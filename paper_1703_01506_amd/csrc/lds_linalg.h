@@ -10,6 +10,15 @@ namespace rpt {
 
 __device__ __forceinline__ int ptri(int i, int c) { return (i * (i + 1)) / 2 + c; }
 
+// 1 / sqrt(x) for x > 0: hardware estimate and two Newton steps (relative
+// error near one ulp; the factorisations below need no correct rounding)
+__device__ __forceinline__ double rsqrt_d(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  return y;
+}
+
 __device__ __forceinline__ double readlane_d(double x, int l) {
   const unsigned long long b = static_cast<unsigned long long>(__double_as_longlong(x));
   const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b & 0xFFFFFFFFull), l));
@@ -40,7 +49,7 @@ __device__ __forceinline__ double dot4(const double* a, const double* b, int kb,
 // k), combined with one shuffle.  On success G holds L (diagonal included),
 // diag[j] = L_jj and dinv[j] = 1 / L_jj; returns 0.  A pivot that is not
 // positive returns j + 1 (same value in every thread).
-__device__ inline int lds_cholesky(double* G, double* diag, double* dinv, int r) {
+__device__ __forceinline__ int lds_cholesky(double* G, double* diag, double* dinv, int r) {
   __shared__ int fail;
   const int tid = threadIdx.x;
   const int row = tid >> 1, half = tid & 1;
@@ -79,7 +88,7 @@ __device__ inline int lds_cholesky(double* G, double* diag, double* dinv, int r)
 
 // Solve L L^T w = b in one wave (wave 0 calls it): lane owns rows lane and
 // lane + 64 (r <= 128); the pivot broadcast is a scalar readlane.
-__device__ inline void wave_chol_solve(const double* G, const double* dinv, const double* rhs, int r, double& z0,
+__device__ __forceinline__ void wave_chol_solve(const double* G, const double* dinv, const double* rhs, int r, double& z0,
                                        double& z1) {
   const int lane = threadIdx.x & 63;
   z0 = lane < r ? rhs[lane] : 0.0;
@@ -106,7 +115,7 @@ __device__ inline void wave_chol_solve(const double* G, const double* dinv, cons
 // L[i][j] Linv[j][c]) / L_ii.  Thread c owns column c (c < r <= kBlock); all
 // threads walk j in lockstep (Linv[j][c] = 0 for j < c) so L[i][j] is a
 // broadcast read.  Linv is FP32 in LDS with leading dimension ld; sums FP64.
-__device__ inline void lds_tri_inverse(const double* G, const double* dinv, int r, float* Li, int ld) {
+__device__ __forceinline__ void lds_tri_inverse(const double* G, const double* dinv, int r, float* Li, int ld) {
   const int c = threadIdx.x;
   for (int i = 0; i < r; ++i) {
     if (c < r) {
@@ -124,6 +133,220 @@ __device__ inline void lds_tri_inverse(const double* G, const double* dinv, int 
     }
     __syncthreads();
   }
+}
+
+// ---------------------------------------------------------------------------
+// Blocked variants (block width kCb).  One wave factors each panel of kCb
+// columns with the panel in registers (a lane owns up to three rows; pivots
+// and the kCb x kCb diagonal block are broadcast by readlane), then every
+// thread applies the panel to the trailing matrix in 4 x 4 register tiles.
+// Two barriers per block of kCb columns.
+
+constexpr int kCb = 16;
+constexpr int kPanelLd = 132;  // > 129 rows below a diagonal block, multiple of 4
+
+// One panel step on wave 0: rows [c0, nrows) x columns [c0, c0 + M) of G;
+// lane l owns rows c0 + l + 64 s, s < NS (nrows - c0 <= 64 NS).  Rows past
+// nrows and entries above the diagonal are loaded from clamped addresses
+// and carried along unmasked: they are never read by a kept entry and never
+// stored.  G must be followed by at least kCb doubles of readable LDS.
+template <int M, int NS>
+__device__ __forceinline__ int chol_panel(double* G, double* dinv, double* P, int c0, int m, int nrows, int lane_in) {
+  // the lane index passes through an opaque register move so that the
+  // lane-dependent predicates below are formed inside the caller's block loop
+  // instead of being hoisted out of it (where they would stay live and spill)
+  int lane;
+  asm volatile("v_mov_b32 %0, %1" : "=v"(lane) : "v"(lane_in));
+  const int mm = M ? M : m;
+  double d[3][kCb];
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int row = min(c0 + 64 * s + lane, nrows - 1);
+    const double* gr = G + ptri(row, c0);  // entries c0.. of a row are contiguous
+#pragma unroll
+    for (int j = 0; j < kCb; ++j) d[s][j] = gr[j];
+  }
+  __shared__ double colb[kCb];
+  int bad = 0;
+#pragma unroll
+  for (int j = 0; j < kCb; ++j) {
+    if (j < mm) {
+      double piv = readlane_d(d[0][j], j);
+      if (!(piv > 0.0)) {
+        if (!bad) bad = c0 + j + 1;
+        piv = 1.0;
+      }
+      const double inv = rsqrt_d(piv);
+      d[0][j] = (lane == j) ? piv * inv : d[0][j] * inv;
+#pragma unroll
+      for (int s = 1; s < NS; ++s) d[s][j] *= inv;
+      if (lane == 0) dinv[c0 + j] = inv;
+      // column j of the diagonal block is broadcast through LDS: a wave's LDS
+      // operations complete in issue order, so the fences only keep the
+      // compiler from reordering them
+      if (lane < kCb) colb[lane] = d[0][j];
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+#pragma unroll
+      for (int q = j + 1; q < kCb; ++q) {
+        if (q < mm) {
+          const double lq = colb[q];  // L[c0 + q][c0 + j]
+#pragma unroll
+          for (int s = 0; s < NS; ++s) d[s][q] = fma(-d[s][j], lq, d[s][q]);
+        }
+      }
+      // finish this pivot's updates before the next pivot starts: deferring
+      // them keeps every broadcast value live and exhausts the registers
+#pragma unroll
+      for (int q = j + 1; q < kCb; ++q)
+#pragma unroll
+        for (int s = 0; s < NS; ++s) asm volatile("" : "+v"(d[s][q]));
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  const int b0 = c0 + m;
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const int row = c0 + 64 * s + lane;
+    if (row < nrows) {
+      double* gr = G + ptri(row, c0);
+      double* pr = P + (row >= b0 ? row - b0 : 0);
+#pragma unroll
+      for (int j = 0; j < kCb; ++j) {
+        if (j < mm && (s > 0 || j <= lane)) gr[j] = d[s][j];
+        if (j < mm && row >= b0) pr[j * kPanelLd] = d[s][j];
+      }
+    }
+  }
+  return bad;
+}
+
+// Trailing update G[i][j] -= sum_q P[q][i - b0] P[q][j - b0], b0 <= j <= i,
+// j < r, i < nrows, in 4 x 4 tiles.
+template <int M>
+__device__ __forceinline__ void chol_trailing(double* G, const double* P, int b0, int m, int r, int nrows) {
+  const int nr = nrows - b0, nc = r - b0;
+  if (nc <= 0) return;
+  const int TR = (nr + 3) >> 2, TC = (nc + 3) >> 2;
+  for (int t = threadIdx.x; t < TR * TC; t += blockDim.x) {
+    const int ti = t / TC, tj = t - ti * TC;
+    if (tj > ti) continue;
+    double acc[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int w = 0; w < 4; ++w) acc[u][w] = 0.0;
+    // partial unroll: full unrolling hoists all 8 x kCb loads and spills
+#pragma unroll 4
+    for (int q = 0; q < (M ? M : m); ++q) {
+      {
+        const double* pq = P + q * kPanelLd;
+        double xi[4], xj[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          xi[u] = pq[4 * ti + u];
+          xj[u] = pq[4 * tj + u];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+#pragma unroll
+          for (int w = 0; w < 4; ++w) acc[u][w] = fma(xi[u], xj[w], acc[u][w]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int row = b0 + 4 * ti + u;
+#pragma unroll
+      for (int w = 0; w < 4; ++w) {
+        const int col = b0 + 4 * tj + w;
+        if (row < nrows && col < r && col <= row) G[ptri(row, col)] -= acc[u][w];
+      }
+    }
+  }
+}
+
+// Cholesky of the leading r x r block of the packed lower trapezoid G (rows
+// [0, nrows), r <= nrows <= 64 NS; entry (i, c) at ptri(i, c),
+// c <= min(i, r - 1)).  On success the leading block holds L (diagonal
+// included), dinv[j] = 1 / L_jj, and every row i >= r holds x_i with
+// L x_i = a_i (for an appended row b^T: z = L^{-1} b).  P is LDS scratch of
+// kCb * kPanelLd doubles.  Returns 0, or j + 1 for the first pivot j that is
+// not positive (same value in every thread; later blocks are not factored).
+template <int NS>
+__device__ __forceinline__ int lds_cholesky_blocked(double* G, double* dinv, double* P, int r, int nrows) {
+  __shared__ int fail;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  if (threadIdx.x == 0) fail = 0;
+  // full blocks, then the ragged last block (separate loops keep the two
+  // unrolled variants out of each other's register live ranges)
+  int c0 = 0;
+#pragma clang loop unroll(disable)
+  for (; c0 + kCb <= r; c0 += kCb) {
+    __syncthreads();  // trailing update of the previous block is complete
+    if (wave == 0) {
+      // c0 made opaque: strength reduction would otherwise carry one address
+      // per unrolled panel entry across the loop
+      const int cb = __builtin_amdgcn_readfirstlane(c0);
+      const int bad = chol_panel<kCb, NS>(G, dinv, P, cb, kCb, nrows, lane);
+      if (lane == 0 && bad) fail = bad;
+    }
+    __syncthreads();
+    if (fail) return fail;
+    chol_trailing<kCb>(G, P, c0 + kCb, kCb, r, nrows);
+  }
+  if (c0 < r) {
+    const int m = r - c0;
+    __syncthreads();
+    if (wave == 0) {
+      const int bad = chol_panel<0, NS>(G, dinv, P, c0, m, nrows, lane);
+      if (lane == 0 && bad) fail = bad;
+    }
+    __syncthreads();
+    if (fail) return fail;
+    chol_trailing<0>(G, P, c0 + m, m, r, nrows);
+  }
+  __syncthreads();
+  return 0;
+}
+
+// Solve L^T w = z in place (w holds z on entry) with L from
+// lds_cholesky_blocked: blocks from the last, each solved by one wave
+// (readlane broadcast of the finished entry), then its contribution removed
+// from all earlier entries by every thread.
+__device__ __forceinline__ void lds_chol_backsolve(const double* G, const double* dinv, double* w, int r) {
+  const int tid = threadIdx.x, nt = blockDim.x, lane = tid & 63, wave = tid >> 6;
+  for (int c0 = ((r - 1) / kCb) * kCb; c0 >= 0; c0 -= kCb) {
+    const int m = min(kCb, r - c0);
+    __syncthreads();
+    if (wave == 0) {
+      // the block's column entries of this lane's row and the pivots, loaded
+      // before the dependent chain starts
+      double lc[kCb], di[kCb];
+#pragma unroll
+      for (int c = 0; c < kCb; ++c) {
+        const bool ok = c < m && lane < c;
+        lc[c] = ok ? G[ptri(c0 + c, c0 + lane)] : 0.0;
+        di[c] = c < m ? dinv[c0 + c] : 0.0;
+      }
+      double val = lane < m ? w[c0 + lane] : 0.0;
+#pragma unroll
+      for (int c = kCb - 1; c >= 0; --c) {
+        if (c < m) {
+          const double wc = readlane_d(val, c) * di[c];
+          val = (lane == c) ? wc : (lane < c ? fma(-lc[c], wc, val) : val);
+        }
+      }
+      if (lane < m) w[c0 + lane] = val;
+    }
+    __syncthreads();
+    for (int j = tid; j < c0; j += nt) {
+      double s = w[j];
+      for (int c = 0; c < m; ++c) s = fma(-G[ptri(c0 + c, j)], w[c0 + c], s);
+      w[j] = s;
+    }
+  }
+  __syncthreads();
 }
 
 }  // namespace rpt

@@ -90,6 +90,10 @@ __device__ __forceinline__ f32x16 mfma_bf16(const u32x4& a, const u32x4& b, cons
   return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
                                                   c, 0, 0, 0);
 }
+__device__ __forceinline__ f32x4 mfma16_bf16(const u32x4& a, const u32x4& b, const f32x4& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b),
+                                                  c, 0, 0, 0);
+}
 __device__ __forceinline__ f32x16 mfma_f32(float a, float b, const f32x16& c) {
   return __builtin_amdgcn_mfma_f32_32x32x2f32(a, b, c, 0, 0, 0);
 }
@@ -97,6 +101,11 @@ __device__ __forceinline__ f32x16 mfma_f32(float a, float b, const f32x16& c) {
 // Row of the 32x32 MFMA output held by accumulator register e of a lane in
 // half h (= lane / 32); the column is lane % 32.
 __device__ __forceinline__ int mfma_row(int e, int h) { return 8 * (e >> 2) + 4 * h + (e & 3); }
+// 16x16x32: lane l holds K = 8 (l / 16) .. + 7 of row (A) / column (B) l % 16;
+// accumulator register e holds row 4 (l / 16) + e, column l % 16.
+__device__ __forceinline__ uint32_t pack_bf2(uint16_t lo, uint16_t hi) {
+  return static_cast<uint32_t>(lo) | (static_cast<uint32_t>(hi) << 16);
+}
 
 __device__ __forceinline__ float wave_max(float x) {
 #pragma unroll

@@ -109,6 +109,7 @@ __global__ __launch_bounds__(kBlock) void chol_rinv_kernel(const double* __restr
   double* diag = G + ntri;
   double* dinv = diag + kR;
   float* Li = reinterpret_cast<float*>(dinv + kR);  // [r][kR]
+  double* P = reinterpret_cast<double*>(Li + r * kR);  // [kCb][kPanelLd] Cholesky scratch
   const int tid = threadIdx.x;
   for (int idx = tid; idx < ntri; idx += kBlock) {
     // invert ptri: row i with i(i+1)/2 <= idx
@@ -118,7 +119,8 @@ __global__ __launch_bounds__(kBlock) void chol_rinv_kernel(const double* __restr
     const int c = idx - i * (i + 1) / 2;
     G[idx] = Gfull[i * r + c];
   }
-  const int failed = lds_cholesky(G, diag, dinv, r);
+  __syncthreads();
+  const int failed = lds_cholesky_blocked<2>(G, dinv, P, r, r);
   if (!failed) lds_tri_inverse(G, dinv, r, Li, kR);
   __syncthreads();
   for (int idx = tid; idx < kR * kR; idx += kBlock) {
@@ -132,7 +134,9 @@ __global__ __launch_bounds__(kBlock) void chol_rinv_kernel(const double* __restr
   if (tid == 0 && info) *info = failed;
 }
 
-size_t chol_smem(int r) { return (static_cast<size_t>(r) * (r + 1) / 2 + 2 * kR) * sizeof(double) + r * kR * sizeof(float); }
+size_t chol_smem(int r) {
+  return (static_cast<size_t>(r) * (r + 1) / 2 + 2 * kR + kCb * kPanelLd) * sizeof(double) + r * kR * sizeof(float);
+}
 
 // U <- U R^{-1}, in place; one wave per 32-row tile.
 template <int KS>
