@@ -150,6 +150,8 @@ struct TrainWs {
   float* gap;
   void* reorth_ws;
   void* recon_ws;
+  int32_t* lhead;  // [v] per-voxel lists of a batch's sampled entries
+  int32_t* lnext;  // [ell][k]
 };
 TrainWs train_carve(void* ws, int64_t v, int n, int n1, int ell, int r, int k, int prec, size_t* total) {
   Carver c(ws);
@@ -166,6 +168,8 @@ TrainWs train_carve(void* ws, int64_t v, int n, int n1, int ell, int r, int k, i
   t.gap = c.take<float>(ell);
   t.reorth_ws = c.take<char>(reorth_bytes(v, r));
   t.recon_ws = c.take<char>(recon_bytes(v, ell, r));
+  t.lhead = c.take<int32_t>(v);
+  t.lnext = c.take<int32_t>(static_cast<size_t>(ell) * k);
   if (total) *total = c.off;
   return t;
 }
@@ -190,7 +194,7 @@ rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx,
   if (!design_ok(v, n, ldx, n1) || 2 * n1 != n) return design_ok(v, n, ldx, n1) ? RPT_ERR_UNSUPPORTED
                                                                                : RPT_ERR_INVALID_ARG;
   if (ell < 1 || r < 1 || r > 128 || r > v || k < 1 || k > v || passes < 0 || batch < 1 || batch > ell ||
-      !(gamma > 0.0f))
+      !(gamma > 0.0f) || static_cast<int64_t>(ell) * k > INT32_MAX)
     return RPT_ERR_INVALID_ARG;
   if (k < r) return RPT_ERR_UNDERDETERMINED;
   if (mu_rule != RPT_MU_MEAN_GAP && mu_rule != RPT_MU_LITERAL && mu_rule != RPT_MU_ZERO) return RPT_ERR_INVALID_ARG;
@@ -215,14 +219,16 @@ rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx,
   }
   RPT_TRY(reorth_launch(U_out, v, r, t.info, t.reorth_ws, s));
   RPT_TRY(reorth_launch(U_out, v, r, t.info, t.reorth_ws, s));
-  // 3. tracking passes
+  // 3. tracking passes: Complete links every sampled entry into the list of
+  // its voxel; the update then adds each voxel's entries in one pass
+  RPT_TRY(fill_i32(t.lhead, v, -1, s));
   for (int pp = 0; pp < passes; ++pp) {
     for (int b0 = 0; b0 < ell; b0 += batch) {
       const int nb = b0 + batch <= ell ? batch : ell - b0;
       const int32_t* om = omega_train + (static_cast<int64_t>(pp) * ell + b0) * k;
       RPT_TRY(complete_run(U_out, v, r, om, k, nullptr, T + static_cast<int64_t>(b0) * v, v, nullptr, nb, t.W,
-                           t.resid, t.info, t.wnorm2, s));
-      RPT_TRY(track_update_launch(U_out, v, r, om, k, t.resid, t.W, t.wnorm2, t.info, nb, gamma, s));
+                           t.resid, t.info, t.wnorm2, s, t.lhead, t.lnext));
+      RPT_TRY(track_apply_launch(U_out, v, r, k, t.resid, t.W, t.wnorm2, t.info, gamma, t.lhead, t.lnext, s));
       RPT_TRY(reorth_launch(U_out, v, r, t.info + ell - 1, t.reorth_ws, s));
     }
   }

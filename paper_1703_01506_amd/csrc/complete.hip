@@ -12,7 +12,10 @@
 // lower triangle in LDS with b^T appended as row r, so that the blocked
 // Cholesky of that trapezoid leaves z = L^{-1} b in row r; one blocked back
 // substitution gives w.  A non-positive pivot j sets info[i] = j + 1 and
-// w_i = 0.  Optionally the residual y - U_O w is written.
+// w_i = 0.  Optionally the residual y - U_O w is written, and each sampled
+// entry (i, q) of a solved column is pushed onto the list of its voxel
+// (lhead / lnext), so that a later pass can apply all entries of one voxel
+// together without floating-point atomics.
 #include "lds_linalg.h"
 #include "rpt_internal.h"
 
@@ -40,6 +43,8 @@ struct CompleteArgs {
   float* resid;         // [L][k] or nullptr
   int32_t* info;        // [L]
   float* wnorm2;        // [L] |w|^2 (or nullptr)
+  int32_t* lhead;       // [v] per-voxel list heads (-1 = empty) or nullptr
+  int32_t* lnext;       // [L][k] list links of the sampled entries
 };
 
 __device__ __forceinline__ float y_at(const CompleteArgs& a, int64_t i, int q) {
@@ -212,6 +217,10 @@ __global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(Comple
         }
       }
       a.resid[i * k + q] = static_cast<float>(yq - ((s0 + s1) + (s2 + s3)));
+      if (a.lhead && row >= 0 && row < a.v) {
+        const int32_t e = static_cast<int32_t>(i * k + q);
+        a.lnext[e] = atomicExch(a.lhead + row, e);
+      }
     }
   }
 }
@@ -220,10 +229,11 @@ __global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(Comple
 
 rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, int k, const float* y,
                         const float* Trows, int64_t ldT, const int32_t* trow, int64_t L, float* W, float* resid,
-                        int32_t* info, float* wnorm2, hipStream_t s) {
+                        int32_t* info, float* wnorm2, hipStream_t s, int32_t* lhead, int32_t* lnext) {
   if (L == 0) return RPT_OK;
   if (r < 1 || r > kRMax) return RPT_ERR_UNSUPPORTED;
-  CompleteArgs a{U, v, r, omega, k, y, Trows, ldT, trow, L, W, resid, info, wnorm2};
+  if (lhead && (!resid || L * static_cast<int64_t>(k) > INT32_MAX)) return RPT_ERR_INVALID_ARG;
+  CompleteArgs a{U, v, r, omega, k, y, Trows, ldT, trow, L, W, resid, info, wnorm2, lhead, lnext};
   const int RB = (r + 15) / 16;
   void* fns[8] = {reinterpret_cast<void*>(&complete_kernel<1>), reinterpret_cast<void*>(&complete_kernel<2>),
                   reinterpret_cast<void*>(&complete_kernel<3>), reinterpret_cast<void*>(&complete_kernel<4>),

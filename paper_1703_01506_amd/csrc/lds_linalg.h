@@ -341,9 +341,88 @@ __device__ __forceinline__ void lds_chol_backsolve(const double* G, const double
     }
     __syncthreads();
     for (int j = tid; j < c0; j += nt) {
-      double s = w[j];
-      for (int c = 0; c < m; ++c) s = fma(-G[ptri(c0 + c, j)], w[c0 + c], s);
-      w[j] = s;
+      // unrolled with two accumulators: the loads do not wait on the sums
+      double s0 = w[j], s1 = 0.0;
+#pragma unroll
+      for (int c = 0; c < kCb; ++c) {
+        if (c < m) {
+          const double g = G[ptri(c0 + c, 0) + j];
+          if (c & 1) s1 = fma(-g, w[c0 + c], s1);
+          else s0 = fma(-g, w[c0 + c], s0);
+        }
+      }
+      w[j] = s0 + s1;
+    }
+  }
+  __syncthreads();
+}
+
+// X = L^{-1} (lower) for the L left by lds_cholesky_blocked, by blocks of
+// kCb rows: every diagonal block is inverted at once (one thread per column
+// of a block, forward substitution in FP64 registers), then block row p is
+//   S = L[p, 0:p] X[0:p, 0:p],   X[p, 0:p] = -X_pp S,
+// two parallel products per block row.  X is FP32 in LDS with leading
+// dimension ld (columns up to kCb * ceil(r / kCb) written, zeros above the
+// diagonal); S uses the kCb * kPanelLd doubles at P.  FP64 sums throughout.
+__device__ __forceinline__ void lds_tri_inverse_blocked(const double* G, const double* dinv, int r, float* X,
+                                                        int ld, double* P) {
+  const int tid = threadIdx.x, nt = blockDim.x;
+  const int nb = (r + kCb - 1) / kCb;
+  const int rp = nb * kCb;
+  for (int t = tid; t < rp * ld; t += nt) X[t] = 0.0f;
+  __syncthreads();
+  // diagonal blocks: thread (p, c) solves L_pp x = e_c
+  if (tid < nb * kCb) {
+    const int p = tid / kCb, c = tid - p * kCb, c0 = p * kCb;
+    const int m = min(kCb, r - c0);
+    if (c < m) {
+      double x[kCb];
+#pragma unroll
+      for (int i = 0; i < kCb; ++i) {
+        if (i < m) {
+          double s = (i == c) ? 1.0 : 0.0;
+#pragma unroll
+          for (int j = 0; j < i; ++j) s = fma(-G[ptri(c0 + i, c0 + j)], x[j], s);
+          x[i] = (i >= c) ? s * dinv[c0 + i] : 0.0;
+          X[(c0 + i) * ld + c0 + c] = static_cast<float>(x[i]);
+        }
+      }
+    }
+  }
+  for (int p = 1; p < nb; ++p) {
+    const int c0 = p * kCb, m = min(kCb, r - c0);
+    __syncthreads();  // block rows < p of X are final
+    // S[a][col] = sum_{j = col}^{c0 - 1} L[c0 + a][j] X[j][col],  a < m, col < c0
+    for (int t = tid; t < m * c0; t += nt) {
+      const int a = t / c0, col = t - a * c0;
+      const double* lr = G + ptri(c0 + a, 0);
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int j = col;
+      // four independent sums keep several LDS loads in flight
+#pragma unroll 2
+      for (; j + 3 < c0; j += 4) {
+        s0 = fma(lr[j], static_cast<double>(X[j * ld + col]), s0);
+        s1 = fma(lr[j + 1], static_cast<double>(X[(j + 1) * ld + col]), s1);
+        s2 = fma(lr[j + 2], static_cast<double>(X[(j + 2) * ld + col]), s2);
+        s3 = fma(lr[j + 3], static_cast<double>(X[(j + 3) * ld + col]), s3);
+      }
+      for (; j < c0; ++j) s0 = fma(lr[j], static_cast<double>(X[j * ld + col]), s0);
+      P[a * kPanelLd + col] = (s0 + s1) + (s2 + s3);
+    }
+    __syncthreads();
+    // X[c0 + a][col] = -sum_{b <= a} X_pp[a][b] S[b][col]
+    for (int t = tid; t < m * c0; t += nt) {
+      const int a = t / c0, col = t - a * c0;
+      double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+      for (int b = 0; b < kCb; ++b) {
+        if (b <= a) {
+          const double t2 = static_cast<double>(X[(c0 + a) * ld + c0 + b]) * P[b * kPanelLd + col];
+          if (b & 1) s1 += t2;
+          else s0 += t2;
+        }
+      }
+      X[(c0 + a) * ld + col] = static_cast<float>(-(s0 + s1));
     }
   }
   __syncthreads();

@@ -189,7 +189,8 @@ rpt_status sampled_launch(const PrepX& p, const uint8_t* labels, int64_t L, cons
 // y ([L][k]) or, when y is null, from rows of T: y[i][q] = Trows[i * ldT + omega[i][q]].
 rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, int k, const float* y,
                         const float* Trows, int64_t ldT, const int32_t* trow, int64_t L, float* W, float* resid,
-                        int32_t* info, float* wnorm2, hipStream_t s);
+                        int32_t* info, float* wnorm2, hipStream_t s, int32_t* lhead = nullptr,
+                        int32_t* lnext = nullptr);
 
 // Reconstruction filter + exact refine with noise (K7).
 size_t recon_bytes(int64_t v, int64_t L, int r);
@@ -202,9 +203,12 @@ size_t reorth_bytes(int64_t v, int r);
 rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hipStream_t s);
 
 // Training helpers (train.hip).
-rpt_status track_update_launch(float* U, int64_t v, int r, const int32_t* omega, int k, const float* resid,
-                               const float* W, const float* wnorm2, const int32_t* info, int64_t B, float gamma,
-                               hipStream_t s);
+// U[x] += gamma sum_e resid[e] W[i(e)] / |w_i(e)|^2 over the entries linked
+// at voxel x by complete_run (i(e) = e / k); every list head is reset to -1.
+rpt_status track_apply_launch(float* U, int64_t v, int r, int k, const float* resid, const float* W,
+                              const float* wnorm2, const int32_t* info, float gamma, int32_t* lhead,
+                              const int32_t* lnext, hipStream_t s);
+rpt_status fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s);
 rpt_status sigma_launch(const float* resid, int64_t n, double* sums, float* sigma_mu, hipStream_t s);
 rpt_status mu_launch(const float* vals, int n, int rule, float* sigma_mu, hipStream_t s);
 rpt_status literal_resid_launch(const float* T, const float* U, const float* W, int64_t v, int r, int64_t ell,

@@ -25,76 +25,147 @@ constexpr int kStage = 64;       // rows per LDS stage
 constexpr int kLd = 72;          // bf16 per staged column (64 + pad)
 
 // ---------------------------------------------------------------- Gram partials
-template <int RT>
-__global__ __launch_bounds__(kBlock) void gram_partial_kernel(const float* __restrict__ U, int64_t v, int r,
-                                                             int64_t rows_per_blk, float* __restrict__ part) {
-  __shared__ __align__(16) uint16_t uth[kR * kLd];
-  __shared__ __align__(16) uint16_t utl[kR * kLd];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, col = lane & 31;
+// U^T U over a contiguous range of rows per workgroup, 64 rows at a time:
+// the chunk (64 r contiguous floats) is read with coalesced 16-byte loads
+// (the next chunk's loads are issued before this chunk's products), split
+// into BF16 hi/lo and stored transposed in LDS; the lower-triangular 16 x 16
+// tiles are spread over the four waves and accumulated on 16x16x32 MFMA as
+// hi.hi + hi.lo + lo.hi.  Each wave writes its own tiles of the partial:
+// tile t = (bi, bj), bj <= bi, element 64 e + lane (row 16 bi +
+// 4 (lane / 16) + e, column 16 bj + lane % 16).
+constexpr int kGramChunk = 64;
+constexpr int kGramLd = kGramChunk + 8;  // bf16 per staged column
+template <int RB>
+__global__ __launch_bounds__(kBlock, 2) void gram_partial_kernel(const float* __restrict__ U, int64_t v, int r,
+                                                                int64_t rows_per_blk, float* __restrict__ part) {
+  constexpr int NTILE = RB * (RB + 1) / 2;
+  constexpr int TPW = (NTILE + 3) / 4;                    // tiles per wave
+  constexpr int NV = (kGramChunk * 16 * RB / 4 + kBlock - 1) / kBlock;  // float4 per thread per chunk
+  __shared__ __align__(16) uint16_t uth[16 * RB * kGramLd];
+  __shared__ __align__(16) uint16_t utl[16 * RB * kGramLd];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, c16 = lane & 15, kq = lane >> 4;
   const int64_t r0 = blockIdx.x * rows_per_blk;
   const int64_t r1 = r0 + rows_per_blk < v ? r0 + rows_per_blk : v;
-  f32x16 acc[RT];
+  const bool vec = (r & 3) == 0 && (reinterpret_cast<uintptr_t>(U) & 15) == 0;
+  const int q4 = r >> 2;  // float4 per row (vector path)
+  f32x4 acc[TPW];
 #pragma unroll
-  for (int t = 0; t < RT; ++t) acc[t] = f32x16{};
-  const int ac = tid & (kR - 1), par = tid >> 7;
-  for (int64_t c0 = r0; c0 < r1; c0 += kStage) {
-    float x[kStage / 2];
+  for (int t = 0; t < TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  f32x4 buf[NV];
+  auto load = [&](int64_t c0) {
+    const int64_t nrow = r1 - c0 < kGramChunk ? r1 - c0 : kGramChunk;
 #pragma unroll
-    for (int m = 0; m < kStage / 2; ++m) {
-      const int64_t row = c0 + par + 2 * m;
-      x[m] = (row < r1 && ac < r) ? U[row * r + ac] : 0.0f;
+    for (int u = 0; u < NV; ++u) {
+      const int t = tid + u * kBlock;
+      if (vec) {
+        const int row = t / q4, c4 = t - row * q4;
+        buf[u] = (row < nrow) ? *reinterpret_cast<const f32x4*>(U + (c0 + row) * r + 4 * c4)
+                              : f32x4{0.f, 0.f, 0.f, 0.f};
+      } else {
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int64_t el = static_cast<int64_t>(t) * 4 + e;  // element of the chunk, row-major
+          buf[u][e] = (el < nrow * r) ? U[c0 * r + el] : 0.0f;
+        }
+      }
     }
+  };
+  // columns of the staged chunk that no thread writes stay zero
+  for (int t = tid; t < 16 * RB * kGramLd; t += kBlock) {
+    uth[t] = 0;
+    utl[t] = 0;
+  }
+  if (r0 < r1) load(r0);
+  for (int64_t c0 = r0; c0 < r1; c0 += kGramChunk) {
+    __syncthreads();  // previous chunk's MFMA reads of the stage are done
+#pragma unroll
+    for (int u = 0; u < NV; ++u) {
+      const int t = tid + u * kBlock;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        int row, col;
+        if (vec) {
+          row = t / q4;
+          col = 4 * (t - row * q4) + e;
+        } else {
+          row = (4 * t + e) / r;
+          col = 4 * t + e - row * r;
+        }
+        if (row < kGramChunk && col < 16 * RB) {
+          const float xv = buf[u][e];
+          const uint16_t hv = f2bf(xv);
+          uth[col * kGramLd + row] = hv;
+          utl[col * kGramLd + row] = f2bf(xv - bf2f(hv));
+        }
+      }
+    }
+    if (c0 + kGramChunk < r1) load(c0 + kGramChunk);
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < kStage / 2; ++m) {
-      const int kk = par + 2 * m;
-      const uint16_t hi = f2bf(x[m]);
-      uth[ac * kLd + kk] = hi;
-      utl[ac * kLd + kk] = f2bf(x[m] - bf2f(hi));
-    }
-    __syncthreads();
-    if (wave < RT) {
+    for (int ks = 0; ks < kGramChunk / 32; ++ks) {
+      const int ko = 32 * ks + 8 * kq;
 #pragma unroll
-      for (int s = 0; s < kStage / 16; ++s) {
-        const int ko = 16 * s + 8 * h;
-        const u32x4 ah = *reinterpret_cast<const u32x4*>(uth + (wave * 32 + col) * kLd + ko);
-        const u32x4 al = *reinterpret_cast<const u32x4*>(utl + (wave * 32 + col) * kLd + ko);
+      for (int tt = 0; tt < TPW; ++tt) {
+        const int t = wave + 4 * tt;
+        if (t < NTILE) {
+          int bi = 0;
 #pragma unroll
-        for (int t = 0; t < RT; ++t) {
-          const u32x4 bh = *reinterpret_cast<const u32x4*>(uth + (t * 32 + col) * kLd + ko);
-          const u32x4 bl = *reinterpret_cast<const u32x4*>(utl + (t * 32 + col) * kLd + ko);
-          acc[t] = mfma_bf16(ah, bh, acc[t]);
-          acc[t] = mfma_bf16(ah, bl, acc[t]);
-          acc[t] = mfma_bf16(al, bh, acc[t]);
+          for (int q = 1; q < RB; ++q) bi += (q * (q + 1) / 2 <= t) ? 1 : 0;
+          const int bj = t - bi * (bi + 1) / 2;
+          const u32x4 ah = *reinterpret_cast<const u32x4*>(uth + (16 * bi + c16) * kGramLd + ko);
+          const u32x4 al = *reinterpret_cast<const u32x4*>(utl + (16 * bi + c16) * kGramLd + ko);
+          const u32x4 bh = *reinterpret_cast<const u32x4*>(uth + (16 * bj + c16) * kGramLd + ko);
+          const u32x4 bl = *reinterpret_cast<const u32x4*>(utl + (16 * bj + c16) * kGramLd + ko);
+          acc[tt] = mfma16_bf16(ah, bh, acc[tt]);
+          acc[tt] = mfma16_bf16(ah, bl, acc[tt]);
+          acc[tt] = mfma16_bf16(al, bh, acc[tt]);
         }
       }
     }
   }
-  if (wave < RT) {
-    float* P = part + static_cast<int64_t>(blockIdx.x) * r * r;
+  float* P = part + static_cast<int64_t>(blockIdx.x) * NTILE * 256;
 #pragma unroll
-    for (int t = 0; t < RT; ++t)
+  for (int tt = 0; tt < TPW; ++tt) {
+    const int t = wave + 4 * tt;
+    if (t < NTILE)
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int row = wave * 32 + mfma_row(e, h), cc = t * 32 + col;
-        if (row < r && cc < r) P[row * r + cc] = acc[t][e];
-      }
+      for (int e = 0; e < 4; ++e) P[t * 256 + 64 * e + lane] = acc[tt][e];
   }
 }
 
-// G = sum of the partials, in FP64: a workgroup owns 64 entries, its four
-// waves sum interleaved quarters of the partials, LDS combines them.
-__global__ __launch_bounds__(kBlock) void gram_reduce_kernel(const float* __restrict__ part, int nblk, int r,
-                                                            double* __restrict__ G) {
-  __shared__ double red[4][64];
+// G (lower triangle, FP64) = sum of the partials: a workgroup owns 64
+// entries; its 16 waves sum interleaved sixteenths of the partials (eight
+// loads in flight per lane), LDS combines them.
+constexpr int kRedWaves = 16;
+__global__ __launch_bounds__(64 * kRedWaves) void gram_reduce_kernel(const float* __restrict__ part, int nblk,
+                                                                    int ntile, int r, double* __restrict__ G) {
+  __shared__ double red[kRedWaves][64];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int idx = blockIdx.x * 64 + lane;
-  double s = 0.0;
-  if (idx < r * r)
-    for (int b = wave; b < nblk; b += 4) s += part[static_cast<int64_t>(b) * r * r + idx];
-  red[wave][lane] = s;
+  const int n = ntile * 256;
+  double s[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (idx < n) {
+    int b = wave;
+    for (; b + 7 * kRedWaves < nblk; b += 8 * kRedWaves) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) s[u] += part[static_cast<int64_t>(b + u * kRedWaves) * n + idx];
+    }
+    for (; b < nblk; b += kRedWaves) s[0] += part[static_cast<int64_t>(b) * n + idx];
+  }
+  red[wave][lane] = ((s[0] + s[1]) + (s[2] + s[3])) + ((s[4] + s[5]) + (s[6] + s[7]));
   __syncthreads();
-  if (wave == 0 && idx < r * r) G[idx] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+  if (wave == 0 && idx < n) {
+    double tot = 0.0;
+#pragma unroll
+    for (int w = 0; w < kRedWaves; ++w) tot += red[w][lane];
+    // decode (tile, element) -> (row, column)
+    const int t = idx >> 8, el = idx & 255, e = el >> 6, l = el & 63;
+    int bi = 0;
+    while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+    const int bj = t - bi * (bi + 1) / 2;
+    const int row = 16 * bi + 4 * (l >> 4) + e, col = 16 * bj + (l & 15);
+    if (row < r && col <= row) G[row * r + col] = tot;
+  }
 }
 
 // Factor G = L L^T (FP64, LDS) and write R^{-1} = L^{-T} transposed
@@ -109,7 +180,7 @@ __global__ __launch_bounds__(kBlock) void chol_rinv_kernel(const double* __restr
   double* diag = G + ntri;
   double* dinv = diag + kR;
   float* Li = reinterpret_cast<float*>(dinv + kR);  // [r][kR]
-  double* P = reinterpret_cast<double*>(Li + r * kR);  // [kCb][kPanelLd] Cholesky scratch
+  double* P = reinterpret_cast<double*>(Li + ((r + kCb - 1) / kCb) * kCb * kR);  // [kCb][kPanelLd] scratch
   const int tid = threadIdx.x;
   for (int idx = tid; idx < ntri; idx += kBlock) {
     // invert ptri: row i with i(i+1)/2 <= idx
@@ -121,7 +192,7 @@ __global__ __launch_bounds__(kBlock) void chol_rinv_kernel(const double* __restr
   }
   __syncthreads();
   const int failed = lds_cholesky_blocked<2>(G, dinv, P, r, r);
-  if (!failed) lds_tri_inverse(G, dinv, r, Li, kR);
+  if (!failed) lds_tri_inverse_blocked(G, dinv, r, Li, kR, P);
   __syncthreads();
   for (int idx = tid; idx < kR * kR; idx += kBlock) {
     const int c = idx / kR, j = idx - c * kR;
@@ -135,100 +206,125 @@ __global__ __launch_bounds__(kBlock) void chol_rinv_kernel(const double* __restr
 }
 
 size_t chol_smem(int r) {
-  return (static_cast<size_t>(r) * (r + 1) / 2 + 2 * kR + kCb * kPanelLd) * sizeof(double) + r * kR * sizeof(float);
+  const size_t rp = static_cast<size_t>((r + kCb - 1) / kCb) * kCb;
+  return (static_cast<size_t>(r) * (r + 1) / 2 + 2 * kR + kCb * kPanelLd) * sizeof(double) + rp * kR * sizeof(float);
 }
 
-// U <- U R^{-1}, in place; one wave per 32-row tile.
+// U <- U R^{-1}, in place.  R^{-T} (BF16 hi/lo) is staged in LDS once per
+// workgroup (rows padded against bank conflicts); each wave then takes
+// 32-row tiles of U in turn: A fragments straight from its rows, the
+// product on the matrix cores as a 3-pass split, written back over the
+// same rows (all reads of a tile happen before its first write).
+constexpr int kRl = kR + 8;  // LDS row length of the staged R^{-T}
 template <int KS>
-__global__ __launch_bounds__(kBlock) void apply_rinv_kernel(float* __restrict__ U, int64_t v, int r,
-                                                           const uint16_t* __restrict__ rth,
-                                                           const uint16_t* __restrict__ rtl) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, col = lane & 31;
-  const int64_t tile = static_cast<int64_t>(blockIdx.x) * 4 + wave;
-  const int64_t v0 = tile * 32;
-  if (v0 >= v) return;
-  // A fragments: lane supplies U[v0 + col][16s + 8h + 0..7] (hi, lo)
-  u32x4 Ah[KS], Al[KS];
-  const int64_t vox = v0 + col;
-  const bool vec = (r & 3) == 0;
-#pragma unroll
-  for (int s = 0; s < KS; ++s) {
-    const int cb = 16 * s + 8 * h;
-    float x[8];
-    if (vec && vox < v && cb + 8 <= r) {
-      const f32x4 p0 = *reinterpret_cast<const f32x4*>(U + vox * r + cb);
-      const f32x4 p1 = *reinterpret_cast<const f32x4*>(U + vox * r + cb + 4);
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        x[e] = p0[e];
-        x[4 + e] = p1[e];
-      }
-    } else {
-#pragma unroll
-      for (int e = 0; e < 8; ++e) x[e] = (vox < v && cb + e < r) ? U[vox * r + cb + e] : 0.0f;
-    }
-    unsigned wh[4], wl[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      uint32_t ph = 0, pl = 0;
-#pragma unroll
-      for (int hl = 0; hl < 2; ++hl) {
-        const float xv = x[2 * q + hl];
-        const uint16_t hi = f2bf(xv);
-        ph |= static_cast<uint32_t>(hi) << (16 * hl);
-        pl |= static_cast<uint32_t>(f2bf(xv - bf2f(hi))) << (16 * hl);
-      }
-      wh[q] = ph;
-      wl[q] = pl;
-    }
-    Ah[s] = u32x4{wh[0], wh[1], wh[2], wh[3]};
-    Al[s] = u32x4{wl[0], wl[1], wl[2], wl[3]};
+__global__ __launch_bounds__(kBlock, 2) void apply_rinv_kernel(float* __restrict__ U, int64_t v, int r,
+                                                              const uint16_t* __restrict__ rth,
+                                                              const uint16_t* __restrict__ rtl) {
+  __shared__ __align__(16) uint16_t sh[kR * kRl];
+  __shared__ __align__(16) uint16_t sl[kR * kRl];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, col = lane & 31;
+  for (int t = tid; t < kR * (kR / 8); t += kBlock) {
+    const int row = t / (kR / 8), c8 = (t - row * (kR / 8)) * 8;
+    *reinterpret_cast<u32x4*>(sh + row * kRl + c8) = *reinterpret_cast<const u32x4*>(rth + row * kR + c8);
+    *reinterpret_cast<u32x4*>(sl + row * kRl + c8) = *reinterpret_cast<const u32x4*>(rtl + row * kR + c8);
   }
+  __syncthreads();
+  const bool vec = (r & 3) == 0 && (reinterpret_cast<uintptr_t>(U) & 15) == 0;
   const int CT = (r + 31) / 32;
-  for (int ct = 0; ct < CT; ++ct) {
-    f32x16 acc = f32x16{};
-    const int c = ct * 32 + col;
+  const int64_t ntile = (v + 31) / 32;
+  for (int64_t tile = static_cast<int64_t>(blockIdx.x) * 4 + wave; tile < ntile;
+       tile += static_cast<int64_t>(gridDim.x) * 4) {
+    const int64_t v0 = tile * 32;
+    // A fragments: lane supplies U[v0 + col][16s + 8h + 0..7] (hi, lo)
+    u32x4 Ah[KS], Al[KS];
+    const int64_t vox = v0 + col;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      const int ko = 16 * s + 8 * h;
-      const u32x4 bh = *reinterpret_cast<const u32x4*>(rth + c * kR + ko);
-      const u32x4 bl = *reinterpret_cast<const u32x4*>(rtl + c * kR + ko);
-      acc = mfma_bf16(Ah[s], bh, acc);
-      acc = mfma_bf16(Ah[s], bl, acc);
-      acc = mfma_bf16(Al[s], bh, acc);
-    }
-    // every lane's reads of this tile happened before the first MFMA above
+      const int cb = 16 * s + 8 * h;
+      float x[8];
+      if (vec && vox < v && cb + 8 <= r) {
+        const f32x4 p0 = *reinterpret_cast<const f32x4*>(U + vox * r + cb);
+        const f32x4 p1 = *reinterpret_cast<const f32x4*>(U + vox * r + cb + 4);
 #pragma unroll
-    for (int e = 0; e < 16; ++e) {
-      const int64_t row = v0 + mfma_row(e, h);
-      if (row < v && c < r) U[row * r + c] = acc[e];
+        for (int e = 0; e < 4; ++e) {
+          x[e] = p0[e];
+          x[4 + e] = p1[e];
+        }
+      } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = (vox < v && cb + e < r) ? U[vox * r + cb + e] : 0.0f;
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const uint16_t h0 = f2bf(x[2 * q]), h1 = f2bf(x[2 * q + 1]);
+        Ah[s][q] = pack_bf2(h0, h1);
+        Al[s][q] = pack_bf2(f2bf(x[2 * q] - bf2f(h0)), f2bf(x[2 * q + 1] - bf2f(h1)));
+      }
+    }
+    for (int ct = 0; ct < CT; ++ct) {
+      f32x16 acc = f32x16{};
+      const int c = ct * 32 + col;
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int ko = 16 * s + 8 * h;
+        const u32x4 bh = *reinterpret_cast<const u32x4*>(sh + c * kRl + ko);
+        const u32x4 bl = *reinterpret_cast<const u32x4*>(sl + c * kRl + ko);
+        acc = mfma_bf16(Ah[s], bh, acc);
+        acc = mfma_bf16(Ah[s], bl, acc);
+        acc = mfma_bf16(Al[s], bh, acc);
+      }
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t row = v0 + mfma_row(e, h);
+        if (row < v && c < r) U[row * r + c] = acc[e];
+      }
     }
   }
 }
 
 // ---------------------------------------------------------------- tracking update
-__global__ __launch_bounds__(kBlock) void track_update_kernel(float* __restrict__ U, int64_t v, int r,
-                                                             const int32_t* __restrict__ omega, int k,
-                                                             const float* __restrict__ resid,
-                                                             const float* __restrict__ W,
-                                                             const float* __restrict__ wnorm2,
-                                                             const int32_t* __restrict__ info, float gamma) {
-  // one workgroup per batch column; thread t covers coefficient t % r of rows
-  const int64_t i = blockIdx.x;
-  if (info[i] != 0) return;
-  const float n2 = wnorm2[i];
-  if (!(n2 > 0.0f)) return;
-  const float sc = gamma / n2;
-  const int tid = threadIdx.x;
-  const int per = kBlock / r > 0 ? kBlock / r : 1;  // rows handled per sweep
-  const int c = tid % r, lr = tid / r;
-  if (lr >= per) return;
-  const float wc = W[i * r + c] * sc;
-  for (int q = lr; q < k; q += per) {
-    const int64_t row = omega[i * k + q];
-    if (row < 0 || row >= v) continue;
-    atomicAdd(U + row * r + c, resid[i * k + q] * wc);
+// Half a wave per voxel: walk the voxel's list of sampled entries (linked by
+// the Complete kernel), sum gamma e / |w_i|^2 * w_i over it, add the sum to
+// the voxel's basis row, and reset the list head.  Lane l covers columns
+// l, l + 32, l + 64, l + 96, so every row access is a 128-byte segment.
+__global__ __launch_bounds__(kBlock) void track_apply_kernel(float* __restrict__ U, int64_t v, int r, int k,
+                                                            const float* __restrict__ resid,
+                                                            const float* __restrict__ W,
+                                                            const float* __restrict__ wnorm2,
+                                                            const int32_t* __restrict__ info, float gamma,
+                                                            int32_t* __restrict__ lhead,
+                                                            const int32_t* __restrict__ lnext) {
+  const int64_t vox = static_cast<int64_t>(blockIdx.x) * (kBlock / 32) + (threadIdx.x >> 5);
+  const int l = threadIdx.x & 31;
+  if (vox >= v) return;
+  int e = lhead[vox];
+  if (e < 0) return;
+  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  while (e >= 0) {
+    const int i = e / k;
+    const float n2 = wnorm2[i];
+    const float coef = (info[i] == 0 && n2 > 0.0f) ? gamma * resid[e] / n2 : 0.0f;
+    const float* wi = W + static_cast<int64_t>(i) * r;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int c = l + 32 * j;
+      if (c < r) acc[j] = fmaf(coef, wi[c], acc[j]);
+    }
+    e = lnext[e];
   }
+  float* u = U + vox * r;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int c = l + 32 * j;
+    if (c < r) u[c] += acc[j];
+  }
+  if (l == 0) lhead[vox] = -1;  // every lane of this half wave read the head above
+}
+
+__global__ __launch_bounds__(kBlock) void fill_i32_kernel(int32_t* p, int64_t n, int32_t value) {
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; t < n;
+       t += static_cast<int64_t>(gridDim.x) * kBlock)
+    p[t] = value;
 }
 
 // ---------------------------------------------------------------- sigma, mu
@@ -303,8 +399,8 @@ __global__ __launch_bounds__(kBlock) void literal_resid_max_kernel(const float* 
 }
 
 int gram_blocks(int64_t v) {
-  int64_t nb = ceil_div(v, 256);
-  if (nb > 256) nb = 256;
+  int64_t nb = ceil_div(v, 512);
+  if (nb > 512) nb = 512;
   if (nb < 1) nb = 1;
   return static_cast<int>(nb);
 }
@@ -313,7 +409,7 @@ int gram_blocks(int64_t v) {
 
 size_t reorth_bytes(int64_t v, int r) {
   Carver c(nullptr);
-  c.take<float>(static_cast<size_t>(gram_blocks(v)) * r * r);
+  c.take<float>(static_cast<size_t>(gram_blocks(v)) * 36 * 256);
   c.take<double>(static_cast<size_t>(r) * r);
   c.take<uint16_t>(static_cast<size_t>(kR) * kR);
   c.take<uint16_t>(static_cast<size_t>(kR) * kR);
@@ -324,22 +420,27 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
   if (r < 1 || r > kR) return RPT_ERR_UNSUPPORTED;
   Carver c(ws);
   const int nb = gram_blocks(v);
-  float* part = c.take<float>(static_cast<size_t>(nb) * r * r);
+  float* part = c.take<float>(static_cast<size_t>(nb) * 36 * 256);
   double* gfull = c.take<double>(static_cast<size_t>(r) * r);
   uint16_t* rth = c.take<uint16_t>(static_cast<size_t>(kR) * kR);
   uint16_t* rtl = c.take<uint16_t>(static_cast<size_t>(kR) * kR);
-  const int RT = (r + 31) / 32;
-  const int64_t rpb = round_up(ceil_div(v, nb), kStage);
+  const int RB = (r + 15) / 16;
+  const int ntile = RB * (RB + 1) / 2;
+  const int64_t rpb = round_up(ceil_div(v, nb), kGramChunk);
   RPT_STAGE("reorth", s);
-  switch (RT) {
+  switch (RB) {
     case 1: hipLaunchKernelGGL(gram_partial_kernel<1>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
     case 2: hipLaunchKernelGGL(gram_partial_kernel<2>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
     case 3: hipLaunchKernelGGL(gram_partial_kernel<3>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
-    default: hipLaunchKernelGGL(gram_partial_kernel<4>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
+    case 4: hipLaunchKernelGGL(gram_partial_kernel<4>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
+    case 5: hipLaunchKernelGGL(gram_partial_kernel<5>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
+    case 6: hipLaunchKernelGGL(gram_partial_kernel<6>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
+    case 7: hipLaunchKernelGGL(gram_partial_kernel<7>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
+    default: hipLaunchKernelGGL(gram_partial_kernel<8>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
   }
   RPT_CHECK_LAUNCH();
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(static_cast<unsigned>(ceil_div(static_cast<int64_t>(r) * r, 64))),
-                     dim3(kBlock), 0, s, part, nb, r, gfull);
+  hipLaunchKernelGGL(gram_reduce_kernel, dim3(static_cast<unsigned>(ceil_div(static_cast<int64_t>(ntile) * 256, 64))),
+                     dim3(64 * kRedWaves), 0, s, part, nb, ntile, r, gfull);
   RPT_CHECK_LAUNCH();
   static bool attr_set = false;
   if (!attr_set) {
@@ -349,7 +450,9 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
   }
   hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(kBlock), chol_smem(r), s, gfull, r, rth, rtl, info);
   RPT_CHECK_LAUNCH();
-  const unsigned blocks = static_cast<unsigned>(ceil_div(ceil_div(v, 32), 4));
+  int64_t ab = ceil_div(ceil_div(v, 32), 4);
+  if (ab > 512) ab = 512;  // two workgroups per CU; each wave then loops over tiles
+  const unsigned blocks = static_cast<unsigned>(ab);
   const int KS = static_cast<int>(ceil_div(r, 16));
   switch (KS) {
     case 1: hipLaunchKernelGGL(apply_rinv_kernel<1>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl); break;
@@ -365,13 +468,23 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
   return RPT_OK;
 }
 
-rpt_status track_update_launch(float* U, int64_t v, int r, const int32_t* omega, int k, const float* resid,
-                               const float* W, const float* wnorm2, const int32_t* info, int64_t B, float gamma,
-                               hipStream_t s) {
-  if (B == 0) return RPT_OK;
+rpt_status track_apply_launch(float* U, int64_t v, int r, int k, const float* resid, const float* W,
+                              const float* wnorm2, const int32_t* info, float gamma, int32_t* lhead,
+                              const int32_t* lnext, hipStream_t s) {
+  if (r < 1 || r > kR) return RPT_ERR_UNSUPPORTED;
   RPT_STAGE("track_update", s);
-  hipLaunchKernelGGL(track_update_kernel, dim3(static_cast<unsigned>(B)), dim3(kBlock), 0, s, U, v, r, omega, k, resid,
-                     W, wnorm2, info, gamma);
+  const unsigned blocks = static_cast<unsigned>(ceil_div(v, kBlock / 32));
+  hipLaunchKernelGGL(track_apply_kernel, dim3(blocks), dim3(kBlock), 0, s, U, v, r, k, resid, W, wnorm2, info, gamma,
+                     lhead, lnext);
+  RPT_CHECK_LAUNCH();
+  return RPT_OK;
+}
+
+rpt_status fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s) {
+  if (n <= 0) return RPT_OK;
+  int64_t blocks = ceil_div(n, kBlock);
+  if (blocks > 2048) blocks = 2048;
+  hipLaunchKernelGGL(fill_i32_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, p, n, value);
   RPT_CHECK_LAUNCH();
   return RPT_OK;
 }

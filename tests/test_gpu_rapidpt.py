@@ -103,7 +103,7 @@ def test_complete_reports_late_pivot_failure():
     assert np.linalg.norm(W.cpu().numpy()[0] - wref) <= 1e-4 * np.linalg.norm(wref)
 
 
-@pytest.mark.parametrize("v,r", [(5000, 64), (250_000, 100), (1000, 128), (37, 5)])
+@pytest.mark.parametrize("v,r", [(5000, 64), (250_000, 100), (1000, 128), (37, 5), (3000, 17), (4000, 112)])
 def test_reorth_is_positive_qr(v, r):
     torch = torch_cuda()
     import paper_1703_01506_amd as rpt
