@@ -10,11 +10,11 @@ namespace rpt {
 
 __device__ __forceinline__ int ptri(int i, int c) { return (i * (i + 1)) / 2 + c; }
 
-// 1 / sqrt(x) for x > 0: hardware estimate and two Newton steps (relative
-// error near one ulp; the factorisations below need no correct rounding)
+// 1 / sqrt(x) for x > 0: the hardware estimate (relative error about 2^-23)
+// and one Newton step (about 2^-45); the factorisations below need no
+// correct rounding
 __device__ __forceinline__ double rsqrt_d(double x) {
   double y = __builtin_amdgcn_rsq(x);
-  y = y * fma(-0.5 * x * y, y, 1.5);
   y = y * fma(-0.5 * x * y, y, 1.5);
   return y;
 }
@@ -166,7 +166,8 @@ __device__ __forceinline__ int chol_panel(double* G, double* dinv, double* P, in
 #pragma unroll
     for (int j = 0; j < kCb; ++j) d[s][j] = gr[j];
   }
-  __shared__ double colb[kCb];
+  const bool two = NS > 1 && nrows - c0 > 64;  // second row slot in use
+  const bool three = NS > 2 && nrows - c0 > 128;
   int bad = 0;
 #pragma unroll
   for (int j = 0; j < kCb; ++j) {
@@ -178,21 +179,18 @@ __device__ __forceinline__ int chol_panel(double* G, double* dinv, double* P, in
       }
       const double inv = rsqrt_d(piv);
       d[0][j] = (lane == j) ? piv * inv : d[0][j] * inv;
-#pragma unroll
-      for (int s = 1; s < NS; ++s) d[s][j] *= inv;
+      if (two) d[1][j] *= inv;
+      if (three) d[2][j] *= inv;
       if (lane == 0) dinv[c0 + j] = inv;
-      // column j of the diagonal block is broadcast through LDS: a wave's LDS
-      // operations complete in issue order, so the fences only keep the
-      // compiler from reordering them
-      if (lane < kCb) colb[lane] = d[0][j];
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
+      // column j of the diagonal block is broadcast by readlane; entries
+      // above the diagonal are updated too (never read, never stored)
 #pragma unroll
       for (int q = j + 1; q < kCb; ++q) {
         if (q < mm) {
-          const double lq = colb[q];  // L[c0 + q][c0 + j]
-#pragma unroll
-          for (int s = 0; s < NS; ++s) d[s][q] = fma(-d[s][j], lq, d[s][q]);
+          const double lq = readlane_d(d[0][j], q);  // L[c0 + q][c0 + j]
+          d[0][q] = fma(-d[0][j], lq, d[0][q]);
+          if (two) d[1][q] = fma(-d[1][j], lq, d[1][q]);
+          if (three) d[2][q] = fma(-d[2][j], lq, d[2][q]);
         }
       }
       // finish this pivot's updates before the next pivot starts: deferring
@@ -201,8 +199,6 @@ __device__ __forceinline__ int chol_panel(double* G, double* dinv, double* P, in
       for (int q = j + 1; q < kCb; ++q)
 #pragma unroll
         for (int s = 0; s < NS; ++s) asm volatile("" : "+v"(d[s][q]));
-      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-      __builtin_amdgcn_wave_barrier();
     }
   }
   const int b0 = c0 + m;

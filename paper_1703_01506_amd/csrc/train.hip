@@ -171,36 +171,47 @@ __global__ __launch_bounds__(64 * kRedWaves) void gram_reduce_kernel(const float
 // Factor G = L L^T (FP64, LDS) and write R^{-1} = L^{-T} transposed
 // (RinvT[c][j] = Rinv[j][c] = Linv[c][j]) split into BF16 hi/lo.  A failed
 // factorisation writes the identity (U is left unchanged) and info = j + 1.
-__global__ __launch_bounds__(kBlock) void chol_rinv_kernel(const double* __restrict__ Gfull, int r,
-                                                          uint16_t* __restrict__ rinvT_hi,
-                                                          uint16_t* __restrict__ rinvT_lo, int32_t* info) {
+// One workgroup of 16 waves: the kernel runs alone, so every phase gets all
+// of a CU's waves.
+constexpr int kCholThreads = 1024;
+__global__ __launch_bounds__(kCholThreads) void chol_rinv_kernel(const double* __restrict__ Gfull, int r,
+                                                                uint16_t* __restrict__ rinvT_hi,
+                                                                uint16_t* __restrict__ rinvT_lo, int32_t* info) {
   extern __shared__ __align__(16) unsigned char sm[];
   const int ntri = r * (r + 1) / 2;
   double* G = reinterpret_cast<double*>(sm);
   double* diag = G + ntri;
   double* dinv = diag + kR;
-  float* Li = reinterpret_cast<float*>(dinv + kR);  // [r][kR]
+  float* Li = reinterpret_cast<float*>(dinv + kR);  // [rp][kR]
   double* P = reinterpret_cast<double*>(Li + ((r + kCb - 1) / kCb) * kCb * kR);  // [kCb][kPanelLd] scratch
   const int tid = threadIdx.x;
-  for (int idx = tid; idx < ntri; idx += kBlock) {
-    // invert ptri: row i with i(i+1)/2 <= idx
-    int i = static_cast<int>((sqrt(8.0 * idx + 1.0) - 1.0) * 0.5);
-    while ((i + 1) * (i + 2) / 2 <= idx) ++i;
-    while (i * (i + 1) / 2 > idx) --i;
-    const int c = idx - i * (i + 1) / 2;
-    G[idx] = Gfull[i * r + c];
-  }
+  // packed lower triangle from the full matrix: thread (i, c) for row i
+  for (int i = tid / 64; i < r; i += kCholThreads / 64)
+    for (int c = tid & 63; c <= i; c += 64) G[ptri(i, c)] = Gfull[i * r + c];
   __syncthreads();
   const int failed = lds_cholesky_blocked<2>(G, dinv, P, r, r);
   if (!failed) lds_tri_inverse_blocked(G, dinv, r, Li, kR, P);
   __syncthreads();
-  for (int idx = tid; idx < kR * kR; idx += kBlock) {
-    const int c = idx / kR, j = idx - c * kR;
-    float x = 0.0f;
-    if (c < r && j < r) x = failed ? (c == j ? 1.0f : 0.0f) : Li[c * kR + j];
-    const uint16_t hi = f2bf(x);
-    rinvT_hi[idx] = hi;
-    rinvT_lo[idx] = f2bf(x - bf2f(hi));
+  // eight consecutive entries per thread, written as 16-byte BF16 vectors
+  for (int idx = tid * 8; idx < kR * kR; idx += kCholThreads * 8) {
+    const int c = idx / kR, j0 = idx - c * kR;
+    u32x4 hv, lv;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      uint16_t h2[2], l2[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const int j = j0 + 2 * q + e;
+        float x = 0.0f;
+        if (c < r && j < r) x = failed ? (c == j ? 1.0f : 0.0f) : Li[c * kR + j];
+        h2[e] = f2bf(x);
+        l2[e] = f2bf(x - bf2f(h2[e]));
+      }
+      hv[q] = pack_bf2(h2[0], h2[1]);
+      lv[q] = pack_bf2(l2[0], l2[1]);
+    }
+    *reinterpret_cast<u32x4*>(rinvT_hi + idx) = hv;
+    *reinterpret_cast<u32x4*>(rinvT_lo + idx) = lv;
   }
   if (tid == 0 && info) *info = failed;
 }
@@ -448,7 +459,7 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(chol_smem(kR)));
     attr_set = true;
   }
-  hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(kBlock), chol_smem(r), s, gfull, r, rth, rtl, info);
+  hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(kCholThreads), chol_smem(r), s, gfull, r, rth, rtl, info);
   RPT_CHECK_LAUNCH();
   int64_t ab = ceil_div(ceil_div(v, 32), 4);
   if (ab > 512) ab = 512;  // two workgroups per CU; each wave then loops over tiles
