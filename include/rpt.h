@@ -238,6 +238,11 @@ rpt_status rpt_reorth(float* U, int64_t v, int32_t r, int32_t* info,
  *   loss    1 FP64 on the device (out)   resid  nnz FP32 = t - U W (out)
  *   dU      v x r FP32, fully overwritten (zero outside sampled rows) (out)
  *   dW      r x B FP32 (out)
+ *   grad_scale  device FP64 scalar multiplying both gradients (the upstream
+ *           gradient of an autograd chain), or NULL for 1.
+ * The backward takes the residuals the forward wrote.  Errors: null required
+ * pointers or negative sizes give RPT_ERR_INVALID_ARG; r > 1024 gives
+ * RPT_ERR_UNSUPPORTED.  Out-of-range voxel indices are treated as zero rows.
  * ------------------------------------------------------------------------- */
 rpt_status rpt_masked_loss_fwd(const float* U, int64_t v, int32_t r, const float* W, int32_t B,
                                const int64_t* omega_ptr, const int32_t* omega_idx,
@@ -246,7 +251,7 @@ rpt_status rpt_masked_loss_fwd(const float* U, int64_t v, int32_t r, const float
 rpt_status rpt_masked_loss_bwd(const float* U, int64_t v, int32_t r, const float* W, int32_t B,
                                const int64_t* omega_ptr, const int32_t* omega_idx,
                                const float* resid, int64_t nnz,
-                               float* dU, float* dW, void* stream);
+                               float* dU, float* dW, const double* grad_scale, void* stream);
 
 #ifdef __cplusplus
 }

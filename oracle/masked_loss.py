@@ -48,3 +48,22 @@ def grad(U, W, ptr, idx, t):
         dW[:, b] = -U[rows].T @ e[s]
         np.add.at(dU, rows, -np.outer(e[s], W[:, b]))
     return dU, dW
+
+
+def grad_rows(U, W, ptr, idx, t, rows):
+    """dU restricted to the given voxel rows, and the full dW, of ``loss``
+    (same sums as ``grad``, without forming the v x r gradient)."""
+    U = np.asarray(U, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    e = residuals(U, W, ptr, idx, t)
+    pos = {int(k): a for a, k in enumerate(rows)}
+    dUr = np.zeros((len(rows), U.shape[1]))
+    dW = np.zeros_like(W)
+    for b in range(len(ptr) - 1):
+        s = slice(ptr[b], ptr[b + 1])
+        dW[:, b] = -U[idx[s]].T @ e[s]
+        for q in range(ptr[b], ptr[b + 1]):
+            a = pos.get(int(idx[q]))
+            if a is not None:
+                dUr[a] -= e[q] * W[:, b]
+    return dUr, dW

@@ -17,10 +17,11 @@ from .api import (  # noqa: F401
     sampled_tstat,
     train_subspace,
 )
+from .autograd import MaskedSubspaceLoss, masked_subspace_loss  # noqa: F401
 
 _lib.load()
 
 __all__ = [
     "naive_maxnull", "sampled_tstat", "complete", "reorth", "train_subspace", "recover_maxnull",
-    "rapidpt_maxnull", "masked_loss_fwd", "masked_loss_bwd",
+    "rapidpt_maxnull", "masked_loss_fwd", "masked_loss_bwd", "MaskedSubspaceLoss", "masked_subspace_loss",
 ]

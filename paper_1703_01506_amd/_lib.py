@@ -39,7 +39,7 @@ SIGNATURES = {
     "rpt_reorth_workspace": (_sz, [_i64, _i32]),
     "rpt_reorth": (_int, [_p, _i64, _i32, _p, _p, _sz, _p]),
     "rpt_masked_loss_fwd": (_int, [_p, _i64, _i32, _p, _i32, _p, _p, _p, _i64, _p, _p, _p]),
-    "rpt_masked_loss_bwd": (_int, [_p, _i64, _i32, _p, _i32, _p, _p, _p, _i64, _p, _p, _p]),
+    "rpt_masked_loss_bwd": (_int, [_p, _i64, _i32, _p, _i32, _p, _p, _p, _i64, _p, _p, _p, _p]),
 }
 
 _lib = None

@@ -206,15 +206,17 @@ def masked_loss_fwd(U, W, omega_ptr, omega_idx, t_vals):
     return loss, resid
 
 
-def masked_loss_bwd(U, W, omega_ptr, omega_idx, resid):
-    """Gradient of the masked loss: (dU (v, r), dW (r, B))."""
+def masked_loss_bwd(U, W, omega_ptr, omega_idx, resid, grad_scale=None):
+    """Gradient of the masked loss: (dU (v, r), dW (r, B)), both multiplied
+    by ``grad_scale`` (a float64 device scalar) when given."""
     lib = _lib.load()
     v, r = U.shape
     B = W.shape[1]
     nnz = omega_idx.numel()
     dU = torch.empty_like(U)
     dW = torch.empty_like(W)
+    gs = None if grad_scale is None else _dev(grad_scale.reshape(1), torch.float64, "grad_scale", 1)
     rc = lib.rpt_masked_loss_bwd(_ptr(U), v, r, _ptr(W), B, _ptr(omega_ptr), _ptr(omega_idx), _ptr(resid), nnz,
-                                 _ptr(dU), _ptr(dW), _stream(U.device))
+                                 _ptr(dU), _ptr(dW), _ptr(gs), _stream(U.device))
     _lib.check(rc, "rpt_masked_loss_bwd")
     return dU, dW

@@ -298,10 +298,11 @@ rpt_status rpt_masked_loss_fwd(const float* U, int64_t v, int32_t r, const float
 
 rpt_status rpt_masked_loss_bwd(const float* U, int64_t v, int32_t r, const float* W, int32_t B,
                                const int64_t* omega_ptr, const int32_t* omega_idx, const float* resid, int64_t nnz,
-                               float* dU, float* dW, void* stream) {
+                               float* dU, float* dW, const double* grad_scale, void* stream) {
   if (v < 1 || r < 1 || B < 0 || nnz < 0 || !dU || (B > 0 && !dW)) return RPT_ERR_INVALID_ARG;
   if (B > 0 && (!U || !W || !omega_ptr || (nnz > 0 && (!omega_idx || !resid)))) return RPT_ERR_INVALID_ARG;
-  return loss_bwd_launch(U, v, r, W, B, omega_ptr, omega_idx, resid, dU, dW, static_cast<hipStream_t>(stream));
+  return loss_bwd_launch(U, v, r, W, B, omega_ptr, omega_idx, resid, dU, dW, grad_scale,
+                         static_cast<hipStream_t>(stream));
 }
 
 }  // extern "C"

@@ -55,11 +55,12 @@ __global__ __launch_bounds__(kBlock) void loss_bwd_kernel(const float* __restric
                                                          const int64_t* __restrict__ ptr,
                                                          const int32_t* __restrict__ idx,
                                                          const float* __restrict__ e, float* __restrict__ dU,
-                                                         float* __restrict__ dW) {
+                                                         float* __restrict__ dW, const double* grad_scale) {
   const int b = blockIdx.x;
   const int64_t q0 = ptr[b], q1 = ptr[b + 1];
+  const float gs = grad_scale ? static_cast<float>(*grad_scale) : 1.0f;
   for (int c = threadIdx.x; c < r; c += kBlock) {
-    const float wc = W[static_cast<int64_t>(c) * B + b];
+    const float wc = W[static_cast<int64_t>(c) * B + b] * gs;
     float g = 0.0f;
     for (int64_t q = q0; q < q1; ++q) {
       const int64_t vox = idx[q];
@@ -69,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void loss_bwd_kernel(const float* __restric
       g = fmaf(U[row + c], eq, g);
       atomicAdd(dU + row + c, -eq * wc);
     }
-    dW[static_cast<int64_t>(c) * B + b] = -g;
+    dW[static_cast<int64_t>(c) * B + b] = -g * gs;
   }
 }
 
@@ -88,7 +89,9 @@ rpt_status loss_fwd_launch(const float* U, int64_t v, int r, const float* W, int
 }
 
 rpt_status loss_bwd_launch(const float* U, int64_t v, int r, const float* W, int B, const int64_t* ptr,
-                           const int32_t* idx, const float* e, float* dU, float* dW, hipStream_t s) {
+                           const int32_t* idx, const float* e, float* dU, float* dW, const double* grad_scale,
+                           hipStream_t s) {
+  if (r > kRLoss) return RPT_ERR_UNSUPPORTED;
   const int64_t n = v * r;
   int64_t blocks = ceil_div(n, kBlock);
   if (blocks > 8192) blocks = 8192;
@@ -96,7 +99,7 @@ rpt_status loss_bwd_launch(const float* U, int64_t v, int r, const float* W, int
   RPT_CHECK_LAUNCH();
   if (B == 0) return RPT_OK;
   RPT_STAGE("masked_loss_bwd", s);
-  hipLaunchKernelGGL(loss_bwd_kernel, dim3(B), dim3(kBlock), 0, s, U, v, r, W, B, ptr, idx, e, dU, dW);
+  hipLaunchKernelGGL(loss_bwd_kernel, dim3(B), dim3(kBlock), 0, s, U, v, r, W, B, ptr, idx, e, dU, dW, grad_scale);
   RPT_CHECK_LAUNCH();
   return RPT_OK;
 }

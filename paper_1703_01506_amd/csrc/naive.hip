@@ -12,8 +12,14 @@
 // per accumulator register; one cross-lane reduction per workgroup finishes
 // it.
 //
-// Balanced designs (n1 = n/2): one contraction, epilogue u = a * rinv + c,
-// partial maxima of u, t = t(max u) in the finalize kernel (see prep.hip).
+// Balanced designs (n1 = n/2), split-BF16: the per-voxel constants are folded
+// into the prepared data (see prep.hip), so the contraction yields u itself;
+// partial maxima of u, t = t(max u) in the finalize kernel.  For the
+// max-only launch the operands are swapped: voxels are the MFMA rows and
+// relabellings the columns, so the 16 accumulator registers of a lane all
+// belong to one relabelling and reduce to one running maximum per tile
+// (four registers instead of 64), which fits two waves per SIMD.
+// FP32 path: epilogue u = a * rinv + c.
 // Unbalanced designs: a second contraction with the squared data gives the
 // group-1 sums of squares and the epilogue evaluates Eq. 2 per element.
 //
@@ -65,8 +71,10 @@ __global__ __launch_bounds__(kBlock) void naive_split_kernel(NaiveArgs a) {
   int64_t pbase;
   block_coords(a, PT, chunk, pbase);
 
-  // indicator fragments: lane supplies A[row = col][subject 16s + 8h + 0..7]
-  u32x4 A[PT][KS];
+  // indicator fragments: lane supplies I[relabelling pbase + 32p + col][subject
+  // 16s + 8h + 0..7] (the A operand layout of the T-storing orientation and
+  // the B operand layout of the max-only one are the same)
+  u32x4 I[PT][KS];
 #pragma unroll
   for (int p = 0; p < PT; ++p) {
     const int64_t perm = pbase + p * 32 + col;
@@ -82,73 +90,63 @@ __global__ __launch_bounds__(kBlock) void naive_split_kernel(NaiveArgs a) {
         const unsigned b1 = (valid && j0 + 1 < a.n && lab[j0 + 1]) ? 0x3F80u : 0u;
         w[q] = b0 | (b1 << 16);
       }
-      A[p][s] = u32x4{w[0], w[1], w[2], w[3]};
+      I[p][s] = u32x4{w[0], w[1], w[2], w[3]};
     }
   }
 
+  const int64_t t0 = static_cast<int64_t>(chunk) * a.tpc;
+  const int64_t t1 = t0 + a.tpc < a.vt ? t0 + a.tpc : a.vt;
+  const size_t kstride = static_cast<size_t>(a.vpad) * 32;  // uint16 per K step
+  // data fragments of voxel tile t: lane supplies x''[voxel 32t + col][subject
+  // 16s + 8h + 0..7]; the prepared layout stores them in lane order
+  auto load = [&](u32x4* X, int64_t t) {
+    const uint16_t* bp = a.kb16 + static_cast<size_t>(t) * 32 * 32 + lane * 8;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      X[2 * s] = *reinterpret_cast<const u32x4*>(bp + s * kstride);
+      X[2 * s + 1] = *reinterpret_cast<const u32x4*>(bp + s * kstride + 512);
+    }
+  };
   const float init = ABS ? 0.0f : -INFINITY;
+
+  // T-storing orientation: rows = relabellings, columns = voxels, so the
+  // stores of one accumulator register are 32 consecutive voxels
   float rm[PT][16];
 #pragma unroll
   for (int p = 0; p < PT; ++p)
 #pragma unroll
     for (int e = 0; e < 16; ++e) rm[p][e] = init;
-
-  const int64_t t0 = static_cast<int64_t>(chunk) * a.tpc;
-  const int64_t t1 = t0 + a.tpc < a.vt ? t0 + a.tpc : a.vt;
-  const size_t kstride = static_cast<size_t>(a.vpad) * 32;  // uint16 per K step
-
   u32x4 Bc[2 * KS], Bn[2 * KS];
-  float2 cc = make_float2(0.f, 0.f), cn = cc;
-  auto load = [&](u32x4* B, float2& c2, int64_t t) {
-    const int64_t vox = t * 32 + col;
-    const uint16_t* bp = a.kb16 + static_cast<size_t>(vox) * 32 + h * 8;
-#pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      B[2 * s] = *reinterpret_cast<const u32x4*>(bp + s * kstride);
-      B[2 * s + 1] = *reinterpret_cast<const u32x4*>(bp + s * kstride + 16);
-    }
-    c2 = a.cst[vox];
-  };
-  auto body = [&](const u32x4* B, float2 c2, int64_t t) {
+  auto body = [&](const u32x4* B, int64_t t) {
     f32x16 acc[PT];
 #pragma unroll
     for (int p = 0; p < PT; ++p) acc[p] = f32x16{};
 #pragma unroll
-    for (int s = 0; s < KS; ++s)
+    for (int s = 0; s < KS; ++s) {
 #pragma unroll
-      for (int p = 0; p < PT; ++p) {
-        acc[p] = mfma_bf16(A[p][s], B[2 * s], acc[p]);
-        acc[p] = mfma_bf16(A[p][s], B[2 * s + 1], acc[p]);
-      }
+      for (int p = 0; p < PT; ++p) acc[p] = mfma_bf16(I[p][s], B[2 * s], acc[p]);
+#pragma unroll
+      for (int p = 0; p < PT; ++p) acc[p] = mfma_bf16(I[p][s], B[2 * s + 1], acc[p]);
+    }
+    const int64_t vox = t * 32 + col;
 #pragma unroll
     for (int p = 0; p < PT; ++p)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const float u = fmaf(acc[p][e], c2.x, c2.y);
+        const float u = acc[p][e];
         rm[p][e] = fmaxf(rm[p][e], ABS ? fabsf(u) : u);
+        const int64_t perm = pbase + p * 32 + mfma_row(e, h);
+        if (perm < a.L && vox < a.v) a.T_out[perm * a.v + vox] = t_from_u_f(u, a.fs, a.tm);
       }
-    if (STORE) {
-      const int64_t vox = t * 32 + col;
-#pragma unroll
-      for (int p = 0; p < PT; ++p)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const int64_t perm = pbase + p * 32 + mfma_row(e, h);
-          if (perm < a.L && vox < a.v)
-            a.T_out[perm * a.v + vox] = t_from_u_f(fmaf(acc[p][e], c2.x, c2.y), a.fs, a.tm);
-        }
-    }
   };
-
-  if (t0 < t1) load(Bc, cc, t0);
+  if (t0 < t1) load(Bc, t0);
   for (int64_t t = t0; t < t1; t += 2) {
-    if (t + 1 < t1) load(Bn, cn, t + 1);
-    body(Bc, cc, t);
+    if (t + 1 < t1) load(Bn, t + 1);
+    body(Bc, t);
     if (t + 1 >= t1) break;
-    if (t + 2 < t1) load(Bc, cc, t + 2);
-    body(Bn, cn, t + 1);
+    if (t + 2 < t1) load(Bc, t + 2);
+    body(Bn, t + 1);
   }
-
 #pragma unroll
   for (int p = 0; p < PT; ++p)
 #pragma unroll
@@ -166,6 +164,104 @@ __global__ __launch_bounds__(kBlock) void naive_split_kernel(NaiveArgs a) {
         const int64_t perm = pbase + p * 32 + mfma_row(e, h);
         if (perm < a.L) a.partial[static_cast<int64_t>(chunk) * a.L + perm] = rm[p][e];
       }
+  }
+}
+
+// ----------------------------------------------------------------------------
+// split-BF16, balanced, maxima only.  Voxels are the MFMA rows and
+// relabellings the columns (a lane's 16 accumulator registers belong to one
+// relabelling).  Each voxel tile (KS steps x hi/lo x 1 KB) is copied once per
+// workgroup straight into LDS (global_load_lds, double-buffered, one barrier
+// per tile) and every wave reads its fragments from there: the four waves
+// share one copy instead of fetching it four times through the vector memory
+// path.
+template <int KS, int PT, bool ABS>
+__global__ __launch_bounds__(kBlock, 2) void naive_max_kernel(NaiveArgs a) {
+  __shared__ __align__(16) uint16_t xs[2][KS][2][64 * 8];
+  typedef __attribute__((address_space(3))) void lds_void;
+  typedef const __attribute__((address_space(1))) void gbl_void;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, col = lane & 31;
+  int chunk;
+  int64_t pbase;
+  block_coords(a, PT, chunk, pbase);
+
+  // indicator fragments (B operand): lane supplies I[relabelling pbase + 32p + col][subject 16s + 8h + 0..7]
+  u32x4 I[PT][KS];
+#pragma unroll
+  for (int p = 0; p < PT; ++p) {
+    const int64_t perm = pbase + p * 32 + col;
+    const bool valid = perm < a.L;
+    const uint8_t* lab = a.labels + (valid ? perm : 0) * a.n;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      unsigned w[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int j0 = 16 * s + 8 * h + 2 * q;
+        const unsigned b0 = (valid && j0 < a.n && lab[j0]) ? 0x3F80u : 0u;
+        const unsigned b1 = (valid && j0 + 1 < a.n && lab[j0 + 1]) ? 0x3F80u : 0u;
+        w[q] = b0 | (b1 << 16);
+      }
+      I[p][s] = u32x4{w[0], w[1], w[2], w[3]};
+    }
+  }
+
+  const int64_t t0 = static_cast<int64_t>(chunk) * a.tpc;
+  const int64_t t1 = t0 + a.tpc < a.vt ? t0 + a.tpc : a.vt;
+  const size_t kstride = static_cast<size_t>(a.vpad) * 32;  // uint16 per K step
+  // copy of tile t into buffer b: wave w moves the 1 KB blocks j = w, w + 4, ...
+  auto issue = [&](int b, int64_t t) {
+#pragma unroll
+    for (int j = 0; j < 2 * KS; j += 4) {
+      const int jj = j + wave;
+      if (jj < 2 * KS) {
+        const int s = jj >> 1, hl = jj & 1;
+        const uint16_t* g = a.kb16 + s * kstride + static_cast<size_t>(t) * 32 * 32 + hl * 512 + lane * 8;
+        __builtin_amdgcn_global_load_lds((gbl_void*)g, (lds_void*)&xs[b][s][hl][0], 16, 0, 0);
+      }
+    }
+  };
+
+  const float init = ABS ? 0.0f : -INFINITY;
+  float rm[PT];
+#pragma unroll
+  for (int p = 0; p < PT; ++p) rm[p] = init;
+  if (t0 < t1) issue(0, t0);
+  for (int64_t t = t0; t < t1; ++t) {
+    const int b = static_cast<int>((t - t0) & 1);
+    // this wave's copies of tile t have landed; after the barrier every
+    // wave's have, and every wave is done reading tile t - 1's buffer
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
+    if (t + 1 < t1) issue(b ^ 1, t + 1);
+    f32x16 acc[PT];
+#pragma unroll
+    for (int p = 0; p < PT; ++p) acc[p] = f32x16{};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      const u32x4 xh = *reinterpret_cast<const u32x4*>(&xs[b][s][0][lane * 8]);
+      const u32x4 xl = *reinterpret_cast<const u32x4*>(&xs[b][s][1][lane * 8]);
+#pragma unroll
+      for (int p = 0; p < PT; ++p) acc[p] = mfma_bf16(xh, I[p][s], acc[p]);
+#pragma unroll
+      for (int p = 0; p < PT; ++p) acc[p] = mfma_bf16(xl, I[p][s], acc[p]);
+    }
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      float m = ABS ? fabsf(acc[p][0]) : acc[p][0];
+#pragma unroll
+      for (int e = 1; e < 16; ++e) m = fmaxf(m, ABS ? fabsf(acc[p][e]) : acc[p][e]);
+      rm[p] = fmaxf(rm[p], m);
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PT; ++p) rm[p] = fmaxf(rm[p], __shfl_xor(rm[p], 32, 64));
+  if (h == 0) {
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+      const int64_t perm = pbase + p * 32 + col;
+      if (perm < a.L) a.partial[static_cast<int64_t>(chunk) * a.L + perm] = rm[p];
+    }
   }
 }
 
@@ -296,12 +392,14 @@ __global__ void naive_finalize_kernel(const float* __restrict__ partial, int nc,
   max_out[i] = apply_t ? static_cast<float>(t_from_u(static_cast<double>(u), m)) : u;
 }
 
+// T-storing launches use naive_split_kernel (PT = 2), max-only launches
+// naive_max_kernel (PT = 4)
 template <int PT, int KS>
 void* split_ptr(int abs_tail, int store) {
-  if (store) return abs_tail ? reinterpret_cast<void*>(&naive_split_kernel<KS, PT, true, true>)
-                             : reinterpret_cast<void*>(&naive_split_kernel<KS, PT, false, true>);
-  return abs_tail ? reinterpret_cast<void*>(&naive_split_kernel<KS, PT, true, false>)
-                  : reinterpret_cast<void*>(&naive_split_kernel<KS, PT, false, false>);
+  if (store) return abs_tail ? reinterpret_cast<void*>(&naive_split_kernel<KS, 2, true, true>)
+                             : reinterpret_cast<void*>(&naive_split_kernel<KS, 2, false, true>);
+  return abs_tail ? reinterpret_cast<void*>(&naive_max_kernel<KS, 4, true>)
+                  : reinterpret_cast<void*>(&naive_max_kernel<KS, 4, false>);
 }
 template <int PT, int KSB, bool U>
 void* f32_ptr() { return reinterpret_cast<void*>(&naive_f32_kernel<KSB, PT, U>); }
@@ -336,8 +434,8 @@ void* pick_f32(int ks) {
 NaivePlan naive_plan(int64_t v, int64_t L, int n, int prec, bool store) {
   NaivePlan pl;
   (void)n;
-  // split max-only path: 4 relabelling tiles per wave fit the register file
-  // without spills; the T-writing path and the FP32 path use 2.
+  // split max-only path: 4 relabelling tiles per wave (data shared through
+  // LDS, two waves per SIMD); the T-writing path and the FP32 path use 2.
   pl.pt = (prec == RPT_SPLIT_BF16 && !store) ? 4 : 2;
   pl.vt = round_up(v, 32) / 32;
   const int64_t group = 4 * pl.pt * 32;
@@ -389,7 +487,7 @@ rpt_status naive_launch(const PrepX& p, const NaivePlan& pl, const uint8_t* labe
   const bool unbal = 2 * p.n1 != p.n;
   void* fn = nullptr;
   if (prec == RPT_SPLIT_BF16) {
-    fn = pl.pt == 4 ? pick_split<4>(p.ksteps, a.abs_tail, a.store) : pick_split<2>(p.ksteps, a.abs_tail, a.store);
+    fn = pick_split<0>(p.ksteps, a.abs_tail, a.store);
   } else {
     fn = unbal ? pick_f32<2, true>(p.ksteps) : pick_f32<2, false>(p.ksteps);
   }

@@ -16,9 +16,17 @@
 // column maximum of t is t(max u).  The constants are computed from the values
 // the contraction actually multiplies (hi + lo for the split path), in FP64.
 //
+// Split path: every relabelling has exactly n1 group-1 subjects, so the
+// constants fold into the data, x''_kj = x_kj rinv_k + c_k / n1, and the
+// contraction of x'' is u itself (no per-voxel epilogue constants).
+//
 // Layouts written (vpad = v rounded up to 32; padding voxels are zero and get
-// epilogue constants that can never win a maximum):
-//   kb16  [ks][vpad][2][16] bf16  hi(x_{16s+e}) then lo(x_{16s+e}), 0 past n
+// epilogue constants that can never win a maximum; in the folded split
+// layout a padding voxel's entries are -1e30 / n1, so its u is -1e30):
+//   kb16  [ks][vpad / 32][2][64][8] bf16: per K step and 32-voxel tile, the
+//         hi block then the lo block, each in MFMA fragment order: lane
+//         L = 32 h + c holds x''[voxel 32 t + c][subject 16 s + 8 h + 0..7]
+//         (0 past n), so a wave's fragment is one contiguous 1 KB
 //   kb32  [ks][vpad][2][4] f32 subject 8s+2q+h at [s][k][h][q]
 //   rows  [vpad][ldn] f32      standardised rows, for the sampled statistics
 //   cst   [vpad] (rinv, -S/2 * rinv)       cstg [vpad] (S, Q)
@@ -37,6 +45,7 @@ constexpr int kPrepNMax = 128;    // subjects held in LDS
 __global__ __launch_bounds__(kBlock) void prep_kernel(const float* __restrict__ X, int64_t v, int n, int64_t ldx,
                                                      PrepX p, int tail, int flags) {
   __shared__ float xs[kPrepTile][kPrepNMax + 1];
+  __shared__ double fold_c[kPrepTile], fold_d[kPrepTile];  // x'' = x * fold_c + fold_d
   const int tid = threadIdx.x;
   const int64_t v0 = static_cast<int64_t>(blockIdx.x) * kPrepTile;
   const bool split = (flags & kPrepSplit) != 0;
@@ -96,15 +105,17 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(const float* __restrict__ 
   Q += __shfl_xor(Q, 2, 64);
   if (q == 0 && vox < p.vpad) {
     if (vox < v) {
-      if (p.cst) {
-        const double rinv = Qc > 0.0 ? 1.0 / sqrt(Qc) : 0.0;
-        p.cst[vox] = make_float2(static_cast<float>(rinv), static_cast<float>(-0.5 * S * rinv));
-      }
+      const double rinv = Qc > 0.0 ? 1.0 / sqrt(Qc) : 0.0;
+      if (p.cst) p.cst[vox] = make_float2(static_cast<float>(rinv), static_cast<float>(-0.5 * S * rinv));
       if (p.cstg) p.cstg[vox] = make_float2(static_cast<float>(S), static_cast<float>(Q));
+      fold_c[r] = rinv;
+      fold_d[r] = -0.5 * S * rinv / p.n1;
     } else {
       // padding voxels never win a maximum
       if (p.cst) p.cst[vox] = make_float2(0.0f, tail == RPT_TAIL_ABS ? 0.0f : -INFINITY);
       if (p.cstg) p.cstg[vox] = make_float2(0.0f, 0.0f);
+      fold_c[r] = 0.0;
+      fold_d[r] = tail == RPT_TAIL_ABS ? 0.0 : -1e30 / p.n1;
     }
   }
   __syncthreads();
@@ -124,7 +135,7 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(const float* __restrict__ 
             const int j = 16 * s + 8 * (c & 1) + 2 * e2 + hl;
             uint16_t val = 0;
             if (j < n) {
-              const float f = xs[rr][j];
+              const float f = static_cast<float>(static_cast<double>(xs[rr][j]) * fold_c[rr] + fold_d[rr]);
               const uint16_t hi = f2bf(f);
               val = (c < 2) ? hi : f2bf(f - bf2f(hi));
             }
@@ -132,7 +143,9 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(const float* __restrict__ 
           }
           w[e2] = pr;
         }
-        u32x4* d = reinterpret_cast<u32x4*>(p.kb16 + (static_cast<size_t>(s) * p.vpad + v0 + rr) * 32 + 8 * c);
+        const int64_t vx = v0 + rr;  // tile vx / 32, column vx % 32; c = 2 hl + h
+        u32x4* d = reinterpret_cast<u32x4*>(p.kb16 + (static_cast<size_t>(s) * p.vpad + (vx & ~int64_t(31))) * 32 +
+                                            (c >> 1) * 512 + ((c & 1) * 32 + (vx & 31)) * 8);
         *d = u32x4{w[0], w[1], w[2], w[3]};
       }
     }

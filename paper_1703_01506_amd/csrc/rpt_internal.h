@@ -218,6 +218,6 @@ rpt_status literal_resid_launch(const float* T, const float* U, const float* W, 
 rpt_status loss_fwd_launch(const float* U, int64_t v, int r, const float* W, int B, const int64_t* ptr, const int32_t* idx,
                            const float* t, double* loss, float* resid, hipStream_t s);
 rpt_status loss_bwd_launch(const float* U, int64_t v, int r, const float* W, int B, const int64_t* ptr,
-                           const int32_t* idx, const float* e, float* dU, float* dW, hipStream_t s);
+                           const int32_t* idx, const float* e, float* dU, float* dW, const double* grad_scale, hipStream_t s);
 
 }  // namespace rpt

@@ -46,3 +46,13 @@ def test_dense_mask_formulation():
     dU, dW = ML.grad(U, W, ptr, idx, t)
     np.testing.assert_allclose(dU, -E @ W.T, atol=1e-12)
     np.testing.assert_allclose(dW, -U.T @ E, atol=1e-12)
+
+
+def test_grad_rows_matches_full_gradient():
+    """The row-restricted gradient is the same sums as the full one."""
+    U, W, ptr, idx, t = _problem(2, v=60, r=4, B=9)
+    dU, dW = ML.grad(U, W, ptr, idx, t)
+    rows = np.array([0, 3, int(idx[5]), int(idx[-1]), 59])
+    dUr, dW2 = ML.grad_rows(U, W, ptr, idx, t, rows)
+    np.testing.assert_allclose(dUr, dU[rows], atol=1e-12)
+    np.testing.assert_allclose(dW2, dW, atol=1e-12)
