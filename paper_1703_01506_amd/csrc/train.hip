@@ -34,68 +34,52 @@ constexpr int kLd = 72;          // bf16 per staged column (64 + pad)
 // tile t = (bi, bj), bj <= bi, element 64 e + lane (row 16 bi +
 // 4 (lane / 16) + e, column 16 bj + lane % 16).
 constexpr int kGramChunk = 64;
-constexpr int kGramLd = kGramChunk + 8;  // bf16 per staged column
+constexpr int kGramLd = kGramChunk + 8;  // bf16 per staged column (16-byte aligned fragments)
 template <int RB>
 __global__ __launch_bounds__(kBlock, 2) void gram_partial_kernel(const float* __restrict__ U, int64_t v, int r,
                                                                 int64_t rows_per_blk, float* __restrict__ part) {
   constexpr int NTILE = RB * (RB + 1) / 2;
   constexpr int TPW = (NTILE + 3) / 4;                    // tiles per wave
-  constexpr int NV = (kGramChunk * 16 * RB / 4 + kBlock - 1) / kBlock;  // float4 per thread per chunk
+  constexpr int NV = RB;  // column groups of 4 per thread per chunk (4 RB groups over 4 waves)
   __shared__ __align__(16) uint16_t uth[16 * RB * kGramLd];
   __shared__ __align__(16) uint16_t utl[16 * RB * kGramLd];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, c16 = lane & 15, kq = lane >> 4;
   const int64_t r0 = blockIdx.x * rows_per_blk;
   const int64_t r1 = r0 + rows_per_blk < v ? r0 + rows_per_blk : v;
   const bool vec = (r & 3) == 0 && (reinterpret_cast<uintptr_t>(U) & 15) == 0;
-  const int q4 = r >> 2;  // float4 per row (vector path)
   f32x4 acc[TPW];
 #pragma unroll
   for (int t = 0; t < TPW; ++t) acc[t] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // lane = row of the chunk; wave w takes column groups 4 (w + 4 u) .. + 3, so
+  // the transpose stores of a wave are 64 consecutive rows of one column
   f32x4 buf[NV];
   auto load = [&](int64_t c0) {
-    const int64_t nrow = r1 - c0 < kGramChunk ? r1 - c0 : kGramChunk;
+    const int64_t row = c0 + lane;
 #pragma unroll
     for (int u = 0; u < NV; ++u) {
-      const int t = tid + u * kBlock;
+      const int cb = 4 * (wave + 4 * u);
       if (vec) {
-        const int row = t / q4, c4 = t - row * q4;
-        buf[u] = (row < nrow) ? *reinterpret_cast<const f32x4*>(U + (c0 + row) * r + 4 * c4)
-                              : f32x4{0.f, 0.f, 0.f, 0.f};
+        buf[u] = (row < r1 && cb < r) ? *reinterpret_cast<const f32x4*>(U + row * r + cb) : f32x4{0.f, 0.f, 0.f, 0.f};
       } else {
 #pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int64_t el = static_cast<int64_t>(t) * 4 + e;  // element of the chunk, row-major
-          buf[u][e] = (el < nrow * r) ? U[c0 * r + el] : 0.0f;
-        }
+        for (int e = 0; e < 4; ++e) buf[u][e] = (row < r1 && cb + e < r) ? U[row * r + cb + e] : 0.0f;
       }
     }
   };
-  // columns of the staged chunk that no thread writes stay zero
-  for (int t = tid; t < 16 * RB * kGramLd; t += kBlock) {
-    uth[t] = 0;
-    utl[t] = 0;
-  }
   if (r0 < r1) load(r0);
   for (int64_t c0 = r0; c0 < r1; c0 += kGramChunk) {
     __syncthreads();  // previous chunk's MFMA reads of the stage are done
 #pragma unroll
     for (int u = 0; u < NV; ++u) {
-      const int t = tid + u * kBlock;
+      const int cb = 4 * (wave + 4 * u);
 #pragma unroll
       for (int e = 0; e < 4; ++e) {
-        int row, col;
-        if (vec) {
-          row = t / q4;
-          col = 4 * (t - row * q4) + e;
-        } else {
-          row = (4 * t + e) / r;
-          col = 4 * t + e - row * r;
-        }
-        if (row < kGramChunk && col < 16 * RB) {
+        const int col = cb + e;
+        if (col < 16 * RB) {
           const float xv = buf[u][e];
           const uint16_t hv = f2bf(xv);
-          uth[col * kGramLd + row] = hv;
-          utl[col * kGramLd + row] = f2bf(xv - bf2f(hv));
+          uth[col * kGramLd + lane] = hv;
+          utl[col * kGramLd + lane] = f2bf(xv - bf2f(hv));
         }
       }
     }
@@ -294,10 +278,12 @@ __global__ __launch_bounds__(kBlock, 2) void apply_rinv_kernel(float* __restrict
 }
 
 // ---------------------------------------------------------------- tracking update
-// Half a wave per voxel: walk the voxel's list of sampled entries (linked by
-// the Complete kernel), sum gamma e / |w_i|^2 * w_i over it, add the sum to
-// the voxel's basis row, and reset the list head.  Lane l covers columns
-// l, l + 32, l + 64, l + 96, so every row access is a 128-byte segment.
+// A quarter wave per voxel: walk the voxel's list of sampled entries (linked
+// by the Complete kernel), sum gamma e / |w_i|^2 * w_i over it, add the sum
+// to the voxel's basis row, and reset the list head.  Lane l of the quarter
+// covers columns l + 16 j, so row accesses are 64-byte segments; four voxels
+// per wave keep four dependent list walks in flight.
+constexpr int kTrackLanes = 16;
 __global__ __launch_bounds__(kBlock) void track_apply_kernel(float* __restrict__ U, int64_t v, int r, int k,
                                                             const float* __restrict__ resid,
                                                             const float* __restrict__ W,
@@ -305,31 +291,34 @@ __global__ __launch_bounds__(kBlock) void track_apply_kernel(float* __restrict__
                                                             const int32_t* __restrict__ info, float gamma,
                                                             int32_t* __restrict__ lhead,
                                                             const int32_t* __restrict__ lnext) {
-  const int64_t vox = static_cast<int64_t>(blockIdx.x) * (kBlock / 32) + (threadIdx.x >> 5);
-  const int l = threadIdx.x & 31;
+  constexpr int NJ = (128 + kTrackLanes - 1) / kTrackLanes;
+  const int64_t vox = static_cast<int64_t>(blockIdx.x) * (kBlock / kTrackLanes) + (threadIdx.x / kTrackLanes);
+  const int l = threadIdx.x % kTrackLanes;
   if (vox >= v) return;
   int e = lhead[vox];
   if (e < 0) return;
-  float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  float acc[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) acc[j] = 0.0f;
   while (e >= 0) {
     const int i = e / k;
     const float n2 = wnorm2[i];
     const float coef = (info[i] == 0 && n2 > 0.0f) ? gamma * resid[e] / n2 : 0.0f;
     const float* wi = W + static_cast<int64_t>(i) * r;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int c = l + 32 * j;
+    for (int j = 0; j < NJ; ++j) {
+      const int c = l + kTrackLanes * j;
       if (c < r) acc[j] = fmaf(coef, wi[c], acc[j]);
     }
     e = lnext[e];
   }
   float* u = U + vox * r;
 #pragma unroll
-  for (int j = 0; j < 4; ++j) {
-    const int c = l + 32 * j;
+  for (int j = 0; j < NJ; ++j) {
+    const int c = l + kTrackLanes * j;
     if (c < r) u[c] += acc[j];
   }
-  if (l == 0) lhead[vox] = -1;  // every lane of this half wave read the head above
+  if (l == 0) lhead[vox] = -1;  // every lane of this quarter wave read the head above
 }
 
 __global__ __launch_bounds__(kBlock) void fill_i32_kernel(int32_t* p, int64_t n, int32_t value) {
@@ -484,7 +473,7 @@ rpt_status track_apply_launch(float* U, int64_t v, int r, int k, const float* re
                               const int32_t* lnext, hipStream_t s) {
   if (r < 1 || r > kR) return RPT_ERR_UNSUPPORTED;
   RPT_STAGE("track_update", s);
-  const unsigned blocks = static_cast<unsigned>(ceil_div(v, kBlock / 32));
+  const unsigned blocks = static_cast<unsigned>(ceil_div(v, kBlock / kTrackLanes));
   hipLaunchKernelGGL(track_apply_kernel, dim3(blocks), dim3(kBlock), 0, s, U, v, r, k, resid, W, wnorm2, info, gamma,
                      lhead, lnext);
   RPT_CHECK_LAUNCH();
