@@ -220,6 +220,54 @@ rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
                                void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
+ * Recovery phase of Alg. 2 for several studies in one call, with uneven
+ * sampled sets (Alg. 2 RECOVERY; the per-study sampled-set sizes follow from
+ * eta and each study's v).  Per study the same steps as rpt_recover_maxnull:
+ * sampled t, Complete, U w + noise, Max + mu.  The noise counter of study s
+ * carries its `study` field in the fourth word, so the studies draw
+ * independent noise from one seed.
+ *
+ *   studies   HOST array of n_studies descriptors (read during the call
+ *             only); every pointer inside is DEVICE memory owned by the caller:
+ *     X, v, n, ldx, n1, labels, L_rec, col0, U, r, sigma_mu, seed: as in
+ *             rpt_recover_maxnull
+ *     omega_ptr  int64 [L_rec + 1], omega_ptr[0] = 0: CSR offsets of the
+ *             sampled sets; row i holds omega_ptr[i + 1] - omega_ptr[i]
+ *             distinct voxel indices (at least r of them for a solvable fit)
+ *     omega_idx  int32 [nnz] voxel indices; nnz = omega_ptr[L_rec] must be
+ *             passed as the host value `nnz`
+ *     max_out  [L_rec] FP32 recovered maxima + mu;  info  [L_rec] int32, 0 or
+ *             the failing pivot + 1 (a row with fewer than r entries fails)
+ * Launches are only stream-ordered kernels on `stream` (no host
+ * synchronisation, allocation or host reads of device memory), so the call
+ * can be captured into a HIP graph; studies share the workspace in turn.
+ * Errors: as rpt_recover_maxnull, checked for every study before any launch.
+ * ------------------------------------------------------------------------- */
+typedef struct rpt_study {
+  const float* X;
+  int64_t v;
+  int32_t n;
+  int32_t n1;
+  int64_t ldx;
+  const uint8_t* labels;
+  int64_t L_rec;
+  int64_t col0;
+  const float* U;
+  int32_t r;
+  uint32_t study;
+  const float* sigma_mu;
+  const int64_t* omega_ptr;
+  const int32_t* omega_idx;
+  int64_t nnz;
+  uint64_t seed;
+  float* max_out;
+  int32_t* info;
+} rpt_study;
+size_t rpt_recover_batched_workspace(const rpt_study* studies, int32_t n_studies);
+rpt_status rpt_recover_maxnull_batched(const rpt_study* studies, int32_t n_studies,
+                                       void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
  * Orthonormalisation used by training: U <- U R^{-1}, with R^T R = U^T U
  * (Cholesky-QR, Gram and Cholesky in FP64, applied twice).  In place.
  *   U  v x r FP32 (in/out).  Requirements: 1 <= r <= 128, v >= r.

@@ -142,20 +142,21 @@ def sigma_mu(T_ex: np.ndarray, U: np.ndarray, omega_sm: np.ndarray, seed: int,
     return sigma, mu, train_max
 
 
-def recover_column(X, g1, U, sigma, mu, idx, seed, col, stat="t"):
+def recover_column(X, g1, U, sigma, mu, idx, seed, col, stat="t", study=0):
     """One recovered maximum: the statistic on the sampled voxels, Complete,
-    U w + s, Max + mu."""
+    U w + s, Max + mu.  ``study`` is the study field of the noise counter."""
     y = STATS[stat](np.asarray(X, dtype=np.float64)[idx], g1)
     w = complete(U, idx, y)
     a = U @ w
-    s = sigma * philox.normals(seed, philox.STREAM_RECOVERY, col, np.arange(U.shape[0]))
+    s = sigma * philox.normals(seed, philox.STREAM_RECOVERY, col, np.arange(U.shape[0]), study)
     return float(np.max(a + s) + mu), w
 
 
-def recover(X, labels, U, sigma, mu, omegas, seed, col0: int = 0, stat: str = "t") -> np.ndarray:
+def recover(X, labels, U, sigma, mu, omegas, seed, col0: int = 0, stat: str = "t", study: int = 0) -> np.ndarray:
     """Recovery phase of Alg. 2 for relabellings labels (L_rec x n) with sampled
-    sets omegas (L_rec x k); column j has global index col0 + j."""
-    return np.array([recover_column(X, labels[j] == 1, U, sigma, mu, omegas[j], seed, col0 + j, stat)[0]
+    sets omegas (one index array per column, sizes may differ); column j has
+    global index col0 + j."""
+    return np.array([recover_column(X, labels[j] == 1, U, sigma, mu, omegas[j], seed, col0 + j, stat, study)[0]
                      for j in range(labels.shape[0])])
 
 

@@ -13,6 +13,9 @@ from .api import (  # noqa: F401
     naive_maxnull,
     rapidpt_maxnull,
     recover_maxnull,
+    recover_maxnull_batched,
+    recover_studies_launch,
+    recover_studies_prepare,
     reorth,
     sampled_tstat,
     train_subspace,
@@ -23,5 +26,6 @@ _lib.load()
 
 __all__ = [
     "naive_maxnull", "sampled_tstat", "complete", "reorth", "train_subspace", "recover_maxnull",
-    "rapidpt_maxnull", "masked_loss_fwd", "masked_loss_bwd", "MaskedSubspaceLoss", "masked_subspace_loss",
+    "rapidpt_maxnull", "recover_maxnull_batched", "recover_studies_prepare", "recover_studies_launch",
+    "masked_loss_fwd", "masked_loss_bwd", "MaskedSubspaceLoss", "masked_subspace_loss",
 ]

@@ -15,6 +15,17 @@ _f32 = C.c_float
 _sz = C.c_size_t
 _int = C.c_int
 
+
+
+class RptStudy(C.Structure):
+    """Mirror of struct rpt_study (include/rpt.h), natural alignment."""
+    _fields_ = [
+        ("X", _p), ("v", _i64), ("n", _i32), ("n1", _i32), ("ldx", _i64), ("labels", _p), ("L_rec", _i64),
+        ("col0", _i64), ("U", _p), ("r", _i32), ("study", C.c_uint32), ("sigma_mu", _p), ("omega_ptr", _p),
+        ("omega_idx", _p), ("nnz", _i64), ("seed", _u64), ("max_out", _p), ("info", _p),
+    ]
+
+
 # name -> (restype, argtypes); mirrors include/rpt.h
 SIGNATURES = {
     "rpt_status_string": (C.c_char_p, [_int]),
@@ -36,6 +47,8 @@ SIGNATURES = {
     "rpt_recover_workspace": (_sz, [_i64, _i32, _i64, _i32, _i32]),
     "rpt_recover_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _i64, _p, _i32, _p, _p, _i32, _u64,
                                    _p, _p, _p, _p, _sz, _p]),
+    "rpt_recover_batched_workspace": (_sz, [C.POINTER(RptStudy), _i32]),
+    "rpt_recover_maxnull_batched": (_int, [C.POINTER(RptStudy), _i32, _p, _sz, _p]),
     "rpt_reorth_workspace": (_sz, [_i64, _i32]),
     "rpt_reorth": (_int, [_p, _i64, _i32, _p, _p, _sz, _p]),
     "rpt_masked_loss_fwd": (_int, [_p, _i64, _i32, _p, _i32, _p, _p, _p, _i64, _p, _p, _p]),

@@ -180,6 +180,58 @@ def recover_maxnull(X, labels, U, sigma_mu, omega, seed: int, col0: int = 0, n1:
     return (out, info, W) if return_W else (out, info)
 
 
+def recover_studies_prepare(studies):
+    """Marshal a list of study dicts (keys: X, labels, U, sigma_mu, omega_ptr
+    (int64 CSR offsets), omega_idx (int32), seed, col0, study, optional n1)
+    into the descriptor array of rpt_recover_maxnull_batched.  Returns
+    (descriptors, outputs [(max (L,), info (L,))], workspace)."""
+    import ctypes as C
+    lib = _lib.load()
+    arr = (_lib.RptStudy * max(len(studies), 1))()
+    outs = []
+    dev = None
+    for q, st in enumerate(studies):
+        X = st["X"]
+        v, n, ldx = _data(X)
+        dev = X.device
+        labels = _dev(st["labels"], torch.uint8, "labels", 2).contiguous()
+        U = _dev(st["U"], torch.float32, "U", 2).contiguous()
+        sm = _dev(st["sigma_mu"], torch.float32, "sigma_mu", 1).contiguous()
+        optr = _dev(st["omega_ptr"], torch.int64, "omega_ptr", 1).contiguous()
+        oidx = _dev(st["omega_idx"], torch.int32, "omega_idx", 1).contiguous()
+        L = labels.shape[0]
+        out = torch.empty(L, dtype=torch.float32, device=dev)
+        info = torch.empty(L, dtype=torch.int32, device=dev)
+        outs.append((out, info))
+        d = arr[q]
+        d.X, d.v, d.n, d.n1, d.ldx = _ptr(X), v, n, int(st.get("n1", n // 2)), ldx
+        d.labels, d.L_rec, d.col0 = _ptr(labels), L, int(st.get("col0", 0))
+        d.U, d.r, d.study, d.sigma_mu = _ptr(U), U.shape[1], int(st.get("study", q)), _ptr(sm)
+        d.omega_ptr, d.omega_idx, d.nnz = _ptr(optr), _ptr(oidx), oidx.numel()
+        d.seed, d.max_out, d.info = int(st["seed"]), _ptr(out), _ptr(info)
+        st["_keep"] = (labels, U, sm, optr, oidx)  # keep the marshalled tensors alive
+    need = lib.rpt_recover_batched_workspace(arr, len(studies))
+    if need == 0:
+        raise ValueError("invalid study descriptor")
+    ws = _workspace(need, dev)
+    return arr, outs, ws
+
+
+def recover_studies_launch(arr, n_studies: int, ws, device):
+    """Enqueue rpt_recover_maxnull_batched (no allocation: capturable)."""
+    lib = _lib.load()
+    rc = lib.rpt_recover_maxnull_batched(arr, n_studies, _ptr(ws), ws.numel(), _stream(device))
+    _lib.check(rc, "rpt_recover_maxnull_batched")
+
+
+def recover_maxnull_batched(studies):
+    """Recovery half of Alg. 2 for several studies with uneven sampled sets
+    (CSR).  Returns [(max (L,), info (L,))] per study."""
+    arr, outs, ws = recover_studies_prepare(studies)
+    recover_studies_launch(arr, len(studies), ws, ws.device)
+    return outs
+
+
 def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omega_rec, passes: int, seed: int,
                     batch: int | None = None, gamma: float = 1.0, mu_rule: str = "mean_gap",
                     prec: str = "split_bf16"):

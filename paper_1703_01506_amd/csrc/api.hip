@@ -286,6 +286,76 @@ rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
                       s);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// several studies, uneven sampled sets
+namespace rpt {
+namespace {
+size_t study_bytes(const rpt_study& st) {
+  Carver c(nullptr);
+  prep_carve(c, st.v, st.n, st.n1, kPrepRows);
+  c.take<float>(static_cast<size_t>(st.nnz > 0 ? st.nnz : 1));
+  c.take<float>(static_cast<size_t>(st.L_rec > 0 ? st.L_rec : 1) * st.r);
+  c.take<char>(recon_bytes(st.v, st.L_rec, st.r));
+  return c.off;
+}
+rpt_status study_check(const rpt_study& st) {
+  if (!design_ok(st.v, st.n, st.ldx, st.n1)) return RPT_ERR_INVALID_ARG;
+  if (2 * st.n1 != st.n) return RPT_ERR_UNSUPPORTED;
+  if (st.L_rec < 0 || st.col0 < 0 || st.r < 1 || st.r > 128 || st.r > st.v || st.nnz < 0 ||
+      st.nnz > INT32_MAX)
+    return RPT_ERR_INVALID_ARG;
+  if (st.L_rec > 0 && (!st.X || !st.labels || !st.U || !st.sigma_mu || !st.omega_ptr || !st.max_out || !st.info ||
+                       (st.nnz > 0 && !st.omega_idx)))
+    return RPT_ERR_INVALID_ARG;
+  return RPT_OK;
+}
+}  // namespace
+}  // namespace rpt
+
+extern "C" {
+
+size_t rpt_recover_batched_workspace(const rpt_study* studies, int32_t n_studies) {
+  if (!studies || n_studies < 0) return 0;
+  size_t mx = 256;
+  for (int32_t q = 0; q < n_studies; ++q) {
+    if (study_check(studies[q]) != RPT_OK) return 0;
+    const size_t b = study_bytes(studies[q]);
+    if (b > mx) mx = b;
+  }
+  return mx;
+}
+
+rpt_status rpt_recover_maxnull_batched(const rpt_study* studies, int32_t n_studies, void* ws, size_t ws_bytes,
+                                       void* stream) {
+  if (n_studies < 0 || (n_studies > 0 && !studies)) return RPT_ERR_INVALID_ARG;
+  size_t need = 256;
+  for (int32_t q = 0; q < n_studies; ++q) {
+    RPT_TRY(study_check(studies[q]));
+    const size_t b = study_bytes(studies[q]);
+    if (b > need) need = b;
+  }
+  if (!ws_ok(ws, ws_bytes, need)) return RPT_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  for (int32_t q = 0; q < n_studies; ++q) {
+    const rpt_study& st = studies[q];
+    if (st.L_rec == 0) continue;
+    Carver c(ws);
+    PrepX p = prep_carve(c, st.v, st.n, st.n1, kPrepRows);
+    float* y = c.take<float>(static_cast<size_t>(st.nnz > 0 ? st.nnz : 1));
+    float* W = c.take<float>(static_cast<size_t>(st.L_rec) * st.r);
+    void* rws = c.take<char>(recon_bytes(st.v, st.L_rec, st.r));
+    RPT_TRY(prep_launch(p, st.X, st.ldx, RPT_TAIL_SIGNED, kPrepRows, s));
+    RPT_TRY(sampled_launch(p, st.labels, st.L_rec, st.omega_idx, 0, nullptr, y, s, st.omega_ptr));
+    RPT_TRY(complete_run(st.U, st.v, st.r, st.omega_idx, 0, y, nullptr, 0, nullptr, st.L_rec, W, nullptr, st.info,
+                         nullptr, s, nullptr, nullptr, st.omega_ptr));
+    RPT_TRY(recon_launch(st.U, st.v, st.r, W, st.L_rec, st.col0, st.seed, RPT_STREAM_RECOVERY, st.sigma_mu,
+                         st.max_out, nullptr, nullptr, rws, s, st.study));
+  }
+  return RPT_OK;
+}
+
 // ---------------------------------------------------------------------------
 // masked loss
 rpt_status rpt_masked_loss_fwd(const float* U, int64_t v, int32_t r, const float* W, int32_t B,

@@ -45,12 +45,14 @@ struct CompleteArgs {
   float* wnorm2;        // [L] |w|^2 (or nullptr)
   int32_t* lhead;       // [v] per-voxel list heads (-1 = empty) or nullptr
   int32_t* lnext;       // [L][k] list links of the sampled entries
+  const int64_t* optr;  // CSR offsets of uneven sampled sets (nullptr: k per column)
 };
 
-__device__ __forceinline__ float y_at(const CompleteArgs& a, int64_t i, int q) {
-  if (a.y) return a.y[i * a.k + q];
+// sampled value q of column i, whose entries start at base (i k, or the CSR offset)
+__device__ __forceinline__ float y_at(const CompleteArgs& a, int64_t i, int64_t base, int q) {
+  if (a.y) return a.y[base + q];
   const int64_t row = a.trow ? a.trow[i] : i;
-  const int64_t vox = a.omega[i * a.k + q];
+  const int64_t vox = a.omega[base + q];
   return (vox >= 0 && vox < a.ldT) ? a.Trows[row * a.ldT + vox] : 0.0f;
 }
 
@@ -66,7 +68,7 @@ template <int RB>
 __global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(CompleteArgs a) {
   constexpr int NTILE = RB * (RB + 1) / 2;
   extern __shared__ __align__(16) unsigned char smem[];
-  const int r = a.r, k = a.k;
+  const int r = a.r;
   double* G = reinterpret_cast<double*>(smem);
   double* P = G + gsize(r);
   double* dinv = P + kCb * kPanelLd;
@@ -76,7 +78,9 @@ __global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(Comple
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, c16 = lane & 15, kq = lane >> 4;
   const int64_t i = blockIdx.x;
-  const int32_t* om = a.omega + i * k;
+  const int64_t base = a.optr ? a.optr[i] : i * a.k;
+  const int k = a.optr ? static_cast<int>(a.optr[i + 1] - base) : a.k;
+  const int32_t* om = a.omega + base;
   const int nrows = r + 1, ntri = nrows * (nrows + 1) / 2;
   for (int t = tid; t < ntri; t += kNT) G[t] = 0.0;
 
@@ -96,7 +100,7 @@ __global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(Comple
       const bool in = t < nb;
       const int64_t row = in ? om[b0 + t] : -1;
       ibuf[t] = (row >= 0 && row < a.v) ? static_cast<int>(row) : -1;  // out of range: zero row
-      ybuf[t] = in ? y_at(a, i, b0 + t) : 0.0f;
+      ybuf[t] = in ? y_at(a, i, base, b0 + t) : 0.0f;
     }
     __syncthreads();
     auto load = [&](int g) {
@@ -178,7 +182,7 @@ __global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(Comple
       if (a.wnorm2) a.wnorm2[i] = 0.0f;
     }
     if (a.resid)
-      for (int q = tid; q < k; q += kNT) a.resid[i * k + q] = y_at(a, i, q);
+      for (int q = tid; q < k; q += kNT) a.resid[base + q] = y_at(a, i, base, q);
     return;
   }
   for (int c = tid; c < r; c += kNT) wv[c] = G[ptri(r, c)];
@@ -200,7 +204,7 @@ __global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(Comple
     const bool vec = (r & 3) == 0 && (reinterpret_cast<uintptr_t>(a.U) & 15) == 0;
     for (int q = tid; q < k; q += kNT) {
       const int64_t row = om[q];
-      const float yq = y_at(a, i, q);
+      const float yq = y_at(a, i, base, q);
       double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
       if (row >= 0 && row < a.v) {
         const float* u = a.U + row * r;
@@ -216,9 +220,9 @@ __global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(Comple
           for (int c = 0; c < r; ++c) s0 = fma(static_cast<double>(u[c]), wv[c], s0);
         }
       }
-      a.resid[i * k + q] = static_cast<float>(yq - ((s0 + s1) + (s2 + s3)));
+      a.resid[base + q] = static_cast<float>(yq - ((s0 + s1) + (s2 + s3)));
       if (a.lhead && row >= 0 && row < a.v) {
-        const int32_t e = static_cast<int32_t>(i * k + q);
+        const int32_t e = static_cast<int32_t>(base + q);
         a.lnext[e] = atomicExch(a.lhead + row, e);
       }
     }
@@ -229,11 +233,12 @@ __global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(Comple
 
 rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, int k, const float* y,
                         const float* Trows, int64_t ldT, const int32_t* trow, int64_t L, float* W, float* resid,
-                        int32_t* info, float* wnorm2, hipStream_t s, int32_t* lhead, int32_t* lnext) {
+                        int32_t* info, float* wnorm2, hipStream_t s, int32_t* lhead, int32_t* lnext,
+                        const int64_t* optr) {
   if (L == 0) return RPT_OK;
   if (r < 1 || r > kRMax) return RPT_ERR_UNSUPPORTED;
-  if (lhead && (!resid || L * static_cast<int64_t>(k) > INT32_MAX)) return RPT_ERR_INVALID_ARG;
-  CompleteArgs a{U, v, r, omega, k, y, Trows, ldT, trow, L, W, resid, info, wnorm2, lhead, lnext};
+  if (lhead && (!resid || optr || L * static_cast<int64_t>(k) > INT32_MAX)) return RPT_ERR_INVALID_ARG;
+  CompleteArgs a{U, v, r, omega, k, y, Trows, ldT, trow, L, W, resid, info, wnorm2, lhead, lnext, optr};
   const int RB = (r + 15) / 16;
   void* fns[8] = {reinterpret_cast<void*>(&complete_kernel<1>), reinterpret_cast<void*>(&complete_kernel<2>),
                   reinterpret_cast<void*>(&complete_kernel<3>), reinterpret_cast<void*>(&complete_kernel<4>),

@@ -230,6 +230,7 @@ struct RefineArgs {
   float* out;         // [L] max + mu
   const float* tmax;  // optional: exact training maxima (mean-gap rule)
   float* gap;         // optional: [L] tmax - max(U w + s)
+  unsigned study;     // study id of the noise counter
 };
 
 __global__ __launch_bounds__(kBlock) void recon_refine_kernel(RefineArgs a) {
@@ -274,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void recon_refine_kernel(RefineArgs a) {
         const float* u = a.U + vox * a.r;
         float s = 0.0f;
         for (int c = 0; c < a.r; ++c) s = fmaf(u[c], w[c], s);
-        const float z = noise_z(a.seed, a.stream, static_cast<unsigned>(a.col0 + i), vox, 0u);
+        const float z = noise_z(a.seed, a.stream, static_cast<unsigned>(a.col0 + i), vox, a.study);
         best = fmaxf(best, fmaf(sigma, z, s));
       }
     }
@@ -304,6 +305,7 @@ struct FusedArgs {
   const float* sigma_mu;
   const int* path;
   float* partial;  // [nc][L]
+  unsigned study;  // study id of the noise counter
 };
 
 __device__ __forceinline__ void box_muller4(const unsigned c[4], float z[4]) {
@@ -392,12 +394,12 @@ __global__ __launch_bounds__(kBlock) void recon_fused_kernel(FusedArgs a) {
         const int64_t g = a.col0 + pbase + p * 32 + 8 * m + 4 * h;  // column of register 4m
         float z[4];
         if (ALIGNED) {
-          unsigned c[4] = {static_cast<unsigned>(vox), static_cast<unsigned>(g >> 2), a.stream, 0u};
+          unsigned c[4] = {static_cast<unsigned>(vox), static_cast<unsigned>(g >> 2), a.stream, a.study};
           philox4x32_10(c, k0, k1);
           box_muller4(c, z);
         } else {
 #pragma unroll
-          for (int jj = 0; jj < 4; ++jj) z[jj] = noise_z(a.seed, a.stream, static_cast<unsigned>(g + jj), vox, 0u);
+          for (int jj = 0; jj < 4; ++jj) z[jj] = noise_z(a.seed, a.stream, static_cast<unsigned>(g + jj), vox, a.study);
         }
 #pragma unroll
         for (int jj = 0; jj < 4; ++jj) {
@@ -525,7 +527,7 @@ size_t recon_bytes(int64_t v, int64_t L, int r) {
 
 rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_t L, int64_t col0, uint64_t seed,
                         int stream_id, const float* sigma_mu, float* out_max, const float* Tmax_for_gap,
-                        float* gap_out, void* ws, hipStream_t s) {
+                        float* gap_out, void* ws, hipStream_t s, unsigned study) {
   if (L == 0) return RPT_OK;
   if (r < 1 || r > kRMaxRefine) return RPT_ERR_UNSUPPORTED;
   Carver c(ws);
@@ -548,7 +550,7 @@ rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_
 
   // fused path (runs when the device decided path 0)
   FusedArgs ua{ukb, W, r, v, pu.vpad, pu.vt, L, pu.tpc, pu.pg, pu.nc, col0, seed,
-               static_cast<unsigned>(stream_id), sigma_mu, path, partial};
+               static_cast<unsigned>(stream_id), sigma_mu, path, partial, study};
   void* ufn = (col0 % 4 == 0) ? pick_fused<kFusedPT, true>(pu.ks) : pick_fused<kFusedPT, false>(pu.ks);
   if (!ufn) return RPT_ERR_UNSUPPORTED;
   void* uargs[] = {&ua};
@@ -601,6 +603,7 @@ rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_
   ra.out = out_max;
   ra.tmax = Tmax_for_gap;
   ra.gap = gap_out;
+  ra.study = study;
   RPT_STAGE("recon_refine", s);
   hipLaunchKernelGGL(recon_refine_kernel, dim3(static_cast<unsigned>(ceil_div(L, 4))), dim3(kBlock), 0, s, ra);
   RPT_CHECK_LAUNCH();

@@ -183,20 +183,21 @@ rpt_status naive_launch(const PrepX& p, const NaivePlan& plan, const uint8_t* la
 
 // Sampled t statistics (K2).
 rpt_status sampled_launch(const PrepX& p, const uint8_t* labels, int64_t L, const int32_t* omega, int k,
-                          const float* Tsrc, float* y, hipStream_t s);
+                          const float* Tsrc, float* y, hipStream_t s,
+                          const int64_t* optr = nullptr);
 
 // Complete (Gram + FP64 Cholesky + solve).  The sampled values come either from
 // y ([L][k]) or, when y is null, from rows of T: y[i][q] = Trows[i * ldT + omega[i][q]].
 rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, int k, const float* y,
                         const float* Trows, int64_t ldT, const int32_t* trow, int64_t L, float* W, float* resid,
                         int32_t* info, float* wnorm2, hipStream_t s, int32_t* lhead = nullptr,
-                        int32_t* lnext = nullptr);
+                        int32_t* lnext = nullptr, const int64_t* optr = nullptr);
 
 // Reconstruction filter + exact refine with noise (K7).
 size_t recon_bytes(int64_t v, int64_t L, int r);
 rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_t L, int64_t col0,
                         uint64_t seed, int stream_id, const float* sigma_mu, float* out_max,
-                        const float* Tmax_for_gap, float* gap_out, void* ws, hipStream_t s);
+                        const float* Tmax_for_gap, float* gap_out, void* ws, hipStream_t s, unsigned study = 0);
 
 // Orthonormalisation (one Cholesky-QR pass).
 size_t reorth_bytes(int64_t v, int r);

@@ -1,5 +1,6 @@
 // K2 -- the test() step of RapidPT recovery (Alg. 2) on the sampled voxels:
-// y[i, q] = t statistic of voxel omega[i, q] under relabelling i.
+// y[i, q] = t statistic of voxel omega[i, q] under relabelling i (sampled
+// sets of k voxels per relabelling, or uneven sets in CSR form).
 //
 // One workgroup per relabelling: the group-1 indicator goes to LDS, each thread
 // takes sampled rows, reads the standardised row (prep.hip, 16-byte aligned)
@@ -22,6 +23,7 @@ struct SampledArgs {
   int n, n1;
   const int32_t* omega;
   int k;
+  const int64_t* optr;  // CSR offsets of uneven sampled sets (nullptr: k per row)
   float* y;
   float fs, tm;
 };
@@ -34,10 +36,12 @@ __global__ __launch_bounds__(kBlock) void sampled_kernel(SampledArgs a) {
   __syncthreads();
   const bool unbal = 2 * a.n1 != a.n;
   const int n1 = a.n1, n2 = a.n - a.n1;
-  for (int q = tid; q < a.k; q += kBlock) {
-    const int64_t vox = a.omega[i * a.k + q];
+  const int64_t base = a.optr ? a.optr[i] : i * a.k;
+  const int ki = a.optr ? static_cast<int>(a.optr[i + 1] - base) : a.k;
+  for (int q = tid; q < ki; q += kBlock) {
+    const int64_t vox = a.omega[base + q];
     if (vox < 0 || vox >= a.v) {  // out-of-range index: no statistic
-      a.y[i * a.k + q] = NAN;
+      a.y[base + q] = NAN;
       continue;
     }
     const f32x4* row = reinterpret_cast<const f32x4*>(a.rows + vox * a.ldn);
@@ -63,16 +67,16 @@ __global__ __launch_bounds__(kBlock) void sampled_kernel(SampledArgs a) {
       const float den2 = v1 / n1 + v2 / n2;
       t = den2 > 0.0f ? (m1 - m2) * rsqrtf(den2) : 0.0f;
     }
-    a.y[i * a.k + q] = t;
+    a.y[base + q] = t;
   }
 }
 
 }  // namespace
 
 rpt_status sampled_launch(const PrepX& p, const uint8_t* labels, int64_t L, const int32_t* omega, int k,
-                          const float* Tsrc, float* y, hipStream_t s) {
+                          const float* Tsrc, float* y, hipStream_t s, const int64_t* optr) {
   (void)Tsrc;
-  if (L == 0 || k == 0) return RPT_OK;
+  if (L == 0 || (k == 0 && !optr)) return RPT_OK;
   if (p.ldn > kBlock) return RPT_ERR_UNSUPPORTED;
   SampledArgs a;
   a.v = p.v;
@@ -85,6 +89,7 @@ rpt_status sampled_launch(const PrepX& p, const uint8_t* labels, int64_t L, cons
   a.n1 = p.n1;
   a.omega = omega;
   a.k = k;
+  a.optr = optr;
   a.y = y;
   const int m = p.n / 2;
   a.fs = static_cast<float>(2.0 * sqrt((m - 1.0) / m));

@@ -62,3 +62,27 @@ def test_naive_argument_validation(lib):
                                  None) == -4
     # L == 0 is a valid no-op
     assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 0, 0, 1, dummy, None, dummy, ws_need, None) == 0
+
+
+def test_batched_recovery_validation(lib):
+    from paper_1703_01506_amd._lib import RptStudy
+    dummy = 256
+    arr = (RptStudy * 2)()
+    for d in arr:
+        d.X, d.v, d.n, d.n1, d.ldx = dummy, 5000, 20, 10, 20
+        d.labels, d.L_rec, d.col0, d.U, d.r, d.study = dummy, 30, 0, dummy, 8, 0
+        d.sigma_mu, d.omega_ptr, d.omega_idx, d.nnz, d.seed = dummy, dummy, dummy, 3000, 1
+        d.max_out, d.info = dummy, dummy
+    need = lib.rpt_recover_batched_workspace(arr, 2)
+    assert need > 0
+    ws = C.c_void_p(512)
+    # workspace too small, and a bad study caught before any launch
+    assert lib.rpt_recover_maxnull_batched(arr, 2, ws, need - 1, None) == -4
+    arr[1].n1 = 9
+    assert lib.rpt_recover_batched_workspace(arr, 2) == 0
+    assert lib.rpt_recover_maxnull_batched(arr, 2, ws, need, None) == -6
+    arr[1].n1 = 10
+    arr[1].r = 129
+    assert lib.rpt_recover_maxnull_batched(arr, 2, ws, need, None) == -1
+    # no studies is a valid no-op
+    assert lib.rpt_recover_maxnull_batched(arr, 0, ws, need, None) == 0
