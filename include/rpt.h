@@ -268,6 +268,37 @@ rpt_status rpt_recover_maxnull_batched(const rpt_study* studies, int32_t n_studi
                                        void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
+ * Inference on the observed labelling (Sec. 2; Sec. 5.5; Eq. 4).
+ *
+ * rpt_observed_tstat: t of Eq. 2 (reading: unbiased group variances) for
+ *   every voxel under the observed labelling, group 1 = subjects 0..n1-1 of
+ *   X (v x n FP32, row stride ldx), into t_out [v] FP32.  Workspace from
+ *   rpt_observed_tstat_workspace (256-byte aligned).  4 <= n <= 128,
+ *   2 <= n1 <= n - 2.
+ * rpt_fwer_threshold: *thr_out (device FP32) = the ascending order statistic
+ *   m_(L - floor(alpha L)) (1-based) of maxima [L]: the level-alpha
+ *   family-wise threshold.  0 <= alpha < 1.
+ * rpt_corrected_pvalues: p_out [v] = #{i : maxima_i >= t_k} / L for every
+ *   entry of t [v] (the fraction of the max null at least as extreme).
+ * rpt_rejection_counts: counts_out (device int64 [3]) = v1, v2, vc: voxels
+ *   with corrected p <= alpha under maxima1 [L1], under maxima2 [L2], and
+ *   under both; Eq. 4's resampling risk is ((v1-vc)/v1 + (v2-vc)/v2) / 2.
+ * All pointers are device memory owned by the caller; the comparisons are
+ * exact in FP32 and the p <= alpha decision is taken in FP64 as (c / L) <=
+ * alpha.  Invalid sizes or null pointers give RPT_ERR_INVALID_ARG.
+ * ------------------------------------------------------------------------- */
+size_t rpt_observed_tstat_workspace(int64_t v, int32_t n);
+rpt_status rpt_observed_tstat(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
+                              float* t_out, void* ws, size_t ws_bytes, void* stream);
+rpt_status rpt_fwer_threshold(const float* maxima, int64_t L, double alpha, float* thr_out,
+                              void* stream);
+rpt_status rpt_corrected_pvalues(const float* maxima, int64_t L, const float* t, int64_t v,
+                                 float* p_out, void* stream);
+rpt_status rpt_rejection_counts(const float* maxima1, int64_t L1, const float* maxima2, int64_t L2,
+                                const float* t, int64_t v, double alpha, int64_t* counts_out,
+                                void* stream);
+
+/* -------------------------------------------------------------------------
  * Orthonormalisation used by training: U <- U R^{-1}, with R^T R = U^T U
  * (Cholesky-QR, Gram and Cholesky in FP64, applied twice).  In place.
  *   U  v x r FP32 (in/out).  Requirements: 1 <= r <= 128, v >= r.

@@ -8,14 +8,18 @@ library and fails loudly if it has not been built
 from . import _lib
 from .api import (  # noqa: F401
     complete,
+    corrected_pvalues,
+    fwer_threshold,
     masked_loss_bwd,
     masked_loss_fwd,
     naive_maxnull,
+    observed_tstat,
     rapidpt_maxnull,
     recover_maxnull,
     recover_maxnull_batched,
     recover_studies_launch,
     recover_studies_prepare,
+    rejection_counts,
     reorth,
     sampled_tstat,
     train_subspace,
@@ -27,5 +31,5 @@ _lib.load()
 __all__ = [
     "naive_maxnull", "sampled_tstat", "complete", "reorth", "train_subspace", "recover_maxnull",
     "rapidpt_maxnull", "recover_maxnull_batched", "recover_studies_prepare", "recover_studies_launch",
-    "masked_loss_fwd", "masked_loss_bwd", "MaskedSubspaceLoss", "masked_subspace_loss",
+    "observed_tstat", "fwer_threshold", "corrected_pvalues", "rejection_counts", "masked_loss_fwd", "masked_loss_bwd", "MaskedSubspaceLoss", "masked_subspace_loss",
 ]

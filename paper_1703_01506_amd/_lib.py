@@ -49,6 +49,11 @@ SIGNATURES = {
                                    _p, _p, _p, _p, _sz, _p]),
     "rpt_recover_batched_workspace": (_sz, [C.POINTER(RptStudy), _i32]),
     "rpt_recover_maxnull_batched": (_int, [C.POINTER(RptStudy), _i32, _p, _sz, _p]),
+    "rpt_observed_tstat_workspace": (_sz, [_i64, _i32]),
+    "rpt_observed_tstat": (_int, [_p, _i64, _i32, _i64, _i32, _p, _p, _sz, _p]),
+    "rpt_fwer_threshold": (_int, [_p, _i64, C.c_double, _p, _p]),
+    "rpt_corrected_pvalues": (_int, [_p, _i64, _p, _i64, _p, _p]),
+    "rpt_rejection_counts": (_int, [_p, _i64, _p, _i64, _p, _i64, C.c_double, _p, _p]),
     "rpt_reorth_workspace": (_sz, [_i64, _i32]),
     "rpt_reorth": (_int, [_p, _i64, _i32, _p, _p, _sz, _p]),
     "rpt_masked_loss_fwd": (_int, [_p, _i64, _i32, _p, _i32, _p, _p, _p, _i64, _p, _p, _p]),

@@ -232,6 +232,53 @@ def recover_maxnull_batched(studies):
     return outs
 
 
+def observed_tstat(X, n1: int | None = None):
+    """t of every voxel under the observed labelling (group 1 = the first n1
+    subjects).  Returns t (v,) FP32."""
+    lib = _lib.load()
+    v, n, ldx = _data(X)
+    n1 = n // 2 if n1 is None else int(n1)
+    t = torch.empty(v, dtype=torch.float32, device=X.device)
+    ws = _workspace(lib.rpt_observed_tstat_workspace(v, n), X.device)
+    rc = lib.rpt_observed_tstat(_ptr(X), v, n, ldx, n1, _ptr(t), _ptr(ws), ws.numel(), _stream(X.device))
+    _lib.check(rc, "rpt_observed_tstat")
+    return t
+
+
+def fwer_threshold(maxima, alpha: float = 0.05):
+    """Level-alpha family-wise threshold (a (1,) FP32 device tensor)."""
+    lib = _lib.load()
+    maxima = _dev(maxima, torch.float32, "maxima", 1).contiguous()
+    out = torch.empty(1, dtype=torch.float32, device=maxima.device)
+    rc = lib.rpt_fwer_threshold(_ptr(maxima), maxima.numel(), float(alpha), _ptr(out), _stream(maxima.device))
+    _lib.check(rc, "rpt_fwer_threshold")
+    return out
+
+
+def corrected_pvalues(maxima, t):
+    """Corrected p-value of every entry of t against the max null."""
+    lib = _lib.load()
+    maxima = _dev(maxima, torch.float32, "maxima", 1).contiguous()
+    t = _dev(t, torch.float32, "t", 1).contiguous()
+    p = torch.empty_like(t)
+    rc = lib.rpt_corrected_pvalues(_ptr(maxima), maxima.numel(), _ptr(t), t.numel(), _ptr(p), _stream(t.device))
+    _lib.check(rc, "rpt_corrected_pvalues")
+    return p
+
+
+def rejection_counts(maxima1, maxima2, t, alpha: float = 0.05):
+    """(v1, v2, vc) rejections at alpha under two max nulls (int64 device (3,))."""
+    lib = _lib.load()
+    m1 = _dev(maxima1, torch.float32, "maxima1", 1).contiguous()
+    m2 = _dev(maxima2, torch.float32, "maxima2", 1).contiguous()
+    t = _dev(t, torch.float32, "t", 1).contiguous()
+    out = torch.empty(3, dtype=torch.int64, device=t.device)
+    rc = lib.rpt_rejection_counts(_ptr(m1), m1.numel(), _ptr(m2), m2.numel(), _ptr(t), t.numel(), float(alpha),
+                                  _ptr(out), _stream(t.device))
+    _lib.check(rc, "rpt_rejection_counts")
+    return out
+
+
 def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omega_rec, passes: int, seed: int,
                     batch: int | None = None, gamma: float = 1.0, mu_rule: str = "mean_gap",
                     prec: str = "split_bf16"):

@@ -1,0 +1,54 @@
+"""GPU: inference on the observed labelling (Sec. 2, Sec. 5.5, Eq. 4) against
+the oracle: observed t map, FWER threshold, corrected p-values, rejection
+counts (integer-exact: same FP32 inputs on both sides)."""
+import numpy as np
+import pytest
+
+import rpt_synth as S
+from gpu_util import announce, assert_t_close, torch_cuda
+from oracle import metrics as OM
+from oracle import tstat as OT
+
+pytestmark = pytest.mark.gpu
+
+
+def _d(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+@pytest.mark.parametrize("n,n1", [(20, 10), (30, 11)])
+def test_observed_tmap(n, n1):
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce(f"observed t n={n} n1={n1}")
+    X, _ = S.iid_volumes(n, 10_007, n1, signal_frac=0.02, shift=0.5, seed=1703)
+    X = X.astype(np.float32)
+    t = rpt.observed_tstat(_d(torch, X), n1=n1).cpu().numpy()
+    g1 = np.zeros(n, dtype=bool)
+    g1[:n1] = True
+    assert_t_close(t, OT.tstat(X.astype(np.float64), g1), "fp32", "t")
+
+
+def test_threshold_pvalues_and_rejections():
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce("inference")
+    rng = np.random.default_rng(5)
+    L, v = 10_000, 50_003
+    h1 = (rng.gumbel(size=L) * 0.3 + 4.0).astype(np.float32)
+    h2 = (h1 + rng.normal(size=L).astype(np.float32) * 0.05).astype(np.float32)
+    h1[:7] = h1[100]  # ties
+    t = (rng.normal(size=v) * 1.5).astype(np.float32)
+    t[:50] = h1[:50]  # statistics equal to maxima
+    t[50:200] = rng.uniform(4.0, 6.0, size=150).astype(np.float32)
+    for alpha in (0.05, 0.01, 0.0):
+        thr = rpt.fwer_threshold(_d(torch, h1), alpha).item()
+        assert thr == np.float32(OM.threshold(h1, alpha))
+    p = rpt.corrected_pvalues(_d(torch, h1), _d(torch, t)).cpu().numpy()
+    pref = OM.corrected_pvalue(h1, t)
+    assert np.array_equal(np.round(p.astype(np.float64) * L), np.round(pref * L))
+    for alpha in (0.05, 0.01):
+        c = rpt.rejection_counts(_d(torch, h1), _d(torch, h2), _d(torch, t), alpha).cpu().numpy()
+        r1, r2 = OM.rejected(h1, t, alpha), OM.rejected(h2, t, alpha)
+        assert list(c) == [int(r1.sum()), int(r2.sum()), int((r1 & r2).sum())]
+        assert c[0] > 0
