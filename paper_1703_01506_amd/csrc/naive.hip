@@ -387,8 +387,17 @@ __global__ void naive_finalize_kernel(const float* __restrict__ partial, int nc,
                                       float* __restrict__ max_out) {
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= L) return;
+  // eight partial maxima in flight per thread
   float u = partial[i];
-  for (int c = 1; c < nc; ++c) u = fmaxf(u, partial[static_cast<int64_t>(c) * L + i]);
+  int c = 1;
+  for (; c + 8 <= nc; c += 8) {
+    float q[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) q[e] = partial[static_cast<int64_t>(c + e) * L + i];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) u = fmaxf(u, q[e]);
+  }
+  for (; c < nc; ++c) u = fmaxf(u, partial[static_cast<int64_t>(c) * L + i]);
   max_out[i] = apply_t ? static_cast<float>(t_from_u(static_cast<double>(u), m)) : u;
 }
 

@@ -74,39 +74,55 @@ __device__ __forceinline__ float noise_z(uint64_t seed, unsigned stream, unsigne
 // umax >= max_k |U_k|_2
 __global__ void recon_init_kernel(unsigned* umax_bits) { *umax_bits = 0u; }
 
+// 64 voxels per workgroup: the rows (64 r contiguous floats) are read with
+// coalesced loads into LDS, then thread (voxel, quarter) converts one
+// 16-byte chunk (hi 0-7, hi 8-15, lo 0-7 or lo 8-15) of every K step.  The
+// largest row norm goes out with one atomic per workgroup.
+constexpr int kPrepUVox = 64;
 __global__ __launch_bounds__(kBlock) void recon_prep_u_kernel(const float* __restrict__ U, int64_t v, int r,
                                                              int64_t vpad, int ks, uint16_t* __restrict__ ukb,
                                                              unsigned* umax_bits) {
-  const int64_t vox = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+  __shared__ float rows[kPrepUVox][kRMaxRefine + 1];
+  __shared__ float red[kBlock / 64];
+  const int tid = threadIdx.x;
+  const int64_t v0 = static_cast<int64_t>(blockIdx.x) * kPrepUVox;
+  const int nv = static_cast<int>(v - v0 < kPrepUVox ? (v - v0 > 0 ? v - v0 : 0) : kPrepUVox);
+  for (int idx = tid; idx < kPrepUVox * r; idx += kBlock) {
+    const int rr = idx / r, c = idx - rr * r;
+    rows[rr][c] = rr < nv ? U[(v0 + rr) * r + c] : 0.0f;
+  }
+  __syncthreads();
+  const int rr = tid >> 2, q = tid & 3;  // voxel within the tile, chunk of 8 values
+  const int64_t vox = v0 + rr;
   float nrm = 0.0f;
   if (vox < vpad) {
-    const float* u = U + vox * r;
     for (int s = 0; s < ks; ++s) {
-      uint32_t wh[8], wl[8];
+      uint32_t w[4];
 #pragma unroll
-      for (int e2 = 0; e2 < 8; ++e2) {
-        uint32_t ph = 0, pl = 0;
+      for (int e2 = 0; e2 < 4; ++e2) {
+        uint32_t pr = 0;
 #pragma unroll
         for (int hl = 0; hl < 2; ++hl) {
-          const int c = 16 * s + 2 * e2 + hl;
-          const float x = (vox < v && c < r) ? u[c] : 0.0f;
-          nrm = fmaf(x, x, nrm);
+          const int c = 16 * s + 8 * (q & 1) + 2 * e2 + hl;
+          const float x = c < r ? rows[rr][c] : 0.0f;
+          if (q < 2) nrm = fmaf(x, x, nrm);
           const uint16_t hi = f2bf(x);
-          ph |= static_cast<uint32_t>(hi) << (16 * hl);
-          pl |= static_cast<uint32_t>(f2bf(x - bf2f(hi))) << (16 * hl);
+          const uint16_t val = (q < 2) ? hi : f2bf(x - bf2f(hi));
+          pr |= static_cast<uint32_t>(val) << (16 * hl);
         }
-        wh[e2] = ph;
-        wl[e2] = pl;
+        w[e2] = pr;
       }
-      u32x4* d = reinterpret_cast<u32x4*>(ukb + (static_cast<size_t>(s) * vpad + vox) * 32);
-      d[0] = u32x4{wh[0], wh[1], wh[2], wh[3]};
-      d[1] = u32x4{wh[4], wh[5], wh[6], wh[7]};
-      d[2] = u32x4{wl[0], wl[1], wl[2], wl[3]};
-      d[3] = u32x4{wl[4], wl[5], wl[6], wl[7]};
+      *reinterpret_cast<u32x4*>(ukb + (static_cast<size_t>(s) * vpad + vox) * 32 + 8 * q) =
+          u32x4{w[0], w[1], w[2], w[3]};
     }
   }
+  // row norm: the two hi quarters of a voxel hold its two halves
+  nrm += __shfl_xor(nrm, 1, 64);
   nrm = wave_max(nrm);
-  if ((threadIdx.x & 63) == 0) atomicMax(umax_bits, __float_as_uint(sqrtf(nrm) * 1.000001f));
+  if ((tid & 63) == 0) red[tid >> 6] = nrm;
+  __syncthreads();
+  if (tid == 0)
+    atomicMax(umax_bits, __float_as_uint(sqrtf(fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]))) * 1.000001f));
 }
 
 // Path choice made on the device (sigma is a device value): exact pruning pays
@@ -442,8 +458,17 @@ __global__ void recon_fused_finalize_kernel(const float* __restrict__ partial, i
   if (*path != 0) return;
   const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
   if (i >= L) return;
+  // eight partial maxima in flight per thread
   float m = partial[i];
-  for (int c = 1; c < nc; ++c) m = fmaxf(m, partial[static_cast<int64_t>(c) * L + i]);
+  int c = 1;
+  for (; c + 8 <= nc; c += 8) {
+    float q[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) q[e] = partial[static_cast<int64_t>(c + e) * L + i];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) m = fmaxf(m, q[e]);
+  }
+  for (; c < nc; ++c) m = fmaxf(m, partial[static_cast<int64_t>(c) * L + i]);
   if (out) out[i] = m + sigma_mu[1];
   if (gap) gap[i] = tmax[i] - m;
 }
@@ -544,8 +569,8 @@ rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_
   RPT_CHECK_LAUNCH();
   hipLaunchKernelGGL(recon_decide_kernel, dim3(1), dim3(1), 0, s, sigma_mu, path);
   RPT_CHECK_LAUNCH();
-  hipLaunchKernelGGL(recon_prep_u_kernel, dim3(static_cast<unsigned>(ceil_div(pl.vpad, kBlock))), dim3(kBlock), 0, s,
-                     U, v, r, pl.vpad, pl.ks, ukb, umax);
+  hipLaunchKernelGGL(recon_prep_u_kernel, dim3(static_cast<unsigned>(ceil_div(pl.vpad, kPrepUVox))), dim3(kBlock), 0,
+                     s, U, v, r, pl.vpad, pl.ks, ukb, umax);
   RPT_CHECK_LAUNCH();
 
   // fused path (runs when the device decided path 0)

@@ -339,9 +339,16 @@ __global__ __launch_bounds__(kBlock) void moments_kernel(const float* __restrict
   }
   s = wave_sum_d(s);
   s2 = wave_sum_d(s2);
+  // one atomic pair per workgroup
+  __shared__ double red[2][kBlock / 64];
   if ((threadIdx.x & 63) == 0) {
-    atomicAdd(sums, s);
-    atomicAdd(sums + 1, s2);
+    red[0][threadIdx.x >> 6] = s;
+    red[1][threadIdx.x >> 6] = s2;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicAdd(sums, (red[0][0] + red[0][1]) + (red[0][2] + red[0][3]));
+    atomicAdd(sums + 1, (red[1][0] + red[1][1]) + (red[1][2] + red[1][3]));
   }
 }
 
@@ -493,8 +500,9 @@ rpt_status sigma_launch(const float* resid, int64_t n, double* sums, float* sigm
   RPT_STAGE("sigma", s);
   hipLaunchKernelGGL(zero_doubles_kernel, dim3(1), dim3(64), 0, s, sums, 2);
   RPT_CHECK_LAUNCH();
-  int64_t blocks = ceil_div(n, kBlock);
-  if (blocks > 1024) blocks = 1024;
+  int64_t blocks = ceil_div(n, kBlock * 4);
+  if (blocks > 256) blocks = 256;
+  if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(moments_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, resid, n, sums);
   RPT_CHECK_LAUNCH();
   hipLaunchKernelGGL(sigma_finish_kernel, dim3(1), dim3(1), 0, s, sums, n, sigma_mu);
