@@ -3,10 +3,13 @@
 Every case feeds the same seeded inputs (relabellings, sampled sets, Gaussian
 start matrix) to both sides; the noise is drawn on both sides from the same
 counter-based generator."""
+import sys
+
 import numpy as np
 import pytest
 
 import rpt_synth as S
+from conftest import golden_path
 from gpu_util import announce, assert_t_close, torch_cuda
 from oracle import metrics as OM
 from oracle import philox as PH
@@ -14,6 +17,8 @@ from oracle import rapidpt as OR
 from oracle import tstat as OT
 
 pytestmark = pytest.mark.gpu
+
+TOL_SUBSPACE_REL = 1e-3
 
 
 def _dev(torch, a):
@@ -251,3 +256,48 @@ def test_masked_loss_forward_backward():
     assert abs(float(loss.cpu().numpy()[0]) - fref) <= 1e-5 * fref
     assert np.linalg.norm(dU.cpu().numpy() - gU) <= 1e-5 * np.linalg.norm(gU)
     assert np.linalg.norm(dW.cpu().numpy() - gW) <= 1e-5 * np.linalg.norm(gW)
+
+
+def test_train_full_size_bench_shape():
+    """The training half at the benchmark's shape and launch configuration:
+    n = 100 (50/50), v = 250,000 smoothed, l = 300, r = 100, 875 sampled
+    voxels per column, 10 passes of one l-column mini-batch, split-BF16.  The
+    FP64 oracle's result (5 minutes of CPU) is stored by
+    tests/golden/make_train_full.py: sigma, mu, the 300 exact maxima and the
+    oracle basis at 48 sampled voxels.  Three t maps are recomputed here one by
+    one.  The subspace is compared through the projector U_S U_S^T on the
+    sampled voxels, which does not depend on the basis chosen inside it."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    sys.path.insert(0, golden_path(""))
+    import make_train_full as G
+    g = G.load()
+    announce("train full size (bench shape)")
+    n, v, L, ell, r, seed, passes = G.N, G.V, G.L, G.ELL, G.R, G.SEED, G.PASSES
+    k = S.omega_count(v, G.ETA_PPM)
+    X = S.smoothed_volumes(n, v, seed=1703)
+    tl = S.relabellings(L, n, n // 2, seed=1506)[:ell]
+    U0 = S.gaussian_matrix(v, r, seed=3).astype(np.float32)
+    omt = S.omega_sets(passes * ell, v, k, seed=41)
+    oms = S.omega_sets(ell, v, k, seed=42)
+    out = rpt.train_subspace(_dev(torch, X), _dev(torch, tl), _dev(torch, U0), _dev(torch, omt), _dev(torch, oms),
+                             passes=passes, seed=seed, return_T=True)
+    Ud = out["U"].double()
+    gram = (Ud.T @ Ud).cpu().numpy()
+    T_ex = out["T_ex"]
+    rows = [0, 157, ell - 1]
+    X64 = X.astype(np.float64)
+    for i in rows:
+        assert_t_close(T_ex[i].cpu().numpy(), OT.tstat(X64, tl[i] == 1), "split", f"T_ex row {i}")
+    assert_t_close(out["train_max"].cpu().numpy(), g["train_max"], "split", "train_max")
+    assert (out["info"].cpu().numpy() == 0).all()
+    np.testing.assert_allclose(gram, np.eye(r), atol=5e-5)
+    Us = out["U"][torch.from_numpy(g["voxels"]).cuda()].double().cpu().numpy()
+    Pg, Po = Us @ Us.T, g["U_rows"] @ g["U_rows"].T
+    rel = np.linalg.norm(Pg - Po) / np.linalg.norm(Po)
+    print(f"projector rel err {rel:.3e}", flush=True)
+    assert rel < TOL_SUBSPACE_REL
+    sigma, mu = [float(x) for x in out["sigma_mu"].cpu().numpy()]
+    print(f"sigma {sigma:.6g} vs {g['sigma']:.6g}, mu {mu:.6g} vs {g['mu']:.6g}", flush=True)
+    assert abs(sigma - g["sigma"]) <= 1e-3 * g["sigma"]
+    assert abs(mu - g["mu"]) <= 2e-3
