@@ -220,6 +220,46 @@ rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
                                void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
+ * Alg. 2 end to end: the TRAINING half (as rpt_train_subspace) followed by
+ * the RECOVERY half (as rpt_recover_maxnull with col0 = l, the basis, sigma
+ * and mu just trained).  h^L is returned as its L = l + L_rec samples:
+ * h_out[0..l) the exact training maxima, h_out[l..l+L_rec) the recovered
+ * maxima + mu.
+ *
+ * Steps that do not depend on each other run on a second stream of the same
+ * device (created by the first call on that device, default priority, kept
+ * until the process ends): the orthonormalisation of U0 while T_ex is
+ * computed on `stream`, then the sampled t statistics of the recovered
+ * columns (they need no basis) while the tracking passes run on `stream`.
+ * The call joins that stream back into `stream` before it returns, so every
+ * output is ordered on `stream` like any other call.  A first call made
+ * while `stream` is being captured into a graph, or a device where the
+ * second stream cannot be created, runs every step on `stream` instead.
+ *
+ *   train_labels  l x n uint8;  rec_labels  L_rec x n uint8             (in)
+ *   U0, omega_train, omega_sm, passes, batch, gamma, mu_rule, prec: as
+ *                 rpt_train_subspace;  omega_rec  L_rec x k int32        (in)
+ *   h_out         l + L_rec FP32                                        (out)
+ *   U_out         v x r FP32 trained basis                              (out)
+ *   sigma_mu      2 FP32 on the device {sigma, mu}                      (out)
+ *   train_info    l int32;  rec_info  L_rec int32 (as rpt_complete)     (out)
+ *   ws            rpt_rapidpt_workspace(v, n, l, L_rec, r, k, prec) bytes
+ * Errors: those of rpt_train_subspace and rpt_recover_maxnull, all checked
+ * before the first launch.
+ * ------------------------------------------------------------------------- */
+size_t rpt_rapidpt_workspace(int64_t v, int32_t n, int32_t ell, int64_t L_rec, int32_t r, int32_t k, int prec);
+rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
+                               const uint8_t* train_labels, int32_t ell,
+                               const uint8_t* rec_labels, int64_t L_rec,
+                               const float* U0, int32_t r,
+                               const int32_t* omega_train, int32_t k, int32_t passes,
+                               int32_t batch, float gamma, const int32_t* omega_sm,
+                               const int32_t* omega_rec, uint64_t seed, int mu_rule, int prec,
+                               float* h_out, float* U_out, float* sigma_mu,
+                               int32_t* train_info, int32_t* rec_info,
+                               void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
  * Recovery phase of Alg. 2 for several studies in one call, with uneven
  * sampled sets (Alg. 2 RECOVERY; the per-study sampled-set sizes follow from
  * eta and each study's v).  Per study the same steps as rpt_recover_maxnull:

@@ -45,6 +45,9 @@ SIGNATURES = {
     "rpt_train_subspace": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i32, _p, _i32, _p, _i32, _i32, _i32, _f32,
                                   _p, _u64, _int, _int, _p, _p, _p, _p, _p, _p, _sz, _p]),
     "rpt_recover_workspace": (_sz, [_i64, _i32, _i64, _i32, _i32]),
+    "rpt_rapidpt_workspace": (_sz, [_i64, _i32, _i32, _i64, _i32, _i32, _int]),
+    "rpt_rapidpt_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i32, _p, _i64, _p, _i32, _p, _i32, _i32, _i32,
+                                   _f32, _p, _p, _u64, _int, _int, _p, _p, _p, _p, _p, _p, _sz, _p]),
     "rpt_recover_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _i64, _p, _i32, _p, _p, _i32, _u64,
                                    _p, _p, _p, _p, _sz, _p]),
     "rpt_recover_batched_workspace": (_sz, [C.POINTER(RptStudy), _i32]),

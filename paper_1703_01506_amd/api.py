@@ -282,12 +282,36 @@ def rejection_counts(maxima1, maxima2, t, alpha: float = 0.05):
 def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omega_rec, passes: int, seed: int,
                     batch: int | None = None, gamma: float = 1.0, mu_rule: str = "mean_gap",
                     prec: str = "split_bf16"):
-    """Alg. 2 end to end: the l exact training maxima followed by the recovered
-    ones.  Returns (h (L,), train dict, recovery info)."""
-    tr = train_subspace(X, train_labels, U0, omega_train, omega_sm, passes, seed, batch, gamma, mu_rule, prec)
-    rec, info = recover_maxnull(X, rec_labels, tr["U"], tr["sigma_mu"], omega_rec, seed,
-                                col0=train_labels.shape[0])
-    return torch.cat([tr["train_max"], rec]), tr, info
+    """Alg. 2 end to end in one library call: the l exact training maxima
+    followed by the recovered ones.  Returns (h (L,), train dict, recovery
+    info); the train dict holds U, sigma_mu, train_max (a view of h) and info."""
+    lib = _lib.load()
+    v, n, ldx = _data(X)
+    train_labels = _dev(train_labels, torch.uint8, "train_labels", 2).contiguous()
+    rec_labels = _dev(rec_labels, torch.uint8, "rec_labels", 2).contiguous()
+    U0 = _dev(U0, torch.float32, "U0", 2).contiguous()
+    omega_train = _dev(omega_train, torch.int32, "omega_train", 2).contiguous()
+    omega_sm = _dev(omega_sm, torch.int32, "omega_sm", 2).contiguous()
+    omega_rec = _dev(omega_rec, torch.int32, "omega_rec", 2).contiguous()
+    ell, L_rec = train_labels.shape[0], rec_labels.shape[0]
+    r, k = U0.shape[1], omega_sm.shape[1]
+    if (omega_train.shape != (passes * ell, k) or omega_sm.shape[0] != ell or omega_rec.shape != (L_rec, k)
+            or U0.shape[0] != v):
+        raise ValueError("inconsistent shapes")
+    batch = ell if batch is None else int(batch)
+    dev = X.device
+    h = torch.empty(ell + L_rec, dtype=torch.float32, device=dev)
+    U = torch.empty((v, r), dtype=torch.float32, device=dev)
+    sm = torch.empty(2, dtype=torch.float32, device=dev)
+    tinfo = torch.empty(ell, dtype=torch.int32, device=dev)
+    rinfo = torch.empty(L_rec, dtype=torch.int32, device=dev)
+    ws = _workspace(lib.rpt_rapidpt_workspace(v, n, ell, L_rec, r, k, PREC[prec]), dev)
+    rc = lib.rpt_rapidpt_maxnull(_ptr(X), v, n, ldx, n // 2, _ptr(train_labels), ell, _ptr(rec_labels), L_rec,
+                                 _ptr(U0), r, _ptr(omega_train), k, passes, batch, float(gamma), _ptr(omega_sm),
+                                 _ptr(omega_rec), int(seed), MU_RULE[mu_rule], PREC[prec], _ptr(h), _ptr(U),
+                                 _ptr(sm), _ptr(tinfo), _ptr(rinfo), _ptr(ws), ws.numel(), _stream(dev))
+    _lib.check(rc, "rpt_rapidpt_maxnull")
+    return h, {"U": U, "sigma_mu": sm, "train_max": h[:ell], "info": tinfo}, rinfo
 
 
 def masked_loss_fwd(U, W, omega_ptr, omega_idx, t_vals):

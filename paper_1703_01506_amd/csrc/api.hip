@@ -1,5 +1,7 @@
 // C ABI of librpt: argument validation, workspace carving and launch order.
 // Every entry point enqueues on the caller's stream and never synchronises.
+#include <mutex>
+
 #include "rpt_internal.h"
 
 namespace rpt {
@@ -185,12 +187,14 @@ size_t rpt_train_workspace(int64_t v, int32_t n, int32_t ell, int32_t r, int32_t
   return total;
 }
 
-rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
-                              const uint8_t* train_labels, int32_t ell, const float* U0, int32_t r,
-                              const int32_t* omega_train, int32_t k, int32_t passes, int32_t batch, float gamma,
-                              const int32_t* omega_sm, uint64_t seed, int mu_rule, int prec, float* U_out,
-                              float* sigma_mu, float* train_max, float* T_ex_out, int32_t* info, void* ws,
-                              size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace rpt {
+namespace {
+rpt_status train_check(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* train_labels,
+                       int32_t ell, const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
+                       int32_t batch, float gamma, const int32_t* omega_sm, int mu_rule, int prec, const float* U_out,
+                       const float* sigma_mu, const float* train_max, const int32_t* info) {
   if (!design_ok(v, n, ldx, n1) || 2 * n1 != n) return design_ok(v, n, ldx, n1) ? RPT_ERR_UNSUPPORTED
                                                                                : RPT_ERR_INVALID_ARG;
   if (ell < 1 || r < 1 || r > 128 || r > v || k < 1 || k > v || passes < 0 || batch < 1 || batch > ell ||
@@ -202,23 +206,63 @@ rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx,
   if (!X || !train_labels || !U0 || (passes > 0 && !omega_train) || !omega_sm || !U_out || !sigma_mu ||
       !train_max || !info)
     return RPT_ERR_INVALID_ARG;
-  if (!ws_ok(ws, ws_bytes, rpt_train_workspace(v, n, ell, r, k, prec))) return RPT_ERR_WORKSPACE;
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  return RPT_OK;
+}
+
+// the training steps on stream s, arguments already checked
+rpt_status train_tex(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* train_labels,
+                     int32_t ell, int32_t r, int32_t k, int prec, float* train_max, float* T_ex_out, void* ws,
+                     hipStream_t s);
+rpt_status train_start_basis(int64_t v, int32_t n, int32_t n1, int32_t ell, const float* U0, int32_t r, int32_t k,
+                             int prec, float* U_out, void* ws, hipStream_t s);
+rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r, const int32_t* omega_train,
+                       int32_t k, int32_t passes, int32_t batch, float gamma, const int32_t* omega_sm, uint64_t seed,
+                       int mu_rule, int prec, float* U_out, float* sigma_mu, float* train_max, float* T_ex_out,
+                       int32_t* info, void* ws, hipStream_t s);
+
+rpt_status train_run(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* train_labels,
+                     int32_t ell, const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
+                     int32_t batch, float gamma, const int32_t* omega_sm, uint64_t seed, int mu_rule, int prec,
+                     float* U_out, float* sigma_mu, float* train_max, float* T_ex_out, int32_t* info, void* ws,
+                     hipStream_t s) {
+  RPT_TRY(train_tex(X, v, n, ldx, n1, train_labels, ell, r, k, prec, train_max, T_ex_out, ws, s));
+  RPT_TRY(train_start_basis(v, n, n1, ell, U0, r, k, prec, U_out, ws, s));
+  return train_track(v, n, n1, ell, r, omega_train, k, passes, batch, gamma, omega_sm, seed, mu_rule, prec, U_out,
+                     sigma_mu, train_max, T_ex_out, info, ws, s);
+}
+
+// 1. training columns T_ex and their exact maxima
+rpt_status train_tex(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* train_labels,
+                     int32_t ell, int32_t r, int32_t k, int prec, float* train_max, float* T_ex_out, void* ws,
+                     hipStream_t s) {
   TrainWs t = train_carve(ws, v, n, n1, ell, r, k, prec, nullptr);
   float* T = T_ex_out ? T_ex_out : t.T;
-  // 1. training columns T_ex and their exact maxima
   const int flags = naive_flags(prec, false);
   RPT_TRY(prep_launch(t.p, X, ldx, RPT_TAIL_SIGNED, flags, s));
   const NaivePlan pl = naive_plan(v, ell, n, prec, true);
-  RPT_TRY(naive_launch(t.p, pl, train_labels, ell, RPT_TAIL_SIGNED, prec, t.partial, T, train_max, s));
-  // 2. U <- Rand. Orth.
+  return naive_launch(t.p, pl, train_labels, ell, RPT_TAIL_SIGNED, prec, t.partial, T, train_max, s);
+}
+
+// 2. U <- Rand. Orth. (independent of T_ex)
+rpt_status train_start_basis(int64_t v, int32_t n, int32_t n1, int32_t ell, const float* U0, int32_t r, int32_t k,
+                             int prec, float* U_out, void* ws, hipStream_t s) {
+  TrainWs t = train_carve(ws, v, n, n1, ell, r, k, prec, nullptr);
   if (hipMemcpyAsync(U_out, U0, sizeof(float) * static_cast<size_t>(v) * r, hipMemcpyDeviceToDevice, s) !=
       hipSuccess) {
     set_hip_error(hipGetLastError());
     return RPT_ERR_HIP;
   }
   RPT_TRY(reorth_launch(U_out, v, r, t.info, t.reorth_ws, s));
-  RPT_TRY(reorth_launch(U_out, v, r, t.info, t.reorth_ws, s));
+  return reorth_launch(U_out, v, r, t.info, t.reorth_ws, s);
+}
+
+// 3.-5. tracking passes, sigma and mu (T_ex and the start basis in place)
+rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r, const int32_t* omega_train,
+                       int32_t k, int32_t passes, int32_t batch, float gamma, const int32_t* omega_sm, uint64_t seed,
+                       int mu_rule, int prec, float* U_out, float* sigma_mu, float* train_max, float* T_ex_out,
+                       int32_t* info, void* ws, hipStream_t s) {
+  TrainWs t = train_carve(ws, v, n, n1, ell, r, k, prec, nullptr);
+  float* T = T_ex_out ? T_ex_out : t.T;
   // 3. tracking passes: Complete links every sampled entry into the list of
   // its voxel; the update then adds each voxel's entries in one pass
   RPT_TRY(fill_i32(t.lhead, v, -1, s));
@@ -248,6 +292,23 @@ rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx,
   }
   return RPT_OK;
 }
+}  // namespace
+}  // namespace rpt
+
+extern "C" {
+
+rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
+                              const uint8_t* train_labels, int32_t ell, const float* U0, int32_t r,
+                              const int32_t* omega_train, int32_t k, int32_t passes, int32_t batch, float gamma,
+                              const int32_t* omega_sm, uint64_t seed, int mu_rule, int prec, float* U_out,
+                              float* sigma_mu, float* train_max, float* T_ex_out, int32_t* info, void* ws,
+                              size_t ws_bytes, void* stream) {
+  RPT_TRY(train_check(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, omega_sm,
+                      mu_rule, prec, U_out, sigma_mu, train_max, info));
+  if (!ws_ok(ws, ws_bytes, rpt_train_workspace(v, n, ell, r, k, prec))) return RPT_ERR_WORKSPACE;
+  return train_run(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, omega_sm, seed,
+                   mu_rule, prec, U_out, sigma_mu, train_max, T_ex_out, info, ws, static_cast<hipStream_t>(stream));
+}
 
 // ---------------------------------------------------------------------------
 // recovery
@@ -261,29 +322,175 @@ size_t rpt_recover_workspace(int64_t v, int32_t n, int64_t L_rec, int32_t r, int
   return c.off;
 }
 
-rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* labels,
-                               int64_t L_rec, int64_t col0, const float* U, int32_t r, const float* sigma_mu,
-                               const int32_t* omega, int32_t k, uint64_t seed, float* max_out, float* W_out,
-                               int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+}  // extern "C"
+
+namespace rpt {
+namespace {
+rpt_status recover_check(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* labels,
+                         int64_t L_rec, int64_t col0, const float* U, int32_t r, const float* sigma_mu,
+                         const int32_t* omega, int32_t k, const float* max_out, const int32_t* info) {
   if (!design_ok(v, n, ldx, n1)) return RPT_ERR_INVALID_ARG;
   if (2 * n1 != n) return RPT_ERR_UNSUPPORTED;
   if (L_rec < 0 || col0 < 0 || r < 1 || r > 128 || r > v || k < 1 || k > v) return RPT_ERR_INVALID_ARG;
   if (k < r) return RPT_ERR_UNDERDETERMINED;
   if (L_rec > 0 && (!X || !labels || !U || !sigma_mu || !omega || !max_out || !info)) return RPT_ERR_INVALID_ARG;
+  return RPT_OK;
+}
+
+struct RecoverWs {
+  PrepX p;
+  float* y;
+  float* W;
+  void* rws;
+};
+RecoverWs recover_carve(void* ws, int64_t v, int32_t n, int32_t n1, int64_t L_rec, int32_t r, int32_t k) {
+  Carver c(ws);
+  RecoverWs w;
+  w.p = prep_carve(c, v, n, n1, kPrepRows);
+  w.y = c.take<float>(static_cast<size_t>(L_rec > 0 ? L_rec : 1) * k);
+  w.W = c.take<float>(static_cast<size_t>(L_rec > 0 ? L_rec : 1) * r);
+  w.rws = c.take<char>(recon_bytes(v, L_rec, r));
+  return w;
+}
+
+// the steps that do not need the basis: sampled t of every recovered column
+rpt_status recover_front(const RecoverWs& w, const float* X, int64_t ldx, const uint8_t* labels, int64_t L_rec,
+                         const int32_t* omega, int32_t k, hipStream_t s) {
+  RPT_TRY(prep_launch(w.p, X, ldx, RPT_TAIL_SIGNED, kPrepRows, s));
+  return sampled_launch(w.p, labels, L_rec, omega, k, nullptr, w.y, s);
+}
+
+// Complete, then U w + noise and the column maxima
+rpt_status recover_back(const RecoverWs& w, int64_t v, int64_t L_rec, int64_t col0, const float* U, int32_t r,
+                        const float* sigma_mu, const int32_t* omega, int32_t k, uint64_t seed, float* max_out,
+                        float* W_out, int32_t* info, hipStream_t s) {
+  float* W = W_out ? W_out : w.W;
+  RPT_TRY(complete_run(U, v, r, omega, k, w.y, nullptr, 0, nullptr, L_rec, W, nullptr, info, nullptr, s));
+  return recon_launch(U, v, r, W, L_rec, col0, seed, RPT_STREAM_RECOVERY, sigma_mu, max_out, nullptr, nullptr,
+                      w.rws, s);
+}
+
+// A second stream per device for work that overlaps the caller's stream:
+// created on first use (never while the caller's stream is being captured),
+// default priority, never destroyed.  Each of the events (fork, mid, join)
+// is recorded and waited on under the device's lock, so concurrent callers
+// cannot swap each other's dependencies.
+struct SideStream {
+  bool ok = false;
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, mid = nullptr, join = nullptr;
+  std::mutex mu;
+};
+constexpr int kMaxDevices = 64;
+std::mutex g_side_init;
+SideStream g_side[kMaxDevices];
+
+SideStream* side_stream(hipStream_t s) {
+  int dev = 0;
+  if (hipStreamGetDevice(s, &dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_side_init);
+  SideStream& sd = g_side[dev];
+  if (sd.ok) return &sd;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) return nullptr;
+  if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
+  bool good = hipStreamCreateWithFlags(&sd.st, hipStreamNonBlocking) == hipSuccess;
+  good = good && hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming) == hipSuccess;
+  good = good && hipEventCreateWithFlags(&sd.mid, hipEventDisableTiming) == hipSuccess;
+  good = good && hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) == hipSuccess;
+  if (cur != dev) (void)hipSetDevice(cur);
+  if (!good) {
+    (void)hipGetLastError();
+    return nullptr;
+  }
+  sd.ok = true;
+  return &sd;
+}
+
+// `to` waits for everything enqueued on `from` so far
+rpt_status stream_wait(SideStream* sd, hipEvent_t ev, hipStream_t from, hipStream_t to) {
+  std::lock_guard<std::mutex> lk(sd->mu);
+  hipError_t e = hipEventRecord(ev, from);
+  if (e == hipSuccess) e = hipStreamWaitEvent(to, ev, 0);
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return RPT_ERR_HIP;
+  }
+  return RPT_OK;
+}
+}  // namespace
+}  // namespace rpt
+
+extern "C" {
+
+rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* labels,
+                               int64_t L_rec, int64_t col0, const float* U, int32_t r, const float* sigma_mu,
+                               const int32_t* omega, int32_t k, uint64_t seed, float* max_out, float* W_out,
+                               int32_t* info, void* ws, size_t ws_bytes, void* stream) {
+  RPT_TRY(recover_check(X, v, n, ldx, n1, labels, L_rec, col0, U, r, sigma_mu, omega, k, max_out, info));
   if (!ws_ok(ws, ws_bytes, rpt_recover_workspace(v, n, L_rec, r, k))) return RPT_ERR_WORKSPACE;
   if (L_rec == 0) return RPT_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  Carver c(ws);
-  PrepX p = prep_carve(c, v, n, n1, kPrepRows);
-  float* y = c.take<float>(static_cast<size_t>(L_rec) * k);
-  float* Wt = c.take<float>(static_cast<size_t>(L_rec) * r);
-  void* rws = c.take<char>(recon_bytes(v, L_rec, r));
-  float* W = W_out ? W_out : Wt;
-  RPT_TRY(prep_launch(p, X, ldx, RPT_TAIL_SIGNED, kPrepRows, s));
-  RPT_TRY(sampled_launch(p, labels, L_rec, omega, k, nullptr, y, s));
-  RPT_TRY(complete_run(U, v, r, omega, k, y, nullptr, 0, nullptr, L_rec, W, nullptr, info, nullptr, s));
-  return recon_launch(U, v, r, W, L_rec, col0, seed, RPT_STREAM_RECOVERY, sigma_mu, max_out, nullptr, nullptr, rws,
-                      s);
+  const RecoverWs w = recover_carve(ws, v, n, n1, L_rec, r, k);
+  RPT_TRY(recover_front(w, X, ldx, labels, L_rec, omega, k, s));
+  return recover_back(w, v, L_rec, col0, U, r, sigma_mu, omega, k, seed, max_out, W_out, info, s);
+}
+
+// ---------------------------------------------------------------------------
+// Alg. 2 end to end
+size_t rpt_rapidpt_workspace(int64_t v, int32_t n, int32_t ell, int64_t L_rec, int32_t r, int32_t k, int prec) {
+  const size_t a = rpt_train_workspace(v, n, ell, r, k, prec);
+  const size_t b = rpt_recover_workspace(v, n, L_rec, r, k);
+  return (a == 0 || b == 0) ? 0 : a + b;
+}
+
+rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
+                               const uint8_t* train_labels, int32_t ell, const uint8_t* rec_labels, int64_t L_rec,
+                               const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
+                               int32_t batch, float gamma, const int32_t* omega_sm, const int32_t* omega_rec,
+                               uint64_t seed, int mu_rule, int prec, float* h_out, float* U_out, float* sigma_mu,
+                               int32_t* train_info, int32_t* rec_info, void* ws, size_t ws_bytes, void* stream) {
+  RPT_TRY(train_check(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, omega_sm,
+                      mu_rule, prec, U_out, sigma_mu, h_out, train_info));
+  RPT_TRY(recover_check(X, v, n, ldx, n1, rec_labels, L_rec, ell, U_out, r, sigma_mu, omega_rec, k, h_out,
+                        rec_info));
+  const size_t tw = rpt_train_workspace(v, n, ell, r, k, prec);
+  if (!ws_ok(ws, ws_bytes, rpt_rapidpt_workspace(v, n, ell, L_rec, r, k, prec))) return RPT_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const RecoverWs w = recover_carve(static_cast<char*>(ws) + tw, v, n, n1, L_rec, r, k);
+  // Two chains share the device: the caller's stream computes T_ex (matrix
+  // cores, the whole chip) and then the tracking passes (latency-bound, few
+  // workgroups at a time); the second stream orthonormalises the start basis
+  // meanwhile (single-workgroup Cholesky) and then computes the sampled t of
+  // the recovered columns, which need no basis, during the tracking passes.
+  SideStream* sd = side_stream(s);
+  if (!sd) {
+    RPT_TRY(train_run(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, omega_sm,
+                      seed, mu_rule, prec, U_out, sigma_mu, h_out, nullptr, train_info, ws, s));
+    if (L_rec == 0) return RPT_OK;
+    RPT_TRY(recover_front(w, X, ldx, rec_labels, L_rec, omega_rec, k, s));
+    return recover_back(w, v, L_rec, ell, U_out, r, sigma_mu, omega_rec, k, seed, h_out + ell, nullptr, rec_info, s);
+  }
+  rpt_status st = stream_wait(sd, sd->fork, s, sd->st);
+  if (st != RPT_OK) return st;
+  // from here on every path joins the second stream back before returning
+  rpt_status st_main = train_tex(X, v, n, ldx, n1, train_labels, ell, r, k, prec, h_out, nullptr, ws, s);
+  rpt_status st_side = train_start_basis(v, n, n1, ell, U0, r, k, prec, U_out, ws, sd->st);
+  st = stream_wait(sd, sd->mid, sd->st, s);  // the basis is ready for the tracking passes
+  if (st_side == RPT_OK && st == RPT_OK && L_rec > 0)
+    st_side = recover_front(w, X, ldx, rec_labels, L_rec, omega_rec, k, sd->st);
+  if (st_main == RPT_OK && st_side == RPT_OK && st == RPT_OK)
+    st_main = train_track(v, n, n1, ell, r, omega_train, k, passes, batch, gamma, omega_sm, seed, mu_rule, prec,
+                          U_out, sigma_mu, h_out, nullptr, train_info, ws, s);
+  const rpt_status st_join = stream_wait(sd, sd->join, sd->st, s);
+  RPT_TRY(st);
+  RPT_TRY(st_side);
+  RPT_TRY(st_main);
+  RPT_TRY(st_join);
+  if (L_rec == 0) return RPT_OK;
+  return recover_back(w, v, L_rec, ell, U_out, r, sigma_mu, omega_rec, k, seed, h_out + ell, nullptr, rec_info, s);
 }
 
 }  // extern "C"
