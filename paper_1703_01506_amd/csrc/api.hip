@@ -312,15 +312,6 @@ rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx,
 
 // ---------------------------------------------------------------------------
 // recovery
-size_t rpt_recover_workspace(int64_t v, int32_t n, int64_t L_rec, int32_t r, int32_t k) {
-  if (v < 1 || n < 4 || L_rec < 0 || r < 1 || k < 1) return 0;
-  Carver c(nullptr);
-  prep_carve(c, v, n, n / 2, kPrepRows);
-  c.take<float>(static_cast<size_t>(L_rec > 0 ? L_rec : 1) * k);
-  c.take<float>(static_cast<size_t>(L_rec > 0 ? L_rec : 1) * r);
-  c.take<char>(recon_bytes(v, L_rec, r));
-  return c.off;
-}
 
 }  // extern "C"
 
@@ -342,14 +333,18 @@ struct RecoverWs {
   float* y;
   float* W;
   void* rws;
+  void* gb;  // Gram matrices of the split Complete
 };
-RecoverWs recover_carve(void* ws, int64_t v, int32_t n, int32_t n1, int64_t L_rec, int32_t r, int32_t k) {
+RecoverWs recover_carve(void* ws, int64_t v, int32_t n, int32_t n1, int64_t L_rec, int32_t r, int32_t k,
+                        size_t* total = nullptr) {
   Carver c(ws);
   RecoverWs w;
   w.p = prep_carve(c, v, n, n1, kPrepRows);
   w.y = c.take<float>(static_cast<size_t>(L_rec > 0 ? L_rec : 1) * k);
   w.W = c.take<float>(static_cast<size_t>(L_rec > 0 ? L_rec : 1) * r);
   w.rws = c.take<char>(recon_bytes(v, L_rec, r));
+  w.gb = c.take<char>(complete_split_bytes(L_rec, r));
+  if (total) *total = c.off;
   return w;
 }
 
@@ -365,65 +360,23 @@ rpt_status recover_back(const RecoverWs& w, int64_t v, int64_t L_rec, int64_t co
                         const float* sigma_mu, const int32_t* omega, int32_t k, uint64_t seed, float* max_out,
                         float* W_out, int32_t* info, hipStream_t s) {
   float* W = W_out ? W_out : w.W;
-  RPT_TRY(complete_run(U, v, r, omega, k, w.y, nullptr, 0, nullptr, L_rec, W, nullptr, info, nullptr, s));
+  RPT_TRY(complete_run(U, v, r, omega, k, w.y, nullptr, 0, nullptr, L_rec, W, nullptr, info, nullptr, s, nullptr,
+                       nullptr, nullptr, w.gb));
   return recon_launch(U, v, r, W, L_rec, col0, seed, RPT_STREAM_RECOVERY, sigma_mu, max_out, nullptr, nullptr,
                       w.rws, s);
 }
 
-// A second stream per device for work that overlaps the caller's stream:
-// created on first use (never while the caller's stream is being captured),
-// default priority, never destroyed.  Each of the events (fork, mid, join)
-// is recorded and waited on under the device's lock, so concurrent callers
-// cannot swap each other's dependencies.
-struct SideStream {
-  bool ok = false;
-  hipStream_t st = nullptr;
-  hipEvent_t fork = nullptr, mid = nullptr, join = nullptr;
-  std::mutex mu;
-};
-constexpr int kMaxDevices = 64;
-std::mutex g_side_init;
-SideStream g_side[kMaxDevices];
-
-SideStream* side_stream(hipStream_t s) {
-  int dev = 0;
-  if (hipStreamGetDevice(s, &dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
-  std::lock_guard<std::mutex> lk(g_side_init);
-  SideStream& sd = g_side[dev];
-  if (sd.ok) return &sd;
-  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  if (hipStreamIsCapturing(s, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) return nullptr;
-  int cur = 0;
-  if (hipGetDevice(&cur) != hipSuccess) return nullptr;
-  if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
-  bool good = hipStreamCreateWithFlags(&sd.st, hipStreamNonBlocking) == hipSuccess;
-  good = good && hipEventCreateWithFlags(&sd.fork, hipEventDisableTiming) == hipSuccess;
-  good = good && hipEventCreateWithFlags(&sd.mid, hipEventDisableTiming) == hipSuccess;
-  good = good && hipEventCreateWithFlags(&sd.join, hipEventDisableTiming) == hipSuccess;
-  if (cur != dev) (void)hipSetDevice(cur);
-  if (!good) {
-    (void)hipGetLastError();
-    return nullptr;
-  }
-  sd.ok = true;
-  return &sd;
-}
-
-// `to` waits for everything enqueued on `from` so far
-rpt_status stream_wait(SideStream* sd, hipEvent_t ev, hipStream_t from, hipStream_t to) {
-  std::lock_guard<std::mutex> lk(sd->mu);
-  hipError_t e = hipEventRecord(ev, from);
-  if (e == hipSuccess) e = hipStreamWaitEvent(to, ev, 0);
-  if (e != hipSuccess) {
-    set_hip_error(e);
-    return RPT_ERR_HIP;
-  }
-  return RPT_OK;
-}
 }  // namespace
 }  // namespace rpt
 
 extern "C" {
+
+size_t rpt_recover_workspace(int64_t v, int32_t n, int64_t L_rec, int32_t r, int32_t k) {
+  if (v < 1 || n < 4 || L_rec < 0 || r < 1 || k < 1) return 0;
+  size_t total = 0;
+  recover_carve(nullptr, v, n, n / 2, L_rec, r, k, &total);
+  return total;
+}
 
 rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* labels,
                                int64_t L_rec, int64_t col0, const float* U, int32_t r, const float* sigma_mu,
@@ -505,6 +458,7 @@ size_t study_bytes(const rpt_study& st) {
   c.take<float>(static_cast<size_t>(st.nnz > 0 ? st.nnz : 1));
   c.take<float>(static_cast<size_t>(st.L_rec > 0 ? st.L_rec : 1) * st.r);
   c.take<char>(recon_bytes(st.v, st.L_rec, st.r));
+  c.take<char>(complete_split_bytes(st.L_rec, st.r));
   return c.off;
 }
 rpt_status study_check(const rpt_study& st) {
@@ -553,10 +507,11 @@ rpt_status rpt_recover_maxnull_batched(const rpt_study* studies, int32_t n_studi
     float* y = c.take<float>(static_cast<size_t>(st.nnz > 0 ? st.nnz : 1));
     float* W = c.take<float>(static_cast<size_t>(st.L_rec) * st.r);
     void* rws = c.take<char>(recon_bytes(st.v, st.L_rec, st.r));
+    void* gb = c.take<char>(complete_split_bytes(st.L_rec, st.r));
     RPT_TRY(prep_launch(p, st.X, st.ldx, RPT_TAIL_SIGNED, kPrepRows, s));
     RPT_TRY(sampled_launch(p, st.labels, st.L_rec, st.omega_idx, 0, nullptr, y, s, st.omega_ptr));
     RPT_TRY(complete_run(st.U, st.v, st.r, st.omega_idx, 0, y, nullptr, 0, nullptr, st.L_rec, W, nullptr, st.info,
-                         nullptr, s, nullptr, nullptr, st.omega_ptr));
+                         nullptr, s, nullptr, nullptr, st.omega_ptr, gb));
     RPT_TRY(recon_launch(st.U, st.v, st.r, W, st.L_rec, st.col0, st.seed, RPT_STREAM_RECOVERY, st.sigma_mu,
                          st.max_out, nullptr, nullptr, rws, s, st.study));
   }

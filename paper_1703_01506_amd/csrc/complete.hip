@@ -64,22 +64,14 @@ size_t smem_bytes(int r) {
          kIdx * (sizeof(int) + sizeof(float));
 }
 
+// The Gram step of column i: the packed FP64 trapezoid G with b^T as row r,
+// complete in LDS when it returns.
 template <int RB>
-__global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(CompleteArgs a) {
+__device__ __forceinline__ void gram_phase(const CompleteArgs& a, int64_t i, int64_t base, int k, double* G,
+                                           int* ibuf, float* ybuf) {
   constexpr int NTILE = RB * (RB + 1) / 2;
-  extern __shared__ __align__(16) unsigned char smem[];
   const int r = a.r;
-  double* G = reinterpret_cast<double*>(smem);
-  double* P = G + gsize(r);
-  double* dinv = P + kCb * kPanelLd;
-  double* wv = dinv + kRMax;
-  int* ibuf = reinterpret_cast<int*>(wv + kRMax);
-  float* ybuf = reinterpret_cast<float*>(ibuf + kIdx);
-
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, c16 = lane & 15, kq = lane >> 4;
-  const int64_t i = blockIdx.x;
-  const int64_t base = a.optr ? a.optr[i] : i * a.k;
-  const int k = a.optr ? static_cast<int>(a.optr[i + 1] - base) : a.k;
   const int32_t* om = a.omega + base;
   const int nrows = r + 1, ntri = nrows * (nrows + 1) / 2;
   for (int t = tid; t < ntri; t += kNT) G[t] = 0.0;
@@ -172,8 +164,18 @@ __global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(Comple
     }
   }
   __syncthreads();
+}
 
-  const int failed = lds_cholesky_blocked<(RB >= 8 ? 3 : 2)>(G, dinv, P, r, nrows);
+// Cholesky, back substitution and the outputs of column i from the
+// trapezoid G in LDS (P: kCb rows of pld doubles).
+template <int RB>
+__device__ __forceinline__ void solve_phase(const CompleteArgs& a, int64_t i, int64_t base, int k, double* G,
+                                            double* P, int pld, double* dinv, double* wv) {
+  const int r = a.r;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int32_t* om = a.omega + base;
+  const int nrows = r + 1;
+  const int failed = lds_cholesky_blocked<(RB >= 8 ? 3 : 2)>(G, dinv, P, r, nrows, pld);
   float* Wi = a.W + i * r;
   if (failed) {
     for (int c = tid; c < r; c += kNT) Wi[c] = 0.0f;
@@ -229,30 +231,131 @@ __global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(Comple
   }
 }
 
+template <int RB>
+__global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(CompleteArgs a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* G = reinterpret_cast<double*>(smem);
+  double* P = G + gsize(a.r);
+  double* dinv = P + kCb * kPanelLd;
+  double* wv = dinv + kRMax;
+  int* ibuf = reinterpret_cast<int*>(wv + kRMax);
+  float* ybuf = reinterpret_cast<float*>(ibuf + kIdx);
+  const int64_t i = blockIdx.x;
+  const int64_t base = a.optr ? a.optr[i] : i * a.k;
+  const int k = a.optr ? static_cast<int>(a.optr[i + 1] - base) : a.k;
+  gram_phase<RB>(a, i, base, k, G, ibuf, ybuf);
+  solve_phase<RB>(a, i, base, k, G, P, kPanelLd, dinv, wv);
+}
+
+// ---------------------------------------------------------------- split form
+// For many columns without residuals the two steps run as two kernels, so
+// that the latency-bound Cholesky does not hold the Gram step's registers and
+// the Gram step does not hold the Cholesky's LDS: the Gram kernel writes
+// G (FP32, rounded once from its exact FP64 sum of the wave partials) and b
+// (FP64) of every column to global memory; the solve kernel needs about
+// 54 KB of LDS at r = 100, three columns per compute unit.
+__host__ __device__ inline int ntri_r(int r) { return r * (r + 1) / 2; }
+__host__ __device__ inline size_t gb_stride(int r) {  // bytes per column: G floats, then b doubles
+  return ((static_cast<size_t>(ntri_r(r)) * sizeof(float) + 7) & ~static_cast<size_t>(7)) +
+         static_cast<size_t>(r) * sizeof(double);
+}
+// Panel rows of r - 15 doubles: the trailing update's 4 x 4 tiles read up to
+// three entries past a row, which land in the next row or in dinv and only
+// feed tile rows that are discarded.  w takes the panel's place once the
+// factorisation is done.  At r = 100 this is 52,896 bytes: three columns per
+// compute unit.
+__host__ __device__ inline int solve_pld(int r) { return r - 15 > 1 ? r - 15 : 1; }
+inline size_t solve_smem(int r) {
+  const size_t pw = static_cast<size_t>(kCb) * solve_pld(r) > static_cast<size_t>(r) ? kCb * solve_pld(r) : r;
+  return (static_cast<size_t>(gsize(r)) + pw + static_cast<size_t>(r) + 4) * sizeof(double);
+}
+inline size_t gram_smem(int r) {
+  return static_cast<size_t>(gsize(r)) * sizeof(double) + kIdx * (sizeof(int) + sizeof(float));
+}
+
+template <int RB>
+__global__ __launch_bounds__(kNT, 2) void complete_gram_kernel(CompleteArgs a, char* gb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* G = reinterpret_cast<double*>(smem);
+  int* ibuf = reinterpret_cast<int*>(G + gsize(a.r));
+  float* ybuf = reinterpret_cast<float*>(ibuf + kIdx);
+  const int64_t i = blockIdx.x;
+  const int64_t base = a.optr ? a.optr[i] : i * a.k;
+  const int k = a.optr ? static_cast<int>(a.optr[i + 1] - base) : a.k;
+  gram_phase<RB>(a, i, base, k, G, ibuf, ybuf);
+  const int r = a.r, nt = ntri_r(r);
+  float* go = reinterpret_cast<float*>(gb + i * gb_stride(r));
+  double* bo = reinterpret_cast<double*>(gb + i * gb_stride(r) + gb_stride(r) - static_cast<size_t>(r) * sizeof(double));
+  for (int t = threadIdx.x; t < nt; t += kNT) go[t] = static_cast<float>(G[t]);  // rows < r are entries [0, nt)
+  for (int c = threadIdx.x; c < r; c += kNT) bo[c] = G[nt + c];                  // row r
+}
+
+template <int RB>
+__global__ __launch_bounds__(kNT, 3) void complete_solve_kernel(CompleteArgs a, const char* gb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const int r = a.r, nt = ntri_r(r), pld = solve_pld(r);
+  double* G = reinterpret_cast<double*>(smem);
+  double* P = G + gsize(r);
+  double* dinv = P + (kCb * pld > r ? kCb * pld : r);
+  double* wv = P;  // the panel is dead once the factorisation is done
+  const int64_t i = blockIdx.x;
+  const int64_t base = a.optr ? a.optr[i] : i * a.k;
+  const int k = a.optr ? static_cast<int>(a.optr[i + 1] - base) : a.k;
+  const float* gi = reinterpret_cast<const float*>(gb + i * gb_stride(r));
+  const double* bi = reinterpret_cast<const double*>(gb + i * gb_stride(r) + gb_stride(r) -
+                                                     static_cast<size_t>(r) * sizeof(double));
+  for (int t = threadIdx.x; t < nt; t += kNT) G[t] = static_cast<double>(gi[t]);
+  for (int c = threadIdx.x; c < r; c += kNT) G[nt + c] = bi[c];
+  __syncthreads();
+  solve_phase<RB>(a, i, base, k, G, P, pld, dinv, wv);
+}
+
 }  // namespace
+
+size_t complete_split_bytes(int64_t L, int r) { return static_cast<size_t>(L > 0 ? L : 1) * gb_stride(r); }
 
 rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, int k, const float* y,
                         const float* Trows, int64_t ldT, const int32_t* trow, int64_t L, float* W, float* resid,
                         int32_t* info, float* wnorm2, hipStream_t s, int32_t* lhead, int32_t* lnext,
-                        const int64_t* optr) {
+                        const int64_t* optr, void* split_ws) {
   if (L == 0) return RPT_OK;
   if (r < 1 || r > kRMax) return RPT_ERR_UNSUPPORTED;
   if (lhead && (!resid || optr || L * static_cast<int64_t>(k) > INT32_MAX)) return RPT_ERR_INVALID_ARG;
   CompleteArgs a{U, v, r, omega, k, y, Trows, ldT, trow, L, W, resid, info, wnorm2, lhead, lnext, optr};
   const int RB = (r + 15) / 16;
-  void* fns[8] = {reinterpret_cast<void*>(&complete_kernel<1>), reinterpret_cast<void*>(&complete_kernel<2>),
-                  reinterpret_cast<void*>(&complete_kernel<3>), reinterpret_cast<void*>(&complete_kernel<4>),
-                  reinterpret_cast<void*>(&complete_kernel<5>), reinterpret_cast<void*>(&complete_kernel<6>),
-                  reinterpret_cast<void*>(&complete_kernel<7>), reinterpret_cast<void*>(&complete_kernel<8>)};
-  void* fn = fns[RB - 1];
+#define RPT_FNS(K) \
+  { reinterpret_cast<void*>(&K<1>), reinterpret_cast<void*>(&K<2>), reinterpret_cast<void*>(&K<3>), \
+    reinterpret_cast<void*>(&K<4>), reinterpret_cast<void*>(&K<5>), reinterpret_cast<void*>(&K<6>), \
+    reinterpret_cast<void*>(&K<7>), reinterpret_cast<void*>(&K<8>) }
+  static void* const fused[8] = RPT_FNS(complete_kernel);
+  static void* const gram[8] = RPT_FNS(complete_gram_kernel);
+  static void* const solve[8] = RPT_FNS(complete_solve_kernel);
+#undef RPT_FNS
   static bool attr_set[8] = {};
   if (!attr_set[RB - 1]) {
-    (void)hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(smem_bytes(kRMax)));
+    (void)hipFuncSetAttribute(fused[RB - 1], hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(smem_bytes(kRMax)));
+    (void)hipFuncSetAttribute(gram[RB - 1], hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(gram_smem(kRMax)));
+    (void)hipFuncSetAttribute(solve[RB - 1], hipFuncAttributeMaxDynamicSharedMemorySize,
+                              static_cast<int>(solve_smem(kRMax)));
     attr_set[RB - 1] = true;
   }
-  void* args[] = {&a};
   RPT_STAGE("complete", s);
-  hipError_t e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(L)), dim3(kNT), args, smem_bytes(r), s);
+  hipError_t e = hipSuccess;
+  if (split_ws && !resid) {
+    char* gb = static_cast<char*>(split_ws);
+    void* ga[] = {&a, &gb};
+    e = hipLaunchKernel(gram[RB - 1], dim3(static_cast<unsigned>(L)), dim3(kNT), ga, gram_smem(r), s);
+    if (e == hipSuccess) {
+      const char* cgb = gb;
+      void* sa[] = {&a, &cgb};
+      e = hipLaunchKernel(solve[RB - 1], dim3(static_cast<unsigned>(L)), dim3(kNT), sa, solve_smem(r), s);
+    }
+  } else {
+    void* args[] = {&a};
+    e = hipLaunchKernel(fused[RB - 1], dim3(static_cast<unsigned>(L)), dim3(kNT), args, smem_bytes(r), s);
+  }
   if (e != hipSuccess) {
     set_hip_error(e);
     return RPT_ERR_HIP;

@@ -151,7 +151,8 @@ constexpr int kPanelLd = 132;  // > 129 rows below a diagonal block, multiple of
 // and carried along unmasked: they are never read by a kept entry and never
 // stored.  G must be followed by at least kCb doubles of readable LDS.
 template <int M, int NS>
-__device__ __forceinline__ int chol_panel(double* G, double* dinv, double* P, int c0, int m, int nrows, int lane_in) {
+__device__ __forceinline__ int chol_panel(double* G, double* dinv, double* P, int c0, int m, int nrows, int lane_in,
+                                          int pld) {
   // the lane index passes through an opaque register move so that the
   // lane-dependent predicates below are formed inside the caller's block loop
   // instead of being hoisted out of it (where they would stay live and spill)
@@ -211,7 +212,7 @@ __device__ __forceinline__ int chol_panel(double* G, double* dinv, double* P, in
 #pragma unroll
       for (int j = 0; j < kCb; ++j) {
         if (j < mm && (s > 0 || j <= lane)) gr[j] = d[s][j];
-        if (j < mm && row >= b0) pr[j * kPanelLd] = d[s][j];
+        if (j < mm && row >= b0) pr[j * pld] = d[s][j];
       }
     }
   }
@@ -221,7 +222,7 @@ __device__ __forceinline__ int chol_panel(double* G, double* dinv, double* P, in
 // Trailing update G[i][j] -= sum_q P[q][i - b0] P[q][j - b0], b0 <= j <= i,
 // j < r, i < nrows, in 4 x 4 tiles.
 template <int M>
-__device__ __forceinline__ void chol_trailing(double* G, const double* P, int b0, int m, int r, int nrows) {
+__device__ __forceinline__ void chol_trailing(double* G, const double* P, int b0, int m, int r, int nrows, int pld) {
   const int nr = nrows - b0, nc = r - b0;
   if (nc <= 0) return;
   const int TR = (nr + 3) >> 2, TC = (nc + 3) >> 2;
@@ -237,7 +238,7 @@ __device__ __forceinline__ void chol_trailing(double* G, const double* P, int b0
 #pragma unroll 4
     for (int q = 0; q < (M ? M : m); ++q) {
       {
-        const double* pq = P + q * kPanelLd;
+        const double* pq = P + q * pld;
         double xi[4], xj[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -267,10 +268,14 @@ __device__ __forceinline__ void chol_trailing(double* G, const double* P, int b0
 // c <= min(i, r - 1)).  On success the leading block holds L (diagonal
 // included), dinv[j] = 1 / L_jj, and every row i >= r holds x_i with
 // L x_i = a_i (for an appended row b^T: z = L^{-1} b).  P is LDS scratch of
-// kCb * kPanelLd doubles.  Returns 0, or j + 1 for the first pivot j that is
-// not positive (same value in every thread; later blocks are not factored).
+// kCb rows of pld doubles, pld >= nrows - kCb (the rows below the first
+// diagonal block); the trailing tiles read up to three entries past a row,
+// which must be readable LDS and feed only discarded tile rows.  Returns 0,
+// or j + 1 for the first pivot j that is not positive (same value in every
+// thread; later blocks are not factored).
 template <int NS>
-__device__ __forceinline__ int lds_cholesky_blocked(double* G, double* dinv, double* P, int r, int nrows) {
+__device__ __forceinline__ int lds_cholesky_blocked(double* G, double* dinv, double* P, int r, int nrows,
+                                                    int pld = kPanelLd) {
   __shared__ int fail;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   if (threadIdx.x == 0) fail = 0;
@@ -284,23 +289,23 @@ __device__ __forceinline__ int lds_cholesky_blocked(double* G, double* dinv, dou
       // c0 made opaque: strength reduction would otherwise carry one address
       // per unrolled panel entry across the loop
       const int cb = __builtin_amdgcn_readfirstlane(c0);
-      const int bad = chol_panel<kCb, NS>(G, dinv, P, cb, kCb, nrows, lane);
+      const int bad = chol_panel<kCb, NS>(G, dinv, P, cb, kCb, nrows, lane, pld);
       if (lane == 0 && bad) fail = bad;
     }
     __syncthreads();
     if (fail) return fail;
-    chol_trailing<kCb>(G, P, c0 + kCb, kCb, r, nrows);
+    chol_trailing<kCb>(G, P, c0 + kCb, kCb, r, nrows, pld);
   }
   if (c0 < r) {
     const int m = r - c0;
     __syncthreads();
     if (wave == 0) {
-      const int bad = chol_panel<0, NS>(G, dinv, P, c0, m, nrows, lane);
+      const int bad = chol_panel<0, NS>(G, dinv, P, c0, m, nrows, lane, pld);
       if (lane == 0 && bad) fail = bad;
     }
     __syncthreads();
     if (fail) return fail;
-    chol_trailing<0>(G, P, c0 + m, m, r, nrows);
+    chol_trailing<0>(G, P, c0 + m, m, r, nrows, pld);
   }
   __syncthreads();
   return 0;

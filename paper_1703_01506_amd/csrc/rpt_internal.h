@@ -6,6 +6,8 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include "rpt.h"
 
 namespace rpt {
@@ -186,12 +188,27 @@ rpt_status sampled_launch(const PrepX& p, const uint8_t* labels, int64_t L, cons
                           const float* Tsrc, float* y, hipStream_t s,
                           const int64_t* optr = nullptr);
 
+// The per-device second stream (streams.hip) and its events; `to` waits for
+// everything enqueued on `from` so far.  side_stream returns null when the
+// stream cannot be created (or is first asked for during graph capture).
+struct SideStream {
+  bool ok = false;
+  hipStream_t st = nullptr;
+  hipEvent_t fork = nullptr, mid = nullptr, join = nullptr;
+  std::mutex mu;
+};
+SideStream* side_stream(hipStream_t s);
+rpt_status stream_wait(SideStream* sd, hipEvent_t ev, hipStream_t from, hipStream_t to);
+
 // Complete (Gram + FP64 Cholesky + solve).  The sampled values come either from
 // y ([L][k]) or, when y is null, from rows of T: y[i][q] = Trows[i * ldT + omega[i][q]].
+// With split_ws (complete_split_bytes(L, r) bytes) and no residual, the Gram
+// step and the solve run as two kernels with the Gram matrices in split_ws.
+size_t complete_split_bytes(int64_t L, int r);
 rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, int k, const float* y,
                         const float* Trows, int64_t ldT, const int32_t* trow, int64_t L, float* W, float* resid,
                         int32_t* info, float* wnorm2, hipStream_t s, int32_t* lhead = nullptr,
-                        int32_t* lnext = nullptr, const int64_t* optr = nullptr);
+                        int32_t* lnext = nullptr, const int64_t* optr = nullptr, void* split_ws = nullptr);
 
 // Reconstruction filter + exact refine with noise (K7).
 size_t recon_bytes(int64_t v, int64_t L, int r);
