@@ -32,9 +32,16 @@ sys.path.insert(0, ROOT)
 METRIC = "max-null permutations/s, n=100 v=250k: RapidPT vs NaivePT on GPU, KL<1e-3"
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak
 PEAK_HBM_GBS = 8000.0
+PEAK_FP64_TFLOPS = 78.6        # vector FP64
+# 32 x 32 -> 64-bit integer products: a wave64 v_mad_u64_u32 occupies a SIMD
+# for 16 cycles (quarter rate), so 256 CUs x 4 SIMDs x 64 lanes / 16 x 2.4 GHz
+PEAK_MUL64_G = 256 * 4 * 64 / 16 * 2.4
+PHILOX_MULS_PER_NORMAL = 5     # Philox4x32-10: 2 products x 10 rounds per call, 4 normals per call
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rapidpt_step_n100_v250k_hbm_traffic.md")
-STAGE_KERNEL = {"complete": "complete_kernel", "recon_fused": "recon_fused_kernel",
-                "naive_contract": "naive_split_kernel", "sampled_t": "sampled_kernel"}
+STAGE_KERNEL = {"complete": "complete_kernel", "complete_gram": "complete_gram_kernel",
+                "complete_solve": "complete_solve_kernel", "recon_fused": "recon_fused_kernel",
+                "naive_contract": "naive_max_kernel", "sampled_t": "sampled_kernel",
+                "track_update": "track_apply_kernel"}
 
 
 def log(msg):
@@ -170,8 +177,13 @@ def main():
                   "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s", "kernel": "naive_contract",
                   "avg_launch_ms": naive_avg_ms}
     naive_roof["frac"] = naive_roof["achieved"] / naive_roof["peak"]
-    naive_roof["traffic"] = None   # counters were taken on the T-storing training launch, not this one
+    naive_roof["traffic"] = measured_traffic("naive_contract")
+    naive_roof["traffic_unit"] = "bytes per launch"
     roof = roofline_for(dom, tot[dom], launches[dom], v, n, L, ell, r, k, P)
+    others = {}
+    for s_ in ("complete", "complete_gram", "complete_solve", "recon_fused", "reorth", "track_update"):
+        if s_ in tot and s_ != dom:
+            others[s_] = roofline_for(s_, tot[s_], launches[s_], v, n, L, ell, r, k, P)
 
     from oracle import metrics as OM
     hn, nvn = h.cpu().numpy(), nv.cpu().numpy()
@@ -192,6 +204,7 @@ def main():
                                f"r={r}, eta=0.35% ({k} voxels), {P} tracking passes",
                    "n": n, "v": v, "L": L, "l": ell, "r": r, "eta_ppm": eta_ppm, "passes": P},
         "roofline": roof,
+        "rooflines_other_stages": others,
         "cpu_baseline": cpu,
         "naivept": {"value": L / (nwall / a.steps), "unit": "perms/s", "ms_per_step": naive_ms,
                     "roofline": naive_roof},
@@ -233,20 +246,41 @@ def roofline_for(stage, ms_per_step, launches_per_step, v, n, L, ell, r, k, P):
     out = {"kernel": stage, "avg_launch_ms": avg_s * 1e3, "launches_per_step": launches_per_step,
            "traffic": measured_traffic(stage), "traffic_unit": "bytes per launch"}
     if stage == "complete":
-        # columns solved per step: P passes over l, the sigma/mu pass, the recovery;
-        # each gathers k basis rows (4r bytes), k indices and k values, writes r coefficients
-        cols = P * ell + ell + Lr
-        byts = cols * (4.0 * k * r + 8.0 * k + 4.0 * r) / launches_per_step
+        # the fused kernel solves the training columns: P passes over l and the
+        # sigma/mu pass; each gathers k basis rows (4r bytes), k indices and k
+        # values, and writes r coefficients and k residuals
+        cols = P * ell + ell
+        byts = cols * (4.0 * k * r + 12.0 * k + 4.0 * r) / launches_per_step
         ach = byts / avg_s / 1e9
         out.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": ach / PEAK_HBM_GBS, "algorithmic_bytes_per_launch": byts})
         return out
-    if stage == "recon_fused":
-        # U W for the training (mean gap) and recovered columns, 3 split passes, 2 flops per MAC
-        flops = 3 * 2.0 * v * r * (ell + Lr) / launches_per_step
+    if stage == "complete_gram":
+        # recovered columns: k gathered basis rows, k indices and values in;
+        # the Gram matrix (FP32 lower triangle) and b (FP64) out
+        byts = Lr * (4.0 * k * r + 8.0 * k + 4.0 * r * (r + 1) / 2 + 8.0 * r) / launches_per_step
+        ach = byts / avg_s / 1e9
+        out.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": ach / PEAK_HBM_GBS, "algorithmic_bytes_per_launch": byts})
+        return out
+    if stage == "complete_solve":
+        # FP64 Cholesky (r^3/3 multiply-adds) and two triangular solves (r^2)
+        # per recovered column, 2 flops per multiply-add; bound in practice by
+        # the dependent chain of each panel, not by this peak
+        flops = Lr * 2.0 * (r ** 3 / 3.0 + r * r) / launches_per_step
         ach = flops / avg_s / 1e12
-        out.update({"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
-                    "frac": ach / PEAK_BF16_TFLOPS, "algorithmic_flops_per_launch": flops})
+        out.update({"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s (fp64)",
+                    "frac": ach / PEAK_FP64_TFLOPS, "algorithmic_flops_per_launch": flops})
+        return out
+    if stage == "recon_fused":
+        # every voxel of every training and recovered column draws its normal
+        # (sigma ~ 0.95 leaves nothing to prune); the Philox multiplies bound it
+        normals = v * (ell + Lr) / launches_per_step
+        ach = normals / avg_s / 1e9
+        peak = PEAK_MUL64_G / PHILOX_MULS_PER_NORMAL
+        out.update({"bound": "alu", "achieved": ach, "peak": peak, "unit": "Gnormal/s",
+                    "frac": ach / peak, "algorithmic_normals_per_launch": normals,
+                    "mfma_tflops": 3 * 2.0 * v * r * (ell + Lr) / launches_per_step / avg_s / 1e12})
         return out
     if stage == "reorth":
         byts = 3 * 4.0 * v * r   # read U twice (Gram, apply), write it once

@@ -341,18 +341,22 @@ rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, 
                               static_cast<int>(solve_smem(kRMax)));
     attr_set[RB - 1] = true;
   }
-  RPT_STAGE("complete", s);
   hipError_t e = hipSuccess;
   if (split_ws && !resid) {
     char* gb = static_cast<char*>(split_ws);
+    const char* cgb = gb;
     void* ga[] = {&a, &gb};
-    e = hipLaunchKernel(gram[RB - 1], dim3(static_cast<unsigned>(L)), dim3(kNT), ga, gram_smem(r), s);
+    void* sa[] = {&a, &cgb};
+    {
+      RPT_STAGE("complete_gram", s);
+      e = hipLaunchKernel(gram[RB - 1], dim3(static_cast<unsigned>(L)), dim3(kNT), ga, gram_smem(r), s);
+    }
     if (e == hipSuccess) {
-      const char* cgb = gb;
-      void* sa[] = {&a, &cgb};
+      RPT_STAGE("complete_solve", s);
       e = hipLaunchKernel(solve[RB - 1], dim3(static_cast<unsigned>(L)), dim3(kNT), sa, solve_smem(r), s);
     }
   } else {
+    RPT_STAGE("complete", s);
     void* args[] = {&a};
     e = hipLaunchKernel(fused[RB - 1], dim3(static_cast<unsigned>(L)), dim3(kNT), args, smem_bytes(r), s);
   }

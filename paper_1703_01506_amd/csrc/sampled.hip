@@ -2,11 +2,13 @@
 // y[i, q] = t statistic of voxel omega[i, q] under relabelling i (sampled
 // sets of k voxels per relabelling, or uneven sets in CSR form).
 //
-// One workgroup per relabelling: the group-1 indicator goes to LDS, each thread
-// takes sampled rows, reads the standardised row (prep.hip, 16-byte aligned)
-// with 16-byte loads and forms the group-1 sum (and sum of squares for
-// unbalanced designs) in FP32.  The balanced statistic uses the same scaled
-// contrast u as NaivePT; unbalanced designs evaluate Eq. 2 directly.
+// One workgroup per relabelling: the group-1 indicator goes to LDS; 32 lanes
+// share one sampled row (prep.hip's standardised row, 16-byte aligned), each
+// reading 16 consecutive bytes of it, so a row costs its own cache lines
+// once; four rows per lane group are in flight at a time.  The group-1 sum
+// (and sum of squares for unbalanced designs) is reduced across the 32 lanes
+// in FP32.  The balanced statistic uses the same scaled contrast u as
+// NaivePT; unbalanced designs evaluate Eq. 2 directly.
 #include "rpt_internal.h"
 
 namespace rpt {
@@ -28,46 +30,65 @@ struct SampledArgs {
   float fs, tm;
 };
 
+constexpr int kRowLanes = 32;  // lanes sharing one sampled row (ldn <= 4 * 32)
+constexpr int kRowsInFlight = 4;
+
+__device__ __forceinline__ float t_of(const SampledArgs& a, int64_t vox, float s1, float q1) {
+  if (2 * a.n1 == a.n) {
+    const float2 c2 = a.cst[vox];
+    return t_from_u_f(fmaf(s1, c2.x, c2.y), a.fs, a.tm);
+  }
+  const int n1 = a.n1, n2 = a.n - a.n1;
+  const float2 sq = a.cstg[vox];
+  const float S2 = sq.x - s1, Q2 = sq.y - q1;
+  const float m1 = s1 / n1, m2 = S2 / n2;
+  const float v1 = fmaxf((q1 - s1 * m1) / (n1 - 1), 0.0f), v2 = fmaxf((Q2 - S2 * m2) / (n2 - 1), 0.0f);
+  const float den2 = v1 / n1 + v2 / n2;
+  return den2 > 0.0f ? (m1 - m2) * rsqrtf(den2) : 0.0f;
+}
+
 __global__ __launch_bounds__(kBlock) void sampled_kernel(SampledArgs a) {
-  __shared__ float lab[kBlock];
+  __shared__ __align__(16) float lab[kBlock];
   const int64_t i = blockIdx.x;
   const int tid = threadIdx.x;
   for (int j = tid; j < a.ldn; j += kBlock) lab[j] = (j < a.n && a.labels[i * a.n + j]) ? 1.0f : 0.0f;
   __syncthreads();
   const bool unbal = 2 * a.n1 != a.n;
-  const int n1 = a.n1, n2 = a.n - a.n1;
   const int64_t base = a.optr ? a.optr[i] : i * a.k;
   const int ki = a.optr ? static_cast<int>(a.optr[i + 1] - base) : a.k;
-  for (int q = tid; q < ki; q += kBlock) {
-    const int64_t vox = a.omega[base + q];
-    if (vox < 0 || vox >= a.v) {  // out-of-range index: no statistic
-      a.y[base + q] = NAN;
-      continue;
-    }
-    const f32x4* row = reinterpret_cast<const f32x4*>(a.rows + vox * a.ldn);
-    float s1 = 0.0f, q1 = 0.0f;
-    for (int j4 = 0; j4 < a.ldn / 4; ++j4) {
-      const f32x4 x = row[j4];
+  const int gl = tid & (kRowLanes - 1);  // lane within the row group
+  const int grp = tid / kRowLanes;       // row group of the workgroup
+  constexpr int kGroups = kBlock / kRowLanes;
+  const bool on = 4 * gl < a.ldn;
+  f32x4 l4{0.f, 0.f, 0.f, 0.f};
+  if (on) l4 = *reinterpret_cast<const f32x4*>(lab + 4 * gl);
+  for (int q0 = 0; q0 < ki; q0 += kGroups * kRowsInFlight) {
+    int64_t vox[kRowsInFlight];
+    f32x4 x[kRowsInFlight];
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const float l = lab[4 * j4 + e];
-        s1 = fmaf(x[e], l, s1);
-        if (unbal) q1 = fmaf(x[e] * x[e], l, q1);
+    for (int e = 0; e < kRowsInFlight; ++e) {
+      const int q = q0 + e * kGroups + grp;
+      vox[e] = q < ki ? a.omega[base + q] : -1;
+      const bool ok = on && vox[e] >= 0 && vox[e] < a.v;
+      x[e] = ok ? *reinterpret_cast<const f32x4*>(a.rows + vox[e] * a.ldn + 4 * gl) : f32x4{0.f, 0.f, 0.f, 0.f};
+    }
+#pragma unroll
+    for (int e = 0; e < kRowsInFlight; ++e) {
+      float s1 = 0.0f, q1 = 0.0f;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        s1 = fmaf(x[e][c], l4[c], s1);
+        if (unbal) q1 = fmaf(x[e][c] * x[e][c], l4[c], q1);
       }
+#pragma unroll
+      for (int off = kRowLanes / 2; off > 0; off >>= 1) {
+        s1 += __shfl_xor(s1, off, kRowLanes);
+        if (unbal) q1 += __shfl_xor(q1, off, kRowLanes);
+      }
+      const int q = q0 + e * kGroups + grp;
+      if (gl == 0 && q < ki)
+        a.y[base + q] = (vox[e] < 0 || vox[e] >= a.v) ? NAN : t_of(a, vox[e], s1, q1);  // out of range: no statistic
     }
-    float t;
-    if (!unbal) {
-      const float2 c2 = a.cst[vox];
-      t = t_from_u_f(fmaf(s1, c2.x, c2.y), a.fs, a.tm);
-    } else {
-      const float2 sq = a.cstg[vox];
-      const float S2 = sq.x - s1, Q2 = sq.y - q1;
-      const float m1 = s1 / n1, m2 = S2 / n2;
-      const float v1 = fmaxf((q1 - s1 * m1) / (n1 - 1), 0.0f), v2 = fmaxf((Q2 - S2 * m2) / (n2 - 1), 0.0f);
-      const float den2 = v1 / n1 + v2 / n2;
-      t = den2 > 0.0f ? (m1 - m2) * rsqrtf(den2) : 0.0f;
-    }
-    a.y[base + q] = t;
   }
 }
 
@@ -77,7 +98,7 @@ rpt_status sampled_launch(const PrepX& p, const uint8_t* labels, int64_t L, cons
                           const float* Tsrc, float* y, hipStream_t s, const int64_t* optr) {
   (void)Tsrc;
   if (L == 0 || (k == 0 && !optr)) return RPT_OK;
-  if (p.ldn > kBlock) return RPT_ERR_UNSUPPORTED;
+  if (p.ldn > 4 * kRowLanes) return RPT_ERR_UNSUPPORTED;
   SampledArgs a;
   a.v = p.v;
   a.rows = p.rows;
