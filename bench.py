@@ -33,10 +33,15 @@ METRIC = "max-null permutations/s, n=100 v=250k: RapidPT vs NaivePT on GPU, KL<1
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6        # vector FP64
-# 32 x 32 -> 64-bit integer products: a wave64 v_mad_u64_u32 occupies a SIMD
-# for 16 cycles (quarter rate), so 256 CUs x 4 SIMDs x 64 lanes / 16 x 2.4 GHz
-PEAK_MUL64_G = 256 * 4 * 64 / 16 * 2.4
-PHILOX_MULS_PER_NORMAL = 5     # Philox4x32-10: 2 products x 10 rounds per call, 4 normals per call
+# VALU issue bound of the noise draw.  One Philox4x32-10 call (4 normals):
+# 20 products (v_mad_u64_u32) and 20 three-input XORs, full rate (4 cycles per
+# wave64 instruction on a SIMD); Box-Muller: 12 ops for the four uniforms, 2
+# scalings and 4 products, full rate, and 8 transcendentals (log, sqrt, sin,
+# cos twice), quarter rate (16 cycles); then 2 full-rate ops per normal (the
+# noise FMA and the running max).  66 x 4 + 8 x 16 = 392 SIMD cycles per 64
+# calls, 98 per 64 normals: 1,024 SIMDs x 2.4 GHz x 64 / 98.
+NOISE_SIMD_CYCLES_PER_64_NORMALS = 98
+PEAK_NOISE_GNORMALS = 1024 * 2.4 * 64 / NOISE_SIMD_CYCLES_PER_64_NORMALS
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rapidpt_step_n100_v250k_hbm_traffic.md")
 STAGE_KERNEL = {"complete": "complete_kernel", "complete_gram": "complete_gram_kernel",
                 "complete_solve": "complete_solve_kernel", "recon_fused": "recon_fused_kernel",
@@ -274,10 +279,10 @@ def roofline_for(stage, ms_per_step, launches_per_step, v, n, L, ell, r, k, P):
         return out
     if stage == "recon_fused":
         # every voxel of every training and recovered column draws its normal
-        # (sigma ~ 0.95 leaves nothing to prune); the Philox multiplies bound it
+        # (sigma ~ 0.95 leaves nothing to prune): bound by VALU issue
         normals = v * (ell + Lr) / launches_per_step
         ach = normals / avg_s / 1e9
-        peak = PEAK_MUL64_G / PHILOX_MULS_PER_NORMAL
+        peak = PEAK_NOISE_GNORMALS
         out.update({"bound": "alu", "achieved": ach, "peak": peak, "unit": "Gnormal/s",
                     "frac": ach / peak, "algorithmic_normals_per_launch": normals,
                     "mfma_tflops": 3 * 2.0 * v * r * (ell + Lr) / launches_per_step / avg_s / 1e12})

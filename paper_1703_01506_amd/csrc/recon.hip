@@ -27,6 +27,40 @@ namespace {
 constexpr int kRMaxRefine = 128;  // basis rank held in LDS by the refine
 
 // ---------------------------------------------------------------- Philox4x32-10
+// a ^ b ^ k in one instruction: gfx950's three-input bitwise op with the XOR
+// truth table (0x96); the compiler emits two v_xor_b32 for it.  The round key
+// k is uniform and goes in as the one scalar operand.
+__device__ __forceinline__ unsigned xor3(unsigned a, unsigned b, unsigned k) {
+  unsigned r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+  return r;
+}
+
+// NC independent counters advanced round by round together, so that the
+// dependent product -> xor chain of one call overlaps the others'
+template <int NC>
+__device__ __forceinline__ void philox4x32_10_n(unsigned (&c)[NC][4], unsigned k0, unsigned k1) {
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    if (rnd > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+#pragma unroll
+    for (int q = 0; q < NC; ++q) {
+      const uint64_t p0 = static_cast<uint64_t>(0xD2511F53u) * c[q][0];
+      const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c[q][2];
+      const unsigned lo0 = static_cast<unsigned>(p0), hi0 = static_cast<unsigned>(p0 >> 32);
+      const unsigned lo1 = static_cast<unsigned>(p1), hi1 = static_cast<unsigned>(p1 >> 32);
+      const unsigned n0 = xor3(hi1, c[q][1], k0), n2 = xor3(hi0, c[q][3], k1);
+      c[q][0] = n0;
+      c[q][1] = lo1;
+      c[q][2] = n2;
+      c[q][3] = lo0;
+    }
+  }
+}
+
 __device__ __forceinline__ void philox4x32_10(unsigned c[4], unsigned k0, unsigned k1) {
 #pragma unroll
   for (int rnd = 0; rnd < 10; ++rnd) {
@@ -38,7 +72,7 @@ __device__ __forceinline__ void philox4x32_10(unsigned c[4], unsigned k0, unsign
     const uint64_t p1 = static_cast<uint64_t>(0xCD9E8D57u) * c[2];
     const unsigned lo0 = static_cast<unsigned>(p0), hi0 = static_cast<unsigned>(p0 >> 32);
     const unsigned lo1 = static_cast<unsigned>(p1), hi1 = static_cast<unsigned>(p1 >> 32);
-    const unsigned n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    const unsigned n0 = xor3(hi1, c[1], k0), n2 = xor3(hi0, c[3], k1);
     c[0] = n0;
     c[1] = lo1;
     c[2] = n2;
@@ -403,26 +437,48 @@ __global__ __launch_bounds__(kBlock) void recon_fused_kernel(FusedArgs a) {
       }
     const int64_t vox = t * 32 + col;
     const bool ok = vox < a.v;
+    if (ALIGNED) {
 #pragma unroll
-    for (int p = 0; p < PT; ++p)
+      for (int p = 0; p < PT; ++p) {
+        // the four calls of this column block, advanced together
+        unsigned c[4][4];
 #pragma unroll
-      for (int m = 0; m < 4; ++m) {
-        const int64_t g = a.col0 + pbase + p * 32 + 8 * m + 4 * h;  // column of register 4m
-        float z[4];
-        if (ALIGNED) {
-          unsigned c[4] = {static_cast<unsigned>(vox), static_cast<unsigned>(g >> 2), a.stream, a.study};
-          philox4x32_10(c, k0, k1);
-          box_muller4(c, z);
-        } else {
-#pragma unroll
-          for (int jj = 0; jj < 4; ++jj) z[jj] = noise_z(a.seed, a.stream, static_cast<unsigned>(g + jj), vox, a.study);
+        for (int m = 0; m < 4; ++m) {
+          const int64_t g = a.col0 + pbase + p * 32 + 8 * m + 4 * h;  // column of register 4m
+          c[m][0] = static_cast<unsigned>(vox);
+          c[m][1] = static_cast<unsigned>(g >> 2);
+          c[m][2] = a.stream;
+          c[m][3] = a.study;
         }
+        philox4x32_10_n<4>(c, k0, k1);
 #pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const float val = fmaf(sigma, z[jj], acc[p][4 * m + jj]);
-          rm[p][4 * m + jj] = ok ? fmaxf(rm[p][4 * m + jj], val) : rm[p][4 * m + jj];
+        for (int m = 0; m < 4; ++m) {
+          float z[4];
+          box_muller4(c[m], z);
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            const float val = fmaf(sigma, z[jj], acc[p][4 * m + jj]);
+            rm[p][4 * m + jj] = ok ? fmaxf(rm[p][4 * m + jj], val) : rm[p][4 * m + jj];
+          }
         }
       }
+    } else {
+#pragma unroll
+      for (int p = 0; p < PT; ++p)
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+          const int64_t g = a.col0 + pbase + p * 32 + 8 * m + 4 * h;  // column of register 4m
+          float z[4];
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj)
+            z[jj] = noise_z(a.seed, a.stream, static_cast<unsigned>(g + jj), vox, a.study);
+#pragma unroll
+          for (int jj = 0; jj < 4; ++jj) {
+            const float val = fmaf(sigma, z[jj], acc[p][4 * m + jj]);
+            rm[p][4 * m + jj] = ok ? fmaxf(rm[p][4 * m + jj], val) : rm[p][4 * m + jj];
+          }
+        }
+    }
   };
   if (t0 < t1) load(Bc, t0);
   for (int64_t t = t0; t < t1; t += 2) {
@@ -525,7 +581,7 @@ ReconPlan recon_plan(int64_t v, int64_t L, int r, int pt) {
   return pl;
 }
 
-constexpr int kFilterPT = 4, kFusedPT = 2;
+constexpr int kFilterPT = 4, kFusedPT = 1;
 
 void recon_carve(Carver& c, int64_t v, int64_t L, int r, uint16_t** ukb, float** smax, float** partial,
                  unsigned** umax, int** path) {
