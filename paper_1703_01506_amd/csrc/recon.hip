@@ -368,7 +368,10 @@ __device__ __forceinline__ void box_muller4(const unsigned c[4], float z[4]) {
 }
 
 template <int KS, int PT, bool ALIGNED>
-__global__ __launch_bounds__(kBlock) void recon_fused_kernel(FusedArgs a) {
+__global__ __launch_bounds__(kBlock, ALIGNED ? 3 : 2) void recon_fused_kernel(FusedArgs a) {
+  __shared__ __align__(16) uint16_t us[2][KS][2][64 * 8];
+  typedef __attribute__((address_space(3))) void lds_void;
+  typedef const __attribute__((address_space(1))) void gbl_void;
   if (*a.path != 0) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, col = lane & 31;
   const int b = blockIdx.x, xcd = b & 7, j = b >> 3;
@@ -414,27 +417,36 @@ __global__ __launch_bounds__(kBlock) void recon_fused_kernel(FusedArgs a) {
   const int64_t t0 = static_cast<int64_t>(chunk) * a.tpc;
   const int64_t t1 = t0 + a.tpc < a.vt ? t0 + a.tpc : a.vt;
   const size_t kstride = static_cast<size_t>(a.vpad) * 32;
-  u32x4 Bc[2 * KS], Bn[2 * KS];
-  auto load = [&](u32x4* B, int64_t t) {
-    const uint16_t* bp = a.ukb + static_cast<size_t>(t * 32 + col) * 32 + h * 8;
+  // The U tile of the current 32 voxels is shared by the four waves: it is
+  // copied once per workgroup into LDS (double-buffered, global_load_lds),
+  // already permuted so that lane l's 16-byte fragment sits at 16 l, and each
+  // wave reads its fragments right before the products.
+  auto issue = [&](int b, int64_t t) {
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      B[2 * s] = *reinterpret_cast<const u32x4*>(bp + s * kstride);
-      B[2 * s + 1] = *reinterpret_cast<const u32x4*>(bp + s * kstride + 16);
+    for (int j = 0; j < 2 * KS; j += 4) {
+      const int jj = j + wave;
+      if (jj < 2 * KS) {
+        const int s = jj >> 1, hl = jj & 1;
+        const uint16_t* g = a.ukb + s * kstride + static_cast<size_t>(t * 32 + col) * 32 + hl * 16 + h * 8;
+        __builtin_amdgcn_global_load_lds((gbl_void*)g, (lds_void*)&us[b][s][hl][0], 16, 0, 0);
+      }
     }
   };
-  auto body = [&](const u32x4* B, int64_t t) {
+  auto body = [&](int b, int64_t t) {
     f32x16 acc[PT];
 #pragma unroll
     for (int p = 0; p < PT; ++p) acc[p] = f32x16{};
 #pragma unroll
-    for (int s = 0; s < KS; ++s)
+    for (int s = 0; s < KS; ++s) {
+      const u32x4 bh = *reinterpret_cast<const u32x4*>(&us[b][s][0][lane * 8]);
+      const u32x4 bl = *reinterpret_cast<const u32x4*>(&us[b][s][1][lane * 8]);
 #pragma unroll
       for (int p = 0; p < PT; ++p) {
-        acc[p] = mfma_bf16(Ah[p][s], B[2 * s], acc[p]);
-        acc[p] = mfma_bf16(Ah[p][s], B[2 * s + 1], acc[p]);
-        acc[p] = mfma_bf16(Al[p][s], B[2 * s], acc[p]);
+        acc[p] = mfma_bf16(Ah[p][s], bh, acc[p]);
+        acc[p] = mfma_bf16(Ah[p][s], bl, acc[p]);
+        acc[p] = mfma_bf16(Al[p][s], bh, acc[p]);
       }
+    }
     const int64_t vox = t * 32 + col;
     const bool ok = vox < a.v;
     if (ALIGNED) {
@@ -480,13 +492,15 @@ __global__ __launch_bounds__(kBlock) void recon_fused_kernel(FusedArgs a) {
         }
     }
   };
-  if (t0 < t1) load(Bc, t0);
-  for (int64_t t = t0; t < t1; t += 2) {
-    if (t + 1 < t1) load(Bn, t + 1);
-    body(Bc, t);
-    if (t + 1 >= t1) break;
-    if (t + 2 < t1) load(Bc, t + 2);
-    body(Bn, t + 1);
+  if (t0 < t1) issue(0, t0);
+  for (int64_t t = t0; t < t1; ++t) {
+    const int b = static_cast<int>((t - t0) & 1);
+    // this wave's copies of tile t have landed; after the barrier every
+    // wave's have, and every wave is done reading tile t - 1's buffer
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
+    if (t + 1 < t1) issue(b ^ 1, t + 1);
+    body(b, t);
   }
 #pragma unroll
   for (int p = 0; p < PT; ++p)
