@@ -1,6 +1,7 @@
 // Per-stage timing: while enabled, every kernel stage records a pair of HIP
 // events on the caller's stream; queries wait for those events and sum their
-// elapsed times.  Off by default (no events are created when disabled).
+// elapsed times.  Off by default (no events are created when disabled);
+// events are pooled and reused after a reset.
 #include <map>
 #include <mutex>
 #include <string>
@@ -15,30 +16,38 @@ namespace {
 std::mutex g_mu;
 bool g_on = false;
 std::map<std::string, std::vector<std::pair<hipEvent_t, hipEvent_t>>> g_ev;
+std::vector<hipEvent_t> g_pool;  // events of earlier rounds, reused (creating one is not cheap)
+
+hipEvent_t take_event() {  // caller holds g_mu
+  if (!g_pool.empty()) {
+    hipEvent_t e = g_pool.back();
+    g_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  return hipEventCreate(&e) == hipSuccess ? e : nullptr;
+}
 }  // namespace
 
 StageScope::StageScope(const char* name, hipStream_t s) : name_(name), s_(s), start_(nullptr) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return;
-  if (hipEventCreate(&start_) != hipSuccess) {
-    start_ = nullptr;
-    return;
-  }
-  if (hipEventRecord(start_, s_) != hipSuccess) {
-    (void)hipEventDestroy(start_);
+  start_ = take_event();
+  if (start_ && hipEventRecord(start_, s_) != hipSuccess) {
+    g_pool.push_back(start_);
     start_ = nullptr;
   }
 }
 
 StageScope::~StageScope() {
   if (!start_) return;
-  hipEvent_t end = nullptr;
-  if (hipEventCreate(&end) != hipSuccess || hipEventRecord(end, s_) != hipSuccess) {
-    (void)hipEventDestroy(start_);
-    if (end) (void)hipEventDestroy(end);
+  std::lock_guard<std::mutex> lk(g_mu);
+  hipEvent_t end = take_event();
+  if (!end || hipEventRecord(end, s_) != hipSuccess) {
+    g_pool.push_back(start_);
+    if (end) g_pool.push_back(end);
     return;
   }
-  std::lock_guard<std::mutex> lk(g_mu);
   g_ev[name_].emplace_back(start_, end);
 }
 
@@ -58,8 +67,8 @@ void rpt_timing_reset(void) {
   for (auto& kv : g_ev)
     for (auto& pr : kv.second) {
       (void)hipEventSynchronize(pr.second);
-      (void)hipEventDestroy(pr.first);
-      (void)hipEventDestroy(pr.second);
+      g_pool.push_back(pr.first);
+      g_pool.push_back(pr.second);
     }
   g_ev.clear();
 }
