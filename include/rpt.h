@@ -114,8 +114,10 @@ int rpt_timing_stages(char* buf, size_t len);
  *   max_out  L FP32                                            (out)
  *   T_out    NULL, or L x v FP32: the full permutation testing matrix,
  *            row i = t map of relabelling i (for tests and training)   (out)
- * Requirements: v >= 1, 4 <= n <= 128, 2 <= n1 <= n-2, L >= 0.
- * n1 != n - n1 (unbalanced designs) needs prec == RPT_FP32.
+ * Requirements: v >= 1, 4 <= n <= 512, 2 <= n1 <= n-2, L >= 0.
+ * n1 != n - n1 (unbalanced designs) needs prec == RPT_FP32; RPT_FP32 takes
+ * n <= 128 (RPT_ERR_UNSUPPORTED above).  The subject limit n <= 512 applies
+ * to every entry point that takes X.
  * ------------------------------------------------------------------------- */
 size_t rpt_naive_workspace(int64_t v, int32_t n, int64_t L, int prec);
 rpt_status rpt_naive_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
@@ -313,7 +315,7 @@ rpt_status rpt_recover_maxnull_batched(const rpt_study* studies, int32_t n_studi
  * rpt_observed_tstat: t of Eq. 2 (reading: unbiased group variances) for
  *   every voxel under the observed labelling, group 1 = subjects 0..n1-1 of
  *   X (v x n FP32, row stride ldx), into t_out [v] FP32.  Workspace from
- *   rpt_observed_tstat_workspace (256-byte aligned).  4 <= n <= 128,
+ *   rpt_observed_tstat_workspace (256-byte aligned).  4 <= n <= 512,
  *   2 <= n1 <= n - 2.
  * rpt_fwer_threshold: *thr_out (device FP32) = the ascending order statistic
  *   m_(L - floor(alpha L)) (1-based) of maxima [L]: the level-alpha

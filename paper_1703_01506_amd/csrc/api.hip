@@ -17,7 +17,7 @@ bool ws_ok(const void* ws, size_t have, size_t need) {
 }
 
 bool design_ok(int64_t v, int32_t n, int64_t ldx, int32_t n1) {
-  return v >= 1 && n >= 4 && n <= 128 && ldx >= n && n1 >= 2 && n1 <= n - 2;
+  return v >= 1 && n >= 4 && n <= 512 && ldx >= n && n1 >= 2 && n1 <= n - 2;
 }
 
 int naive_flags(int prec, bool unbal) {
@@ -65,6 +65,7 @@ rpt_status rpt_naive_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, 
   if (L > 0 && (!X || !labels || (!max_out && !T_out))) return RPT_ERR_INVALID_ARG;
   const bool unbal = 2 * n1 != n;
   if (unbal && prec != RPT_FP32) return RPT_ERR_UNSUPPORTED;
+  if (prec == RPT_FP32 && n > 128) return RPT_ERR_UNSUPPORTED;  // FP32 path: fragments for up to 128 subjects
   if (!ws_ok(ws, ws_bytes, rpt_naive_workspace(v, n, L, prec))) return RPT_ERR_WORKSPACE;
   if (L == 0) return RPT_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);

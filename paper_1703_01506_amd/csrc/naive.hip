@@ -266,6 +266,148 @@ __global__ __launch_bounds__(kBlock, 2) void naive_max_kernel(NaiveArgs a) {
 }
 
 // ----------------------------------------------------------------------------
+// split-BF16, balanced, more than 128 subjects (up to 512: 32 K steps).  The
+// K steps are taken kWideKC at a time: each 32-voxel tile's chunk of K steps
+// (hi and lo, 2 KB per step) is copied once per workgroup into LDS with
+// global_load_lds, double-buffered over the (tile, chunk) sequence.  The
+// indicator of a wave's relabellings is kept in LDS as bits, eight subjects per
+// byte, and expanded to a BF16 fragment when it is used: two indicator bits
+// x become the 32-bit pair ((x | x << 15) & 0x10001) * 0x3F80.  Relabellings
+// are the MFMA rows (A operand), voxels the columns; the same kernel keeps
+// running maxima and, in STORE mode, writes t for every element.
+constexpr int kWideKC = 8;      // K steps per staged chunk
+constexpr int kWideNMax = 512;  // subjects
+
+__device__ __forceinline__ u32x4 indicator_frag(unsigned byte) {
+  u32x4 f;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const unsigned x = (byte >> (2 * q)) & 3u;
+    f[q] = ((x | (x << 15)) & 0x10001u) * 0x3F80u;
+  }
+  return f;
+}
+
+template <int PT, bool ABS, bool STORE>
+__global__ __launch_bounds__(kBlock, 2) void naive_wide_kernel(NaiveArgs a) {
+  __shared__ __align__(16) uint16_t xs[2][kWideKC][2][64 * 8];
+  __shared__ uint8_t lb[4][PT][32][kWideNMax / 8];
+  typedef __attribute__((address_space(3))) void lds_void;
+  typedef const __attribute__((address_space(1))) void gbl_void;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, col = lane & 31;
+  int chunk;
+  int64_t pbase;
+  block_coords(a, PT, chunk, pbase);
+  const int ks = (a.n + 15) / 16;
+  const int nkc = (ks + kWideKC - 1) / kWideKC;
+
+  // indicator bits of this wave's relabellings: byte g holds subjects 8g..8g+7
+  for (int idx = lane; idx < PT * 32 * 2 * ks; idx += 64) {
+    const int p = idx / (64 * ks), rem = idx - p * 64 * ks, c = rem / (2 * ks), g = rem - c * 2 * ks;
+    const int64_t perm = pbase + p * 32 + c;
+    unsigned bits = 0;
+    if (perm < a.L) {
+      const uint8_t* lab = a.labels + perm * a.n;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int j = 8 * g + i;
+        if (j < a.n && lab[j]) bits |= 1u << i;
+      }
+    }
+    lb[wave][p][c][g] = static_cast<uint8_t>(bits);
+  }
+
+  const int64_t t0 = static_cast<int64_t>(chunk) * a.tpc;
+  const int64_t t1 = t0 + a.tpc < a.vt ? t0 + a.tpc : a.vt;
+  const size_t kstride = static_cast<size_t>(a.vpad) * 32;  // uint16 per K step
+  // copy of K chunk c of tile t into buffer b: wave w moves the 1 KB blocks
+  // j = w, w + 4, ... (block j: K step 8c + j / 2, hi or lo)
+  auto issue = [&](int b, int64_t t, int c) {
+    const int s0 = c * kWideKC, nks = ks - s0 < kWideKC ? ks - s0 : kWideKC;
+#pragma unroll
+    for (int j = 0; j < 2 * kWideKC; j += 4) {
+      const int jj = j + wave;
+      if (jj < 2 * nks) {
+        const int s = jj >> 1, hl = jj & 1;
+        const uint16_t* g = a.kb16 + (s0 + s) * kstride + static_cast<size_t>(t) * 32 * 32 + hl * 512 + lane * 8;
+        __builtin_amdgcn_global_load_lds((gbl_void*)g, (lds_void*)&xs[b][s][hl][0], 16, 0, 0);
+      }
+    }
+  };
+
+  const float init = ABS ? 0.0f : -INFINITY;
+  float rm[PT][16];
+#pragma unroll
+  for (int p = 0; p < PT; ++p)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) rm[p][e] = init;
+  f32x16 acc[PT];
+#pragma unroll
+  for (int p = 0; p < PT; ++p) acc[p] = f32x16{};
+  const int64_t npair = (t1 - t0) * nkc;
+  if (npair > 0) issue(0, t0, 0);
+  for (int64_t i = 0; i < npair; ++i) {
+    const int64_t t = t0 + i / nkc;
+    const int c = static_cast<int>(i % nkc);
+    const int b = static_cast<int>(i & 1);
+    // this wave's copies have landed; after the barrier every wave's have
+    // (and the indicator bytes are written), and every wave is done with
+    // the other buffer
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
+    __syncthreads();
+    if (i + 1 < npair) issue(b ^ 1, t0 + (i + 1) / nkc, static_cast<int>((i + 1) % nkc));
+    const int s0 = c * kWideKC, nks = ks - s0 < kWideKC ? ks - s0 : kWideKC;
+#pragma unroll
+    for (int s = 0; s < kWideKC; ++s) {
+      if (s < nks) {
+        const u32x4 xh = *reinterpret_cast<const u32x4*>(&xs[b][s][0][lane * 8]);
+        const u32x4 xl = *reinterpret_cast<const u32x4*>(&xs[b][s][1][lane * 8]);
+#pragma unroll
+        for (int p = 0; p < PT; ++p) {
+          const u32x4 ind = indicator_frag(lb[wave][p][col][2 * (s0 + s) + h]);
+          acc[p] = mfma_bf16(ind, xh, acc[p]);
+          acc[p] = mfma_bf16(ind, xl, acc[p]);
+        }
+      }
+    }
+    if (c == nkc - 1) {
+      const int64_t vox = t * 32 + col;
+#pragma unroll
+      for (int p = 0; p < PT; ++p) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const float u = acc[p][e];
+          rm[p][e] = fmaxf(rm[p][e], ABS ? fabsf(u) : u);
+          if (STORE) {
+            const int64_t perm = pbase + p * 32 + mfma_row(e, h);
+            if (perm < a.L && vox < a.v) a.T_out[perm * a.v + vox] = t_from_u_f(u, a.fs, a.tm);
+          }
+        }
+        acc[p] = f32x16{};
+      }
+    }
+  }
+#pragma unroll
+  for (int p = 0; p < PT; ++p)
+#pragma unroll
+    for (int e = 0; e < 16; ++e) {
+      float x = rm[p][e];
+#pragma unroll
+      for (int off = 1; off < 32; off <<= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
+      rm[p][e] = x;
+    }
+  if (col == 0) {
+#pragma unroll
+    for (int p = 0; p < PT; ++p)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int64_t perm = pbase + p * 32 + mfma_row(e, h);
+        if (perm < a.L) a.partial[static_cast<int64_t>(chunk) * a.L + perm] = rm[p][e];
+      }
+  }
+}
+
+// ----------------------------------------------------------------------------
 // FP32 (balanced, or unbalanced with a second contraction of the squares)
 template <int KSB, int PT, bool UNBAL>
 __global__ __launch_bounds__(kBlock) void naive_f32_kernel(NaiveArgs a) {
@@ -442,10 +584,9 @@ void* pick_f32(int ks) {
 
 NaivePlan naive_plan(int64_t v, int64_t L, int n, int prec, bool store) {
   NaivePlan pl;
-  (void)n;
   // split max-only path: 4 relabelling tiles per wave (data shared through
   // LDS, two waves per SIMD); the T-writing path and the FP32 path use 2.
-  pl.pt = (prec == RPT_SPLIT_BF16 && !store) ? 4 : 2;
+  pl.pt = (prec == RPT_SPLIT_BF16 && !store && n <= 128) ? 4 : 2;
   pl.vt = round_up(v, 32) / 32;
   const int64_t group = 4 * pl.pt * 32;
   pl.pg = static_cast<int>(ceil_div(L > 0 ? L : 1, group));
@@ -495,7 +636,13 @@ rpt_status naive_launch(const PrepX& p, const NaivePlan& pl, const uint8_t* labe
   a.T_out = T_out;
   const bool unbal = 2 * p.n1 != p.n;
   void* fn = nullptr;
-  if (prec == RPT_SPLIT_BF16) {
+  if (prec == RPT_SPLIT_BF16 && p.ksteps > 8) {
+    if (unbal || p.n > kWideNMax) return RPT_ERR_UNSUPPORTED;
+    fn = a.store ? (a.abs_tail ? reinterpret_cast<void*>(&naive_wide_kernel<2, true, true>)
+                               : reinterpret_cast<void*>(&naive_wide_kernel<2, false, true>))
+                 : (a.abs_tail ? reinterpret_cast<void*>(&naive_wide_kernel<2, true, false>)
+                               : reinterpret_cast<void*>(&naive_wide_kernel<2, false, false>));
+  } else if (prec == RPT_SPLIT_BF16) {
     fn = pick_split<0>(p.ksteps, a.abs_tail, a.store);
   } else {
     fn = unbal ? pick_f32<2, true>(p.ksteps) : pick_f32<2, false>(p.ksteps);

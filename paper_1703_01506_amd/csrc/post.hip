@@ -151,7 +151,7 @@ size_t rpt_observed_tstat_workspace(int64_t v, int32_t n) {
 rpt_status rpt_observed_tstat(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, float* t_out, void* ws,
                               size_t ws_bytes, void* stream) {
   using namespace rpt;
-  if (v < 1 || n < 4 || n > 128 || ldx < n || n1 < 2 || n1 > n - 2 || !X || !t_out) return RPT_ERR_INVALID_ARG;
+  if (v < 1 || n < 4 || n > 512 || ldx < n || n1 < 2 || n1 > n - 2 || !X || !t_out) return RPT_ERR_INVALID_ARG;
   const size_t need = rpt_observed_tstat_workspace(v, n);
   if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255)) return RPT_ERR_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);

@@ -36,46 +36,54 @@ namespace rpt {
 
 namespace {
 
-constexpr int kPrepTile = 64;     // voxels per workgroup
-constexpr int kPrepNMax = 128;    // subjects held in LDS
+constexpr int kPrepNMax = 512;  // subjects
 
-// One workgroup prepares 64 voxel rows: a coalesced load of the rows into LDS,
-// FP64 row statistics with 4 threads per row, then coalesced writes of every
-// output layout.
+// sum over the TPR consecutive lanes of a row group
+template <int TPR>
+__device__ __forceinline__ double row_sum(double x) {
+#pragma unroll
+  for (int off = 1; off < TPR; off <<= 1) x += __shfl_xor(x, off, 64);
+  return x;
+}
+
+// One workgroup prepares TILE voxel rows (64 for n <= 128, 16 up to 512, so
+// that the rows fit in LDS): a coalesced load of the rows into LDS, FP64 row
+// statistics with kBlock / TILE threads per row, then coalesced writes of
+// every output layout.
+template <int TILE, int NMAX>
 __global__ __launch_bounds__(kBlock) void prep_kernel(const float* __restrict__ X, int64_t v, int n, int64_t ldx,
                                                      PrepX p, int tail, int flags) {
-  __shared__ float xs[kPrepTile][kPrepNMax + 1];
-  __shared__ double fold_c[kPrepTile], fold_d[kPrepTile];  // x'' = x * fold_c + fold_d
+  constexpr int TPR = kBlock / TILE;
+  __shared__ float xs[TILE][NMAX + 1];
+  __shared__ double fold_c[TILE], fold_d[TILE];  // x'' = x * fold_c + fold_d
   const int tid = threadIdx.x;
-  const int64_t v0 = static_cast<int64_t>(blockIdx.x) * kPrepTile;
+  const int64_t v0 = static_cast<int64_t>(blockIdx.x) * TILE;
   const bool split = (flags & kPrepSplit) != 0;
 
-  for (int idx = tid; idx < kPrepTile * n; idx += kBlock) {
+  for (int idx = tid; idx < TILE * n; idx += kBlock) {
     const int r = idx / n, j = idx - r * n;
     const int64_t vox = v0 + r;
     xs[r][j] = vox < v ? X[vox * ldx + j] : 0.0f;
   }
   __syncthreads();
 
-  // statistics: thread group of 4 per row (lanes 4r..4r+3 of the block)
-  const int r = tid >> 2, q = tid & 3;
+  // statistics: thread group of TPR per row (lanes TPR r .. TPR r + TPR - 1)
+  const int r = tid / TPR, q = tid % TPR;
   const int64_t vox = v0 + r;
   double s0 = 0.0;
-  for (int j = q; j < n; j += 4) s0 += xs[r][j];
-  s0 += __shfl_xor(s0, 1, 64);
-  s0 += __shfl_xor(s0, 2, 64);
+  for (int j = q; j < n; j += TPR) s0 += xs[r][j];
+  s0 = row_sum<TPR>(s0);
   const double mean = s0 / n;
   double ss = 0.0;
-  for (int j = q; j < n; j += 4) {
+  for (int j = q; j < n; j += TPR) {
     const double d = xs[r][j] - mean;
     ss += d * d;
   }
-  ss += __shfl_xor(ss, 1, 64);
-  ss += __shfl_xor(ss, 2, 64);
+  ss = row_sum<TPR>(ss);
   const double sc = (ss > 0.0 && vox < v) ? sqrt((n - 1.0) / ss) : 0.0;
   // standardise in place (each thread its own entries)
   double S = 0.0;
-  for (int j = q; j < n; j += 4) {
+  for (int j = q; j < n; j += TPR) {
     const float f = static_cast<float>((xs[r][j] - mean) * sc);
     xs[r][j] = f;
     float st = f;
@@ -85,11 +93,10 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(const float* __restrict__ 
     }
     S += st;
   }
-  S += __shfl_xor(S, 1, 64);
-  S += __shfl_xor(S, 2, 64);
+  S = row_sum<TPR>(S);
   const double mu = S / n;
   double Qc = 0.0, Q = 0.0;
-  for (int j = q; j < n; j += 4) {
+  for (int j = q; j < n; j += TPR) {
     const float f = xs[r][j];
     float st = f;
     if (split) {
@@ -99,10 +106,8 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(const float* __restrict__ 
     Qc += (st - mu) * (st - mu);
     Q += static_cast<double>(st) * st;
   }
-  Qc += __shfl_xor(Qc, 1, 64);
-  Qc += __shfl_xor(Qc, 2, 64);
-  Q += __shfl_xor(Q, 1, 64);
-  Q += __shfl_xor(Q, 2, 64);
+  Qc = row_sum<TPR>(Qc);
+  Q = row_sum<TPR>(Q);
   if (q == 0 && vox < p.vpad) {
     if (vox < v) {
       const double rinv = Qc > 0.0 ? 1.0 / sqrt(Qc) : 0.0;
@@ -120,11 +125,11 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(const float* __restrict__ 
   }
   __syncthreads();
 
-  const int nv = static_cast<int>((p.vpad - v0) < kPrepTile ? (p.vpad - v0) : kPrepTile);
+  const int nv = static_cast<int>((p.vpad - v0) < TILE ? (p.vpad - v0) : TILE);
   if (p.kb16) {
-    // per K step: 64 voxels x (hi 16 | lo 16) bf16 = 256 chunks of 16 bytes
-    const int rr = tid >> 2, c = tid & 3;
-    for (int s = 0; s < p.ksteps; ++s) {
+    // per K step: TILE voxels x (hi 16 | lo 16) bf16 = 4 TILE chunks of 16 bytes
+    for (int idx = tid; idx < p.ksteps * 4 * TILE; idx += kBlock) {
+      const int s = idx / (4 * TILE), rr = (idx >> 2) % TILE, c = idx & 3;
       if (rr < nv) {
         uint32_t w[4];
 #pragma unroll
@@ -151,9 +156,9 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(const float* __restrict__ 
     }
   }
   if (p.kb32) {
-    // per K block: 64 voxels x 8 floats = 128 chunks of 16 bytes
+    // per K block: TILE voxels x 8 floats = 2 TILE chunks of 16 bytes
     for (int s = 0; s < p.ksteps; ++s) {
-      for (int ch = tid; ch < 2 * kPrepTile; ch += kBlock) {
+      for (int ch = tid; ch < 2 * TILE; ch += kBlock) {
         const int rr = ch >> 1, hh = ch & 1;
         if (rr >= nv) continue;
         float f[4], f2[4];
@@ -211,10 +216,14 @@ PrepX prep_carve(Carver& c, int64_t v, int n, int n1, int flags) {
 
 rpt_status prep_launch(const PrepX& p, const float* X, int64_t ldx, int tail, int flags, hipStream_t s) {
   if (p.n > kPrepNMax) return RPT_ERR_UNSUPPORTED;
-  const int64_t blocks = ceil_div(p.vpad, kPrepTile);
   RPT_STAGE("prep", s);
-  hipLaunchKernelGGL(prep_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, X, p.v, p.n, ldx, p,
-                     tail, flags);
+  if (p.n <= 128) {
+    hipLaunchKernelGGL((prep_kernel<64, 128>), dim3(static_cast<unsigned>(ceil_div(p.vpad, 64))), dim3(kBlock), 0, s,
+                       X, p.v, p.n, ldx, p, tail, flags);
+  } else {
+    hipLaunchKernelGGL((prep_kernel<16, kPrepNMax>), dim3(static_cast<unsigned>(ceil_div(p.vpad, 16))),
+                       dim3(kBlock), 0, s, X, p.v, p.n, ldx, p, tail, flags);
+  }
   RPT_CHECK_LAUNCH();
   return RPT_OK;
 }

@@ -55,6 +55,13 @@ def test_naive_argument_validation(lib):
     assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 0, 9, dummy, None, dummy, ws_need, None) == -1
     # unbalanced split-BF16 is not provided
     assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 8, dummy, 50, 0, 1, dummy, None, dummy, ws_need, None) == -6
+    # more than 512 subjects; the FP32 path above 128
+    ws_wide = lib.rpt_naive_workspace(1000, 513, 50, 1)
+    assert lib.rpt_naive_maxnull(dummy, 1000, 513, 513, 256, dummy, 50, 0, 1, dummy, None, dummy, ws_wide,
+                                 None) == -1
+    ws_f32 = lib.rpt_naive_workspace(1000, 200, 50, 0)
+    assert lib.rpt_naive_maxnull(dummy, 1000, 200, 200, 100, dummy, 50, 0, 0, dummy, None, dummy, ws_f32,
+                                 None) == -6
     # workspace too small / misaligned
     assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 0, 1, dummy, None, dummy, ws_need - 1,
                                  None) == -4

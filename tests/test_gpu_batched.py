@@ -10,8 +10,9 @@ from oracle import rapidpt as OR
 pytestmark = pytest.mark.gpu
 
 # (n, v, r, L, sigma, mu, col0, study id)
+# the last study has more subjects than one 128-wide piece of a row
 STUDIES = [(20, 3001, 8, 40, 0.3, 0.05, 0, 3), (36, 5003, 17, 33, 0.0, -0.1, 300, 7),
-           (100, 20000, 40, 25, 0.05, 0.2, 301, 11)]
+           (100, 20000, 40, 25, 0.05, 0.2, 301, 11), (200, 7001, 30, 21, 0.1, 0.0, 600, 13)]
 
 
 def _study(torch, q, n, v, r, L, sigma, mu, col0, sid, seed=2017):

@@ -16,7 +16,7 @@ def _d(torch, a):
     return torch.from_numpy(np.ascontiguousarray(a)).cuda()
 
 
-@pytest.mark.parametrize("n,n1", [(20, 10), (30, 11)])
+@pytest.mark.parametrize("n,n1", [(20, 10), (30, 11), (300, 150), (301, 120)])
 def test_observed_tmap(n, n1):
     torch = torch_cuda()
     import paper_1703_01506_amd as rpt

@@ -115,3 +115,43 @@ def test_naive_full_size_sampled(prec):
     ref = np.array([OT.tstat(X64, labels[i] == 1).max() for i in idx])
     assert_t_close(got[idx], ref, prec, "max")
     assert np.isfinite(got).all()
+
+
+@pytest.mark.parametrize("n", [136, 200, 400, 512])
+@pytest.mark.parametrize("tail", ["signed", "abs"])
+def test_naive_wide_subjects(n, tail):
+    """More than 128 subjects (the multi-study range 150-400 and the limit
+    512): K steps staged in chunks of 8 with a ragged last chunk (n = 136 has
+    9 steps), ragged voxel and relabelling tiles; full T element by element
+    and the maxima, split BF16.  The FP32 path refuses these sizes."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce(f"naive wide n={n} tail={tail}")
+    rng = np.random.default_rng(n)
+    v, L = 2011, 261
+    X = (rng.normal(size=(v, n)) * rng.uniform(0.5, 2.0, size=(v, 1)) + rng.normal(size=(v, 1)) * 3).astype(np.float32)
+    labels = S.relabellings(L, n, n // 2, seed=n + 1)
+    mx, T = _run(torch, X, labels, n // 2, tail, "split_bf16", return_T=True)
+    Tref = OT.tmatrix(X.astype(np.float64), labels)
+    assert_t_close(T, Tref, "split", "T")
+    ref = np.abs(Tref).max(axis=1) if tail == "abs" else Tref.max(axis=1)
+    assert_t_close(mx, ref, "split", "max")
+    mx2 = _run(torch, X, labels, n // 2, tail, "split_bf16")  # max-only launch
+    assert_t_close(mx2, ref, "split", "max (max-only)")
+    with pytest.raises(RuntimeError):
+        _run(torch, X, labels, n // 2, tail, "fp32")
+
+
+def test_naive_wide_full_size_sampled():
+    """n = 400 (200/200) on the 250,000-voxel smoothed volume, L = 2,000:
+    10 relabellings recomputed by the oracle one by one."""
+    torch = torch_cuda()
+    announce("naive wide full-size n=400")
+    X = S.smoothed_volumes(400, 250_000, seed=1703)
+    labels = S.relabellings(2_000, 400, 200, seed=1506)
+    got = _run(torch, X, labels, 200, "signed", "split_bf16")
+    idx = np.linspace(0, 1_999, 10).astype(int)
+    X64 = X.astype(np.float64)
+    ref = np.array([OT.tstat(X64, labels[i] == 1).max() for i in idx])
+    assert_t_close(got[idx], ref, "split", "max")
+    assert np.isfinite(got).all()

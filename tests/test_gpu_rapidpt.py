@@ -28,7 +28,8 @@ def _dev(torch, a):
 def test_sampled_tstat_balanced_and_unbalanced():
     torch = torch_cuda()
     import paper_1703_01506_amd as rpt
-    for (n, n1) in [(40, 20), (30, 11)]:
+    # up to 128 subjects one 16-byte piece per lane, then four (512 subjects)
+    for (n, n1) in [(40, 20), (30, 11), (132, 66), (300, 150), (260, 100), (512, 256)]:
         announce(f"sampled n={n} n1={n1}")
         rng = np.random.default_rng(n)
         v, L, k = 5003, 37, 301
@@ -221,9 +222,10 @@ def test_rapidpt_end_to_end_gates():
     omt = S.omega_sets(passes * ell, v, k, seed=41)
     oms = S.omega_sets(ell, v, k, seed=42)
     omr = S.omega_sets(L - ell, v, k, seed=43)
+    # T_ex in split BF16: the FP32 contraction takes at most 128 subjects
     h, tr, info = rpt.rapidpt_maxnull(_dev(torch, X), _dev(torch, labels[:ell]), _dev(torch, labels[ell:]),
                                       _dev(torch, U0), _dev(torch, omt), _dev(torch, oms), _dev(torch, omr),
-                                      passes=passes, seed=seed, prec="fp32")
+                                      passes=passes, seed=seed, prec="split_bf16")
     h = h.cpu().numpy()
     assert (info.cpu().numpy() == 0).all()
     href, Uo, so, muo = OR.rapidpt_maxnull(X.astype(np.float64), labels[:ell], labels[ell:], U0.astype(np.float64),
@@ -353,3 +355,33 @@ def test_rapidpt_single_call_matches_stages_and_replays():
 def _same_maxnull(a, b, ell):
     np.testing.assert_array_equal(a[:ell], b[:ell])
     np.testing.assert_allclose(a[ell:], b[ell:], atol=1e-4, rtol=0)
+
+
+def test_rapidpt_end_to_end_wide_subjects():
+    """Alg. 2 end to end with 160 subjects (80/80; the wide NaivePT kernel for
+    T_ex, four-piece sampled rows): v = 8,000, L = 600, l = 60, r = 24,
+    4 passes, 2% sampled voxels.  Same gates as the 20-subject case."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce("rapidpt end to end n=160")
+    n, v, L, ell, r, passes, seed = 160, 8_000, 600, 60, 24, 4, 2017
+    k = S.omega_count(v, 20_000)
+    X, _ = S.iid_volumes(n, v, n // 2, signal_frac=0.02, shift=0.5, seed=7)
+    X = X.astype(np.float32)
+    labels = S.relabellings(L, n, n // 2, seed=8)
+    U0 = S.gaussian_matrix(v, r, seed=9).astype(np.float32)
+    omt = S.omega_sets(passes * ell, v, k, seed=10)
+    oms = S.omega_sets(ell, v, k, seed=11)
+    omr = S.omega_sets(L - ell, v, k, seed=12)
+    # T_ex in split BF16: the FP32 contraction takes at most 128 subjects
+    h, tr, info = rpt.rapidpt_maxnull(_dev(torch, X), _dev(torch, labels[:ell]), _dev(torch, labels[ell:]),
+                                      _dev(torch, U0), _dev(torch, omt), _dev(torch, oms), _dev(torch, omr),
+                                      passes=passes, seed=seed, prec="split_bf16")
+    h = h.cpu().numpy()
+    assert (info.cpu().numpy() == 0).all()
+    href, Uo, so, muo = OR.rapidpt_maxnull(X.astype(np.float64), labels[:ell], labels[ell:], U0.astype(np.float64),
+                                           omt, oms, omr, passes, seed)
+    assert OM.kl_divergence(href, h) < 1e-3
+    t_ref, t_gpu = OM.threshold(href, 0.05), OM.threshold(h, 0.05)
+    assert abs(t_gpu - t_ref) <= 0.01 * abs(t_ref)
+    np.testing.assert_allclose(h, href, atol=5e-3, rtol=0)
