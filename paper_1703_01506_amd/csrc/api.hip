@@ -219,7 +219,8 @@ rpt_status train_start_basis(int64_t v, int32_t n, int32_t n1, int32_t ell, cons
 rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r, const int32_t* omega_train,
                        int32_t k, int32_t passes, int32_t batch, float gamma, const int32_t* omega_sm, uint64_t seed,
                        int mu_rule, int prec, float* U_out, float* sigma_mu, float* train_max, float* T_ex_out,
-                       int32_t* info, void* ws, hipStream_t s);
+                       int32_t* info, void* ws, hipStream_t s,
+                       const std::function<rpt_status(int, int)>& at_step = nullptr);
 
 rpt_status train_run(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* train_labels,
                      int32_t ell, const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
@@ -258,15 +259,20 @@ rpt_status train_start_basis(int64_t v, int32_t n, int32_t n1, int32_t ell, cons
 }
 
 // 3.-5. tracking passes, sigma and mu (T_ex and the start basis in place)
+// at_step(j, steps), when given, runs before the Cholesky of tracking step j
+// of `steps`.
 rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r, const int32_t* omega_train,
                        int32_t k, int32_t passes, int32_t batch, float gamma, const int32_t* omega_sm, uint64_t seed,
                        int mu_rule, int prec, float* U_out, float* sigma_mu, float* train_max, float* T_ex_out,
-                       int32_t* info, void* ws, hipStream_t s) {
+                       int32_t* info, void* ws, hipStream_t s,
+                       const std::function<rpt_status(int, int)>& at_step) {
   TrainWs t = train_carve(ws, v, n, n1, ell, r, k, prec, nullptr);
   float* T = T_ex_out ? T_ex_out : t.T;
   // 3. tracking passes: Complete links every sampled entry into the list of
   // its voxel; the update then adds each voxel's entries in one pass
   RPT_TRY(fill_i32(t.lhead, v, -1, s));
+  const int steps = passes * ((ell + batch - 1) / batch);
+  int step = 0;
   for (int pp = 0; pp < passes; ++pp) {
     for (int b0 = 0; b0 < ell; b0 += batch) {
       const int nb = b0 + batch <= ell ? batch : ell - b0;
@@ -274,7 +280,9 @@ rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r,
       RPT_TRY(complete_run(U_out, v, r, om, k, nullptr, T + static_cast<int64_t>(b0) * v, v, nullptr, nb, t.W,
                            t.resid, t.info, t.wnorm2, s, t.lhead, t.lnext));
       RPT_TRY(track_apply_launch(U_out, v, r, k, t.resid, t.W, t.wnorm2, t.info, gamma, t.lhead, t.lnext, s));
-      RPT_TRY(reorth_launch(U_out, v, r, t.info + ell - 1, t.reorth_ws, s));
+      const std::function<rpt_status()> hook = [&, j = step]() { return at_step(j, steps); };
+      RPT_TRY(reorth_launch(U_out, v, r, t.info + ell - 1, t.reorth_ws, s, at_step ? &hook : nullptr));
+      ++step;
     }
   }
   // 4. sigma from fresh sampled sets with the final U
@@ -356,6 +364,13 @@ rpt_status recover_front(const RecoverWs& w, const float* X, int64_t ldx, const 
   return sampled_launch(w.p, labels, L_rec, omega, k, nullptr, w.y, s);
 }
 
+// sampled t of recovered columns [c0, c1) (prep done)
+rpt_status recover_sampled(const RecoverWs& w, const uint8_t* labels, int32_t n, int64_t c0, int64_t c1,
+                           const int32_t* omega, int32_t k, hipStream_t s) {
+  if (c1 <= c0) return RPT_OK;
+  return sampled_launch(w.p, labels + c0 * n, c1 - c0, omega + c0 * k, k, nullptr, w.y + c0 * k, s);
+}
+
 // Complete, then U w + noise and the column maxima
 rpt_status recover_back(const RecoverWs& w, int64_t v, int64_t L_rec, int64_t col0, const float* U, int32_t r,
                         const float* sigma_mu, const int32_t* omega, int32_t k, uint64_t seed, float* max_out,
@@ -415,10 +430,11 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
   hipStream_t s = static_cast<hipStream_t>(stream);
   const RecoverWs w = recover_carve(static_cast<char*>(ws) + tw, v, n, n1, L_rec, r, k);
   // Two chains share the device: the caller's stream computes T_ex (matrix
-  // cores, the whole chip) and then the tracking passes (latency-bound, few
-  // workgroups at a time); the second stream orthonormalises the start basis
-  // meanwhile (single-workgroup Cholesky) and then computes the sampled t of
-  // the recovered columns, which need no basis, during the tracking passes.
+  // cores, the whole chip) and then the tracking passes (latency-bound, a
+  // single-workgroup Cholesky in every step); the second stream
+  // orthonormalises the start basis meanwhile and then computes the sampled t
+  // of the recovered columns, which need no basis, in one chunk per tracking
+  // step, each started as that step's Cholesky is reached.
   SideStream* sd = side_stream(s);
   if (!sd) {
     RPT_TRY(train_run(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, omega_sm,
@@ -434,10 +450,23 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
   rpt_status st_side = train_start_basis(v, n, n1, ell, U0, r, k, prec, U_out, ws, sd->st);
   st = stream_wait(sd, sd->mid, sd->st, s);  // the basis is ready for the tracking passes
   if (st_side == RPT_OK && st == RPT_OK && L_rec > 0)
-    st_side = recover_front(w, X, ldx, rec_labels, L_rec, omega_rec, k, sd->st);
+    st_side = prep_launch(w.p, X, ldx, RPT_TAIL_SIGNED, kPrepRows, sd->st);
+  // the sampled t of the recovered columns in one chunk per tracking step,
+  // each released when that step reaches its single-workgroup Cholesky
+  int64_t done = 0;
+  const std::function<rpt_status(int, int)> at_step = [&](int j, int steps) -> rpt_status {
+    if (st_side != RPT_OK || L_rec == 0) return RPT_OK;
+    RPT_TRY(stream_wait(sd, sd->step, s, sd->st));
+    const int64_t c1 = L_rec * (j + 1) / steps;
+    st_side = recover_sampled(w, rec_labels, n, done, c1, omega_rec, k, sd->st);
+    done = c1;
+    return RPT_OK;
+  };
   if (st_main == RPT_OK && st_side == RPT_OK && st == RPT_OK)
     st_main = train_track(v, n, n1, ell, r, omega_train, k, passes, batch, gamma, omega_sm, seed, mu_rule, prec,
-                          U_out, sigma_mu, h_out, nullptr, train_info, ws, s);
+                          U_out, sigma_mu, h_out, nullptr, train_info, ws, s, at_step);
+  if (st_side == RPT_OK && done < L_rec)  // no tracking steps: all columns now
+    st_side = recover_sampled(w, rec_labels, n, done, L_rec, omega_rec, k, sd->st);
   const rpt_status st_join = stream_wait(sd, sd->join, sd->st, s);
   RPT_TRY(st);
   RPT_TRY(st_side);

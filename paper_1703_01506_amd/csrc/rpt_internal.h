@@ -6,6 +6,7 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <functional>
 #include <mutex>
 
 #include "rpt.h"
@@ -194,7 +195,7 @@ rpt_status sampled_launch(const PrepX& p, const uint8_t* labels, int64_t L, cons
 struct SideStream {
   bool ok = false;
   hipStream_t st = nullptr;
-  hipEvent_t fork = nullptr, mid = nullptr, join = nullptr;
+  hipEvent_t fork = nullptr, mid = nullptr, join = nullptr, step = nullptr;
   std::mutex mu;
 };
 SideStream* side_stream(hipStream_t s);
@@ -216,9 +217,12 @@ rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_
                         uint64_t seed, int stream_id, const float* sigma_mu, float* out_max,
                         const float* Tmax_for_gap, float* gap_out, void* ws, hipStream_t s, unsigned study = 0);
 
-// Orthonormalisation (one Cholesky-QR pass).
+// Orthonormalisation (one Cholesky-QR pass).  before_chol, when given, is
+// called once the Gram reduction is enqueued and before the single-workgroup
+// Cholesky (a point where the rest of the chip is about to idle).
 size_t reorth_bytes(int64_t v, int r);
-rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hipStream_t s);
+rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hipStream_t s,
+                         const std::function<rpt_status()>* before_chol = nullptr);
 
 // Training helpers (train.hip).
 // U[x] += gamma sum_e resid[e] W[i(e)] / |w_i(e)|^2 over the entries linked

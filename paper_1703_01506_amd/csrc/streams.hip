@@ -25,7 +25,7 @@ SideStream* side_stream(hipStream_t s) {
   if (hipGetDevice(&cur) != hipSuccess) return nullptr;
   if (cur != dev && hipSetDevice(dev) != hipSuccess) return nullptr;
   bool good = hipStreamCreateWithFlags(&sd.st, hipStreamNonBlocking) == hipSuccess;
-  for (hipEvent_t* ev : {&sd.fork, &sd.mid, &sd.join})
+  for (hipEvent_t* ev : {&sd.fork, &sd.mid, &sd.join, &sd.step})
     good = good && hipEventCreateWithFlags(ev, hipEventDisableTiming) == hipSuccess;
   if (cur != dev) (void)hipSetDevice(cur);
   if (!good) {

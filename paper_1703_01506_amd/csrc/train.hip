@@ -423,7 +423,8 @@ size_t reorth_bytes(int64_t v, int r) {
   return c.off;
 }
 
-rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hipStream_t s) {
+rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hipStream_t s,
+                         const std::function<rpt_status()>* before_chol) {
   if (r < 1 || r > kR) return RPT_ERR_UNSUPPORTED;
   Carver c(ws);
   const int nb = gram_blocks(v);
@@ -449,6 +450,7 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
   hipLaunchKernelGGL(gram_reduce_kernel, dim3(static_cast<unsigned>(ceil_div(static_cast<int64_t>(ntile) * 256, 64))),
                      dim3(64 * kRedWaves), 0, s, part, nb, ntile, r, gfull);
   RPT_CHECK_LAUNCH();
+  if (before_chol && *before_chol) RPT_TRY((*before_chol)());
   static bool attr_set = false;
   if (!attr_set) {
     (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&chol_rinv_kernel),
