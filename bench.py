@@ -53,10 +53,11 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(X, labels, U0, omt, oms, omr, ell, passes, seed, budget_s=25.0):
+def cpu_baseline(X, labels, U0, omt, oms, omr, ell, passes, seed, part_s=4.0):
     """The FP64 oracle on a bounded sample of the same workload, scaled to the
-    full step: T_ex for 2 of the l training columns, one tracking pass over 2
-    columns, and recovery of 4 columns, each rate scaled to its full count."""
+    full step: training t maps, tracking-step column visits and recovered
+    columns, each part repeated until about part_s seconds are spent (about
+    12 s in all), each rate scaled to its full count."""
     from oracle import rapidpt as OR
     from oracle import tstat as OT
     try:
@@ -65,25 +66,28 @@ def cpu_baseline(X, labels, U0, omt, oms, omr, ell, passes, seed, budget_s=25.0)
     except Exception:  # pragma: no cover
         cores = os.cpu_count() or 1
     X64 = X.astype(np.float64)
-    v = X.shape[0]
     L = labels.shape[0]
-    t0 = time.perf_counter()
-    T2 = OT.tmatrix(X64, labels[:2])
-    t_tex = (time.perf_counter() - t0) / 2
-    U = OR.orthonormalize(U0[:, :].astype(np.float64))
-    t0 = time.perf_counter()
-    OR.track_step(U, T2, [omt[0], omt[1]])
-    t_pass_col = (time.perf_counter() - t0) / 2
-    t0 = time.perf_counter()
-    n_rec = 4
-    for j in range(n_rec):
-        OR.recover_column(X64, labels[ell + j] == 1, U, 0.5, 0.0, omr[j], seed, ell + j)
-    t_rec = (time.perf_counter() - t0) / n_rec
-    est = t_tex * ell + t_pass_col * ell * passes + t_rec * ell + t_rec * (L - ell)
+
+    def until(budget, fn, cap):
+        t0, cnt = time.perf_counter(), 0
+        while cnt < cap and (cnt == 0 or time.perf_counter() - t0 < budget):
+            fn(cnt)
+            cnt += 1
+        return (time.perf_counter() - t0) / cnt, cnt
+
+    maps = []
+    t_tex, n_tex = until(part_s, lambda j: maps.append(OT.tstat(X64, labels[j] == 1)), ell)
+    U = OR.orthonormalize(U0.astype(np.float64))
+    T2 = np.stack(maps[:2]) if len(maps) >= 2 else OT.tmatrix(X64, labels[:2])
+    t_pair, n_pair = until(part_s, lambda j: OR.track_step(U, T2, [omt[2 * j], omt[2 * j + 1]]), passes * ell // 2)
+    t_visit = t_pair / 2
+    t_rec, n_rec = until(part_s, lambda j: OR.recover_column(X64, labels[ell + j] == 1, U, 0.5, 0.0, omr[j], seed,
+                                                             ell + j), L - ell)
+    est = t_tex * ell + t_visit * ell * passes + t_rec * ell + t_rec * (L - ell)
     return {"value": L / est, "unit": "perms/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"oracle timed on 2 training t maps ({t_tex:.2f} s each), one tracking step over "
-                       f"2 columns ({t_pass_col:.2f} s per column visit) and 4 recovered columns "
-                       f"({t_rec:.2f} s each), scaled to l={ell} maps, {passes} passes, l sigma/mu columns "
+            "sample": (f"oracle timed on {n_tex} training t maps ({t_tex:.3f} s each), {n_pair} tracking steps "
+                       f"over 2 columns ({t_visit:.3f} s per column visit) and {n_rec} recovered columns "
+                       f"({t_rec:.4f} s each), scaled to l={ell} maps, {passes} passes, l sigma/mu columns "
                        f"and {L - ell} recoveries: {est:.0f} s estimated for the {L}-column step")}
 
 
