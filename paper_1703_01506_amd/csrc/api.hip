@@ -277,9 +277,10 @@ rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r,
     for (int b0 = 0; b0 < ell; b0 += batch) {
       const int nb = b0 + batch <= ell ? batch : ell - b0;
       const int32_t* om = omega_train + (static_cast<int64_t>(pp) * ell + b0) * k;
-      RPT_TRY(complete_run(U_out, v, r, om, k, nullptr, T + static_cast<int64_t>(b0) * v, v, nullptr, nb, t.W,
-                           t.resid, t.info, t.wnorm2, s, t.lhead, t.lnext));
-      RPT_TRY(track_apply_launch(U_out, v, r, k, t.resid, t.W, t.wnorm2, t.info, gamma, t.lhead, t.lnext, s));
+      const float* Tb = T + static_cast<int64_t>(b0) * v;
+      RPT_TRY(complete_run(U_out, v, r, om, k, nullptr, Tb, v, nullptr, nb, t.W, nullptr, t.info, t.wnorm2, s,
+                           t.lhead, t.lnext));
+      RPT_TRY(track_apply_launch(U_out, v, r, k, Tb, v, t.W, t.wnorm2, t.info, gamma, t.lhead, t.lnext, s));
       const std::function<rpt_status()> hook = [&, j = step]() { return at_step(j, steps); };
       RPT_TRY(reorth_launch(U_out, v, r, t.info + ell - 1, t.reorth_ws, s, at_step ? &hook : nullptr));
       ++step;

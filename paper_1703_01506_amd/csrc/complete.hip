@@ -12,8 +12,8 @@
 // lower triangle in LDS with b^T appended as row r, so that the blocked
 // Cholesky of that trapezoid leaves z = L^{-1} b in row r; one blocked back
 // substitution gives w.  A non-positive pivot j sets info[i] = j + 1 and
-// w_i = 0.  Optionally the residual y - U_O w is written, and each sampled
-// entry (i, q) of a solved column is pushed onto the list of its voxel
+// w_i = 0.  Optionally the residual y - U_O w is written, and optionally each
+// sampled entry (i, q) of a solved column is pushed onto the list of its voxel
 // (lhead / lnext), so that a later pass can apply all entries of one voxel
 // together without floating-point atomics.
 #include "lds_linalg.h"
@@ -228,6 +228,15 @@ __device__ __forceinline__ void solve_phase(const CompleteArgs& a, int64_t i, in
         a.lnext[e] = atomicExch(a.lhead + row, e);
       }
     }
+  } else if (a.lhead) {
+    // lists only: the tracking update forms the residual itself
+    for (int q = tid; q < k; q += kNT) {
+      const int64_t row = om[q];
+      if (row >= 0 && row < a.v) {
+        const int32_t e = static_cast<int32_t>(base + q);
+        a.lnext[e] = atomicExch(a.lhead + row, e);
+      }
+    }
   }
 }
 
@@ -320,7 +329,7 @@ rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, 
                         const int64_t* optr, void* split_ws) {
   if (L == 0) return RPT_OK;
   if (r < 1 || r > kRMax) return RPT_ERR_UNSUPPORTED;
-  if (lhead && (!resid || optr || L * static_cast<int64_t>(k) > INT32_MAX)) return RPT_ERR_INVALID_ARG;
+  if (lhead && (!lnext || optr || L * static_cast<int64_t>(k) > INT32_MAX)) return RPT_ERR_INVALID_ARG;
   CompleteArgs a{U, v, r, omega, k, y, Trows, ldT, trow, L, W, resid, info, wnorm2, lhead, lnext, optr};
   const int RB = (r + 15) / 16;
 #define RPT_FNS(K) \

@@ -227,7 +227,7 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
 // Training helpers (train.hip).
 // U[x] += gamma sum_e resid[e] W[i(e)] / |w_i(e)|^2 over the entries linked
 // at voxel x by complete_run (i(e) = e / k); every list head is reset to -1.
-rpt_status track_apply_launch(float* U, int64_t v, int r, int k, const float* resid, const float* W,
+rpt_status track_apply_launch(float* U, int64_t v, int r, int k, const float* T, int64_t ldT, const float* W,
                               const float* wnorm2, const int32_t* info, float gamma, int32_t* lhead,
                               const int32_t* lnext, hipStream_t s);
 rpt_status fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s);

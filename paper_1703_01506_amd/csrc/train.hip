@@ -7,9 +7,11 @@
 //   positive-diagonal R ("Rand. Orth." of Alg. 2 and the retraction after
 //   each tracking step).
 // * Tracking update: U[omega_i, :] += gamma e_i w_i^T / |w_i|^2 summed over a
-//   mini-batch (atomic FP32 adds: two columns of a batch may sample the same
-//   voxel).  For one column this is GROUSE's greedy geodesic step up to the
-//   choice of basis of the new subspace.
+//   mini-batch, e_i = y_i - U[omega_i, :] w_i with the basis before the update
+//   (two columns of a batch may sample the same voxel: each voxel's entries
+//   are linked into a list by Complete and applied together).  For one column
+//   this is GROUSE's greedy geodesic step up to the choice of basis of the new
+//   subspace.
 // * sigma: sample standard deviation of the sampled-entry residuals (FP64).
 // * mu: mean of the per-column gaps (mean-gap rule) or the literal maximum
 //   residual of Alg. 2.
@@ -278,14 +280,15 @@ __global__ __launch_bounds__(kBlock, 2) void apply_rinv_kernel(float* __restrict
 }
 
 // ---------------------------------------------------------------- tracking update
-// A quarter wave per voxel: walk the voxel's list of sampled entries (linked
-// by the Complete kernel), sum gamma e / |w_i|^2 * w_i over it, add the sum
-// to the voxel's basis row, and reset the list head.  Lane l of the quarter
-// covers columns l + 16 j, so row accesses are 64-byte segments; four voxels
-// per wave keep four dependent list walks in flight.
+// A quarter wave per voxel: read the voxel's basis row, walk its list of
+// sampled entries (linked by the Complete kernel), form each entry's residual
+// e = T[i][voxel] - row . w_i (a 16-lane reduction), sum gamma e / |w_i|^2 *
+// w_i over the list, write the row plus the sum, and reset the list head.
+// Lane l of the quarter covers columns l + 16 j, so row accesses are 64-byte
+// segments; four voxels per wave keep four dependent list walks in flight.
 constexpr int kTrackLanes = 16;
 __global__ __launch_bounds__(kBlock) void track_apply_kernel(float* __restrict__ U, int64_t v, int r, int k,
-                                                            const float* __restrict__ resid,
+                                                            const float* __restrict__ T, int64_t ldT,
                                                             const float* __restrict__ W,
                                                             const float* __restrict__ wnorm2,
                                                             const int32_t* __restrict__ info, float gamma,
@@ -297,26 +300,39 @@ __global__ __launch_bounds__(kBlock) void track_apply_kernel(float* __restrict__
   if (vox >= v) return;
   int e = lhead[vox];
   if (e < 0) return;
-  float acc[NJ];
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) acc[j] = 0.0f;
-  while (e >= 0) {
-    const int i = e / k;
-    const float n2 = wnorm2[i];
-    const float coef = (info[i] == 0 && n2 > 0.0f) ? gamma * resid[e] / n2 : 0.0f;
-    const float* wi = W + static_cast<int64_t>(i) * r;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      const int c = l + kTrackLanes * j;
-      if (c < r) acc[j] = fmaf(coef, wi[c], acc[j]);
-    }
-    e = lnext[e];
-  }
+  // the voxel's basis row before the update: every entry's residual uses it
   float* u = U + vox * r;
+  float u0[NJ], acc[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     const int c = l + kTrackLanes * j;
-    if (c < r) u[c] += acc[j];
+    u0[j] = c < r ? u[c] : 0.0f;
+    acc[j] = 0.0f;
+  }
+  while (e >= 0) {
+    const int i = e / k;
+    const float n2 = wnorm2[i];
+    const float y = T[static_cast<int64_t>(i) * ldT + vox];
+    const float* wi = W + static_cast<int64_t>(i) * r;
+    float wv[NJ], dot = 0.0f;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      const int c = l + kTrackLanes * j;
+      wv[j] = c < r ? wi[c] : 0.0f;
+      dot = fmaf(u0[j], wv[j], dot);
+    }
+#pragma unroll
+    for (int off = kTrackLanes / 2; off > 0; off >>= 1) dot += __shfl_xor(dot, off, kTrackLanes);
+    // residual e = y - U_vox . w_i of this sampled entry
+    const float coef = (info[i] == 0 && n2 > 0.0f) ? gamma * (y - dot) / n2 : 0.0f;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) acc[j] = fmaf(coef, wv[j], acc[j]);
+    e = lnext[e];
+  }
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    const int c = l + kTrackLanes * j;
+    if (c < r) u[c] = u0[j] + acc[j];
   }
   if (l == 0) lhead[vox] = -1;  // every lane of this quarter wave read the head above
 }
@@ -477,14 +493,14 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
   return RPT_OK;
 }
 
-rpt_status track_apply_launch(float* U, int64_t v, int r, int k, const float* resid, const float* W,
+rpt_status track_apply_launch(float* U, int64_t v, int r, int k, const float* T, int64_t ldT, const float* W,
                               const float* wnorm2, const int32_t* info, float gamma, int32_t* lhead,
                               const int32_t* lnext, hipStream_t s) {
   if (r < 1 || r > kR) return RPT_ERR_UNSUPPORTED;
   RPT_STAGE("track_update", s);
   const unsigned blocks = static_cast<unsigned>(ceil_div(v, kBlock / kTrackLanes));
-  hipLaunchKernelGGL(track_apply_kernel, dim3(blocks), dim3(kBlock), 0, s, U, v, r, k, resid, W, wnorm2, info, gamma,
-                     lhead, lnext);
+  hipLaunchKernelGGL(track_apply_kernel, dim3(blocks), dim3(kBlock), 0, s, U, v, r, k, T, ldT, W, wnorm2, info,
+                     gamma, lhead, lnext);
   RPT_CHECK_LAUNCH();
   return RPT_OK;
 }
