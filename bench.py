@@ -46,7 +46,8 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rapidpt_step_n100_v250k_hbm_traff
 STAGE_KERNEL = {"complete": "complete_kernel", "complete_gram": "complete_gram_kernel",
                 "complete_solve": "complete_solve_kernel", "recon_fused": "recon_fused_kernel",
                 "naive_contract": "naive_max_kernel", "sampled_t": "sampled_kernel",
-                "track_update": "track_apply_kernel"}
+                "track_update": "track_apply_kernel", "reorth_gram": "gram_partial_kernel",
+                "reorth_apply": "apply_rinv_kernel", "reorth_chol": "chol_rinv_kernel"}
 
 
 def log(msg):
@@ -192,7 +193,8 @@ def main():
     naive_roof["traffic_unit"] = "bytes per launch"
     roof = roofline_for(dom, tot[dom], launches[dom], v, n, L, ell, r, k, P)
     others = {}
-    for s_ in ("complete", "complete_gram", "complete_solve", "recon_fused", "reorth", "track_update"):
+    for s_ in ("complete", "complete_gram", "complete_solve", "recon_fused", "reorth_gram", "reorth_chol",
+               "reorth_apply", "track_update", "sampled_t"):
         if s_ in tot and s_ != dom:
             others[s_] = roofline_for(s_, tot[s_], launches[s_], v, n, L, ell, r, k, P)
 
@@ -294,14 +296,32 @@ def roofline_for(stage, ms_per_step, launches_per_step, v, n, L, ell, r, k, P):
                     "frac": ach / peak, "algorithmic_normals_per_launch": normals,
                     "mfma_tflops": 3 * 2.0 * v * r * (ell + Lr) / launches_per_step / avg_s / 1e12})
         return out
-    if stage == "reorth":
-        byts = 3 * 4.0 * v * r   # read U twice (Gram, apply), write it once
+    if stage in ("reorth_gram", "reorth_apply"):
+        # the Gram pass reads U once; the apply pass reads and writes it
+        byts = (4.0 if stage == "reorth_gram" else 8.0) * v * r
         ach = byts / avg_s / 1e9
         out.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": ach / PEAK_HBM_GBS, "algorithmic_bytes_per_launch": byts})
         return out
+    if stage == "reorth_chol":
+        # one FP64 Cholesky (r^3/3) and triangular inverse (r^3/3) in one
+        # workgroup: a latency chain, far from this peak by construction
+        flops = 2.0 * (2.0 * r ** 3 / 3.0)
+        ach = flops / avg_s / 1e12
+        out.update({"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s (fp64)",
+                    "frac": ach / PEAK_FP64_TFLOPS, "algorithmic_flops_per_launch": flops})
+        return out
     if stage == "track_update":
-        byts = 2 * 4.0 * k * r * ell   # read-modify-write of the sampled basis rows
+        # read-modify-write of the touched basis rows (each sampled entry at
+        # most once), its coefficient row and its T value
+        byts = (2 * 4.0 * r + 4.0 + 4.0) * k * ell
+        ach = byts / avg_s / 1e9
+        out.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": ach / PEAK_HBM_GBS, "algorithmic_bytes_per_launch": byts})
+        return out
+    if stage == "sampled_t":
+        # recovered columns: k standardised rows (4n bytes), k indices in, k values out
+        byts = Lr * k * (4.0 * n + 8.0) / launches_per_step
         ach = byts / avg_s / 1e9
         out.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                     "frac": ach / PEAK_HBM_GBS, "algorithmic_bytes_per_launch": byts})

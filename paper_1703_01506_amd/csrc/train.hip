@@ -451,7 +451,8 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
   const int RB = (r + 15) / 16;
   const int ntile = RB * (RB + 1) / 2;
   const int64_t rpb = round_up(ceil_div(v, nb), kGramChunk);
-  RPT_STAGE("reorth", s);
+  {
+  RPT_STAGE("reorth_gram", s);
   switch (RB) {
     case 1: hipLaunchKernelGGL(gram_partial_kernel<1>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
     case 2: hipLaunchKernelGGL(gram_partial_kernel<2>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
@@ -463,9 +464,14 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
     default: hipLaunchKernelGGL(gram_partial_kernel<8>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
   }
   RPT_CHECK_LAUNCH();
-  hipLaunchKernelGGL(gram_reduce_kernel, dim3(static_cast<unsigned>(ceil_div(static_cast<int64_t>(ntile) * 256, 64))),
-                     dim3(64 * kRedWaves), 0, s, part, nb, ntile, r, gfull);
-  RPT_CHECK_LAUNCH();
+  }
+  {
+    RPT_STAGE("reorth_reduce", s);
+    hipLaunchKernelGGL(gram_reduce_kernel,
+                       dim3(static_cast<unsigned>(ceil_div(static_cast<int64_t>(ntile) * 256, 64))),
+                       dim3(64 * kRedWaves), 0, s, part, nb, ntile, r, gfull);
+    RPT_CHECK_LAUNCH();
+  }
   if (before_chol && *before_chol) RPT_TRY((*before_chol)());
   static bool attr_set = false;
   if (!attr_set) {
@@ -473,12 +479,16 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(chol_smem(kR)));
     attr_set = true;
   }
-  hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(kCholThreads), chol_smem(r), s, gfull, r, rth, rtl, info);
-  RPT_CHECK_LAUNCH();
+  {
+    RPT_STAGE("reorth_chol", s);
+    hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(kCholThreads), chol_smem(r), s, gfull, r, rth, rtl, info);
+    RPT_CHECK_LAUNCH();
+  }
   int64_t ab = ceil_div(ceil_div(v, 32), 4);
   if (ab > 512) ab = 512;  // two workgroups per CU; each wave then loops over tiles
   const unsigned blocks = static_cast<unsigned>(ab);
   const int KS = static_cast<int>(ceil_div(r, 16));
+  RPT_STAGE("reorth_apply", s);
   switch (KS) {
     case 1: hipLaunchKernelGGL(apply_rinv_kernel<1>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl); break;
     case 2: hipLaunchKernelGGL(apply_rinv_kernel<2>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl); break;

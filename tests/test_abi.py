@@ -93,3 +93,23 @@ def test_batched_recovery_validation(lib):
     assert lib.rpt_recover_maxnull_batched(arr, 2, ws, need, None) == -1
     # no studies is a valid no-op
     assert lib.rpt_recover_maxnull_batched(arr, 0, ws, need, None) == 0
+
+
+def test_rapidpt_end_to_end_validation(lib):
+    """rpt_rapidpt_maxnull checks the training and the recovery arguments and
+    the combined workspace before any launch."""
+    d = C.c_void_p(256)
+    v, n, ell, L_rec, r, k, prec = 5000, 20, 30, 70, 8, 40, 1
+    need = lib.rpt_rapidpt_workspace(v, n, ell, L_rec, r, k, prec)
+    assert need >= lib.rpt_train_workspace(v, n, ell, r, k, prec) + lib.rpt_recover_workspace(v, n, L_rec, r, k)
+    ws = C.c_void_p(512)
+
+    def call(n1=10, r_=r, k_=k, ws_bytes=need, batch=ell, passes=2):
+        return lib.rpt_rapidpt_maxnull(d, v, n, n, n1, d, ell, d, L_rec, d, r_, d, k_, passes, batch, 1.0, d, d, 7,
+                                       0, prec, d, d, d, d, d, ws, ws_bytes, None)
+
+    assert call(ws_bytes=need - 1) == -4      # workspace
+    assert call(n1=9) == -6                    # unbalanced designs are not provided
+    assert call(r_=129) == -1                  # rank above 128
+    assert call(k_=7) == -2                    # fewer sampled voxels than the rank
+    assert call(batch=ell + 1) == -1           # mini-batch larger than l
