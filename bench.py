@@ -141,6 +141,12 @@ def main():
     def step():
         return rpt.rapidpt_maxnull(Xd, Ld[:ell], Ld[ell:], U0d, omtd, omsd, omrd, passes=P, seed=seed)
 
+    # tile choices measured on these shapes (the library's autotuner)
+    tuned = {"naive_chunks": rpt.autotune_naive(Xd, Ld),
+             "recon_chunks_recovery": rpt.autotune_recover(v, r, L - ell, device=dev),
+             "recon_chunks_training": rpt.autotune_recover(v, r, ell, device=dev)}
+    log(f"autotuned {tuned}")
+
     def timed(fn, stage_events):
         """K calls of fn between two synchronisations; with stage_events the
         library's per-stage HIP events are recorded too (they cost time, so
@@ -226,6 +232,7 @@ def main():
         "stages_ms_per_step": {s: round(t, 4) for s, t in sorted(tot.items(), key=lambda kv: -kv[1])},
         "naivept_stages_ms_per_step": {s: round(q[0] / a.steps, 4) for s, q in nstages.items() if q},
         "rapidpt_quality": quality,
+        "autotuned": tuned,
     }
     print(json.dumps(out), flush=True)
 

@@ -102,6 +102,45 @@ int rpt_timing_query(const char* stage, double* total_ms, int64_t* count);
 int rpt_timing_stages(char* buf, size_t len);
 
 /* -------------------------------------------------------------------------
+ * Autotuning of tile choices.
+ *
+ * The NaivePT contraction and the fused reconstruction (recovery) split the
+ * voxels of every group of relabellings into chunks, one workgroup each.  The
+ * planners start from a rule of thumb (about 1,280 workgroups); these calls
+ * time the candidate chunk counts around it (half, same, 2, 4, 8 and 16 times,
+ * multiples of 8) on the given shape and keep the fastest in the library's
+ * plan table, which every later call of that exact shape (v, L, n or r,
+ * precision) uses.  Workspace sizes already cover every candidate, so tuned
+ * and untuned calls take the same workspaces, and results do not depend on
+ * the choice (the column maxima are exact maxima of the same values).
+ *
+ * rpt_autotune_naive: prepares X, then times `reps` max-only contractions of
+ *   `labels` (L x n) per candidate.  Arguments and workspace as
+ *   rpt_naive_maxnull.  *chosen (HOST int32) receives the kept count.
+ * rpt_autotune_recover: times `reps` reconstruction calls per candidate for
+ *   L_rec columns of rank r over v voxels on synthetic data in its own
+ *   workspace (rpt_autotune_recover_workspace bytes); sigma = 1, so every
+ *   voxel draws its noise, the fused path's full work.
+ * Both synchronise `stream`, create and destroy HIP events, and must not be
+ * called during graph capture.
+ * rpt_autotune_save / rpt_autotune_load: the plan table as text, one line
+ *   "kernel v L dim variant chunks" per entry; return the number of entries
+ *   written / read, or -1 if the file cannot be opened.  A file named by the
+ *   environment variable RPT_TUNE_CACHE is read on first use of the table.
+ * rpt_autotune_clear empties the table; rpt_autotune_count reports its size.
+ * ------------------------------------------------------------------------- */
+rpt_status rpt_autotune_naive(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
+                              const uint8_t* labels, int64_t L, int prec, int32_t reps,
+                              void* ws, size_t ws_bytes, void* stream, int32_t* chosen);
+size_t rpt_autotune_recover_workspace(int64_t v, int32_t r, int64_t L_rec);
+rpt_status rpt_autotune_recover(int64_t v, int32_t r, int64_t L_rec, int32_t reps,
+                                void* ws, size_t ws_bytes, void* stream, int32_t* chosen);
+int rpt_autotune_save(const char* path);
+int rpt_autotune_load(const char* path);
+void rpt_autotune_clear(void);
+int rpt_autotune_count(void);
+
+/* -------------------------------------------------------------------------
  * NaivePT -- Alg. 1 (Sec. 2.1).
  *
  * For each of the L relabellings, computes the t statistic at all v voxels and

@@ -7,6 +7,12 @@ library and fails loudly if it has not been built
 """
 from . import _lib
 from .api import (  # noqa: F401
+    autotune_clear,
+    autotune_count,
+    autotune_load,
+    autotune_naive,
+    autotune_recover,
+    autotune_save,
     complete,
     corrected_pvalues,
     fwer_threshold,
@@ -31,5 +37,7 @@ _lib.load()
 __all__ = [
     "naive_maxnull", "sampled_tstat", "complete", "reorth", "train_subspace", "recover_maxnull",
     "rapidpt_maxnull", "recover_maxnull_batched", "recover_studies_prepare", "recover_studies_launch",
-    "observed_tstat", "fwer_threshold", "corrected_pvalues", "rejection_counts", "masked_loss_fwd", "masked_loss_bwd", "MaskedSubspaceLoss", "masked_subspace_loss",
+    "observed_tstat", "fwer_threshold", "corrected_pvalues", "rejection_counts", "masked_loss_fwd", "masked_loss_bwd",
+    "MaskedSubspaceLoss", "masked_subspace_loss", "autotune_naive", "autotune_recover", "autotune_save",
+    "autotune_load", "autotune_clear", "autotune_count",
 ]

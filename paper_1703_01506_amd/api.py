@@ -7,6 +7,8 @@ Functions raise RPTError (a RuntimeError) with the library's status string.
 """
 from __future__ import annotations
 
+import ctypes as C
+
 import torch
 
 from . import _lib
@@ -343,3 +345,55 @@ def masked_loss_bwd(U, W, omega_ptr, omega_idx, resid, grad_scale=None):
                                  _ptr(dU), _ptr(dW), _ptr(gs), _stream(U.device))
     _lib.check(rc, "rpt_masked_loss_bwd")
     return dU, dW
+
+
+def autotune_naive(X, labels, n1: int | None = None, prec: str = "split_bf16", reps: int = 3) -> int:
+    """Times the NaivePT contraction's candidate voxel-chunk counts on this
+    shape and keeps the fastest in the library's plan table (synchronises)."""
+    lib = _lib.load()
+    v, n, ldx = _data(X)
+    labels = _dev(labels, torch.uint8, "labels", 2).contiguous()
+    L = labels.shape[0]
+    n1 = n // 2 if n1 is None else int(n1)
+    ws = _workspace(lib.rpt_naive_workspace(v, n, L, PREC[prec]), X.device)
+    chosen = C.c_int32(0)
+    rc = lib.rpt_autotune_naive(_ptr(X), v, n, ldx, n1, _ptr(labels), L, PREC[prec], int(reps), _ptr(ws), ws.numel(),
+                                _stream(X.device), C.byref(chosen))
+    _lib.check(rc, "rpt_autotune_naive")
+    return chosen.value
+
+
+def autotune_recover(v: int, r: int, L_rec: int, reps: int = 2, device=None) -> int:
+    """Times the fused reconstruction's candidate voxel-chunk counts for
+    (v, r, L_rec) and keeps the fastest in the plan table (synchronises)."""
+    lib = _lib.load()
+    device = torch.device("cuda") if device is None else device
+    ws = _workspace(lib.rpt_autotune_recover_workspace(v, r, L_rec), device)
+    chosen = C.c_int32(0)
+    rc = lib.rpt_autotune_recover(v, r, L_rec, int(reps), _ptr(ws), ws.numel(), _stream(device), C.byref(chosen))
+    _lib.check(rc, "rpt_autotune_recover")
+    return chosen.value
+
+
+def autotune_save(path: str) -> int:
+    """Writes the plan table as text; returns the number of entries."""
+    n = _lib.load().rpt_autotune_save(str(path).encode())
+    if n < 0:
+        raise OSError(f"cannot write {path}")
+    return n
+
+
+def autotune_load(path: str) -> int:
+    """Reads a plan table written by autotune_save; returns the number of entries."""
+    n = _lib.load().rpt_autotune_load(str(path).encode())
+    if n < 0:
+        raise OSError(f"cannot read {path}")
+    return n
+
+
+def autotune_clear() -> None:
+    _lib.load().rpt_autotune_clear()
+
+
+def autotune_count() -> int:
+    return _lib.load().rpt_autotune_count()

@@ -161,7 +161,7 @@ TrainWs train_carve(void* ws, int64_t v, int n, int n1, int ell, int r, int k, i
   TrainWs t;
   t.p = prep_carve(c, v, n, n1, naive_flags(prec, false));
   const NaivePlan pl = naive_plan(v, ell, n, prec, true);
-  t.partial = c.take<float>(static_cast<size_t>(pl.nc) * ell);
+  t.partial = c.take<float>(static_cast<size_t>(pl.nc_cap) * ell);
   t.T = c.take<float>(static_cast<size_t>(ell) * v);
   t.W = c.take<float>(static_cast<size_t>(ell) * r);
   t.resid = c.take<float>(static_cast<size_t>(ell) * k);
@@ -546,6 +546,131 @@ rpt_status rpt_recover_maxnull_batched(const rpt_study* studies, int32_t n_studi
     RPT_TRY(recon_launch(st.U, st.v, st.r, W, st.L_rec, st.col0, st.seed, RPT_STREAM_RECOVERY, st.sigma_mu,
                          st.max_out, nullptr, nullptr, rws, s, st.study));
   }
+  return RPT_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// autotuning of the voxel-chunk counts (synchronises the stream; not for graph
+// capture; the measured choice is kept for the shape in the plan table)
+namespace rpt {
+namespace {
+// times `reps` calls of fn (after one untimed call); -1 on a HIP error
+template <class F>
+float time_calls(F fn, int reps, hipStream_t s) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  float ms = -1.0f;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) goto done;
+  if (fn() != RPT_OK) goto done;
+  if (hipEventRecord(e0, s) != hipSuccess) goto done;
+  for (int q = 0; q < reps; ++q)
+    if (fn() != RPT_OK) goto done;
+  if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess) goto done;
+  if (hipEventElapsedTime(&ms, e0, e1) != hipSuccess) ms = -1.0f;
+done:
+  if (e0) (void)hipEventDestroy(e0);
+  if (e1) (void)hipEventDestroy(e1);
+  return ms;
+}
+
+struct ReconTuneWs {
+  void* rws;
+  float *U, *W, *sm, *out;
+};
+ReconTuneWs recon_tune_carve(void* ws, int64_t v, int32_t r, int64_t L, size_t* total) {
+  Carver c(ws);
+  ReconTuneWs t;
+  t.rws = c.take<char>(recon_bytes(v, L, r));
+  t.U = c.take<float>(static_cast<size_t>(v) * r);
+  t.W = c.take<float>(static_cast<size_t>(L > 0 ? L : 1) * r);
+  t.sm = c.take<float>(2);
+  t.out = c.take<float>(static_cast<size_t>(L > 0 ? L : 1));
+  if (total) *total = c.off;
+  return t;
+}
+}  // namespace
+}  // namespace rpt
+
+extern "C" {
+
+rpt_status rpt_autotune_naive(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* labels,
+                              int64_t L, int prec, int32_t reps, void* ws, size_t ws_bytes, void* stream,
+                              int32_t* chosen) {
+  if (!design_ok(v, n, ldx, n1) || L < 1 || reps < 1 || !X || !labels || !chosen) return RPT_ERR_INVALID_ARG;
+  if (prec != RPT_FP32 && prec != RPT_SPLIT_BF16) return RPT_ERR_INVALID_ARG;
+  const bool unbal = 2 * n1 != n;
+  if ((unbal && prec != RPT_FP32) || (prec == RPT_FP32 && n > 128)) return RPT_ERR_UNSUPPORTED;
+  if (!ws_ok(ws, ws_bytes, rpt_naive_workspace(v, n, L, prec))) return RPT_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const int flags = naive_flags(prec, unbal);
+  Carver c(ws);
+  PrepX p = prep_carve(c, v, n, n1, flags);
+  float* partial = c.take<float>(static_cast<size_t>(naive_plan(v, L, n, prec, false).nc_cap) * L);
+  RPT_TRY(prep_launch(p, X, ldx, RPT_TAIL_SIGNED, flags, s));
+  const NaivePlan base = naive_plan(v, L, n, prec, false);
+  int cand[kMaxChunkCandidates];
+  const int m = chunk_candidates(base.nc_heur, round_up(base.vt, 8), cand);
+  int best = base.nc_heur;
+  float best_ms = 0.0f;
+  for (int q = 0; q < m; ++q) {
+    const NaivePlan pl = naive_plan(v, L, n, prec, false, cand[q]);
+    const float ms = time_calls(
+        [&]() { return naive_launch(p, pl, labels, L, RPT_TAIL_SIGNED, prec, partial, nullptr, nullptr, s); }, reps,
+        s);
+    if (ms < 0.0f) return RPT_ERR_HIP;
+    if (q == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = cand[q];
+    }
+  }
+  set_tuned_chunks(kTuneNaive, v, L, n, 2 * prec, best);
+  *chosen = best;
+  return RPT_OK;
+}
+
+size_t rpt_autotune_recover_workspace(int64_t v, int32_t r, int64_t L_rec) {
+  if (v < 1 || r < 1 || L_rec < 1) return 0;
+  size_t total = 0;
+  recon_tune_carve(nullptr, v, r, L_rec, &total);
+  return total;
+}
+
+rpt_status rpt_autotune_recover(int64_t v, int32_t r, int64_t L_rec, int32_t reps, void* ws, size_t ws_bytes,
+                                void* stream, int32_t* chosen) {
+  if (v < 1 || r < 1 || r > 128 || L_rec < 1 || reps < 1 || !chosen) return RPT_ERR_INVALID_ARG;
+  if (!ws_ok(ws, ws_bytes, rpt_autotune_recover_workspace(v, r, L_rec))) return RPT_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const ReconTuneWs t = recon_tune_carve(ws, v, r, L_rec, nullptr);
+  // a zero basis and zero coefficients with sigma = 1: every voxel draws its
+  // normal, the fused path's full work (its time does not depend on values)
+  const float sm_host[2] = {1.0f, 0.0f};
+  if (hipMemsetAsync(t.U, 0, sizeof(float) * static_cast<size_t>(v) * r, s) != hipSuccess ||
+      hipMemsetAsync(t.W, 0, sizeof(float) * static_cast<size_t>(L_rec) * r, s) != hipSuccess ||
+      hipMemcpyAsync(t.sm, sm_host, sizeof(sm_host), hipMemcpyHostToDevice, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    set_hip_error(hipGetLastError());
+    return RPT_ERR_HIP;
+  }
+  int cand[kMaxChunkCandidates];
+  const int m = recon_chunk_candidates(v, L_rec, r, cand);
+  int best = cand[0];
+  float best_ms = 0.0f;
+  for (int q = 0; q < m; ++q) {
+    const float ms = time_calls(
+        [&]() {
+          return recon_launch(t.U, v, r, t.W, L_rec, 0, 1, RPT_STREAM_RECOVERY, t.sm, t.out, nullptr, nullptr, t.rws,
+                              s, 0, cand[q]);
+        },
+        reps, s);
+    if (ms < 0.0f) return RPT_ERR_HIP;
+    if (q == 0 || ms < best_ms) {
+      best_ms = ms;
+      best = cand[q];
+    }
+  }
+  set_tuned_chunks(kTuneRecon, v, L_rec, r, 0, best);
+  *chosen = best;
   return RPT_OK;
 }
 

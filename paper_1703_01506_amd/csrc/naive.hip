@@ -582,7 +582,7 @@ void* pick_f32(int ks) {
 
 }  // namespace
 
-NaivePlan naive_plan(int64_t v, int64_t L, int n, int prec, bool store) {
+NaivePlan naive_plan(int64_t v, int64_t L, int n, int prec, bool store, int force_nc) {
   NaivePlan pl;
   // split max-only path: 4 relabelling tiles per wave (data shared through
   // LDS, two waves per SIMD); the T-writing path and the FP32 path use 2.
@@ -590,21 +590,27 @@ NaivePlan naive_plan(int64_t v, int64_t L, int n, int prec, bool store) {
   pl.vt = round_up(v, 32) / 32;
   const int64_t group = 4 * pl.pt * 32;
   pl.pg = static_cast<int>(ceil_div(L > 0 ? L : 1, group));
+  // rule of thumb: about 1,280 workgroups; a measured choice replaces it
   int64_t nc = round_up(ceil_div(1280, pl.pg), 8);
   const int64_t ncmax = round_up(pl.vt, 8);
   if (nc > ncmax) nc = ncmax;
   if (nc < 8) nc = 8;
+  pl.nc_heur = static_cast<int>(nc);
+  pl.nc_cap = static_cast<int>(chunk_cap(nc, ncmax));
+  int64_t pick = force_nc > 0 ? force_nc : tuned_chunks(kTuneNaive, v, L, n, 2 * prec + (store ? 1 : 0));
+  if (pick >= 8 && pick <= pl.nc_cap && pick % 8 == 0) nc = pick;
   pl.nc = static_cast<int>(nc);
   pl.tpc = static_cast<int>(ceil_div(pl.vt, nc));
   return pl;
 }
 
 size_t naive_bytes(int64_t v, int n, int64_t L, int prec) {
-  // the larger of the two plans (max-only / T-writing)
+  // the larger of the two plans (max-only / T-writing), at their largest
+  // candidate chunk count
   int64_t nc = 0;
   for (int st = 0; st < 2; ++st) {
     NaivePlan pl = naive_plan(v, L, n, prec, st != 0);
-    if (pl.nc > nc) nc = pl.nc;
+    if (pl.nc_cap > nc) nc = pl.nc_cap;
   }
   return round_up(nc * (L > 0 ? L : 1) * 4, 256);
 }

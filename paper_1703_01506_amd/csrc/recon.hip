@@ -574,11 +574,15 @@ void* pick_filter(int ks) {
 }
 
 struct ReconPlan {
-  int ks, pt, pg, nc, tpc;
+  int ks, pt, pg, nc, tpc, nc_heur, nc_cap;
   int64_t vpad, vt;
 };
 
-ReconPlan recon_plan(int64_t v, int64_t L, int r, int pt) {
+constexpr int kFilterPT = 4, kFusedPT = 1;
+
+// tuned: a measured chunk count of the fused kernel may replace the rule of
+// thumb (force_nc > 0: the autotuner's trial)
+ReconPlan recon_plan(int64_t v, int64_t L, int r, int pt, int force_nc = 0) {
   ReconPlan pl;
   pl.ks = static_cast<int>(ceil_div(r, 16));
   pl.pt = pt;
@@ -590,12 +594,16 @@ ReconPlan recon_plan(int64_t v, int64_t L, int r, int pt) {
   const int64_t ncmax = round_up(pl.vt, 8);
   if (nc > ncmax) nc = ncmax;
   if (nc < 8) nc = 8;
+  pl.nc_heur = static_cast<int>(nc);
+  pl.nc_cap = pt == kFusedPT ? static_cast<int>(chunk_cap(nc, ncmax)) : static_cast<int>(nc);
+  if (pt == kFusedPT) {
+    const int64_t pick = force_nc > 0 ? force_nc : tuned_chunks(kTuneRecon, v, L, r, 0);
+    if (pick >= 8 && pick <= pl.nc_cap && pick % 8 == 0) nc = pick;
+  }
   pl.nc = static_cast<int>(nc);
   pl.tpc = static_cast<int>(ceil_div(pl.vt, nc));
   return pl;
 }
-
-constexpr int kFilterPT = 4, kFusedPT = 1;
 
 void recon_carve(Carver& c, int64_t v, int64_t L, int r, uint16_t** ukb, float** smax, float** partial,
                  unsigned** umax, int** path) {
@@ -603,12 +611,17 @@ void recon_carve(Carver& c, int64_t v, int64_t L, int r, uint16_t** ukb, float**
   const ReconPlan pu = recon_plan(v, L, r, kFusedPT);
   *ukb = c.take<uint16_t>(static_cast<size_t>(pf.ks) * pf.vpad * 32);
   *smax = c.take<float>(static_cast<size_t>(L > 0 ? L : 1) * pf.nc * 32);
-  *partial = c.take<float>(static_cast<size_t>(L > 0 ? L : 1) * pu.nc);
+  *partial = c.take<float>(static_cast<size_t>(L > 0 ? L : 1) * pu.nc_cap);
   *umax = c.take<unsigned>(64);
   *path = c.take<int>(64);
 }
 
 }  // namespace
+
+int recon_chunk_candidates(int64_t v, int64_t L, int r, int* out) {
+  const ReconPlan pu = recon_plan(v, L, r, kFusedPT);
+  return chunk_candidates(pu.nc_heur, round_up(pu.vt, 8), out);
+}
 
 size_t recon_bytes(int64_t v, int64_t L, int r) {
   Carver c(nullptr);
@@ -622,7 +635,7 @@ size_t recon_bytes(int64_t v, int64_t L, int r) {
 
 rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_t L, int64_t col0, uint64_t seed,
                         int stream_id, const float* sigma_mu, float* out_max, const float* Tmax_for_gap,
-                        float* gap_out, void* ws, hipStream_t s, unsigned study) {
+                        float* gap_out, void* ws, hipStream_t s, unsigned study, int force_nc) {
   if (L == 0) return RPT_OK;
   if (r < 1 || r > kRMaxRefine) return RPT_ERR_UNSUPPORTED;
   Carver c(ws);
@@ -632,7 +645,7 @@ rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_
   int* path;
   recon_carve(c, v, L, r, &ukb, &smax, &partial, &umax, &path);
   const ReconPlan pl = recon_plan(v, L, r, kFilterPT);
-  const ReconPlan pu = recon_plan(v, L, r, kFusedPT);
+  const ReconPlan pu = recon_plan(v, L, r, kFusedPT, force_nc);
 
   RPT_STAGE("recon_total", s);
   hipLaunchKernelGGL(recon_init_kernel, dim3(1), dim3(1), 0, s, umax);

@@ -178,8 +178,21 @@ struct NaivePlan {
   int nc = 0;       // voxel chunks (multiple of 8)
   int tpc = 0;      // voxel tiles per chunk
   int64_t vt = 0;   // voxel tiles
+  int nc_heur = 0;  // the rule-of-thumb chunk count
+  int nc_cap = 0;   // the largest candidate (workspace bound)
 };
-NaivePlan naive_plan(int64_t v, int64_t L, int n, int prec, bool store);
+// force_nc > 0 replaces the chunk count (the autotuner's trials)
+NaivePlan naive_plan(int64_t v, int64_t L, int n, int prec, bool store, int force_nc = 0);
+
+// Voxel-chunk counts chosen by measurement (tune.hip): the candidates around
+// the planner's rule of thumb (ascending, at most 6), the largest of them, and
+// the table of measured choices keyed by kernel and shape (0: none).
+enum { kTuneNaive = 0, kTuneRecon = 1 };
+constexpr int kMaxChunkCandidates = 6;
+int chunk_candidates(int64_t nc_heur, int64_t ncmax, int* out);
+int64_t chunk_cap(int64_t nc_heur, int64_t ncmax);
+int tuned_chunks(int kernel, int64_t v, int64_t L, int dim, int variant);
+void set_tuned_chunks(int kernel, int64_t v, int64_t L, int dim, int variant, int nc);
 size_t naive_bytes(int64_t v, int n, int64_t L, int prec);
 rpt_status naive_launch(const PrepX& p, const NaivePlan& plan, const uint8_t* labels, int64_t L, int tail,
                         int prec, float* partial, float* T_out, float* max_out, hipStream_t s);
@@ -215,7 +228,10 @@ rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, 
 size_t recon_bytes(int64_t v, int64_t L, int r);
 rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_t L, int64_t col0,
                         uint64_t seed, int stream_id, const float* sigma_mu, float* out_max,
-                        const float* Tmax_for_gap, float* gap_out, void* ws, hipStream_t s, unsigned study = 0);
+                        const float* Tmax_for_gap, float* gap_out, void* ws, hipStream_t s, unsigned study = 0,
+                        int force_nc = 0);
+// the fused reconstruction's chunk-count candidates for one shape (tune.hip)
+int recon_chunk_candidates(int64_t v, int64_t L, int r, int* out);
 
 // Orthonormalisation (one Cholesky-QR pass).  before_chol, when given, is
 // called once the Gram reduction is enqueued and before the single-workgroup

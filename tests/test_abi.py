@@ -113,3 +113,27 @@ def test_rapidpt_end_to_end_validation(lib):
     assert call(r_=129) == -1                  # rank above 128
     assert call(k_=7) == -2                    # fewer sampled voxels than the rank
     assert call(batch=ell + 1) == -1           # mini-batch larger than l
+
+
+def test_autotune_table_roundtrip(lib, tmp_path):
+    """The plan table is plain text and survives a save / load round trip
+    (no GPU: entries are written by hand)."""
+    lib.rpt_autotune_clear()
+    assert lib.rpt_autotune_count() == 0
+    src = tmp_path / "plans.txt"
+    src.write_text("0 250000 10000 100 2 128\n1 250000 9700 100 0 64\n0 5 5 5 5 12\n")  # last: not a multiple of 8
+    assert lib.rpt_autotune_load(str(src).encode()) == 2
+    assert lib.rpt_autotune_count() == 2
+    out = tmp_path / "saved.txt"
+    assert lib.rpt_autotune_save(str(out).encode()) == 2
+    assert sorted(out.read_text().split("\n")[:2]) == ["0 250000 10000 100 2 128", "1 250000 9700 100 0 64"]
+    assert lib.rpt_autotune_load(str(tmp_path / "missing.txt").encode()) == -1
+    # workspaces cover every candidate: unchanged by a tuned entry for the shape
+    before = lib.rpt_naive_workspace(250000, 100, 10000, 1)
+    lib.rpt_autotune_clear()
+    assert lib.rpt_naive_workspace(250000, 100, 10000, 1) == before
+    dummy = C.c_void_p(256)
+    chosen = C.c_int32(0)
+    assert lib.rpt_autotune_naive(dummy, 1000, 20, 20, 10, dummy, 0, 1, 3, dummy, 1 << 30, None,
+                                  C.byref(chosen)) == -1   # L = 0
+    assert lib.rpt_autotune_recover(1000, 129, 50, 2, dummy, 1 << 30, None, C.byref(chosen)) == -1
