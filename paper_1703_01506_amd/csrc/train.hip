@@ -422,8 +422,8 @@ __global__ __launch_bounds__(kBlock) void literal_resid_max_kernel(const float* 
 }
 
 int gram_blocks(int64_t v) {
-  int64_t nb = ceil_div(v, 512);
-  if (nb > 512) nb = 512;
+  int64_t nb = ceil_div(v, 256);
+  if (nb > 768) nb = 768;  // three workgroups per CU (150 VGPRs: three waves per SIMD)
   if (nb < 1) nb = 1;
   return static_cast<int>(nb);
 }
