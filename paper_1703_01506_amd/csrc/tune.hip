@@ -112,6 +112,7 @@ void rpt_autotune_clear(void) {
 
 int rpt_autotune_count(void) {
   std::lock_guard<std::mutex> lk(g_tune_mu);
+  read_env_once();
   return static_cast<int>(g_tuned.size());
 }
 

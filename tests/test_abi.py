@@ -4,6 +4,7 @@ device work, so these run without a GPU)."""
 import ctypes as C
 import os
 import re
+import sys
 
 import pytest
 
@@ -137,3 +138,21 @@ def test_autotune_table_roundtrip(lib, tmp_path):
     assert lib.rpt_autotune_naive(dummy, 1000, 20, 20, 10, dummy, 0, 1, 3, dummy, 1 << 30, None,
                                   C.byref(chosen)) == -1   # L = 0
     assert lib.rpt_autotune_recover(1000, 129, 50, 2, dummy, 1 << 30, None, C.byref(chosen)) == -1
+
+
+def test_autotune_table_from_environment(tmp_path):
+    """A table named by RPT_TUNE_CACHE is read on the table's first use (in a
+    fresh process, so that this process's table is not involved)."""
+    import subprocess
+    src = tmp_path / "plans.txt"
+    src.write_text("0 250000 10000 100 2 128\n1 250000 9700 100 0 64\n")
+    code = ("import sys; sys.path.insert(0, %r); from paper_1703_01506_amd import _lib; "
+            "l = _lib.load(); print(l.rpt_autotune_count())" % ROOT)
+    env = dict(os.environ, RPT_TUNE_CACHE=str(src))
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "2"
+    env["RPT_TUNE_CACHE"] = str(tmp_path / "missing.txt")  # unreadable file: empty table, no error
+    out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip().splitlines()[-1] == "0"
