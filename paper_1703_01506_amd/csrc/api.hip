@@ -1,6 +1,8 @@
 // C ABI of librpt: argument validation, workspace carving and launch order.
 // Every entry point enqueues on the caller's stream and never synchronises.
+#include <algorithm>
 #include <mutex>
+#include <vector>
 
 #include "rpt_internal.h"
 
@@ -483,14 +485,45 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
 // several studies, uneven sampled sets
 namespace rpt {
 namespace {
-size_t study_bytes(const rpt_study& st) {
+// Batched workspace: [counters][transient: the largest study's prep, sampled
+// values and Complete buffers, used by the studies in turn][per study: W and
+// the reconstruction buffers, kept until the shared reconstruction launch].
+size_t study_transient_bytes(const rpt_study& st) {
   Carver c(nullptr);
   prep_carve(c, st.v, st.n, st.n1, kPrepRows);
   c.take<float>(static_cast<size_t>(st.nnz > 0 ? st.nnz : 1));
-  c.take<float>(static_cast<size_t>(st.L_rec > 0 ? st.L_rec : 1) * st.r);
-  c.take<char>(recon_bytes(st.v, st.L_rec, st.r));
   c.take<char>(complete_split_bytes(st.L_rec, st.r));
   return c.off;
+}
+int batch_ks(const rpt_study* studies, int32_t n) {
+  int ks = 1;
+  for (int32_t q = 0; q < n; ++q) {
+    const int k = (studies[q].r + 15) / 16;
+    if (studies[q].L_rec > 0 && k > ks) ks = k;
+  }
+  return ks;
+}
+struct BatchLayout {
+  int* counters;
+  void* transient;
+  std::vector<float*> W;
+  std::vector<void*> rws;
+  size_t total;
+};
+BatchLayout batch_layout(void* ws, const rpt_study* studies, int32_t n, int ks) {
+  BatchLayout b;
+  Carver c(ws);
+  b.counters = c.take<int>(recon_batch_counters(n));
+  size_t tr = 256;
+  for (int32_t q = 0; q < n; ++q) tr = std::max(tr, study_transient_bytes(studies[q]));
+  b.transient = c.take<char>(tr);
+  for (int32_t q = 0; q < n; ++q) {
+    const rpt_study& st = studies[q];
+    b.W.push_back(c.take<float>(static_cast<size_t>(st.L_rec > 0 ? st.L_rec : 1) * st.r));
+    b.rws.push_back(c.take<char>(st.L_rec > 0 ? recon_bytes(st.v, st.L_rec, st.r, ks) : 256));
+  }
+  b.total = c.off;
+  return b;
 }
 rpt_status study_check(const rpt_study& st) {
   if (!design_ok(st.v, st.n, st.ldx, st.n1)) return RPT_ERR_INVALID_ARG;
@@ -510,42 +543,42 @@ extern "C" {
 
 size_t rpt_recover_batched_workspace(const rpt_study* studies, int32_t n_studies) {
   if (!studies || n_studies < 0) return 0;
-  size_t mx = 256;
-  for (int32_t q = 0; q < n_studies; ++q) {
+  for (int32_t q = 0; q < n_studies; ++q)
     if (study_check(studies[q]) != RPT_OK) return 0;
-    const size_t b = study_bytes(studies[q]);
-    if (b > mx) mx = b;
-  }
-  return mx;
+  return batch_layout(nullptr, studies, n_studies, batch_ks(studies, n_studies)).total;
 }
 
 rpt_status rpt_recover_maxnull_batched(const rpt_study* studies, int32_t n_studies, void* ws, size_t ws_bytes,
                                        void* stream) {
   if (n_studies < 0 || (n_studies > 0 && !studies)) return RPT_ERR_INVALID_ARG;
-  size_t need = 256;
-  for (int32_t q = 0; q < n_studies; ++q) {
-    RPT_TRY(study_check(studies[q]));
-    const size_t b = study_bytes(studies[q]);
-    if (b > need) need = b;
-  }
+  for (int32_t q = 0; q < n_studies; ++q) RPT_TRY(study_check(studies[q]));
+  const int ks = batch_ks(studies, n_studies);
+  const size_t need = batch_layout(nullptr, studies, n_studies, ks).total;
   if (!ws_ok(ws, ws_bytes, need)) return RPT_ERR_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const BatchLayout lay = batch_layout(ws, studies, n_studies, ks);
+  std::vector<ReconStudy> rec;
+  // per study: sampled t and Complete in the shared region, then the study's
+  // own copy of U for the reconstruction
   for (int32_t q = 0; q < n_studies; ++q) {
     const rpt_study& st = studies[q];
     if (st.L_rec == 0) continue;
-    Carver c(ws);
+    Carver c(lay.transient);
     PrepX p = prep_carve(c, st.v, st.n, st.n1, kPrepRows);
     float* y = c.take<float>(static_cast<size_t>(st.nnz > 0 ? st.nnz : 1));
-    float* W = c.take<float>(static_cast<size_t>(st.L_rec) * st.r);
-    void* rws = c.take<char>(recon_bytes(st.v, st.L_rec, st.r));
     void* gb = c.take<char>(complete_split_bytes(st.L_rec, st.r));
+    float* W = lay.W[q];
     RPT_TRY(prep_launch(p, st.X, st.ldx, RPT_TAIL_SIGNED, kPrepRows, s));
     RPT_TRY(sampled_launch(p, st.labels, st.L_rec, st.omega_idx, 0, nullptr, y, s, st.omega_ptr));
     RPT_TRY(complete_run(st.U, st.v, st.r, st.omega_idx, 0, y, nullptr, 0, nullptr, st.L_rec, W, nullptr, st.info,
                          nullptr, s, nullptr, nullptr, st.omega_ptr, gb));
-    RPT_TRY(recon_launch(st.U, st.v, st.r, W, st.L_rec, st.col0, st.seed, RPT_STREAM_RECOVERY, st.sigma_mu,
-                         st.max_out, nullptr, nullptr, rws, s, st.study));
+    const ReconStudy rs{st.U, st.v, st.r, W, st.L_rec, st.col0, st.seed, st.sigma_mu, st.max_out, lay.rws[q],
+                        st.study};
+    RPT_TRY(recon_prepare_study(rs, ks, s));
+    rec.push_back(rs);
   }
+  // U w + noise + max of all studies: persistent launches over their work items
+  if (!rec.empty()) RPT_TRY(recon_batched(rec.data(), static_cast<int>(rec.size()), ks, lay.counters, s));
   return RPT_OK;
 }
 

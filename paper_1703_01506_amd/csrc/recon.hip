@@ -367,14 +367,15 @@ __device__ __forceinline__ void box_muller4(const unsigned c[4], float z[4]) {
   z[3] = r2 * __builtin_amdgcn_sinf(t2);
 }
 
+// One work item of the fused pass: permutation group j % pg and voxel chunk
+// xcd + 8 (j / pg), so that every chunk of a study stays on one XCD (its U
+// tiles are fetched into that XCD's L2 once for all permutation groups).
 template <int KS, int PT, bool ALIGNED>
-__global__ __launch_bounds__(kBlock, ALIGNED ? 3 : 2) void recon_fused_kernel(FusedArgs a) {
+__device__ __forceinline__ void fused_item(const FusedArgs& a, int xcd, int j) {
   __shared__ __align__(16) uint16_t us[2][KS][2][64 * 8];
   typedef __attribute__((address_space(3))) void lds_void;
   typedef const __attribute__((address_space(1))) void gbl_void;
-  if (*a.path != 0) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, col = lane & 31;
-  const int b = blockIdx.x, xcd = b & 7, j = b >> 3;
   const int pg = j % a.pg;
   const int chunk = xcd + 8 * (j / a.pg);
   const int64_t pbase = static_cast<int64_t>(pg) * (4 * PT * 32) + static_cast<int64_t>(wave) * (PT * 32);
@@ -522,6 +523,50 @@ __global__ __launch_bounds__(kBlock, ALIGNED ? 3 : 2) void recon_fused_kernel(Fu
   }
 }
 
+template <int KS, int PT, bool ALIGNED>
+__global__ __launch_bounds__(kBlock, ALIGNED ? 3 : 2) void recon_fused_kernel(FusedArgs a) {
+  if (*a.path != 0) return;
+  fused_item<KS, PT, ALIGNED>(a, static_cast<int>(blockIdx.x & 7), static_cast<int>(blockIdx.x >> 3));
+}
+
+// ---------------------------------------------------------------- several studies
+// The fused pass of up to kPersistMax studies in one persistent launch.  The
+// work items of all studies form eight queues, one per XCD (item (study, j)
+// of queue x is block 8 j + x of that study's own grid); workgroup b serves
+// queue b % 8 through an atomic counter until the queue is empty, so every
+// workgroup exits once all items are taken, and results equal the per-study
+// launches exactly.  Studies share the launch's KS (smaller ranks are padded
+// with zero U columns, whose products add exact zeros).
+constexpr int kPersistMax = 16;
+struct PersistTable {
+  FusedArgs st[kPersistMax];
+  int64_t items[kPersistMax];  // items per queue of each study (pg nc / 8)
+  int ns;
+  int64_t total;               // items per queue of all studies
+  int* counters;               // [8], zero at launch
+};
+
+template <int KS, int PT, bool ALIGNED>
+__global__ __launch_bounds__(kBlock, ALIGNED ? 3 : 2) void recon_fused_persistent_kernel(PersistTable t) {
+  __shared__ int64_t item_s;
+  const int x = static_cast<int>(blockIdx.x & 7);
+  for (;;) {
+    __syncthreads();  // the previous item's LDS reads are done; item_s is free
+    if (threadIdx.x == 0) item_s = atomicAdd(t.counters + x, 1);
+    __syncthreads();
+    const int64_t it = item_s;
+    if (it >= t.total) break;
+    int q = 0;
+    int64_t base = 0;
+    while (q + 1 < t.ns && it >= base + t.items[q]) {
+      base += t.items[q];
+      ++q;
+    }
+    if (*t.st[q].path != 0) continue;  // this study takes the exact-pruning path
+    fused_item<KS, PT, ALIGNED>(t.st[q], x, static_cast<int>(it - base));
+  }
+}
+
 __global__ void recon_fused_finalize_kernel(const float* __restrict__ partial, int nc, int64_t L,
                                             const float* sigma_mu, const int* path, float* out,
                                             const float* tmax, float* gap) {
@@ -605,81 +650,64 @@ ReconPlan recon_plan(int64_t v, int64_t L, int r, int pt, int force_nc = 0) {
   return pl;
 }
 
-void recon_carve(Carver& c, int64_t v, int64_t L, int r, uint16_t** ukb, float** smax, float** partial,
-                 unsigned** umax, int** path) {
-  const ReconPlan pf = recon_plan(v, L, r, kFilterPT);
-  const ReconPlan pu = recon_plan(v, L, r, kFusedPT);
-  *ukb = c.take<uint16_t>(static_cast<size_t>(pf.ks) * pf.vpad * 32);
-  *smax = c.take<float>(static_cast<size_t>(L > 0 ? L : 1) * pf.nc * 32);
-  *partial = c.take<float>(static_cast<size_t>(L > 0 ? L : 1) * pu.nc_cap);
-  *umax = c.take<unsigned>(64);
-  *path = c.take<int>(64);
-}
-
-}  // namespace
-
-int recon_chunk_candidates(int64_t v, int64_t L, int r, int* out) {
-  const ReconPlan pu = recon_plan(v, L, r, kFusedPT);
-  return chunk_candidates(pu.nc_heur, round_up(pu.vt, 8), out);
-}
-
-size_t recon_bytes(int64_t v, int64_t L, int r) {
-  Carver c(nullptr);
-  uint16_t* a;
-  float *b, *b2;
-  unsigned* d;
-  int* e;
-  recon_carve(c, v, L, r, &a, &b, &b2, &d, &e);
-  return c.off;
-}
-
-rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_t L, int64_t col0, uint64_t seed,
-                        int stream_id, const float* sigma_mu, float* out_max, const float* Tmax_for_gap,
-                        float* gap_out, void* ws, hipStream_t s, unsigned study, int force_nc) {
-  if (L == 0) return RPT_OK;
-  if (r < 1 || r > kRMaxRefine) return RPT_ERR_UNSUPPORTED;
-  Carver c(ws);
+struct ReconBufs {
   uint16_t* ukb;
-  float *smax, *partial;
+  float* smax;
+  float* partial;
   unsigned* umax;
   int* path;
-  recon_carve(c, v, L, r, &ukb, &smax, &partial, &umax, &path);
-  const ReconPlan pl = recon_plan(v, L, r, kFilterPT);
-  const ReconPlan pu = recon_plan(v, L, r, kFusedPT, force_nc);
+};
 
-  RPT_STAGE("recon_total", s);
-  hipLaunchKernelGGL(recon_init_kernel, dim3(1), dim3(1), 0, s, umax);
+// ks: U slices of 16 columns in ukb (0: the rank's own ceil(r / 16))
+ReconBufs recon_carve(Carver& c, int64_t v, int64_t L, int r, int ks) {
+  const ReconPlan pf = recon_plan(v, L, r, kFilterPT);
+  const ReconPlan pu = recon_plan(v, L, r, kFusedPT);
+  ReconBufs b;
+  b.ukb = c.take<uint16_t>(static_cast<size_t>(ks > pf.ks ? ks : pf.ks) * pf.vpad * 32);
+  b.smax = c.take<float>(static_cast<size_t>(L > 0 ? L : 1) * pf.nc * 32);
+  b.partial = c.take<float>(static_cast<size_t>(L > 0 ? L : 1) * pu.nc_cap);
+  b.umax = c.take<unsigned>(64);
+  b.path = c.take<int>(64);
+  return b;
+}
+
+// path decision and the BF16 hi/lo copy of U (ks slices)
+rpt_status recon_prepare(const float* U, int64_t v, int r, int64_t L, const float* sigma_mu, int ks,
+                         const ReconBufs& b, hipStream_t s) {
+  const ReconPlan pl = recon_plan(v, L, r, kFilterPT);
+  hipLaunchKernelGGL(recon_init_kernel, dim3(1), dim3(1), 0, s, b.umax);
   RPT_CHECK_LAUNCH();
-  hipLaunchKernelGGL(recon_decide_kernel, dim3(1), dim3(1), 0, s, sigma_mu, path);
+  hipLaunchKernelGGL(recon_decide_kernel, dim3(1), dim3(1), 0, s, sigma_mu, b.path);
   RPT_CHECK_LAUNCH();
   hipLaunchKernelGGL(recon_prep_u_kernel, dim3(static_cast<unsigned>(ceil_div(pl.vpad, kPrepUVox))), dim3(kBlock), 0,
-                     s, U, v, r, pl.vpad, pl.ks, ukb, umax);
+                     s, U, v, r, pl.vpad, ks, b.ukb, b.umax);
   RPT_CHECK_LAUNCH();
+  return RPT_OK;
+}
 
-  // fused path (runs when the device decided path 0)
-  FusedArgs ua{ukb, W, r, v, pu.vpad, pu.vt, L, pu.tpc, pu.pg, pu.nc, col0, seed,
-               static_cast<unsigned>(stream_id), sigma_mu, path, partial, study};
-  void* ufn = (col0 % 4 == 0) ? pick_fused<kFusedPT, true>(pu.ks) : pick_fused<kFusedPT, false>(pu.ks);
-  if (!ufn) return RPT_ERR_UNSUPPORTED;
-  void* uargs[] = {&ua};
-  hipError_t e;
-  {
-    RPT_STAGE("recon_fused", s);
-    e = hipLaunchKernel(ufn, dim3(static_cast<unsigned>(pu.pg) * pu.nc), dim3(kBlock), uargs, 0, s);
-  }
-  if (e != hipSuccess) {
-    set_hip_error(e);
-    return RPT_ERR_HIP;
-  }
+FusedArgs fused_args(const ReconBufs& b, const float* W, int r, int64_t v, int64_t L, int64_t col0, uint64_t seed,
+                     int stream_id, const float* sigma_mu, unsigned study, const ReconPlan& pu) {
+  return FusedArgs{b.ukb, W,  r,           v,        pu.vpad, pu.vt,  L,       pu.tpc, pu.pg,
+                   pu.nc, col0, seed, static_cast<unsigned>(stream_id), sigma_mu, b.path, b.partial, study};
+}
+
+// merge of the fused pass's partial maxima, then the exact-pruning path (each
+// kernel does its work only on its own path)
+rpt_status recon_finish(const float* U, int64_t v, int r, const float* W, int64_t L, int64_t col0, uint64_t seed,
+                        int stream_id, const float* sigma_mu, float* out_max, const float* Tmax_for_gap,
+                        float* gap_out, int ks, const ReconBufs& b, const ReconPlan& pu, hipStream_t s,
+                        unsigned study) {
+  const ReconPlan pl = recon_plan(v, L, r, kFilterPT);
   hipLaunchKernelGGL(recon_fused_finalize_kernel, dim3(static_cast<unsigned>(ceil_div(L, kBlock))), dim3(kBlock), 0,
-                     s, partial, pu.nc, L, sigma_mu, path, out_max, Tmax_for_gap, gap_out);
+                     s, b.partial, pu.nc, L, sigma_mu, b.path, out_max, Tmax_for_gap, gap_out);
   RPT_CHECK_LAUNCH();
 
   // exact-pruning path (runs when the device decided path 1)
-  FilterArgs fa{ukb, W, r, pl.ks, v, pl.vpad, pl.vt, L, pl.tpc, pl.pg, pl.nc, smax, path};
-  void* fn = pick_filter<kFilterPT>(pl.ks);
+  FilterArgs fa{b.ukb, W, r, ks, v, pl.vpad, pl.vt, L, pl.tpc, pl.pg, pl.nc, b.smax, b.path};
+  void* fn = pick_filter<kFilterPT>(ks);
   if (!fn) return RPT_ERR_UNSUPPORTED;
   void* args[] = {&fa};
+  hipError_t e;
   {
     RPT_STAGE("recon_filter", s);
     e = hipLaunchKernel(fn, dim3(static_cast<unsigned>(pl.pg) * pl.nc), dim3(kBlock), args, 0, s);
@@ -689,7 +717,7 @@ rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_
     return RPT_ERR_HIP;
   }
   RefineArgs ra;
-  ra.path = path;
+  ra.path = b.path;
   ra.U = U;
   ra.W = W;
   ra.v = v;
@@ -698,10 +726,10 @@ rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_
   ra.r = r;
   ra.tpc = pl.tpc;
   ra.nc = pl.nc;
-  ra.smax = smax;
-  ra.umax_bits = umax;
+  ra.smax = b.smax;
+  ra.umax_bits = b.umax;
   ra.sigma_mu = sigma_mu;
-  const int kpad = 16 * pl.ks;
+  const int kpad = 16 * ks;
   // BF16 rounding of both operands (2^-9 each), their product term, and FP32
   // accumulation in the filter and in the refine (K terms each, 2^-24)
   ra.eps = static_cast<float>((ldexp(1.0, -8) + ldexp(1.0, -18) + 2.02 * (kpad + r) * ldexp(1.0, -24)) * 1.01);
@@ -715,6 +743,136 @@ rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_
   RPT_STAGE("recon_refine", s);
   hipLaunchKernelGGL(recon_refine_kernel, dim3(static_cast<unsigned>(ceil_div(L, 4))), dim3(kBlock), 0, s, ra);
   RPT_CHECK_LAUNCH();
+  return RPT_OK;
+}
+
+template <int PT, bool AL>
+void* pick_persistent(int ks) {
+  switch (ks) {
+    case 1: return reinterpret_cast<void*>(&recon_fused_persistent_kernel<1, PT, AL>);
+    case 2: return reinterpret_cast<void*>(&recon_fused_persistent_kernel<2, PT, AL>);
+    case 3: return reinterpret_cast<void*>(&recon_fused_persistent_kernel<3, PT, AL>);
+    case 4: return reinterpret_cast<void*>(&recon_fused_persistent_kernel<4, PT, AL>);
+    case 5: return reinterpret_cast<void*>(&recon_fused_persistent_kernel<5, PT, AL>);
+    case 6: return reinterpret_cast<void*>(&recon_fused_persistent_kernel<6, PT, AL>);
+    case 7: return reinterpret_cast<void*>(&recon_fused_persistent_kernel<7, PT, AL>);
+    case 8: return reinterpret_cast<void*>(&recon_fused_persistent_kernel<8, PT, AL>);
+    default: return nullptr;
+  }
+}
+
+}  // namespace
+
+int recon_chunk_candidates(int64_t v, int64_t L, int r, int* out) {
+  const ReconPlan pu = recon_plan(v, L, r, kFusedPT);
+  return chunk_candidates(pu.nc_heur, round_up(pu.vt, 8), out);
+}
+
+size_t recon_bytes(int64_t v, int64_t L, int r, int ks) {
+  Carver c(nullptr);
+  (void)recon_carve(c, v, L, r, ks);
+  return c.off;
+}
+
+rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_t L, int64_t col0, uint64_t seed,
+                        int stream_id, const float* sigma_mu, float* out_max, const float* Tmax_for_gap,
+                        float* gap_out, void* ws, hipStream_t s, unsigned study, int force_nc) {
+  if (L == 0) return RPT_OK;
+  if (r < 1 || r > kRMaxRefine) return RPT_ERR_UNSUPPORTED;
+  Carver c(ws);
+  const ReconBufs b = recon_carve(c, v, L, r, 0);
+  const ReconPlan pu = recon_plan(v, L, r, kFusedPT, force_nc);
+  RPT_STAGE("recon_total", s);
+  RPT_TRY(recon_prepare(U, v, r, L, sigma_mu, pu.ks, b, s));
+  FusedArgs ua = fused_args(b, W, r, v, L, col0, seed, stream_id, sigma_mu, study, pu);
+  void* ufn = (col0 % 4 == 0) ? pick_fused<kFusedPT, true>(pu.ks) : pick_fused<kFusedPT, false>(pu.ks);
+  if (!ufn) return RPT_ERR_UNSUPPORTED;
+  void* uargs[] = {&ua};
+  hipError_t e;
+  {
+    RPT_STAGE("recon_fused", s);
+    e = hipLaunchKernel(ufn, dim3(static_cast<unsigned>(pu.pg) * pu.nc), dim3(kBlock), uargs, 0, s);
+  }
+  if (e != hipSuccess) {
+    set_hip_error(e);
+    return RPT_ERR_HIP;
+  }
+  return recon_finish(U, v, r, W, L, col0, seed, stream_id, sigma_mu, out_max, Tmax_for_gap, gap_out, pu.ks, b, pu,
+                      s, study);
+}
+
+int recon_batch_ks(const ReconStudy* st, int ns) {
+  int ks = 1;
+  for (int q = 0; q < ns; ++q) {
+    const int k = static_cast<int>(ceil_div(st[q].r, 16));
+    if (k > ks) ks = k;
+  }
+  return ks;
+}
+
+size_t recon_batch_counters(int ns) { return 8 * static_cast<size_t>(ceil_div(ns > 0 ? ns : 1, kPersistMax)); }
+
+rpt_status recon_prepare_study(const ReconStudy& st, int ks, hipStream_t s) {
+  if (st.L == 0) return RPT_OK;
+  if (st.r < 1 || st.r > kRMaxRefine || ks < 1 || ks > 8) return RPT_ERR_UNSUPPORTED;
+  Carver c(st.ws);
+  const ReconBufs b = recon_carve(c, st.v, st.L, st.r, ks);
+  return recon_prepare(st.U, st.v, st.r, st.L, st.sigma_mu, ks, b, s);
+}
+
+rpt_status recon_batched(const ReconStudy* st, int ns, int ks, int* counters, hipStream_t s) {
+  if (ks < 1 || ks > 8) return RPT_ERR_UNSUPPORTED;
+  bool aligned = true;
+  for (int q = 0; q < ns; ++q) aligned = aligned && (st[q].L == 0 || st[q].col0 % 4 == 0);
+  void* fn = aligned ? pick_persistent<kFusedPT, true>(ks) : pick_persistent<kFusedPT, false>(ks);
+  if (!fn) return RPT_ERR_UNSUPPORTED;
+  // a resident grid: three (aligned) or two workgroups per compute unit
+  int cus = 256;
+  {
+    int dev = 0;
+    if (hipGetDevice(&dev) == hipSuccess) {
+      int n = 0;
+      if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess && n > 0) cus = n;
+    }
+  }
+  const unsigned grid = static_cast<unsigned>(round_up(static_cast<int64_t>(cus) * (aligned ? 3 : 2), 8));
+  RPT_TRY(fill_i32(counters, static_cast<int64_t>(recon_batch_counters(ns)), 0, s));
+  for (int g0 = 0, gi = 0; g0 < ns; g0 += kPersistMax, ++gi) {
+    PersistTable t{};
+    t.ns = 0;
+    t.total = 0;
+    t.counters = counters + 8 * gi;
+    for (int q = g0; q < ns && q < g0 + kPersistMax; ++q) {
+      if (st[q].L == 0) continue;
+      Carver c(st[q].ws);
+      const ReconBufs b = recon_carve(c, st[q].v, st[q].L, st[q].r, ks);
+      const ReconPlan pu = recon_plan(st[q].v, st[q].L, st[q].r, kFusedPT);
+      t.st[t.ns] = fused_args(b, st[q].W, st[q].r, st[q].v, st[q].L, st[q].col0, st[q].seed, RPT_STREAM_RECOVERY,
+                              st[q].sigma_mu, st[q].study, pu);
+      t.items[t.ns] = static_cast<int64_t>(pu.pg) * pu.nc / 8;  // nc is a multiple of 8
+      t.total += t.items[t.ns];
+      ++t.ns;
+    }
+    if (t.ns == 0) continue;
+    void* args[] = {&t};
+    hipError_t e;
+    {
+      RPT_STAGE("recon_fused_batched", s);
+      e = hipLaunchKernel(fn, dim3(grid), dim3(kBlock), args, 0, s);
+    }
+    if (e != hipSuccess) {
+      set_hip_error(e);
+      return RPT_ERR_HIP;
+    }
+  }
+  for (int q = 0; q < ns; ++q) {
+    if (st[q].L == 0) continue;
+    Carver c(st[q].ws);
+    const ReconBufs b = recon_carve(c, st[q].v, st[q].L, st[q].r, ks);
+    const ReconPlan pu = recon_plan(st[q].v, st[q].L, st[q].r, kFusedPT);
+    RPT_TRY(recon_finish(st[q].U, st[q].v, st[q].r, st[q].W, st[q].L, st[q].col0, st[q].seed, RPT_STREAM_RECOVERY,
+                         st[q].sigma_mu, st[q].out_max, nullptr, nullptr, ks, b, pu, s, st[q].study));
+  }
   return RPT_OK;
 }
 

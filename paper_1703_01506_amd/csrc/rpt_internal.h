@@ -225,13 +225,34 @@ rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, 
                         int32_t* lnext = nullptr, const int64_t* optr = nullptr, void* split_ws = nullptr);
 
 // Reconstruction filter + exact refine with noise (K7).
-size_t recon_bytes(int64_t v, int64_t L, int r);
+// ks: U slices of 16 columns held for the reconstruction (0: ceil(r / 16))
+size_t recon_bytes(int64_t v, int64_t L, int r, int ks = 0);
 rpt_status recon_launch(const float* U, int64_t v, int r, const float* W, int64_t L, int64_t col0,
                         uint64_t seed, int stream_id, const float* sigma_mu, float* out_max,
                         const float* Tmax_for_gap, float* gap_out, void* ws, hipStream_t s, unsigned study = 0,
                         int force_nc = 0);
 // the fused reconstruction's chunk-count candidates for one shape (tune.hip)
 int recon_chunk_candidates(int64_t v, int64_t L, int r, int* out);
+// Reconstruction of several studies with one persistent fused launch (per
+// group of up to 16 studies): recon_prepare_study for each study once its W is
+// written (ws: recon_bytes(v, L, r, ks) bytes of its own), then recon_batched.
+struct ReconStudy {
+  const float* U;
+  int64_t v;
+  int r;
+  const float* W;
+  int64_t L;
+  int64_t col0;
+  uint64_t seed;
+  const float* sigma_mu;
+  float* out_max;
+  void* ws;
+  unsigned study;
+};
+int recon_batch_ks(const ReconStudy* st, int ns);
+size_t recon_batch_counters(int ns);  // int32 counters recon_batched needs
+rpt_status recon_prepare_study(const ReconStudy& st, int ks, hipStream_t s);
+rpt_status recon_batched(const ReconStudy* st, int ns, int ks, int* counters, hipStream_t s);
 
 // Orthonormalisation (one Cholesky-QR pass).  before_chol, when given, is
 // called once the Gram reduction is enqueued and before the single-workgroup

@@ -86,3 +86,68 @@ def test_batched_recovery_graph_replays():
         for (o, info), e in zip(outs, eager):
             np.testing.assert_allclose(o.cpu().numpy(), e, atol=1e-5, rtol=0)
             assert (info.cpu().numpy() == 0).all()
+
+
+def _uniform_study(torch, q, n, v, r, L, k, sigma, mu, col0, seed=2017):
+    """A study whose sampled sets all have k entries, in both layouts (dense
+    L x k for the single-study entry point, CSR for the batched one)."""
+    rng = np.random.default_rng(500 + q)
+    X = (rng.normal(size=(v, n)) + rng.normal(size=(v, 1))).astype(np.float32)
+    labels = S.relabellings(L, n, n // 2, seed=600 + q)
+    U = OR.orthonormalize(rng.normal(size=(v, r))).astype(np.float32)
+    om = S.omega_sets(L, v, k, seed=700 + q)
+    d = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    st = {"X": d(X), "labels": d(labels), "U": d(U), "sigma_mu": d(np.array([sigma, mu], dtype=np.float32)),
+          "omega_ptr": d(np.arange(L + 1, dtype=np.int64) * k), "omega_idx": d(om.reshape(-1)), "seed": seed,
+          "col0": col0, "study": 0}
+    return st, d(om)
+
+
+def _single(rpt, st, om):
+    m, info = rpt.recover_maxnull(st["X"], st["labels"], st["U"], st["sigma_mu"], om, st["seed"], col0=st["col0"])
+    return m.cpu().numpy(), info.cpu().numpy()
+
+
+def test_batched_persistent_launch_equals_single_study_calls():
+    """The studies' reconstructions share persistent launches (a study's work
+    items keep their own chunking, lower ranks are padded with zero columns):
+    the maxima equal the single-study calls bit for bit when every study
+    starts on an aligned column.  18 studies: two launches of up to 16; one
+    study with sigma = 0 takes the exact-pruning path instead."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce("batched persistent vs single calls")
+    cfgs = []
+    for q in range(18):
+        r = [8, 17, 40, 100, 30, 64][q % 6]
+        n = [20, 36, 60, 100, 24, 80][q % 6]
+        v = 1500 + 997 * q
+        L = 20 + 7 * (q % 5)
+        k = 2 * r + 11 * (q % 3) + 5
+        sigma = 0.0 if q == 5 else 0.05 + 0.03 * (q % 4)
+        cfgs.append((n, v, r, L, k, sigma, 0.1 * (q % 3) - 0.1, 4 * (q % 7) * 13))
+    pairs = [_uniform_study(torch, q, *c) for q, c in enumerate(cfgs)]
+    outs = rpt.recover_maxnull_batched([p[0] for p in pairs])
+    torch.cuda.synchronize()
+    for q, ((st, om), (got, info)) in enumerate(zip(pairs, outs)):
+        ref, rinfo = _single(rpt, st, om)
+        assert (info.cpu().numpy() == rinfo).all()
+        np.testing.assert_array_equal(got.cpu().numpy(), ref, err_msg=f"study {q}")
+
+
+def test_batched_persistent_unaligned_columns():
+    """A study starting at an unaligned column makes the shared launch use the
+    general noise path for every study: maxima equal the single-study calls
+    to FP32 rounding."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce("batched persistent, unaligned")
+    cfgs = [(20, 3001, 8, 40, 24, 0.3, 0.05, 0), (36, 5003, 17, 33, 50, 0.2, -0.1, 301),
+            (100, 20000, 40, 25, 90, 0.05, 0.2, 4)]
+    pairs = [_uniform_study(torch, 40 + q, *c) for q, c in enumerate(cfgs)]
+    outs = rpt.recover_maxnull_batched([p[0] for p in pairs])
+    torch.cuda.synchronize()
+    for q, ((st, om), (got, info)) in enumerate(zip(pairs, outs)):
+        ref, rinfo = _single(rpt, st, om)
+        assert (info.cpu().numpy() == rinfo).all()
+        np.testing.assert_allclose(got.cpu().numpy(), ref, rtol=1e-6, atol=1e-6, err_msg=f"study {q}")
