@@ -321,7 +321,12 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
  *             the failing pivot + 1 (a row with fewer than r entries fails)
  * Launches are only stream-ordered kernels on `stream` (no host
  * synchronisation, allocation or host reads of device memory), so the call
- * can be captured into a HIP graph; studies share the workspace in turn.
+ * can be captured into a HIP graph.  The sampled-t and Complete steps of the
+ * studies share one workspace region in turn; each study keeps its W and its
+ * reconstruction buffers, and the fused U w + noise + max of up to 16 studies
+ * runs as one persistent launch (results identical to rpt_recover_maxnull per
+ * study).  rpt_recover_batched_workspace gives the bytes (0 for an invalid
+ * descriptor).
  * Errors: as rpt_recover_maxnull, checked for every study before any launch.
  * ------------------------------------------------------------------------- */
 typedef struct rpt_study {
