@@ -36,6 +36,15 @@ __device__ __forceinline__ unsigned xor3(unsigned a, unsigned b, unsigned k) {
   return r;
 }
 
+// max(a, b) in one v_max_f32: the library's fmaxf first quiets a possible
+// NaN in an operand it cannot prove canonical (one more instruction per
+// element in the running maxima below, whose inputs are never NaN)
+__device__ __forceinline__ float vmax(float a, float b) {
+  float r;
+  asm("v_max_f32 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+  return r;
+}
+
 // NC independent counters advanced round by round together, so that the
 // dependent product -> xor chain of one call overlaps the others'
 template <int NC>
@@ -83,13 +92,15 @@ __device__ __forceinline__ void philox4x32_10(unsigned c[4], unsigned k0, unsign
 // Box-Muller on the hardware transcendental units: v_log_f32 is log2,
 // v_sin_f32 / v_cos_f32 take their argument in revolutions (sin(2 pi x)), the
 // exact form the transform needs; u lies in (0, 1).
+// u = ((x >> 8) + 1/2) 2^-24 as one FMA: scaling by 2^-24 commutes with the
+// single rounding, so this equals rounding the sum and then scaling
+__device__ __forceinline__ float unif24(unsigned x) {
+  return fmaf(static_cast<float>(x >> 8), 5.9604644775390625e-08f, 2.98023223876953125e-08f);  // 2^-24, 2^-25
+}
 __device__ __forceinline__ float bm_radius(unsigned x) {
-  const float u = (static_cast<float>(x >> 8) + 0.5f) * 5.9604644775390625e-08f;  // 2^-24
-  return __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u));  // -2 ln 2 log2(u)
+  return __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(unif24(x)));  // -2 ln 2 log2(u)
 }
-__device__ __forceinline__ float bm_turns(unsigned x) {
-  return (static_cast<float>(x >> 8) + 0.5f) * 5.9604644775390625e-08f;
-}
+__device__ __forceinline__ float bm_turns(unsigned x) { return unif24(x); }
 
 // z(seed, stream, col, vox): counter (vox, col >> 2, stream, study); column
 // col & 3 selects the word pair (0,1) or (2,3) and cos or sin.
@@ -471,7 +482,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int xcd, int j) {
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj) {
             const float val = fmaf(sigma, z[jj], acc[p][4 * m + jj]);
-            rm[p][4 * m + jj] = ok ? fmaxf(rm[p][4 * m + jj], val) : rm[p][4 * m + jj];
+            rm[p][4 * m + jj] = vmax(rm[p][4 * m + jj], ok ? val : -INFINITY);
           }
         }
       }
@@ -488,7 +499,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int xcd, int j) {
 #pragma unroll
           for (int jj = 0; jj < 4; ++jj) {
             const float val = fmaf(sigma, z[jj], acc[p][4 * m + jj]);
-            rm[p][4 * m + jj] = ok ? fmaxf(rm[p][4 * m + jj], val) : rm[p][4 * m + jj];
+            rm[p][4 * m + jj] = vmax(rm[p][4 * m + jj], ok ? val : -INFINITY);
           }
         }
     }
