@@ -47,7 +47,8 @@ STAGE_KERNEL = {"complete": "complete_kernel", "complete_gram": "complete_gram_k
                 "complete_solve": "complete_solve_kernel", "recon_fused": "recon_fused_kernel",
                 "naive_contract": "naive_max_kernel", "sampled_t": "sampled_kernel",
                 "track_update": "track_apply_kernel", "reorth_gram": "gram_partial_kernel",
-                "reorth_apply": "apply_rinv_kernel", "reorth_chol": "chol_rinv_kernel"}
+                "reorth_apply": "apply_rinv_kernel", "reorth_chol": "chol_rinv_kernel",
+                "recon_refine": "recon_refine_kernel"}
 
 
 def log(msg):
@@ -309,7 +310,9 @@ def roofline_for(stage, ms_per_step, launches_per_step, v, n, L, ell, r, k, P):
         peak = PEAK_NOISE_GNORMALS
         out.update({"bound": "alu", "achieved": ach, "peak": peak, "unit": "Gnormal/s",
                     "frac": ach / peak, "algorithmic_normals_per_launch": normals,
-                    "mfma_tflops": 3 * 2.0 * v * r * (ell + Lr) / launches_per_step / avg_s / 1e12})
+                    # one BF16 product pass (the exact values of the few
+                    # candidate voxels come from the refine stage)
+                    "mfma_tflops": 2.0 * v * r * (ell + Lr) / launches_per_step / avg_s / 1e12})
         return out
     if stage in ("reorth_gram", "reorth_apply"):
         # the Gram pass reads U once; the apply pass reads and writes it

@@ -240,9 +240,12 @@ rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx,
  * counter-based generator on stream RPT_STREAM_RECOVERY, and
  *     max_out[j] = max_k ( (U w_j)_k + s_k ) + mu.
  * U W is never written out: a BF16 matrix-core pass bounds every voxel's
- * reconstructed value, and only voxels that can still attain the maximum
- * (within the proven noise bound |z| < 5.8872 and the pass's error bound) are
- * recomputed in FP32 with their noise draw.
+ * reconstructed value, and only voxels that can still attain the maximum are
+ * recomputed in FP32 with their noise draw.  For small sigma the pass bounds
+ * U w alone and the proven noise bound |z| < 5.8872 selects the candidates;
+ * otherwise the pass adds every voxel's exact noise draw and only the voxel
+ * streams whose bound maximum lies within twice the pass's error bound of the
+ * column's best are recomputed.
  *
  *   U         v x r FP32 (orthonormal basis from training)          (in)
  *   sigma_mu  2 FP32 on the device {sigma, mu}                      (in)

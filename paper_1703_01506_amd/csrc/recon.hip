@@ -280,7 +280,8 @@ struct RefineArgs {
   const float* U;
   const float* W;
   int64_t v, vt, L;
-  int r, tpc, nc;
+  int r, tpc, nc;      // streams of the exact-pruning pass (path 1)
+  int tpc_f, nc_f;     // streams of the fused pass (path 0)
   const float* smax;
   const unsigned* umax_bits;
   const float* sigma_mu;
@@ -295,7 +296,7 @@ struct RefineArgs {
 };
 
 __global__ __launch_bounds__(kBlock) void recon_refine_kernel(RefineArgs a) {
-  if (*a.path != 1) return;
+  const int path = *a.path;
   __shared__ float wsh[4][kRMaxRefine];
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * 4 + wave;
@@ -310,14 +311,20 @@ __global__ __launch_bounds__(kBlock) void recon_refine_kernel(RefineArgs a) {
     wn = fmaf(x, x, wn);
   }
   wn = sqrtf(wave_sum(wn));
-  const float umax = __uint_as_float(*a.umax_bits);
-  const float delta = a.eps * umax * wn;
-  const int64_t ns = static_cast<int64_t>(a.nc) * 32;
+  const float A = __uint_as_float(*a.umax_bits) * wn;  // >= |U_k w| for every voxel
+  const bool vec = (a.r & 3) == 0 && (reinterpret_cast<uintptr_t>(a.U) & 15) == 0;
+  const int nc = path == 0 ? a.nc_f : a.nc, tpc = path == 0 ? a.tpc_f : a.tpc;
+  const int64_t ns = static_cast<int64_t>(nc) * 32;
   const float* sm = a.smax + i * ns;
   float M = -INFINITY;
   for (int64_t s = lane; s < ns; s += 64) M = fmaxf(M, sm[s]);
   M = wave_max(M);
-  const float tau = M - 2.0f * kZBound * sigma - 2.0f * delta;
+  // path 1: stream maxima of U w alone, so the noise can move any value by
+  // kZBound sigma; path 0: maxima of U w + sigma z (the same z as below), and
+  // both this pass and the bound pass round the noisy value once in FP32
+  // (values below A (1 + eps) + kZBound sigma)
+  const float tau = path == 0 ? M - 2.0f * (a.eps * A + 2.4e-7f * (A + kZBound * sigma))
+                              : M - 2.0f * kZBound * sigma - 2.0f * a.eps * A;
   float best = -INFINITY;
   for (int64_t s0 = 0; s0 < ns; s0 += 64) {
     const bool cand = (s0 + lane < ns) && sm[s0 + lane] >= tau;
@@ -328,16 +335,41 @@ __global__ __launch_bounds__(kBlock) void recon_refine_kernel(RefineArgs a) {
       const int64_t stream_id = s0 + bit;
       const int64_t chunk = stream_id >> 5;
       const int colc = static_cast<int>(stream_id & 31);
-      const int64_t t0 = chunk * a.tpc;
-      const int64_t t1 = t0 + a.tpc < a.vt ? t0 + a.tpc : a.vt;
-      for (int64_t t = t0 + lane; t < t1; t += 64) {
-        const int64_t vox = t * 32 + colc;
-        if (vox >= a.v) continue;
-        const float* u = a.U + vox * a.r;
-        float s = 0.0f;
-        for (int c = 0; c < a.r; ++c) s = fmaf(u[c], w[c], s);
-        const float z = noise_z(a.seed, a.stream, static_cast<unsigned>(a.col0 + i), vox, a.study);
-        best = fmaxf(best, fmaf(sigma, z, s));
+      const int64_t t0 = chunk * tpc;
+      const int64_t t1 = t0 + tpc < a.vt ? t0 + tpc : a.vt;
+      // 64 voxels of the stream at a time: every lane draws one voxel's
+      // noise, then four voxels per step are dotted with w by 16 lanes each
+      // (coalesced reads of the basis rows), summed by shuffles
+      for (int64_t tb = t0; tb < t1; tb += 64) {
+        const int64_t tl = tb + lane, voxl = tl * 32 + colc;
+        const float zl = (tl < t1 && voxl < a.v)
+                             ? noise_z(a.seed, a.stream, static_cast<unsigned>(a.col0 + i), voxl, a.study)
+                             : 0.0f;
+        const int nb = t1 - tb < 64 ? static_cast<int>(t1 - tb) : 64;
+        const int g = lane >> 4, l16 = lane & 15;
+        for (int q = 0; q < nb; q += 4) {
+          const int64_t vox = (tb + q + g) * 32 + colc;
+          const bool okq = q + g < nb && vox < a.v;
+          float sacc = 0.0f;
+          if (okq) {
+            const float* u = a.U + vox * a.r;
+            for (int c = 4 * l16; c < a.r; c += 64) {
+              if (vec && c + 4 <= a.r) {
+                const f32x4 x = *reinterpret_cast<const f32x4*>(u + c);
+                sacc = fmaf(x[0], w[c], sacc);
+                sacc = fmaf(x[1], w[c + 1], sacc);
+                sacc = fmaf(x[2], w[c + 2], sacc);
+                sacc = fmaf(x[3], w[c + 3], sacc);
+              } else {
+                for (int e = c; e < c + 4 && e < a.r; ++e) sacc = fmaf(u[e], w[e], sacc);
+              }
+            }
+          }
+#pragma unroll
+          for (int off = 1; off < 16; off <<= 1) sacc += __shfl_xor(sacc, off, 64);
+          const float z = __shfl(zl, q + g, 64);
+          if (okq) best = fmaxf(best, fmaf(sigma, z, sacc));
+        }
       }
     }
   }
@@ -349,11 +381,16 @@ __global__ __launch_bounds__(kBlock) void recon_refine_kernel(RefineArgs a) {
 }
 
 // ---------------------------------------------------------------- fused path
-// Reconstruction on the matrix cores as hi.hi + hi.lo + lo.hi (W and U split
-// into BF16 halves, FP32 accumulation), the noise of every element, and the
-// running maximum, in one pass.  Accumulator registers 4m..4m+3 of a lane hold
-// four consecutive columns 4q..4q+3 at one voxel: exactly the four normals of
-// one Philox call at counter (voxel, q, stream, 0).
+// One pass over every voxel: the reconstruction on the matrix cores in BF16
+// (W and U rounded to BF16, FP32 accumulation), the exact noise of every
+// element, and the running maximum of every stream (the voxels of one voxel
+// column of the tiles of one chunk).  The BF16 products are within
+// delta = eps |U_k| |w| of the FP32 value, so only the streams whose maximum
+// comes within 2 delta (plus roundings) of the column's best stream can hold
+// the maximum; recon_refine_kernel recomputes those in FP32 with the same
+// noise.  Accumulator registers 4m..4m+3 of a lane hold four consecutive
+// columns 4q..4q+3 at one voxel: exactly the four normals of one Philox call
+// at counter (voxel, q, stream, 0).
 struct FusedArgs {
   const uint16_t* ukb;
   const float* W;
@@ -365,7 +402,7 @@ struct FusedArgs {
   unsigned stream;
   const float* sigma_mu;
   const int* path;
-  float* partial;  // [nc][L]
+  float* smax;  // [L][nc * 32] stream maxima of the bound values
   unsigned study;  // study id of the noise counter
 };
 
@@ -383,7 +420,7 @@ __device__ __forceinline__ void box_muller4(const unsigned c[4], float z[4]) {
 // tiles are fetched into that XCD's L2 once for all permutation groups).
 template <int KS, int PT, bool ALIGNED>
 __device__ __forceinline__ void fused_item(const FusedArgs& a, int xcd, int j) {
-  __shared__ __align__(16) uint16_t us[2][KS][2][64 * 8];
+  __shared__ __align__(16) uint16_t us[2][KS][64 * 8];
   typedef __attribute__((address_space(3))) void lds_void;
   typedef const __attribute__((address_space(1))) void gbl_void;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, col = lane & 31;
@@ -393,7 +430,7 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int xcd, int j) {
   const float sigma = a.sigma_mu[0];
   const unsigned k0 = static_cast<unsigned>(a.seed), k1 = static_cast<unsigned>(a.seed >> 32);
 
-  u32x4 Ah[PT][KS], Al[PT][KS];
+  u32x4 Ah[PT][KS];
 #pragma unroll
   for (int p = 0; p < PT; ++p) {
     const int64_t perm = pbase + p * 32 + col;
@@ -401,23 +438,19 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int xcd, int j) {
     const float* wr = a.W + (valid ? perm : 0) * a.r;
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      unsigned wh[4], wl[4];
+      unsigned wh[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        uint32_t ph = 0, pl = 0;
+        uint32_t ph = 0;
 #pragma unroll
         for (int hl = 0; hl < 2; ++hl) {
           const int c = 16 * s + 8 * h + 2 * q + hl;
           const float x = (valid && c < a.r) ? wr[c] : 0.0f;
-          const uint16_t hi = f2bf(x);
-          ph |= static_cast<uint32_t>(hi) << (16 * hl);
-          pl |= static_cast<uint32_t>(f2bf(x - bf2f(hi))) << (16 * hl);
+          ph |= static_cast<uint32_t>(f2bf(x)) << (16 * hl);
         }
         wh[q] = ph;
-        wl[q] = pl;
       }
       Ah[p][s] = u32x4{wh[0], wh[1], wh[2], wh[3]};
-      Al[p][s] = u32x4{wl[0], wl[1], wl[2], wl[3]};
     }
   }
   float rm[PT][16];
@@ -435,12 +468,11 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int xcd, int j) {
   // wave reads its fragments right before the products.
   auto issue = [&](int b, int64_t t) {
 #pragma unroll
-    for (int j = 0; j < 2 * KS; j += 4) {
-      const int jj = j + wave;
-      if (jj < 2 * KS) {
-        const int s = jj >> 1, hl = jj & 1;
-        const uint16_t* g = a.ukb + s * kstride + static_cast<size_t>(t * 32 + col) * 32 + hl * 16 + h * 8;
-        __builtin_amdgcn_global_load_lds((gbl_void*)g, (lds_void*)&us[b][s][hl][0], 16, 0, 0);
+    for (int j = 0; j < KS; j += 4) {
+      const int s = j + wave;
+      if (s < KS) {
+        const uint16_t* g = a.ukb + s * kstride + static_cast<size_t>(t * 32 + col) * 32 + h * 8;
+        __builtin_amdgcn_global_load_lds((gbl_void*)g, (lds_void*)&us[b][s][0], 16, 0, 0);
       }
     }
   };
@@ -450,14 +482,9 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int xcd, int j) {
     for (int p = 0; p < PT; ++p) acc[p] = f32x16{};
 #pragma unroll
     for (int s = 0; s < KS; ++s) {
-      const u32x4 bh = *reinterpret_cast<const u32x4*>(&us[b][s][0][lane * 8]);
-      const u32x4 bl = *reinterpret_cast<const u32x4*>(&us[b][s][1][lane * 8]);
+      const u32x4 bh = *reinterpret_cast<const u32x4*>(&us[b][s][lane * 8]);
 #pragma unroll
-      for (int p = 0; p < PT; ++p) {
-        acc[p] = mfma_bf16(Ah[p][s], bh, acc[p]);
-        acc[p] = mfma_bf16(Ah[p][s], bl, acc[p]);
-        acc[p] = mfma_bf16(Al[p][s], bh, acc[p]);
-      }
+      for (int p = 0; p < PT; ++p) acc[p] = mfma_bf16(Ah[p][s], bh, acc[p]);
     }
     const int64_t vox = t * 32 + col;
     const bool ok = vox < a.v;
@@ -514,24 +541,16 @@ __device__ __forceinline__ void fused_item(const FusedArgs& a, int xcd, int j) {
     if (t + 1 < t1) issue(b ^ 1, t + 1);
     body(b, t);
   }
+  // the maximum of every stream (chunk, voxel column col): lane col holds it
+  // for the 16 permutations of its accumulator rows
+  const int64_t ns = static_cast<int64_t>(a.nc) * 32;
 #pragma unroll
   for (int p = 0; p < PT; ++p)
 #pragma unroll
     for (int e = 0; e < 16; ++e) {
-      float x = rm[p][e];
-#pragma unroll
-      for (int off = 1; off < 32; off <<= 1) x = fmaxf(x, __shfl_xor(x, off, 64));
-      rm[p][e] = x;
+      const int64_t perm = pbase + p * 32 + mfma_row(e, h);
+      if (perm < a.L) a.smax[perm * ns + static_cast<int64_t>(chunk) * 32 + col] = rm[p][e];
     }
-  if (col == 0) {
-#pragma unroll
-    for (int p = 0; p < PT; ++p)
-#pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int64_t perm = pbase + p * 32 + mfma_row(e, h);
-        if (perm < a.L) a.partial[static_cast<int64_t>(chunk) * a.L + perm] = rm[p][e];
-      }
-  }
 }
 
 template <int KS, int PT, bool ALIGNED>
@@ -576,27 +595,6 @@ __global__ __launch_bounds__(kBlock, ALIGNED ? 3 : 2) void recon_fused_persisten
     if (*t.st[q].path != 0) continue;  // this study takes the exact-pruning path
     fused_item<KS, PT, ALIGNED>(t.st[q], x, static_cast<int>(it - base));
   }
-}
-
-__global__ void recon_fused_finalize_kernel(const float* __restrict__ partial, int nc, int64_t L,
-                                            const float* sigma_mu, const int* path, float* out,
-                                            const float* tmax, float* gap) {
-  if (*path != 0) return;
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
-  if (i >= L) return;
-  // eight partial maxima in flight per thread
-  float m = partial[i];
-  int c = 1;
-  for (; c + 8 <= nc; c += 8) {
-    float q[8];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) q[e] = partial[static_cast<int64_t>(c + e) * L + i];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) m = fmaxf(m, q[e]);
-  }
-  for (; c < nc; ++c) m = fmaxf(m, partial[static_cast<int64_t>(c) * L + i]);
-  if (out) out[i] = m + sigma_mu[1];
-  if (gap) gap[i] = tmax[i] - m;
 }
 
 template <int PT, bool AL>
@@ -663,8 +661,7 @@ ReconPlan recon_plan(int64_t v, int64_t L, int r, int pt, int force_nc = 0) {
 
 struct ReconBufs {
   uint16_t* ukb;
-  float* smax;
-  float* partial;
+  float* smax;  // stream maxima of either pass
   unsigned* umax;
   int* path;
 };
@@ -675,8 +672,7 @@ ReconBufs recon_carve(Carver& c, int64_t v, int64_t L, int r, int ks) {
   const ReconPlan pu = recon_plan(v, L, r, kFusedPT);
   ReconBufs b;
   b.ukb = c.take<uint16_t>(static_cast<size_t>(ks > pf.ks ? ks : pf.ks) * pf.vpad * 32);
-  b.smax = c.take<float>(static_cast<size_t>(L > 0 ? L : 1) * pf.nc * 32);
-  b.partial = c.take<float>(static_cast<size_t>(L > 0 ? L : 1) * pu.nc_cap);
+  b.smax = c.take<float>(static_cast<size_t>(L > 0 ? L : 1) * (pf.nc > pu.nc_cap ? pf.nc : pu.nc_cap) * 32);
   b.umax = c.take<unsigned>(64);
   b.path = c.take<int>(64);
   return b;
@@ -699,19 +695,21 @@ rpt_status recon_prepare(const float* U, int64_t v, int r, int64_t L, const floa
 FusedArgs fused_args(const ReconBufs& b, const float* W, int r, int64_t v, int64_t L, int64_t col0, uint64_t seed,
                      int stream_id, const float* sigma_mu, unsigned study, const ReconPlan& pu) {
   return FusedArgs{b.ukb, W,  r,           v,        pu.vpad, pu.vt,  L,       pu.tpc, pu.pg,
-                   pu.nc, col0, seed, static_cast<unsigned>(stream_id), sigma_mu, b.path, b.partial, study};
+                   pu.nc, col0, seed, static_cast<unsigned>(stream_id), sigma_mu, b.path, b.smax, study};
 }
 
-// merge of the fused pass's partial maxima, then the exact-pruning path (each
-// kernel does its work only on its own path)
+// the exact-pruning pass (path 1 only), then the FP32 recomputation of the
+// candidate streams of whichever pass ran
 rpt_status recon_finish(const float* U, int64_t v, int r, const float* W, int64_t L, int64_t col0, uint64_t seed,
                         int stream_id, const float* sigma_mu, float* out_max, const float* Tmax_for_gap,
                         float* gap_out, int ks, const ReconBufs& b, const ReconPlan& pu, hipStream_t s,
                         unsigned study) {
   const ReconPlan pl = recon_plan(v, L, r, kFilterPT);
-  hipLaunchKernelGGL(recon_fused_finalize_kernel, dim3(static_cast<unsigned>(ceil_div(L, kBlock))), dim3(kBlock), 0,
-                     s, b.partial, pu.nc, L, sigma_mu, b.path, out_max, Tmax_for_gap, gap_out);
-  RPT_CHECK_LAUNCH();
+  // BF16 rounding of both operands (2^-9 each), their product term, and FP32
+  // accumulation in the bound pass and in the exact pass (K terms each, 2^-24)
+  const int kpad = 16 * ks;
+  const float eps =
+      static_cast<float>((ldexp(1.0, -8) + ldexp(1.0, -18) + 2.02 * (kpad + r) * ldexp(1.0, -24)) * 1.01);
 
   // exact-pruning path (runs when the device decided path 1)
   FilterArgs fa{b.ukb, W, r, ks, v, pl.vpad, pl.vt, L, pl.tpc, pl.pg, pl.nc, b.smax, b.path};
@@ -737,13 +735,12 @@ rpt_status recon_finish(const float* U, int64_t v, int r, const float* W, int64_
   ra.r = r;
   ra.tpc = pl.tpc;
   ra.nc = pl.nc;
+  ra.tpc_f = pu.tpc;
+  ra.nc_f = pu.nc;
   ra.smax = b.smax;
   ra.umax_bits = b.umax;
   ra.sigma_mu = sigma_mu;
-  const int kpad = 16 * ks;
-  // BF16 rounding of both operands (2^-9 each), their product term, and FP32
-  // accumulation in the filter and in the refine (K terms each, 2^-24)
-  ra.eps = static_cast<float>((ldexp(1.0, -8) + ldexp(1.0, -18) + 2.02 * (kpad + r) * ldexp(1.0, -24)) * 1.01);
+  ra.eps = eps;
   ra.seed = seed;
   ra.stream = static_cast<unsigned>(stream_id);
   ra.col0 = col0;
