@@ -263,14 +263,61 @@ __device__ __forceinline__ void chol_trailing(double* G, const double* P, int b0
   }
 }
 
+// The same trailing update for a full panel (M = kCb) on the FP64 matrix
+// cores: 16 x 16 tiles of the lower part (and the rows past r), one wave per
+// tile, K = kCb in four 16x16x4 products.  Lane l supplies A[l % 16][l / 16]
+// and B[l / 16][l % 16] and receives D[l / 16 + 4 e][l % 16] in element e.
+// Tile loads read up to 15 entries past the last row of P (into readable LDS;
+// they feed only discarded tile rows and columns).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ void chol_trailing_mfma(double* G, const double* P, int b0, int r, int nrows, int pld) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  const int ng = nrows - b0, nc = r - b0;
+  if (nc <= 0) return;
+  const int TC = (nc + 15) >> 4, TR = (ng + 15) >> 4;
+  const int ntri = TC * (TC + 1) / 2;
+  const int total = ntri + (TR > TC ? TR - TC : 0) * TC;
+  const int li = lane & 15, lk = lane >> 4;
+  for (int t = wave; t < total; t += nw) {
+    int ti, tj;
+    if (t < ntri) {
+      ti = 0;
+      while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+      tj = t - ti * (ti + 1) / 2;
+    } else {
+      const int u = t - ntri;
+      ti = TC + u / TC;
+      tj = u - (u / TC) * TC;
+    }
+    dbl4 acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int s4 = 0; s4 < kCb / 4; ++s4) {
+      const double* pk = P + (4 * s4 + lk) * pld;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(pk[16 * ti + li], pk[16 * tj + li], acc, 0, 0, 0);
+    }
+    const int col = 16 * tj + li;
+    double g[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 16 * ti + lk + 4 * e;
+      g[e] = (row < ng && col < nc && col <= row) ? G[ptri(b0 + row, b0 + col)] : 0.0;
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int row = 16 * ti + lk + 4 * e;
+      if (row < ng && col < nc && col <= row) G[ptri(b0 + row, b0 + col)] = g[e] - acc[e];
+    }
+  }
+}
+
 // Cholesky of the leading r x r block of the packed lower trapezoid G (rows
 // [0, nrows), r <= nrows <= 64 NS; entry (i, c) at ptri(i, c),
 // c <= min(i, r - 1)).  On success the leading block holds L (diagonal
 // included), dinv[j] = 1 / L_jj, and every row i >= r holds x_i with
 // L x_i = a_i (for an appended row b^T: z = L^{-1} b).  P is LDS scratch of
 // kCb rows of pld doubles, pld >= nrows - kCb (the rows below the first
-// diagonal block); the trailing tiles read up to three entries past a row,
-// which must be readable LDS and feed only discarded tile rows.  Returns 0,
+// diagonal block); the trailing tiles read up to 15 entries past the last row
+// of P, which must be readable LDS and feed only discarded tile rows.  Returns 0,
 // or j + 1 for the first pivot j that is not positive (same value in every
 // thread; later blocks are not factored).
 template <int NS>
@@ -294,7 +341,7 @@ __device__ __forceinline__ int lds_cholesky_blocked(double* G, double* dinv, dou
     }
     __syncthreads();
     if (fail) return fail;
-    chol_trailing<kCb>(G, P, c0 + kCb, kCb, r, nrows, pld);
+    chol_trailing_mfma(G, P, c0 + kCb, r, nrows, pld);
   }
   if (c0 < r) {
     const int m = r - c0;
