@@ -268,12 +268,12 @@ __host__ __device__ inline size_t gb_stride(int r) {  // bytes per column: G flo
   return ((static_cast<size_t>(ntri_r(r)) * sizeof(float) + 7) & ~static_cast<size_t>(7)) +
          static_cast<size_t>(r) * sizeof(double);
 }
-// Panel rows of r - 15 doubles: the trailing update's 16 x 16 tiles read up
+// Panel rows of r + 1 - kCb doubles: the trailing update's 16 x 16 tiles read up
 // to 15 entries past the panel, which land in dinv (r >= 17 whenever there is
 // a trailing update) and only feed tile rows and columns that are discarded.
 // w takes the panel's place once the factorisation is done.  At r = 100 this
 // is 52,896 bytes: three columns per compute unit.
-__host__ __device__ inline int solve_pld(int r) { return r - 15 > 1 ? r - 15 : 1; }
+__host__ __device__ inline int solve_pld(int r) { return r + 1 - kCb > 1 ? r + 1 - kCb : 1; }
 inline size_t solve_smem(int r) {
   const size_t pw = static_cast<size_t>(kCb) * solve_pld(r) > static_cast<size_t>(r) ? kCb * solve_pld(r) : r;
   return (static_cast<size_t>(gsize(r)) + pw + static_cast<size_t>(r) + 4) * sizeof(double);
