@@ -149,9 +149,12 @@ def main():
     if a.tune_cache and os.path.exists(a.tune_cache):
         tuned = {"loaded_from": a.tune_cache, "entries": rpt.autotune_load(a.tune_cache)}
     else:
+        Tscratch = torch.empty((ell, v), dtype=torch.float32, device=dev)
         tuned = {"naive_chunks": rpt.autotune_naive(Xd, Ld),
+                 "t_ex_chunks": rpt.autotune_naive(Xd, Ld[:ell], T=Tscratch),
                  "recon_chunks_recovery": rpt.autotune_recover(v, r, L - ell, device=dev),
                  "recon_chunks_training": rpt.autotune_recover(v, r, ell, device=dev)}
+        del Tscratch
         if a.tune_cache:
             rpt.autotune_save(a.tune_cache)
     log(f"autotuned {tuned}")

@@ -114,8 +114,11 @@ int rpt_timing_stages(char* buf, size_t len);
  * and untuned calls take the same workspaces, and results do not depend on
  * the choice (the column maxima are exact maxima of the same values).
  *
- * rpt_autotune_naive: prepares X, then times `reps` max-only contractions of
- *   `labels` (L x n) per candidate.  Arguments and workspace as
+ * rpt_autotune_naive: prepares X, then times `reps` contractions of `labels`
+ *   (L x n) per candidate: max-only when T_out is NULL, else the launch that
+ *   also writes T (L x v FP32 DEVICE scratch owned by the caller, as
+ *   rpt_naive_maxnull's T_out; its contents are overwritten), each form
+ *   tuned for itself.  Other arguments and the workspace as
  *   rpt_naive_maxnull.  *chosen (HOST int32) receives the kept count.
  * rpt_autotune_recover: times `reps` reconstruction calls per candidate for
  *   L_rec columns of rank r over v voxels on synthetic data in its own
@@ -130,7 +133,7 @@ int rpt_timing_stages(char* buf, size_t len);
  * rpt_autotune_clear empties the table; rpt_autotune_count reports its size.
  * ------------------------------------------------------------------------- */
 rpt_status rpt_autotune_naive(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
-                              const uint8_t* labels, int64_t L, int prec, int32_t reps,
+                              const uint8_t* labels, int64_t L, int prec, float* T_out, int32_t reps,
                               void* ws, size_t ws_bytes, void* stream, int32_t* chosen);
 size_t rpt_autotune_recover_workspace(int64_t v, int32_t r, int64_t L_rec);
 rpt_status rpt_autotune_recover(int64_t v, int32_t r, int64_t L_rec, int32_t reps,

@@ -347,9 +347,11 @@ def masked_loss_bwd(U, W, omega_ptr, omega_idx, resid, grad_scale=None):
     return dU, dW
 
 
-def autotune_naive(X, labels, n1: int | None = None, prec: str = "split_bf16", reps: int = 3) -> int:
+def autotune_naive(X, labels, n1: int | None = None, prec: str = "split_bf16", reps: int = 3, T=None) -> int:
     """Times the NaivePT contraction's candidate voxel-chunk counts on this
-    shape and keeps the fastest in the library's plan table (synchronises)."""
+    shape and keeps the fastest in the library's plan table (synchronises).
+    With T (an (L, v) float32 GPU scratch tensor) the T-writing launch is
+    tuned instead of the max-only one."""
     lib = _lib.load()
     v, n, ldx = _data(X)
     labels = _dev(labels, torch.uint8, "labels", 2).contiguous()
@@ -357,8 +359,12 @@ def autotune_naive(X, labels, n1: int | None = None, prec: str = "split_bf16", r
     n1 = n // 2 if n1 is None else int(n1)
     ws = _workspace(lib.rpt_naive_workspace(v, n, L, PREC[prec]), X.device)
     chosen = C.c_int32(0)
-    rc = lib.rpt_autotune_naive(_ptr(X), v, n, ldx, n1, _ptr(labels), L, PREC[prec], int(reps), _ptr(ws), ws.numel(),
-                                _stream(X.device), C.byref(chosen))
+    if T is not None:
+        T = _dev(T, torch.float32, "T", 2)
+        if tuple(T.shape) != (L, v) or not T.is_contiguous():
+            raise ValueError("T must be a contiguous (L, v) tensor")
+    rc = lib.rpt_autotune_naive(_ptr(X), v, n, ldx, n1, _ptr(labels), L, PREC[prec], _ptr(T), int(reps), _ptr(ws),
+                                ws.numel(), _stream(X.device), C.byref(chosen))
     _lib.check(rc, "rpt_autotune_naive")
     return chosen.value
 

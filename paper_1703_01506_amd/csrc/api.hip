@@ -628,8 +628,8 @@ ReconTuneWs recon_tune_carve(void* ws, int64_t v, int32_t r, int64_t L, size_t* 
 extern "C" {
 
 rpt_status rpt_autotune_naive(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* labels,
-                              int64_t L, int prec, int32_t reps, void* ws, size_t ws_bytes, void* stream,
-                              int32_t* chosen) {
+                              int64_t L, int prec, float* T_out, int32_t reps, void* ws, size_t ws_bytes,
+                              void* stream, int32_t* chosen) {
   if (!design_ok(v, n, ldx, n1) || L < 1 || reps < 1 || !X || !labels || !chosen) return RPT_ERR_INVALID_ARG;
   if (prec != RPT_FP32 && prec != RPT_SPLIT_BF16) return RPT_ERR_INVALID_ARG;
   const bool unbal = 2 * n1 != n;
@@ -639,17 +639,18 @@ rpt_status rpt_autotune_naive(const float* X, int64_t v, int32_t n, int64_t ldx,
   const int flags = naive_flags(prec, unbal);
   Carver c(ws);
   PrepX p = prep_carve(c, v, n, n1, flags);
-  float* partial = c.take<float>(static_cast<size_t>(naive_plan(v, L, n, prec, false).nc_cap) * L);
+  const bool store = T_out != nullptr;
+  float* partial = c.take<float>(static_cast<size_t>(naive_plan(v, L, n, prec, store).nc_cap) * L);
   RPT_TRY(prep_launch(p, X, ldx, RPT_TAIL_SIGNED, flags, s));
-  const NaivePlan base = naive_plan(v, L, n, prec, false);
+  const NaivePlan base = naive_plan(v, L, n, prec, store);
   int cand[kMaxChunkCandidates];
   const int m = chunk_candidates(base.nc_heur, round_up(base.vt, 8), cand);
   int best = base.nc_heur;
   float best_ms = 0.0f;
   for (int q = 0; q < m; ++q) {
-    const NaivePlan pl = naive_plan(v, L, n, prec, false, cand[q]);
+    const NaivePlan pl = naive_plan(v, L, n, prec, store, cand[q]);
     const float ms = time_calls(
-        [&]() { return naive_launch(p, pl, labels, L, RPT_TAIL_SIGNED, prec, partial, nullptr, nullptr, s); }, reps,
+        [&]() { return naive_launch(p, pl, labels, L, RPT_TAIL_SIGNED, prec, partial, T_out, nullptr, s); }, reps,
         s);
     if (ms < 0.0f) return RPT_ERR_HIP;
     if (q == 0 || ms < best_ms) {
@@ -657,7 +658,7 @@ rpt_status rpt_autotune_naive(const float* X, int64_t v, int32_t n, int64_t ldx,
       best = cand[q];
     }
   }
-  set_tuned_chunks(kTuneNaive, v, L, n, 2 * prec, best);
+  set_tuned_chunks(kTuneNaive, v, L, n, 2 * prec + (store ? 1 : 0), best);
   *chosen = best;
   return RPT_OK;
 }

@@ -135,7 +135,7 @@ def test_autotune_table_roundtrip(lib, tmp_path):
     assert lib.rpt_naive_workspace(250000, 100, 10000, 1) == before
     dummy = C.c_void_p(256)
     chosen = C.c_int32(0)
-    assert lib.rpt_autotune_naive(dummy, 1000, 20, 20, 10, dummy, 0, 1, 3, dummy, 1 << 30, None,
+    assert lib.rpt_autotune_naive(dummy, 1000, 20, 20, 10, dummy, 0, 1, None, 3, dummy, 1 << 30, None,
                                   C.byref(chosen)) == -1   # L = 0
     assert lib.rpt_autotune_recover(1000, 129, 50, 2, dummy, 1 << 30, None, C.byref(chosen)) == -1
 

@@ -52,3 +52,25 @@ def test_autotune_recover_keeps_results():
     after, _ = rpt.recover_maxnull(*args, col0=300)
     np.testing.assert_array_equal(after.cpu().numpy(), before)
     rpt.autotune_clear()
+
+
+def test_autotune_naive_t_writing_keeps_results():
+    """The T-writing launch is tuned on its own (separate table entry); T and
+    the maxima stay bit for bit the same."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce("autotune naive, T-writing")
+    rpt.autotune_clear()
+    n, v, L = 100, 30_011, 300
+    X = S.smoothed_volumes(n, v, seed=7)
+    labels = S.relabellings(L, n, n // 2, seed=8)
+    Xd, Ld = _d(torch, X), _d(torch, labels)
+    m0, T0 = rpt.naive_maxnull(Xd, Ld, return_T=True)
+    m0, T0 = m0.cpu().numpy(), T0.cpu().numpy()
+    scratch = torch.empty((L, v), dtype=torch.float32, device="cuda")
+    chosen = rpt.autotune_naive(Xd, Ld, reps=2, T=scratch)
+    assert chosen >= 8 and chosen % 8 == 0 and rpt.autotune_count() == 1
+    m1, T1 = rpt.naive_maxnull(Xd, Ld, return_T=True)
+    np.testing.assert_array_equal(m1.cpu().numpy(), m0)
+    np.testing.assert_array_equal(T1.cpu().numpy(), T0)
+    rpt.autotune_clear()
