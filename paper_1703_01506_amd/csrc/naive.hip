@@ -547,8 +547,8 @@ __global__ void naive_finalize_kernel(const float* __restrict__ partial, int nc,
 // naive_max_kernel (PT = 4)
 template <int PT, int KS>
 void* split_ptr(int abs_tail, int store) {
-  if (store) return abs_tail ? reinterpret_cast<void*>(&naive_split_kernel<KS, 2, true, true>)
-                             : reinterpret_cast<void*>(&naive_split_kernel<KS, 2, false, true>);
+  if (store) return abs_tail ? reinterpret_cast<void*>(&naive_split_kernel<KS, 1, true, true>)
+                             : reinterpret_cast<void*>(&naive_split_kernel<KS, 1, false, true>);
   return abs_tail ? reinterpret_cast<void*>(&naive_max_kernel<KS, 4, true>)
                   : reinterpret_cast<void*>(&naive_max_kernel<KS, 4, false>);
 }
@@ -585,8 +585,10 @@ void* pick_f32(int ks) {
 NaivePlan naive_plan(int64_t v, int64_t L, int n, int prec, bool store, int force_nc) {
   NaivePlan pl;
   // split max-only path: 4 relabelling tiles per wave (data shared through
-  // LDS, two waves per SIMD); the T-writing path and the FP32 path use 2.
-  pl.pt = (prec == RPT_SPLIT_BF16 && !store && n <= 128) ? 4 : 2;
+  // LDS, two waves per SIMD); the split T-writing path 1 (its data tiles
+  // stay in registers, so one tile keeps two waves per SIMD); the FP32 path
+  // and the wide-subject path 2.
+  pl.pt = (prec == RPT_SPLIT_BF16 && n <= 128) ? (store ? 1 : 4) : 2;
   pl.vt = round_up(v, 32) / 32;
   const int64_t group = 4 * pl.pt * 32;
   pl.pg = static_cast<int>(ceil_div(L > 0 ? L : 1, group));
