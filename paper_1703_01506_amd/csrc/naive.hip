@@ -525,25 +525,21 @@ __global__ __launch_bounds__(kBlock) void naive_f32_kernel(NaiveArgs a) {
   }
 }
 
-__global__ void naive_finalize_kernel(const float* __restrict__ partial, int nc, int64_t L, int m, int apply_t,
-                                      float* __restrict__ max_out) {
-  const int64_t i = blockIdx.x * static_cast<int64_t>(blockDim.x) + threadIdx.x;
+// One wave per relabelling: the lanes take the chunks' partial maxima in
+// turn (a few hundred chunks for short launches), then a wave maximum
+__global__ __launch_bounds__(kBlock) void naive_finalize_kernel(const float* __restrict__ partial, int nc, int64_t L,
+                                                                int m, int apply_t, float* __restrict__ max_out) {
+  const int lane = threadIdx.x & 63;
+  const int64_t i = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
   if (i >= L) return;
-  // eight partial maxima in flight per thread
-  float u = partial[i];
-  int c = 1;
-  for (; c + 8 <= nc; c += 8) {
-    float q[8];
+  float u = -INFINITY;
+  for (int c = lane; c < nc; c += 64) u = fmaxf(u, partial[static_cast<int64_t>(c) * L + i]);
 #pragma unroll
-    for (int e = 0; e < 8; ++e) q[e] = partial[static_cast<int64_t>(c + e) * L + i];
-#pragma unroll
-    for (int e = 0; e < 8; ++e) u = fmaxf(u, q[e]);
-  }
-  for (; c < nc; ++c) u = fmaxf(u, partial[static_cast<int64_t>(c) * L + i]);
-  max_out[i] = apply_t ? static_cast<float>(t_from_u(static_cast<double>(u), m)) : u;
+  for (int off = 32; off >= 1; off >>= 1) u = fmaxf(u, __shfl_xor(u, off, 64));
+  if (lane == 0) max_out[i] = apply_t ? static_cast<float>(t_from_u(static_cast<double>(u), m)) : u;
 }
 
-// T-storing launches use naive_split_kernel (PT = 2), max-only launches
+// T-storing launches use naive_split_kernel (PT = 1), max-only launches
 // naive_max_kernel (PT = 4)
 template <int PT, int KS>
 void* split_ptr(int abs_tail, int store) {
@@ -669,8 +665,8 @@ rpt_status naive_launch(const PrepX& p, const NaivePlan& pl, const uint8_t* labe
   }
   if (max_out) {
     RPT_STAGE("naive_finalize", s);
-    hipLaunchKernelGGL(naive_finalize_kernel, dim3(static_cast<unsigned>(ceil_div(L, kBlock))), dim3(kBlock), 0, s,
-                       partial, pl.nc, L, m, unbal ? 0 : 1, max_out);
+    hipLaunchKernelGGL(naive_finalize_kernel, dim3(static_cast<unsigned>(ceil_div(L, kBlock / 64))), dim3(kBlock), 0,
+                       s, partial, pl.nc, L, m, unbal ? 0 : 1, max_out);
     RPT_CHECK_LAUNCH();
   }
   return RPT_OK;
