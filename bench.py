@@ -33,14 +33,22 @@ METRIC = "max-null permutations/s, n=100 v=250k: RapidPT vs NaivePT on GPU, KL<1
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6        # vector FP64
-# VALU issue bound of the noise draw.  One Philox4x32-10 call (4 normals):
-# 20 products (v_mad_u64_u32) and 20 three-input XORs, full rate (4 cycles per
-# wave64 instruction on a SIMD); Box-Muller: 12 ops for the four uniforms, 2
-# scalings and 4 products, full rate, and 8 transcendentals (log, sqrt, sin,
-# cos twice), quarter rate (16 cycles); then 2 full-rate ops per normal (the
-# noise FMA and the running max).  66 x 4 + 8 x 16 = 392 SIMD cycles per 64
-# calls, 98 per 64 normals: 1,024 SIMDs x 2.4 GHz x 64 / 98.
-NOISE_SIMD_CYCLES_PER_64_NORMALS = 98
+# VALU issue bound of the noise draw, per 16 normals of one lane (four
+# Philox4x32-10 calls, every wave64 instruction covering 64 lanes): 67
+# v_mad_u64_u32 and 74 v_bitop3_b32 (the products and three-input XORs of the
+# ten rounds, those of the first two rounds shared by the four calls),
+# 104 full-rate ops (per normal: shift, convert and FMA of its uniform, half a
+# log scaling, the radius product, the noise FMA and the running max) and 32
+# transcendentals (log, sqrt, sin, cos per pair).  Issue cycles per wave64
+# instruction on a SIMD, measured on the whole chip at eight waves per SIMD
+# (`bench.py --issue-rates`, profiles/valu_issue_rates_mi355x.md; a clock of
+# 2.4 GHz): v_mad_u64_u32 5.11, v_bitop3_b32 4.46, FP32 add 2.86,
+# transcendental 9.46.  67 x 5.11 + 74 x 4.46 + 104 x 2.86 + 32 x 9.46 = 1,272
+# cycles per 1,024 normals of a wave, 79.5 per 64: 1,024 SIMDs x 2.4 GHz x 64
+# / 79.5.
+ISSUE_CYCLES = {"mad": 5.112, "bitop3": 4.455, "full": 2.858, "trans": (9.405 + 9.517) / 2}
+NOISE_SIMD_CYCLES_PER_64_NORMALS = (67 * ISSUE_CYCLES["mad"] + 74 * ISSUE_CYCLES["bitop3"] +
+                                    104 * ISSUE_CYCLES["full"] + 32 * ISSUE_CYCLES["trans"]) / 16
 PEAK_NOISE_GNORMALS = 1024 * 2.4 * 64 / NOISE_SIMD_CYCLES_PER_64_NORMALS
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rapidpt_step_n100_v250k_hbm_traffic.md")
 STAGE_KERNEL = {"complete": "complete_kernel", "complete_gram": "complete_gram_kernel",
@@ -104,7 +112,26 @@ def main():
                     help="plan-table file: loaded (no tuning runs) if it exists, else written after tuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
+    ap.add_argument("--issue-rates", action="store_true",
+                    help="only measure the VALU issue rates behind the noise generator's ALU bound")
     a = ap.parse_args()
+    if a.issue_rates:
+        import ctypes as C
+        import torch
+        from paper_1703_01506_amd import _lib
+        lib = _lib.load()
+        cus = torch.cuda.get_device_properties(0).multi_processor_count
+        ws = torch.empty(lib.rpt_issue_rates_workspace(cus), dtype=torch.uint8, device="cuda")
+        cyc = (C.c_double * 5)()
+        rc = lib.rpt_issue_rates(cus, 2.4, 20000, cyc, ws.data_ptr(), ws.numel(),
+                                 torch.cuda.current_stream().cuda_stream)
+        _lib.check(rc, "rpt_issue_rates")
+        names = ["fp32_add", "log_f32", "sin_f32", "bitop3_b32", "mad_u64_u32_and_xor_mean"]
+        out = {n_: round(c_, 3) for n_, c_ in zip(names, cyc)}
+        out["mad_u64_u32"] = round(2 * cyc[4] - cyc[0], 3)  # the pair's xor at the add rate
+        print(json.dumps({"compute_units": cus, "clock_ghz": 2.4,
+                          "simd_cycles_per_wave64_instruction": out}))
+        return
     if a.copy_calibration:
         import torch
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
