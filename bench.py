@@ -101,6 +101,105 @@ def cpu_baseline(X, labels, U0, omt, oms, omr, ell, passes, seed, part_s=4.0):
                        f"and {L - ell} recoveries: {est:.0f} s estimated for the {L}-column step")}
 
 
+def kl_max_nulls(ref, test, bins=50, pseudocount=0.5):
+    """D_KL(ref || test) of two max nulls (Sec. 5.5's accuracy measure): 50
+    equal-width bins over the two samples' common range, 0.5 added to every
+    bin count so that empty bins stay finite."""
+    ref = np.asarray(ref.cpu() if hasattr(ref, "cpu") else ref, dtype=np.float64)
+    test = np.asarray(test.cpu() if hasattr(test, "cpu") else test, dtype=np.float64)
+    lo, hi = min(ref.min(), test.min()), max(ref.max(), test.max())
+    if hi <= lo:
+        return 0.0
+    edges = np.linspace(lo, hi, bins + 1)
+    p = np.histogram(ref, edges)[0] + pseudocount
+    q = np.histogram(test, edges)[0] + pseudocount
+    p, q = p / p.sum(), q / q.sum()
+    return float(np.sum(p * np.log(p / q)))
+
+
+# Simulation Data I and II (Sec. 5.1, 5.2) with the hyperparameter grid of
+# Sec. 5.4 (Tables 2-4, simulation rows).  Sim II's n = 600 datasets exceed
+# the library's 512-subject limit and are left out; the basis rank is
+# min(l, n, 128).
+SIM1 = {"n": 30, "v": 20_000, "signal_frac": 0.01, "shift": 1.0}
+SIM1_ETA_PCT = (0.5, 1.0, 1.6, 2.0, 4.0, 8.0, 16.0, 32.0, 64.0)
+SIM1_L = (5_000, 20_000)
+SIM2_N = (60, 150)
+SIM2_FRAC = (0.01, 0.05, 0.10, 0.25)
+SIM2_SHIFT = (1.0, 5.0, 10.0, 25.0)
+SIM2_L, SIM2_ETA_PCT = 50_000, 3.2    # eta = 2 eta_min with eta_min ~ 1.6% (Sec. 6.1)
+SIM_ALPHAS = (0.05, 0.01, 0.001)
+
+
+def simulations(a):
+    """RapidPT against NaivePT on the same relabellings for the simulated
+    workloads: KL divergence of the two max nulls, percent difference of the
+    FWER thresholds at several alphas, and the KL of two NaivePT runs on
+    independent relabellings (the run-to-run floor).  One JSON line."""
+    import torch
+    import rpt_synth as S
+    import paper_1703_01506_amd as rpt
+
+    dev = torch.device("cuda:0")
+    d = lambda x: torch.from_numpy(np.ascontiguousarray(x)).to(dev)
+    P, seed = a.passes, 2017
+
+    def compare(Xd, n, v, Ld, Ld_alt, L, ell, eta_pct, omr_all, tag):
+        k = S.omega_count(v, int(round(eta_pct * 1e4)))
+        r = min(ell, n, 128)
+        U0 = d(S.gaussian_matrix(v, r, seed=3).astype(np.float32))
+        omt = d(S.omega_sets(P * ell, v, k, seed=41))
+        oms = d(S.omega_sets(ell, v, k, seed=42))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        h, tr, _ = rpt.rapidpt_maxnull(Xd, Ld[:ell], Ld[ell:L], U0, omt, oms, omr_all[:L - ell], passes=P,
+                                       seed=seed)
+        torch.cuda.synchronize()
+        t_rapid = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        nv = rpt.naive_maxnull(Xd, Ld[:L])
+        torch.cuda.synchronize()
+        t_naive = time.perf_counter() - t0
+        nv2 = rpt.naive_maxnull(Xd, Ld_alt[:L])
+        rec = {"workload": tag, "n": n, "v": v, "L": L, "l": ell, "r": r, "eta_pct": eta_pct, "k": k,
+               "kl": kl_max_nulls(nv, h), "kl_naive_runs": kl_max_nulls(nv, nv2),
+               "sigma": float(tr["sigma_mu"][0].item()), "mu": float(tr["sigma_mu"][1].item()),
+               "rapidpt_ms": 1e3 * t_rapid, "naivept_ms": 1e3 * t_naive}
+        for al in SIM_ALPHAS:
+            tn = float(rpt.fwer_threshold(nv, al).item())
+            tq = float(rpt.fwer_threshold(h, al).item())
+            rec[f"thr_pct_diff_{al}"] = 100.0 * (tq - tn) / abs(tn)   # signed: RapidPT minus NaivePT
+        log(json.dumps({q: (round(x, 6) if isinstance(x, float) else x) for q, x in rec.items()}))
+        return rec
+
+    out = []
+    # Simulation Data I: one dataset, hyperparameters varied
+    n, v = SIM1["n"], SIM1["v"]
+    X, _ = S.iid_volumes(n, v, n // 2, SIM1["signal_frac"], SIM1["shift"], seed=1703, signal_group=2)
+    Xd = d(X.astype(np.float32))
+    Lmax = max(SIM1_L)
+    Ld, Ld_alt = d(S.relabellings(Lmax, n, n // 2, seed=1506)), d(S.relabellings(Lmax, n, n // 2, seed=1507))
+    for eta in SIM1_ETA_PCT:
+        k = S.omega_count(v, int(round(eta * 1e4)))
+        omr_all = d(S.omega_sets(Lmax, v, k, seed=43))
+        for L in SIM1_L:
+            for ell in (n // 3, n, 2 * n):
+                out.append(compare(Xd, n, v, Ld, Ld_alt, L, ell, eta, omr_all, "sim1"))
+        del omr_all
+    # Simulation Data II: hyperparameters fixed, datasets varied
+    v = 20_000
+    k = S.omega_count(v, int(round(SIM2_ETA_PCT * 1e4)))
+    omr_all = d(S.omega_sets(SIM2_L, v, k, seed=43))
+    for n in SIM2_N:
+        Ld, Ld_alt = d(S.relabellings(SIM2_L, n, n // 2, seed=1506)), d(S.relabellings(SIM2_L, n, n // 2, seed=1507))
+        for frac in SIM2_FRAC:
+            for shift in SIM2_SHIFT:
+                X, _ = S.iid_volumes(n, v, n // 2, frac, shift, seed=1703, signal_group=2)
+                out.append(compare(d(X.astype(np.float32)), n, v, Ld, Ld_alt, SIM2_L, n, SIM2_ETA_PCT,
+                                   omr_all, f"sim2 frac={frac} shift={shift}"))
+    print(json.dumps({"simulations": out, "passes": P, "seed": seed}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -112,6 +211,8 @@ def main():
                     help="plan-table file: loaded (no tuning runs) if it exists, else written after tuning")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
+    ap.add_argument("--simulations", action="store_true",
+                    help="only run RapidPT against NaivePT on Simulation Data I and II (accuracy sweep)")
     ap.add_argument("--issue-rates", action="store_true",
                     help="only measure the VALU issue rates behind the noise generator's ALU bound")
     a = ap.parse_args()
@@ -132,6 +233,9 @@ def main():
         print(json.dumps({"compute_units": cus, "clock_ghz": 2.4,
                           "simd_cycles_per_wave64_instruction": out}))
         return
+    if a.simulations:
+        simulations(a)
+        return
     if a.copy_calibration:
         import torch
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
@@ -143,8 +247,8 @@ def main():
         print(json.dumps({"copy_bytes_read": x.numel() * 4, "copy_bytes_written": y.numel() * 4}))
         return
     if a.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); the multi-GPU layout is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {a.gpus}); sharding the relabellings "
+              "over several GPUs is not built", file=sys.stderr)
         sys.exit(2)
 
     import torch
@@ -243,10 +347,9 @@ def main():
         if s_ in tot and s_ != dom:
             others[s_] = roofline_for(s_, tot[s_], launches[s_], v, n, L, ell, r, k, P)
 
-    from oracle import metrics as OM
-    hn, nvn = h.cpu().numpy(), nv.cpu().numpy()
-    quality = {"kl_naive_vs_rapid": OM.kl_divergence(nvn, hn), "threshold_naive": OM.threshold(nvn, 0.05),
-               "threshold_rapid": OM.threshold(hn, 0.05),
+    quality = {"kl_naive_vs_rapid": kl_max_nulls(nv, h),
+               "threshold_naive": float(rpt.fwer_threshold(nv, 0.05).item()),
+               "threshold_rapid": float(rpt.fwer_threshold(h, 0.05).item()),
                "sigma": float(tr["sigma_mu"][0].item()), "mu": float(tr["sigma_mu"][1].item())}
 
     cpu = None

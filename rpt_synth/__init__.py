@@ -97,15 +97,21 @@ def smoothed_volumes(n: int, v: int, fwhm: float = 3.0, seed: int = 1703,
 
 
 def iid_volumes(n: int, v: int, n1: int, signal_frac: float = 0.0,
-                shift: float = 0.0, seed: int = 1703, dtype=np.float64):
-    """Simulated data of the kind of Sec. 5.1: X (v x n) with i.i.d. N(0,1)
-    entries; the first n1 columns (group 1) get +shift on a seeded subset of
-    round(signal_frac * v) voxels.  Returns (X, signal_voxel_indices)."""
+                shift: float = 0.0, seed: int = 1703, dtype=np.float64,
+                signal_group: int = 1):
+    """Simulated data of the kind of Sec. 5.1 and 5.2 (Simulation Data I and
+    II): X (v x n) with i.i.d. N(0,1) entries; the columns of one group (group
+    1 = the first n1 columns, group 2 = the rest) get +shift, i.e. N(shift, 1),
+    on a seeded subset of round(signal_frac * v) voxels.
+    Returns (X, signal_voxel_indices)."""
+    if signal_group not in (1, 2):
+        raise ValueError("signal_group is 1 or 2")
     X = _rng(seed, _TAG_DATA).standard_normal((v, n))
     ns = int(round(signal_frac * v))
     sig = np.sort(_rng(seed, _TAG_SIGNAL).choice(v, size=ns, replace=False)) if ns else np.zeros(0, np.int64)
     if ns:
-        X[np.ix_(sig, np.arange(n1))] += shift
+        cols = np.arange(n1) if signal_group == 1 else np.arange(n1, n)
+        X[np.ix_(sig, cols)] += shift
     return X.astype(dtype), sig
 
 
