@@ -327,6 +327,25 @@ def main():
     naive_ms = 1e3 * nwall / a.steps
     log(f"naivept {naive_ms:.3f} ms/step")
 
+    # the recovery half alone (Alg. 2's RECOVERY on the trained basis)
+    recover = lambda: rpt.recover_maxnull(Xd, Ld[ell:], tr["U"], tr["sigma_mu"], omrd, seed, col0=ell)
+    recover()
+    _, rwall, _ = timed(recover, False)
+    rec_ms = 1e3 * rwall / a.steps
+    log(f"recovery alone {rec_ms:.2f} ms/call")
+
+    # X from pinned host memory to the device (the library's inputs are
+    # device-resident; this is the copy a caller starting from host data adds)
+    Xh = torch.from_numpy(np.ascontiguousarray(X)).pin_memory()
+    Xtmp = torch.empty_like(Xd)
+    Xtmp.copy_(Xh, non_blocking=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Xtmp.copy_(Xh, non_blocking=True)
+    torch.cuda.synchronize()
+    h2d_ms = 1e3 * (time.perf_counter() - t0)
+    del Xtmp, Xh
+
     # roofline of the dominant kernel stage of the RapidPT step
     tot = {s: q[0] / a.steps for s, q in stages.items() if q and not s.endswith("_total")}
     launches = {s: q[1] / a.steps for s, q in stages.items() if q and not s.endswith("_total")}
@@ -352,10 +371,17 @@ def main():
                "threshold_rapid": float(rpt.fwer_threshold(h, 0.05).item()),
                "sigma": float(tr["sigma_mu"][0].item()), "mu": float(tr["sigma_mu"][1].item())}
 
-    cpu = None
+    cpu = cpu1 = None
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(X, labels, U0, omt, oms, omr, ell, P, seed)
+        try:
+            from threadpoolctl import threadpool_limits
+            with threadpool_limits(limits=1):
+                log("cpu baseline (oracle, one thread) ...")
+                cpu1 = cpu_baseline(X, labels, U0, omt, oms, omr, ell, P, seed, part_s=2.0)
+        except ImportError:  # pragma: no cover
+            cpu1 = None
 
     out = {
         "metric": METRIC, "value": value, "unit": "perms/s", "n_gpus": 1, "steps": a.steps,
@@ -367,6 +393,10 @@ def main():
         "roofline": roof,
         "rooflines_other_stages": others,
         "cpu_baseline": cpu,
+        "cpu_baseline_one_thread": cpu1,
+        "recovery_only": {"value": (L - ell) / (rwall / a.steps), "unit": "perms/s", "ms_per_call": rec_ms,
+                          "columns": L - ell},
+        "h2d_ms_X": h2d_ms,
         "naivept": {"value": L / (nwall / a.steps), "unit": "perms/s", "ms_per_step": naive_ms,
                     "roofline": naive_roof},
         "rapidpt_vs_naivept": value / (L / (nwall / a.steps)),
