@@ -207,6 +207,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--passes", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="skip the recovery-only, host-copy and one-thread oracle figures (profiled runs: the "
+                         "traced launches are then exactly the steps' own)")
     ap.add_argument("--tune-cache", default=None,
                     help="plan-table file: loaded (no tuning runs) if it exists, else written after tuning")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -327,24 +330,27 @@ def main():
     naive_ms = 1e3 * nwall / a.steps
     log(f"naivept {naive_ms:.3f} ms/step")
 
-    # the recovery half alone (Alg. 2's RECOVERY on the trained basis)
-    recover = lambda: rpt.recover_maxnull(Xd, Ld[ell:], tr["U"], tr["sigma_mu"], omrd, seed, col0=ell)
-    recover()
-    _, rwall, _ = timed(recover, False)
-    rec_ms = 1e3 * rwall / a.steps
-    log(f"recovery alone {rec_ms:.2f} ms/call")
-
-    # X from pinned host memory to the device (the library's inputs are
-    # device-resident; this is the copy a caller starting from host data adds)
-    Xh = torch.from_numpy(np.ascontiguousarray(X)).pin_memory()
-    Xtmp = torch.empty_like(Xd)
-    Xtmp.copy_(Xh, non_blocking=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    Xtmp.copy_(Xh, non_blocking=True)
-    torch.cuda.synchronize()
-    h2d_ms = 1e3 * (time.perf_counter() - t0)
-    del Xtmp, Xh
+    rec_only = h2d_ms = None
+    if not a.headline_only:
+        # the recovery half alone (Alg. 2's RECOVERY on the trained basis)
+        recover = lambda: rpt.recover_maxnull(Xd, Ld[ell:], tr["U"], tr["sigma_mu"], omrd, seed, col0=ell)
+        recover()
+        _, rwall, _ = timed(recover, False)
+        rec_ms = 1e3 * rwall / a.steps
+        rec_only = {"value": (L - ell) / (rwall / a.steps), "unit": "perms/s", "ms_per_call": rec_ms,
+                    "columns": L - ell}
+        log(f"recovery alone {rec_ms:.2f} ms/call")
+        # X from pinned host memory to the device (the library's inputs are
+        # device-resident; this is the copy a caller starting from host data adds)
+        Xh = torch.from_numpy(np.ascontiguousarray(X)).pin_memory()
+        Xtmp = torch.empty_like(Xd)
+        Xtmp.copy_(Xh, non_blocking=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        Xtmp.copy_(Xh, non_blocking=True)
+        torch.cuda.synchronize()
+        h2d_ms = 1e3 * (time.perf_counter() - t0)
+        del Xtmp, Xh
 
     # roofline of the dominant kernel stage of the RapidPT step
     tot = {s: q[0] / a.steps for s, q in stages.items() if q and not s.endswith("_total")}
@@ -375,13 +381,11 @@ def main():
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         cpu = cpu_baseline(X, labels, U0, omt, oms, omr, ell, P, seed)
-        try:
+        if not a.headline_only:
             from threadpoolctl import threadpool_limits
             with threadpool_limits(limits=1):
                 log("cpu baseline (oracle, one thread) ...")
                 cpu1 = cpu_baseline(X, labels, U0, omt, oms, omr, ell, P, seed, part_s=2.0)
-        except ImportError:  # pragma: no cover
-            cpu1 = None
 
     out = {
         "metric": METRIC, "value": value, "unit": "perms/s", "n_gpus": 1, "steps": a.steps,
@@ -394,8 +398,7 @@ def main():
         "rooflines_other_stages": others,
         "cpu_baseline": cpu,
         "cpu_baseline_one_thread": cpu1,
-        "recovery_only": {"value": (L - ell) / (rwall / a.steps), "unit": "perms/s", "ms_per_call": rec_ms,
-                          "columns": L - ell},
+        "recovery_only": rec_only,
         "h2d_ms_X": h2d_ms,
         "naivept": {"value": L / (nwall / a.steps), "unit": "perms/s", "ms_per_step": naive_ms,
                     "roofline": naive_roof},
