@@ -42,11 +42,28 @@ def test_sampled_tstat_balanced_and_unbalanced():
         assert_t_close(y, ref, "fp32", "y")
 
 
+def test_sampled_tstat_every_voxel_sampled():
+    """The largest sampled set, k = v (every voxel of every column), against
+    the full t maps."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce("sampled k = v")
+    n, n1, v, L = 30, 15, 4001, 9
+    X, _ = S.iid_volumes(n, v, n1, 0.05, 1.0, seed=12)
+    X = X.astype(np.float32)
+    labels = S.relabellings(L, n, n1, seed=13)
+    om = S.omega_sets(L, v, v, seed=14)
+    y = rpt.sampled_tstat(_dev(torch, X), _dev(torch, labels), _dev(torch, om), n1=n1).cpu().numpy()
+    T = OT.tmatrix(X.astype(np.float64), labels)
+    assert_t_close(y, np.take_along_axis(T, om.astype(np.int64), axis=1), "fp32", "y", m=n1)
+
+
 @pytest.mark.parametrize("r,k", [(7, 40), (32, 100), (100, 875), (128, 300), (100, 1750), (17, 2100), (50, 61),
-                                 (81, 1024), (112, 1025)])
+                                 (81, 1024), (112, 1025), (30, 6000)])
 def test_complete_least_squares(r, k):
-    """Every 16-column block count of the Gram tiles, ragged row groups, and
-    more sampled rows than one LDS index block (1,024) holds."""
+    """Every 16-column block count of the Gram tiles, ragged row groups, more
+    sampled rows than one LDS index block (1,024) holds, and k = v (every
+    voxel sampled)."""
     torch = torch_cuda()
     import paper_1703_01506_amd as rpt
     announce(f"complete r={r} k={k}")
