@@ -337,38 +337,29 @@ __global__ __launch_bounds__(kBlock) void recon_refine_kernel(RefineArgs a) {
       const int colc = static_cast<int>(stream_id & 31);
       const int64_t t0 = chunk * tpc;
       const int64_t t1 = t0 + tpc < a.vt ? t0 + tpc : a.vt;
-      // 64 voxels of the stream at a time: every lane draws one voxel's
-      // noise, then four voxels per step are dotted with w by 16 lanes each
-      // (coalesced reads of the basis rows), summed by shuffles
+      // 64 voxels of the stream at a time, one per lane: the lane draws its
+      // voxel's noise and dots the voxel's basis row with w (w broadcast from
+      // LDS; the row's 16-byte loads are independent, so several stay in
+      // flight per lane, and a stream of 81 voxels takes two rounds)
       for (int64_t tb = t0; tb < t1; tb += 64) {
-        const int64_t tl = tb + lane, voxl = tl * 32 + colc;
-        const float zl = (tl < t1 && voxl < a.v)
-                             ? noise_z(a.seed, a.stream, static_cast<unsigned>(a.col0 + i), voxl, a.study)
-                             : 0.0f;
-        const int nb = t1 - tb < 64 ? static_cast<int>(t1 - tb) : 64;
-        const int g = lane >> 4, l16 = lane & 15;
-        for (int q = 0; q < nb; q += 4) {
-          const int64_t vox = (tb + q + g) * 32 + colc;
-          const bool okq = q + g < nb && vox < a.v;
-          float sacc = 0.0f;
-          if (okq) {
-            const float* u = a.U + vox * a.r;
-            for (int c = 4 * l16; c < a.r; c += 64) {
-              if (vec && c + 4 <= a.r) {
-                const f32x4 x = *reinterpret_cast<const f32x4*>(u + c);
-                sacc = fmaf(x[0], w[c], sacc);
-                sacc = fmaf(x[1], w[c + 1], sacc);
-                sacc = fmaf(x[2], w[c + 2], sacc);
-                sacc = fmaf(x[3], w[c + 3], sacc);
-              } else {
-                for (int e = c; e < c + 4 && e < a.r; ++e) sacc = fmaf(u[e], w[e], sacc);
-              }
+        const int64_t tl = tb + lane, vox = tl * 32 + colc;
+        if (tl < t1 && vox < a.v) {
+          const float z = noise_z(a.seed, a.stream, static_cast<unsigned>(a.col0 + i), vox, a.study);
+          const float* u = a.U + vox * a.r;
+          float acc = 0.0f;
+          if (vec) {
+#pragma unroll 5
+            for (int c = 0; c < a.r; c += 4) {
+              const f32x4 x = *reinterpret_cast<const f32x4*>(u + c);
+              acc = fmaf(x[0], w[c], acc);
+              acc = fmaf(x[1], w[c + 1], acc);
+              acc = fmaf(x[2], w[c + 2], acc);
+              acc = fmaf(x[3], w[c + 3], acc);
             }
+          } else {
+            for (int c = 0; c < a.r; ++c) acc = fmaf(u[c], w[c], acc);
           }
-#pragma unroll
-          for (int off = 1; off < 16; off <<= 1) sacc += __shfl_xor(sacc, off, 64);
-          const float z = __shfl(zl, q + g, 64);
-          if (okq) best = fmaxf(best, fmaf(sigma, z, sacc));
+          best = fmaxf(best, fmaf(sigma, z, acc));
         }
       }
     }
