@@ -33,6 +33,7 @@ METRIC = "max-null permutations/s, n=100 v=250k: RapidPT vs NaivePT on GPU, KL<1
 PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6        # vector FP64
+PEAK_FP32_TFLOPS = 157.3       # FP32 (vector and matrix)
 # VALU issue bound of the noise draw, per 16 normals of one lane (four
 # Philox4x32-10 calls, every wave64 instruction covering 64 lanes): 67
 # v_mad_u64_u32 and 74 v_bitop3_b32 (the products and three-input XORs of the
@@ -330,8 +331,18 @@ def main():
     naive_ms = 1e3 * nwall / a.steps
     log(f"naivept {naive_ms:.3f} ms/step")
 
-    rec_only = h2d_ms = None
+    rec_only = h2d_ms = naive_fp32 = None
     if not a.headline_only:
+        # NaivePT on the FP32 path (FP32 matrix cores, one product per
+        # relabelling tile): the precision alternative to the split-BF16 one
+        naive32 = lambda: rpt.naive_maxnull(Xd, Ld, prec="fp32")
+        naive32()
+        _, n32wall, _ = timed(naive32, False)
+        n32_ms = 1e3 * n32wall / a.steps
+        ach32 = 2.0 * v * n * L / (n32_ms * 1e-3) / 1e12
+        naive_fp32 = {"value": L / (n32wall / a.steps), "unit": "perms/s", "ms_per_step": n32_ms,
+                      "achieved_tflops": ach32, "peak_tflops": PEAK_FP32_TFLOPS, "frac": ach32 / PEAK_FP32_TFLOPS}
+        log(f"naivept fp32 {n32_ms:.3f} ms/step")
         # the recovery half alone (Alg. 2's RECOVERY on the trained basis)
         recover = lambda: rpt.recover_maxnull(Xd, Ld[ell:], tr["U"], tr["sigma_mu"], omrd, seed, col0=ell)
         recover()
@@ -402,6 +413,7 @@ def main():
         "h2d_ms_X": h2d_ms,
         "naivept": {"value": L / (nwall / a.steps), "unit": "perms/s", "ms_per_step": naive_ms,
                     "roofline": naive_roof},
+        "naivept_fp32": naive_fp32,
         "rapidpt_vs_naivept": value / (L / (nwall / a.steps)),
         "ms_per_step_with_stage_events": 1e3 * wall_ev / a.steps,
         "stages_ms_per_step": {s: round(t, 4) for s, t in sorted(tot.items(), key=lambda kv: -kv[1])},
