@@ -156,3 +156,13 @@ def test_autotune_table_from_environment(tmp_path):
     out = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip().splitlines()[-1] == "0"
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """The benchmark is one-GPU only: --gpus above 1 exits with status 2 and a
+    message, before touching any device."""
+    import subprocess
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                         text=True, timeout=120)
+    assert out.returncode == 2
+    assert "one GPU only" in out.stderr
