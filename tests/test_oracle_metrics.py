@@ -43,3 +43,19 @@ def test_threshold_order_statistic():
     np.testing.assert_allclose(p, [0.06, 0.05, 0.01, 1.0])
     rej = M.rejected(m, np.array([95.0, 95.5, 101.0]), 0.05)
     assert list(rej) == [False, True, True]
+
+
+def test_bench_kl_matches_the_oracle_definition():
+    """The benchmark's own KL of two max nulls (it may not call the oracle)
+    follows the same binning as the oracle's."""
+    import importlib.util
+    import os
+    from conftest import ROOT
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    rng = np.random.default_rng(3)
+    a = rng.gumbel(size=5000) * 0.3 + 4.0
+    b = a + rng.normal(size=5000) * 0.05
+    assert abs(bench.kl_max_nulls(a, b) - M.kl_divergence(a, b)) <= 1e-12
+    assert bench.kl_max_nulls(a, a) == 0.0
