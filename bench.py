@@ -217,26 +217,7 @@ def main():
                     help="only run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     ap.add_argument("--simulations", action="store_true",
                     help="only run RapidPT against NaivePT on Simulation Data I and II (accuracy sweep)")
-    ap.add_argument("--issue-rates", action="store_true",
-                    help="only measure the VALU issue rates behind the noise generator's ALU bound")
     a = ap.parse_args()
-    if a.issue_rates:
-        import ctypes as C
-        import torch
-        from paper_1703_01506_amd import _lib
-        lib = _lib.load()
-        cus = torch.cuda.get_device_properties(0).multi_processor_count
-        ws = torch.empty(lib.rpt_issue_rates_workspace(cus), dtype=torch.uint8, device="cuda")
-        cyc = (C.c_double * 5)()
-        rc = lib.rpt_issue_rates(cus, 2.4, 20000, cyc, ws.data_ptr(), ws.numel(),
-                                 torch.cuda.current_stream().cuda_stream)
-        _lib.check(rc, "rpt_issue_rates")
-        names = ["fp32_add", "log_f32", "sin_f32", "bitop3_b32", "mad_u64_u32_and_xor_mean"]
-        out = {n_: round(c_, 3) for n_, c_ in zip(names, cyc)}
-        out["mad_u64_u32"] = round(2 * cyc[4] - cyc[0], 3)  # the pair's xor at the add rate
-        print(json.dumps({"compute_units": cus, "clock_ghz": 2.4,
-                          "simd_cycles_per_wave64_instruction": out}))
-        return
     if a.simulations:
         simulations(a)
         return

@@ -144,20 +144,6 @@ void rpt_autotune_clear(void);
 int rpt_autotune_count(void);
 
 /* -------------------------------------------------------------------------
- * Diagnostic: issue rates of the VALU instruction classes of the noise
- * generator (FP32 add, v_log_f32, v_sin_f32, v_bitop3_b32, and the pair
- * v_mad_u64_u32 + v_xor_b32), measured with eight independent chains per lane
- * and eight waves per SIMD over `compute_units` x 8 workgroups.
- * cycles_out (HOST, 5 doubles) receives SIMD cycles per wave64 instruction at
- * clock_ghz (the pair's entry is the mean of its two instructions).  ws: DEVICE
- * scratch of rpt_issue_rates_workspace(compute_units) bytes.  Synchronises
- * `stream`; not for graph capture.  Not used by any computation above.
- * ------------------------------------------------------------------------- */
-size_t rpt_issue_rates_workspace(int32_t compute_units);
-rpt_status rpt_issue_rates(int32_t compute_units, double clock_ghz, int32_t iters, double* cycles_out,
-                           void* ws, size_t ws_bytes, void* stream);
-
-/* -------------------------------------------------------------------------
  * NaivePT -- Alg. 1 (Sec. 2.1).
  *
  * For each of the L relabellings, computes the t statistic at all v voxels and

@@ -6,9 +6,11 @@ column i of the paper's v x L matrix):
 TRAINING (Sec. 4.1)
   U <- Rand. Orth.          : Q factor (positive diag R) of a v x r Gaussian.
   T_ex[:, i] <- test(...)   : l fully computed columns (``tstat.tmatrix``).
-  Subspace-Tracking(r)      : several passes over the l columns; each visit
-                              samples ceil(eta v) voxels, fits the column on
-                              them by least squares (Complete) and moves U.
+  Subspace-Tracking(r)      : passes over the l columns, one column at a time;
+                              each visit samples ceil(eta v) voxels, fits the
+                              column on them by least squares (Complete) and
+                              moves U; passes repeat until the subspace stops
+                              moving (or a pass cap is reached).
   sigma, mu                 : residual spread and max-null shift.
 RECOVERY (Sec. 4.2)
   for each remaining column: sample Omega_i, t on the sampled voxels,
@@ -16,14 +18,25 @@ RECOVERY (Sec. 4.2)
 
 Readings where the paper is silent:
 
-* Subspace tracking is GROUSE (Balzano, Nowak & Recht 2010, the l2 tracker the
-  paper cites) with the greedy step angle theta = arctan(|r| / |p|) (Zhang &
-  Balzano 2016).  For one column that step maps span(U) to the span of U
-  restricted to w-perp plus the imputed column p + r, which is exactly
-  span(U + r w^T / |w|^2).  We apply this first-order form to a mini-batch of
-  B columns at once (all w from the same U, updates summed), scaled by a
-  damping factor gamma, then re-orthonormalise by QR.  B = 1 reproduces
-  sequential GROUSE's subspace sequence.
+* Subspace tracking is GROUSE (Balzano, Nowak & Recht 2010, the l2 tracker
+  the paper cites), applied to the training columns one by one as Sec. 4.1
+  describes, with the greedy step angle theta = arctan(|r| / |p|) (Zhang &
+  Balzano 2016) scaled by gamma (1 = greedy): U <- U + ((cos theta - 1) p/|p|
+  + sin theta r/|r|) w^T/|w|, p = U w the fitted column, r the residual on the
+  sampled entries (zero elsewhere).  ``grouse_step``.
+* "Until convergence": the tracking minimises Eq. 1 one visit at a time; the
+  objective of a pass is the sum over its visits of the squared residual of
+  the column's fit on its sampled entries, taken before U moves.  Tracking
+  stops after the first pass (from the second on) whose objective fell by at
+  most a relative tolerance from the pass before, or after the given number
+  of passes (tol = 0 runs them all).
+  ``subspace_change`` and ``calibration`` measure how far the basis moved and
+  how far it is from T_ex's leading singular subspace; they are reports, not
+  part of the rule.
+* A non-paper variant (``batch`` > 1) moves U by the summed first-order
+  updates r_b w_b^T / |w_b|^2 of a mini-batch of columns, all fitted on the
+  same U, then re-orthonormalises by QR (Jacobi-style; B = 1 spans the same
+  subspace as one greedy GROUSE step).  ``track_step``.
 * A fresh sampled set is drawn for every (pass, column) visit.
 * sigma: sample standard deviation (divisor N-1) of the least-squares residuals
   y - U_Omega w over all sampled entries of a final pass over the l columns
@@ -34,18 +47,26 @@ Readings where the paper is silent:
   maximum that Sec. 4.1 describes.  ``mu_rule="literal"`` is Alg. 2's
   sup_i Max(T_ex[:, i] - U W_ex[:, i]); ``"zero"`` disables the shift.
 * Complete is the ordinary least-squares fit on the sampled rows.
+* The statistic is an input of Alg. 2: the t statistic of Eq. 2 (``"t"``) or
+  the linear mean difference (``"meandiff"``), whose permutation matrix has
+  rank at most n - 1 (Sec. 3.2).
 * The first l maxima are the exact training maxima (Alg. 2), the rest are
   recovered; the recovered maximum is signed.
 
 Pins (tests/test_oracle_rapidpt.py): least squares vs. the normal equations
-and an explicit residual-orthogonality check; orthonormality after every
-update; the single-column greedy-step identity (refitting the same column on
-the same set gives a zero residual); exact recovery of an exactly rank-r
-subspace from full observations; the linear mean-difference statistic, whose
-permutation matrix is exactly low rank, where recovery with sigma = mu = 0
-reproduces the NaivePT maxima.  The convergence rate of tracking on
-t-statistics has no printed value in the paper: parity unpinned there (GPU
-and oracle are compared on identical inputs instead).
+and an explicit residual-orthogonality check; the geodesic step written out
+from GROUSE's definition, orthonormality after every step and for any gamma;
+the greedy-step identity (refitting the same column on the same set gives a
+zero residual); sequential tracking and the mini-batch variant each recover
+an exactly rank-r subspace from sampled (not full) observations, principal
+angles going to zero, and a sign error in either update fails that; the
+subspace change against principal angles; the stopping rule's pass count;
+sigma and both mu rules on hand-computed cases (including the sign of the
+mean gap); the linear mean-difference statistic, whose permutation matrix is
+exactly low rank, where recovery with sigma = mu = 0 reproduces the NaivePT
+maxima.  The convergence rate of tracking on t-statistics has no printed
+value in the paper: parity unpinned there (GPU and oracle are compared on
+identical inputs instead).
 """
 from __future__ import annotations
 
@@ -73,11 +94,39 @@ def complete(U: np.ndarray, idx: np.ndarray, y: np.ndarray) -> np.ndarray:
     return w
 
 
-def track_step(U: np.ndarray, T_rows: np.ndarray, sets, gamma: float = 1.0) -> np.ndarray:
-    """One mini-batch tracking update.
+def grouse_step(U: np.ndarray, x: np.ndarray, idx, gamma: float = 1.0, loss: list | None = None) -> np.ndarray:
+    """One GROUSE step on column x (length v) observed at the voxels idx.
+
+    w = Complete(U, idx, x[idx]); p = U w; r = x - p on idx, 0 elsewhere;
+    theta = gamma * arctan(|r| / |p|);
+    U <- U + ((cos theta - 1) p / |p| + sin theta r / |r|) (w / |w|)^T.
+    No move when w = 0 or r = 0.  U must be orthonormal (the step keeps it so).
+    `loss`, when given, receives |r|^2 (the fit's squared sampled residual
+    before the move).
+    """
+    idx = np.asarray(idx)
+    y = np.asarray(x, dtype=np.float64)[idx]
+    w = complete(U, idx, y)
+    p = U @ w
+    r = np.zeros(U.shape[0])
+    r[idx] = y - p[idx]
+    nw, nr, npn = np.linalg.norm(w), np.linalg.norm(r), np.linalg.norm(p)
+    if loss is not None:
+        loss.append(nr * nr)
+    if nw == 0.0 or nr == 0.0 or npn == 0.0:
+        return U
+    theta = gamma * np.arctan(nr / npn)
+    step = (np.cos(theta) - 1.0) * p / npn + np.sin(theta) * r / nr
+    return U + np.outer(step, w / nw)
+
+
+def track_step(U: np.ndarray, T_rows: np.ndarray, sets, gamma: float = 1.0,
+               loss: list | None = None) -> np.ndarray:
+    """One mini-batch update of the non-paper Jacobi variant.
 
     T_rows[b] is the full column of T for batch member b, sets[b] its sampled
-    voxel indices.  Returns the re-orthonormalised basis.
+    voxel indices.  Returns the re-orthonormalised basis; `loss`, when given,
+    receives each member's squared sampled residual.
     """
     D = np.zeros_like(U)
     for b in range(len(sets)):
@@ -85,27 +134,82 @@ def track_step(U: np.ndarray, T_rows: np.ndarray, sets, gamma: float = 1.0) -> n
         y = T_rows[b][idx]
         w = complete(U, idx, y)
         e = y - U[idx] @ w
+        if loss is not None:
+            loss.append(float(e @ e))
         nw2 = float(w @ w)
         if nw2 > 0.0:
             D[idx] += np.outer(e, w) * (gamma / nw2)
     return orthonormalize(U + D)
 
 
+def subspace_change(U_old: np.ndarray, U_new: np.ndarray) -> float:
+    """|P_new - P_old|_F / sqrt(2 r) for orthonormal bases (P = U U^T): 0 for
+    the same subspace, 1 for orthogonal ones.  Uses |P_a - P_b|_F^2 =
+    2 (r - |U_a^T U_b|_F^2)."""
+    r = U_old.shape[1]
+    C = U_old.T @ U_new
+    return float(np.sqrt(max(0.0, r - float(np.sum(C * C))) / r))
+
+
 def train_subspace(T_ex: np.ndarray, U0: np.ndarray, omega_train: np.ndarray,
-                   passes: int, batch: int | None = None, gamma: float = 1.0) -> np.ndarray:
-    """Subspace tracking over the training columns.
+                   passes: int, batch: int = 1, gamma: float = 1.0, tol: float = 0.0,
+                   history: list | None = None) -> np.ndarray:
+    """Subspace tracking over the training columns (Sec. 4.1).
 
     T_ex: l x v; U0: v x r (orthonormalised first); omega_train:
     (passes*l) x k, row p*l + i is the sampled set of column i in pass p.
+    batch = 1 is GROUSE column by column (the paper's mode); batch > 1 the
+    mini-batch variant.
+
+    Until convergence: the objective of a pass is Eq. 1 on the entries the
+    pass samples, sum_i |r_i|^2 with r_i the residual of column i's fit just
+    before U moves.  Tracking stops after the first pass p >= 2 whose
+    objective fell by at most tol (relative) from the pass before, else after
+    `passes` passes (tol = 0: always `passes`).  `history`, when given,
+    receives each pass's objective.
     """
     ell = T_ex.shape[0]
-    batch = ell if batch is None else int(batch)
+    batch = int(batch)
     U = orthonormalize(U0)
+    prev = None
     for p in range(passes):
-        for b0 in range(0, ell, batch):
-            b1 = min(ell, b0 + batch)
-            U = track_step(U, T_ex[b0:b1], [omega_train[p * ell + i] for i in range(b0, b1)], gamma)
+        loss: list = []
+        if batch == 1:
+            for i in range(ell):
+                U = grouse_step(U, T_ex[i], omega_train[p * ell + i], gamma, loss)
+        else:
+            for b0 in range(0, ell, batch):
+                b1 = min(ell, b0 + batch)
+                U = track_step(U, T_ex[b0:b1], [omega_train[p * ell + i] for i in range(b0, b1)], gamma, loss)
+        obj = float(np.sum(loss))
+        if history is not None:
+            history.append(obj)
+        if tol > 0.0 and prev is not None and prev - obj <= tol * prev:
+            break
+        prev = obj
     return U
+
+
+def principal_angle_cosines(U: np.ndarray, V: np.ndarray) -> np.ndarray:
+    """Cosines of the principal angles between span(U) and span(V)
+    (orthonormal columns): the singular values of U^T V, descending."""
+    return np.linalg.svd(U.T @ V, compute_uv=False)
+
+
+def calibration(T_ex: np.ndarray, U: np.ndarray, T_held: np.ndarray | None = None) -> dict:
+    """How far a tracked basis is from the best rank-r basis of T_ex: the
+    principal angles between U and the r leading left singular vectors of
+    T_ex (the brute-force alternative Sec. 4.1 describes), and the residual
+    spread of T_ex and of held-out columns after projection onto U."""
+    r = U.shape[1]
+    Us = np.linalg.svd(T_ex.T, full_matrices=False)[0][:, :r]
+    cs = np.clip(principal_angle_cosines(U, Us), 0.0, 1.0)
+    out = {"max_angle_deg": float(np.degrees(np.arccos(cs.min()))),
+           "mean_cos2": float(np.mean(cs ** 2)),
+           "train_resid_std": float(np.std(T_ex - (T_ex @ U) @ U.T))}
+    if T_held is not None:
+        out["held_resid_std"] = float(np.std(T_held - (T_held @ U) @ U.T))
+    return out
 
 
 def sigma_mu(T_ex: np.ndarray, U: np.ndarray, omega_sm: np.ndarray, seed: int,
@@ -161,12 +265,13 @@ def recover(X, labels, U, sigma, mu, omegas, seed, col0: int = 0, stat: str = "t
 
 
 def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omega_rec,
-                    passes, seed, batch=None, gamma=1.0, mu_rule="mean_gap"):
+                    passes, seed, batch=1, gamma=1.0, mu_rule="mean_gap", stat="t", tol=0.0,
+                    history=None):
     """Alg. 2 end to end.  Returns (h, U, sigma, mu): h holds the l exact
     training maxima followed by the L - l recovered ones."""
-    from .tstat import tmatrix
-    T_ex = tmatrix(X, train_labels)
-    U = train_subspace(T_ex, U0, omega_train, passes, batch, gamma)
+    X = np.asarray(X, dtype=np.float64)
+    T_ex = np.stack([STATS[stat](X, train_labels[i] == 1) for i in range(train_labels.shape[0])])
+    U = train_subspace(T_ex, U0, omega_train, passes, batch, gamma, tol, history)
     sigma, mu, tmax = sigma_mu(T_ex, U, omega_sm, seed, mu_rule)
-    rec = recover(X, rec_labels, U, sigma, mu, omega_rec, seed, col0=T_ex.shape[0])
+    rec = recover(X, rec_labels, U, sigma, mu, omega_rec, seed, col0=T_ex.shape[0], stat=stat)
     return np.concatenate([tmax, rec]), U, sigma, mu

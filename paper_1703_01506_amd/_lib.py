@@ -45,8 +45,6 @@ SIGNATURES = {
     "rpt_train_subspace": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i32, _p, _i32, _p, _i32, _i32, _i32, _f32,
                                   _p, _u64, _int, _int, _p, _p, _p, _p, _p, _p, _sz, _p]),
     "rpt_recover_workspace": (_sz, [_i64, _i32, _i64, _i32, _i32]),
-    "rpt_issue_rates_workspace": (_sz, [_i32]),
-    "rpt_issue_rates": (_int, [_i32, C.c_double, _i32, _p, _p, _sz, _p]),
     "rpt_autotune_naive": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _int, _p, _i32, _p, _sz, _p, _p]),
     "rpt_autotune_recover_workspace": (_sz, [_i64, _i32, _i64]),
     "rpt_autotune_recover": (_int, [_i64, _i32, _i64, _i32, _p, _sz, _p, _p]),

@@ -696,11 +696,14 @@ rpt_status recon_finish(const float* U, int64_t v, int r, const float* W, int64_
                         float* gap_out, int ks, const ReconBufs& b, const ReconPlan& pu, hipStream_t s,
                         unsigned study) {
   const ReconPlan pl = recon_plan(v, L, r, kFilterPT);
-  // BF16 rounding of both operands (2^-9 each), their product term, and FP32
-  // accumulation in the bound pass and in the exact pass (K terms each, 2^-24)
+  // BF16 keeps 8 significant bits, so round-to-nearest moves each operand by
+  // at most 2^-8 of itself and a product of two rounded operands by at most
+  // (2 * 2^-8 + 2^-16) of the exact product; summed over the K terms that is
+  // at most (2^-7 + 2^-16) |U_k| |w| (Cauchy-Schwarz).  FP32 accumulation in
+  // the bound pass and in the exact pass adds K terms of 2^-24 each.
   const int kpad = 16 * ks;
   const float eps =
-      static_cast<float>((ldexp(1.0, -8) + ldexp(1.0, -18) + 2.02 * (kpad + r) * ldexp(1.0, -24)) * 1.01);
+      static_cast<float>((ldexp(1.0, -7) + ldexp(1.0, -16) + 2.02 * (kpad + r) * ldexp(1.0, -24)) * 1.01);
 
   // exact-pruning path (runs when the device decided path 1)
   FilterArgs fa{b.ukb, W, r, ks, v, pl.vpad, pl.vt, L, pl.tpc, pl.pg, pl.nc, b.smax, b.path};

@@ -101,7 +101,7 @@ __global__ __launch_bounds__(kBlock) void sampled_kernel(SampledArgs a) {
       }
       const int q = q0 + e * kGroups + grp;
       if (gl == 0 && q < ki)
-        a.y[base + q] = (vox[e] < 0 || vox[e] >= a.v) ? NAN : t_of(a, vox[e], s1, q1);  // out of range: no statistic
+        a.y[base + q] = (vox[e] < 0 || vox[e] >= a.v) ? 0.0f : t_of(a, vox[e], s1, q1);  // out of range: 0
     }
   }
 }

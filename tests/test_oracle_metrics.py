@@ -34,6 +34,22 @@ def test_kl_self_zero_and_positive():
     assert M.kl_divergence(a, a + 0.5) > 0.05
 
 
+def test_kl_hand_value_fixes_direction_binning_and_pseudocount():
+    """3 equal-width bins over the common range [0, 3] (edges 0, 1, 2, 3; the
+    last bin closed).  ref = (0, 0.5, 1, 3): counts (2, 1, 1); test = (2.1,
+    2.9, 3, 3): counts (0, 0, 4).  With 0.5 added per bin the normalised masses
+    are p = (2.5, 1.5, 1.5)/5.5 and q = (0.5, 0.5, 4.5)/5.5, and
+    D_KL(p || q) = sum p log(p / q)."""
+    ref = [0.0, 0.5, 1.0, 3.0]
+    test = [2.1, 2.9, 3.0, 3.0]
+    hand = (2.5 / 5.5) * np.log(2.5 / 0.5) + (1.5 / 5.5) * np.log(1.5 / 0.5) + (1.5 / 5.5) * np.log(1.5 / 4.5)
+    assert M.kl_divergence(ref, test, bins=3) == pytest.approx(hand, rel=1e-14)
+    assert hand == pytest.approx(0.73156, abs=1e-5)
+    back = (0.5 / 5.5) * np.log(0.5 / 2.5) + (0.5 / 5.5) * np.log(0.5 / 1.5) + (4.5 / 5.5) * np.log(4.5 / 1.5)
+    assert M.kl_divergence(test, ref, bins=3) == pytest.approx(back, rel=1e-14)
+    assert abs(back - hand) > 0.05   # the direction matters
+
+
 def test_threshold_order_statistic():
     m = np.arange(1, 101, dtype=float)[::-1]  # 100 .. 1
     # alpha = 0.05, L = 100: m_(100 - 5) = 95
