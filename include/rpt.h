@@ -205,11 +205,21 @@ rpt_status rpt_complete(const float* U, int64_t v, int32_t r,
  * 1. T_ex: the t maps of the l training relabellings (the same contraction as
  *    NaivePT); train_max[i] = max_k T_ex[i, k] (exact maxima).
  * 2. U <- orthonormalised U0 (Q factor with positive diagonal R).
- * 3. `passes` passes over the l columns in mini-batches of `batch` columns:
- *    each visit of column i in pass p samples omega_train[(p*l + i)*k ..+k),
- *    fits w by Complete, forms the residual e on the sampled entries, and the
- *    batch moves U by gamma * sum_i e_i w_i^T / |w_i|^2 (the first-order form
- *    of GROUSE's greedy geodesic step) followed by re-orthonormalisation.
+ * 3. Subspace tracking, up to `passes` passes over the l columns; the visit of
+ *    column i in pass p samples omega_train[(p*l + i)*k ..+k).
+ *    batch == 1 (the paper's mode, Sec. 4.1: each column modifies the
+ *      estimate of U in turn): GROUSE's geodesic step on the column, with
+ *      w = Complete(U, omega, t), p = U w, e the sampled residual and
+ *      theta = gamma * arctan(|e| / |p|) (gamma = 1: the greedy step):
+ *      U <- U + ((cos theta - 1) p/|p| + sin theta e/|e|) w^T/|w|.  Needs
+ *      0 < gamma < 1.5.
+ *      Stopping rule ("until convergence"): the objective of a pass is Eq. 1
+ *      on the entries it samples, sum_i |e_i|^2 taken before U moves; with
+ *      tol > 0 tracking stops after the first pass p >= 1 (counted from 0)
+ *      whose objective fell by at most tol (relative) from pass p - 1.
+ *    batch > 1 (a variant, not the paper's): mini-batches of `batch` columns
+ *      fitted on the same U move it by gamma * sum_i e_i w_i^T / |w_i|^2,
+ *      then re-orthonormalisation; all `passes` passes run (tol must be 0).
  * 4. sigma = sample std (N-1) of the Complete residuals of every training
  *    column on a fresh sampled set omega_sm (l x k); mu by `mu_rule`, with the
  *    mean-gap rule drawing the noise on stream RPT_STREAM_TRAINING.
@@ -221,19 +231,25 @@ rpt_status rpt_complete(const float* U, int64_t v, int32_t r,
  *   sigma_mu     2 FP32 on the device: {sigma, mu}                  (out)
  *   train_max    l FP32                                             (out)
  *   T_ex_out     NULL or l x v FP32                                 (out)
- *   info         l int32 (Complete status of the last visit)        (out)
+ *   info         l int32: 0, or (batch 1) -1 / -2 when a column's fit
+ *                failed (Gram not positive definite / no convergence) and
+ *                U did not move; then the status of the sigma fits  (out)
+ *   objective    NULL or passes FP64: each pass's objective (batch 1; 0 for
+ *                passes not run, and for batch > 1)                  (out)
+ *   passes_used  NULL or 1 int32: passes run                         (out)
  * Requirements: as NaivePT and Complete; balanced designs (n1 = n - n1);
- * 1 <= batch <= l; gamma > 0.
+ * 1 <= batch <= l; gamma > 0; tol >= 0.
  * ------------------------------------------------------------------------- */
 size_t rpt_train_workspace(int64_t v, int32_t n, int32_t ell, int32_t r, int32_t k, int prec);
 rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
                               const uint8_t* train_labels, int32_t ell,
                               const float* U0, int32_t r,
                               const int32_t* omega_train, int32_t k, int32_t passes,
-                              int32_t batch, float gamma,
+                              int32_t batch, float gamma, double tol,
                               const int32_t* omega_sm, uint64_t seed, int mu_rule, int prec,
                               float* U_out, float* sigma_mu, float* train_max, float* T_ex_out,
-                              int32_t* info, void* ws, size_t ws_bytes, void* stream);
+                              int32_t* info, double* objective, int32_t* passes_used,
+                              void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
  * Recovery -- the RECOVERY half of Alg. 2 (Sec. 4.2).
@@ -284,12 +300,13 @@ rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
  * second stream cannot be created, runs every step on `stream` instead.
  *
  *   train_labels  l x n uint8;  rec_labels  L_rec x n uint8             (in)
- *   U0, omega_train, omega_sm, passes, batch, gamma, mu_rule, prec: as
- *                 rpt_train_subspace;  omega_rec  L_rec x k int32        (in)
+ *   U0, omega_train, omega_sm, passes, batch, gamma, tol, mu_rule, prec:
+ *                 as rpt_train_subspace;  omega_rec  L_rec x k int32     (in)
  *   h_out         l + L_rec FP32                                        (out)
  *   U_out         v x r FP32 trained basis                              (out)
  *   sigma_mu      2 FP32 on the device {sigma, mu}                      (out)
  *   train_info    l int32;  rec_info  L_rec int32 (as rpt_complete)     (out)
+ *   objective, passes_used: as rpt_train_subspace                       (out)
  *   ws            rpt_rapidpt_workspace(v, n, l, L_rec, r, k, prec) bytes
  * Errors: those of rpt_train_subspace and rpt_recover_maxnull, all checked
  * before the first launch.
@@ -300,10 +317,11 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
                                const uint8_t* rec_labels, int64_t L_rec,
                                const float* U0, int32_t r,
                                const int32_t* omega_train, int32_t k, int32_t passes,
-                               int32_t batch, float gamma, const int32_t* omega_sm,
+                               int32_t batch, float gamma, double tol, const int32_t* omega_sm,
                                const int32_t* omega_rec, uint64_t seed, int mu_rule, int prec,
                                float* h_out, float* U_out, float* sigma_mu,
                                int32_t* train_info, int32_t* rec_info,
+                               double* objective, int32_t* passes_used,
                                void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------

@@ -43,7 +43,7 @@ SIGNATURES = {
     "rpt_complete": (_int, [_p, _i64, _i32, _p, _i32, _p, _i64, _p, _p, _p, _p, _sz, _p]),
     "rpt_train_workspace": (_sz, [_i64, _i32, _i32, _i32, _i32, _int]),
     "rpt_train_subspace": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i32, _p, _i32, _p, _i32, _i32, _i32, _f32,
-                                  _p, _u64, _int, _int, _p, _p, _p, _p, _p, _p, _sz, _p]),
+                                  C.c_double, _p, _u64, _int, _int, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p]),
     "rpt_recover_workspace": (_sz, [_i64, _i32, _i64, _i32, _i32]),
     "rpt_autotune_naive": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _int, _p, _i32, _p, _sz, _p, _p]),
     "rpt_autotune_recover_workspace": (_sz, [_i64, _i32, _i64]),
@@ -54,7 +54,8 @@ SIGNATURES = {
     "rpt_autotune_count": (_int, []),
     "rpt_rapidpt_workspace": (_sz, [_i64, _i32, _i32, _i64, _i32, _i32, _int]),
     "rpt_rapidpt_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i32, _p, _i64, _p, _i32, _p, _i32, _i32, _i32,
-                                   _f32, _p, _p, _u64, _int, _int, _p, _p, _p, _p, _p, _p, _sz, _p]),
+                                   _f32, C.c_double, _p, _p, _u64, _int, _int, _p, _p, _p, _p, _p, _p, _p, _p,
+                                   _sz, _p]),
     "rpt_recover_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _i64, _p, _i32, _p, _p, _i32, _u64,
                                    _p, _p, _p, _p, _sz, _p]),
     "rpt_recover_batched_workspace": (_sz, [C.POINTER(RptStudy), _i32]),

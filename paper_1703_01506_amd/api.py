@@ -123,10 +123,13 @@ def reorth(U: torch.Tensor):
 
 
 def train_subspace(X, train_labels, U0, omega_train, omega_sm, passes: int, seed: int,
-                   batch: int | None = None, gamma: float = 1.0, mu_rule: str = "mean_gap",
-                   prec: str = "split_bf16", n1: int | None = None, return_T: bool = False):
-    """Training half of Alg. 2.  Returns a dict with U (v, r), sigma_mu (2,),
-    train_max (l,), info (l,) and optionally T_ex (l, v)."""
+                   batch: int = 1, gamma: float = 1.0, mu_rule: str = "mean_gap",
+                   prec: str = "split_bf16", n1: int | None = None, return_T: bool = False, tol: float = 0.0):
+    """Training half of Alg. 2.  batch = 1 tracks one column at a time
+    (GROUSE, the paper's mode); tol > 0 stops once a pass's objective no longer
+    falls by more than tol (relative).  Returns a dict with U (v, r), sigma_mu
+    (2,), train_max (l,), info (l,), objective (passes,) FP64, passes_used (1,)
+    and optionally T_ex (l, v)."""
     lib = _lib.load()
     v, n, ldx = _data(X)
     train_labels = _dev(train_labels, torch.uint8, "train_labels", 2).contiguous()
@@ -138,21 +141,24 @@ def train_subspace(X, train_labels, U0, omega_train, omega_sm, passes: int, seed
     k = omega_sm.shape[1]
     if omega_train.shape != (passes * ell, k) or omega_sm.shape[0] != ell or U0.shape[0] != v:
         raise ValueError("inconsistent shapes")
-    batch = ell if batch is None else int(batch)
+    batch = int(batch)
     n1 = n // 2 if n1 is None else int(n1)
     dev = X.device
     U = torch.empty((v, r), dtype=torch.float32, device=dev)
     sm = torch.empty(2, dtype=torch.float32, device=dev)
     tmax = torch.empty(ell, dtype=torch.float32, device=dev)
     info = torch.empty(ell, dtype=torch.int32, device=dev)
+    obj = torch.empty(max(passes, 1), dtype=torch.float64, device=dev)
+    used = torch.empty(1, dtype=torch.int32, device=dev)
     T = torch.empty((ell, v), dtype=torch.float32, device=dev) if return_T else None
     ws = _workspace(lib.rpt_train_workspace(v, n, ell, r, k, PREC[prec]), dev)
     rc = lib.rpt_train_subspace(_ptr(X), v, n, ldx, n1, _ptr(train_labels), ell, _ptr(U0), r,
-                                _ptr(omega_train), k, passes, batch, float(gamma), _ptr(omega_sm),
+                                _ptr(omega_train), k, passes, batch, float(gamma), float(tol), _ptr(omega_sm),
                                 int(seed), MU_RULE[mu_rule], PREC[prec], _ptr(U), _ptr(sm), _ptr(tmax),
-                                _ptr(T), _ptr(info), _ptr(ws), ws.numel(), _stream(dev))
+                                _ptr(T), _ptr(info), _ptr(obj), _ptr(used), _ptr(ws), ws.numel(), _stream(dev))
     _lib.check(rc, "rpt_train_subspace")
-    out = {"U": U, "sigma_mu": sm, "train_max": tmax, "info": info}
+    out = {"U": U, "sigma_mu": sm, "train_max": tmax, "info": info, "objective": obj[:passes],
+           "passes_used": used}
     if return_T:
         out["T_ex"] = T
     return out
@@ -282,11 +288,12 @@ def rejection_counts(maxima1, maxima2, t, alpha: float = 0.05):
 
 
 def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omega_rec, passes: int, seed: int,
-                    batch: int | None = None, gamma: float = 1.0, mu_rule: str = "mean_gap",
-                    prec: str = "split_bf16"):
+                    batch: int = 1, gamma: float = 1.0, mu_rule: str = "mean_gap",
+                    prec: str = "split_bf16", tol: float = 0.0):
     """Alg. 2 end to end in one library call: the l exact training maxima
     followed by the recovered ones.  Returns (h (L,), train dict, recovery
-    info); the train dict holds U, sigma_mu, train_max (a view of h) and info."""
+    info); the train dict holds U, sigma_mu, train_max (a view of h), info,
+    objective and passes_used (as train_subspace)."""
     lib = _lib.load()
     v, n, ldx = _data(X)
     train_labels = _dev(train_labels, torch.uint8, "train_labels", 2).contiguous()
@@ -300,20 +307,24 @@ def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omeg
     if (omega_train.shape != (passes * ell, k) or omega_sm.shape[0] != ell or omega_rec.shape != (L_rec, k)
             or U0.shape[0] != v):
         raise ValueError("inconsistent shapes")
-    batch = ell if batch is None else int(batch)
+    batch = int(batch)
     dev = X.device
     h = torch.empty(ell + L_rec, dtype=torch.float32, device=dev)
     U = torch.empty((v, r), dtype=torch.float32, device=dev)
     sm = torch.empty(2, dtype=torch.float32, device=dev)
     tinfo = torch.empty(ell, dtype=torch.int32, device=dev)
     rinfo = torch.empty(L_rec, dtype=torch.int32, device=dev)
+    obj = torch.empty(max(passes, 1), dtype=torch.float64, device=dev)
+    used = torch.empty(1, dtype=torch.int32, device=dev)
     ws = _workspace(lib.rpt_rapidpt_workspace(v, n, ell, L_rec, r, k, PREC[prec]), dev)
     rc = lib.rpt_rapidpt_maxnull(_ptr(X), v, n, ldx, n // 2, _ptr(train_labels), ell, _ptr(rec_labels), L_rec,
-                                 _ptr(U0), r, _ptr(omega_train), k, passes, batch, float(gamma), _ptr(omega_sm),
-                                 _ptr(omega_rec), int(seed), MU_RULE[mu_rule], PREC[prec], _ptr(h), _ptr(U),
-                                 _ptr(sm), _ptr(tinfo), _ptr(rinfo), _ptr(ws), ws.numel(), _stream(dev))
+                                 _ptr(U0), r, _ptr(omega_train), k, passes, batch, float(gamma), float(tol),
+                                 _ptr(omega_sm), _ptr(omega_rec), int(seed), MU_RULE[mu_rule], PREC[prec], _ptr(h),
+                                 _ptr(U), _ptr(sm), _ptr(tinfo), _ptr(rinfo), _ptr(obj), _ptr(used), _ptr(ws),
+                                 ws.numel(), _stream(dev))
     _lib.check(rc, "rpt_rapidpt_maxnull")
-    return h, {"U": U, "sigma_mu": sm, "train_max": h[:ell], "info": tinfo}, rinfo
+    return h, {"U": U, "sigma_mu": sm, "train_max": h[:ell], "info": tinfo, "objective": obj[:passes],
+               "passes_used": used}, rinfo
 
 
 def masked_loss_fwd(U, W, omega_ptr, omega_idx, t_vals):

@@ -157,6 +157,7 @@ struct TrainWs {
   void* recon_ws;
   int32_t* lhead;  // [v] per-voxel lists of a batch's sampled entries
   int32_t* lnext;  // [ell][k]
+  GrouseState g;   // sequential tracking (batch 1)
 };
 TrainWs train_carve(void* ws, int64_t v, int n, int n1, int ell, int r, int k, int prec, size_t* total) {
   Carver c(ws);
@@ -175,6 +176,7 @@ TrainWs train_carve(void* ws, int64_t v, int n, int n1, int ell, int r, int k, i
   t.recon_ws = c.take<char>(recon_bytes(v, ell, r));
   t.lhead = c.take<int32_t>(v);
   t.lnext = c.take<int32_t>(static_cast<size_t>(ell) * k);
+  t.g = grouse_carve(c.take<char>(grouse_bytes(r, k)), r, k);
   if (total) *total = c.off;
   return t;
 }
@@ -196,13 +198,15 @@ namespace rpt {
 namespace {
 rpt_status train_check(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* train_labels,
                        int32_t ell, const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
-                       int32_t batch, float gamma, const int32_t* omega_sm, int mu_rule, int prec, const float* U_out,
-                       const float* sigma_mu, const float* train_max, const int32_t* info) {
+                       int32_t batch, float gamma, double tol, const int32_t* omega_sm, int mu_rule, int prec,
+                       const float* U_out, const float* sigma_mu, const float* train_max, const int32_t* info) {
   if (!design_ok(v, n, ldx, n1) || 2 * n1 != n) return design_ok(v, n, ldx, n1) ? RPT_ERR_UNSUPPORTED
                                                                                : RPT_ERR_INVALID_ARG;
   if (ell < 1 || r < 1 || r > 128 || r > v || k < 1 || k > v || passes < 0 || batch < 1 || batch > ell ||
-      !(gamma > 0.0f) || static_cast<int64_t>(ell) * k > INT32_MAX)
+      !(gamma > 0.0f) || static_cast<int64_t>(ell) * k > INT32_MAX || !(tol >= 0.0))
     return RPT_ERR_INVALID_ARG;
+  if (batch == 1 && !(gamma < 1.5f)) return RPT_ERR_INVALID_ARG;  // geodesic angle below 3 pi / 4
+  if (batch > 1 && tol > 0.0) return RPT_ERR_UNSUPPORTED;        // the stopping rule tracks one column at a time
   if (k < r) return RPT_ERR_UNDERDETERMINED;
   if (mu_rule != RPT_MU_MEAN_GAP && mu_rule != RPT_MU_LITERAL && mu_rule != RPT_MU_ZERO) return RPT_ERR_INVALID_ARG;
   if (prec != RPT_FP32 && prec != RPT_SPLIT_BF16) return RPT_ERR_INVALID_ARG;
@@ -219,20 +223,20 @@ rpt_status train_tex(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t 
 rpt_status train_start_basis(int64_t v, int32_t n, int32_t n1, int32_t ell, const float* U0, int32_t r, int32_t k,
                              int prec, float* U_out, void* ws, hipStream_t s);
 rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r, const int32_t* omega_train,
-                       int32_t k, int32_t passes, int32_t batch, float gamma, const int32_t* omega_sm, uint64_t seed,
-                       int mu_rule, int prec, float* U_out, float* sigma_mu, float* train_max, float* T_ex_out,
-                       int32_t* info, void* ws, hipStream_t s,
-                       const std::function<rpt_status(int, int)>& at_step = nullptr);
+                       int32_t k, int32_t passes, int32_t batch, float gamma, double tol, const int32_t* omega_sm,
+                       uint64_t seed, int mu_rule, int prec, float* U_out, float* sigma_mu, float* train_max,
+                       float* T_ex_out, int32_t* info, double* objective, int32_t* passes_used, void* ws,
+                       hipStream_t s, const std::function<rpt_status(int, int)>& at_step = nullptr);
 
 rpt_status train_run(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* train_labels,
                      int32_t ell, const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
-                     int32_t batch, float gamma, const int32_t* omega_sm, uint64_t seed, int mu_rule, int prec,
-                     float* U_out, float* sigma_mu, float* train_max, float* T_ex_out, int32_t* info, void* ws,
-                     hipStream_t s) {
+                     int32_t batch, float gamma, double tol, const int32_t* omega_sm, uint64_t seed, int mu_rule,
+                     int prec, float* U_out, float* sigma_mu, float* train_max, float* T_ex_out, int32_t* info,
+                     double* objective, int32_t* passes_used, void* ws, hipStream_t s) {
   RPT_TRY(train_tex(X, v, n, ldx, n1, train_labels, ell, r, k, prec, train_max, T_ex_out, ws, s));
   RPT_TRY(train_start_basis(v, n, n1, ell, U0, r, k, prec, U_out, ws, s));
-  return train_track(v, n, n1, ell, r, omega_train, k, passes, batch, gamma, omega_sm, seed, mu_rule, prec, U_out,
-                     sigma_mu, train_max, T_ex_out, info, ws, s);
+  return train_track(v, n, n1, ell, r, omega_train, k, passes, batch, gamma, tol, omega_sm, seed, mu_rule, prec,
+                     U_out, sigma_mu, train_max, T_ex_out, info, objective, passes_used, ws, s);
 }
 
 // 1. training columns T_ex and their exact maxima
@@ -264,18 +268,31 @@ rpt_status train_start_basis(int64_t v, int32_t n, int32_t n1, int32_t ell, cons
 // at_step(j, steps), when given, runs before the Cholesky of tracking step j
 // of `steps`.
 rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r, const int32_t* omega_train,
-                       int32_t k, int32_t passes, int32_t batch, float gamma, const int32_t* omega_sm, uint64_t seed,
-                       int mu_rule, int prec, float* U_out, float* sigma_mu, float* train_max, float* T_ex_out,
-                       int32_t* info, void* ws, hipStream_t s,
-                       const std::function<rpt_status(int, int)>& at_step) {
+                       int32_t k, int32_t passes, int32_t batch, float gamma, double tol, const int32_t* omega_sm,
+                       uint64_t seed, int mu_rule, int prec, float* U_out, float* sigma_mu, float* train_max,
+                       float* T_ex_out, int32_t* info, double* objective, int32_t* passes_used, void* ws,
+                       hipStream_t s, const std::function<rpt_status(int, int)>& at_step) {
   TrainWs t = train_carve(ws, v, n, n1, ell, r, k, prec, nullptr);
   float* T = T_ex_out ? T_ex_out : t.T;
-  // 3. tracking passes: Complete links every sampled entry into the list of
-  // its voxel; the update then adds each voxel's entries in one pass
+  RPT_TRY(grouse_init_launch(t.g, passes_used, objective, passes, s));
+  if (batch == 1) {
+    // 3. GROUSE column by column (the paper's mode), one workgroup per pass;
+    // the rest of the chip is free for whatever at_step starts
+    for (int pp = 0; pp < passes; ++pp) {
+      if (at_step) RPT_TRY(at_step(pp, passes));
+      RPT_TRY(grouse_pass_launch(t.g, U_out, v, r, T, v, omega_train + static_cast<int64_t>(pp) * ell * k, k, ell,
+                                 gamma, pp, tol, objective, passes_used, t.info, s));
+      // span(B) is the tracked subspace: its orthonormal basis starts the next pass
+      RPT_TRY(reorth_launch(U_out, v, r, t.g.rinfo, t.reorth_ws, s, nullptr, t.g.stop, pp));
+    }
+  }
+  // 3'. the mini-batch variant: Complete links every sampled entry into the
+  // list of its voxel; the update then adds each voxel's entries in one pass
   RPT_TRY(fill_i32(t.lhead, v, -1, s));
-  const int steps = passes * ((ell + batch - 1) / batch);
+  if (batch > 1 && passes_used) RPT_TRY(fill_i32(passes_used, 1, passes, s));
+  const int steps = batch > 1 ? passes * ((ell + batch - 1) / batch) : 0;
   int step = 0;
-  for (int pp = 0; pp < passes; ++pp) {
+  for (int pp = 0; pp < (batch > 1 ? passes : 0); ++pp) {
     for (int b0 = 0; b0 < ell; b0 += batch) {
       const int nb = b0 + batch <= ell ? batch : ell - b0;
       const int32_t* om = omega_train + (static_cast<int64_t>(pp) * ell + b0) * k;
@@ -312,14 +329,15 @@ extern "C" {
 rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
                               const uint8_t* train_labels, int32_t ell, const float* U0, int32_t r,
                               const int32_t* omega_train, int32_t k, int32_t passes, int32_t batch, float gamma,
-                              const int32_t* omega_sm, uint64_t seed, int mu_rule, int prec, float* U_out,
-                              float* sigma_mu, float* train_max, float* T_ex_out, int32_t* info, void* ws,
-                              size_t ws_bytes, void* stream) {
-  RPT_TRY(train_check(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, omega_sm,
-                      mu_rule, prec, U_out, sigma_mu, train_max, info));
+                              double tol, const int32_t* omega_sm, uint64_t seed, int mu_rule, int prec,
+                              float* U_out, float* sigma_mu, float* train_max, float* T_ex_out, int32_t* info,
+                              double* objective, int32_t* passes_used, void* ws, size_t ws_bytes, void* stream) {
+  RPT_TRY(train_check(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, tol,
+                      omega_sm, mu_rule, prec, U_out, sigma_mu, train_max, info));
   if (!ws_ok(ws, ws_bytes, rpt_train_workspace(v, n, ell, r, k, prec))) return RPT_ERR_WORKSPACE;
-  return train_run(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, omega_sm, seed,
-                   mu_rule, prec, U_out, sigma_mu, train_max, T_ex_out, info, ws, static_cast<hipStream_t>(stream));
+  return train_run(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, tol, omega_sm,
+                   seed, mu_rule, prec, U_out, sigma_mu, train_max, T_ex_out, info, objective, passes_used, ws,
+                   static_cast<hipStream_t>(stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -421,11 +439,12 @@ size_t rpt_rapidpt_workspace(int64_t v, int32_t n, int32_t ell, int64_t L_rec, i
 rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
                                const uint8_t* train_labels, int32_t ell, const uint8_t* rec_labels, int64_t L_rec,
                                const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
-                               int32_t batch, float gamma, const int32_t* omega_sm, const int32_t* omega_rec,
-                               uint64_t seed, int mu_rule, int prec, float* h_out, float* U_out, float* sigma_mu,
-                               int32_t* train_info, int32_t* rec_info, void* ws, size_t ws_bytes, void* stream) {
-  RPT_TRY(train_check(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, omega_sm,
-                      mu_rule, prec, U_out, sigma_mu, h_out, train_info));
+                               int32_t batch, float gamma, double tol, const int32_t* omega_sm,
+                               const int32_t* omega_rec, uint64_t seed, int mu_rule, int prec, float* h_out,
+                               float* U_out, float* sigma_mu, int32_t* train_info, int32_t* rec_info,
+                               double* objective, int32_t* passes_used, void* ws, size_t ws_bytes, void* stream) {
+  RPT_TRY(train_check(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, tol,
+                      omega_sm, mu_rule, prec, U_out, sigma_mu, h_out, train_info));
   RPT_TRY(recover_check(X, v, n, ldx, n1, rec_labels, L_rec, ell, U_out, r, sigma_mu, omega_rec, k, h_out,
                         rec_info));
   const size_t tw = rpt_train_workspace(v, n, ell, r, k, prec);
@@ -440,8 +459,9 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
   // step, each started as that step's Cholesky is reached.
   SideStream* sd = side_stream(s);
   if (!sd) {
-    RPT_TRY(train_run(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, omega_sm,
-                      seed, mu_rule, prec, U_out, sigma_mu, h_out, nullptr, train_info, ws, s));
+    RPT_TRY(train_run(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, tol,
+                      omega_sm, seed, mu_rule, prec, U_out, sigma_mu, h_out, nullptr, train_info, objective,
+                      passes_used, ws, s));
     if (L_rec == 0) return RPT_OK;
     RPT_TRY(recover_front(w, X, ldx, rec_labels, L_rec, omega_rec, k, s));
     return recover_back(w, v, L_rec, ell, U_out, r, sigma_mu, omega_rec, k, seed, h_out + ell, nullptr, rec_info, s);
@@ -466,8 +486,8 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
     return RPT_OK;
   };
   if (st_main == RPT_OK && st_side == RPT_OK && st == RPT_OK)
-    st_main = train_track(v, n, n1, ell, r, omega_train, k, passes, batch, gamma, omega_sm, seed, mu_rule, prec,
-                          U_out, sigma_mu, h_out, nullptr, train_info, ws, s, at_step);
+    st_main = train_track(v, n, n1, ell, r, omega_train, k, passes, batch, gamma, tol, omega_sm, seed, mu_rule,
+                          prec, U_out, sigma_mu, h_out, nullptr, train_info, objective, passes_used, ws, s, at_step);
   if (st_side == RPT_OK && done < L_rec)  // no tracking steps: all columns now
     st_side = recover_sampled(w, rec_labels, n, done, L_rec, omega_rec, k, sd->st);
   const rpt_status st_join = stream_wait(sd, sd->join, sd->st, s);

@@ -256,10 +256,13 @@ rpt_status recon_batched(const ReconStudy* st, int ns, int ks, int* counters, hi
 
 // Orthonormalisation (one Cholesky-QR pass).  before_chol, when given, is
 // called once the Gram reduction is enqueued and before the single-workgroup
-// Cholesky (a point where the rest of the chip is about to idle).
+// Cholesky (a point where the rest of the chip is about to idle).  With stop
+// given, every kernel of the pass does nothing once *stop < pass (a
+// converged tracking loop, decided on the device).
 size_t reorth_bytes(int64_t v, int r);
 rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hipStream_t s,
-                         const std::function<rpt_status()>* before_chol = nullptr);
+                         const std::function<rpt_status()>* before_chol = nullptr, const int32_t* stop = nullptr,
+                         int pass = 0);
 
 // Training helpers (train.hip).
 // U[x] += gamma sum_e resid[e] W[i(e)] / |w_i(e)|^2 over the entries linked
@@ -272,6 +275,31 @@ rpt_status sigma_launch(const float* resid, int64_t n, double* sums, float* sigm
 rpt_status mu_launch(const float* vals, int n, int rule, float* sigma_mu, hipStream_t s);
 rpt_status literal_resid_launch(const float* T, const float* U, const float* W, int64_t v, int r, int64_t ell,
                                 float* out, hipStream_t s);
+
+// Sequential GROUSE tracking (grouse.hip): the basis factor B (in place, v x
+// r) and the r x r factor M of U = B M, its inverse, the sampled values /
+// residuals of the current column, the objectives of the last two passes and
+// the convergence flags.
+struct GrouseState {
+  double* M = nullptr;
+  double* Minv = nullptr;
+  float* ybuf = nullptr;
+  double* objr = nullptr;
+  int32_t* stop = nullptr;
+  int32_t* used_ws = nullptr;
+  int32_t* rinfo = nullptr;  // status of the end-of-pass orthonormalisation
+};
+size_t grouse_bytes(int r, int k);
+GrouseState grouse_carve(void* ws, int r, int k);
+// stop <- none, passes used <- 0 (used: caller's device int, or the workspace's),
+// obj_out[0 .. passes) <- 0 when given
+rpt_status grouse_init_launch(const GrouseState& g, int32_t* used, double* obj_out, int passes, hipStream_t s);
+// One pass of GROUSE steps over the ell training columns (rows of T, leading
+// dimension ldT) with this pass's sampled sets (ell x k), then B <- B M.
+// Skipped on the device once an earlier pass met the stopping rule.
+rpt_status grouse_pass_launch(const GrouseState& g, float* B, int64_t v, int r, const float* T, int64_t ldT,
+                              const int32_t* omega, int k, int ell, float gamma, int pass, double tol,
+                              double* obj_out, int32_t* used, int32_t* info, hipStream_t s);
 
 // Masked loss (masked_loss.hip).
 rpt_status loss_fwd_launch(const float* U, int64_t v, int r, const float* W, int B, const int64_t* ptr, const int32_t* idx,

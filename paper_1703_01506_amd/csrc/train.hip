@@ -39,13 +39,15 @@ constexpr int kGramChunk = 64;
 constexpr int kGramLd = kGramChunk + 8;  // bf16 per staged column (16-byte aligned fragments)
 template <int RB>
 __global__ __launch_bounds__(kBlock, 2) void gram_partial_kernel(const float* __restrict__ U, int64_t v, int r,
-                                                                int64_t rows_per_blk, float* __restrict__ part) {
+                                                                int64_t rows_per_blk, float* __restrict__ part,
+                                                                const int32_t* stop, int pass) {
   constexpr int NTILE = RB * (RB + 1) / 2;
   constexpr int TPW = (NTILE + 3) / 4;                    // tiles per wave
   constexpr int NV = RB;  // column groups of 4 per thread per chunk (4 RB groups over 4 waves)
   __shared__ __align__(16) uint16_t uth[16 * RB * kGramLd];
   __shared__ __align__(16) uint16_t utl[16 * RB * kGramLd];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, c16 = lane & 15, kq = lane >> 4;
+  if (stop && *stop < pass) return;
   const int64_t r0 = blockIdx.x * rows_per_blk;
   const int64_t r1 = r0 + rows_per_blk < v ? r0 + rows_per_blk : v;
   const bool vec = (r & 3) == 0 && (reinterpret_cast<uintptr_t>(U) & 15) == 0;
@@ -124,8 +126,10 @@ __global__ __launch_bounds__(kBlock, 2) void gram_partial_kernel(const float* __
 // loads in flight per lane), LDS combines them.
 constexpr int kRedWaves = 16;
 __global__ __launch_bounds__(64 * kRedWaves) void gram_reduce_kernel(const float* __restrict__ part, int nblk,
-                                                                    int ntile, int r, double* __restrict__ G) {
+                                                                    int ntile, int r, double* __restrict__ G,
+                                                                    const int32_t* stop, int pass) {
   __shared__ double red[kRedWaves][64];
+  if (stop && *stop < pass) return;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int idx = blockIdx.x * 64 + lane;
   const int n = ntile * 256;
@@ -162,8 +166,10 @@ __global__ __launch_bounds__(64 * kRedWaves) void gram_reduce_kernel(const float
 constexpr int kCholThreads = 1024;
 __global__ __launch_bounds__(kCholThreads) void chol_rinv_kernel(const double* __restrict__ Gfull, int r,
                                                                 uint16_t* __restrict__ rinvT_hi,
-                                                                uint16_t* __restrict__ rinvT_lo, int32_t* info) {
+                                                                uint16_t* __restrict__ rinvT_lo, int32_t* info,
+                                                                const int32_t* stop, int pass) {
   extern __shared__ __align__(16) unsigned char sm[];
+  if (stop && *stop < pass) return;
   const int ntri = r * (r + 1) / 2;
   double* G = reinterpret_cast<double*>(sm);
   double* diag = G + ntri;
@@ -216,9 +222,11 @@ constexpr int kRl = kR + 8;  // LDS row length of the staged R^{-T}
 template <int KS>
 __global__ __launch_bounds__(kBlock, 2) void apply_rinv_kernel(float* __restrict__ U, int64_t v, int r,
                                                               const uint16_t* __restrict__ rth,
-                                                              const uint16_t* __restrict__ rtl) {
+                                                              const uint16_t* __restrict__ rtl,
+                                                              const int32_t* stop, int pass) {
   __shared__ __align__(16) uint16_t sh[kR * kRl];
   __shared__ __align__(16) uint16_t sl[kR * kRl];
+  if (stop && *stop < pass) return;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, col = lane & 31;
   for (int t = tid; t < kR * (kR / 8); t += kBlock) {
     const int row = t / (kR / 8), c8 = (t - row * (kR / 8)) * 8;
@@ -440,7 +448,7 @@ size_t reorth_bytes(int64_t v, int r) {
 }
 
 rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hipStream_t s,
-                         const std::function<rpt_status()>* before_chol) {
+                         const std::function<rpt_status()>* before_chol, const int32_t* stop, int pass) {
   if (r < 1 || r > kR) return RPT_ERR_UNSUPPORTED;
   Carver c(ws);
   const int nb = gram_blocks(v);
@@ -454,14 +462,14 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
   {
   RPT_STAGE("reorth_gram", s);
   switch (RB) {
-    case 1: hipLaunchKernelGGL(gram_partial_kernel<1>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
-    case 2: hipLaunchKernelGGL(gram_partial_kernel<2>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
-    case 3: hipLaunchKernelGGL(gram_partial_kernel<3>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
-    case 4: hipLaunchKernelGGL(gram_partial_kernel<4>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
-    case 5: hipLaunchKernelGGL(gram_partial_kernel<5>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
-    case 6: hipLaunchKernelGGL(gram_partial_kernel<6>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
-    case 7: hipLaunchKernelGGL(gram_partial_kernel<7>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
-    default: hipLaunchKernelGGL(gram_partial_kernel<8>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part); break;
+    case 1: hipLaunchKernelGGL(gram_partial_kernel<1>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part, stop, pass); break;
+    case 2: hipLaunchKernelGGL(gram_partial_kernel<2>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part, stop, pass); break;
+    case 3: hipLaunchKernelGGL(gram_partial_kernel<3>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part, stop, pass); break;
+    case 4: hipLaunchKernelGGL(gram_partial_kernel<4>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part, stop, pass); break;
+    case 5: hipLaunchKernelGGL(gram_partial_kernel<5>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part, stop, pass); break;
+    case 6: hipLaunchKernelGGL(gram_partial_kernel<6>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part, stop, pass); break;
+    case 7: hipLaunchKernelGGL(gram_partial_kernel<7>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part, stop, pass); break;
+    default: hipLaunchKernelGGL(gram_partial_kernel<8>, dim3(nb), dim3(kBlock), 0, s, U, v, r, rpb, part, stop, pass); break;
   }
   RPT_CHECK_LAUNCH();
   }
@@ -469,7 +477,7 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
     RPT_STAGE("reorth_reduce", s);
     hipLaunchKernelGGL(gram_reduce_kernel,
                        dim3(static_cast<unsigned>(ceil_div(static_cast<int64_t>(ntile) * 256, 64))),
-                       dim3(64 * kRedWaves), 0, s, part, nb, ntile, r, gfull);
+                       dim3(64 * kRedWaves), 0, s, part, nb, ntile, r, gfull, stop, pass);
     RPT_CHECK_LAUNCH();
   }
   if (before_chol && *before_chol) RPT_TRY((*before_chol)());
@@ -481,7 +489,8 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
   }
   {
     RPT_STAGE("reorth_chol", s);
-    hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(kCholThreads), chol_smem(r), s, gfull, r, rth, rtl, info);
+    hipLaunchKernelGGL(chol_rinv_kernel, dim3(1), dim3(kCholThreads), chol_smem(r), s, gfull, r, rth, rtl, info, stop,
+                       pass);
     RPT_CHECK_LAUNCH();
   }
   int64_t ab = ceil_div(ceil_div(v, 32), 4);
@@ -490,14 +499,14 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
   const int KS = static_cast<int>(ceil_div(r, 16));
   RPT_STAGE("reorth_apply", s);
   switch (KS) {
-    case 1: hipLaunchKernelGGL(apply_rinv_kernel<1>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl); break;
-    case 2: hipLaunchKernelGGL(apply_rinv_kernel<2>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl); break;
-    case 3: hipLaunchKernelGGL(apply_rinv_kernel<3>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl); break;
-    case 4: hipLaunchKernelGGL(apply_rinv_kernel<4>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl); break;
-    case 5: hipLaunchKernelGGL(apply_rinv_kernel<5>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl); break;
-    case 6: hipLaunchKernelGGL(apply_rinv_kernel<6>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl); break;
-    case 7: hipLaunchKernelGGL(apply_rinv_kernel<7>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl); break;
-    default: hipLaunchKernelGGL(apply_rinv_kernel<8>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl); break;
+    case 1: hipLaunchKernelGGL(apply_rinv_kernel<1>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl, stop, pass); break;
+    case 2: hipLaunchKernelGGL(apply_rinv_kernel<2>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl, stop, pass); break;
+    case 3: hipLaunchKernelGGL(apply_rinv_kernel<3>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl, stop, pass); break;
+    case 4: hipLaunchKernelGGL(apply_rinv_kernel<4>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl, stop, pass); break;
+    case 5: hipLaunchKernelGGL(apply_rinv_kernel<5>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl, stop, pass); break;
+    case 6: hipLaunchKernelGGL(apply_rinv_kernel<6>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl, stop, pass); break;
+    case 7: hipLaunchKernelGGL(apply_rinv_kernel<7>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl, stop, pass); break;
+    default: hipLaunchKernelGGL(apply_rinv_kernel<8>, dim3(blocks), dim3(kBlock), 0, s, U, v, r, rth, rtl, stop, pass); break;
   }
   RPT_CHECK_LAUNCH();
   return RPT_OK;

@@ -105,15 +105,18 @@ def test_rapidpt_end_to_end_validation(lib):
     assert need >= lib.rpt_train_workspace(v, n, ell, r, k, prec) + lib.rpt_recover_workspace(v, n, L_rec, r, k)
     ws = C.c_void_p(512)
 
-    def call(n1=10, r_=r, k_=k, ws_bytes=need, batch=ell, passes=2):
-        return lib.rpt_rapidpt_maxnull(d, v, n, n, n1, d, ell, d, L_rec, d, r_, d, k_, passes, batch, 1.0, d, d, 7,
-                                       0, prec, d, d, d, d, d, ws, ws_bytes, None)
+    def call(n1=10, r_=r, k_=k, ws_bytes=need, batch=ell, passes=2, gamma=1.0, tol=0.0):
+        return lib.rpt_rapidpt_maxnull(d, v, n, n, n1, d, ell, d, L_rec, d, r_, d, k_, passes, batch, gamma, tol, d,
+                                       d, 7, 0, prec, d, d, d, d, d, d, d, ws, ws_bytes, None)
 
     assert call(ws_bytes=need - 1) == -4      # workspace
     assert call(n1=9) == -6                    # unbalanced designs are not provided
     assert call(r_=129) == -1                  # rank above 128
     assert call(k_=7) == -2                    # fewer sampled voxels than the rank
     assert call(batch=ell + 1) == -1           # mini-batch larger than l
+    assert call(batch=1, gamma=1.5) == -1      # geodesic angle must stay below 3 pi / 4
+    assert call(tol=-1.0) == -1                # negative stopping tolerance
+    assert call(batch=2, tol=1e-3) == -6       # the stopping rule belongs to column-by-column tracking
 
 
 def test_autotune_table_roundtrip(lib, tmp_path):

@@ -200,26 +200,75 @@ def _train_inputs(n=20, v=3001, ell=30, r=12, k=150, passes=3, seed=31):
     return X, tl, U0, omt, oms
 
 
-@pytest.mark.parametrize("batch", [30, 7])
-def test_train_subspace_matches_oracle(batch):
+@pytest.mark.parametrize("batch,gamma,mu_rule", [(1, 1.0, "mean_gap"), (1, 0.6, "literal"), (1, 1.0, "zero"),
+                                                  (30, 1.0, "mean_gap"), (7, 1.0, "mean_gap"), (7, 0.5, "literal")])
+def test_train_subspace_matches_oracle(batch, gamma, mu_rule):
+    """Training half of Alg. 2 against the oracle: batch 1 is GROUSE column by
+    column (Sec. 4.1), larger batches the mini-batch variant; greedy and
+    damped steps; the three mu rules."""
     torch = torch_cuda()
     import paper_1703_01506_amd as rpt
-    announce(f"train batch={batch}")
+    announce(f"train batch={batch} gamma={gamma} mu={mu_rule}")
     passes, seed = 3, 2017
     X, tl, U0, omt, oms = _train_inputs(passes=passes)
     out = rpt.train_subspace(_dev(torch, X), _dev(torch, tl), _dev(torch, U0), _dev(torch, omt), _dev(torch, oms),
-                             passes=passes, seed=seed, batch=batch, prec="fp32", return_T=True)
+                             passes=passes, seed=seed, batch=batch, gamma=gamma, mu_rule=mu_rule, prec="fp32",
+                             return_T=True)
     U = out["U"].cpu().numpy().astype(np.float64)
     sigma, mu = [float(x) for x in out["sigma_mu"].cpu().numpy()]
     T_ex = OT.tmatrix(X.astype(np.float64), tl)
     assert_t_close(out["T_ex"].cpu().numpy(), T_ex, "fp32", "T_ex")
     assert_t_close(out["train_max"].cpu().numpy(), T_ex.max(axis=1), "fp32", "train_max")
-    Uo = OR.train_subspace(T_ex, U0.astype(np.float64), omt, passes, batch=batch)
-    so, muo, _ = OR.sigma_mu(T_ex, Uo, oms, seed)
+    hist = []
+    Uo = OR.train_subspace(T_ex, U0.astype(np.float64), omt, passes, batch=batch, gamma=gamma, history=hist)
+    so, muo, _ = OR.sigma_mu(T_ex, Uo, oms, seed, mu_rule=mu_rule)
     np.testing.assert_allclose(U.T @ U, np.eye(U.shape[1]), atol=5e-5)
     assert np.abs(U @ U.T - Uo @ Uo.T).max() < 2e-4
     assert abs(sigma - so) <= 1e-3 * so
     assert abs(mu - muo) <= 2e-3
+    assert int(out["passes_used"].item()) == passes
+    if batch == 1:
+        np.testing.assert_allclose(out["objective"].cpu().numpy(), hist, rtol=1e-3)
+    if mu_rule == "zero":
+        assert mu == 0.0
+
+
+def test_train_grouse_stopping_rule():
+    """Until convergence (Sec. 4.1): with a tolerance, tracking stops after the
+    first pass whose objective fell by at most tol from the pass before; the
+    GPU stops at the same pass as the oracle and its objectives agree.  Eight
+    subjects and a rank-7 basis (T_ex is close to rank n - 1) with 20% of the
+    voxels sampled, so the objective falls clearly from pass to pass; the
+    tolerance keeps a 20% margin to every decision the rule takes."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce("train grouse stopping rule")
+    passes, seed = 8, 2017
+    X, tl, U0, omt, oms = _train_inputs(n=8, passes=passes, v=2003, r=7, k=400)
+    T_ex = OT.tmatrix(X.astype(np.float64), tl)
+    full = []
+    OR.train_subspace(T_ex, U0.astype(np.float64), omt, passes, history=full)
+    drops = [(full[p - 1] - full[p]) / full[p - 1] for p in range(1, passes)]
+    # a pass j + 1 whose drop is positive and at most 1/1.5 of every earlier
+    # drop: tol = 1.2 x its drop stops there with a margin of 20% either way
+    pick = [j for j in range(len(drops))
+            if drops[j] > 0 and all(drops[i] > 1.5 * drops[j] for i in range(j))]
+    pick = [j for j in pick if j >= 1] or pick
+    if not pick:
+        pytest.skip("objective sequence gives no clean stopping margin")
+    p_stop = pick[0] + 1
+    tol = 1.2 * drops[pick[0]]
+    hist = []
+    Uo = OR.train_subspace(T_ex, U0.astype(np.float64), omt, passes, tol=tol, history=hist)
+    assert len(hist) == p_stop + 1
+    out = rpt.train_subspace(_dev(torch, X), _dev(torch, tl), _dev(torch, U0), _dev(torch, omt), _dev(torch, oms),
+                             passes=passes, seed=seed, prec="fp32", tol=tol)
+    assert int(out["passes_used"].item()) == len(hist)
+    obj = out["objective"].cpu().numpy()
+    np.testing.assert_allclose(obj[:len(hist)], hist, rtol=1e-3)
+    assert (obj[len(hist):] == 0).all()
+    U = out["U"].cpu().numpy().astype(np.float64)
+    assert np.abs(U @ U.T - Uo @ Uo.T).max() < 2e-4
 
 
 def test_rapidpt_end_to_end_gates():
