@@ -67,6 +67,16 @@ typedef enum {
   RPT_TAIL_ABS = 1     /* m_i = max_k |t_ik|          (two-sided testing)     */
 } rpt_tail;
 
+/* The `stat` input of Alg. 2 (REQUIRE line): which two-sample statistic forms
+ * T.  RPT_STAT_T is Eq. 2 (see the conventions above); RPT_STAT_MEANDIFF is
+ * the linear difference of the group means, m1 - m2, whose permutation
+ * testing matrix T = X C has rank at most n - 1 (Sec. 3.2), so that RapidPT
+ * with an exact basis reproduces NaivePT (balanced designs only). */
+typedef enum {
+  RPT_STAT_T = 0,
+  RPT_STAT_MEANDIFF = 1
+} rpt_stat;
+
 typedef enum {
   RPT_MU_MEAN_GAP = 0, /* mu = mean_i [max T_ex[:,i] - max(U w_i + s_i)]       */
   RPT_MU_LITERAL = 1,  /* mu = sup_i max(T_ex[:,i] - U W_ex[:,i])  (Alg. 2)    */
@@ -156,28 +166,30 @@ int rpt_autotune_count(void);
  *   max_out  L FP32                                            (out)
  *   T_out    NULL, or L x v FP32: the full permutation testing matrix,
  *            row i = t map of relabelling i (for tests and training)   (out)
+ *   stat     RPT_STAT_T (Eq. 2) or RPT_STAT_MEANDIFF (balanced designs only)
  * Requirements: v >= 1, 4 <= n <= 512, 2 <= n1 <= n-2, L >= 0.
- * n1 != n - n1 (unbalanced designs) needs prec == RPT_FP32; RPT_FP32 takes
- * n <= 128 (RPT_ERR_UNSUPPORTED above).  The subject limit n <= 512 applies
- * to every entry point that takes X.
+ * n1 != n - n1 (unbalanced designs) needs prec == RPT_FP32 and stat ==
+ * RPT_STAT_T; RPT_FP32 takes n <= 128 (RPT_ERR_UNSUPPORTED above).  The
+ * subject limit n <= 512 applies to every entry point that takes X.
  * ------------------------------------------------------------------------- */
 size_t rpt_naive_workspace(int64_t v, int32_t n, int64_t L, int prec);
 rpt_status rpt_naive_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
-                             const uint8_t* labels, int64_t L, int tail, int prec,
+                             const uint8_t* labels, int64_t L, int tail, int prec, int stat,
                              float* max_out, float* T_out,
                              void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
  * Sampled t statistics -- the test() step of RapidPT recovery (Alg. 2).
  *
- * y[i*k + q] = t statistic of voxel omega[i*k + q] under relabelling i.
+ * y[i*k + q] = statistic `stat` (as rpt_naive_maxnull) of voxel
+ * omega[i*k + q] under relabelling i.
  *   omega  L x k int32 voxel indices in [0, v), k >= 1      (in)
  *   y      L x k FP32                                       (out)
  * ------------------------------------------------------------------------- */
 size_t rpt_sampled_tstat_workspace(int64_t v, int32_t n);
 rpt_status rpt_sampled_tstat(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
                              const uint8_t* labels, int64_t L,
-                             const int32_t* omega, int32_t k, float* y,
+                             const int32_t* omega, int32_t k, int stat, float* y,
                              void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
@@ -237,6 +249,7 @@ rpt_status rpt_complete(const float* U, int64_t v, int32_t r,
  *   objective    NULL or passes FP64: each pass's objective (batch 1; 0 for
  *                passes not run, and for batch > 1)                  (out)
  *   passes_used  NULL or 1 int32: passes run                         (out)
+ *   stat         the statistic of T_ex (as rpt_naive_maxnull)
  * Requirements: as NaivePT and Complete; balanced designs (n1 = n - n1);
  * 1 <= batch <= l; gamma > 0; tol >= 0.
  * ------------------------------------------------------------------------- */
@@ -246,7 +259,7 @@ rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx,
                               const float* U0, int32_t r,
                               const int32_t* omega_train, int32_t k, int32_t passes,
                               int32_t batch, float gamma, double tol,
-                              const int32_t* omega_sm, uint64_t seed, int mu_rule, int prec,
+                              const int32_t* omega_sm, uint64_t seed, int mu_rule, int prec, int stat,
                               float* U_out, float* sigma_mu, float* train_max, float* T_ex_out,
                               int32_t* info, double* objective, int32_t* passes_used,
                               void* ws, size_t ws_bytes, void* stream);
@@ -268,7 +281,13 @@ rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx,
  *
  *   U         v x r FP32 (orthonormal basis from training)          (in)
  *   sigma_mu  2 FP32 on the device {sigma, mu}                      (in)
- *   omega     L_rec x k int32                                       (in)
+ *   omega     L_rec x k int32 when omega_ptr is NULL; otherwise the
+ *             CSR indices of uneven sampled sets: row j holds
+ *             omega_ptr[j+1] - omega_ptr[j] distinct voxels, every row
+ *             at most k long (k sizes the workspace); a row shorter
+ *             than r gives a failed fit in info               (in)
+ *   omega_ptr NULL or int64 [L_rec + 1] CSR offsets, omega_ptr[0] = 0 (in)
+ *   stat      the statistic sampled (as rpt_naive_maxnull)          (in)
  *   max_out   L_rec FP32                                            (out)
  *   W_out     NULL or L_rec x r FP32 (the fitted coefficients)      (out)
  *   info      L_rec int32 (as rpt_complete)                         (out)
@@ -278,7 +297,8 @@ size_t rpt_recover_workspace(int64_t v, int32_t n, int64_t L_rec, int32_t r, int
 rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
                                const uint8_t* labels, int64_t L_rec, int64_t col0,
                                const float* U, int32_t r, const float* sigma_mu,
-                               const int32_t* omega, int32_t k, uint64_t seed,
+                               const int32_t* omega, int32_t k, const int64_t* omega_ptr,
+                               uint64_t seed, int stat,
                                float* max_out, float* W_out, int32_t* info,
                                void* ws, size_t ws_bytes, void* stream);
 
@@ -300,8 +320,8 @@ rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
  * second stream cannot be created, runs every step on `stream` instead.
  *
  *   train_labels  l x n uint8;  rec_labels  L_rec x n uint8             (in)
- *   U0, omega_train, omega_sm, passes, batch, gamma, tol, mu_rule, prec:
- *                 as rpt_train_subspace;  omega_rec  L_rec x k int32     (in)
+ *   U0, omega_train, omega_sm, passes, batch, gamma, tol, mu_rule, prec,
+ *   stat:         as rpt_train_subspace;  omega_rec  L_rec x k int32     (in)
  *   h_out         l + L_rec FP32                                        (out)
  *   U_out         v x r FP32 trained basis                              (out)
  *   sigma_mu      2 FP32 on the device {sigma, mu}                      (out)
@@ -318,7 +338,7 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
                                const float* U0, int32_t r,
                                const int32_t* omega_train, int32_t k, int32_t passes,
                                int32_t batch, float gamma, double tol, const int32_t* omega_sm,
-                               const int32_t* omega_rec, uint64_t seed, int mu_rule, int prec,
+                               const int32_t* omega_rec, uint64_t seed, int mu_rule, int prec, int stat,
                                float* h_out, float* U_out, float* sigma_mu,
                                int32_t* train_info, int32_t* rec_info,
                                double* objective, int32_t* passes_used,

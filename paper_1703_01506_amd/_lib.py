@@ -36,14 +36,15 @@ SIGNATURES = {
     "rpt_timing_query": (_int, [C.c_char_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)]),
     "rpt_timing_stages": (_int, [C.c_char_p, _sz]),
     "rpt_naive_workspace": (_sz, [_i64, _i32, _i64, _int]),
-    "rpt_naive_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _int, _int, _p, _p, _p, _sz, _p]),
+    "rpt_naive_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _int, _int, _int, _p, _p, _p, _sz, _p]),
     "rpt_sampled_tstat_workspace": (_sz, [_i64, _i32]),
-    "rpt_sampled_tstat": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _p, _i32, _p, _p, _sz, _p]),
+    "rpt_sampled_tstat": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _p, _i32, _int, _p, _p, _sz, _p]),
     "rpt_complete_workspace": (_sz, [_i64, _i32]),
     "rpt_complete": (_int, [_p, _i64, _i32, _p, _i32, _p, _i64, _p, _p, _p, _p, _sz, _p]),
     "rpt_train_workspace": (_sz, [_i64, _i32, _i32, _i32, _i32, _int]),
     "rpt_train_subspace": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i32, _p, _i32, _p, _i32, _i32, _i32, _f32,
-                                  C.c_double, _p, _u64, _int, _int, _p, _p, _p, _p, _p, _p, _p, _p, _sz, _p]),
+                                  C.c_double, _p, _u64, _int, _int, _int, _p, _p, _p, _p, _p, _p, _p, _p, _sz,
+                                  _p]),
     "rpt_recover_workspace": (_sz, [_i64, _i32, _i64, _i32, _i32]),
     "rpt_autotune_naive": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _int, _p, _i32, _p, _sz, _p, _p]),
     "rpt_autotune_recover_workspace": (_sz, [_i64, _i32, _i64]),
@@ -54,10 +55,10 @@ SIGNATURES = {
     "rpt_autotune_count": (_int, []),
     "rpt_rapidpt_workspace": (_sz, [_i64, _i32, _i32, _i64, _i32, _i32, _int]),
     "rpt_rapidpt_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i32, _p, _i64, _p, _i32, _p, _i32, _i32, _i32,
-                                   _f32, C.c_double, _p, _p, _u64, _int, _int, _p, _p, _p, _p, _p, _p, _p, _p,
-                                   _sz, _p]),
-    "rpt_recover_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _i64, _p, _i32, _p, _p, _i32, _u64,
-                                   _p, _p, _p, _p, _sz, _p]),
+                                   _f32, C.c_double, _p, _p, _u64, _int, _int, _int, _p, _p, _p, _p, _p, _p, _p,
+                                   _p, _sz, _p]),
+    "rpt_recover_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _i64, _p, _i32, _p, _p, _i32, _p, _u64,
+                                   _int, _p, _p, _p, _p, _sz, _p]),
     "rpt_recover_batched_workspace": (_sz, [C.POINTER(RptStudy), _i32]),
     "rpt_recover_maxnull_batched": (_int, [C.POINTER(RptStudy), _i32, _p, _sz, _p]),
     "rpt_observed_tstat_workspace": (_sz, [_i64, _i32]),

@@ -16,6 +16,7 @@ from . import _lib
 PREC = {"fp32": 0, "split_bf16": 1}
 TAIL = {"signed": 0, "abs": 1}
 MU_RULE = {"mean_gap": 0, "literal": 1, "zero": 2}
+STAT = {"t": 0, "meandiff": 1}
 
 
 def _ptr(t):
@@ -49,9 +50,10 @@ def _data(X: torch.Tensor):
 
 
 def naive_maxnull(X: torch.Tensor, labels: torch.Tensor, n1: int | None = None, tail: str = "signed",
-                  prec: str = "split_bf16", return_T: bool = False):
+                  prec: str = "split_bf16", return_T: bool = False, stat: str = "t"):
     """NaivePT (Alg. 1).  X (v, n) float32, labels (L, n) uint8 with n1 ones per
-    row.  Returns max (L,) float32, and T (L, v) if return_T."""
+    row; stat "t" (Eq. 2) or "meandiff".  Returns max (L,) float32, and T (L, v)
+    if return_T."""
     lib = _lib.load()
     v, n, ldx = _data(X)
     labels = _dev(labels, torch.uint8, "labels", 2).contiguous()
@@ -64,14 +66,15 @@ def naive_maxnull(X: torch.Tensor, labels: torch.Tensor, n1: int | None = None, 
     T = torch.empty((L, v), dtype=torch.float32, device=dev) if return_T else None
     nb = lib.rpt_naive_workspace(v, n, L, PREC[prec])
     ws = _workspace(nb, dev)
-    rc = lib.rpt_naive_maxnull(_ptr(X), v, n, ldx, n1, _ptr(labels), L, TAIL[tail], PREC[prec],
+    rc = lib.rpt_naive_maxnull(_ptr(X), v, n, ldx, n1, _ptr(labels), L, TAIL[tail], PREC[prec], STAT[stat],
                                _ptr(out), _ptr(T), _ptr(ws), ws.numel(), _stream(dev))
     _lib.check(rc, "rpt_naive_maxnull")
     return (out, T) if return_T else out
 
 
-def sampled_tstat(X: torch.Tensor, labels: torch.Tensor, omega: torch.Tensor, n1: int | None = None):
-    """t statistics at sampled voxels: y[i, q] = t(voxel omega[i, q], labels[i])."""
+def sampled_tstat(X: torch.Tensor, labels: torch.Tensor, omega: torch.Tensor, n1: int | None = None,
+                  stat: str = "t"):
+    """Statistics at sampled voxels: y[i, q] = stat(voxel omega[i, q], labels[i])."""
     lib = _lib.load()
     v, n, ldx = _data(X)
     labels = _dev(labels, torch.uint8, "labels", 2).contiguous()
@@ -82,7 +85,7 @@ def sampled_tstat(X: torch.Tensor, labels: torch.Tensor, omega: torch.Tensor, n1
     n1 = n // 2 if n1 is None else int(n1)
     y = torch.empty((L, k), dtype=torch.float32, device=X.device)
     ws = _workspace(lib.rpt_sampled_tstat_workspace(v, n), X.device)
-    rc = lib.rpt_sampled_tstat(_ptr(X), v, n, ldx, n1, _ptr(labels), L, _ptr(omega), k, _ptr(y),
+    rc = lib.rpt_sampled_tstat(_ptr(X), v, n, ldx, n1, _ptr(labels), L, _ptr(omega), k, STAT[stat], _ptr(y),
                                _ptr(ws), ws.numel(), _stream(X.device))
     _lib.check(rc, "rpt_sampled_tstat")
     return y
@@ -124,7 +127,8 @@ def reorth(U: torch.Tensor):
 
 def train_subspace(X, train_labels, U0, omega_train, omega_sm, passes: int, seed: int,
                    batch: int = 1, gamma: float = 1.0, mu_rule: str = "mean_gap",
-                   prec: str = "split_bf16", n1: int | None = None, return_T: bool = False, tol: float = 0.0):
+                   prec: str = "split_bf16", n1: int | None = None, return_T: bool = False, tol: float = 0.0,
+                   stat: str = "t"):
     """Training half of Alg. 2.  batch = 1 tracks one column at a time
     (GROUSE, the paper's mode); tol > 0 stops once a pass's objective no longer
     falls by more than tol (relative).  Returns a dict with U (v, r), sigma_mu
@@ -154,7 +158,7 @@ def train_subspace(X, train_labels, U0, omega_train, omega_sm, passes: int, seed
     ws = _workspace(lib.rpt_train_workspace(v, n, ell, r, k, PREC[prec]), dev)
     rc = lib.rpt_train_subspace(_ptr(X), v, n, ldx, n1, _ptr(train_labels), ell, _ptr(U0), r,
                                 _ptr(omega_train), k, passes, batch, float(gamma), float(tol), _ptr(omega_sm),
-                                int(seed), MU_RULE[mu_rule], PREC[prec], _ptr(U), _ptr(sm), _ptr(tmax),
+                                int(seed), MU_RULE[mu_rule], PREC[prec], STAT[stat], _ptr(U), _ptr(sm), _ptr(tmax),
                                 _ptr(T), _ptr(info), _ptr(obj), _ptr(used), _ptr(ws), ws.numel(), _stream(dev))
     _lib.check(rc, "rpt_train_subspace")
     out = {"U": U, "sigma_mu": sm, "train_max": tmax, "info": info, "objective": obj[:passes],
@@ -165,25 +169,38 @@ def train_subspace(X, train_labels, U0, omega_train, omega_sm, passes: int, seed
 
 
 def recover_maxnull(X, labels, U, sigma_mu, omega, seed: int, col0: int = 0, n1: int | None = None,
-                    return_W: bool = False):
-    """Recovery half of Alg. 2.  Returns (max (L,), info (L,)[, W (L, r)])."""
+                    return_W: bool = False, stat: str = "t", omega_ptr=None):
+    """Recovery half of Alg. 2.  omega is (L, k) int32, or with omega_ptr (L + 1
+    int64 CSR offsets) the flat int32 indices of uneven sampled sets.  Returns
+    (max (L,), info (L,)[, W (L, r)])."""
     lib = _lib.load()
     v, n, ldx = _data(X)
     labels = _dev(labels, torch.uint8, "labels", 2).contiguous()
     U = _dev(U, torch.float32, "U", 2).contiguous()
     sigma_mu = _dev(sigma_mu, torch.float32, "sigma_mu", 1).contiguous()
-    omega = _dev(omega, torch.int32, "omega", 2).contiguous()
-    L, k = omega.shape
+    if omega_ptr is None:
+        omega = _dev(omega, torch.int32, "omega", 2).contiguous()
+        L, k = omega.shape
+    else:
+        omega = _dev(omega, torch.int32, "omega", 1).contiguous()
+        omega_ptr = _dev(omega_ptr, torch.int64, "omega_ptr", 1).contiguous()
+        L = omega_ptr.shape[0] - 1
+        if L != labels.shape[0]:
+            raise ValueError("omega_ptr must have one entry per relabelling plus one")
+        # the longest row sizes the workspace (a host read of the offsets,
+        # marshalling only)
+        offs = omega_ptr.cpu()
+        k = int((offs[1:] - offs[:-1]).max().item()) if L > 0 else 1
     r = U.shape[1]
     n1 = n // 2 if n1 is None else int(n1)
     dev = X.device
     out = torch.empty(L, dtype=torch.float32, device=dev)
     info = torch.empty(L, dtype=torch.int32, device=dev)
     W = torch.empty((L, r), dtype=torch.float32, device=dev) if return_W else None
-    ws = _workspace(lib.rpt_recover_workspace(v, n, L, r, k), dev)
+    ws = _workspace(lib.rpt_recover_workspace(v, n, L, r, max(k, 1)), dev)
     rc = lib.rpt_recover_maxnull(_ptr(X), v, n, ldx, n1, _ptr(labels), L, int(col0), _ptr(U), r,
-                                 _ptr(sigma_mu), _ptr(omega), k, int(seed), _ptr(out), _ptr(W), _ptr(info),
-                                 _ptr(ws), ws.numel(), _stream(dev))
+                                 _ptr(sigma_mu), _ptr(omega), max(k, 1), _ptr(omega_ptr), int(seed), STAT[stat],
+                                 _ptr(out), _ptr(W), _ptr(info), _ptr(ws), ws.numel(), _stream(dev))
     _lib.check(rc, "rpt_recover_maxnull")
     return (out, info, W) if return_W else (out, info)
 
@@ -289,7 +306,7 @@ def rejection_counts(maxima1, maxima2, t, alpha: float = 0.05):
 
 def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omega_rec, passes: int, seed: int,
                     batch: int = 1, gamma: float = 1.0, mu_rule: str = "mean_gap",
-                    prec: str = "split_bf16", tol: float = 0.0):
+                    prec: str = "split_bf16", tol: float = 0.0, stat: str = "t"):
     """Alg. 2 end to end in one library call: the l exact training maxima
     followed by the recovered ones.  Returns (h (L,), train dict, recovery
     info); the train dict holds U, sigma_mu, train_max (a view of h), info,
@@ -319,7 +336,8 @@ def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omeg
     ws = _workspace(lib.rpt_rapidpt_workspace(v, n, ell, L_rec, r, k, PREC[prec]), dev)
     rc = lib.rpt_rapidpt_maxnull(_ptr(X), v, n, ldx, n // 2, _ptr(train_labels), ell, _ptr(rec_labels), L_rec,
                                  _ptr(U0), r, _ptr(omega_train), k, passes, batch, float(gamma), float(tol),
-                                 _ptr(omega_sm), _ptr(omega_rec), int(seed), MU_RULE[mu_rule], PREC[prec], _ptr(h),
+                                 _ptr(omega_sm), _ptr(omega_rec), int(seed), MU_RULE[mu_rule], PREC[prec],
+                                 STAT[stat], _ptr(h),
                                  _ptr(U), _ptr(sm), _ptr(tinfo), _ptr(rinfo), _ptr(obj), _ptr(used), _ptr(ws),
                                  ws.numel(), _stream(dev))
     _lib.check(rc, "rpt_rapidpt_maxnull")

@@ -22,6 +22,10 @@ bool design_ok(int64_t v, int32_t n, int64_t ldx, int32_t n1) {
   return v >= 1 && n >= 4 && n <= 512 && ldx >= n && n1 >= 2 && n1 <= n - 2;
 }
 
+bool stat_ok(int stat, int32_t n, int32_t n1) {
+  return stat == RPT_STAT_T || (stat == RPT_STAT_MEANDIFF && 2 * n1 == n);
+}
+
 int naive_flags(int prec, bool unbal) {
   if (prec == RPT_SPLIT_BF16) return kPrepSplit;
   return kPrepF32 | (unbal ? kPrepUnbal : 0);
@@ -59,9 +63,11 @@ size_t rpt_naive_workspace(int64_t v, int32_t n, int64_t L, int prec) {
 }
 
 rpt_status rpt_naive_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* labels,
-                             int64_t L, int tail, int prec, float* max_out, float* T_out, void* ws, size_t ws_bytes,
-                             void* stream) {
+                             int64_t L, int tail, int prec, int stat, float* max_out, float* T_out, void* ws,
+                             size_t ws_bytes, void* stream) {
   if (!design_ok(v, n, ldx, n1) || L < 0) return RPT_ERR_INVALID_ARG;
+  if (stat != RPT_STAT_T && stat != RPT_STAT_MEANDIFF) return RPT_ERR_INVALID_ARG;
+  if (!stat_ok(stat, n, n1)) return RPT_ERR_UNSUPPORTED;
   if (tail != RPT_TAIL_SIGNED && tail != RPT_TAIL_ABS) return RPT_ERR_INVALID_ARG;
   if (prec != RPT_FP32 && prec != RPT_SPLIT_BF16) return RPT_ERR_INVALID_ARG;
   if (L > 0 && (!X || !labels || (!max_out && !T_out))) return RPT_ERR_INVALID_ARG;
@@ -71,7 +77,7 @@ rpt_status rpt_naive_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, 
   if (!ws_ok(ws, ws_bytes, rpt_naive_workspace(v, n, L, prec))) return RPT_ERR_WORKSPACE;
   if (L == 0) return RPT_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int flags = naive_flags(prec, unbal);
+  const int flags = naive_flags(prec, unbal) | stat_flags(stat);
   Carver c(ws);
   PrepX p = prep_carve(c, v, n, n1, flags);
   const NaivePlan pl = naive_plan(v, L, n, prec, T_out != nullptr);
@@ -90,14 +96,16 @@ size_t rpt_sampled_tstat_workspace(int64_t v, int32_t n) {
 }
 
 rpt_status rpt_sampled_tstat(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* labels,
-                             int64_t L, const int32_t* omega, int32_t k, float* y, void* ws, size_t ws_bytes,
-                             void* stream) {
+                             int64_t L, const int32_t* omega, int32_t k, int stat, float* y, void* ws,
+                             size_t ws_bytes, void* stream) {
   if (!design_ok(v, n, ldx, n1) || L < 0 || k < 0) return RPT_ERR_INVALID_ARG;
+  if (stat != RPT_STAT_T && stat != RPT_STAT_MEANDIFF) return RPT_ERR_INVALID_ARG;
+  if (!stat_ok(stat, n, n1)) return RPT_ERR_UNSUPPORTED;
   if (L > 0 && k > 0 && (!X || !labels || !omega || !y)) return RPT_ERR_INVALID_ARG;
   if (!ws_ok(ws, ws_bytes, rpt_sampled_tstat_workspace(v, n))) return RPT_ERR_WORKSPACE;
   if (L == 0 || k == 0) return RPT_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const int flags = kPrepRows | (2 * n1 != n ? kPrepUnbal : 0);
+  const int flags = kPrepRows | (2 * n1 != n ? kPrepUnbal : 0) | stat_flags(stat);
   Carver c(ws);
   PrepX p = prep_carve(c, v, n, n1, flags | kPrepUnbal);
   if (!(flags & kPrepUnbal)) p.cstg = nullptr;
@@ -159,10 +167,11 @@ struct TrainWs {
   int32_t* lnext;  // [ell][k]
   GrouseState g;   // sequential tracking (batch 1)
 };
-TrainWs train_carve(void* ws, int64_t v, int n, int n1, int ell, int r, int k, int prec, size_t* total) {
+TrainWs train_carve(void* ws, int64_t v, int n, int n1, int ell, int r, int k, int prec, size_t* total,
+                    int stat = RPT_STAT_T) {
   Carver c(ws);
   TrainWs t;
-  t.p = prep_carve(c, v, n, n1, naive_flags(prec, false));
+  t.p = prep_carve(c, v, n, n1, naive_flags(prec, false) | stat_flags(stat));
   const NaivePlan pl = naive_plan(v, ell, n, prec, true);
   t.partial = c.take<float>(static_cast<size_t>(pl.nc_cap) * ell);
   t.T = c.take<float>(static_cast<size_t>(ell) * v);
@@ -199,7 +208,9 @@ namespace {
 rpt_status train_check(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* train_labels,
                        int32_t ell, const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
                        int32_t batch, float gamma, double tol, const int32_t* omega_sm, int mu_rule, int prec,
-                       const float* U_out, const float* sigma_mu, const float* train_max, const int32_t* info) {
+                       int stat, const float* U_out, const float* sigma_mu, const float* train_max,
+                       const int32_t* info) {
+  if (stat != RPT_STAT_T && stat != RPT_STAT_MEANDIFF) return RPT_ERR_INVALID_ARG;
   if (!design_ok(v, n, ldx, n1) || 2 * n1 != n) return design_ok(v, n, ldx, n1) ? RPT_ERR_UNSUPPORTED
                                                                                : RPT_ERR_INVALID_ARG;
   if (ell < 1 || r < 1 || r > 128 || r > v || k < 1 || k > v || passes < 0 || batch < 1 || batch > ell ||
@@ -218,8 +229,8 @@ rpt_status train_check(const float* X, int64_t v, int32_t n, int64_t ldx, int32_
 
 // the training steps on stream s, arguments already checked
 rpt_status train_tex(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* train_labels,
-                     int32_t ell, int32_t r, int32_t k, int prec, float* train_max, float* T_ex_out, void* ws,
-                     hipStream_t s);
+                     int32_t ell, int32_t r, int32_t k, int prec, int stat, float* train_max, float* T_ex_out,
+                     void* ws, hipStream_t s);
 rpt_status train_start_basis(int64_t v, int32_t n, int32_t n1, int32_t ell, const float* U0, int32_t r, int32_t k,
                              int prec, float* U_out, void* ws, hipStream_t s);
 rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r, const int32_t* omega_train,
@@ -231,9 +242,9 @@ rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r,
 rpt_status train_run(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* train_labels,
                      int32_t ell, const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
                      int32_t batch, float gamma, double tol, const int32_t* omega_sm, uint64_t seed, int mu_rule,
-                     int prec, float* U_out, float* sigma_mu, float* train_max, float* T_ex_out, int32_t* info,
-                     double* objective, int32_t* passes_used, void* ws, hipStream_t s) {
-  RPT_TRY(train_tex(X, v, n, ldx, n1, train_labels, ell, r, k, prec, train_max, T_ex_out, ws, s));
+                     int prec, int stat, float* U_out, float* sigma_mu, float* train_max, float* T_ex_out,
+                     int32_t* info, double* objective, int32_t* passes_used, void* ws, hipStream_t s) {
+  RPT_TRY(train_tex(X, v, n, ldx, n1, train_labels, ell, r, k, prec, stat, train_max, T_ex_out, ws, s));
   RPT_TRY(train_start_basis(v, n, n1, ell, U0, r, k, prec, U_out, ws, s));
   return train_track(v, n, n1, ell, r, omega_train, k, passes, batch, gamma, tol, omega_sm, seed, mu_rule, prec,
                      U_out, sigma_mu, train_max, T_ex_out, info, objective, passes_used, ws, s);
@@ -241,11 +252,11 @@ rpt_status train_run(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t 
 
 // 1. training columns T_ex and their exact maxima
 rpt_status train_tex(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* train_labels,
-                     int32_t ell, int32_t r, int32_t k, int prec, float* train_max, float* T_ex_out, void* ws,
-                     hipStream_t s) {
-  TrainWs t = train_carve(ws, v, n, n1, ell, r, k, prec, nullptr);
+                     int32_t ell, int32_t r, int32_t k, int prec, int stat, float* train_max, float* T_ex_out,
+                     void* ws, hipStream_t s) {
+  TrainWs t = train_carve(ws, v, n, n1, ell, r, k, prec, nullptr, stat);
   float* T = T_ex_out ? T_ex_out : t.T;
-  const int flags = naive_flags(prec, false);
+  const int flags = naive_flags(prec, false) | stat_flags(stat);
   RPT_TRY(prep_launch(t.p, X, ldx, RPT_TAIL_SIGNED, flags, s));
   const NaivePlan pl = naive_plan(v, ell, n, prec, true);
   return naive_launch(t.p, pl, train_labels, ell, RPT_TAIL_SIGNED, prec, t.partial, T, train_max, s);
@@ -330,13 +341,14 @@ rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx,
                               const uint8_t* train_labels, int32_t ell, const float* U0, int32_t r,
                               const int32_t* omega_train, int32_t k, int32_t passes, int32_t batch, float gamma,
                               double tol, const int32_t* omega_sm, uint64_t seed, int mu_rule, int prec,
-                              float* U_out, float* sigma_mu, float* train_max, float* T_ex_out, int32_t* info,
-                              double* objective, int32_t* passes_used, void* ws, size_t ws_bytes, void* stream) {
+                              int stat, float* U_out, float* sigma_mu, float* train_max, float* T_ex_out,
+                              int32_t* info, double* objective, int32_t* passes_used, void* ws, size_t ws_bytes,
+                              void* stream) {
   RPT_TRY(train_check(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, tol,
-                      omega_sm, mu_rule, prec, U_out, sigma_mu, train_max, info));
+                      omega_sm, mu_rule, prec, stat, U_out, sigma_mu, train_max, info));
   if (!ws_ok(ws, ws_bytes, rpt_train_workspace(v, n, ell, r, k, prec))) return RPT_ERR_WORKSPACE;
   return train_run(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, tol, omega_sm,
-                   seed, mu_rule, prec, U_out, sigma_mu, train_max, T_ex_out, info, objective, passes_used, ws,
+                   seed, mu_rule, prec, stat, U_out, sigma_mu, train_max, T_ex_out, info, objective, passes_used, ws,
                    static_cast<hipStream_t>(stream));
 }
 
@@ -349,8 +361,10 @@ namespace rpt {
 namespace {
 rpt_status recover_check(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* labels,
                          int64_t L_rec, int64_t col0, const float* U, int32_t r, const float* sigma_mu,
-                         const int32_t* omega, int32_t k, const float* max_out, const int32_t* info) {
+                         const int32_t* omega, int32_t k, const float* max_out, const int32_t* info,
+                         int stat = RPT_STAT_T) {
   if (!design_ok(v, n, ldx, n1)) return RPT_ERR_INVALID_ARG;
+  if (stat != RPT_STAT_T && stat != RPT_STAT_MEANDIFF) return RPT_ERR_INVALID_ARG;
   if (2 * n1 != n) return RPT_ERR_UNSUPPORTED;
   if (L_rec < 0 || col0 < 0 || r < 1 || r > 128 || r > v || k < 1 || k > v) return RPT_ERR_INVALID_ARG;
   if (k < r) return RPT_ERR_UNDERDETERMINED;
@@ -366,10 +380,10 @@ struct RecoverWs {
   void* gb;  // Gram matrices of the split Complete
 };
 RecoverWs recover_carve(void* ws, int64_t v, int32_t n, int32_t n1, int64_t L_rec, int32_t r, int32_t k,
-                        size_t* total = nullptr) {
+                        size_t* total = nullptr, int stat = RPT_STAT_T) {
   Carver c(ws);
   RecoverWs w;
-  w.p = prep_carve(c, v, n, n1, kPrepRows);
+  w.p = prep_carve(c, v, n, n1, kPrepRows | stat_flags(stat));
   w.y = c.take<float>(static_cast<size_t>(L_rec > 0 ? L_rec : 1) * k);
   w.W = c.take<float>(static_cast<size_t>(L_rec > 0 ? L_rec : 1) * r);
   w.rws = c.take<char>(recon_bytes(v, L_rec, r));
@@ -380,9 +394,9 @@ RecoverWs recover_carve(void* ws, int64_t v, int32_t n, int32_t n1, int64_t L_re
 
 // the steps that do not need the basis: sampled t of every recovered column
 rpt_status recover_front(const RecoverWs& w, const float* X, int64_t ldx, const uint8_t* labels, int64_t L_rec,
-                         const int32_t* omega, int32_t k, hipStream_t s) {
-  RPT_TRY(prep_launch(w.p, X, ldx, RPT_TAIL_SIGNED, kPrepRows, s));
-  return sampled_launch(w.p, labels, L_rec, omega, k, nullptr, w.y, s);
+                         const int32_t* omega, int32_t k, hipStream_t s, const int64_t* optr = nullptr) {
+  RPT_TRY(prep_launch(w.p, X, ldx, RPT_TAIL_SIGNED, kPrepRows | stat_flags(w.p.stat), s));
+  return sampled_launch(w.p, labels, L_rec, omega, optr ? 0 : k, nullptr, w.y, s, optr);
 }
 
 // sampled t of recovered columns [c0, c1) (prep done)
@@ -395,10 +409,10 @@ rpt_status recover_sampled(const RecoverWs& w, const uint8_t* labels, int32_t n,
 // Complete, then U w + noise and the column maxima
 rpt_status recover_back(const RecoverWs& w, int64_t v, int64_t L_rec, int64_t col0, const float* U, int32_t r,
                         const float* sigma_mu, const int32_t* omega, int32_t k, uint64_t seed, float* max_out,
-                        float* W_out, int32_t* info, hipStream_t s) {
+                        float* W_out, int32_t* info, hipStream_t s, const int64_t* optr = nullptr) {
   float* W = W_out ? W_out : w.W;
-  RPT_TRY(complete_run(U, v, r, omega, k, w.y, nullptr, 0, nullptr, L_rec, W, nullptr, info, nullptr, s, nullptr,
-                       nullptr, nullptr, w.gb));
+  RPT_TRY(complete_run(U, v, r, omega, optr ? 0 : k, w.y, nullptr, 0, nullptr, L_rec, W, nullptr, info, nullptr, s,
+                       nullptr, nullptr, optr, w.gb));
   return recon_launch(U, v, r, W, L_rec, col0, seed, RPT_STREAM_RECOVERY, sigma_mu, max_out, nullptr, nullptr,
                       w.rws, s);
 }
@@ -417,15 +431,16 @@ size_t rpt_recover_workspace(int64_t v, int32_t n, int64_t L_rec, int32_t r, int
 
 rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* labels,
                                int64_t L_rec, int64_t col0, const float* U, int32_t r, const float* sigma_mu,
-                               const int32_t* omega, int32_t k, uint64_t seed, float* max_out, float* W_out,
-                               int32_t* info, void* ws, size_t ws_bytes, void* stream) {
-  RPT_TRY(recover_check(X, v, n, ldx, n1, labels, L_rec, col0, U, r, sigma_mu, omega, k, max_out, info));
+                               const int32_t* omega, int32_t k, const int64_t* omega_ptr, uint64_t seed, int stat,
+                               float* max_out, float* W_out, int32_t* info, void* ws, size_t ws_bytes,
+                               void* stream) {
+  RPT_TRY(recover_check(X, v, n, ldx, n1, labels, L_rec, col0, U, r, sigma_mu, omega, k, max_out, info, stat));
   if (!ws_ok(ws, ws_bytes, rpt_recover_workspace(v, n, L_rec, r, k))) return RPT_ERR_WORKSPACE;
   if (L_rec == 0) return RPT_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const RecoverWs w = recover_carve(ws, v, n, n1, L_rec, r, k);
-  RPT_TRY(recover_front(w, X, ldx, labels, L_rec, omega, k, s));
-  return recover_back(w, v, L_rec, col0, U, r, sigma_mu, omega, k, seed, max_out, W_out, info, s);
+  const RecoverWs w = recover_carve(ws, v, n, n1, L_rec, r, k, nullptr, stat);
+  RPT_TRY(recover_front(w, X, ldx, labels, L_rec, omega, k, s, omega_ptr));
+  return recover_back(w, v, L_rec, col0, U, r, sigma_mu, omega, k, seed, max_out, W_out, info, s, omega_ptr);
 }
 
 // ---------------------------------------------------------------------------
@@ -440,17 +455,17 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
                                const uint8_t* train_labels, int32_t ell, const uint8_t* rec_labels, int64_t L_rec,
                                const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
                                int32_t batch, float gamma, double tol, const int32_t* omega_sm,
-                               const int32_t* omega_rec, uint64_t seed, int mu_rule, int prec, float* h_out,
-                               float* U_out, float* sigma_mu, int32_t* train_info, int32_t* rec_info,
+                               const int32_t* omega_rec, uint64_t seed, int mu_rule, int prec, int stat,
+                               float* h_out, float* U_out, float* sigma_mu, int32_t* train_info, int32_t* rec_info,
                                double* objective, int32_t* passes_used, void* ws, size_t ws_bytes, void* stream) {
   RPT_TRY(train_check(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, tol,
-                      omega_sm, mu_rule, prec, U_out, sigma_mu, h_out, train_info));
+                      omega_sm, mu_rule, prec, stat, U_out, sigma_mu, h_out, train_info));
   RPT_TRY(recover_check(X, v, n, ldx, n1, rec_labels, L_rec, ell, U_out, r, sigma_mu, omega_rec, k, h_out,
-                        rec_info));
+                        rec_info, stat));
   const size_t tw = rpt_train_workspace(v, n, ell, r, k, prec);
   if (!ws_ok(ws, ws_bytes, rpt_rapidpt_workspace(v, n, ell, L_rec, r, k, prec))) return RPT_ERR_WORKSPACE;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  const RecoverWs w = recover_carve(static_cast<char*>(ws) + tw, v, n, n1, L_rec, r, k);
+  const RecoverWs w = recover_carve(static_cast<char*>(ws) + tw, v, n, n1, L_rec, r, k, nullptr, stat);
   // Two chains share the device: the caller's stream computes T_ex (matrix
   // cores, the whole chip) and then the tracking passes (latency-bound, a
   // single-workgroup Cholesky in every step); the second stream
@@ -460,7 +475,7 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
   SideStream* sd = side_stream(s);
   if (!sd) {
     RPT_TRY(train_run(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, tol,
-                      omega_sm, seed, mu_rule, prec, U_out, sigma_mu, h_out, nullptr, train_info, objective,
+                      omega_sm, seed, mu_rule, prec, stat, U_out, sigma_mu, h_out, nullptr, train_info, objective,
                       passes_used, ws, s));
     if (L_rec == 0) return RPT_OK;
     RPT_TRY(recover_front(w, X, ldx, rec_labels, L_rec, omega_rec, k, s));
@@ -469,11 +484,11 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
   rpt_status st = stream_wait(sd, sd->fork, s, sd->st);
   if (st != RPT_OK) return st;
   // from here on every path joins the second stream back before returning
-  rpt_status st_main = train_tex(X, v, n, ldx, n1, train_labels, ell, r, k, prec, h_out, nullptr, ws, s);
+  rpt_status st_main = train_tex(X, v, n, ldx, n1, train_labels, ell, r, k, prec, stat, h_out, nullptr, ws, s);
   rpt_status st_side = train_start_basis(v, n, n1, ell, U0, r, k, prec, U_out, ws, sd->st);
   st = stream_wait(sd, sd->mid, sd->st, s);  // the basis is ready for the tracking passes
   if (st_side == RPT_OK && st == RPT_OK && L_rec > 0)
-    st_side = prep_launch(w.p, X, ldx, RPT_TAIL_SIGNED, kPrepRows, sd->st);
+    st_side = prep_launch(w.p, X, ldx, RPT_TAIL_SIGNED, kPrepRows | stat_flags(stat), sd->st);
   // the sampled t of the recovered columns in one chunk per tracking step,
   // each released when that step reaches its single-workgroup Cholesky
   int64_t done = 0;

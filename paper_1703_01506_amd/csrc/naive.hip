@@ -527,8 +527,10 @@ __global__ __launch_bounds__(kBlock) void naive_f32_kernel(NaiveArgs a) {
 
 // One wave per relabelling: the lanes take the chunks' partial maxima in
 // turn (a few hundred chunks for short launches), then a wave maximum
+// mode: 0 the partials are the statistic already (unbalanced FP32 path),
+// 1 t of Eq. 2 from u, 2 the mean difference 2 u / m
 __global__ __launch_bounds__(kBlock) void naive_finalize_kernel(const float* __restrict__ partial, int nc, int64_t L,
-                                                                int m, int apply_t, float* __restrict__ max_out) {
+                                                                int m, int mode, float* __restrict__ max_out) {
   const int lane = threadIdx.x & 63;
   const int64_t i = static_cast<int64_t>(blockIdx.x) * (kBlock / 64) + (threadIdx.x >> 6);
   if (i >= L) return;
@@ -536,7 +538,10 @@ __global__ __launch_bounds__(kBlock) void naive_finalize_kernel(const float* __r
   for (int c = lane; c < nc; c += 64) u = fmaxf(u, partial[static_cast<int64_t>(c) * L + i]);
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) u = fmaxf(u, __shfl_xor(u, off, 64));
-  if (lane == 0) max_out[i] = apply_t ? static_cast<float>(t_from_u(static_cast<double>(u), m)) : u;
+  if (lane == 0)
+    max_out[i] = mode == 1   ? static_cast<float>(t_from_u(static_cast<double>(u), m))
+                 : mode == 2 ? static_cast<float>(2.0 * static_cast<double>(u) / m)
+                             : u;
 }
 
 // T-storing launches use naive_split_kernel (PT = 1), max-only launches
@@ -634,8 +639,7 @@ rpt_status naive_launch(const PrepX& p, const NaivePlan& pl, const uint8_t* labe
   a.abs_tail = tail == RPT_TAIL_ABS;
   a.store = T_out != nullptr;
   const int m = p.n / 2;
-  a.fs = static_cast<float>(2.0 * sqrt((m - 1.0) / m));
-  a.tm = static_cast<float>(2.0 / m);
+  stat_consts(p, &a.fs, &a.tm);
   a.partial = partial;
   a.T_out = T_out;
   const bool unbal = 2 * p.n1 != p.n;
@@ -666,7 +670,7 @@ rpt_status naive_launch(const PrepX& p, const NaivePlan& pl, const uint8_t* labe
   if (max_out) {
     RPT_STAGE("naive_finalize", s);
     hipLaunchKernelGGL(naive_finalize_kernel, dim3(static_cast<unsigned>(ceil_div(L, kBlock / 64))), dim3(kBlock), 0,
-                       s, partial, pl.nc, L, m, unbal ? 0 : 1, max_out);
+                       s, partial, pl.nc, L, m, unbal ? 0 : (p.stat == RPT_STAT_MEANDIFF ? 2 : 1), max_out);
     RPT_CHECK_LAUNCH();
   }
   return RPT_OK;

@@ -167,9 +167,7 @@ rpt_status rpt_observed_tstat(const float* X, int64_t v, int32_t n, int64_t ldx,
   a.cstg = p.cstg;
   a.n = n;
   a.n1 = n1;
-  const int m = n / 2;
-  a.fs = static_cast<float>(2.0 * sqrt((m - 1.0) / m));
-  a.tm = static_cast<float>(2.0 / m);
+  stat_consts(p, &a.fs, &a.tm);
   a.t = t_out;
   RPT_STAGE("observed_t", s);
   hipLaunchKernelGGL(observed_kernel, dim3(static_cast<unsigned>(ceil_div(v, kBlock))), dim3(kBlock), 0, s, a);

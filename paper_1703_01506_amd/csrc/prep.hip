@@ -110,7 +110,9 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(const float* __restrict__ 
   Q = row_sum<TPR>(Q);
   if (q == 0 && vox < p.vpad) {
     if (vox < v) {
-      const double rinv = Qc > 0.0 ? 1.0 / sqrt(Qc) : 0.0;
+      // t: scale to unit centred sum of squares; mean difference: undo the
+      // standardisation's scale, so u is the centred group-1 sum of X itself
+      const double rinv = (flags & kPrepMeanDiff) ? (sc > 0.0 ? 1.0 / sc : 0.0) : (Qc > 0.0 ? 1.0 / sqrt(Qc) : 0.0);
       if (p.cst) p.cst[vox] = make_float2(static_cast<float>(rinv), static_cast<float>(-0.5 * S * rinv));
       if (p.cstg) p.cstg[vox] = make_float2(static_cast<float>(S), static_cast<float>(Q));
       fold_c[r] = rinv;
@@ -193,6 +195,7 @@ size_t prep_bytes(int64_t v, int n, int flags) {
 
 PrepX prep_carve(Carver& c, int64_t v, int n, int n1, int flags) {
   PrepX p;
+  p.stat = (flags & kPrepMeanDiff) ? RPT_STAT_MEANDIFF : RPT_STAT_T;
   p.v = v;
   p.vpad = round_up(v, 32);
   p.n = n;

@@ -163,9 +163,27 @@ struct PrepX {
   int ldn = 0;
   float2* cst = nullptr;     // [vpad] balanced epilogue (rinv, -h*rinv)
   float2* cstg = nullptr;    // [vpad] unbalanced epilogue (S, Q)
+  int stat = RPT_STAT_T;     // statistic the constants were made for
 };
+// (fs, tm) of t_from_u_f for the prepared statistic: Eq. 2's t, or the mean
+// difference 2 u / m (fs = 2 / m, tm = 0)
+inline void stat_consts(const PrepX& p, float* fs, float* tm) {
+  const int m = p.n / 2;
+  if (p.stat == RPT_STAT_MEANDIFF) {
+    *fs = static_cast<float>(2.0 / m);
+    *tm = 0.0f;
+  } else {
+    *fs = static_cast<float>(2.0 * sqrt((m - 1.0) / m));
+    *tm = static_cast<float>(2.0 / m);
+  }
+}
 
-enum PrepFlags { kPrepSplit = 1, kPrepF32 = 2, kPrepRows = 4, kPrepUnbal = 8 };
+// kPrepMeanDiff: the statistic is the linear mean difference m1 - m2 instead
+// of Eq. 2's t (balanced designs): the rows are centred but not scaled in the
+// contraction's constants, so u is the centred group-1 sum and the statistic
+// is 2 u / m, again one increasing function of u shared by all voxels
+enum PrepFlags { kPrepSplit = 1, kPrepF32 = 2, kPrepRows = 4, kPrepUnbal = 8, kPrepMeanDiff = 16 };
+inline int stat_flags(int stat) { return stat == RPT_STAT_MEANDIFF ? kPrepMeanDiff : 0; }
 
 size_t prep_bytes(int64_t v, int n, int flags);
 PrepX prep_carve(Carver& c, int64_t v, int n, int n1, int flags);

@@ -126,9 +126,7 @@ rpt_status sampled_launch(const PrepX& p, const uint8_t* labels, int64_t L, cons
   a.k = k;
   a.optr = optr;
   a.y = y;
-  const int m = p.n / 2;
-  a.fs = static_cast<float>(2.0 * sqrt((m - 1.0) / m));
-  a.tm = static_cast<float>(2.0 / m);
+  stat_consts(p, &a.fs, &a.tm);
   RPT_STAGE("sampled_t", s);
   if (p.ldn <= 4 * kRowLanes)
     hipLaunchKernelGGL(sampled_kernel<1>, dim3(static_cast<unsigned>(L)), dim3(kBlock), 0, s, a);

@@ -48,28 +48,31 @@ def test_naive_argument_validation(lib):
     ws_need = lib.rpt_naive_workspace(1000, 20, 50, 1)
     assert ws_need > 0
     # n1 out of range
-    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 1, dummy, 50, 0, 1, dummy, None, dummy, ws_need, None) == -1
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 1, dummy, 50, 0, 1, 0, dummy, None, dummy, ws_need, None) == -1
     # ldx < n
-    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 10, 10, dummy, 50, 0, 1, dummy, None, dummy, ws_need, None) == -1
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 10, 10, dummy, 50, 0, 1, 0, dummy, None, dummy, ws_need, None) == -1
     # bad tail / precision
-    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 7, 1, dummy, None, dummy, ws_need, None) == -1
-    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 0, 9, dummy, None, dummy, ws_need, None) == -1
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 7, 1, 0, dummy, None, dummy, ws_need, None) == -1
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 0, 9, 0, dummy, None, dummy, ws_need, None) == -1
     # unbalanced split-BF16 is not provided
-    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 8, dummy, 50, 0, 1, dummy, None, dummy, ws_need, None) == -6
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 8, dummy, 50, 0, 1, 0, dummy, None, dummy, ws_need, None) == -6
     # more than 512 subjects; the FP32 path above 128
     ws_wide = lib.rpt_naive_workspace(1000, 513, 50, 1)
-    assert lib.rpt_naive_maxnull(dummy, 1000, 513, 513, 256, dummy, 50, 0, 1, dummy, None, dummy, ws_wide,
+    assert lib.rpt_naive_maxnull(dummy, 1000, 513, 513, 256, dummy, 50, 0, 1, 0, dummy, None, dummy, ws_wide,
                                  None) == -1
     ws_f32 = lib.rpt_naive_workspace(1000, 200, 50, 0)
-    assert lib.rpt_naive_maxnull(dummy, 1000, 200, 200, 100, dummy, 50, 0, 0, dummy, None, dummy, ws_f32,
+    assert lib.rpt_naive_maxnull(dummy, 1000, 200, 200, 100, dummy, 50, 0, 0, 0, dummy, None, dummy, ws_f32,
                                  None) == -6
     # workspace too small / misaligned
-    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 0, 1, dummy, None, dummy, ws_need - 1,
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 0, 1, 0, dummy, None, dummy, ws_need - 1,
                                  None) == -4
-    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 0, 1, dummy, None, C.c_void_p(257), ws_need,
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 0, 1, 0, dummy, None, C.c_void_p(257), ws_need,
                                  None) == -4
     # L == 0 is a valid no-op
-    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 0, 0, 1, dummy, None, dummy, ws_need, None) == 0
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 0, 0, 1, 0, dummy, None, dummy, ws_need, None) == 0
+    # the statistic: 0 = Eq. 2's t, 1 = mean difference (balanced designs only)
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 10, dummy, 50, 0, 1, 2, dummy, None, dummy, ws_need, None) == -1
+    assert lib.rpt_naive_maxnull(dummy, 1000, 20, 20, 8, dummy, 50, 0, 0, 1, dummy, None, dummy, ws_need, None) == -6
 
 
 def test_batched_recovery_validation(lib):
@@ -105,9 +108,9 @@ def test_rapidpt_end_to_end_validation(lib):
     assert need >= lib.rpt_train_workspace(v, n, ell, r, k, prec) + lib.rpt_recover_workspace(v, n, L_rec, r, k)
     ws = C.c_void_p(512)
 
-    def call(n1=10, r_=r, k_=k, ws_bytes=need, batch=ell, passes=2, gamma=1.0, tol=0.0):
+    def call(n1=10, r_=r, k_=k, ws_bytes=need, batch=ell, passes=2, gamma=1.0, tol=0.0, stat=0):
         return lib.rpt_rapidpt_maxnull(d, v, n, n, n1, d, ell, d, L_rec, d, r_, d, k_, passes, batch, gamma, tol, d,
-                                       d, 7, 0, prec, d, d, d, d, d, d, d, ws, ws_bytes, None)
+                                       d, 7, 0, prec, stat, d, d, d, d, d, d, d, ws, ws_bytes, None)
 
     assert call(ws_bytes=need - 1) == -4      # workspace
     assert call(n1=9) == -6                    # unbalanced designs are not provided
@@ -117,6 +120,7 @@ def test_rapidpt_end_to_end_validation(lib):
     assert call(batch=1, gamma=1.5) == -1      # geodesic angle must stay below 3 pi / 4
     assert call(tol=-1.0) == -1                # negative stopping tolerance
     assert call(batch=2, tol=1e-3) == -6       # the stopping rule belongs to column-by-column tracking
+    assert call(stat=2) == -1                  # no such statistic
 
 
 def test_autotune_table_roundtrip(lib, tmp_path):
