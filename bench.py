@@ -4,9 +4,11 @@
 
 One step is RapidPT end to end (Alg. 2) on the n = 100 (50/50), v = 250,000
 workload: per-voxel preparation, l = 300 fully computed training columns,
-P tracking passes with 0.35% sampled entries per column (875 voxels), sigma
-and mu, and recovery of the remaining 9,700 columns (sampled t statistics,
-masked least squares, reconstruction + residual noise + maximum).  `value` is
+subspace tracking one column at a time (Sec. 4.1) with 0.35% sampled entries
+per column (875 voxels), passes repeated until the pass objective falls by at
+most 0.1% (at most P passes), sigma and mu, and recovery of the remaining
+9,700 columns (sampled t statistics, masked least squares, reconstruction +
+residual noise + maximum).  `value` is
 max-null columns per second for the whole step (L = 10,000 per step), with
 all inputs already resident on the GPU.  NaivePT (Alg. 1) on the same data
 and relabellings is timed alongside and reported under "naivept".
@@ -34,25 +36,10 @@ PEAK_BF16_TFLOPS = 2500.0      # MI355X dense BF16 matrix peak
 PEAK_HBM_GBS = 8000.0
 PEAK_FP64_TFLOPS = 78.6        # vector FP64
 PEAK_FP32_TFLOPS = 157.3       # FP32 (vector and matrix)
-# VALU issue bound of the noise draw, per 16 normals of one lane (four
-# Philox4x32-10 calls, every wave64 instruction covering 64 lanes): 67
-# v_mad_u64_u32 and 74 v_bitop3_b32 (the products and three-input XORs of the
-# ten rounds, those of the first two rounds shared by the four calls),
-# 104 full-rate ops (per normal: shift, convert and FMA of its uniform, half a
-# log scaling, the radius product, the noise FMA and the running max) and 32
-# transcendentals (log, sqrt, sin, cos per pair).  Issue cycles per wave64
-# instruction on a SIMD, measured on the whole chip at eight waves per SIMD
-# (`bench.py --issue-rates`, profiles/valu_issue_rates_mi355x.md; a clock of
-# 2.4 GHz): v_mad_u64_u32 5.11, v_bitop3_b32 4.46, FP32 add 2.86,
-# transcendental 9.46.  67 x 5.11 + 74 x 4.46 + 104 x 2.86 + 32 x 9.46 = 1,272
-# cycles per 1,024 normals of a wave, 79.5 per 64: 1,024 SIMDs x 2.4 GHz x 64
-# / 79.5.
-ISSUE_CYCLES = {"mad": 5.112, "bitop3": 4.455, "full": 2.858, "trans": (9.405 + 9.517) / 2}
-NOISE_SIMD_CYCLES_PER_64_NORMALS = (67 * ISSUE_CYCLES["mad"] + 74 * ISSUE_CYCLES["bitop3"] +
-                                    104 * ISSUE_CYCLES["full"] + 32 * ISSUE_CYCLES["trans"]) / 16
-PEAK_NOISE_GNORMALS = 1024 * 2.4 * 64 / NOISE_SIMD_CYCLES_PER_64_NORMALS
+TOL = 1e-3                     # stopping tolerance of the tracking passes (Sec. 4.1, until convergence)
+GOLDEN = os.path.join(ROOT, "tests", "golden", "train_full_n100_v250k.txt")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rapidpt_step_n100_v250k_hbm_traffic.md")
-STAGE_KERNEL = {"complete": "complete_kernel", "complete_gram": "complete_gram_kernel",
+STAGE_KERNEL = {"track_grouse": "grouse_pass_kernel", "complete": "complete_kernel", "complete_gram": "complete_gram_kernel",
                 "complete_solve": "complete_solve_kernel", "recon_fused": "recon_fused_kernel",
                 "naive_contract": "naive_max_kernel", "sampled_t": "sampled_kernel",
                 "track_update": "track_apply_kernel", "reorth_gram": "gram_partial_kernel",
@@ -65,10 +52,12 @@ def log(msg):
 
 
 def cpu_baseline(X, labels, U0, omt, oms, omr, ell, passes, seed, part_s=4.0):
-    """The FP64 oracle on a bounded sample of the same workload, scaled to the
-    full step: training t maps, tracking-step column visits and recovered
-    columns, each part repeated until about part_s seconds are spent (about
-    12 s in all), each rate scaled to its full count."""
+    """The FP64 oracle as configured (GROUSE one column at a time) on a
+    bounded sample of the same workload, scaled to the full step: training t
+    maps, column visits of the tracking (each a geodesic step on the full v x
+    r basis) and recovered columns, each part repeated until about part_s
+    seconds are spent, each rate scaled to its full count (passes = the
+    passes the step used)."""
     from oracle import rapidpt as OR
     from oracle import tstat as OT
     try:
@@ -88,18 +77,20 @@ def cpu_baseline(X, labels, U0, omt, oms, omr, ell, passes, seed, part_s=4.0):
 
     maps = []
     t_tex, n_tex = until(part_s, lambda j: maps.append(OT.tstat(X64, labels[j] == 1)), ell)
-    U = OR.orthonormalize(U0.astype(np.float64))
-    T2 = np.stack(maps[:2]) if len(maps) >= 2 else OT.tmatrix(X64, labels[:2])
-    t_pair, n_pair = until(part_s, lambda j: OR.track_step(U, T2, [omt[2 * j], omt[2 * j + 1]]), passes * ell // 2)
-    t_visit = t_pair / 2
+    state = {"U": OR.orthonormalize(U0.astype(np.float64))}
+
+    def visit(j):
+        state["U"] = OR.grouse_step(state["U"], maps[j % len(maps)], omt[j])
+    t_visit, n_visit = until(part_s, visit, passes * ell)
+    U = state["U"]
     t_rec, n_rec = until(part_s, lambda j: OR.recover_column(X64, labels[ell + j] == 1, U, 0.5, 0.0, omr[j], seed,
                                                              ell + j), L - ell)
     est = t_tex * ell + t_visit * ell * passes + t_rec * ell + t_rec * (L - ell)
     return {"value": L / est, "unit": "perms/s", "cores": int(cores), "kind": "oracle",
-            "sample": (f"oracle timed on {n_tex} training t maps ({t_tex:.3f} s each), {n_pair} tracking steps "
-                       f"over 2 columns ({t_visit:.3f} s per column visit) and {n_rec} recovered columns "
-                       f"({t_rec:.4f} s each), scaled to l={ell} maps, {passes} passes, l sigma/mu columns "
-                       f"and {L - ell} recoveries: {est:.0f} s estimated for the {L}-column step")}
+            "sample": (f"oracle timed on {n_tex} training t maps ({t_tex:.3f} s each), {n_visit} GROUSE column "
+                       f"visits ({t_visit:.3f} s each) and {n_rec} recovered columns ({t_rec:.4f} s each), "
+                       f"scaled to l={ell} maps, {passes} passes of {ell} visits, l sigma/mu columns and "
+                       f"{L - ell} recoveries: {est:.0f} s estimated for the {L}-column step")}
 
 
 def kl_max_nulls(ref, test, bins=50, pseudocount=0.5):
@@ -116,6 +107,55 @@ def kl_max_nulls(ref, test, bins=50, pseudocount=0.5):
     q = np.histogram(test, edges)[0] + pseudocount
     p, q = p / p.sum(), q / q.sum()
     return float(np.sum(p * np.log(p / q)))
+
+
+def calibration(rpt, torch, Xd, tl, U0d, omtd, omsd, passes, seed, U):
+    """How far the trained basis is from the best rank-r basis of the training
+    columns (the brute-force alternative of Sec. 4.1): principal angles between
+    span(U) and the r leading left singular vectors of T_ex, from the
+    eigenvectors of the l x l Gram matrix T_ex T_ex^T (FP64, after the timed
+    region; a report, not part of the step)."""
+    out = rpt.train_subspace(Xd, tl, U0d, omtd, omsd, passes=passes, seed=seed, tol=TOL, return_T=True)
+    T = out["T_ex"].double()
+    r = U.shape[1]
+    lam, V = torch.linalg.eigh(T @ T.T)
+    lam, V = lam[-r:], V[:, -r:]
+    Us = (T.T @ V) / torch.sqrt(lam)
+    cos = torch.linalg.svdvals(U.double().T @ Us).clamp(0.0, 1.0)
+    resid = T - (T @ U.double()) @ U.double().T
+    return {"max_principal_angle_deg": float(torch.rad2deg(torch.arccos(cos.min())).item()),
+            "mean_cos2": float((cos ** 2).mean().item()),
+            "t_ex_residual_std": float(resid.std().item()),
+            "t_ex_best_rank_r_residual_std": float((T - (T @ Us) @ Us.T).std().item())}
+
+
+def oracle_gate(h, passes):
+    """The metric's gate: the GPU's max null against the FP64 oracle's on the
+    same inputs and noise streams (tests/golden/make_train_full.py), as
+    KL(oracle || GPU) < 1e-3 and the alpha = 0.05 threshold within 1%.  None
+    when the stored run's configuration differs from this one."""
+    if not os.path.exists(GOLDEN):
+        return None
+    hdr = open(GOLDEN).readline() + open(GOLDEN).readlines()[1]
+    if f"passes<={passes} " not in hdr or f"tol={TOL}" not in hdr:
+        return None
+    g = {}
+    for line in open(GOLDEN):
+        if line.startswith("h ") or line.startswith("passes_used "):
+            key, *vals = line.split()
+            g[key] = np.array([float(x) for x in vals])
+    href = g["h"]
+    hg = h.cpu().numpy().astype(np.float64)
+    kl = kl_max_nulls(href, hg)
+
+    def thr(x, alpha=0.05):
+        srt = np.sort(x)
+        return float(srt[len(x) - int(np.floor(alpha * len(x))) - 1])
+    t_ref, t_gpu = thr(href), thr(hg)
+    rel = abs(t_gpu - t_ref) / abs(t_ref)
+    return {"kl_oracle_vs_gpu": kl, "threshold_oracle": t_ref, "threshold_gpu": t_gpu, "threshold_rel_diff": rel,
+            "oracle_passes_used": int(g["passes_used"][0]), "kl_below_1e-3": bool(kl < 1e-3),
+            "threshold_within_1pct": bool(rel <= 0.01), "max_abs_diff": float(np.max(np.abs(hg - href)))}
 
 
 # Simulation Data I and II (Sec. 5.1, 5.2) with the hyperparameter grid of
@@ -258,7 +298,7 @@ def main():
     torch.cuda.synchronize()
 
     def step():
-        return rpt.rapidpt_maxnull(Xd, Ld[:ell], Ld[ell:], U0d, omtd, omsd, omrd, passes=P, seed=seed)
+        return rpt.rapidpt_maxnull(Xd, Ld[:ell], Ld[ell:], U0d, omtd, omsd, omrd, passes=P, seed=seed, tol=TOL)
 
     # tile choices measured on these shapes (the library's autotuner); a
     # saved table skips the trial launches (profiled runs use one)
@@ -300,7 +340,10 @@ def main():
     _, wall_ev, stages = timed(step, True)
     ms_per_step = 1e3 * wall / a.steps
     value = L / (wall / a.steps)
-    log(f"rapidpt {ms_per_step:.2f} ms/step ({1e3 * wall_ev / a.steps:.2f} with stage events)")
+    passes_used = int(tr["passes_used"].item())
+    objective = [float(x) for x in tr["objective"].cpu().numpy()[:passes_used]]
+    log(f"rapidpt {ms_per_step:.2f} ms/step ({1e3 * wall_ev / a.steps:.2f} with stage events), "
+        f"{passes_used} tracking passes")
 
     # NaivePT on the same data and relabellings (split-BF16 contraction)
     naive = lambda: rpt.naive_maxnull(Xd, Ld)
@@ -312,8 +355,19 @@ def main():
     naive_ms = 1e3 * nwall / a.steps
     log(f"naivept {naive_ms:.3f} ms/step")
 
-    rec_only = h2d_ms = naive_fp32 = None
+    rec_only = h2d_ms = naive_fp32 = variant = None
     if not a.headline_only:
+        # the mini-batch tracking variant (not the paper's: all l columns fitted
+        # on the same basis, one update and re-orthonormalisation per pass), P
+        # passes
+        var = lambda: rpt.rapidpt_maxnull(Xd, Ld[:ell], Ld[ell:], U0d, omtd, omsd, omrd, passes=P, seed=seed,
+                                          batch=ell)
+        var()
+        (hv, trv, _), vwall, _ = timed(var, False)
+        variant = {"tracking": f"mini-batch of l={ell} columns per update, {P} passes", "value": L / (vwall / a.steps),
+                   "unit": "perms/s", "ms_per_step": 1e3 * vwall / a.steps,
+                   "sigma": float(trv["sigma_mu"][0].item()), "mu": float(trv["sigma_mu"][1].item())}
+        log(f"mini-batch variant {variant['ms_per_step']:.2f} ms/step")
         # NaivePT on the FP32 path (FP32 matrix cores, one product per
         # relabelling tile): the precision alternative to the split-BF16 one
         naive32 = lambda: rpt.naive_maxnull(Xd, Ld, prec="fp32")
@@ -347,6 +401,10 @@ def main():
     # roofline of the dominant kernel stage of the RapidPT step
     tot = {s: q[0] / a.steps for s, q in stages.items() if q and not s.endswith("_total")}
     launches = {s: q[1] / a.steps for s, q in stages.items() if q and not s.endswith("_total")}
+    # the tracking launches of passes after the stopping rule holds return at
+    # once: a launch is one pass that ran
+    if "track_grouse" in launches:
+        launches["track_grouse"] = passes_used
     dom = max(tot, key=tot.get)
     kc = nstages.get("naive_contract")
     naive_avg_ms = kc[0] / kc[1]
@@ -357,35 +415,43 @@ def main():
     naive_roof["frac"] = naive_roof["achieved"] / naive_roof["peak"]
     naive_roof["traffic"] = measured_traffic("naive_contract")
     naive_roof["traffic_unit"] = "bytes per launch"
-    roof = roofline_for(dom, tot[dom], launches[dom], v, n, L, ell, r, k, P)
+    roof = roofline_for(dom, tot[dom], launches[dom], v, n, L, ell, r, k, passes_used)
     others = {}
-    for s_ in ("complete", "complete_gram", "complete_solve", "recon_fused", "reorth_gram", "reorth_chol",
-               "reorth_apply", "track_update", "sampled_t"):
+    for s_ in ("track_grouse", "complete", "complete_gram", "complete_solve", "recon_fused", "reorth_gram",
+               "reorth_chol", "reorth_apply", "track_update", "sampled_t"):
         if s_ in tot and s_ != dom:
-            others[s_] = roofline_for(s_, tot[s_], launches[s_], v, n, L, ell, r, k, P)
+            others[s_] = roofline_for(s_, tot[s_], launches[s_], v, n, L, ell, r, k, passes_used)
 
     quality = {"kl_naive_vs_rapid": kl_max_nulls(nv, h),
                "threshold_naive": float(rpt.fwer_threshold(nv, 0.05).item()),
                "threshold_rapid": float(rpt.fwer_threshold(h, 0.05).item()),
-               "sigma": float(tr["sigma_mu"][0].item()), "mu": float(tr["sigma_mu"][1].item())}
+               "sigma": float(tr["sigma_mu"][0].item()), "mu": float(tr["sigma_mu"][1].item()),
+               "passes_used": passes_used, "pass_objective": objective,
+               "calibration": calibration(rpt, torch, Xd, Ld[:ell], U0d, omtd, omsd, P, seed, tr["U"])}
+    if variant is not None:
+        variant["kl_naive_vs_rapid"] = kl_max_nulls(nv, hv)
+    gate = oracle_gate(h, P)
+    log(f"quality {json.dumps(quality)} gate {json.dumps(gate)}")
 
     cpu = cpu1 = None
     if not a.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
-        cpu = cpu_baseline(X, labels, U0, omt, oms, omr, ell, P, seed)
+        cpu = cpu_baseline(X, labels, U0, omt, oms, omr, ell, passes_used, seed)
         if not a.headline_only:
             from threadpoolctl import threadpool_limits
             with threadpool_limits(limits=1):
                 log("cpu baseline (oracle, one thread) ...")
-                cpu1 = cpu_baseline(X, labels, U0, omt, oms, omr, ell, P, seed, part_s=2.0)
+                cpu1 = cpu_baseline(X, labels, U0, omt, oms, omr, ell, passes_used, seed, part_s=2.0)
 
     out = {
         "metric": METRIC, "value": value, "unit": "perms/s", "n_gpus": 1, "steps": a.steps,
         "warmup": a.warmup, "ms_per_step": ms_per_step, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16-split/f32 (f64 Cholesky)", "data": "synthetic",
+        "vs_baseline": None, "dtype": "bf16-split/f32 (f64 solves)", "data": "synthetic",
         "config": {"workload": f"RapidPT end to end, n={n} (50/50), v={v} smoothed FWHM 3, L={L}, l={ell}, "
-                               f"r={r}, eta=0.35% ({k} voxels), {P} tracking passes",
-                   "n": n, "v": v, "L": L, "l": ell, "r": r, "eta_ppm": eta_ppm, "passes": P},
+                               f"r={r}, eta=0.35% ({k} voxels), tracking one column at a time until the pass "
+                               f"objective falls by at most {TOL:g} (at most {P} passes)",
+                   "n": n, "v": v, "L": L, "l": ell, "r": r, "eta_ppm": eta_ppm, "max_passes": P, "tol": TOL},
+        "oracle_gate": gate,
         "roofline": roof,
         "rooflines_other_stages": others,
         "cpu_baseline": cpu,
@@ -400,6 +466,7 @@ def main():
         "stages_ms_per_step": {s: round(t, 4) for s, t in sorted(tot.items(), key=lambda kv: -kv[1])},
         "naivept_stages_ms_per_step": {s: round(q[0] / a.steps, 4) for s, q in nstages.items() if q},
         "rapidpt_quality": quality,
+        "rapidpt_minibatch_variant": variant,
         "autotuned": tuned,
     }
     print(json.dumps(out), flush=True)
@@ -434,6 +501,17 @@ def roofline_for(stage, ms_per_step, launches_per_step, v, n, L, ell, r, k, P):
     Lr = L - ell
     out = {"kernel": stage, "avg_launch_ms": avg_s * 1e3, "launches_per_step": launches_per_step,
            "traffic": measured_traffic(stage), "traffic_unit": "bytes per launch"}
+    if stage == "track_grouse":
+        # one launch is one pass of column visits; per visit the k sampled
+        # basis rows are read and written once (4r bytes each way) and the k
+        # indices and T values read: the least traffic a step needs.  A
+        # dependent chain on one workgroup, so far below this peak.
+        byts = ell * k * (8.0 * r + 8.0)
+        ach = byts / avg_s / 1e9
+        out.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                    "frac": ach / PEAK_HBM_GBS, "algorithmic_bytes_per_launch": byts,
+                    "us_per_column_visit": avg_s * 1e6 / ell})
+        return out
     if stage == "complete":
         # the fused kernel solves the training columns: P passes over l and the
         # sigma/mu pass; each gathers k basis rows (4r bytes), k indices and k
@@ -462,16 +540,15 @@ def roofline_for(stage, ms_per_step, launches_per_step, v, n, L, ell, r, k, P):
                     "frac": ach / PEAK_FP64_TFLOPS, "algorithmic_flops_per_launch": flops})
         return out
     if stage == "recon_fused":
-        # every voxel of every training and recovered column draws its normal
-        # (sigma ~ 0.95 leaves nothing to prune): bound by VALU issue
-        normals = v * (ell + Lr) / launches_per_step
-        ach = normals / avg_s / 1e9
-        peak = PEAK_NOISE_GNORMALS
-        out.update({"bound": "alu", "achieved": ach, "peak": peak, "unit": "Gnormal/s",
-                    "frac": ach / peak, "algorithmic_normals_per_launch": normals,
-                    # one BF16 product pass (the exact values of the few
-                    # candidate voxels come from the refine stage)
-                    "mfma_tflops": 2.0 * v * r * (ell + Lr) / launches_per_step / avg_s / 1e12})
+        # U w for every voxel of every training and recovered column, one
+        # BF16 product pass (2 v r flops per column); the noise of every voxel
+        # is drawn in the same pass (VALU work the matrix-core peak does not
+        # count)
+        flops = 2.0 * v * r * (ell + Lr) / launches_per_step
+        ach = flops / avg_s / 1e12
+        out.update({"bound": "mfma", "achieved": ach, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                    "frac": ach / PEAK_BF16_TFLOPS, "algorithmic_flops_per_launch": flops,
+                    "normals_per_s": v * (ell + Lr) / launches_per_step / avg_s})
         return out
     if stage in ("reorth_gram", "reorth_apply"):
         # the Gram pass reads U once; the apply pass reads and writes it

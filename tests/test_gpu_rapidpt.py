@@ -326,39 +326,53 @@ def test_masked_loss_forward_backward():
     assert np.linalg.norm(dW.cpu().numpy() - gW) <= 1e-5 * np.linalg.norm(gW)
 
 
+def _full_inputs(G):
+    n, v, L, ell, r = G.N, G.V, G.L, G.ELL, G.R
+    k = S.omega_count(v, G.ETA_PPM)
+    X = S.smoothed_volumes(n, v, seed=1703)
+    labels = S.relabellings(L, n, n // 2, seed=1506)
+    U0 = S.gaussian_matrix(v, r, seed=3).astype(np.float32)
+    omt = S.omega_sets(G.PASSES * ell, v, k, seed=41)
+    oms = S.omega_sets(ell, v, k, seed=42)
+    omr = S.omega_sets(L - ell, v, k, seed=43)
+    return X, labels, U0, omt, oms, omr
+
+
+def _golden_full():
+    sys.path.insert(0, golden_path(""))
+    import make_train_full as G
+    return G, G.load()
+
+
 def test_train_full_size_bench_shape():
     """The training half at the benchmark's shape and launch configuration:
     n = 100 (50/50), v = 250,000 smoothed, l = 300, r = 100, 875 sampled
-    voxels per column, 10 passes of one l-column mini-batch, split-BF16.  The
-    FP64 oracle's result (5 minutes of CPU) is stored by
-    tests/golden/make_train_full.py: sigma, mu, the 300 exact maxima and the
-    oracle basis at 48 sampled voxels.  Three t maps are recomputed here one by
-    one.  The subspace is compared through the projector U_S U_S^T on the
-    sampled voxels, which does not depend on the basis chosen inside it."""
+    voxels per column, GROUSE one column at a time until the pass objective
+    falls by at most 0.1% (at most 10 passes), split-BF16 T_ex.  The FP64
+    oracle's run (tests/golden/make_train_full.py) fixes the passes used and
+    their objectives, sigma, mu, the 300 exact maxima and the oracle basis at
+    48 sampled voxels.  Three t maps are recomputed here one by one.  The
+    subspace is compared through the projector U_S U_S^T on the sampled
+    voxels, which does not depend on the basis chosen inside it."""
     torch = torch_cuda()
     import paper_1703_01506_amd as rpt
-    sys.path.insert(0, golden_path(""))
-    import make_train_full as G
-    g = G.load()
+    G, g = _golden_full()
     announce("train full size (bench shape)")
-    n, v, L, ell, r, seed, passes = G.N, G.V, G.L, G.ELL, G.R, G.SEED, G.PASSES
-    k = S.omega_count(v, G.ETA_PPM)
-    X = S.smoothed_volumes(n, v, seed=1703)
-    tl = S.relabellings(L, n, n // 2, seed=1506)[:ell]
-    U0 = S.gaussian_matrix(v, r, seed=3).astype(np.float32)
-    omt = S.omega_sets(passes * ell, v, k, seed=41)
-    oms = S.omega_sets(ell, v, k, seed=42)
+    n, v, ell, r, seed = G.N, G.V, G.ELL, G.R, G.SEED
+    X, labels, U0, omt, oms, _ = _full_inputs(G)
+    tl = labels[:ell]
     out = rpt.train_subspace(_dev(torch, X), _dev(torch, tl), _dev(torch, U0), _dev(torch, omt), _dev(torch, oms),
-                             passes=passes, seed=seed, return_T=True)
+                             passes=G.PASSES, seed=seed, tol=G.TOL, return_T=True)
     Ud = out["U"].double()
     gram = (Ud.T @ Ud).cpu().numpy()
     T_ex = out["T_ex"]
-    rows = [0, 157, ell - 1]
     X64 = X.astype(np.float64)
-    for i in rows:
+    for i in [0, 157, ell - 1]:
         assert_t_close(T_ex[i].cpu().numpy(), OT.tstat(X64, tl[i] == 1), "split", f"T_ex row {i}")
     assert_t_close(out["train_max"].cpu().numpy(), g["train_max"], "split", "train_max")
     assert (out["info"].cpu().numpy() == 0).all()
+    assert int(out["passes_used"].item()) == g["passes_used"]
+    np.testing.assert_allclose(out["objective"].cpu().numpy()[:g["passes_used"]], g["objective"], rtol=1e-3)
     np.testing.assert_allclose(gram, np.eye(r), atol=5e-5)
     Us = out["U"][torch.from_numpy(g["voxels"]).cuda()].double().cpu().numpy()
     Pg, Po = Us @ Us.T, g["U_rows"] @ g["U_rows"].T
@@ -369,6 +383,32 @@ def test_train_full_size_bench_shape():
     print(f"sigma {sigma:.6g} vs {g['sigma']:.6g}, mu {mu:.6g} vs {g['mu']:.6g}", flush=True)
     assert abs(sigma - g["sigma"]) <= 1e-3 * g["sigma"]
     assert abs(mu - g["mu"]) <= 2e-3
+
+
+def test_rapidpt_full_size_maxnull_gate():
+    """The metric's gate at the benchmark's configuration: Alg. 2 end to end
+    (one library call, the benchmark's launch) at n = 100, v = 250,000,
+    L = 10,000 against the FP64 oracle's max null on the same inputs and noise
+    streams: KL(oracle || GPU) < 1e-3 (50 bins, reading 14) and the alpha =
+    0.05 threshold within 1%; the 300 exact maxima within the split-BF16 bar
+    on t."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    G, g = _golden_full()
+    announce("rapidpt full size: max null against the oracle")
+    ell = G.ELL
+    X, labels, U0, omt, oms, omr = _full_inputs(G)
+    d = [_dev(torch, a) for a in (X, labels[:ell], labels[ell:], U0, omt, oms, omr)]
+    h, tr, info = rpt.rapidpt_maxnull(*d, passes=G.PASSES, seed=G.SEED, tol=G.TOL)
+    h = h.cpu().numpy().astype(np.float64)
+    assert (info.cpu().numpy() == 0).all()
+    assert int(tr["passes_used"].item()) == g["passes_used"]
+    assert_t_close(h[:ell], g["h"][:ell], "split", "exact maxima")
+    kl = OM.kl_divergence(g["h"], h)
+    t_ref, t_gpu = OM.threshold(g["h"], 0.05), OM.threshold(h, 0.05)
+    print(f"KL {kl:.3e}, thresholds {t_gpu:.5f} vs {t_ref:.5f}, max |dh| {np.abs(h - g['h']).max():.3e}", flush=True)
+    assert kl < 1e-3
+    assert abs(t_gpu - t_ref) <= 0.01 * abs(t_ref)
 
 
 def test_rapidpt_single_call_matches_stages_and_replays():
