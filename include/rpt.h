@@ -438,6 +438,25 @@ rpt_status rpt_reorth(float* U, int64_t v, int32_t r, int32_t* info,
                       void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
+ * rpt_reorth without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  The arguments of rpt_reorth without the workspace,
+ * and its kernels and results; the scratch space is a fixed device array
+ * inside the library (every kernel writes what it later reads, so nothing
+ * in it needs clearing between calls),
+ * rpt_reorth_noalloc_capacity() bytes (28.5 MB: every v with r <= 128 fits),
+ * held on each GPU the library runs on until the process ends.  The call
+ * allocates nothing.  Every call on one GPU shares that GPU's array, so two
+ * calls that overlap in time on one GPU (different streams without ordering
+ * between them) race and corrupt each other's results.  The first call on a
+ * GPU looks up the array's device address (hipGetSymbolAddress); later calls
+ * do not touch the runtime beyond their launches.  A size beyond the array
+ * gives RPT_ERR_UNSUPPORTED.
+ * ------------------------------------------------------------------------- */
+size_t rpt_reorth_noalloc_capacity(void);
+rpt_status rpt_reorth_noalloc(float* U, int64_t v, int32_t r, int32_t* info, void* stream);
+
+/* -------------------------------------------------------------------------
  * Masked completion loss of Eq. 1 and its gradient.
  *
  *   f = 1/2 sum_b sum_{k in Omega_b} (t_bk - U[k,:] W[:,b])^2

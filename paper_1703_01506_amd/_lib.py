@@ -68,6 +68,8 @@ SIGNATURES = {
     "rpt_rejection_counts": (_int, [_p, _i64, _p, _i64, _p, _i64, C.c_double, _p, _p]),
     "rpt_reorth_workspace": (_sz, [_i64, _i32]),
     "rpt_reorth": (_int, [_p, _i64, _i32, _p, _p, _sz, _p]),
+    "rpt_reorth_noalloc_capacity": (_sz, []),
+    "rpt_reorth_noalloc": (_int, [_p, _i64, _i32, _p, _p]),
     "rpt_masked_loss_fwd": (_int, [_p, _i64, _i32, _p, _i32, _p, _p, _p, _i64, _p, _p, _p]),
     "rpt_masked_loss_bwd": (_int, [_p, _i64, _i32, _p, _i32, _p, _p, _p, _i64, _p, _p, _p, _p]),
 }
