@@ -249,8 +249,8 @@ def main():
     ap.add_argument("--passes", type=int, default=10)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--headline-only", action="store_true",
-                    help="skip the recovery-only, host-copy and one-thread oracle figures (profiled runs: the "
-                         "traced launches are then exactly the steps' own)")
+                    help="skip the mini-batch variant, the calibration, the recovery-only, host-copy and one-thread "
+                         "oracle figures (profiled runs: the traced launches are then exactly the steps' own)")
     ap.add_argument("--tune-cache", default=None,
                     help="plan-table file: loaded (no tuning runs) if it exists, else written after tuning")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -427,7 +427,8 @@ def main():
                "threshold_rapid": float(rpt.fwer_threshold(h, 0.05).item()),
                "sigma": float(tr["sigma_mu"][0].item()), "mu": float(tr["sigma_mu"][1].item()),
                "passes_used": passes_used, "pass_objective": objective,
-               "calibration": calibration(rpt, torch, Xd, Ld[:ell], U0d, omtd, omsd, P, seed, tr["U"])}
+               "calibration": None if a.headline_only else
+               calibration(rpt, torch, Xd, Ld[:ell], U0d, omtd, omsd, P, seed, tr["U"])}
     if variant is not None:
         variant["kl_naive_vs_rapid"] = kl_max_nulls(nv, hv)
     gate = oracle_gate(h, P)
