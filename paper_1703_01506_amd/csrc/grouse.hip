@@ -19,38 +19,50 @@
 // same p, e and theta), and span(U) = span(B); so at the end of a pass B is
 // orthonormalised (Cholesky-QR) and becomes the next pass's U with N = I.
 //
-// One workgroup of 8 waves runs a whole pass (the steps form a dependent
-// chain).  Per step:
-//  1. Gram of [B_O | x_O]: the sampled rows, SR at a time, are gathered with
-//     16-byte loads (the next group in flight while the current one is
-//     multiplied), split into BF16 hi/lo and staged transposed in LDS; the
-//     lower 16 x 16 tiles of the (r+1) x (r+1) Gram matrix are spread over
-//     the waves and accumulated on 16x16x32 matrix-core products as
-//     hi.hi + hi.lo + lo.hi.  Column r is x_O, so row r holds b = B_O^T x_O.
-//  2. H z = b by Jacobi-preconditioned conjugate gradients in FP64 (H in LDS
-//     in FP32): a dependent chain of short matrix-vector products, much
-//     shorter than an r-step Cholesky on one workgroup.
-//  3. e = x_O - B_O z (16 lanes per sampled row, four rows per lane group
-//     in flight), |e|^2 in FP64.
-//  4. w = N z, the angle, u = N^T wh and the rank-one update of N (FP32 in
-//     LDS), then B[O] += (s / |e|) e (u / c)^T.
-// The Eq. 1 objective of the pass, the sum over its visits of |e|^2 before U
-// moves, decides when tracking has converged.
+// A pass is one launch of nwg workgroups of four waves (one wave per SIMD,
+// so each holds up to 512 registers).  The k sampled rows of a step are cut
+// into slices of 32; workgroup g owns slices g, g + nwg, ... (one each up to
+// 64 slices).  Per step:
+//  1. Every workgroup gathers its rows once into LDS as [B_q | x_q | 0 ..]
+//     and accumulates its partial Gram tiles of [B_O | x_O] on 16x16x4 FP32
+//     matrix-core products (lane (c, q) holds row q of a group of four at
+//     column c of each 16-column block; wave w takes the tiles t = w mod 4).
+//  2. Grid barrier; each workgroup sums a share of the tiles over all
+//     partials; grid barrier.  Row r of the summed H is b = B_O^T x_O.
+//  3. Every workgroup solves H z = b itself by Jacobi-preconditioned
+//     conjugate gradients in FP64, H in registers (lane (q, c) of wave w:
+//     rows 32 w + 8 q .. + 7, columns 8 c .. 8 c + 7; H p is eight FMAs per
+//     row and a reduce-scatter over the 16 lanes of a DPP row).  The solve
+//     and the r x r updates below are identical in every workgroup, so z, w,
+//     the angle and N agree bit for bit without being exchanged.
+//  4. The residuals e = x_O - B_O z of its rows (from LDS) give a partial
+//     |e|^2; grid barrier; every workgroup adds the partials in one order.
+//  5. w = N z, the angle, u = N^T wh and the rank-one update of N (each
+//     lane keeps its 8 x 8 block of N, the layout of H, in registers); then
+//     each workgroup writes B[q] + (s / |e|) e_q (u / c)^T for its rows;
+//     grid barrier, so that the next step gathers the moved rows.
+// N stretches by 1/c along wh at every step; when the steps are large it
+// loses its conditioning within a pass, so the pass then refreshes
+// B <- B N^{-1} (= U) over all rows and restarts from N = I (N^{-1} is kept
+// by the same rank-one updates).
+// A single workgroup would gather the 875 rows of a step at about 20 GB/s;
+// spread over 28 workgroups the gathers overlap and the step is bounded by
+// the solve and the four barriers.  The Eq. 1 objective of the pass, the
+// sum over its visits of |e|^2 before U moves, decides when tracking has
+// converged.
+#include <type_traits>
+
 #include "rpt_internal.h"
 
 namespace rpt {
 
 namespace {
 
-constexpr int kGT = 512;           // threads of the tracking workgroup
-constexpr int kGWaves = kGT / 64;  // 8
-constexpr int kCB = kGT / 128;     // column blocks of the matrix-vector products
-constexpr int kCW = 128 / kCB;     // their width
+constexpr int kGT = 256;           // threads of a tracking workgroup: one wave per SIMD
+constexpr int kGWaves = kGT / 64;  // 4
 constexpr int kGR = 128;           // rank bound
 constexpr int kCgMaxIt = 300;      // conjugate-gradient iteration cap
 constexpr double kCgTol = 1e-8;    // stop when |b - H z| <= kCgTol |b|
-constexpr int kRowLanes = 16;      // lanes per sampled row in the row phases
-constexpr int kRowU = 4;           // rows per lane group in flight
 constexpr size_t kLdsMax = 160 * 1024;
 
 struct GrouseArgs {
@@ -63,7 +75,6 @@ struct GrouseArgs {
   int k;
   int ell;
   float gamma;
-  float* ybuf;           // [k]: sampled values, then residuals
   double* objr;          // [2]: objectives of the previous and current pass
   double* obj_out;       // [passes] or null
   int pass;
@@ -71,640 +82,734 @@ struct GrouseArgs {
   int32_t* used;         // passes run
   double tol;
   int32_t* info;         // [ell]
-  int lidx;              // sampled indices held in LDS
 };
 
 // FP64 vectors of the solve and the move, then FP32 ones
 struct GrouseVec {
-  double x[kGR], p2[2][kGR], zv[kGR], wh[kGR];
-  double part[kCB][kGR];
+  double zv[kGR];  // CG direction source z_t, then the solution z
+  double wv[kGR];  // w = N z
+  double uu[kGR];  // u = N^T wh
+  double mw[kGR];   // N^{-1} wh
   double red[4][kGWaves];
-  double red2[2][2][kGWaves];
+  double nrm[2][kGWaves];  // per-wave |N|_F^2 and |N^{-1}|_F^2
   int badf[kGWaves];
-  float zf[kGR], qf[kGR], u[kGR];
-  float sink;
-  int flag;
+  float zf[kGR], qf[kGR];
 };
 
-// dynamic LDS: [GrouseVec][N: r x (r + 1) FP32][union: staging | H][idx: k int]
-struct GrouseLds {
-  size_t n_off, u_off, idx_off, total;
-};
-__host__ __device__ inline int g_ncol(int r) { return 16 * ((r + 1 + 15) / 16); }
-// H row length: at least r + 1 and 1 mod 32 words, so that the eight rows
-// and four column blocks a half-wave reads in the solve fall in distinct banks
-__host__ __device__ inline int g_hld(int r) { return ((r + 31) / 32) * 32 + 1; }
-__host__ __device__ inline GrouseLds grouse_lds(int r, int k, int sr, bool lidx) {
-  GrouseLds l;
-  size_t off = (sizeof(GrouseVec) + 15) & ~size_t(15);
-  l.n_off = off;
-  off += static_cast<size_t>(r) * (r + 1) * sizeof(float);
-  off = (off + 15) & ~size_t(15);
-  l.u_off = off;
-  const size_t stage = static_cast<size_t>(2) * g_ncol(r) * (sr + 8) * sizeof(uint16_t);
-  const size_t h = static_cast<size_t>(r + 1) * g_hld(r) * sizeof(float);
-  off += stage > h ? stage : h;
-  off = (off + 15) & ~size_t(15);
-  l.idx_off = off;
-  if (lidx) off += static_cast<size_t>(k) * sizeof(int);
-  l.total = off;
-  return l;
-}
-
-// sum over the whole workgroup into every thread (red: kGWaves doubles, free
-// on entry and not written again before the next barrier)
-__device__ __forceinline__ double block_sum_d(double x, double* red) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  x = wave_sum_d(x);
-  if (lane == 0) red[wave] = x;
-  __syncthreads();
-  double t = 0.0;
-#pragma unroll
-  for (int i = 0; i < kGWaves; ++i) t += red[i];
-  return t;
-}
-
-// sum over threads 0..127 (the first two waves) into red[0..1]; callers
-// synchronise before reading it
-__device__ __forceinline__ void two_wave_sum(double x, double* red) {
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  if (wave < 2) {
-    x = wave_sum_d(x);
-    if (lane == 0) red[wave] = x;
-  }
-}
-
-// sum over the 64 lanes of one wave with DPP moves (quad permutations, row
-// mirrors, row broadcasts); the total ends in lane 63 and is read back as a
-// scalar, so every lane gets it
-__device__ __forceinline__ double dpp_add(double s, int ctrl_id) {
+// column blocks of 16 covering columns 0..r; H holds all 16 RB rows and the
+// columns the tiles write (row length 16 RB + 1 words)
+__host__ __device__ constexpr int g_rb(int r) { return (r + 1 + 15) / 16; }
+__host__ __device__ constexpr int g_hld(int rb) { return 16 * rb + 1; }
+// DPP lane moves within rows of 16 lanes: quad_perm [1, 0, 3, 2] (0xB1),
+// quad_perm [2, 3, 0, 1] (0x4E), row_half_mirror (0x141), row_mirror
+// (0x140); row_bcast:15 (0x142) and row_bcast:31 (0x143) into the upper
+// rows for whole-wave sums
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ double dpp_mov_d(double s) {
   const long long b = __double_as_longlong(s);
-  int lo = static_cast<int>(b & 0xFFFFFFFFll), hi = static_cast<int>(b >> 32);
-  switch (ctrl_id) {
-    case 0:
-      lo = __builtin_amdgcn_update_dpp(0, lo, 0xB1, 0xF, 0xF, false);
-      hi = __builtin_amdgcn_update_dpp(0, hi, 0xB1, 0xF, 0xF, false);
-      break;
-    case 1:
-      lo = __builtin_amdgcn_update_dpp(0, lo, 0x4E, 0xF, 0xF, false);
-      hi = __builtin_amdgcn_update_dpp(0, hi, 0x4E, 0xF, 0xF, false);
-      break;
-    case 2:
-      lo = __builtin_amdgcn_update_dpp(0, lo, 0x141, 0xF, 0xF, false);
-      hi = __builtin_amdgcn_update_dpp(0, hi, 0x141, 0xF, 0xF, false);
-      break;
-    case 3:
-      lo = __builtin_amdgcn_update_dpp(0, lo, 0x140, 0xF, 0xF, false);
-      hi = __builtin_amdgcn_update_dpp(0, hi, 0x140, 0xF, 0xF, false);
-      break;
-    case 4:
-      lo = __builtin_amdgcn_update_dpp(0, lo, 0x142, 0xA, 0xF, false);
-      hi = __builtin_amdgcn_update_dpp(0, hi, 0x142, 0xA, 0xF, false);
-      break;
-    default:
-      lo = __builtin_amdgcn_update_dpp(0, lo, 0x143, 0xC, 0xF, false);
-      hi = __builtin_amdgcn_update_dpp(0, hi, 0x143, 0xC, 0xF, false);
-      break;
-  }
-  const long long m = (static_cast<long long>(static_cast<unsigned>(hi)) << 32) | static_cast<unsigned>(lo);
-  return s + __longlong_as_double(m);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xFFFFFFFFll), CTRL, ROWMASK, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROWMASK, 0xF, false);
+  return __longlong_as_double((static_cast<long long>(static_cast<unsigned>(hi)) << 32) | static_cast<unsigned>(lo));
 }
+template <int CTRL>
+__device__ __forceinline__ float dpp_mov_f(float s) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), CTRL, 0xF, 0xF, false));
+}
+// sum over the 64 lanes of one wave; the total ends in lane 63 and is read
+// back as a scalar, so every lane gets it
 __device__ __forceinline__ double wave_sum_dpp(double s) {
-  s = dpp_add(s, 0);  // quad_perm [1, 0, 3, 2]
-  s = dpp_add(s, 1);  // quad_perm [2, 3, 0, 1]: quad sums
-  s = dpp_add(s, 2);  // row_half_mirror: sums of eight
-  s = dpp_add(s, 3);  // row_mirror: row sums
-  s = dpp_add(s, 4);  // row_bcast:15 into rows 1 and 3
-  s = dpp_add(s, 5);  // row_bcast:31 into rows 2 and 3: lane 63 holds the total
+  s += dpp_mov_d<0xB1, 0xF>(s);
+  s += dpp_mov_d<0x4E, 0xF>(s);   // quad sums
+  s += dpp_mov_d<0x141, 0xF>(s);  // sums of eight
+  s += dpp_mov_d<0x140, 0xF>(s);  // row sums
+  s += dpp_mov_d<0x142, 0xA>(s);  // rows 1 and 3 add rows 0 and 2
+  s += dpp_mov_d<0x143, 0xC>(s);  // rows 2 and 3 add row 1: lane 63 holds the total
   const long long b = __double_as_longlong(s);
   const unsigned lo = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b & 0xFFFFFFFFll), 63));
   const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), 63));
   return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
-
-template <int RB, int SR>
-__global__ __launch_bounds__(kGT) void grouse_pass_kernel(GrouseArgs a) {
-  constexpr int NCOL = 16 * RB;
-  constexpr int NG = NCOL / 4;                    // column groups of four
-  constexpr int NU = (NG + kGWaves - 1) / kGWaves;
-  constexpr int NT = RB * (RB + 1) / 2;           // lower 16 x 16 tiles
-  constexpr int TPW = (NT + kGWaves - 1) / kGWaves;
-  constexpr int RPL = SR / 64;                    // staged rows per lane
-  constexpr int SLD = SR + 8;                     // BF16 per staged column
-  extern __shared__ __align__(16) unsigned char lds[];
-  if (*a.stop < a.pass) return;  // converged in an earlier pass
-  const int r = a.r, k = a.k;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, c16 = lane & 15, kq = lane >> 4;
-  const GrouseLds L = grouse_lds(r, k, SR, a.lidx != 0);
-  GrouseVec& sv = *reinterpret_cast<GrouseVec*>(lds);
-  float* N = reinterpret_cast<float*>(lds + L.n_off);
-  uint16_t* sh = reinterpret_cast<uint16_t*>(lds + L.u_off);
-  uint16_t* sl = sh + NCOL * SLD;
-  float* H = reinterpret_cast<float*>(lds + L.u_off);
-  int* sidx = reinterpret_cast<int*>(lds + L.idx_off);
-  const int nld = r + 1, hld = g_hld(r);
-  const bool vec = (r & 3) == 0 && (reinterpret_cast<uintptr_t>(a.B) & 15) == 0;
-  // the pass starts from U = B, N = I
-  for (int t = tid; t < r * nld; t += kGT) {
-    const int i = t / nld, c = t - i * nld;
-    N[t] = i == c ? 1.0f : 0.0f;
-  }
-  int tbi[TPW], tbj[TPW];
+// sum over the 16 lanes of a DPP row into every one of them
+__device__ __forceinline__ float row16_sum_f(float x) {
+  x += dpp_mov_f<0xB1>(x);
+  x += dpp_mov_f<0x4E>(x);
+  x += dpp_mov_f<0x141>(x);
+  x += dpp_mov_f<0x140>(x);
+  return x;
+}
+// Eight values per lane, summed over the 16 lanes of a DPP row; lane c of
+// the row ends with the sum of value row8_sel(c) (two lanes per value, c
+// and c ^ 1).  Each exchange sends the half the partner keeps: row_mirror
+// pairs c with 15 - c (lanes from 8 on keep values 4..7), row_half_mirror
+// pairs c with 7 - c in each half (c % 8 >= 4 keeps the upper two), the
+// quad exchange c ^ 2 halves them again (c % 4 >= 2 keeps the upper one),
+// c ^ 1 completes the sum.
+__device__ __forceinline__ int row8_sel(int c) { return ((c >> 3) << 2) | (((c >> 2) & 1) << 1) | ((c >> 1) & 1); }
+__device__ __forceinline__ double row16_reduce_scatter8(const double (&v)[8], int c) {
+  const bool h8 = c >= 8, h4 = (c & 4) != 0, h2 = (c & 2) != 0;
+  double k4[4];
 #pragma unroll
-  for (int j = 0; j < TPW; ++j) {
-    int t = wave + kGWaves * j, bi = 0;
-    if (t < NT) {
-      while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
-      tbi[j] = bi;
-      tbj[j] = t - bi * (bi + 1) / 2;
-    } else {
-      tbi[j] = tbj[j] = -1;
-    }
+  for (int m = 0; m < 4; ++m) {
+    const double keep = h8 ? v[4 + m] : v[m], send = h8 ? v[m] : v[4 + m];
+    k4[m] = keep + dpp_mov_d<0x140, 0xF>(send);
   }
-  double obj = 0.0;
-  // row phases: lane group g = tid / 16 takes rows g, g + 32, ...; lane
-  // covers columns 4 l + 64 h .. + 3 (h = 0, 1), l = lane % 16
-  const int rg = tid / kRowLanes, rl = tid % kRowLanes;
-  constexpr int NRG = kGT / kRowLanes;  // 32 row groups
+  double k2[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) {
+    const double keep = h4 ? k4[2 + m] : k4[m], send = h4 ? k4[m] : k4[2 + m];
+    k2[m] = keep + dpp_mov_d<0x141, 0xF>(send);
+  }
+  double k1 = h2 ? k2[1] : k2[0];
+  const double s1 = h2 ? k2[0] : k2[1];
+  k1 += dpp_mov_d<0x4E, 0xF>(s1);
+  k1 += dpp_mov_d<0xB1, 0xF>(k1);
+  return k1;
+}
+
+// the lower 16 x 16 tiles (bi >= bj) of an RB-block Gram matrix, numbered
+// bi (bi + 1) / 2 + bj; tile group G of TG takes the tiles t = G mod TG.
+// One 16x16x4 FP32 matrix-core product per tile and group of four rows:
+// lane (c, q) holds row q of the group at column c of each block (x[b]).
+__host__ __device__ constexpr int gram_ntw(int rb, int tg) { return (rb * (rb + 1) / 2 + tg - 1) / tg; }
+template <int RB, int TG, int G>
+__device__ __forceinline__ void gram_products(f32x4 (&acc)[gram_ntw(RB, TG)], const float (&x)[RB]) {
+#pragma unroll
+  for (int bi = 0; bi < RB; ++bi)
+#pragma unroll
+    for (int bj = 0; bj <= bi; ++bj) {
+      const int t = bi * (bi + 1) / 2 + bj;
+      if (t % TG == G) acc[t / TG] = __builtin_amdgcn_mfma_f32_16x16x4f32(x[bi], x[bj], acc[t / TG], 0, 0, 0);
+    }
+}
+
+// H z = b (b: row r of H) by Jacobi-preconditioned conjugate gradients in
+// FP64, H in registers in the matrix layout (lane (rq, cb) of wave w: rows
+// rbase .. rbase + 7, columns 8 cb .. 8 cb + 7; after a reduce-scatter the
+// lane holds row myrow, owned by the even lane of its pair).  On return
+// sv.zv and sv.zf hold z (zero from r on); the result is 0, 1 (a
+// non-positive curvature or diagonal) or 2 (iteration cap).  Ends with a
+// barrier.
+template <int HLD>
+__device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, int lane, int wave, int rbase, int cb,
+                                         int myrow, bool owner, bool rowok) {
+  constexpr int hld = HLD;
+  int cg_fail = 0;
+  double h[8][8];
+#pragma unroll
+  for (int ii = 0; ii < 8; ++ii)
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int rr = rbase + ii, cc = 8 * cb + j;
+      const int hi = min(max(rr, cc), r - 1), lo = min(min(rr, cc), r - 1);
+      const float hv = H[hi * hld + lo];
+      h[ii][j] = (rr < r && cc < r) ? static_cast<double>(hv) : 0.0;
+    }
+  const int rowc = rowok ? myrow : 0;
+  const double bq = rowok ? static_cast<double>(H[r * hld + rowc]) : 0.0;
+  const double dg = rowok ? static_cast<double>(H[rowc * hld + rowc]) : 1.0;
+  const double di = dg > 0.0 ? 1.0 / dg : 0.0;
+  const bool cnt = owner && rowok;
+  double xr = 0.0, sr = bq, zr = di * bq, pr = 0.0;
+  double pc[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) pc[j] = 0.0;
+  const double pb = wave_sum_dpp(cnt ? bq * bq : 0.0);
+  const double pz = wave_sum_dpp(cnt ? sr * zr : 0.0);
+  const bool anybad = __ballot(rowok && !(dg > 0.0)) != 0ull;
+  if (lane == 0) {
+    sv.red[2][wave] = pb;
+    sv.red[3][wave] = pz;
+    sv.badf[wave] = anybad ? 1 : 0;
+  }
+  if (owner) sv.zv[myrow] = zr;  // rows >= r hold 0
   __syncthreads();
-
-  for (int i = 0; i < a.ell; ++i) {
-    const int32_t* om = a.omega + static_cast<int64_t>(i) * k;
-    const float* Ti = a.T + static_cast<int64_t>(i) * a.ldT;
-    // sampled voxels (out of range: -1, a zero row and a zero value) and values
-    for (int q = tid; q < k; q += kGT) {
-      const int64_t vox = om[q];
-      const bool ok = vox >= 0 && vox < a.v;
-      if (a.lidx) sidx[q] = ok ? static_cast<int>(vox) : -1;
-      a.ybuf[q] = ok ? Ti[vox] : 0.0f;
-    }
-    if (tid == 0) sv.flag = 0;
-    __threadfence_block();
-    __syncthreads();
-    auto voxel = [&](int q) -> int64_t {
-      if (a.lidx) return sidx[q];
-      const int64_t vx = om[q];
-      return (vx >= 0 && vx < a.v) ? vx : -1;
-    };
-    // Warm the caches with this column's sampled rows before the Gram groups
-    // gather them: one load per 128-byte line a row can touch, ten in flight
-    // per lane, addresses clamped so that every load is issued.  The Gram
-    // groups then wait for cache hits instead of one memory round trip each.
-    {
-      const int lines = (4 * r + 127) / 128 + 1;
-      const int total = k * lines;
-      for (int base = 0; base < total; base += 10 * kGT) {
-        float pv[10];
+  double bn2 = 0.0, rz = 0.0;
 #pragma unroll
-        for (int u = 0; u < 10; ++u) {
-          const int t = min(base + u * kGT + tid, total - 1);
-          const int q = t / lines, l = t - q * lines;
-          const int64_t vx = voxel(q);
-          pv[u] = a.B[(vx >= 0 ? vx : 0) * r + min(32 * l, r - 1)];
+  for (int w = 0; w < kGWaves; ++w) {
+    bn2 += sv.red[2][w];
+    rz += sv.red[3][w];
+    cg_fail |= sv.badf[w];
+  }
+  if (bn2 > 0.0 && !cg_fail) {
+    const double stop2 = kCgTol * kCgTol * bn2;
+    double beta = 0.0;
+    int it = 0;
+#pragma unroll 1
+    for (; it < kCgMaxIt; ++it) {
+      // p_t = z_t + beta p_{t-1}, at this lane's columns and at its row
+#pragma unroll
+      for (int j = 0; j < 8; ++j) pc[j] = fma(beta, pc[j], sv.zv[8 * cb + j]);
+      pr = fma(beta, pr, zr);
+      double ap[8];
+#pragma unroll
+      for (int ii = 0; ii < 8; ++ii) {
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; j += 2) {
+          a0 = fma(h[ii][j], pc[j], a0);
+          a1 = fma(h[ii][j + 1], pc[j + 1], a1);
         }
-        float sum = 0.0f;
-#pragma unroll
-        for (int u = 0; u < 10; ++u) sum += pv[u];
-        if (sum == -1.0e-37f) sv.sink = sum;  // keeps the loads (practically never taken)
+        ap[ii] = a0 + a1;
       }
-    }
-    // ---------------------------------------------------------- 1. Gram
-    f32x4 acc[TPW];
+      const double apr = row16_reduce_scatter8(ap, cb);
+      const double pap_w = wave_sum_dpp(cnt ? pr * apr : 0.0);
+      if (lane == 0) sv.red[0][wave] = pap_w;
+      __syncthreads();  // every read of z_t is done, p.Hp partials are in
+      double pap = 0.0;
 #pragma unroll
-    for (int j = 0; j < TPW; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-    float xv[RPL][NU][4];
-    auto gather = [&](int s0) {
-#pragma unroll
-      for (int h = 0; h < RPL; ++h) {
-        const int row = s0 + (RPL == 2 ? 2 * lane + h : lane);
-        const int64_t vox = row < k ? voxel(row) : -1;
-        const bool ok = vox >= 0;
-        const float* br = a.B + (ok ? vox : 0) * r;
-        const float yv = ok ? a.ybuf[row] : 0.0f;
-#pragma unroll
-        for (int u = 0; u < NU; ++u) {
-          const int g = wave + kGWaves * u;
-          const int c0 = 4 * g;
-          if (vec) {
-            // r is a multiple of 4: a group lies wholly below r or at and
-            // above it; the load address is clamped, so every load is issued
-            const f32x4 q = *reinterpret_cast<const f32x4*>(br + min(c0, r - 4));
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              xv[h][u][e] = (g < NG && ok) ? (c0 < r ? q[e] : (c0 + e == r ? yv : 0.0f)) : 0.0f;
-          } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e) {
-              const int c = c0 + e;
-              float x = 0.0f;
-              if (g < NG && ok) x = c < r ? br[c] : (c == r ? yv : 0.0f);
-              xv[h][u][e] = x;
-            }
-          }
-        }
+      for (int w = 0; w < kGWaves; ++w) pap += sv.red[0][w];
+      if (!(pap > 0.0)) {
+        cg_fail = 1;
+        break;
       }
-    };
-    const int ngrp = (k + SR - 1) / SR;
-    gather(0);
-    for (int s = 0; s < ngrp; ++s) {
-      // stage the registers (the previous group's products are done); with
-      // two rows per lane they are rows 2 lane and 2 lane + 1, stored as one
-      // 32-bit word per column and half
-#pragma unroll
-      for (int u = 0; u < NU; ++u) {
-        const int g = wave + kGWaves * u;
-        if (g < NG) {
-#pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            const int c = 4 * g + e;
-            if (RPL == 2) {
-              const uint16_t h0 = f2bf(xv[0][u][e]), h1 = f2bf(xv[RPL - 1][u][e]);
-              const uint16_t l0 = f2bf(xv[0][u][e] - bf2f(h0)), l1 = f2bf(xv[RPL - 1][u][e] - bf2f(h1));
-              *reinterpret_cast<uint32_t*>(sh + c * SLD + 2 * lane) = pack_bf2(h0, h1);
-              *reinterpret_cast<uint32_t*>(sl + c * SLD + 2 * lane) = pack_bf2(l0, l1);
-            } else {
-              const uint16_t hb = f2bf(xv[0][u][e]);
-              sh[c * SLD + lane] = hb;
-              sl[c * SLD + lane] = f2bf(xv[0][u][e] - bf2f(hb));
-            }
-          }
-        }
-      }
-      __syncthreads();
-      if (s + 1 < ngrp) gather((s + 1) * SR);
-#pragma unroll
-      for (int j = 0; j < TPW; ++j) {
-        if (tbi[j] < 0) continue;
-        const int ra = (16 * tbi[j] + c16) * SLD + 8 * kq;
-        const int rb = (16 * tbj[j] + c16) * SLD + 8 * kq;
-#pragma unroll
-        for (int kk = 0; kk < SR; kk += 32) {
-          const u32x4 ah = *reinterpret_cast<const u32x4*>(sh + ra + kk);
-          const u32x4 al = *reinterpret_cast<const u32x4*>(sl + ra + kk);
-          const u32x4 bh = *reinterpret_cast<const u32x4*>(sh + rb + kk);
-          const u32x4 bl = *reinterpret_cast<const u32x4*>(sl + rb + kk);
-          acc[j] = mfma16_bf16(ah, bh, acc[j]);
-          acc[j] = mfma16_bf16(ah, bl, acc[j]);
-          acc[j] = mfma16_bf16(al, bh, acc[j]);
-        }
-      }
-      __syncthreads();
-    }
-    // tiles into H (aliases the staging buffer, whose reads are all done):
-    // the lower triangle and its mirror, rows and columns 0..r
-#pragma unroll
-    for (int j = 0; j < TPW; ++j) {
-      if (tbi[j] < 0) continue;
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int row = 16 * tbi[j] + 4 * kq + e, col = 16 * tbj[j] + c16;
-        if (row >= col && row <= r) {
-          H[row * hld + col] = acc[j][e];
-          H[col * hld + row] = acc[j][e];
-        }
-      }
-    }
-    __syncthreads();
-
-    // ---------------------------------------------------------- 2. H z = b
-    // Wave w owns rows 16 w .. 16 w + 15: lane 4 j + q forms the part of row
-    // 16 w + j over the columns 32 m + 8 q .. + 7 (m = 0..3), a quad
-    // reduction completes it.
-    // Every wave forms the search direction p_t = z_t + beta p_{t-1} itself
-    // from z_t and p_{t-1} in LDS while the owners store p_t into the other
-    // of two buffers, so an iteration needs two barriers (after the p.Hp
-    // partial sums and after the residual partial sums).
-    int cg_fail = 0;
-    {
-      const int jr = lane >> 2, qc = lane & 3;
-      const int row = 16 * wave + jr;
-      const bool ownr = row < r;
-      const int rowc = ownr ? row : 0;
-      const double b = ownr ? static_cast<double>(H[r * hld + row]) : 0.0;
-      const double dg = ownr ? static_cast<double>(H[row * hld + row]) : 1.0;
-      const double di = dg > 0.0 ? 1.0 / dg : 0.0;
-      const bool lead = qc == 0;
-      double xr = 0.0, sr = b, zr = di * b, pr = 0.0;
-      const double pb = wave_sum_dpp(lead ? b * b : 0.0);
-      const double pz = wave_sum_dpp(lead ? sr * zr : 0.0);
-      const bool anybad = __ballot(ownr && !(dg > 0.0)) != 0ull;
+      const double alpha = rz / pap;
+      xr = fma(alpha, pr, xr);
+      sr = fma(-alpha, apr, sr);
+      zr = rowok ? di * sr : 0.0;
+      if (owner) sv.zv[myrow] = zr;
+      const double rz_w = wave_sum_dpp(cnt ? sr * zr : 0.0);
+      const double rr_w = wave_sum_dpp(cnt ? sr * sr : 0.0);
       if (lane == 0) {
-        sv.red[2][wave] = pb;
-        sv.red[3][wave] = pz;
-        sv.badf[wave] = anybad ? 1 : 0;
+        sv.red[1][wave] = rz_w;
+        sv.red[2][wave] = rr_w;
       }
-      if (lead) {
-        sv.zv[row] = zr;        // rows >= r hold 0
-        sv.p2[1][row] = 0.0;    // p_{-1}
-      }
-      __syncthreads();
-      double bn2 = 0.0, rz = 0.0;
+      __syncthreads();  // z_{t+1} and the residual partials are in
+      double rz1 = 0.0, rr1 = 0.0;
 #pragma unroll
       for (int w = 0; w < kGWaves; ++w) {
-        bn2 += sv.red[2][w];
-        rz += sv.red[3][w];
-        cg_fail |= sv.badf[w];
+        rz1 += sv.red[1][w];
+        rr1 += sv.red[2][w];
       }
-      if (bn2 > 0.0 && !cg_fail) {
-        const double stop2 = kCgTol * kCgTol * bn2;
-        const float* hrow = H + rowc * hld;
-        double beta = 0.0;
-        int it = 0;
-        for (; it < kCgMaxIt; ++it) {
-          const int slot = it & 1;
-          const double* pold = sv.p2[slot ^ 1];
-          pr = fma(beta, pr, zr);
-          if (lead) sv.p2[slot][row] = ownr ? pr : 0.0;
-          double a0 = 0.0, a1 = 0.0;
-#pragma unroll 1
-          for (int m = 0; m < 4; ++m) {
-            double pc[8];
-            float hv[8];
-#pragma unroll
-            for (int e = 0; e < 8; ++e) {
-              const int c = 32 * m + 8 * qc + e;
-              pc[e] = fma(beta, pold[c], sv.zv[c]);  // zero from column r on
-              hv[e] = hrow[min(c, r)];                 // clamped into the row: finite
-            }
-#pragma unroll
-            for (int e = 0; e < 8; e += 2) {
-              a0 = fma(static_cast<double>(hv[e]), pc[e], a0);
-              a1 = fma(static_cast<double>(hv[e + 1]), pc[e + 1], a1);
-            }
-          }
-          double apr = a0 + a1;
-          apr += __shfl_xor(apr, 1, 64);
-          apr += __shfl_xor(apr, 2, 64);
-          if (!ownr) apr = 0.0;
-          const double pap_w = wave_sum_dpp(lead ? pr * apr : 0.0);
-          if (lane == 0) sv.red2[slot][0][wave] = pap_w;
-          __syncthreads();  // every read of z and p_{t-1} is done, p.Hp partials are in
-          double pap = 0.0;
-#pragma unroll
-          for (int w = 0; w < kGWaves; ++w) pap += sv.red2[slot][0][w];
-          if (!(pap > 0.0)) {
-            cg_fail = 1;
-            break;
-          }
-          const double alpha = rz / pap;
-          xr = fma(alpha, pr, xr);
-          sr = fma(-alpha, apr, sr);
-          zr = di * sr;
-          if (lead) sv.zv[row] = ownr ? zr : 0.0;
-          const double rz_w = wave_sum_dpp(lead ? sr * zr : 0.0);
-          const double rr_w = wave_sum_dpp(lead ? sr * sr : 0.0);
-          if (lane == 0) {
-            sv.red2[slot][1][wave] = rz_w;
-            sv.red[slot][wave] = rr_w;
-          }
-          __syncthreads();  // z_{t+1} and the residual partials are in
-          double rz1 = 0.0, rr1 = 0.0;
-#pragma unroll
-          for (int w = 0; w < kGWaves; ++w) {
-            rz1 += sv.red2[slot][1][w];
-            rr1 += sv.red[slot][w];
-          }
-          if (rr1 <= stop2) break;
-          beta = rz1 / rz;
-          rz = rz1;
-        }
-        if (it == kCgMaxIt) cg_fail = 2;
-      }
-      if (lead) {
-        sv.x[row] = ownr ? xr : 0.0;
-        sv.zf[row] = ownr ? static_cast<float>(xr) : 0.0f;
-      }
-      __syncthreads();
+      if (rr1 <= stop2) break;
+      beta = rz1 / rz;
+      rz = rz1;
     }
-    const bool own = tid < r;
+    if (it == kCgMaxIt) cg_fail = 2;
+  }
+  // every read of zv in the loop happened before its last barrier
+  if (owner) {
+    sv.zv[myrow] = rowok ? xr : 0.0;
+    sv.zf[myrow] = rowok ? static_cast<float>(xr) : 0.0f;
+  }
+  __syncthreads();
+  return cg_fail;
+}
 
-    // ---------------------------------------------------------- 3. residual
-    float zl[8];
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int c = 4 * rl + 64 * h + e;
-        zl[4 * h + e] = c < r ? sv.zf[c] : 0.0f;
+constexpr int kCoopSlice = 32;        // sampled rows per slice
+constexpr int kCoopMaxWg = 64;        // workgroups of one pass
+constexpr long kSpinMax = 1L << 22;   // polls of a grid barrier before it gives up
+constexpr double kRefresh = 1.05;     // refresh B = U N when |N|_F |N^{-1}|_F > kRefresh r
+
+struct CoopArgs {
+  GrouseArgs g;
+  float* part;      // [nwg][NT][256]: partial Gram tiles
+  float* hred;      // [NT][256]: the summed tiles
+  double* epart;    // [nwg]: partial |e|^2
+  uint32_t* ctr;    // [2]: barrier counters of even and odd passes
+  int32_t* abort;   // raised when a barrier wait expires
+  int nwg;          // workgroups
+  int spw;          // slices of 32 sampled rows per workgroup (at most)
+};
+
+// dynamic LDS: [GrouseVec][H: 16 RB x hld FP32, later the partial sums of
+// u][rows: 32 spw x rs FP32][voxel, e: 32 spw each][flag]
+__host__ __device__ constexpr int coop_rs(int rb) { return 16 * rb + 2; }
+__host__ __device__ inline size_t coop_lds(int r, int spw) {
+  const int rb = g_rb(r);
+  size_t off = (sizeof(GrouseVec) + 15) & ~size_t(15);
+  const size_t h = static_cast<size_t>(16 * rb) * g_hld(rb) * sizeof(float);
+  const size_t up = static_cast<size_t>(4 * kGWaves) * kGR * sizeof(double);
+  off += h > up ? h : up;
+  off = (off + 15) & ~size_t(15);
+  off += static_cast<size_t>(kCoopSlice) * spw * coop_rs(rb) * sizeof(float);
+  off += static_cast<size_t>(2 * kCoopSlice * spw + 4) * sizeof(int);
+  return off;
+}
+
+// Every workgroup arrives before any leaves.  Stores made before it are
+// seen by loads after it in every workgroup: the release fence writes this
+// XCD's L2 back, the acquire fence invalidates this CU's L1 and the L2.  The
+// wait is bounded; when it expires the abort flag is raised, and every
+// workgroup that sees it (or expires itself) returns false and leaves the
+// pass.
+__device__ __forceinline__ bool coop_barrier(uint32_t* ctr, uint32_t target, int32_t* abort, int* flag) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int ok = 1;
+    long spins = 0;
+    while (__hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+      if (__hip_atomic_load(abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+        ok = 0;
+        break;
       }
-    double ee = 0.0;
-    for (int q0 = rg; q0 < k; q0 += NRG * kRowU) {
-      float d[kRowU];
-      bool okr[kRowU];
-      if (vec) {
-        // every row's loads issued before the first product (rows out of
-        // range read row 0 and are dropped)
-        f32x4 b4[kRowU][2];
+      __builtin_amdgcn_s_sleep(2);
+      if (++spins > kSpinMax) {
+        __hip_atomic_store(abort, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        ok = 0;
+        break;
+      }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    *flag = ok;
+  }
+  __syncthreads();
+  return *flag != 0;
+}
+
+template <int RB>
+__global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
+  extern __shared__ __align__(16) unsigned char lds[];
+  const GrouseArgs& a = ca.g;
+  if (*a.stop < a.pass) return;  // converged in an earlier pass
+  constexpr int hld = g_hld(RB), rs = coop_rs(RB);
+  constexpr int NT = RB * (RB + 1) / 2, TG = kGWaves, NTW = gram_ntw(RB, kGWaves);
+  const int r = a.r, k = a.k, nwg = ca.nwg, wg = blockIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  GrouseVec& sv = *reinterpret_cast<GrouseVec*>(lds);
+  size_t off = (sizeof(GrouseVec) + 15) & ~size_t(15);
+  float* H = reinterpret_cast<float*>(lds + off);
+  double* upart = reinterpret_cast<double*>(lds + off);
+  {
+    const size_t h = static_cast<size_t>(16 * RB) * hld * sizeof(float);
+    const size_t up = static_cast<size_t>(4 * kGWaves) * kGR * sizeof(double);
+    off += h > up ? h : up;
+    off = (off + 15) & ~size_t(15);
+  }
+  // this workgroup's slices: wg, wg + nwg, ... (nsl of them)
+  const int nslices = (k + kCoopSlice - 1) / kCoopSlice;
+  const int nsl = (nslices - wg + nwg - 1) / nwg;
+  float* rows = reinterpret_cast<float*>(lds + off);
+  int* svox = reinterpret_cast<int*>(rows + kCoopSlice * ca.spw * rs);
+  float* se = reinterpret_cast<float*>(svox + kCoopSlice * ca.spw);
+  int* flag = reinterpret_cast<int*>(se + kCoopSlice * ca.spw);
+  uint32_t* ctr = ca.ctr + (a.pass & 1);
+  if (wg == 0 && tid == 0) ca.ctr[(a.pass + 1) & 1] = 0;  // the next pass's counter, idle during this one
+  uint32_t target = 0;
+  const bool vec = (r & 3) == 0 && (reinterpret_cast<uintptr_t>(a.B) & 15) == 0;
+  // this lane's 8 x 8 block of N (rows 32 w + 8 rq + i, columns 8 cb + j), in
+  // registers; the pass starts from N = I
+  // (and of N^{-1}, nin)
+  float nreg[8][8], nin[8][8];
+  auto identity = [&]() {
 #pragma unroll
-        for (int u = 0; u < kRowU; ++u) {
-          const int q = q0 + NRG * u;
-          const int64_t vx = q < k ? voxel(q) : -1;
-          okr[u] = vx >= 0;
-          const float* br = a.B + (okr[u] ? vx : 0) * r;
+    for (int i = 0; i < 8; ++i)
 #pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int c0 = 4 * rl + 64 * h;
-            b4[u][h] = *reinterpret_cast<const f32x4*>(br + min(c0, r - 4));  // clamped: always issued
+      for (int j = 0; j < 8; ++j) {
+        const int rr = 32 * wave + 8 * (lane >> 4) + i, cc = 8 * (lane & 15) + j;
+        nreg[i][j] = nin[i][j] = (rr == cc && rr < r) ? 1.0f : 0.0f;
+      }
+  };
+  identity();
+  double obj = 0.0;
+  bool alive = true;
+
+#pragma unroll 1
+  for (int i = 0; i < a.ell && alive; ++i) {
+    // Lane coordinates, formed afresh in every step: the empty asm hides the
+    // lane id from loop-invariant code motion, which would otherwise keep
+    // dozens of addresses and masks derived from it in registers for the
+    // whole pass.
+    int ln = lane;
+    asm volatile("" : "+v"(ln));
+    const int c16 = ln & 15, kq = ln >> 4;
+    const int rq = ln >> 4, cb = ln & 15;
+    const int rbase = 32 * wave + 8 * rq;
+    const int myrow = rbase + row8_sel(cb);
+    const bool owner = (cb & 1) == 0, rowok = myrow < r;
+    const int rg = 4 * wave + (ln >> 4), rl = ln & 15;  // 16 row groups of 16 lanes
+    // ---------------------------------------------------------- 0. refresh
+    // Each step stretches N by 1/c along wh; where the steps are large (a
+    // large share of the voxels sampled) N loses its conditioning within a
+    // pass, and so do B = U N and the Gram matrices built from it.  When
+    // |N|_F |N^{-1}|_F / r (1 for N = I) exceeds kRefresh, B <- B N^{-1} = U
+    // over all v rows (each workgroup a share) and N <- I: the subspace and
+    // the step are unchanged.
+    if (i > 0) {
+      double nf = 0.0, mf = 0.0;
+#pragma unroll
+      for (int w = 0; w < kGWaves; ++w) {
+        nf += sv.nrm[0][w];
+        mf += sv.nrm[1][w];
+      }
+      if (sqrt(nf * mf) > kRefresh * r) {
+        float* Md = H;  // N^{-1}, r x r
+#pragma unroll
+        for (int ii = 0; ii < 8; ++ii)
+#pragma unroll
+          for (int j = 0; j < 8; ++j)
+            if (rbase + ii < r && 8 * cb + j < r) Md[(rbase + ii) * r + 8 * cb + j] = nin[ii][j];
+        __syncthreads();
+        const int64_t lo = a.v * wg / nwg, hi = a.v * (wg + 1) / nwg;
+#pragma unroll 1
+        for (int64_t b0 = lo; b0 < hi; b0 += kCoopSlice) {
+          const int nr = static_cast<int>(min(static_cast<int64_t>(kCoopSlice), hi - b0));
+#pragma unroll
+          for (int u = 0; u < kCoopSlice / 16; ++u) {
+            const int row = rg + 16 * u;
+            if (row < nr)
+              for (int c = rl; c < r; c += 16) rows[row * rs + c] = a.B[(b0 + row) * r + c];
           }
-        }
+          __syncthreads();
+          // thread (row, chunk): columns 16 chunk .. + 15 of one row
+          const int row = tid >> 3, c0 = 16 * (tid & 7);
+          if (row < nr && c0 < r) {
+            float o[16];
 #pragma unroll
-        for (int u = 0; u < kRowU; ++u) {
-          float t = 0.0f;
+            for (int jj = 0; jj < 16; ++jj) o[jj] = 0.0f;
+#pragma unroll 1
+            for (int ii = 0; ii < r; ++ii) {
+              const float bv = rows[row * rs + ii];
 #pragma unroll
-          for (int h = 0; h < 2; ++h)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) t = fmaf(b4[u][h][e], zl[4 * h + e], t);
-          d[u] = okr[u] ? t : 0.0f;
-        }
-      } else {
-#pragma unroll
-        for (int u = 0; u < kRowU; ++u) {
-          const int q = q0 + NRG * u;
-          const int64_t vx = q < k ? voxel(q) : -1;
-          okr[u] = vx >= 0;
-          d[u] = 0.0f;
-          if (okr[u]) {
-            const float* br = a.B + vx * r;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const int c0 = 4 * rl + 64 * h;
-#pragma unroll
-              for (int e = 0; e < 4; ++e)
-                if (c0 + e < r) d[u] = fmaf(br[c0 + e], zl[4 * h + e], d[u]);
+              for (int jj = 0; jj < 16; ++jj) o[jj] = fmaf(bv, Md[ii * r + min(c0 + jj, r - 1)], o[jj]);
             }
+#pragma unroll
+            for (int jj = 0; jj < 16; ++jj)
+              if (c0 + jj < r) a.B[(b0 + row) * r + c0 + jj] = o[jj];
+          }
+          __syncthreads();
+        }
+        identity();
+        target += nwg;
+        if (!(alive = coop_barrier(ctr, target, ca.abort, flag))) break;
+      }
+    }
+    // ---------------------------------------------------------- 1. gather
+    // local row lq = 32 m + j is sampled row q = 32 (wg + nwg m) + j
+    const int32_t* om = a.omega + static_cast<int64_t>(i) * k;
+    const float* Ti = a.T + static_cast<int64_t>(i) * a.ldT;
+    for (int lq = tid; lq < kCoopSlice * nsl; lq += kGT) {
+      const int q = kCoopSlice * (wg + nwg * (lq / kCoopSlice)) + lq % kCoopSlice;
+      const int64_t vox = q < k ? om[q] : -1;
+      const int vx = (vox >= 0 && vox < a.v) ? static_cast<int>(vox) : -1;
+      svox[lq] = vx;
+      se[lq] = vx >= 0 ? Ti[vx] : 0.0f;  // x_q, later the residual
+    }
+    __syncthreads();
+    // rows into LDS as [B_q | x_q | 0 ...] up to column 16 RB (rows out of
+    // range: zeros); lane rl of a row group covers columns 4 rl + 64 h .. + 3
+    constexpr int NCH = (16 * RB + 63) / 64;
+#pragma unroll 1
+    for (int m = 0; m < nsl; ++m) {
+#pragma unroll
+      for (int u = 0; u < kCoopSlice / 16; ++u) {
+        const int lq = kCoopSlice * m + rg + 16 * u;
+        const int vx = svox[lq];
+        const float xq = se[lq];
+        const float* br = a.B + static_cast<int64_t>(vx >= 0 ? vx : 0) * r;
+        float* lr = rows + lq * rs;
+        f32x4 b4[NCH];
+#pragma unroll
+        for (int hh = 0; hh < NCH; ++hh) {
+          const int c0 = 4 * rl + 64 * hh;
+          if (vec) {
+            b4[hh] = *reinterpret_cast<const f32x4*>(br + min(c0, r - 4));  // clamped: always issued
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) b4[hh][e] = br[min(c0 + e, r - 1)];
+          }
+        }
+#pragma unroll
+        for (int hh = 0; hh < NCH; ++hh) {
+          const int c0 = 4 * rl + 64 * hh;
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int c = c0 + e;
+            if (c < 16 * RB) lr[c] = (vx >= 0 && c < r) ? b4[hh][e] : (c == r ? xq : 0.0f);
           }
         }
       }
+    }
+    __syncthreads();
+    // ---------------------------------------------------------- 2. partial Gram
+    {
+      f32x4 acc[NTW];
 #pragma unroll
-      for (int u = 0; u < kRowU; ++u) {
+      for (int j = 0; j < NTW; ++j) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+      auto slices = [&](auto G) {
+        constexpr int g = decltype(G)::value;
+#pragma unroll 1
+        for (int m = 0; m < nsl; ++m) {
 #pragma unroll
-        for (int off = kRowLanes / 2; off >= 1; off >>= 1) d[u] += __shfl_xor(d[u], off, 64);
-        const int q = q0 + NRG * u;
-        if (rl == 0 && q < k) {
-          const float e = a.ybuf[q] - d[u];
-          a.ybuf[q] = e;
+          for (int st = 0; st < kCoopSlice / 4; ++st) {
+            float x[RB];
+#pragma unroll
+            for (int b = 0; b < RB; ++b) x[b] = rows[(kCoopSlice * m + 4 * st + kq) * rs + 16 * b + c16];
+            gram_products<RB, TG, g>(acc, x);
+          }
+        }
+        float* pw = ca.part + static_cast<size_t>(wg) * NT * 256;
+#pragma unroll
+        for (int t = g; t < NT; t += TG) *reinterpret_cast<f32x4*>(pw + t * 256 + 4 * lane) = acc[t / TG];
+      };
+      // wave w takes the tiles t = w mod 4
+      if (wave == 0)
+        slices(std::integral_constant<int, 0>());
+      else if (wave == 1)
+        slices(std::integral_constant<int, 1>());
+      else if (wave == 2)
+        slices(std::integral_constant<int, 2>());
+      else
+        slices(std::integral_constant<int, 3>());
+    }
+    target += nwg;
+    if (!(alive = coop_barrier(ctr, target, ca.abort, flag))) break;
+    // ---------------------------------------------------------- 3. sum a share of the tiles
+    {
+      const int E = NT * 256;
+      const int e0 = static_cast<int>(static_cast<int64_t>(E) * wg / nwg);
+      const int e1 = static_cast<int>(static_cast<int64_t>(E) * (wg + 1) / nwg);
+      for (int e = e0 + tid; e < e1; e += kGT) {
+        float t = 0.0f;
+        for (int p = 0; p < nwg; ++p) t += ca.part[static_cast<size_t>(p) * E + e];
+        ca.hred[e] = t;
+      }
+    }
+    target += nwg;
+    if (!(alive = coop_barrier(ctr, target, ca.abort, flag))) break;
+    // the summed tiles into H (lower tiles; element e of tile t is row
+    // 16 bi + 4 (l / 16) + e % 4, column 16 bj + l % 16, l = (e % 256) / 4)
+    for (int e4 = tid; e4 < NT * 64; e4 += kGT) {
+      const int t = e4 >> 6, l = e4 & 63;
+      int bi = 0;
+      while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
+      const int bj = t - bi * (bi + 1) / 2;
+      const f32x4 v4 = *reinterpret_cast<const f32x4*>(ca.hred + 4 * e4);
+#pragma unroll
+      for (int e = 0; e < 4; ++e) H[(16 * bi + 4 * (l >> 4) + e) * hld + 16 * bj + (l & 15)] = v4[e];
+    }
+    __syncthreads();
+    // ---------------------------------------------------------- 4. H z = b (every workgroup)
+    const int cg_fail = grouse_cg<hld>(H, r, sv, lane, wave, rbase, cb, myrow, owner, rowok);
+    // ---------------------------------------------------------- 5. residuals of this slice
+    {
+      float zl[8];
+#pragma unroll
+      for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int c = 4 * rl + 64 * hh + e;
+          zl[4 * hh + e] = c < r ? sv.zf[c] : 0.0f;
+        }
+      double ee = 0.0;
+#pragma unroll 1
+      for (int lq = rg; lq < kCoopSlice * nsl; lq += 16) {
+        const int q = lq;
+        const float* lr = rows + q * rs;
+        float t = 0.0f;
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int c = 4 * rl + 64 * hh + e;
+            t = fmaf(lr[min(c, 16 * RB - 1)], zl[4 * hh + e], t);  // zl is zero from r on
+          }
+        const float d = row16_sum_f(t);
+        if (rl == 0) {
+          const float e = svox[q] >= 0 ? lr[r] - d : 0.0f;
+          se[q] = e;
           ee += static_cast<double>(e) * e;
         }
       }
-    }
-    __threadfence_block();
-    ee = block_sum_d(ee, sv.red[3]);
-    obj += ee;
-
-    // ---------------------------------------------------------- 4. move
-    // w = N z (thread (row, block of kCW columns))
-    {
-      const int row = tid & (kGR - 1), cb = tid >> 7;
-      double s = 0.0;
-      if (row < r) {
-        // column indices clamped to r - 1 (x is zero from r on): no
-        // conditional loads
-        const float* nr = N + row * nld;
-#pragma unroll 8
-        for (int c = 0; c < kCW; ++c) {
-          const int cc = kCW * cb + c;
-          s = fma(static_cast<double>(nr[min(cc, r - 1)]), sv.x[cc], s);
-        }
-      }
-      sv.part[cb][row] = s;
-    }
-    __syncthreads();
-    if (tid < kGR) {
-      double wv = 0.0;
+      ee = wave_sum_dpp(ee);
+      if (lane == 0) sv.red[3][wave] = ee;
+      __syncthreads();
+      if (tid == 0) {
+        double t = 0.0;
 #pragma unroll
-      for (int b = 0; b < kCB; ++b) wv += sv.part[b][tid];
-      if (!own) wv = 0.0;
-      sv.wh[tid] = wv;
-      two_wave_sum(wv * wv, sv.red[0]);
+        for (int w = 0; w < kGWaves; ++w) t += sv.red[3][w];
+        ca.epart[wg] = t;
+      }
+    }
+    target += nwg;
+    if (!(alive = coop_barrier(ctr, target, ca.abort, flag))) break;
+    double ee = 0.0;
+    for (int p = 0; p < nwg; ++p) ee += ca.epart[p];
+    obj += ee;
+    // ---------------------------------------------------------- 6. w = N z, the angle
+    {
+      double zc[8], wp[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) zc[j] = sv.zv[8 * cb + j];
+#pragma unroll
+      for (int ii = 0; ii < 8; ++ii) {
+        double t = 0.0;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) t = fma(static_cast<double>(nreg[ii][j]), zc[j], t);
+        wp[ii] = t;
+      }
+      const double wrow = row16_reduce_scatter8(wp, cb);
+      if (owner) sv.wv[myrow] = wrow;
+      const double ww = wave_sum_dpp(owner ? wrow * wrow : 0.0);
+      if (lane == 0) sv.red[0][wave] = ww;
     }
     __syncthreads();
-    const double nw = sqrt(sv.red[0][0] + sv.red[0][1]);
+    double nw2 = 0.0;
+#pragma unroll
+    for (int w = 0; w < kGWaves; ++w) nw2 += sv.red[0][w];
+    const double nw = sqrt(nw2);
     const double ne = sqrt(ee);
     double cth = 1.0, sth = 0.0;
     if (nw > 0.0 && ne > 0.0 && !cg_fail) {
-      const double th = static_cast<double>(a.gamma) * atan(ne / nw);
-      cth = cos(th);
-      sth = sin(th);
+      if (a.gamma == 1.0f) {
+        const double hyp = sqrt(nw2 + ee);
+        cth = nw / hyp;
+        sth = ne / hyp;
+      } else {
+        const double th = static_cast<double>(a.gamma) * atan(ne / nw);
+        cth = cos(th);
+        sth = sin(th);
+      }
     }
     if (sth != 0.0 && fabs(cth) > 1e-12) {
-      // u = N^T wh: thread (column, block of kCW rows)
+      // ---------------------------------------------------------- 7. u = N^T wh, N, this slice's rows
+      const double inw = 1.0 / nw;
+      double whv[8];
+#pragma unroll
+      for (int ii = 0; ii < 8; ++ii) whv[ii] = sv.wv[rbase + ii] * inw;
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        double t = 0.0;
+#pragma unroll
+        for (int ii = 0; ii < 8; ++ii) t = fma(static_cast<double>(nreg[ii][j]), whv[ii], t);
+        upart[(4 * wave + rq) * kGR + 8 * cb + j] = t;
+      }
       {
-        const int col = tid & (kGR - 1), blk = tid >> 7;
-        const double inw = 1.0 / nw;
-        double su = 0.0;
-        if (col < r) {
-#pragma unroll 8
-          for (int i2 = 0; i2 < kCW; ++i2) {
-            const int rr = kCW * blk + i2;
-            su = fma(sv.wh[rr] * inw, static_cast<double>(N[min(rr, r - 1) * nld + col]), su);
-          }
+        // N^{-1} wh at this lane's rows, reduce-scattered onto the row owners
+        double whc[8], mp[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) whc[j] = sv.wv[8 * cb + j] * inw;
+#pragma unroll
+        for (int ii = 0; ii < 8; ++ii) {
+          double t = 0.0;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) t = fma(static_cast<double>(nin[ii][j]), whc[j], t);
+          mp[ii] = t;
         }
-        sv.part[blk][col] = su;
+        const double mrow = row16_reduce_scatter8(mp, cb);
+        if (owner) sv.mw[myrow] = mrow;
       }
       __syncthreads();
       if (tid < kGR) {
-        double tu = 0.0;
+        double t = 0.0;
 #pragma unroll
-        for (int b = 0; b < kCB; ++b) tu += sv.part[b][tid];
-        sv.u[tid] = own ? static_cast<float>(tu) : 0.0f;
-        sv.qf[tid] = own ? static_cast<float>(tu / cth) : 0.0f;
-        sv.zf[tid] = own ? static_cast<float>(sv.wh[tid] / nw) : 0.0f;  // wh
+        for (int p = 0; p < 4 * kGWaves; ++p) t += upart[p * kGR + tid];
+        const bool own = tid < r;
+        sv.uu[tid] = own ? t : 0.0;
+        sv.qf[tid] = own ? static_cast<float>(t / cth) : 0.0f;
       }
       __syncthreads();
-      // N += (1/c - 1) wh u^T
       const float fi = static_cast<float>(1.0 / cth - 1.0);
-      for (int t = tid; t < r * nld; t += kGT) {
-        const int i2 = t / nld, c = t - i2 * nld;
-        if (c < r) N[t] = fmaf(fi * sv.zf[i2], sv.u[c], N[t]);
+#pragma unroll
+      for (int ii = 0; ii < 8; ++ii) {
+        const float fw = fi * static_cast<float>(whv[ii]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) nreg[ii][j] = fmaf(fw, static_cast<float>(sv.uu[8 * cb + j]), nreg[ii][j]);
       }
-      // B[O] += (s / |e|) e q^T
-      const float g = static_cast<float>(sth / ne);
+      // N^{-1} <- N^{-1} (I + (c - 1) wh wh^T)
+      const double cm1 = cth - 1.0;
+#pragma unroll
+      for (int ii = 0; ii < 8; ++ii) {
+        const float fm = static_cast<float>(cm1 * sv.mw[rbase + ii]);
+#pragma unroll
+        for (int j = 0; j < 8; ++j) nin[ii][j] = fmaf(fm, static_cast<float>(sv.wv[8 * cb + j] * inw), nin[ii][j]);
+      }
+      const float gs = static_cast<float>(sth / ne);
       float ql[8];
 #pragma unroll
-      for (int h = 0; h < 2; ++h)
+      for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
-          const int c = 4 * rl + 64 * h + e;
-          ql[4 * h + e] = c < r ? sv.qf[c] : 0.0f;
+          const int c = 4 * rl + 64 * hh + e;
+          ql[4 * hh + e] = c < r ? sv.qf[c] : 0.0f;
         }
-      for (int q0 = rg; q0 < k; q0 += NRG * kRowU) {
-        f32x4 b4[kRowU][2];
-        int64_t vx[kRowU];
-        float ge[kRowU];
+#pragma unroll 2
+      for (int q = rg; q < kCoopSlice * nsl; q += 16) {
+        const int vx = svox[q];
+        if (vx < 0) continue;
+        const float ge = gs * se[q];
+        const float* lr = rows + q * rs;
+        float* br = a.B + static_cast<int64_t>(vx) * r;
 #pragma unroll
-        for (int u = 0; u < kRowU; ++u) {
-          const int q = q0 + NRG * u;
-          vx[u] = q < k ? voxel(q) : -1;
-          ge[u] = vx[u] >= 0 ? g * a.ybuf[q] : 0.0f;
+        for (int hh = 0; hh < 2; ++hh) {
+          const int c0 = 4 * rl + 64 * hh;
           if (vec) {
-            const float* br = a.B + (vx[u] >= 0 ? vx[u] : 0) * r;
+            if (c0 + 4 <= r) {
+              f32x4 t4;
 #pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const int c0 = 4 * rl + 64 * h;
-              b4[u][h] = *reinterpret_cast<const f32x4*>(br + min(c0, r - 4));  // clamped: always issued
+              for (int e = 0; e < 4; ++e) t4[e] = fmaf(ge, ql[4 * hh + e], lr[c0 + e]);
+              *reinterpret_cast<f32x4*>(br + c0) = t4;
             }
-          }
-        }
+          } else {
 #pragma unroll
-        for (int u = 0; u < kRowU; ++u) {
-          if (vx[u] < 0) continue;
-          float* br = a.B + vx[u] * r;
-#pragma unroll
-          for (int h = 0; h < 2; ++h) {
-            const int c0 = 4 * rl + 64 * h;
-            if (vec) {
-              if (c0 + 4 <= r) {
-                f32x4 t4 = b4[u][h];
-#pragma unroll
-                for (int e = 0; e < 4; ++e) t4[e] = fmaf(ge[u], ql[4 * h + e], t4[e]);
-                *reinterpret_cast<f32x4*>(br + c0) = t4;
-              }
-            } else {
-#pragma unroll
-              for (int e = 0; e < 4; ++e)
-                if (c0 + e < r) br[c0 + e] = fmaf(ge[u], ql[4 * h + e], br[c0 + e]);
-            }
+            for (int e = 0; e < 4; ++e)
+              if (c0 + e < r) br[c0 + e] = fmaf(ge, ql[4 * hh + e], lr[c0 + e]);
           }
         }
       }
     }
-    if (tid == 0) a.info[i] = cg_fail ? -cg_fail : 0;
-    __threadfence_block();
-    __syncthreads();
+    if (wg == 0 && tid == 0) a.info[i] = cg_fail ? -cg_fail : 0;
+    {
+      double nf = 0.0, mf = 0.0;
+#pragma unroll
+      for (int ii = 0; ii < 8; ++ii)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          nf += static_cast<double>(nreg[ii][j]) * nreg[ii][j];
+          mf += static_cast<double>(nin[ii][j]) * nin[ii][j];
+        }
+      nf = wave_sum_dpp(nf);
+      mf = wave_sum_dpp(mf);
+      if (lane == 0) {
+        sv.nrm[0][wave] = nf;
+        sv.nrm[1][wave] = mf;
+      }
+    }
+    target += nwg;
+    if (!(alive = coop_barrier(ctr, target, ca.abort, flag))) break;
   }
 
-  if (tid == 0) {
+  if (wg == 0 && tid == 0) {
     const int slot = a.pass & 1;
+    if (!alive) {
+      *a.stop = a.pass;  // a barrier wait expired: no further passes
+      a.info[0] = -3;
+    }
     a.objr[slot] = obj;
     if (a.obj_out) a.obj_out[a.pass] = obj;
     *a.used = a.pass + 1;
-    if (a.pass >= 1 && a.tol > 0.0) {
+    if (alive && a.pass >= 1 && a.tol > 0.0) {
       const double prev = a.objr[slot ^ 1];
       if (prev - obj <= a.tol * prev) *a.stop = a.pass;
     }
   }
 }
 
-__global__ void grouse_init_kernel(int32_t* stop, int32_t* used, double* objr, double* obj_out, int passes) {
+__global__ void grouse_init_kernel(int32_t* stop, int32_t* used, double* objr, double* obj_out, int passes,
+                                   uint32_t* ctr, int32_t* abort) {
   if (threadIdx.x == 0) {
     *stop = 0x7FFFFFFF;
     *used = 0;
     objr[0] = 0.0;
     objr[1] = 0.0;
+    ctr[0] = 0u;
+    ctr[1] = 0u;
+    *abort = 0;
   }
   if (obj_out)
     for (int p = threadIdx.x; p < passes; p += blockDim.x) obj_out[p] = 0.0;
 }
 
-template <int RB, int SR>
-rpt_status launch_pass(const GrouseArgs& a, size_t smem, hipStream_t s) {
+template <int RB>
+rpt_status launch_coop(const CoopArgs& ca, size_t smem, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&grouse_pass_kernel<RB, SR>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&grouse_coop_kernel<RB>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsMax));
     attr = true;
   }
-  hipLaunchKernelGGL((grouse_pass_kernel<RB, SR>), dim3(1), dim3(kGT), smem, s, a);
+  hipLaunchKernelGGL((grouse_coop_kernel<RB>), dim3(ca.nwg), dim3(kGT), smem, s, ca);
   RPT_CHECK_LAUNCH();
   return RPT_OK;
 }
@@ -713,29 +818,39 @@ rpt_status launch_pass(const GrouseArgs& a, size_t smem, hipStream_t s) {
 
 size_t grouse_bytes(int r, int k) {
   Carver c(nullptr);
-  c.take<float>(static_cast<size_t>(k));
+  (void)k;
+  const size_t nt = static_cast<size_t>(g_rb(r)) * (g_rb(r) + 1) / 2;
+  c.take<float>(static_cast<size_t>(kCoopMaxWg) * nt * 256);
+  c.take<float>(nt * 256);
+  c.take<double>(kCoopMaxWg);
   c.take<double>(2);
   c.take<int32_t>(3);
-  (void)r;
+  c.take<uint32_t>(2);
+  c.take<int32_t>(1);
   return c.off;
 }
 
 GrouseState grouse_carve(void* ws, int r, int k) {
   Carver c(ws);
   GrouseState g;
-  g.ybuf = c.take<float>(static_cast<size_t>(k));
+  (void)k;
+  const size_t nt = static_cast<size_t>(g_rb(r)) * (g_rb(r) + 1) / 2;
+  g.part = c.take<float>(static_cast<size_t>(kCoopMaxWg) * nt * 256);
+  g.hred = c.take<float>(nt * 256);
+  g.epart = c.take<double>(kCoopMaxWg);
   g.objr = c.take<double>(2);
   int32_t* flags = c.take<int32_t>(3);
   g.stop = flags;
   g.used_ws = flags ? flags + 1 : nullptr;
   g.rinfo = flags ? flags + 2 : nullptr;
-  (void)r;
+  g.ctr = c.take<uint32_t>(2);
+  g.abort = c.take<int32_t>(1);
   return g;
 }
 
 rpt_status grouse_init_launch(const GrouseState& g, int32_t* used, double* obj_out, int passes, hipStream_t s) {
   hipLaunchKernelGGL(grouse_init_kernel, dim3(1), dim3(256), 0, s, g.stop, used ? used : g.used_ws, g.objr, obj_out,
-                     passes);
+                     passes, g.ctr, g.abort);
   RPT_CHECK_LAUNCH();
   return RPT_OK;
 }
@@ -743,8 +858,9 @@ rpt_status grouse_init_launch(const GrouseState& g, int32_t* used, double* obj_o
 rpt_status grouse_pass_launch(const GrouseState& g, float* B, int64_t v, int r, const float* T, int64_t ldT,
                               const int32_t* omega, int k, int ell, float gamma, int pass, double tol,
                               double* obj_out, int32_t* used, int32_t* info, hipStream_t s) {
-  if (r < 1 || r > kGR) return RPT_ERR_UNSUPPORTED;
-  GrouseArgs a;
+  if (r < 1 || r > kGR || k < 1) return RPT_ERR_UNSUPPORTED;
+  CoopArgs ca;
+  GrouseArgs& a = ca.g;
   a.B = B;
   a.v = v;
   a.r = r;
@@ -754,7 +870,6 @@ rpt_status grouse_pass_launch(const GrouseState& g, float* B, int64_t v, int r, 
   a.k = k;
   a.ell = ell;
   a.gamma = gamma;
-  a.ybuf = g.ybuf;
   a.objr = g.objr;
   a.obj_out = obj_out;
   a.pass = pass;
@@ -762,31 +877,30 @@ rpt_status grouse_pass_launch(const GrouseState& g, float* B, int64_t v, int r, 
   a.used = used ? used : g.used_ws;
   a.tol = tol;
   a.info = info;
-  // 128 staged rows when they fit in LDS with the rest, else 64; the sampled
-  // indices in LDS when they fit too
-  const int RB = (r + 1 + 15) / 16;
-  const bool big = RB <= 8 && grouse_lds(r, k, 128, false).total <= kLdsMax;
-  const int sr = big ? 128 : 64;
-  a.lidx = grouse_lds(r, k, sr, true).total <= kLdsMax ? 1 : 0;
-  const size_t smem = grouse_lds(r, k, sr, a.lidx != 0).total;
+  ca.part = g.part;
+  ca.hred = g.hred;
+  ca.epart = g.epart;
+  ca.ctr = g.ctr;
+  ca.abort = g.abort;
+  // one slice of 32 sampled rows per workgroup up to 64 slices, then more
+  // slices per workgroup while their rows fit in LDS
+  const int nslices = (k + kCoopSlice - 1) / kCoopSlice;
+  ca.nwg = nslices < kCoopMaxWg ? nslices : kCoopMaxWg;
+  ca.spw = (nslices + ca.nwg - 1) / ca.nwg;
+  const size_t smem = coop_lds(r, ca.spw);
   if (smem > kLdsMax) return RPT_ERR_UNSUPPORTED;
   RPT_STAGE("track_grouse", s);
-#define RPT_GROUSE_CASE(rb) \
-  case rb:                  \
-    return big ? launch_pass<rb, 128>(a, smem, s) : launch_pass<rb, 64>(a, smem, s);
-  switch (RB) {
-    RPT_GROUSE_CASE(1)
-    RPT_GROUSE_CASE(2)
-    RPT_GROUSE_CASE(3)
-    RPT_GROUSE_CASE(4)
-    RPT_GROUSE_CASE(5)
-    RPT_GROUSE_CASE(6)
-    RPT_GROUSE_CASE(7)
-    RPT_GROUSE_CASE(8)
-    default:
-      return launch_pass<9, 64>(a, smem, s);
+  switch (g_rb(r)) {
+    case 1: return launch_coop<1>(ca, smem, s);
+    case 2: return launch_coop<2>(ca, smem, s);
+    case 3: return launch_coop<3>(ca, smem, s);
+    case 4: return launch_coop<4>(ca, smem, s);
+    case 5: return launch_coop<5>(ca, smem, s);
+    case 6: return launch_coop<6>(ca, smem, s);
+    case 7: return launch_coop<7>(ca, smem, s);
+    case 8: return launch_coop<8>(ca, smem, s);
+    default: return launch_coop<9>(ca, smem, s);
   }
-#undef RPT_GROUSE_CASE
 }
 
 }  // namespace rpt

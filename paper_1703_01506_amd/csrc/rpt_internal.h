@@ -299,9 +299,11 @@ rpt_status literal_resid_launch(const float* T, const float* U, const float* W, 
 // residuals of the current column, the objectives of the last two passes and
 // the convergence flags.
 struct GrouseState {
-  double* M = nullptr;
-  double* Minv = nullptr;
-  float* ybuf = nullptr;
+  float* part = nullptr;     // partial Gram tiles of the cooperative pass
+  float* hred = nullptr;     // their sums
+  double* epart = nullptr;   // partial |e|^2
+  uint32_t* ctr = nullptr;   // grid-barrier counters [2]
+  int32_t* abort = nullptr;  // raised when a grid-barrier wait expires
   double* objr = nullptr;
   int32_t* stop = nullptr;
   int32_t* used_ws = nullptr;

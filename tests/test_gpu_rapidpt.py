@@ -233,6 +233,37 @@ def test_train_subspace_matches_oracle(batch, gamma, mu_rule):
         assert mu == 0.0
 
 
+@pytest.mark.parametrize("v,r,k", [(6001, 120, 400), (6001, 128, 700), (20011, 20, 3000), (20011, 100, 2100)])
+def test_train_grouse_shapes_match_oracle(v, r, k):
+    """Column-by-column tracking (Sec. 4.1) at the rank and sampled-set sizes
+    that select the other kernel variants: ranks above 111 (eight and nine
+    16-column blocks, the Gram tiles split over the waves) and sampled sets
+    above 2,048 (one workgroup runs the pass instead of one per 32 rows).
+    Basis, pass objectives and sigma against the oracle."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce(f"train grouse v={v} r={r} k={k}")
+    passes, seed = 2, 2017
+    # more subjects and training columns than the rank, so that T_ex is not
+    # captured by the basis after one pass and both objectives stay large
+    X, tl, U0, omt, oms = _train_inputs(n=160, v=v, ell=r + 16, r=r, k=k, passes=passes)
+    out = rpt.train_subspace(_dev(torch, X), _dev(torch, tl), _dev(torch, U0), _dev(torch, omt), _dev(torch, oms),
+                             passes=passes, seed=seed, batch=1, return_T=True)
+    U = out["U"].cpu().numpy().astype(np.float64)
+    # the oracle tracks the training columns the GPU computed (160 subjects
+    # take the split-BF16 contraction; its parity is tested elsewhere)
+    T_ex = out["T_ex"].cpu().numpy().astype(np.float64)
+    assert_t_close(out["T_ex"].cpu().numpy(), OT.tmatrix(X.astype(np.float64), tl), "split_bf16", "T_ex")
+    hist = []
+    Uo = OR.train_subspace(T_ex, U0.astype(np.float64), omt, passes, batch=1, history=hist)
+    so, _, _ = OR.sigma_mu(T_ex, Uo, oms, seed)
+    sigma = float(out["sigma_mu"][0].item())
+    np.testing.assert_allclose(U.T @ U, np.eye(r), atol=5e-5)
+    assert np.abs(U @ U.T - Uo @ Uo.T).max() < 2e-4
+    np.testing.assert_allclose(out["objective"].cpu().numpy(), hist, rtol=1e-3)
+    assert abs(sigma - so) <= 1e-3 * so
+
+
 def test_train_grouse_stopping_rule():
     """Until convergence (Sec. 4.1): with a tolerance, tracking stops after the
     first pass whose objective fell by at most tol from the pass before; the
