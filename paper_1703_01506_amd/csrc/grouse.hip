@@ -62,7 +62,7 @@ constexpr int kGT = 256;           // threads of a tracking workgroup: one wave 
 constexpr int kGWaves = kGT / 64;  // 4
 constexpr int kGR = 128;           // rank bound
 constexpr int kCgMaxIt = 300;      // conjugate-gradient iteration cap
-constexpr double kCgTol = 1e-8;    // stop when |b - H z| <= kCgTol |b|
+constexpr double kCgTol = 1e-6;    // stop when (r, M r) <= kCgTol^2 (b, M b) (H is exact to about 1e-6)
 constexpr size_t kLdsMax = 160 * 1024;
 
 struct GrouseArgs {
@@ -90,6 +90,8 @@ struct GrouseVec {
   double wv[kGR];  // w = N z
   double uu[kGR];  // u = N^T wh
   double mw[kGR];   // N^{-1} wh
+  double mv[2][kGR];  // M w of the conjugate-gradient iterations
+  double cgr[2][kGWaves][2];
   double red[4][kGWaves];
   double nrm[2][kGWaves];  // per-wave |N|_F^2 and |N^{-1}|_F^2
   int badf[kGWaves];
@@ -183,17 +185,20 @@ __device__ __forceinline__ void gram_products(f32x4 (&acc)[gram_ntw(RB, TG)], co
 }
 
 // H z = b (b: row r of H) by Jacobi-preconditioned conjugate gradients in
-// FP64, H in registers in the matrix layout (lane (rq, cb) of wave w: rows
-// rbase .. rbase + 7, columns 8 cb .. 8 cb + 7; after a reduce-scatter the
-// lane holds row myrow, owned by the even lane of its pair).  On return
-// sv.zv and sv.zf hold z (zero from r on); the result is 0, 1 (a
-// non-positive curvature or diagonal) or 2 (iteration cap).  Ends with a
-// barrier.
+// FP64, in the pipelined form (Ghysels & Vanroose 2014) whose only exchange
+// per iteration is one barrier: the inner products (r, u) and (w, u) (u =
+// M r, M the inverse diagonal) and the vector m = M w that the next product
+// H m needs are written together.  The iteration stops when (r, M r) has
+// fallen by kCgTol^2.  H is held in registers in the matrix layout (lane (rq, cb) of
+// wave w: rows rbase .. rbase + 7, columns 8 cb .. 8 cb + 7; after a
+// reduce-scatter the lane holds row myrow, owned by the even lane of its
+// pair).  On return sv.zv and sv.zf hold z (zero from r on); the result is 0,
+// 1 (a non-positive diagonal or curvature) or 2 (iteration cap).  Ends with
+// a barrier.
 template <int HLD>
 __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, int lane, int wave, int rbase, int cb,
                                          int myrow, bool owner, bool rowok) {
   constexpr int hld = HLD;
-  int cg_fail = 0;
   double h[8][8];
 #pragma unroll
   for (int ii = 0; ii < 8; ++ii)
@@ -209,84 +214,98 @@ __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, i
   const double dg = rowok ? static_cast<double>(H[rowc * hld + rowc]) : 1.0;
   const double di = dg > 0.0 ? 1.0 / dg : 0.0;
   const bool cnt = owner && rowok;
-  double xr = 0.0, sr = bq, zr = di * bq, pr = 0.0;
-  double pc[8];
+  // H y at this lane's row for y given at every column through LDS
+  auto hprod = [&](const double* y) -> double {
+    double yc[8], ap[8];
 #pragma unroll
-  for (int j = 0; j < 8; ++j) pc[j] = 0.0;
-  const double pb = wave_sum_dpp(cnt ? bq * bq : 0.0);
-  const double pz = wave_sum_dpp(cnt ? sr * zr : 0.0);
+    for (int j = 0; j < 8; ++j) yc[j] = y[8 * cb + j];
+#pragma unroll
+    for (int ii = 0; ii < 8; ++ii) {
+      double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+      for (int j = 0; j < 8; j += 2) {
+        a0 = fma(h[ii][j], yc[j], a0);
+        a1 = fma(h[ii][j + 1], yc[j + 1], a1);
+      }
+      ap[ii] = a0 + a1;
+    }
+    return row16_reduce_scatter8(ap, cb);
+  };
+  // x_0 = 0, r_0 = b, u_0 = M r_0, w_0 = H u_0
+  double xr = 0.0, rr_ = bq, ur = di * bq;
+  const double pb = wave_sum_dpp(cnt ? bq * di * bq : 0.0);  // (r_0, M r_0)
   const bool anybad = __ballot(rowok && !(dg > 0.0)) != 0ull;
   if (lane == 0) {
-    sv.red[2][wave] = pb;
-    sv.red[3][wave] = pz;
+    sv.red[3][wave] = pb;
     sv.badf[wave] = anybad ? 1 : 0;
   }
-  if (owner) sv.zv[myrow] = zr;  // rows >= r hold 0
+  if (owner) sv.zv[myrow] = ur;  // rows >= r hold 0
   __syncthreads();
-  double bn2 = 0.0, rz = 0.0;
+  double bn2 = 0.0;
+  int cg_fail = 0;
 #pragma unroll
   for (int w = 0; w < kGWaves; ++w) {
-    bn2 += sv.red[2][w];
-    rz += sv.red[3][w];
+    bn2 += sv.red[3][w];
     cg_fail |= sv.badf[w];
   }
   if (bn2 > 0.0 && !cg_fail) {
     const double stop2 = kCgTol * kCgTol * bn2;
-    double beta = 0.0;
+    double wr = hprod(sv.zv);
+    double zr = 0.0, qr = 0.0, sr = 0.0, pr = 0.0;
+    double rcp_gamma_old = 1.0, rcp_alpha_old = 1.0;
     int it = 0;
 #pragma unroll 1
     for (; it < kCgMaxIt; ++it) {
-      // p_t = z_t + beta p_{t-1}, at this lane's columns and at its row
-#pragma unroll
-      for (int j = 0; j < 8; ++j) pc[j] = fma(beta, pc[j], sv.zv[8 * cb + j]);
-      pr = fma(beta, pr, zr);
-      double ap[8];
-#pragma unroll
-      for (int ii = 0; ii < 8; ++ii) {
-        double a0 = 0.0, a1 = 0.0;
-#pragma unroll
-        for (int j = 0; j < 8; j += 2) {
-          a0 = fma(h[ii][j], pc[j], a0);
-          a1 = fma(h[ii][j + 1], pc[j + 1], a1);
-        }
-        ap[ii] = a0 + a1;
+      const int sl = it & 1;  // double-buffered exchange slots
+      const double mr = rowok ? di * wr : 0.0;
+      const double g0 = wave_sum_dpp(cnt ? rr_ * ur : 0.0);
+      const double g1 = wave_sum_dpp(cnt ? wr * ur : 0.0);
+      if (lane == 0) {
+        sv.cgr[sl][wave][0] = g0;
+        sv.cgr[sl][wave][1] = g1;
       }
-      const double apr = row16_reduce_scatter8(ap, cb);
-      const double pap_w = wave_sum_dpp(cnt ? pr * apr : 0.0);
-      if (lane == 0) sv.red[0][wave] = pap_w;
-      __syncthreads();  // every read of z_t is done, p.Hp partials are in
-      double pap = 0.0;
+      if (owner) sv.mv[sl][myrow] = mr;
+      __syncthreads();  // the inner products and m = M w are in
+      double gam = 0.0, del = 0.0;
 #pragma unroll
-      for (int w = 0; w < kGWaves; ++w) pap += sv.red[0][w];
-      if (!(pap > 0.0)) {
+      for (int w = 0; w < kGWaves; ++w) {
+        gam += sv.cgr[sl][w][0];
+        del += sv.cgr[sl][w][1];
+      }
+      if (gam <= stop2) break;
+      const double nr = hprod(sv.mv[sl]);
+      // the step lengths with a hardware reciprocal and two Newton steps
+      // (quadratic: relative error below 2^-52 from the rcp's 2^-22)
+      auto rcp = [](double d) {
+        double x = __builtin_amdgcn_rcp(d);
+        x = fma(x, fma(-d, x, 1.0), x);
+        return fma(x, fma(-d, x, 1.0), x);
+      };
+      double beta = 0.0, alpha;
+      if (it == 0) {
+        alpha = gam * rcp(del);
+      } else {
+        beta = gam * rcp_gamma_old;
+        alpha = gam * rcp(del - beta * gam * rcp_alpha_old);
+      }
+      if (!(del > 0.0) || !(alpha > 0.0)) {
         cg_fail = 1;
         break;
       }
-      const double alpha = rz / pap;
+      zr = fma(beta, zr, nr);
+      qr = fma(beta, qr, mr);
+      sr = fma(beta, sr, wr);
+      pr = fma(beta, pr, ur);
       xr = fma(alpha, pr, xr);
-      sr = fma(-alpha, apr, sr);
-      zr = rowok ? di * sr : 0.0;
-      if (owner) sv.zv[myrow] = zr;
-      const double rz_w = wave_sum_dpp(cnt ? sr * zr : 0.0);
-      const double rr_w = wave_sum_dpp(cnt ? sr * sr : 0.0);
-      if (lane == 0) {
-        sv.red[1][wave] = rz_w;
-        sv.red[2][wave] = rr_w;
-      }
-      __syncthreads();  // z_{t+1} and the residual partials are in
-      double rz1 = 0.0, rr1 = 0.0;
-#pragma unroll
-      for (int w = 0; w < kGWaves; ++w) {
-        rz1 += sv.red[1][w];
-        rr1 += sv.red[2][w];
-      }
-      if (rr1 <= stop2) break;
-      beta = rz1 / rz;
-      rz = rz1;
+      rr_ = fma(-alpha, sr, rr_);
+      ur = fma(-alpha, qr, ur);
+      wr = fma(-alpha, zr, wr);
+      rcp_gamma_old = rcp(gam);
+      rcp_alpha_old = rcp(alpha);
     }
     if (it == kCgMaxIt) cg_fail = 2;
   }
-  // every read of zv in the loop happened before its last barrier
+  // every read of zv happened before the loop's first barrier
   if (owner) {
     sv.zv[myrow] = rowok ? xr : 0.0;
     sv.zf[myrow] = rowok ? static_cast<float>(xr) : 0.0f;
@@ -556,28 +575,61 @@ __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
     target += nwg;
     if (!(alive = coop_barrier(ctr, target, ca.abort, flag))) break;
     // ---------------------------------------------------------- 3. sum a share of the tiles
+    // This workgroup's share: 16-byte quads q0 .. q1 of the NT * 256 entries.
+    // Every (partial, quad) load goes out at once and lands in LDS (the H
+    // region is free); each entry is then added in workgroup order.
     {
-      const int E = NT * 256;
-      const int e0 = static_cast<int>(static_cast<int64_t>(E) * wg / nwg);
-      const int e1 = static_cast<int>(static_cast<int64_t>(E) * (wg + 1) / nwg);
-      for (int e = e0 + tid; e < e1; e += kGT) {
+      constexpr int E4 = NT * 64;
+      const int q0 = E4 * wg / nwg, q1 = E4 * (wg + 1) / nwg, nq = q1 - q0;
+      f32x4* stage = reinterpret_cast<f32x4*>(H);
+      const int nl = nq * nwg;
+      constexpr int LPT = (E4 + kCoopMaxWg + kGT - 1) / kGT;  // loads per thread, at most
+      const float inq = 1.0f / static_cast<float>(nq);
+#pragma unroll
+      for (int m = 0; m < LPT; ++m) {
+        const int L = tid + kGT * m;
+        if (L < nl) {
+          // L / nq (exact: L < 2^12 and the quotient is rounded down from
+          // within 2^-10 of an integer)
+          const int p = static_cast<int>((static_cast<float>(L) + 0.5f) * inq), qq = L - p * nq;
+          stage[L] = *reinterpret_cast<const f32x4*>(ca.part + (static_cast<size_t>(p) * E4 + q0 + qq) * 4);
+        }
+      }
+      __syncthreads();
+      const float* st = reinterpret_cast<const float*>(stage);
+      for (int x = tid; x < 4 * nq; x += kGT) {
+        const int qq = x >> 2, j = x & 3;
         float t = 0.0f;
-        for (int p = 0; p < nwg; ++p) t += ca.part[static_cast<size_t>(p) * E + e];
-        ca.hred[e] = t;
+        for (int p = 0; p < nwg; ++p) t += st[4 * (p * nq + qq) + j];
+        ca.hred[4 * (q0 + qq) + j] = t;
       }
     }
     target += nwg;
     if (!(alive = coop_barrier(ctr, target, ca.abort, flag))) break;
     // the summed tiles into H (lower tiles; element e of tile t is row
     // 16 bi + 4 (l / 16) + e % 4, column 16 bj + l % 16, l = (e % 256) / 4)
-    for (int e4 = tid; e4 < NT * 64; e4 += kGT) {
-      const int t = e4 >> 6, l = e4 & 63;
-      int bi = 0;
-      while ((bi + 1) * (bi + 2) / 2 <= t) ++bi;
-      const int bj = t - bi * (bi + 1) / 2;
-      const f32x4 v4 = *reinterpret_cast<const f32x4*>(ca.hred + 4 * e4);
+    {
+      constexpr int NE = (NT * 64 + kGT - 1) / kGT, NB4 = NE < 4 ? NE : 4;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) H[(16 * bi + 4 * (l >> 4) + e) * hld + 16 * bj + (l & 15)] = v4[e];
+      for (int m0 = 0; m0 < NE; m0 += NB4) {
+        f32x4 v4[NB4];
+#pragma unroll
+        for (int m = 0; m < NB4; ++m) {
+          const int e4 = min(tid + kGT * (m0 + m), NT * 64 - 1);
+          v4[m] = *reinterpret_cast<const f32x4*>(ca.hred + 4 * e4);
+        }
+#pragma unroll
+        for (int m = 0; m < NB4; ++m) {
+          const int e4 = tid + kGT * (m0 + m);
+          if (e4 < NT * 64) {
+            const int t = e4 >> 6, l = e4 & 63;
+            const int bi = static_cast<int>((sqrtf(8.0f * t + 1.0f) - 1.0f) * 0.5f);
+            const int bj = t - bi * (bi + 1) / 2;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) H[(16 * bi + 4 * (l >> 4) + e) * hld + 16 * bj + (l & 15)] = v4[m][e];
+          }
+        }
+      }
     }
     __syncthreads();
     // ---------------------------------------------------------- 4. H z = b (every workgroup)
