@@ -275,3 +275,85 @@ def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omeg
     sigma, mu, tmax = sigma_mu(T_ex, U, omega_sm, seed, mu_rule)
     rec = recover(X, rec_labels, U, sigma, mu, omega_rec, seed, col0=T_ex.shape[0], stat=stat)
     return np.concatenate([tmax, rec]), U, sigma, mu
+
+
+# ---------------------------------------------------------------------------
+# Robust tracking (l1 loss).  Sec. 3.1 and Sec. 4.1 cite GRASTA (He, Balzano
+# & Szlam 2012) beside GROUSE as the Grassmannian tracker behind the
+# training phase.  Readings where the paper is silent: the column fit is
+# min |x_O - U_O w|_1, solved by ADMM on  min |s|_1  s.t.  U_O w + s = x_O
+# with a fixed penalty rho and a fixed number of iterations; U moves along
+# the geodesic of the augmented Lagrangian's gradient with the constant-step
+# angle theta = eta |Gamma| |w| (at most pi / 2).
+
+def l1_fit(A: np.ndarray, y: np.ndarray, rho: float, iters: int):
+    """ADMM for min_w |y - A w|_1 written as min |s|_1 s.t. A w + s = y.
+
+    Augmented Lagrangian L = |s|_1 + lam^T (A w + s - y) + rho/2 |A w + s - y|^2;
+    each iteration: w <- argmin_w L (least squares), s <- shrink(y - A w -
+    lam / rho, 1 / rho), lam <- lam + rho (A w + s - y).  A final w step
+    follows, so that Gamma = lam + rho (A w + s - y), the gradient of L with
+    respect to the fitted column, satisfies A^T Gamma = 0.
+    Returns (w, s, lam, Gamma)."""
+    A = np.asarray(A, dtype=np.float64)
+    y = np.asarray(y, dtype=np.float64)
+    G = A.T @ A
+    s = np.zeros_like(y)
+    lam = np.zeros_like(y)
+    solve = lambda t: np.linalg.solve(G, A.T @ t)
+    for _ in range(int(iters)):
+        w = solve(y - s - lam / rho)
+        f = A @ w
+        d = y - f - lam / rho
+        s = np.sign(d) * np.maximum(np.abs(d) - 1.0 / rho, 0.0)
+        lam = lam + rho * (f + s - y)
+    w = solve(y - s - lam / rho)
+    gam = lam + rho * (A @ w + s - y)
+    return w, s, lam, gam
+
+
+def grasta_step(U: np.ndarray, x: np.ndarray, idx, eta: float, rho: float, iters: int,
+                loss: list | None = None) -> np.ndarray:
+    """One robust step on column x observed at idx (U orthonormal, v x r).
+
+    (w, s, lam, Gamma_O) = l1_fit(U[idx], x[idx]); Gamma is Gamma_O on idx
+    and 0 elsewhere, so U^T Gamma = 0 and -Gamma w^T is the descent direction
+    on the Grassmannian; sigma = |Gamma| |w|, theta = min(eta sigma, pi/2):
+    U <- U + ((cos theta - 1) U w / |w| - sin theta Gamma / |Gamma|) w^T / |w|.
+    No move when w = 0 or Gamma = 0.  `loss`, when given, receives the l1
+    misfit |x_O - U_O w|_1 before the move."""
+    idx = np.asarray(idx)
+    y = np.asarray(x, dtype=np.float64)[idx]
+    w, s, lam, g = l1_fit(U[idx], y, rho, iters)
+    if loss is not None:
+        loss.append(float(np.sum(np.abs(y - U[idx] @ w))))
+    nw, ng = np.linalg.norm(w), np.linalg.norm(g)
+    if nw == 0.0 or ng == 0.0:
+        return U
+    theta = min(eta * ng * nw, 0.5 * np.pi)
+    gam = np.zeros(U.shape[0])
+    gam[idx] = g
+    step = (np.cos(theta) - 1.0) * (U @ w) / nw - np.sin(theta) * gam / ng
+    return U + np.outer(step, w / nw)
+
+
+def train_subspace_l1(T_ex: np.ndarray, U0: np.ndarray, omega_train: np.ndarray, passes: int,
+                      eta: float, rho: float = 1.0, iters: int = 30, tol: float = 0.0,
+                      history: list | None = None) -> np.ndarray:
+    """Robust subspace tracking over the training columns, one column at a
+    time (``grasta_step``), with the stopping rule of ``train_subspace`` on
+    the pass objective sum_i |x_O - U_O w_i|_1."""
+    ell = T_ex.shape[0]
+    U = orthonormalize(U0)
+    prev = None
+    for p in range(passes):
+        loss: list = []
+        for i in range(ell):
+            U = grasta_step(U, T_ex[i], omega_train[p * ell + i], eta, rho, iters, loss)
+        obj = float(np.sum(loss))
+        if history is not None:
+            history.append(obj)
+        if tol > 0.0 and prev is not None and prev - obj <= tol * prev:
+            break
+        prev = obj
+    return U
