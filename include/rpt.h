@@ -77,6 +77,19 @@ typedef enum {
   RPT_STAT_MEANDIFF = 1
 } rpt_stat;
 
+/* The subspace tracker of the training phase (Sec. 4.1, which cites GROUSE
+ * and GRASTA).  NULL in the training calls means GROUSE. */
+typedef enum {
+  RPT_TRACK_GROUSE = 0, /* l2 fit, geodesic step (the default)                  */
+  RPT_TRACK_L1 = 1      /* robust l1 fit by ADMM, geodesic step along the     */
+                        /* augmented Lagrangian's gradient (GRASTA)           */
+} rpt_track_kind;
+typedef struct {
+  int32_t kind;       /* rpt_track_kind                                        */
+  float rho;          /* RPT_TRACK_L1: ADMM penalty, > 0                       */
+  int32_t admm_iters; /* RPT_TRACK_L1: ADMM iterations per column, 1..1000     */
+} rpt_tracker;
+
 typedef enum {
   RPT_MU_MEAN_GAP = 0, /* mu = mean_i [max T_ex[:,i] - max(U w_i + s_i)]       */
   RPT_MU_LITERAL = 1,  /* mu = sup_i max(T_ex[:,i] - U W_ex[:,i])  (Alg. 2)    */
@@ -232,6 +245,15 @@ rpt_status rpt_complete(const float* U, int64_t v, int32_t r,
  *    batch > 1 (a variant, not the paper's): mini-batches of `batch` columns
  *      fitted on the same U move it by gamma * sum_i e_i w_i^T / |w_i|^2,
  *      then re-orthonormalisation; all `passes` passes run (tol must be 0).
+ *    tracker->kind == RPT_TRACK_L1 (batch 1; GRASTA, He, Balzano & Szlam
+ *      2012, cited beside GROUSE in Sec. 3.1 and 4.1): each column's fit is
+ *      min |t_O - U_O w|_1, by tracker->admm_iters ADMM iterations on
+ *      min |s|_1 s.t. U_O w + s = t_O with penalty tracker->rho, then one
+ *      more w step; Gamma = lam + rho (U_O w + s - t_O) on the sampled
+ *      voxels is orthogonal to U and U moves along the geodesic of -Gamma w^T
+ *      by the angle min(gamma |Gamma| |w|, pi/2):
+ *      U <- U + ((cos th - 1) U w/|w| - sin th Gamma/|Gamma|) w^T/|w|.
+ *      The pass objective is sum_i |t_O - U_O w_i|_1.
  * 4. sigma = sample std (N-1) of the Complete residuals of every training
  *    column on a fresh sampled set omega_sm (l x k); mu by `mu_rule`, with the
  *    mean-gap rule drawing the noise on stream RPT_STREAM_TRAINING.
@@ -250,8 +272,9 @@ rpt_status rpt_complete(const float* U, int64_t v, int32_t r,
  *                passes not run, and for batch > 1)                  (out)
  *   passes_used  NULL or 1 int32: passes run                         (out)
  *   stat         the statistic of T_ex (as rpt_naive_maxnull)
+ *   tracker      NULL (GROUSE) or host pointer to an rpt_tracker     (in)
  * Requirements: as NaivePT and Complete; balanced designs (n1 = n - n1);
- * 1 <= batch <= l; gamma > 0; tol >= 0.
+ * 1 <= batch <= l; gamma > 0; tol >= 0; the l1 tracker needs batch 1.
  * ------------------------------------------------------------------------- */
 size_t rpt_train_workspace(int64_t v, int32_t n, int32_t ell, int32_t r, int32_t k, int prec);
 rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
@@ -260,6 +283,7 @@ rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx,
                               const int32_t* omega_train, int32_t k, int32_t passes,
                               int32_t batch, float gamma, double tol,
                               const int32_t* omega_sm, uint64_t seed, int mu_rule, int prec, int stat,
+                              const rpt_tracker* tracker,
                               float* U_out, float* sigma_mu, float* train_max, float* T_ex_out,
                               int32_t* info, double* objective, int32_t* passes_used,
                               void* ws, size_t ws_bytes, void* stream);
@@ -321,7 +345,7 @@ rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
  *
  *   train_labels  l x n uint8;  rec_labels  L_rec x n uint8             (in)
  *   U0, omega_train, omega_sm, passes, batch, gamma, tol, mu_rule, prec,
- *   stat:         as rpt_train_subspace;  omega_rec  L_rec x k int32     (in)
+ *   stat, tracker: as rpt_train_subspace;  omega_rec  L_rec x k int32    (in)
  *   h_out         l + L_rec FP32                                        (out)
  *   U_out         v x r FP32 trained basis                              (out)
  *   sigma_mu      2 FP32 on the device {sigma, mu}                      (out)
@@ -339,6 +363,7 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
                                const int32_t* omega_train, int32_t k, int32_t passes,
                                int32_t batch, float gamma, double tol, const int32_t* omega_sm,
                                const int32_t* omega_rec, uint64_t seed, int mu_rule, int prec, int stat,
+                               const rpt_tracker* tracker,
                                float* h_out, float* U_out, float* sigma_mu,
                                int32_t* train_info, int32_t* rec_info,
                                double* objective, int32_t* passes_used,

@@ -26,6 +26,11 @@ class RptStudy(C.Structure):
     ]
 
 
+class RptTracker(C.Structure):
+    """Mirror of rpt_tracker (include/rpt.h)."""
+    _fields_ = [("kind", _i32), ("rho", C.c_float), ("admm_iters", _i32)]
+
+
 # name -> (restype, argtypes); mirrors include/rpt.h
 SIGNATURES = {
     "rpt_status_string": (C.c_char_p, [_int]),
@@ -43,8 +48,8 @@ SIGNATURES = {
     "rpt_complete": (_int, [_p, _i64, _i32, _p, _i32, _p, _i64, _p, _p, _p, _p, _sz, _p]),
     "rpt_train_workspace": (_sz, [_i64, _i32, _i32, _i32, _i32, _int]),
     "rpt_train_subspace": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i32, _p, _i32, _p, _i32, _i32, _i32, _f32,
-                                  C.c_double, _p, _u64, _int, _int, _int, _p, _p, _p, _p, _p, _p, _p, _p, _sz,
-                                  _p]),
+                                  C.c_double, _p, _u64, _int, _int, _int, C.POINTER(RptTracker), _p, _p, _p, _p,
+                                  _p, _p, _p, _p, _sz, _p]),
     "rpt_recover_workspace": (_sz, [_i64, _i32, _i64, _i32, _i32]),
     "rpt_autotune_naive": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _int, _p, _i32, _p, _sz, _p, _p]),
     "rpt_autotune_recover_workspace": (_sz, [_i64, _i32, _i64]),
@@ -55,8 +60,8 @@ SIGNATURES = {
     "rpt_autotune_count": (_int, []),
     "rpt_rapidpt_workspace": (_sz, [_i64, _i32, _i32, _i64, _i32, _i32, _int]),
     "rpt_rapidpt_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i32, _p, _i64, _p, _i32, _p, _i32, _i32, _i32,
-                                   _f32, C.c_double, _p, _p, _u64, _int, _int, _int, _p, _p, _p, _p, _p, _p, _p,
-                                   _p, _sz, _p]),
+                                   _f32, C.c_double, _p, _p, _u64, _int, _int, _int, C.POINTER(RptTracker), _p, _p,
+                                   _p, _p, _p, _p, _p, _p, _sz, _p]),
     "rpt_recover_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _i64, _p, _i32, _p, _p, _i32, _p, _u64,
                                    _int, _p, _p, _p, _p, _sz, _p]),
     "rpt_recover_batched_workspace": (_sz, [C.POINTER(RptStudy), _i32]),

@@ -17,6 +17,7 @@ PREC = {"fp32": 0, "split_bf16": 1}
 TAIL = {"signed": 0, "abs": 1}
 MU_RULE = {"mean_gap": 0, "literal": 1, "zero": 2}
 STAT = {"t": 0, "meandiff": 1}
+TRACKER = {"grouse": 0, "l1": 1}
 
 
 def _ptr(t):
@@ -125,15 +126,24 @@ def reorth(U: torch.Tensor):
     return info
 
 
+def _tracker(tracker: str, rho: float, admm_iters: int):
+    """rpt_tracker for the tracker name: "grouse" (l2) or "l1" (GRASTA)."""
+    if tracker not in TRACKER:
+        raise ValueError(f"unknown tracker {tracker!r}")
+    return C.byref(_lib.RptTracker(TRACKER[tracker], float(rho), int(admm_iters)))
+
+
 def train_subspace(X, train_labels, U0, omega_train, omega_sm, passes: int, seed: int,
                    batch: int = 1, gamma: float = 1.0, mu_rule: str = "mean_gap",
                    prec: str = "split_bf16", n1: int | None = None, return_T: bool = False, tol: float = 0.0,
-                   stat: str = "t"):
+                   stat: str = "t", tracker: str = "grouse", rho: float = 1.0, admm_iters: int = 30):
     """Training half of Alg. 2.  batch = 1 tracks one column at a time
     (GROUSE, the paper's mode); tol > 0 stops once a pass's objective no longer
-    falls by more than tol (relative).  Returns a dict with U (v, r), sigma_mu
-    (2,), train_max (l,), info (l,), objective (passes,) FP64, passes_used (1,)
-    and optionally T_ex (l, v)."""
+    falls by more than tol (relative).  tracker = "l1" fits each column in the
+    l1 norm (ADMM with penalty rho, admm_iters iterations) and moves U along
+    the robust gradient with the angle gamma |Gamma| |w| (GRASTA).  Returns a
+    dict with U (v, r), sigma_mu (2,), train_max (l,), info (l,), objective
+    (passes,) FP64, passes_used (1,) and optionally T_ex (l, v)."""
     lib = _lib.load()
     v, n, ldx = _data(X)
     train_labels = _dev(train_labels, torch.uint8, "train_labels", 2).contiguous()
@@ -158,7 +168,8 @@ def train_subspace(X, train_labels, U0, omega_train, omega_sm, passes: int, seed
     ws = _workspace(lib.rpt_train_workspace(v, n, ell, r, k, PREC[prec]), dev)
     rc = lib.rpt_train_subspace(_ptr(X), v, n, ldx, n1, _ptr(train_labels), ell, _ptr(U0), r,
                                 _ptr(omega_train), k, passes, batch, float(gamma), float(tol), _ptr(omega_sm),
-                                int(seed), MU_RULE[mu_rule], PREC[prec], STAT[stat], _ptr(U), _ptr(sm), _ptr(tmax),
+                                int(seed), MU_RULE[mu_rule], PREC[prec], STAT[stat],
+                                _tracker(tracker, rho, admm_iters), _ptr(U), _ptr(sm), _ptr(tmax),
                                 _ptr(T), _ptr(info), _ptr(obj), _ptr(used), _ptr(ws), ws.numel(), _stream(dev))
     _lib.check(rc, "rpt_train_subspace")
     out = {"U": U, "sigma_mu": sm, "train_max": tmax, "info": info, "objective": obj[:passes],
@@ -306,11 +317,13 @@ def rejection_counts(maxima1, maxima2, t, alpha: float = 0.05):
 
 def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omega_rec, passes: int, seed: int,
                     batch: int = 1, gamma: float = 1.0, mu_rule: str = "mean_gap",
-                    prec: str = "split_bf16", tol: float = 0.0, stat: str = "t"):
+                    prec: str = "split_bf16", tol: float = 0.0, stat: str = "t", tracker: str = "grouse",
+                    rho: float = 1.0, admm_iters: int = 30):
     """Alg. 2 end to end in one library call: the l exact training maxima
     followed by the recovered ones.  Returns (h (L,), train dict, recovery
     info); the train dict holds U, sigma_mu, train_max (a view of h), info,
-    objective and passes_used (as train_subspace)."""
+    objective and passes_used (as train_subspace, whose tracker arguments
+    these are)."""
     lib = _lib.load()
     v, n, ldx = _data(X)
     train_labels = _dev(train_labels, torch.uint8, "train_labels", 2).contiguous()
@@ -337,7 +350,7 @@ def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omeg
     rc = lib.rpt_rapidpt_maxnull(_ptr(X), v, n, ldx, n // 2, _ptr(train_labels), ell, _ptr(rec_labels), L_rec,
                                  _ptr(U0), r, _ptr(omega_train), k, passes, batch, float(gamma), float(tol),
                                  _ptr(omega_sm), _ptr(omega_rec), int(seed), MU_RULE[mu_rule], PREC[prec],
-                                 STAT[stat], _ptr(h),
+                                 STAT[stat], _tracker(tracker, rho, admm_iters), _ptr(h),
                                  _ptr(U), _ptr(sm), _ptr(tinfo), _ptr(rinfo), _ptr(obj), _ptr(used), _ptr(ws),
                                  ws.numel(), _stream(dev))
     _lib.check(rc, "rpt_rapidpt_maxnull")

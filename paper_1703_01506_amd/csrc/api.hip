@@ -205,18 +205,32 @@ size_t rpt_train_workspace(int64_t v, int32_t n, int32_t ell, int32_t r, int32_t
 
 namespace rpt {
 namespace {
+TrackOpts track_opts(const rpt_tracker* t) {
+  TrackOpts o;
+  if (t) {
+    o.mode = t->kind;
+    o.rho = t->rho;
+    o.admm_iters = t->admm_iters;
+  }
+  return o;
+}
 rpt_status train_check(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* train_labels,
                        int32_t ell, const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
                        int32_t batch, float gamma, double tol, const int32_t* omega_sm, int mu_rule, int prec,
-                       int stat, const float* U_out, const float* sigma_mu, const float* train_max,
-                       const int32_t* info) {
+                       int stat, const TrackOpts& opt, const float* U_out, const float* sigma_mu,
+                       const float* train_max, const int32_t* info) {
   if (stat != RPT_STAT_T && stat != RPT_STAT_MEANDIFF) return RPT_ERR_INVALID_ARG;
+  if (opt.mode != RPT_TRACK_GROUSE && opt.mode != RPT_TRACK_L1) return RPT_ERR_INVALID_ARG;
+  if (opt.mode == RPT_TRACK_L1 && (!(opt.rho > 0.0f) || opt.admm_iters < 1 || opt.admm_iters > 1000))
+    return RPT_ERR_INVALID_ARG;
+  if (opt.mode == RPT_TRACK_L1 && batch != 1) return RPT_ERR_UNSUPPORTED;  // the l1 fit moves U column by column
   if (!design_ok(v, n, ldx, n1) || 2 * n1 != n) return design_ok(v, n, ldx, n1) ? RPT_ERR_UNSUPPORTED
                                                                                : RPT_ERR_INVALID_ARG;
   if (ell < 1 || r < 1 || r > 128 || r > v || k < 1 || k > v || passes < 0 || batch < 1 || batch > ell ||
       !(gamma > 0.0f) || static_cast<int64_t>(ell) * k > INT32_MAX || !(tol >= 0.0))
     return RPT_ERR_INVALID_ARG;
-  if (batch == 1 && !(gamma < 1.5f)) return RPT_ERR_INVALID_ARG;  // geodesic angle below 3 pi / 4
+  if (batch == 1 && opt.mode == RPT_TRACK_GROUSE && !(gamma < 1.5f))
+    return RPT_ERR_INVALID_ARG;  // geodesic angle below 3 pi / 4
   if (batch > 1 && tol > 0.0) return RPT_ERR_UNSUPPORTED;        // the stopping rule tracks one column at a time
   if (k < r) return RPT_ERR_UNDERDETERMINED;
   if (mu_rule != RPT_MU_MEAN_GAP && mu_rule != RPT_MU_LITERAL && mu_rule != RPT_MU_ZERO) return RPT_ERR_INVALID_ARG;
@@ -235,19 +249,20 @@ rpt_status train_start_basis(int64_t v, int32_t n, int32_t n1, int32_t ell, cons
                              int prec, float* U_out, void* ws, hipStream_t s);
 rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r, const int32_t* omega_train,
                        int32_t k, int32_t passes, int32_t batch, float gamma, double tol, const int32_t* omega_sm,
-                       uint64_t seed, int mu_rule, int prec, float* U_out, float* sigma_mu, float* train_max,
-                       float* T_ex_out, int32_t* info, double* objective, int32_t* passes_used, void* ws,
-                       hipStream_t s, const std::function<rpt_status(int, int)>& at_step = nullptr);
+                       uint64_t seed, int mu_rule, int prec, const TrackOpts& opt, float* U_out, float* sigma_mu,
+                       float* train_max, float* T_ex_out, int32_t* info, double* objective, int32_t* passes_used,
+                       void* ws, hipStream_t s, const std::function<rpt_status(int, int)>& at_step = nullptr);
 
 rpt_status train_run(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* train_labels,
                      int32_t ell, const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
                      int32_t batch, float gamma, double tol, const int32_t* omega_sm, uint64_t seed, int mu_rule,
-                     int prec, int stat, float* U_out, float* sigma_mu, float* train_max, float* T_ex_out,
-                     int32_t* info, double* objective, int32_t* passes_used, void* ws, hipStream_t s) {
+                     int prec, int stat, const TrackOpts& opt, float* U_out, float* sigma_mu, float* train_max,
+                     float* T_ex_out, int32_t* info, double* objective, int32_t* passes_used, void* ws,
+                     hipStream_t s) {
   RPT_TRY(train_tex(X, v, n, ldx, n1, train_labels, ell, r, k, prec, stat, train_max, T_ex_out, ws, s));
   RPT_TRY(train_start_basis(v, n, n1, ell, U0, r, k, prec, U_out, ws, s));
   return train_track(v, n, n1, ell, r, omega_train, k, passes, batch, gamma, tol, omega_sm, seed, mu_rule, prec,
-                     U_out, sigma_mu, train_max, T_ex_out, info, objective, passes_used, ws, s);
+                     opt, U_out, sigma_mu, train_max, T_ex_out, info, objective, passes_used, ws, s);
 }
 
 // 1. training columns T_ex and their exact maxima
@@ -280,9 +295,9 @@ rpt_status train_start_basis(int64_t v, int32_t n, int32_t n1, int32_t ell, cons
 // of `steps`.
 rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r, const int32_t* omega_train,
                        int32_t k, int32_t passes, int32_t batch, float gamma, double tol, const int32_t* omega_sm,
-                       uint64_t seed, int mu_rule, int prec, float* U_out, float* sigma_mu, float* train_max,
-                       float* T_ex_out, int32_t* info, double* objective, int32_t* passes_used, void* ws,
-                       hipStream_t s, const std::function<rpt_status(int, int)>& at_step) {
+                       uint64_t seed, int mu_rule, int prec, const TrackOpts& opt, float* U_out, float* sigma_mu,
+                       float* train_max, float* T_ex_out, int32_t* info, double* objective, int32_t* passes_used,
+                       void* ws, hipStream_t s, const std::function<rpt_status(int, int)>& at_step) {
   TrainWs t = train_carve(ws, v, n, n1, ell, r, k, prec, nullptr);
   float* T = T_ex_out ? T_ex_out : t.T;
   RPT_TRY(grouse_init_launch(t.g, passes_used, objective, passes, s));
@@ -292,7 +307,7 @@ rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r,
     for (int pp = 0; pp < passes; ++pp) {
       if (at_step) RPT_TRY(at_step(pp, passes));
       RPT_TRY(grouse_pass_launch(t.g, U_out, v, r, T, v, omega_train + static_cast<int64_t>(pp) * ell * k, k, ell,
-                                 gamma, pp, tol, objective, passes_used, t.info, s));
+                                 gamma, pp, tol, objective, passes_used, t.info, opt, s));
       // span(B) is the tracked subspace: its orthonormal basis starts the next pass
       RPT_TRY(reorth_launch(U_out, v, r, t.g.rinfo, t.reorth_ws, s, nullptr, t.g.stop, pp));
     }
@@ -341,15 +356,16 @@ rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx,
                               const uint8_t* train_labels, int32_t ell, const float* U0, int32_t r,
                               const int32_t* omega_train, int32_t k, int32_t passes, int32_t batch, float gamma,
                               double tol, const int32_t* omega_sm, uint64_t seed, int mu_rule, int prec,
-                              int stat, float* U_out, float* sigma_mu, float* train_max, float* T_ex_out,
-                              int32_t* info, double* objective, int32_t* passes_used, void* ws, size_t ws_bytes,
-                              void* stream) {
+                              int stat, const rpt_tracker* tracker, float* U_out, float* sigma_mu,
+                              float* train_max, float* T_ex_out, int32_t* info, double* objective,
+                              int32_t* passes_used, void* ws, size_t ws_bytes, void* stream) {
+  const TrackOpts opt = track_opts(tracker);
   RPT_TRY(train_check(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, tol,
-                      omega_sm, mu_rule, prec, stat, U_out, sigma_mu, train_max, info));
+                      omega_sm, mu_rule, prec, stat, opt, U_out, sigma_mu, train_max, info));
   if (!ws_ok(ws, ws_bytes, rpt_train_workspace(v, n, ell, r, k, prec))) return RPT_ERR_WORKSPACE;
   return train_run(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, tol, omega_sm,
-                   seed, mu_rule, prec, stat, U_out, sigma_mu, train_max, T_ex_out, info, objective, passes_used, ws,
-                   static_cast<hipStream_t>(stream));
+                   seed, mu_rule, prec, stat, opt, U_out, sigma_mu, train_max, T_ex_out, info, objective,
+                   passes_used, ws, static_cast<hipStream_t>(stream));
 }
 
 // ---------------------------------------------------------------------------
@@ -456,10 +472,12 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
                                const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
                                int32_t batch, float gamma, double tol, const int32_t* omega_sm,
                                const int32_t* omega_rec, uint64_t seed, int mu_rule, int prec, int stat,
-                               float* h_out, float* U_out, float* sigma_mu, int32_t* train_info, int32_t* rec_info,
-                               double* objective, int32_t* passes_used, void* ws, size_t ws_bytes, void* stream) {
+                               const rpt_tracker* tracker, float* h_out, float* U_out, float* sigma_mu,
+                               int32_t* train_info, int32_t* rec_info, double* objective, int32_t* passes_used,
+                               void* ws, size_t ws_bytes, void* stream) {
+  const TrackOpts opt = track_opts(tracker);
   RPT_TRY(train_check(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, tol,
-                      omega_sm, mu_rule, prec, stat, U_out, sigma_mu, h_out, train_info));
+                      omega_sm, mu_rule, prec, stat, opt, U_out, sigma_mu, h_out, train_info));
   RPT_TRY(recover_check(X, v, n, ldx, n1, rec_labels, L_rec, ell, U_out, r, sigma_mu, omega_rec, k, h_out,
                         rec_info, stat));
   const size_t tw = rpt_train_workspace(v, n, ell, r, k, prec);
@@ -468,15 +486,15 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
   const RecoverWs w = recover_carve(static_cast<char*>(ws) + tw, v, n, n1, L_rec, r, k, nullptr, stat);
   // Two chains share the device: the caller's stream computes T_ex (matrix
   // cores, the whole chip) and then the tracking passes (latency-bound, a
-  // single-workgroup Cholesky in every step); the second stream
+  // few dozen workgroups); the second stream
   // orthonormalises the start basis meanwhile and then computes the sampled t
   // of the recovered columns, which need no basis, in one chunk per tracking
   // step, each started as that step's Cholesky is reached.
   SideStream* sd = side_stream(s);
   if (!sd) {
     RPT_TRY(train_run(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, tol,
-                      omega_sm, seed, mu_rule, prec, stat, U_out, sigma_mu, h_out, nullptr, train_info, objective,
-                      passes_used, ws, s));
+                      omega_sm, seed, mu_rule, prec, stat, opt, U_out, sigma_mu, h_out, nullptr, train_info,
+                      objective, passes_used, ws, s));
     if (L_rec == 0) return RPT_OK;
     RPT_TRY(recover_front(w, X, ldx, rec_labels, L_rec, omega_rec, k, s));
     return recover_back(w, v, L_rec, ell, U_out, r, sigma_mu, omega_rec, k, seed, h_out + ell, nullptr, rec_info, s);
@@ -489,8 +507,8 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
   st = stream_wait(sd, sd->mid, sd->st, s);  // the basis is ready for the tracking passes
   if (st_side == RPT_OK && st == RPT_OK && L_rec > 0)
     st_side = prep_launch(w.p, X, ldx, RPT_TAIL_SIGNED, kPrepRows | stat_flags(stat), sd->st);
-  // the sampled t of the recovered columns in one chunk per tracking step,
-  // each released when that step reaches its single-workgroup Cholesky
+  // the sampled t of the recovered columns in one chunk per tracking pass,
+  // each released as that pass starts
   int64_t done = 0;
   const std::function<rpt_status(int, int)> at_step = [&](int j, int steps) -> rpt_status {
     if (st_side != RPT_OK || L_rec == 0) return RPT_OK;
@@ -502,7 +520,8 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
   };
   if (st_main == RPT_OK && st_side == RPT_OK && st == RPT_OK)
     st_main = train_track(v, n, n1, ell, r, omega_train, k, passes, batch, gamma, tol, omega_sm, seed, mu_rule,
-                          prec, U_out, sigma_mu, h_out, nullptr, train_info, objective, passes_used, ws, s, at_step);
+                          prec, opt, U_out, sigma_mu, h_out, nullptr, train_info, objective, passes_used, ws, s,
+                          at_step);
   if (st_side == RPT_OK && done < L_rec)  // no tracking steps: all columns now
     st_side = recover_sampled(w, rec_labels, n, done, L_rec, omega_rec, k, sd->st);
   const rpt_status st_join = stream_wait(sd, sd->join, sd->st, s);

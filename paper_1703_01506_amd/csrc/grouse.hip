@@ -91,6 +91,7 @@ struct GrouseVec {
   double uu[kGR];  // u = N^T wh
   double mw[kGR];   // N^{-1} wh
   double mv[2][kGR];  // M w of the conjugate-gradient iterations
+  double gv[kGR];     // right-hand side of the l1 fit's solves
   double cgr[2][kGWaves][2];
   double red[4][kGWaves];
   double nrm[2][kGWaves];  // per-wave |N|_F^2 and |N^{-1}|_F^2
@@ -192,12 +193,13 @@ __device__ __forceinline__ void gram_products(f32x4 (&acc)[gram_ntw(RB, TG)], co
 // fallen by kCgTol^2.  H is held in registers in the matrix layout (lane (rq, cb) of
 // wave w: rows rbase .. rbase + 7, columns 8 cb .. 8 cb + 7; after a
 // reduce-scatter the lane holds row myrow, owned by the even lane of its
-// pair).  On return sv.zv and sv.zf hold z (zero from r on); the result is 0,
-// 1 (a non-positive diagonal or curvature) or 2 (iteration cap).  Ends with
-// a barrier.
-template <int HLD>
+// pair).  The right-hand side is row r of H, or with WARM the vector bvec
+// (FP64, in LDS) and the iteration starts from the z in sv.zv.  On return sv.zv and
+// sv.zf hold z (zero from r on); the result is 0, 1 (a non-positive diagonal
+// or curvature) or 2 (iteration cap).  Ends with a barrier.
+template <int HLD, bool WARM>
 __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, int lane, int wave, int rbase, int cb,
-                                         int myrow, bool owner, bool rowok) {
+                                         int myrow, bool owner, bool rowok, const double* bvec) {
   constexpr int hld = HLD;
   double h[8][8];
 #pragma unroll
@@ -210,7 +212,7 @@ __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, i
       h[ii][j] = (rr < r && cc < r) ? static_cast<double>(hv) : 0.0;
     }
   const int rowc = rowok ? myrow : 0;
-  const double bq = rowok ? static_cast<double>(H[r * hld + rowc]) : 0.0;
+  const double bq = rowok ? (WARM ? bvec[rowc] : static_cast<double>(H[r * hld + rowc])) : 0.0;
   const double dg = rowok ? static_cast<double>(H[rowc * hld + rowc]) : 1.0;
   const double di = dg > 0.0 ? 1.0 / dg : 0.0;
   const bool cnt = owner && rowok;
@@ -231,15 +233,22 @@ __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, i
     }
     return row16_reduce_scatter8(ap, cb);
   };
-  // x_0 = 0, r_0 = b, u_0 = M r_0, w_0 = H u_0
-  double xr = 0.0, rr_ = bq, ur = di * bq;
+  // x_0 = 0 (or the previous solution in sv.zv), r_0 = b - H x_0,
+  // u_0 = M r_0, w_0 = H u_0
+  double xr = 0.0, rr_ = bq;
+  if (WARM) {
+    const double hx = hprod(sv.zv);
+    xr = rowok ? sv.zv[myrow] : 0.0;
+    rr_ = rowok ? bq - hx : 0.0;
+  }
+  double ur = di * rr_;
   const double pb = wave_sum_dpp(cnt ? bq * di * bq : 0.0);  // (r_0, M r_0)
   const bool anybad = __ballot(rowok && !(dg > 0.0)) != 0ull;
   if (lane == 0) {
     sv.red[3][wave] = pb;
     sv.badf[wave] = anybad ? 1 : 0;
   }
-  if (owner) sv.zv[myrow] = ur;  // rows >= r hold 0
+  if (owner) sv.mv[1][myrow] = ur;  // rows >= r hold 0
   __syncthreads();
   double bn2 = 0.0;
   int cg_fail = 0;
@@ -250,7 +259,7 @@ __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, i
   }
   if (bn2 > 0.0 && !cg_fail) {
     const double stop2 = kCgTol * kCgTol * bn2;
-    double wr = hprod(sv.zv);
+    double wr = hprod(sv.mv[1]);
     double zr = 0.0, qr = 0.0, sr = 0.0, pr = 0.0;
     double rcp_gamma_old = 1.0, rcp_alpha_old = 1.0;
     int it = 0;
@@ -305,7 +314,7 @@ __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, i
     }
     if (it == kCgMaxIt) cg_fail = 2;
   }
-  // every read of zv happened before the loop's first barrier
+  // every read of zv and mv[1] happened before the loop's first barrier
   if (owner) {
     sv.zv[myrow] = rowok ? xr : 0.0;
     sv.zf[myrow] = rowok ? static_cast<float>(xr) : 0.0f;
@@ -323,15 +332,20 @@ struct CoopArgs {
   GrouseArgs g;
   float* part;      // [nwg][NT][256]: partial Gram tiles
   float* hred;      // [NT][256]: the summed tiles
-  double* epart;    // [nwg]: partial |e|^2
+  double* epart;    // [2 nwg]: partial |e|^2 (l1: |Gamma|^2 and the misfit)
   uint32_t* ctr;    // [2]: barrier counters of even and odd passes
   int32_t* abort;   // raised when a barrier wait expires
   int nwg;          // workgroups
   int spw;          // slices of 32 sampled rows per workgroup (at most)
+  // robust (l1) tracking
+  float* gpart;     // [nwg][kGR]: partial right-hand sides of the l1 fit's solves
+  float rho;        // ADMM penalty
+  int admm_iters;   // ADMM iterations per column
 };
 
 // dynamic LDS: [GrouseVec][H: 16 RB x hld FP32, later the partial sums of
-// u][rows: 32 spw x rs FP32][voxel, e: 32 spw each][flag]
+// u][rows: 32 spw x rs FP32][voxel, e, and the l1 fit's s, lam, t: 32 spw
+// each][flag]
 __host__ __device__ constexpr int coop_rs(int rb) { return 16 * rb + 2; }
 __host__ __device__ inline size_t coop_lds(int r, int spw) {
   const int rb = g_rb(r);
@@ -341,7 +355,7 @@ __host__ __device__ inline size_t coop_lds(int r, int spw) {
   off += h > up ? h : up;
   off = (off + 15) & ~size_t(15);
   off += static_cast<size_t>(kCoopSlice) * spw * coop_rs(rb) * sizeof(float);
-  off += static_cast<size_t>(2 * kCoopSlice * spw + 4) * sizeof(int);
+  off += static_cast<size_t>(5 * kCoopSlice * spw + 4) * sizeof(int);
   return off;
 }
 
@@ -377,7 +391,7 @@ __device__ __forceinline__ bool coop_barrier(uint32_t* ctr, uint32_t target, int
   return *flag != 0;
 }
 
-template <int RB>
+template <int RB, int MODE>
 __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
   extern __shared__ __align__(16) unsigned char lds[];
   const GrouseArgs& a = ca.g;
@@ -402,7 +416,10 @@ __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
   float* rows = reinterpret_cast<float*>(lds + off);
   int* svox = reinterpret_cast<int*>(rows + kCoopSlice * ca.spw * rs);
   float* se = reinterpret_cast<float*>(svox + kCoopSlice * ca.spw);
-  int* flag = reinterpret_cast<int*>(se + kCoopSlice * ca.spw);
+  float* ss = se + kCoopSlice * ca.spw;   // the l1 fit's s, lam and x - s - lam / rho
+  float* sl = ss + kCoopSlice * ca.spw;
+  float* st = sl + kCoopSlice * ca.spw;
+  int* flag = reinterpret_cast<int*>(st + kCoopSlice * ca.spw);
   uint32_t* ctr = ca.ctr + (a.pass & 1);
   if (wg == 0 && tid == 0) ca.ctr[(a.pass + 1) & 1] = 0;  // the next pass's counter, idle during this one
   uint32_t target = 0;
@@ -633,52 +650,158 @@ __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
     }
     __syncthreads();
     // ---------------------------------------------------------- 4. H z = b (every workgroup)
-    const int cg_fail = grouse_cg<hld>(H, r, sv, lane, wave, rbase, cb, myrow, owner, rowok);
-    // ---------------------------------------------------------- 5. residuals of this slice
-    {
-      float zl[8];
-#pragma unroll
-      for (int hh = 0; hh < 2; ++hh)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int c = 4 * rl + 64 * hh + e;
-          zl[4 * hh + e] = c < r ? sv.zf[c] : 0.0f;
+    int cg_fail = 0;
+    double ee = 0.0;  // |e|^2, or |Gamma|^2 for the l1 fit
+    if (MODE == 0) {
+      // ---------------------------------------------------------- 4. H z = b (every workgroup)
+      cg_fail = grouse_cg<hld, false>(H, r, sv, lane, wave, rbase, cb, myrow, owner, rowok, nullptr);
+      // ---------------------------------------------------------- 5. residuals of this slice
+      {
+        float zl[8];
+  #pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+  #pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            const int c = 4 * rl + 64 * hh + e;
+            zl[4 * hh + e] = c < r ? sv.zf[c] : 0.0f;
+          }
+        double ee = 0.0;
+  #pragma unroll 1
+        for (int lq = rg; lq < kCoopSlice * nsl; lq += 16) {
+          const int q = lq;
+          const float* lr = rows + q * rs;
+          float t = 0.0f;
+  #pragma unroll
+          for (int hh = 0; hh < 2; ++hh)
+  #pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int c = 4 * rl + 64 * hh + e;
+              t = fmaf(lr[min(c, 16 * RB - 1)], zl[4 * hh + e], t);  // zl is zero from r on
+            }
+          const float d = row16_sum_f(t);
+          if (rl == 0) {
+            const float e = svox[q] >= 0 ? lr[r] - d : 0.0f;
+            se[q] = e;
+            ee += static_cast<double>(e) * e;
+          }
         }
-      double ee = 0.0;
+        ee = wave_sum_dpp(ee);
+        if (lane == 0) sv.red[3][wave] = ee;
+        __syncthreads();
+        if (tid == 0) {
+          double t = 0.0;
+  #pragma unroll
+          for (int w = 0; w < kGWaves; ++w) t += sv.red[3][w];
+          ca.epart[wg] = t;
+        }
+      }
+      target += nwg;
+      if (!(alive = coop_barrier(ctr, target, ca.abort, flag))) break;
+      for (int p = 0; p < nwg; ++p) ee += ca.epart[p];
+      obj += ee;
+    } else {
+      // ---------------------------------------------------------- 4'. the l1 fit (ADMM)
+      // On this workgroup's rows x_q (column r of the row cache), s_q and
+      // lam_q; every iteration solves H z = B_O^T (x - s - lam / rho) (the
+      // right-hand side summed over the workgroups, the solve warm-started),
+      // then s <- shrink(x - B_O z - lam / rho, 1 / rho), lam <- lam +
+      // rho (B_O z + s - x).  A final solve gives the z whose gradient Gamma
+      // = lam + rho (B_O z + s - x) is orthogonal to the basis.
+      const float rho = ca.rho, irho = 1.0f / ca.rho;
+      const int K = ca.admm_iters, nrow = kCoopSlice * nsl;
+      for (int q = tid; q < nrow; q += kGT) {
+        ss[q] = 0.0f;
+        sl[q] = 0.0f;
+      }
+      if (tid < kGR) sv.zv[tid] = 0.0;
+      __syncthreads();
+      double gg = 0.0, mis = 0.0;
 #pragma unroll 1
-      for (int lq = rg; lq < kCoopSlice * nsl; lq += 16) {
-        const int q = lq;
-        const float* lr = rows + q * rs;
-        float t = 0.0f;
+      for (int it = 0; it <= K; ++it) {
+        for (int q = tid; q < nrow; q += kGT) st[q] = svox[q] >= 0 ? rows[q * rs + r] - ss[q] - sl[q] * irho : 0.0f;
+        __syncthreads();
+        if (tid < kGR) {
+          float g = 0.0f;
+          if (tid < r)
+            for (int q = 0; q < nrow; ++q) g = fmaf(rows[q * rs + tid], st[q], g);
+          ca.gpart[wg * kGR + tid] = g;
+        }
+        target += nwg;
+        if (!(alive = coop_barrier(ctr, target, ca.abort, flag))) break;
+        if (tid < kGR) {
+          double g = 0.0;
+          for (int p = 0; p < nwg; ++p) g += ca.gpart[p * kGR + tid];
+          sv.gv[tid] = tid < r ? g : 0.0;
+        }
+        __syncthreads();
+        cg_fail |= grouse_cg<hld, true>(H, r, sv, lane, wave, rbase, cb, myrow, owner, rowok, sv.gv);
+        float zl[8];
 #pragma unroll
         for (int hh = 0; hh < 2; ++hh)
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             const int c = 4 * rl + 64 * hh + e;
-            t = fmaf(lr[min(c, 16 * RB - 1)], zl[4 * hh + e], t);  // zl is zero from r on
+            zl[4 * hh + e] = c < r ? sv.zf[c] : 0.0f;
           }
-        const float d = row16_sum_f(t);
-        if (rl == 0) {
-          const float e = svox[q] >= 0 ? lr[r] - d : 0.0f;
-          se[q] = e;
-          ee += static_cast<double>(e) * e;
+#pragma unroll 1
+        for (int q = rg; q < nrow; q += 16) {
+          const float* lr = rows + q * rs;
+          float t = 0.0f;
+#pragma unroll
+          for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+              const int c = 4 * rl + 64 * hh + e;
+              t = fmaf(lr[min(c, 16 * RB - 1)], zl[4 * hh + e], t);  // zl is zero from r on
+            }
+          const float f = row16_sum_f(t);
+          if (rl == 0) {
+            const bool ok = svox[q] >= 0;
+            const float xq = lr[r];
+            if (it < K) {
+              if (ok) {
+                const float d = xq - f - sl[q] * irho;
+                const float sq = copysignf(fmaxf(fabsf(d) - irho, 0.0f), d);
+                ss[q] = sq;
+                sl[q] = fmaf(rho, f + sq - xq, sl[q]);
+              }
+            } else {
+              const float g = ok ? fmaf(rho, f + ss[q] - xq, sl[q]) : 0.0f;
+              se[q] = -g;  // the step moves along -Gamma
+              gg += static_cast<double>(g) * g;
+              mis += ok ? fabs(static_cast<double>(xq) - f) : 0.0;
+            }
+          }
         }
+        __syncthreads();
       }
-      ee = wave_sum_dpp(ee);
-      if (lane == 0) sv.red[3][wave] = ee;
+      if (!alive) break;
+      gg = wave_sum_dpp(gg);
+      mis = wave_sum_dpp(mis);
+      if (lane == 0) {
+        sv.red[2][wave] = gg;
+        sv.red[3][wave] = mis;
+      }
       __syncthreads();
       if (tid == 0) {
-        double t = 0.0;
+        double a2 = 0.0, a3 = 0.0;
 #pragma unroll
-        for (int w = 0; w < kGWaves; ++w) t += sv.red[3][w];
-        ca.epart[wg] = t;
+        for (int w = 0; w < kGWaves; ++w) {
+          a2 += sv.red[2][w];
+          a3 += sv.red[3][w];
+        }
+        ca.epart[2 * wg] = a2;
+        ca.epart[2 * wg + 1] = a3;
       }
+      target += nwg;
+      if (!(alive = coop_barrier(ctr, target, ca.abort, flag))) break;
+      double misfit = 0.0;
+      for (int p = 0; p < nwg; ++p) {
+        ee += ca.epart[2 * p];
+        misfit += ca.epart[2 * p + 1];
+      }
+      obj += misfit;
     }
-    target += nwg;
-    if (!(alive = coop_barrier(ctr, target, ca.abort, flag))) break;
-    double ee = 0.0;
-    for (int p = 0; p < nwg; ++p) ee += ca.epart[p];
-    obj += ee;
     // ---------------------------------------------------------- 6. w = N z, the angle
     {
       double zc[8], wp[8];
@@ -704,7 +827,12 @@ __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
     const double ne = sqrt(ee);
     double cth = 1.0, sth = 0.0;
     if (nw > 0.0 && ne > 0.0 && !cg_fail) {
-      if (a.gamma == 1.0f) {
+      if (MODE == 1) {
+        // the geodesic step along -Gamma w^T: angle eta |Gamma| |w|
+        const double th = fmin(static_cast<double>(a.gamma) * ne * nw, 0.5 * M_PI);
+        cth = cos(th);
+        sth = sin(th);
+      } else if (a.gamma == 1.0f) {
         const double hyp = sqrt(nw2 + ee);
         cth = nw / hyp;
         sth = ne / hyp;
@@ -853,17 +981,21 @@ __global__ void grouse_init_kernel(int32_t* stop, int32_t* used, double* objr, d
     for (int p = threadIdx.x; p < passes; p += blockDim.x) obj_out[p] = 0.0;
 }
 
-template <int RB>
-rpt_status launch_coop(const CoopArgs& ca, size_t smem, hipStream_t s) {
+template <int RB, int MODE>
+rpt_status launch_coop_m(const CoopArgs& ca, size_t smem, hipStream_t s) {
   static bool attr = false;
   if (!attr) {
-    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&grouse_coop_kernel<RB>),
+    (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&grouse_coop_kernel<RB, MODE>),
                               hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(kLdsMax));
     attr = true;
   }
-  hipLaunchKernelGGL((grouse_coop_kernel<RB>), dim3(ca.nwg), dim3(kGT), smem, s, ca);
+  hipLaunchKernelGGL((grouse_coop_kernel<RB, MODE>), dim3(ca.nwg), dim3(kGT), smem, s, ca);
   RPT_CHECK_LAUNCH();
   return RPT_OK;
+}
+template <int RB>
+rpt_status launch_coop(const CoopArgs& ca, int mode, size_t smem, hipStream_t s) {
+  return mode == 1 ? launch_coop_m<RB, 1>(ca, smem, s) : launch_coop_m<RB, 0>(ca, smem, s);
 }
 
 }  // namespace
@@ -874,7 +1006,8 @@ size_t grouse_bytes(int r, int k) {
   const size_t nt = static_cast<size_t>(g_rb(r)) * (g_rb(r) + 1) / 2;
   c.take<float>(static_cast<size_t>(kCoopMaxWg) * nt * 256);
   c.take<float>(nt * 256);
-  c.take<double>(kCoopMaxWg);
+  c.take<double>(2 * kCoopMaxWg);
+  c.take<float>(static_cast<size_t>(kCoopMaxWg) * kGR);
   c.take<double>(2);
   c.take<int32_t>(3);
   c.take<uint32_t>(2);
@@ -889,7 +1022,8 @@ GrouseState grouse_carve(void* ws, int r, int k) {
   const size_t nt = static_cast<size_t>(g_rb(r)) * (g_rb(r) + 1) / 2;
   g.part = c.take<float>(static_cast<size_t>(kCoopMaxWg) * nt * 256);
   g.hred = c.take<float>(nt * 256);
-  g.epart = c.take<double>(kCoopMaxWg);
+  g.epart = c.take<double>(2 * kCoopMaxWg);
+  g.gpart = c.take<float>(static_cast<size_t>(kCoopMaxWg) * kGR);
   g.objr = c.take<double>(2);
   int32_t* flags = c.take<int32_t>(3);
   g.stop = flags;
@@ -909,9 +1043,13 @@ rpt_status grouse_init_launch(const GrouseState& g, int32_t* used, double* obj_o
 
 rpt_status grouse_pass_launch(const GrouseState& g, float* B, int64_t v, int r, const float* T, int64_t ldT,
                               const int32_t* omega, int k, int ell, float gamma, int pass, double tol,
-                              double* obj_out, int32_t* used, int32_t* info, hipStream_t s) {
+                              double* obj_out, int32_t* used, int32_t* info, const TrackOpts& opt, hipStream_t s) {
   if (r < 1 || r > kGR || k < 1) return RPT_ERR_UNSUPPORTED;
+  const int mode = opt.mode == RPT_TRACK_L1 ? 1 : 0;
   CoopArgs ca;
+  ca.gpart = g.gpart;
+  ca.rho = opt.rho;
+  ca.admm_iters = opt.admm_iters;
   GrouseArgs& a = ca.g;
   a.B = B;
   a.v = v;
@@ -943,15 +1081,15 @@ rpt_status grouse_pass_launch(const GrouseState& g, float* B, int64_t v, int r, 
   if (smem > kLdsMax) return RPT_ERR_UNSUPPORTED;
   RPT_STAGE("track_grouse", s);
   switch (g_rb(r)) {
-    case 1: return launch_coop<1>(ca, smem, s);
-    case 2: return launch_coop<2>(ca, smem, s);
-    case 3: return launch_coop<3>(ca, smem, s);
-    case 4: return launch_coop<4>(ca, smem, s);
-    case 5: return launch_coop<5>(ca, smem, s);
-    case 6: return launch_coop<6>(ca, smem, s);
-    case 7: return launch_coop<7>(ca, smem, s);
-    case 8: return launch_coop<8>(ca, smem, s);
-    default: return launch_coop<9>(ca, smem, s);
+    case 1: return launch_coop<1>(ca, mode, smem, s);
+    case 2: return launch_coop<2>(ca, mode, smem, s);
+    case 3: return launch_coop<3>(ca, mode, smem, s);
+    case 4: return launch_coop<4>(ca, mode, smem, s);
+    case 5: return launch_coop<5>(ca, mode, smem, s);
+    case 6: return launch_coop<6>(ca, mode, smem, s);
+    case 7: return launch_coop<7>(ca, mode, smem, s);
+    case 8: return launch_coop<8>(ca, mode, smem, s);
+    default: return launch_coop<9>(ca, mode, smem, s);
   }
 }
 

@@ -294,14 +294,16 @@ rpt_status mu_launch(const float* vals, int n, int rule, float* sigma_mu, hipStr
 rpt_status literal_resid_launch(const float* T, const float* U, const float* W, int64_t v, int r, int64_t ell,
                                 float* out, hipStream_t s);
 
-// Sequential GROUSE tracking (grouse.hip): the basis factor B (in place, v x
-// r) and the r x r factor M of U = B M, its inverse, the sampled values /
-// residuals of the current column, the objectives of the last two passes and
-// the convergence flags.
+// Column-by-column subspace tracking (grouse.hip): the basis factor B of
+// U = B N^{-1} is updated in place; the workspace holds the cooperative
+// pass's partial Gram tiles, their sums, the partial residual norms and
+// right-hand sides, the grid-barrier counters, the objectives of the last
+// two passes and the convergence flags.
 struct GrouseState {
   float* part = nullptr;     // partial Gram tiles of the cooperative pass
   float* hred = nullptr;     // their sums
   double* epart = nullptr;   // partial |e|^2
+  float* gpart = nullptr;    // partial right-hand sides of the l1 fit
   uint32_t* ctr = nullptr;   // grid-barrier counters [2]
   int32_t* abort = nullptr;  // raised when a grid-barrier wait expires
   double* objr = nullptr;
@@ -314,12 +316,20 @@ GrouseState grouse_carve(void* ws, int r, int k);
 // stop <- none, passes used <- 0 (used: caller's device int, or the workspace's),
 // obj_out[0 .. passes) <- 0 when given
 rpt_status grouse_init_launch(const GrouseState& g, int32_t* used, double* obj_out, int passes, hipStream_t s);
-// One pass of GROUSE steps over the ell training columns (rows of T, leading
-// dimension ldT) with this pass's sampled sets (ell x k), then B <- B M.
+// The tracker: GROUSE (mode RPT_TRACK_GROUSE) or the robust l1 fit with
+// the ADMM penalty rho and admm_iters iterations per column (RPT_TRACK_L1).
+struct TrackOpts {
+  int mode = RPT_TRACK_GROUSE;
+  float rho = 1.0f;
+  int admm_iters = 30;
+};
+// One pass of tracking steps over the ell training columns (rows of T,
+// leading dimension ldT) with this pass's sampled sets (ell x k); B ends as
+// a basis factor of the tracked subspace (the caller orthonormalises it).
 // Skipped on the device once an earlier pass met the stopping rule.
 rpt_status grouse_pass_launch(const GrouseState& g, float* B, int64_t v, int r, const float* T, int64_t ldT,
                               const int32_t* omega, int k, int ell, float gamma, int pass, double tol,
-                              double* obj_out, int32_t* used, int32_t* info, hipStream_t s);
+                              double* obj_out, int32_t* used, int32_t* info, const TrackOpts& opt, hipStream_t s);
 
 // Masked loss (masked_loss.hip).
 rpt_status loss_fwd_launch(const float* U, int64_t v, int r, const float* W, int B, const int64_t* ptr, const int32_t* idx,

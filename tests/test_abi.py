@@ -108,9 +108,10 @@ def test_rapidpt_end_to_end_validation(lib):
     assert need >= lib.rpt_train_workspace(v, n, ell, r, k, prec) + lib.rpt_recover_workspace(v, n, L_rec, r, k)
     ws = C.c_void_p(512)
 
-    def call(n1=10, r_=r, k_=k, ws_bytes=need, batch=ell, passes=2, gamma=1.0, tol=0.0, stat=0):
+    def call(n1=10, r_=r, k_=k, ws_bytes=need, batch=ell, passes=2, gamma=1.0, tol=0.0, stat=0, tracker=None):
+        tr = C.byref(tracker) if tracker is not None else None
         return lib.rpt_rapidpt_maxnull(d, v, n, n, n1, d, ell, d, L_rec, d, r_, d, k_, passes, batch, gamma, tol, d,
-                                       d, 7, 0, prec, stat, d, d, d, d, d, d, d, ws, ws_bytes, None)
+                                       d, 7, 0, prec, stat, tr, d, d, d, d, d, d, d, ws, ws_bytes, None)
 
     assert call(ws_bytes=need - 1) == -4      # workspace
     assert call(n1=9) == -6                    # unbalanced designs are not provided
@@ -121,6 +122,12 @@ def test_rapidpt_end_to_end_validation(lib):
     assert call(tol=-1.0) == -1                # negative stopping tolerance
     assert call(batch=2, tol=1e-3) == -6       # the stopping rule belongs to column-by-column tracking
     assert call(stat=2) == -1                  # no such statistic
+    from paper_1703_01506_amd._lib import RptTracker as T
+    assert call(tracker=T(2, 1.0, 30)) == -1               # no such tracker
+    assert call(batch=1, tracker=T(1, 0.0, 30)) == -1      # ADMM penalty must be positive
+    assert call(batch=1, tracker=T(1, 1.0, 0)) == -1       # at least one ADMM iteration
+    assert call(batch=2, tracker=T(1, 1.0, 30)) == -6      # the l1 fit moves U one column at a time
+    assert call(batch=1, gamma=2.0, tracker=T(1, 1.0, 30), ws_bytes=need - 1) == -4  # gamma is its step size
 
 
 def test_autotune_table_roundtrip(lib, tmp_path):

@@ -264,6 +264,33 @@ def test_train_grouse_shapes_match_oracle(v, r, k):
     assert abs(sigma - so) <= 1e-3 * so
 
 
+@pytest.mark.parametrize("n,v,r,k,eta", [(20, 3001, 12, 150, 1e-3), (60, 6001, 40, 700, 2e-4)])
+def test_train_l1_tracker_matches_oracle(n, v, r, k, eta):
+    """Robust tracking (GRASTA, the l1 tracker Sec. 3.1 and 4.1 cite beside
+    GROUSE): 30 ADMM iterations per column, two passes, against the oracle on
+    the training columns the GPU computed.  Basis, pass objectives (l1
+    misfits) and sigma."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce(f"train l1 tracker n={n} v={v} r={r} k={k}")
+    passes, seed = 2, 2017
+    X, tl, U0, omt, oms = _train_inputs(n=n, v=v, ell=30, r=r, k=k, passes=passes)
+    out = rpt.train_subspace(_dev(torch, X), _dev(torch, tl), _dev(torch, U0), _dev(torch, omt), _dev(torch, oms),
+                             passes=passes, seed=seed, batch=1, gamma=eta, prec="fp32", return_T=True,
+                             tracker="l1", rho=1.0, admm_iters=30)
+    U = out["U"].cpu().numpy().astype(np.float64)
+    T_ex = out["T_ex"].cpu().numpy().astype(np.float64)
+    hist = []
+    Uo = OR.train_subspace_l1(T_ex, U0.astype(np.float64), omt, passes, eta=eta, rho=1.0, iters=30, history=hist)
+    so, _, _ = OR.sigma_mu(T_ex, Uo, oms, seed)
+    sigma = float(out["sigma_mu"][0].item())
+    dP = np.abs(U @ U.T - Uo @ Uo.T).max()
+    np.testing.assert_allclose(U.T @ U, np.eye(r), atol=5e-5)
+    assert dP < 2e-4
+    np.testing.assert_allclose(out["objective"].cpu().numpy(), hist, rtol=1e-3)
+    assert abs(sigma - so) <= 1e-3 * so
+
+
 def test_train_grouse_stopping_rule():
     """Until convergence (Sec. 4.1): with a tolerance, tracking stops after the
     first pass whose objective fell by at most tol from the pass before; the
