@@ -289,6 +289,33 @@ rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx,
                               void* ws, size_t ws_bytes, void* stream);
 
 /* -------------------------------------------------------------------------
+ * sigma and mu of Alg. 2 from held-out columns.  Sec. 4.1 estimates the
+ * residual spread and the shift of the max null from training columns; the
+ * basis was fitted to those columns, so their residuals understate the
+ * residuals of unseen ones.  This call computes h further columns in full
+ * (the relabellings `labels`, as T_ex of rpt_train_subspace: stored t maps
+ * and their exact maxima col_max) and applies the same rules as step 4 of
+ * rpt_train_subspace to them with the given basis: sigma = sample std of the
+ * Complete residuals on the sampled sets omega (h x k), mu by mu_rule (the
+ * mean-gap rule draws its noise on stream RPT_STREAM_TRAINING, columns
+ * 0..h-1).  The result replaces the training call's sigma_mu for recovery.
+ *
+ *   labels    h x n uint8, exactly n1 ones per row                  (in)
+ *   U         v x r FP32 trained basis                              (in)
+ *   omega     h x k int32                                           (in)
+ *   sigma_mu  2 FP32 on the device {sigma, mu}                      (out)
+ *   col_max   h FP32: max_k of each held-out column                 (out)
+ *   info      h int32 (as rpt_complete)                             (out)
+ * Requirements: as rpt_train_subspace (balanced designs; r <= k).
+ * ------------------------------------------------------------------------- */
+size_t rpt_sigma_mu_workspace(int64_t v, int32_t n, int32_t h, int32_t r, int32_t k, int prec);
+rpt_status rpt_sigma_mu(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
+                        const uint8_t* labels, int32_t h, const float* U, int32_t r,
+                        const int32_t* omega, int32_t k, uint64_t seed, int mu_rule, int prec, int stat,
+                        float* sigma_mu, float* col_max, int32_t* info,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
  * Recovery -- the RECOVERY half of Alg. 2 (Sec. 4.2).
  *
  * For each recovered column j (global column index col0 + j): t at the sampled

@@ -28,6 +28,7 @@ from .api import (  # noqa: F401
     rejection_counts,
     reorth,
     sampled_tstat,
+    sigma_mu_heldout,
     train_subspace,
 )
 from .autograd import MaskedSubspaceLoss, masked_subspace_loss  # noqa: F401
@@ -35,7 +36,7 @@ from .autograd import MaskedSubspaceLoss, masked_subspace_loss  # noqa: F401
 _lib.load()
 
 __all__ = [
-    "naive_maxnull", "sampled_tstat", "complete", "reorth", "train_subspace", "recover_maxnull",
+    "naive_maxnull", "sampled_tstat", "complete", "reorth", "train_subspace", "sigma_mu_heldout", "recover_maxnull",
     "rapidpt_maxnull", "recover_maxnull_batched", "recover_studies_prepare", "recover_studies_launch",
     "observed_tstat", "fwer_threshold", "corrected_pvalues", "rejection_counts", "masked_loss_fwd", "masked_loss_bwd",
     "MaskedSubspaceLoss", "masked_subspace_loss", "autotune_naive", "autotune_recover", "autotune_save",

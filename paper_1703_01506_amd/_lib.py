@@ -50,6 +50,9 @@ SIGNATURES = {
     "rpt_train_subspace": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i32, _p, _i32, _p, _i32, _i32, _i32, _f32,
                                   C.c_double, _p, _u64, _int, _int, _int, C.POINTER(RptTracker), _p, _p, _p, _p,
                                   _p, _p, _p, _p, _sz, _p]),
+    "rpt_sigma_mu_workspace": (_sz, [_i64, _i32, _i32, _i32, _i32, _int]),
+    "rpt_sigma_mu": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i32, _p, _i32, _p, _i32, _u64, _int, _int, _int, _p,
+                            _p, _p, _p, _sz, _p]),
     "rpt_recover_workspace": (_sz, [_i64, _i32, _i64, _i32, _i32]),
     "rpt_autotune_naive": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i64, _int, _p, _i32, _p, _sz, _p, _p]),
     "rpt_autotune_recover_workspace": (_sz, [_i64, _i32, _i64]),

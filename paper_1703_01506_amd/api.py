@@ -179,6 +179,31 @@ def train_subspace(X, train_labels, U0, omega_train, omega_sm, passes: int, seed
     return out
 
 
+def sigma_mu_heldout(X, labels, U, omega, seed: int, mu_rule: str = "mean_gap", prec: str = "split_bf16",
+                     stat: str = "t"):
+    """sigma and mu for the basis U from h held-out relabellings (labels h x n,
+    fully computed) and their sampled sets omega (h x k).  Returns
+    (sigma_mu (2,), col_max (h,), info (h,))."""
+    lib = _lib.load()
+    v, n, ldx = _data(X)
+    labels = _dev(labels, torch.uint8, "labels", 2).contiguous()
+    U = _dev(U, torch.float32, "U", 2).contiguous()
+    omega = _dev(omega, torch.int32, "omega", 2).contiguous()
+    h, r, k = labels.shape[0], U.shape[1], omega.shape[1]
+    if omega.shape[0] != h or U.shape[0] != v:
+        raise ValueError("inconsistent shapes")
+    dev = X.device
+    sm = torch.empty(2, dtype=torch.float32, device=dev)
+    cmax = torch.empty(h, dtype=torch.float32, device=dev)
+    info = torch.empty(h, dtype=torch.int32, device=dev)
+    ws = _workspace(lib.rpt_sigma_mu_workspace(v, n, h, r, k, PREC[prec]), dev)
+    rc = lib.rpt_sigma_mu(_ptr(X), v, n, ldx, n // 2, _ptr(labels), h, _ptr(U), r, _ptr(omega), k, int(seed),
+                          MU_RULE[mu_rule], PREC[prec], STAT[stat], _ptr(sm), _ptr(cmax), _ptr(info), _ptr(ws),
+                          ws.numel(), _stream(dev))
+    _lib.check(rc, "rpt_sigma_mu")
+    return sm, cmax, info
+
+
 def recover_maxnull(X, labels, U, sigma_mu, omega, seed: int, col0: int = 0, n1: int | None = None,
                     return_W: bool = False, stat: str = "t", omega_ptr=None):
     """Recovery half of Alg. 2.  omega is (L, k) int32, or with omega_ptr (L + 1

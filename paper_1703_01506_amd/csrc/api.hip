@@ -253,6 +253,10 @@ rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r,
                        float* train_max, float* T_ex_out, int32_t* info, double* objective, int32_t* passes_used,
                        void* ws, hipStream_t s, const std::function<rpt_status(int, int)>& at_step = nullptr);
 
+rpt_status sigma_mu_run(const TrainWs& t, const float* U, int64_t v, int32_t r, const int32_t* omega, int32_t k,
+                        const float* T, int32_t ell, const float* col_max, uint64_t seed, int mu_rule,
+                        float* sigma_mu, int32_t* info, hipStream_t s);
+
 rpt_status train_run(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* train_labels,
                      int32_t ell, const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
                      int32_t batch, float gamma, double tol, const int32_t* omega_sm, uint64_t seed, int mu_rule,
@@ -331,16 +335,22 @@ rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r,
       ++step;
     }
   }
-  // 4. sigma from fresh sampled sets with the final U
-  RPT_TRY(complete_run(U_out, v, r, omega_sm, k, nullptr, T, v, nullptr, ell, t.W, t.resid, info, t.wnorm2, s));
+  return sigma_mu_run(t, U_out, v, r, omega_sm, k, T, ell, train_max, seed, mu_rule, sigma_mu, info, s);
+}
+
+// 4. sigma from fresh sampled sets of the columns T (ell x v, exact maxima
+// col_max) with the basis U; 5. mu
+rpt_status sigma_mu_run(const TrainWs& t, const float* U, int64_t v, int32_t r, const int32_t* omega, int32_t k,
+                        const float* T, int32_t ell, const float* col_max, uint64_t seed, int mu_rule,
+                        float* sigma_mu, int32_t* info, hipStream_t s) {
+  RPT_TRY(complete_run(U, v, r, omega, k, nullptr, T, v, nullptr, ell, t.W, t.resid, info, t.wnorm2, s));
   RPT_TRY(sigma_launch(t.resid, static_cast<int64_t>(ell) * k, t.sums, sigma_mu, s));
-  // 5. mu
   if (mu_rule == RPT_MU_MEAN_GAP) {
-    RPT_TRY(recon_launch(U_out, v, r, t.W, ell, 0, seed, RPT_STREAM_TRAINING, sigma_mu, nullptr, train_max, t.gap,
+    RPT_TRY(recon_launch(U, v, r, t.W, ell, 0, seed, RPT_STREAM_TRAINING, sigma_mu, nullptr, col_max, t.gap,
                          t.recon_ws, s));
     RPT_TRY(mu_launch(t.gap, ell, mu_rule, sigma_mu, s));
   } else if (mu_rule == RPT_MU_LITERAL) {
-    RPT_TRY(literal_resid_launch(T, U_out, t.W, v, r, ell, t.gap, s));
+    RPT_TRY(literal_resid_launch(T, U, t.W, v, r, ell, t.gap, s));
     RPT_TRY(mu_launch(t.gap, ell, mu_rule, sigma_mu, s));
   } else {
     RPT_TRY(mu_launch(t.gap, 0, mu_rule, sigma_mu, s));
@@ -366,6 +376,32 @@ rpt_status rpt_train_subspace(const float* X, int64_t v, int32_t n, int64_t ldx,
   return train_run(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, tol, omega_sm,
                    seed, mu_rule, prec, stat, opt, U_out, sigma_mu, train_max, T_ex_out, info, objective,
                    passes_used, ws, static_cast<hipStream_t>(stream));
+}
+
+size_t rpt_sigma_mu_workspace(int64_t v, int32_t n, int32_t h, int32_t r, int32_t k, int prec) {
+  return rpt_train_workspace(v, n, h, r, k, prec);
+}
+
+rpt_status rpt_sigma_mu(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1, const uint8_t* labels,
+                        int32_t h, const float* U, int32_t r, const int32_t* omega, int32_t k, uint64_t seed,
+                        int mu_rule, int prec, int stat, float* sigma_mu, float* col_max, int32_t* info, void* ws,
+                        size_t ws_bytes, void* stream) {
+  if (stat != RPT_STAT_T && stat != RPT_STAT_MEANDIFF) return RPT_ERR_INVALID_ARG;
+  if (!design_ok(v, n, ldx, n1) || 2 * n1 != n) return design_ok(v, n, ldx, n1) ? RPT_ERR_UNSUPPORTED
+                                                                               : RPT_ERR_INVALID_ARG;
+  if (h < 1 || r < 1 || r > 128 || r > v || k < 1 || k > v || static_cast<int64_t>(h) * k > INT32_MAX)
+    return RPT_ERR_INVALID_ARG;
+  if (k < r) return RPT_ERR_UNDERDETERMINED;
+  if (mu_rule != RPT_MU_MEAN_GAP && mu_rule != RPT_MU_LITERAL && mu_rule != RPT_MU_ZERO) return RPT_ERR_INVALID_ARG;
+  if (prec != RPT_FP32 && prec != RPT_SPLIT_BF16) return RPT_ERR_INVALID_ARG;
+  if (!X || !labels || !U || !omega || !sigma_mu || !col_max || !info) return RPT_ERR_INVALID_ARG;
+  if (!ws_ok(ws, ws_bytes, rpt_sigma_mu_workspace(v, n, h, r, k, prec))) return RPT_ERR_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // the held-out columns as T_ex of the training call (stored t maps and
+  // their exact maxima), then the same sigma and mu rules
+  RPT_TRY(train_tex(X, v, n, ldx, n1, labels, h, r, k, prec, stat, col_max, nullptr, ws, s));
+  const TrainWs t = train_carve(ws, v, n, n1, h, r, k, prec, nullptr, stat);
+  return sigma_mu_run(t, U, v, r, omega, k, t.T, h, col_max, seed, mu_rule, sigma_mu, info, s);
 }
 
 // ---------------------------------------------------------------------------

@@ -130,6 +130,27 @@ def test_rapidpt_end_to_end_validation(lib):
     assert call(batch=1, gamma=2.0, tracker=T(1, 1.0, 30), ws_bytes=need - 1) == -4  # gamma is its step size
 
 
+def test_sigma_mu_heldout_validation(lib):
+    """rpt_sigma_mu checks its arguments and workspace before any launch."""
+    d = C.c_void_p(256)
+    v, n, h, r, k, prec = 5000, 20, 25, 8, 40, 1
+    need = lib.rpt_sigma_mu_workspace(v, n, h, r, k, prec)
+    assert need == lib.rpt_train_workspace(v, n, h, r, k, prec)
+    ws = C.c_void_p(512)
+
+    def call(n1=10, h_=h, r_=r, k_=k, mu_rule=0, stat=0, ws_bytes=need):
+        return lib.rpt_sigma_mu(d, v, n, n, n1, d, h_, d, r_, d, k_, 7, mu_rule, prec, stat, d, d, d, ws, ws_bytes,
+                                None)
+
+    assert call(ws_bytes=need - 1) == -4
+    assert call(n1=9) == -6
+    assert call(h_=0) == -1
+    assert call(r_=129) == -1
+    assert call(k_=7) == -2
+    assert call(mu_rule=3) == -1
+    assert call(stat=2) == -1
+
+
 def test_autotune_table_roundtrip(lib, tmp_path):
     """The plan table is plain text and survives a save / load round trip
     (no GPU: entries are written by hand)."""

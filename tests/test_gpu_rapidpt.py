@@ -291,6 +291,32 @@ def test_train_l1_tracker_matches_oracle(n, v, r, k, eta):
     assert abs(sigma - so) <= 1e-3 * so
 
 
+@pytest.mark.parametrize("mu_rule", ["mean_gap", "literal"])
+def test_sigma_mu_heldout_matches_oracle(mu_rule):
+    """sigma and mu from held-out fully computed columns (rpt_sigma_mu): the
+    oracle's sigma_mu rule applied to the held-out t maps with the trained
+    basis; the held-out maxima are exact."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce(f"sigma mu held out {mu_rule}")
+    passes, seed = 2, 2017
+    X, tl, U0, omt, oms = _train_inputs(passes=passes)
+    out = rpt.train_subspace(_dev(torch, X), _dev(torch, tl), _dev(torch, U0), _dev(torch, omt), _dev(torch, oms),
+                             passes=passes, seed=seed, prec="fp32")
+    hl = S.relabellings(25, X.shape[1], X.shape[1] // 2, seed=99)
+    omh = S.omega_sets(25, X.shape[0], oms.shape[1], seed=98)
+    sm, cmax, info = rpt.sigma_mu_heldout(_dev(torch, X), _dev(torch, hl), out["U"], _dev(torch, omh), seed=seed,
+                                          mu_rule=mu_rule, prec="fp32")
+    T_h = OT.tmatrix(X.astype(np.float64), hl)
+    U = out["U"].cpu().numpy().astype(np.float64)
+    so, muo, _ = OR.sigma_mu(T_h, U, omh, seed, mu_rule=mu_rule)
+    assert int((info != 0).sum().item()) == 0
+    assert_t_close(cmax.cpu().numpy(), T_h.max(axis=1), "fp32", "held-out maxima")
+    sigma, mu = [float(x) for x in sm.cpu().numpy()]
+    assert abs(sigma - so) <= 1e-3 * so
+    assert abs(mu - muo) <= 2e-3
+
+
 def test_train_grouse_stopping_rule():
     """Until convergence (Sec. 4.1): with a tolerance, tracking stops after the
     first pass whose objective fell by at most tol from the pass before; the
