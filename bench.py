@@ -39,7 +39,7 @@ PEAK_FP32_TFLOPS = 157.3       # FP32 (vector and matrix)
 TOL = 1e-3                     # stopping tolerance of the tracking passes (Sec. 4.1, until convergence)
 GOLDEN = os.path.join(ROOT, "tests", "golden", "train_full_n100_v250k.txt")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rapidpt_step_n100_v250k_hbm_traffic.md")
-STAGE_KERNEL = {"track_grouse": "grouse_pass_kernel", "complete": "complete_kernel", "complete_gram": "complete_gram_kernel",
+STAGE_KERNEL = {"track_grouse": "grouse_coop_kernel", "complete": "complete_kernel", "complete_gram": "complete_gram_kernel",
                 "complete_solve": "complete_solve_kernel", "recon_fused": "recon_fused_kernel",
                 "naive_contract": "naive_max_kernel", "sampled_t": "sampled_kernel",
                 "track_update": "track_apply_kernel", "reorth_gram": "gram_partial_kernel",
@@ -355,7 +355,7 @@ def main():
     naive_ms = 1e3 * nwall / a.steps
     log(f"naivept {naive_ms:.3f} ms/step")
 
-    rec_only = h2d_ms = naive_fp32 = variant = None
+    rec_only = h2d_ms = naive_fp32 = variant = l1_variant = heldout = None
     if not a.headline_only:
         # the mini-batch tracking variant (not the paper's: all l columns fitted
         # on the same basis, one update and re-orthonormalisation per pass), P
@@ -368,6 +368,34 @@ def main():
                    "unit": "perms/s", "ms_per_step": 1e3 * vwall / a.steps,
                    "sigma": float(trv["sigma_mu"][0].item()), "mu": float(trv["sigma_mu"][1].item())}
         log(f"mini-batch variant {variant['ms_per_step']:.2f} ms/step")
+        # the robust l1 tracker (GRASTA reading) in place of GROUSE, same
+        # passes and stopping rule; one timed call (its ADMM column fits make
+        # it several times slower per visit)
+        l1 = lambda: rpt.rapidpt_maxnull(Xd, Ld[:ell], Ld[ell:], U0d, omtd, omsd, omrd, passes=P, seed=seed,
+                                         tol=TOL, tracker="l1", gamma=1.0, rho=1.0, admm_iters=30)
+        l1()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hl1, trl1, _ = l1()
+        torch.cuda.synchronize()
+        l1_ms = 1e3 * (time.perf_counter() - t0)
+        l1_variant = {"tracking": f"robust l1 fit (ADMM, rho=1, 30 iterations) and geodesic step, eta=1, "
+                                  f"at most {P} passes", "value": L / (l1_ms * 1e-3), "unit": "perms/s",
+                      "ms_per_step": l1_ms, "passes_used": int(trl1["passes_used"].item()),
+                      "sigma": float(trl1["sigma_mu"][0].item()), "mu": float(trl1["sigma_mu"][1].item())}
+        log(f"l1 tracker variant {l1_ms:.2f} ms/step")
+        # sigma and mu from h held-out fully computed relabellings instead of
+        # the training columns (a report after the timed region)
+        hh = 60
+        hl = d(S.relabellings(hh, n, n // 2, seed=1508))
+        hom = d(S.omega_sets(hh, v, k, seed=44))
+        sm_ho, _, _ = rpt.sigma_mu_heldout(Xd, hl, tr["U"], hom, seed + 1)
+        rec_ho, _ = rpt.recover_maxnull(Xd, Ld[ell:], tr["U"], sm_ho, omrd, seed, col0=ell)
+        h_ho = torch.cat([h[:ell], rec_ho])
+        heldout = {"h": hh, "sigma": float(sm_ho[0].item()), "mu": float(sm_ho[1].item()),
+                   "kl_naive_vs_rapid": kl_max_nulls(nv, h_ho),
+                   "threshold_rapid": float(rpt.fwer_threshold(h_ho, 0.05).item())}
+        del hl, hom
         # NaivePT on the FP32 path (FP32 matrix cores, one product per
         # relabelling tile): the precision alternative to the split-BF16 one
         naive32 = lambda: rpt.naive_maxnull(Xd, Ld, prec="fp32")
@@ -431,6 +459,8 @@ def main():
                calibration(rpt, torch, Xd, Ld[:ell], U0d, omtd, omsd, P, seed, tr["U"])}
     if variant is not None:
         variant["kl_naive_vs_rapid"] = kl_max_nulls(nv, hv)
+        l1_variant["kl_naive_vs_rapid"] = kl_max_nulls(nv, hl1)
+        quality["heldout_sigma_mu"] = heldout
     gate = oracle_gate(h, P)
     log(f"quality {json.dumps(quality)} gate {json.dumps(gate)}")
 
@@ -468,6 +498,7 @@ def main():
         "naivept_stages_ms_per_step": {s: round(q[0] / a.steps, 4) for s, q in nstages.items() if q},
         "rapidpt_quality": quality,
         "rapidpt_minibatch_variant": variant,
+        "rapidpt_l1_tracker_variant": l1_variant,
         "autotuned": tuned,
     }
     print(json.dumps(out), flush=True)
@@ -505,8 +536,10 @@ def roofline_for(stage, ms_per_step, launches_per_step, v, n, L, ell, r, k, P):
     if stage == "track_grouse":
         # one launch is one pass of column visits; per visit the k sampled
         # basis rows are read and written once (4r bytes each way) and the k
-        # indices and T values read: the least traffic a step needs.  A
-        # dependent chain on one workgroup, so far below this peak.
+        # indices and T values read: the least traffic a step needs.  Each
+        # visit is a dependent chain (Gram, solve, update) spread over a few
+        # dozen workgroups joined by grid barriers, so latency, not this
+        # peak, bounds it.
         byts = ell * k * (8.0 * r + 8.0)
         ach = byts / avg_s / 1e9
         out.update({"bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
