@@ -10,6 +10,9 @@ Permutation Testing in Voxel-wise Analysis through Subspace Tracking"):
                     SC'11) and the Box-Muller transform, used for the residual
                     noise draw of Alg. 2;
 * ``rapidpt``    -- RapidPT training and recovery (Sec. 4, Alg. 2);
+* ``sampling``   -- relabellings, sampled sets and the start basis drawn from
+                    a seed (Philox words driving a partial Fisher-Yates
+                    shuffle; Alg. 1, Alg. 2);
 * ``masked_loss``-- the masked completion loss of Eq. 1 and its gradient;
 * ``metrics``    -- KL divergence, thresholds, p-values and the resampling
                     risk of Sec. 5.5 (Eq. 4).
