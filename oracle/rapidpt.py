@@ -190,6 +190,58 @@ def train_subspace(T_ex: np.ndarray, U0: np.ndarray, omega_train: np.ndarray,
     return U
 
 
+def gradient_step(U: np.ndarray, T_rows: np.ndarray, sets, alpha: float,
+                  loss: list | None = None) -> np.ndarray:
+    """One step in which the masked loss of Eq. 1 drives U.
+
+    Every batch member b is fitted on the current U (w_b = Complete on its
+    sampled set), giving f(U, W) = 1/2 sum_b |P_Omega_b (t_b - U w_b)|^2; the
+    Euclidean gradient G = df/dU comes from ``masked_loss.grad``, the
+    Riemannian gradient on the Grassmannian is (I - U U^T) G, and U moves
+    along it with step size alpha and is retracted by QR:
+        U <- qr(U - alpha (I - U U^T) G).
+    (With each w_b the exact least-squares fit, U^T G = -sum_b U_O^T e_b w_b^T
+    = 0, so the projection changes nothing but rounding.)  `loss`, when given,
+    receives each member's |e_b|^2 before U moves."""
+    from . import masked_loss as ML
+    B = len(sets)
+    ptr = np.zeros(B + 1, dtype=np.int64)
+    idx, t, W = [], [], np.zeros((U.shape[1], B))
+    for b in range(B):
+        o = np.asarray(sets[b])
+        y = np.asarray(T_rows[b], dtype=np.float64)[o]
+        W[:, b] = complete(U, o, y)
+        if loss is not None:
+            e = y - U[o] @ W[:, b]
+            loss.append(float(e @ e))
+        ptr[b + 1] = ptr[b] + len(o)
+        idx.append(o)
+        t.append(y)
+    idx = np.concatenate(idx) if B else np.zeros(0, dtype=np.int64)
+    t = np.concatenate(t) if B else np.zeros(0)
+    G, _ = ML.grad(U, W, ptr, idx, t)
+    G = G - U @ (U.T @ G)
+    return orthonormalize(U - alpha * G)
+
+
+def train_subspace_gradient(T_ex: np.ndarray, U0: np.ndarray, omega_train: np.ndarray, passes: int,
+                            batch: int, alpha: float, history: list | None = None) -> np.ndarray:
+    """Subspace training driven by the masked loss (``gradient_step``) over
+    mini-batches of `batch` consecutive training columns, `passes` passes
+    (row p l + i of omega_train is column i's set in pass p); `history`
+    receives each pass's objective sum_i |e_i|^2."""
+    ell = T_ex.shape[0]
+    U = orthonormalize(U0)
+    for p in range(passes):
+        loss: list = []
+        for b0 in range(0, ell, batch):
+            b1 = min(ell, b0 + batch)
+            U = gradient_step(U, T_ex[b0:b1], [omega_train[p * ell + i] for i in range(b0, b1)], alpha, loss)
+        if history is not None:
+            history.append(float(np.sum(loss)))
+    return U
+
+
 def principal_angle_cosines(U: np.ndarray, V: np.ndarray) -> np.ndarray:
     """Cosines of the principal angles between span(U) and span(V)
     (orthonormal columns): the singular values of U^T V, descending."""
