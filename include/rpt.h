@@ -81,8 +81,11 @@ typedef enum {
  * and GRASTA).  NULL in the training calls means GROUSE. */
 typedef enum {
   RPT_TRACK_GROUSE = 0, /* l2 fit, geodesic step (the default)                  */
-  RPT_TRACK_L1 = 1      /* robust l1 fit by ADMM, geodesic step along the     */
+  RPT_TRACK_L1 = 1,     /* robust l1 fit by ADMM, geodesic step along the     */
                         /* augmented Lagrangian's gradient (GRASTA)           */
+  RPT_TRACK_GRADIENT = 2 /* the masked loss of Eq. 1 drives U: per batch the  */
+                        /* least-squares fit, the loss's backward dU, the     */
+                        /* step U - gamma dU and a QR retraction              */
 } rpt_track_kind;
 typedef struct {
   int32_t kind;       /* rpt_track_kind                                        */
@@ -254,6 +257,15 @@ rpt_status rpt_complete(const float* U, int64_t v, int32_t r,
  *      by the angle min(gamma |Gamma| |w|, pi/2):
  *      U <- U + ((cos th - 1) U w/|w| - sin th Gamma/|Gamma|) w^T/|w|.
  *      The pass objective is sum_i |t_O - U_O w_i|_1.
+ *    tracker->kind == RPT_TRACK_GRADIENT (any batch; the masked loss
+ *      f(U, W) = 1/2 sum_i |P_O_i (t_i - U w_i)|^2 of Eq. 1 drives U, through
+ *      the same backward as rpt_masked_loss_bwd): per mini-batch every
+ *      column is fitted (w_i = Complete), dU = -sum_i P_O_i(e_i) w_i^T (its
+ *      Riemannian projection (I - U U^T) dU equals dU at the least-squares
+ *      fit), U <- qr(U - gamma dU).  gamma is the step length (scale it
+ *      with the data: the step grows with |e| |w|); all `passes` passes run
+ *      (tol must be 0); the pass objective is sum_i |e_i|^2.  Summation
+ *      into dU uses atomics, so two runs may differ in FP32 rounding.
  * 4. sigma = sample std (N-1) of the Complete residuals of every training
  *    column on a fresh sampled set omega_sm (l x k); mu by `mu_rule`, with the
  *    mean-gap rule drawing the noise on stream RPT_STREAM_TRAINING.
@@ -268,8 +280,9 @@ rpt_status rpt_complete(const float* U, int64_t v, int32_t r,
  *   info         l int32: 0, or (batch 1) -1 / -2 when a column's fit
  *                failed (Gram not positive definite / no convergence) and
  *                U did not move; then the status of the sigma fits  (out)
- *   objective    NULL or passes FP64: each pass's objective (batch 1; 0 for
- *                passes not run, and for batch > 1)                  (out)
+ *   objective    NULL or passes FP64: each pass's objective (batch 1 and
+ *                the gradient tracker; 0 for passes not run, and for the
+ *                batch > 1 variant)                                 (out)
  *   passes_used  NULL or 1 int32: passes run                         (out)
  *   stat         the statistic of T_ex (as rpt_naive_maxnull)
  *   tracker      NULL (GROUSE) or host pointer to an rpt_tracker     (in)
@@ -378,11 +391,23 @@ rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
  *   sigma_mu      2 FP32 on the device {sigma, mu}                      (out)
  *   train_info    l int32;  rec_info  L_rec int32 (as rpt_complete)     (out)
  *   objective, passes_used: as rpt_train_subspace                       (out)
- *   ws            rpt_rapidpt_workspace(v, n, l, L_rec, r, k, prec) bytes
+ *   ws            rpt_rapidpt_workspace(v, n, l, L_rec, r, k, prec) bytes,
+ *                 plus rpt_rapidpt_gen_workspace(n, l, L_rec, k, passes)
+ *                 when any of the labels or sampled sets is NULL
+ * Inputs drawn from the seed: train_labels, rec_labels, U0, omega_train,
+ * omega_sm and omega_rec may each be NULL.  The call then draws them as
+ * rpt_gen_relabellings, rpt_gen_sampled_sets and rpt_gen_start_basis do with
+ * the same seed: relabelling c and the sets of column c of h^L use row c
+ * (training columns 0..l-1, then the recovered ones); the sigma/mu and
+ * recovery sets are set 0 and tracking pass p uses set 1 + p; the labels and
+ * sets go to the workspace after its first rpt_rapidpt_workspace bytes, the
+ * Gaussian start basis straight into U_out.  Drawn sets need k <= 4096
+ * (RPT_ERR_UNSUPPORTED above).
  * Errors: those of rpt_train_subspace and rpt_recover_maxnull, all checked
  * before the first launch.
  * ------------------------------------------------------------------------- */
 size_t rpt_rapidpt_workspace(int64_t v, int32_t n, int32_t ell, int64_t L_rec, int32_t r, int32_t k, int prec);
+size_t rpt_rapidpt_gen_workspace(int32_t n, int32_t ell, int64_t L_rec, int32_t k, int32_t passes);
 rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
                                const uint8_t* train_labels, int32_t ell,
                                const uint8_t* rec_labels, int64_t L_rec,
@@ -395,6 +420,39 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
                                int32_t* train_info, int32_t* rec_info,
                                double* objective, int32_t* passes_used,
                                void* ws, size_t ws_bytes, void* stream);
+
+/* -------------------------------------------------------------------------
+ * Inputs drawn from a seed (Alg. 1 draws Permute[1, n] per relabelling and
+ * gives the first n1 subjects group 1, Sec. 2.1; Alg. 2 samples each Omega
+ * uniformly without replacement, Sec. 4.1 and 4.2, and starts from Rand.
+ * Orth.).  Every draw is a word of Philox4x32-10 (Salmon et al., SC'11) with
+ * key = (seed mod 2^32, seed >> 32) and counter (j >> 2, row, stream, set),
+ * step j taking word j & 3; an index on [0, m) is the high half of the
+ * 64-bit product of the word and m.  A partial Fisher-Yates shuffle of k
+ * steps over 0..m-1 (step j draws t on [j, m) and swaps entries j and t)
+ * chooses the subset.  Rows are independent: any range can be drawn alone.
+ *
+ * rpt_sample_count: |Omega| = ceil(eta v) for eta = eta_ppm / 10^6, in
+ *   integer arithmetic; -1 when v < 0 or eta_ppm is outside [0, 10^6].
+ * rpt_gen_relabellings: rows row0..row0+L-1 (stream 0, set 0), each n uint8
+ *   entries with 1 for the n1 shuffled-in subjects (group 1), to `labels`
+ *   (L x n, device).  2 <= n <= 512, 1 <= n1 < n, row0 + L <= 2^32.
+ * rpt_gen_sampled_sets: rows row0..row0+rows-1 of set `set_id` (stream 1),
+ *   each k distinct voxel indices in [0, v) in ascending order, to `omega`
+ *   (rows x k int32, device).  1 <= k <= v; k above 4096 returns
+ *   RPT_ERR_UNSUPPORTED (the shuffle keeps its displaced entries in LDS).
+ * rpt_gen_start_basis: the v x r FP32 Gaussian matrix (row-major, device)
+ *   whose entry (q, c) is the residual-noise draw of column c at voxel q on
+ *   stream 3 (Box-Muller of words 0, 1 or 2, 3 of the call (q, c >> 2, 3,
+ *   0)); Rand. Orth. of rpt_train_subspace orthonormalises it.
+ * All three validate synchronously, launch on `stream` and never allocate.
+ * ------------------------------------------------------------------------- */
+int64_t rpt_sample_count(int64_t v, int32_t eta_ppm);
+rpt_status rpt_gen_relabellings(uint64_t seed, int64_t row0, int64_t L, int32_t n, int32_t n1, uint8_t* labels,
+                                void* stream);
+rpt_status rpt_gen_sampled_sets(uint64_t seed, int32_t set_id, int64_t row0, int64_t rows, int64_t v, int32_t k,
+                                int32_t* omega, void* stream);
+rpt_status rpt_gen_start_basis(uint64_t seed, int64_t v, int32_t r, float* U, void* stream);
 
 /* -------------------------------------------------------------------------
  * Recovery phase of Alg. 2 for several studies in one call, with uneven

@@ -17,16 +17,21 @@ from .api import (  # noqa: F401
     corrected_pvalues,
     fwer_threshold,
     masked_loss_bwd,
+    gen_relabellings,
+    gen_sampled_sets,
+    gen_start_basis,
     masked_loss_fwd,
     naive_maxnull,
     observed_tstat,
     rapidpt_maxnull,
+    rapidpt_maxnull_seeded,
     recover_maxnull,
     recover_maxnull_batched,
     recover_studies_launch,
     recover_studies_prepare,
     rejection_counts,
     reorth,
+    sample_count,
     sampled_tstat,
     sigma_mu_heldout,
     train_subspace,
@@ -40,5 +45,6 @@ __all__ = [
     "rapidpt_maxnull", "recover_maxnull_batched", "recover_studies_prepare", "recover_studies_launch",
     "observed_tstat", "fwer_threshold", "corrected_pvalues", "rejection_counts", "masked_loss_fwd", "masked_loss_bwd",
     "MaskedSubspaceLoss", "masked_subspace_loss", "autotune_naive", "autotune_recover", "autotune_save",
-    "autotune_load", "autotune_clear", "autotune_count",
+    "autotune_load", "autotune_clear", "autotune_count", "rapidpt_maxnull_seeded", "sample_count",
+    "gen_relabellings", "gen_sampled_sets", "gen_start_basis",
 ]

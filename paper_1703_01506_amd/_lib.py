@@ -62,6 +62,11 @@ SIGNATURES = {
     "rpt_autotune_clear": (None, []),
     "rpt_autotune_count": (_int, []),
     "rpt_rapidpt_workspace": (_sz, [_i64, _i32, _i32, _i64, _i32, _i32, _int]),
+    "rpt_rapidpt_gen_workspace": (_sz, [_i32, _i32, _i64, _i32, _i32]),
+    "rpt_sample_count": (_i64, [_i64, _i32]),
+    "rpt_gen_relabellings": (_int, [_u64, _i64, _i64, _i32, _i32, _p, _p]),
+    "rpt_gen_sampled_sets": (_int, [_u64, _i32, _i64, _i64, _i64, _i32, _p, _p]),
+    "rpt_gen_start_basis": (_int, [_u64, _i64, _i32, _p, _p]),
     "rpt_rapidpt_maxnull": (_int, [_p, _i64, _i32, _i64, _i32, _p, _i32, _p, _i64, _p, _i32, _p, _i32, _i32, _i32,
                                    _f32, C.c_double, _p, _p, _u64, _int, _int, _int, C.POINTER(RptTracker), _p, _p,
                                    _p, _p, _p, _p, _p, _p, _sz, _p]),

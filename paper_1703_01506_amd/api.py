@@ -17,7 +17,7 @@ PREC = {"fp32": 0, "split_bf16": 1}
 TAIL = {"signed": 0, "abs": 1}
 MU_RULE = {"mean_gap": 0, "literal": 1, "zero": 2}
 STAT = {"t": 0, "meandiff": 1}
-TRACKER = {"grouse": 0, "l1": 1}
+TRACKER = {"grouse": 0, "l1": 1, "gradient": 2}
 
 
 def _ptr(t):
@@ -349,8 +349,7 @@ def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omeg
     info); the train dict holds U, sigma_mu, train_max (a view of h), info,
     objective and passes_used (as train_subspace, whose tracker arguments
     these are)."""
-    lib = _lib.load()
-    v, n, ldx = _data(X)
+    v = X.shape[0]
     train_labels = _dev(train_labels, torch.uint8, "train_labels", 2).contiguous()
     rec_labels = _dev(rec_labels, torch.uint8, "rec_labels", 2).contiguous()
     U0 = _dev(U0, torch.float32, "U0", 2).contiguous()
@@ -362,6 +361,28 @@ def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omeg
     if (omega_train.shape != (passes * ell, k) or omega_sm.shape[0] != ell or omega_rec.shape != (L_rec, k)
             or U0.shape[0] != v):
         raise ValueError("inconsistent shapes")
+    return _rapidpt_call(X, (train_labels, rec_labels, U0, omega_train, omega_sm, omega_rec), ell, L_rec, r, k,
+                         passes, seed, batch, gamma, mu_rule, prec, tol, stat, tracker, rho, admm_iters)
+
+
+def rapidpt_maxnull_seeded(X, ell: int, L: int, r: int, eta_ppm: int, passes: int, seed: int, **kw):
+    """Alg. 2 end to end with every relabelling, sampled set and the start
+    basis drawn from the seed inside the library (NULL inputs of
+    rpt_rapidpt_maxnull).  L counts all columns (l training + L - l
+    recovered); |Omega| = sample_count(v, eta_ppm).  Keyword arguments as
+    rapidpt_maxnull.  Returns what rapidpt_maxnull returns."""
+    k = sample_count(X.shape[0], eta_ppm)
+    opts = dict(batch=1, gamma=1.0, mu_rule="mean_gap", prec="split_bf16", tol=0.0, stat="t", tracker="grouse",
+                rho=1.0, admm_iters=30)
+    opts.update(kw)
+    return _rapidpt_call(X, (None,) * 6, int(ell), int(L) - int(ell), int(r), k, passes, seed, **opts)
+
+
+def _rapidpt_call(X, inputs, ell, L_rec, r, k, passes, seed, batch, gamma, mu_rule, prec, tol, stat, tracker,
+                  rho, admm_iters):
+    lib = _lib.load()
+    v, n, ldx = _data(X)
+    train_labels, rec_labels, U0, omega_train, omega_sm, omega_rec = inputs
     batch = int(batch)
     dev = X.device
     h = torch.empty(ell + L_rec, dtype=torch.float32, device=dev)
@@ -371,7 +392,10 @@ def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omeg
     rinfo = torch.empty(L_rec, dtype=torch.int32, device=dev)
     obj = torch.empty(max(passes, 1), dtype=torch.float64, device=dev)
     used = torch.empty(1, dtype=torch.int32, device=dev)
-    ws = _workspace(lib.rpt_rapidpt_workspace(v, n, ell, L_rec, r, k, PREC[prec]), dev)
+    nbytes = lib.rpt_rapidpt_workspace(v, n, ell, L_rec, r, k, PREC[prec])
+    if any(t is None for t in (train_labels, rec_labels, omega_train, omega_sm, omega_rec)):
+        nbytes += lib.rpt_rapidpt_gen_workspace(n, ell, L_rec, k, passes)
+    ws = _workspace(nbytes, dev)
     rc = lib.rpt_rapidpt_maxnull(_ptr(X), v, n, ldx, n // 2, _ptr(train_labels), ell, _ptr(rec_labels), L_rec,
                                  _ptr(U0), r, _ptr(omega_train), k, passes, batch, float(gamma), float(tol),
                                  _ptr(omega_sm), _ptr(omega_rec), int(seed), MU_RULE[mu_rule], PREC[prec],
@@ -381,6 +405,44 @@ def rapidpt_maxnull(X, train_labels, rec_labels, U0, omega_train, omega_sm, omeg
     _lib.check(rc, "rpt_rapidpt_maxnull")
     return h, {"U": U, "sigma_mu": sm, "train_max": h[:ell], "info": tinfo, "objective": obj[:passes],
                "passes_used": used}, rinfo
+
+
+def sample_count(v: int, eta_ppm: int) -> int:
+    """|Omega| = ceil(eta v) for eta = eta_ppm / 10^6 (integer arithmetic)."""
+    k = _lib.load().rpt_sample_count(int(v), int(eta_ppm))
+    if k < 0:
+        raise ValueError("v must be >= 0 and eta_ppm in [0, 10^6]")
+    return int(k)
+
+
+def gen_relabellings(seed: int, row0: int, L: int, n: int, n1: int, device=None):
+    """Relabellings row0 .. row0 + L - 1 drawn from the seed: (L, n) uint8 on
+    the device, n1 ones per row."""
+    device = torch.device(device or "cuda")
+    out = torch.empty((L, n), dtype=torch.uint8, device=device)
+    rc = _lib.load().rpt_gen_relabellings(int(seed), int(row0), int(L), int(n), int(n1), _ptr(out), _stream(device))
+    _lib.check(rc, "rpt_gen_relabellings")
+    return out
+
+
+def gen_sampled_sets(seed: int, set_id: int, row0: int, rows: int, v: int, k: int, device=None):
+    """Sampled sets row0 .. row0 + rows - 1 of set set_id drawn from the seed:
+    (rows, k) int32 on the device, ascending distinct voxel indices."""
+    device = torch.device(device or "cuda")
+    out = torch.empty((rows, k), dtype=torch.int32, device=device)
+    rc = _lib.load().rpt_gen_sampled_sets(int(seed), int(set_id), int(row0), int(rows), int(v), int(k), _ptr(out),
+                                          _stream(device))
+    _lib.check(rc, "rpt_gen_sampled_sets")
+    return out
+
+
+def gen_start_basis(seed: int, v: int, r: int, device=None):
+    """The (v, r) FP32 Gaussian matrix that Rand. Orth. orthonormalises."""
+    device = torch.device(device or "cuda")
+    out = torch.empty((v, r), dtype=torch.float32, device=device)
+    rc = _lib.load().rpt_gen_start_basis(int(seed), int(v), int(r), _ptr(out), _stream(device))
+    _lib.check(rc, "rpt_gen_start_basis")
+    return out
 
 
 def masked_loss_fwd(U, W, omega_ptr, omega_idx, t_vals):

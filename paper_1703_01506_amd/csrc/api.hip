@@ -166,6 +166,10 @@ struct TrainWs {
   int32_t* lhead;  // [v] per-voxel lists of a batch's sampled entries
   int32_t* lnext;  // [ell][k]
   GrouseState g;   // sequential tracking (batch 1)
+  float* WT;       // [r][ell] a batch's W in the masked loss's layout
+  float* dW;       // [r][ell]
+  int64_t* optr;   // [ell + 1] CSR offsets of a batch's sets
+  float* dU;       // [v][r] the masked loss's gradient
 };
 TrainWs train_carve(void* ws, int64_t v, int n, int n1, int ell, int r, int k, int prec, size_t* total,
                     int stat = RPT_STAT_T) {
@@ -186,6 +190,10 @@ TrainWs train_carve(void* ws, int64_t v, int n, int n1, int ell, int r, int k, i
   t.lhead = c.take<int32_t>(v);
   t.lnext = c.take<int32_t>(static_cast<size_t>(ell) * k);
   t.g = grouse_carve(c.take<char>(grouse_bytes(r, k)), r, k);
+  t.WT = c.take<float>(static_cast<size_t>(ell) * r);
+  t.dW = c.take<float>(static_cast<size_t>(ell) * r);
+  t.optr = c.take<int64_t>(static_cast<size_t>(ell) + 1);
+  t.dU = c.take<float>(static_cast<size_t>(v) * r);
   if (total) *total = c.off;
   return t;
 }
@@ -220,7 +228,9 @@ rpt_status train_check(const float* X, int64_t v, int32_t n, int64_t ldx, int32_
                        int stat, const TrackOpts& opt, const float* U_out, const float* sigma_mu,
                        const float* train_max, const int32_t* info) {
   if (stat != RPT_STAT_T && stat != RPT_STAT_MEANDIFF) return RPT_ERR_INVALID_ARG;
-  if (opt.mode != RPT_TRACK_GROUSE && opt.mode != RPT_TRACK_L1) return RPT_ERR_INVALID_ARG;
+  if (opt.mode != RPT_TRACK_GROUSE && opt.mode != RPT_TRACK_L1 && opt.mode != RPT_TRACK_GRADIENT)
+    return RPT_ERR_INVALID_ARG;
+  if (opt.mode == RPT_TRACK_GRADIENT && tol > 0.0) return RPT_ERR_UNSUPPORTED;  // fixed pass count
   if (opt.mode == RPT_TRACK_L1 && (!(opt.rho > 0.0f) || opt.admm_iters < 1 || opt.admm_iters > 1000))
     return RPT_ERR_INVALID_ARG;
   if (opt.mode == RPT_TRACK_L1 && batch != 1) return RPT_ERR_UNSUPPORTED;  // the l1 fit moves U column by column
@@ -285,8 +295,9 @@ rpt_status train_tex(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t 
 rpt_status train_start_basis(int64_t v, int32_t n, int32_t n1, int32_t ell, const float* U0, int32_t r, int32_t k,
                              int prec, float* U_out, void* ws, hipStream_t s) {
   TrainWs t = train_carve(ws, v, n, n1, ell, r, k, prec, nullptr);
-  if (hipMemcpyAsync(U_out, U0, sizeof(float) * static_cast<size_t>(v) * r, hipMemcpyDeviceToDevice, s) !=
-      hipSuccess) {
+  if (U0 != U_out &&
+      hipMemcpyAsync(U_out, U0, sizeof(float) * static_cast<size_t>(v) * r, hipMemcpyDeviceToDevice, s) !=
+          hipSuccess) {
     set_hip_error(hipGetLastError());
     return RPT_ERR_HIP;
   }
@@ -305,9 +316,10 @@ rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r,
   TrainWs t = train_carve(ws, v, n, n1, ell, r, k, prec, nullptr);
   float* T = T_ex_out ? T_ex_out : t.T;
   RPT_TRY(grouse_init_launch(t.g, passes_used, objective, passes, s));
-  if (batch == 1) {
-    // 3. GROUSE column by column (the paper's mode), one workgroup per pass;
-    // the rest of the chip is free for whatever at_step starts
+  const bool grad = opt.mode == RPT_TRACK_GRADIENT;
+  if (batch == 1 && !grad) {
+    // 3. GROUSE column by column (the paper's mode), one cooperative launch
+    // per pass; the rest of the chip is free for whatever at_step starts
     for (int pp = 0; pp < passes; ++pp) {
       if (at_step) RPT_TRY(at_step(pp, passes));
       RPT_TRY(grouse_pass_launch(t.g, U_out, v, r, T, v, omega_train + static_cast<int64_t>(pp) * ell * k, k, ell,
@@ -317,19 +329,31 @@ rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r,
     }
   }
   // 3'. the mini-batch variant: Complete links every sampled entry into the
-  // list of its voxel; the update then adds each voxel's entries in one pass
+  // list of its voxel; the update then adds each voxel's entries in one pass.
+  // 3''. the masked loss drives U: Complete with residuals, the loss's
+  // backward gives dU = -P_O(E) W^T, U <- U - gamma dU (the gradient is
+  // tangent at the least-squares fit, U^T dU = 0), QR retraction.
+  const bool minib = batch > 1 || grad;
   RPT_TRY(fill_i32(t.lhead, v, -1, s));
-  if (batch > 1 && passes_used) RPT_TRY(fill_i32(passes_used, 1, passes, s));
-  const int steps = batch > 1 ? passes * ((ell + batch - 1) / batch) : 0;
+  if (minib && passes_used) RPT_TRY(fill_i32(passes_used, 1, passes, s));
+  const int steps = minib ? passes * ((ell + batch - 1) / batch) : 0;
   int step = 0;
-  for (int pp = 0; pp < (batch > 1 ? passes : 0); ++pp) {
+  for (int pp = 0; pp < (minib ? passes : 0); ++pp) {
     for (int b0 = 0; b0 < ell; b0 += batch) {
       const int nb = b0 + batch <= ell ? batch : ell - b0;
       const int32_t* om = omega_train + (static_cast<int64_t>(pp) * ell + b0) * k;
       const float* Tb = T + static_cast<int64_t>(b0) * v;
-      RPT_TRY(complete_run(U_out, v, r, om, k, nullptr, Tb, v, nullptr, nb, t.W, nullptr, t.info, t.wnorm2, s,
-                           t.lhead, t.lnext));
-      RPT_TRY(track_apply_launch(U_out, v, r, k, Tb, v, t.W, t.wnorm2, t.info, gamma, t.lhead, t.lnext, s));
+      if (grad) {
+        RPT_TRY(complete_run(U_out, v, r, om, k, nullptr, Tb, v, nullptr, nb, t.W, t.resid, t.info, t.wnorm2, s));
+        if (objective) RPT_TRY(sumsq_add_launch(t.resid, static_cast<int64_t>(nb) * k, objective + pp, s));
+        RPT_TRY(grad_prep_launch(t.W, nb, r, t.WT, t.optr, k, s));
+        RPT_TRY(loss_bwd_launch(U_out, v, r, t.WT, nb, t.optr, om, t.resid, t.dU, t.dW, nullptr, s));
+        RPT_TRY(axpy_launch(U_out, t.dU, v * r, -gamma, s));
+      } else {
+        RPT_TRY(complete_run(U_out, v, r, om, k, nullptr, Tb, v, nullptr, nb, t.W, nullptr, t.info, t.wnorm2, s,
+                             t.lhead, t.lnext));
+        RPT_TRY(track_apply_launch(U_out, v, r, k, Tb, v, t.W, t.wnorm2, t.info, gamma, t.lhead, t.lnext, s));
+      }
       const std::function<rpt_status()> hook = [&, j = step]() { return at_step(j, steps); };
       RPT_TRY(reorth_launch(U_out, v, r, t.info + ell - 1, t.reorth_ws, s, at_step ? &hook : nullptr));
       ++step;
@@ -503,6 +527,46 @@ size_t rpt_rapidpt_workspace(int64_t v, int32_t n, int32_t ell, int64_t L_rec, i
   return (a == 0 || b == 0) ? 0 : a + b;
 }
 
+}  // extern "C"
+
+namespace rpt {
+namespace {
+// Inputs of the end-to-end call drawn from the seed, after its workspace:
+// relabellings of columns 0..L-1 (training then recovered), the tracking
+// passes' sets, the sigma/mu sets and the recovery sets
+struct GenWs {
+  uint8_t* labels;
+  int32_t* om_train;
+  int32_t* om_sm;
+  int32_t* om_rec;
+  size_t bytes;
+};
+GenWs gen_carve(void* base, int32_t n, int32_t ell, int64_t L_rec, int32_t k, int32_t passes) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  GenWs g{};
+  char* p = static_cast<char*>(base);
+  size_t off = 0;
+  g.labels = reinterpret_cast<uint8_t*>(p + off);
+  off += al(static_cast<size_t>(ell + L_rec) * n);
+  g.om_train = reinterpret_cast<int32_t*>(p + off);
+  off += al(sizeof(int32_t) * static_cast<size_t>(passes) * ell * k);
+  g.om_sm = reinterpret_cast<int32_t*>(p + off);
+  off += al(sizeof(int32_t) * static_cast<size_t>(ell) * k);
+  g.om_rec = reinterpret_cast<int32_t*>(p + off);
+  off += al(sizeof(int32_t) * static_cast<size_t>(L_rec) * k);
+  g.bytes = off;
+  return g;
+}
+}  // namespace
+}  // namespace rpt
+
+extern "C" {
+
+size_t rpt_rapidpt_gen_workspace(int32_t n, int32_t ell, int64_t L_rec, int32_t k, int32_t passes) {
+  if (n < 1 || ell < 0 || L_rec < 0 || k < 0 || passes < 0) return 0;
+  return rpt::gen_carve(nullptr, n, ell, L_rec, k, passes).bytes;
+}
+
 rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx, int32_t n1,
                                const uint8_t* train_labels, int32_t ell, const uint8_t* rec_labels, int64_t L_rec,
                                const float* U0, int32_t r, const int32_t* omega_train, int32_t k, int32_t passes,
@@ -512,13 +576,42 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
                                int32_t* train_info, int32_t* rec_info, double* objective, int32_t* passes_used,
                                void* ws, size_t ws_bytes, void* stream) {
   const TrackOpts opt = track_opts(tracker);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  // inputs left NULL are drawn from the seed into the workspace's tail (the
+  // start basis straight into U_out)
+  const size_t base = rpt_rapidpt_workspace(v, n, ell, L_rec, r, k, prec);
+  // (a NULL pointer for an empty input is no request to draw it)
+  const bool gen_lab = (!train_labels && ell > 0) || (!rec_labels && L_rec > 0);
+  const bool gen_om = (!omega_train && passes > 0 && ell > 0) || (!omega_sm && ell > 0) || (!omega_rec && L_rec > 0);
+  const bool gen_u0 = !U0;
+  GenWs g{};
+  if (gen_lab || gen_om) {
+    if (n < 1 || ell < 0 || L_rec < 0 || k < 1 || passes < 0 || base == 0) return RPT_ERR_INVALID_ARG;
+    if (gen_lab) RPT_TRY(gen_labels_check(0, ell + L_rec, n, n1));
+    if (gen_om) RPT_TRY(gen_sets_check(passes + 1, 0, ell + L_rec, v, k));
+    g = gen_carve(static_cast<char*>(ws) + base, n, ell, L_rec, k, passes);
+    if (!train_labels) train_labels = g.labels;
+    if (!rec_labels) rec_labels = g.labels + static_cast<size_t>(ell) * n;
+    if (!omega_train) omega_train = g.om_train;
+    if (!omega_sm) omega_sm = g.om_sm;
+    if (!omega_rec) omega_rec = g.om_rec;
+  }
+  if (gen_u0) U0 = U_out;
   RPT_TRY(train_check(X, v, n, ldx, n1, train_labels, ell, U0, r, omega_train, k, passes, batch, gamma, tol,
                       omega_sm, mu_rule, prec, stat, opt, U_out, sigma_mu, h_out, train_info));
   RPT_TRY(recover_check(X, v, n, ldx, n1, rec_labels, L_rec, ell, U_out, r, sigma_mu, omega_rec, k, h_out,
                         rec_info, stat));
   const size_t tw = rpt_train_workspace(v, n, ell, r, k, prec);
-  if (!ws_ok(ws, ws_bytes, rpt_rapidpt_workspace(v, n, ell, L_rec, r, k, prec))) return RPT_ERR_WORKSPACE;
-  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (!ws_ok(ws, ws_bytes, base + g.bytes)) return RPT_ERR_WORKSPACE;
+  // relabelling c and sampled sets of column c of h^L: row c; set 0 for the
+  // sigma/mu and recovery sets, 1 + p for tracking pass p
+  if (gen_lab) RPT_TRY(gen_labels_launch(seed, 0, ell + L_rec, n, n1, g.labels, s));
+  if (gen_om && omega_train == g.om_train)
+    for (int32_t p = 0; p < passes; ++p)
+      RPT_TRY(gen_sets_launch(seed, 1 + p, 0, ell, v, k, g.om_train + static_cast<size_t>(p) * ell * k, s));
+  if (gen_om && omega_sm == g.om_sm) RPT_TRY(gen_sets_launch(seed, 0, 0, ell, v, k, g.om_sm, s));
+  if (gen_om && omega_rec == g.om_rec) RPT_TRY(gen_sets_launch(seed, 0, ell, L_rec, v, k, g.om_rec, s));
+  if (gen_u0) RPT_TRY(gen_start_launch(seed, v, r, U_out, s));
   const RecoverWs w = recover_carve(static_cast<char*>(ws) + tw, v, n, n1, L_rec, r, k, nullptr, stat);
   // Two chains share the device: the caller's stream computes T_ex (matrix
   // cores, the whole chip) and then the tracking passes (latency-bound, a

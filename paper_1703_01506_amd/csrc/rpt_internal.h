@@ -289,6 +289,11 @@ rpt_status track_apply_launch(float* U, int64_t v, int r, int k, const float* T,
                               const float* wnorm2, const int32_t* info, float gamma, int32_t* lhead,
                               const int32_t* lnext, hipStream_t s);
 rpt_status fill_i32(int32_t* p, int64_t n, int32_t value, hipStream_t s);
+// The masked-loss-driven step: W^T (r x nb) and CSR offsets b k of a batch;
+// U += a G; *out += sum e^2 (one workgroup, fixed order)
+rpt_status grad_prep_launch(const float* W, int nb, int r, float* WT, int64_t* ptr, int k, hipStream_t s);
+rpt_status axpy_launch(float* U, const float* G, int64_t n, float a, hipStream_t s);
+rpt_status sumsq_add_launch(const float* e, int64_t n, double* out, hipStream_t s);
 rpt_status sigma_launch(const float* resid, int64_t n, double* sums, float* sigma_mu, hipStream_t s);
 rpt_status mu_launch(const float* vals, int n, int rule, float* sigma_mu, hipStream_t s);
 rpt_status literal_resid_launch(const float* T, const float* U, const float* W, int64_t v, int r, int64_t ell,
@@ -336,5 +341,17 @@ rpt_status loss_fwd_launch(const float* U, int64_t v, int r, const float* W, int
                            const float* t, double* loss, float* resid, hipStream_t s);
 rpt_status loss_bwd_launch(const float* U, int64_t v, int r, const float* W, int B, const int64_t* ptr,
                            const int32_t* idx, const float* e, float* dU, float* dW, const double* grad_scale, hipStream_t s);
+
+// Inputs drawn from a seed (gen.hip): relabellings (stream 0), sampled sets
+// (stream 1, at most kGenMaxSet voxels each) and the Gaussian start basis
+// (stream 3).  The checks are synchronous; the launches assume them passed.
+constexpr int kGenMaxSet = 4096;
+rpt_status gen_labels_check(int64_t row0, int64_t L, int32_t n, int32_t n1);
+rpt_status gen_sets_check(int32_t set_id, int64_t row0, int64_t rows, int64_t v, int32_t k);
+rpt_status gen_labels_launch(uint64_t seed, int64_t row0, int64_t L, int32_t n, int32_t n1, uint8_t* labels,
+                             hipStream_t s);
+rpt_status gen_sets_launch(uint64_t seed, int32_t set_id, int64_t row0, int64_t rows, int64_t v, int32_t k,
+                           int32_t* omega, hipStream_t s);
+rpt_status gen_start_launch(uint64_t seed, int64_t v, int32_t r, float* U, hipStream_t s);
 
 }  // namespace rpt

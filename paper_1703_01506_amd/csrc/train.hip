@@ -512,6 +512,83 @@ rpt_status reorth_launch(float* U, int64_t v, int r, int32_t* info, void* ws, hi
   return RPT_OK;
 }
 
+// ---------------------------------------------------------------- masked-loss step
+// W^T of a batch (nb x r -> r x nb, the masked loss's layout) and the CSR
+// offsets b k of its dense sampled sets
+__global__ __launch_bounds__(kBlock) void grad_prep_kernel(const float* __restrict__ W, int nb, int r,
+                                                          float* __restrict__ WT, int64_t* __restrict__ ptr, int k) {
+  const int64_t n = static_cast<int64_t>(nb) * r;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; t < n;
+       t += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int64_t b = t / r, c = t - b * r;
+    WT[c * nb + b] = W[t];
+  }
+  for (int64_t b = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; b <= nb;
+       b += static_cast<int64_t>(gridDim.x) * kBlock)
+    ptr[b] = b * k;
+}
+
+// U += a G over n entries (16-byte accesses over the first 4 n4)
+__global__ __launch_bounds__(kBlock) void axpy_kernel(float* __restrict__ U, const float* __restrict__ G, int64_t n,
+                                                     int64_t n4, float a) {
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; t < n4;
+       t += static_cast<int64_t>(gridDim.x) * kBlock) {
+    f32x4 u = reinterpret_cast<f32x4*>(U)[t];
+    const f32x4 g = reinterpret_cast<const f32x4*>(G)[t];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) u[e] = fmaf(a, g[e], u[e]);
+    reinterpret_cast<f32x4*>(U)[t] = u;
+  }
+  for (int64_t t = 4 * n4 + blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; t < n;
+       t += static_cast<int64_t>(gridDim.x) * kBlock)
+    U[t] = fmaf(a, G[t], U[t]);
+}
+
+// *out += sum e^2 over n values, one workgroup in a fixed order (FP64)
+__global__ __launch_bounds__(kBlock) void sumsq_add_kernel(const float* __restrict__ e, int64_t n, double* out) {
+  __shared__ double red[kBlock / kWave];
+  double s = 0.0;
+  for (int64_t t = threadIdx.x; t < n; t += kBlock) {
+    const double x = e[t];
+    s = fma(x, x, s);
+  }
+  s = wave_sum_d(s);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < kBlock / kWave; ++w) t += red[w];
+    *out += t;
+  }
+}
+
+rpt_status grad_prep_launch(const float* W, int nb, int r, float* WT, int64_t* ptr, int k, hipStream_t s) {
+  int64_t blocks = ceil_div(static_cast<int64_t>(nb) * r + 1, kBlock);
+  if (blocks > 1024) blocks = 1024;
+  hipLaunchKernelGGL(grad_prep_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, W, nb, r, WT, ptr,
+                     k);
+  RPT_CHECK_LAUNCH();
+  return RPT_OK;
+}
+
+rpt_status axpy_launch(float* U, const float* G, int64_t n, float a, hipStream_t s) {
+  if (n <= 0) return RPT_OK;
+  RPT_STAGE("grad_step", s);
+  int64_t blocks = ceil_div(n / 4 + 1, kBlock);
+  if (blocks > 4096) blocks = 4096;
+  const bool al = ((reinterpret_cast<uintptr_t>(U) | reinterpret_cast<uintptr_t>(G)) & 15) == 0;
+  hipLaunchKernelGGL(axpy_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, U, G, n, al ? n / 4 : 0,
+                     a);
+  RPT_CHECK_LAUNCH();
+  return RPT_OK;
+}
+
+rpt_status sumsq_add_launch(const float* e, int64_t n, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(sumsq_add_kernel, dim3(1), dim3(kBlock), 0, s, e, n, out);
+  RPT_CHECK_LAUNCH();
+  return RPT_OK;
+}
+
 rpt_status track_apply_launch(float* U, int64_t v, int r, int k, const float* T, int64_t ldT, const float* W,
                               const float* wnorm2, const int32_t* info, float gamma, int32_t* lhead,
                               const int32_t* lnext, hipStream_t s) {

@@ -123,7 +123,10 @@ def test_rapidpt_end_to_end_validation(lib):
     assert call(batch=2, tol=1e-3) == -6       # the stopping rule belongs to column-by-column tracking
     assert call(stat=2) == -1                  # no such statistic
     from paper_1703_01506_amd._lib import RptTracker as T
-    assert call(tracker=T(2, 1.0, 30)) == -1               # no such tracker
+    assert call(tracker=T(3, 1.0, 30)) == -1               # no such tracker
+    assert call(batch=5, tol=1e-3, tracker=T(2, 1.0, 30)) == -6   # the gradient tracker runs every pass
+    assert call(batch=1, tol=1e-3, tracker=T(2, 1.0, 30)) == -6
+    assert call(batch=5, gamma=0.0, tracker=T(2, 1.0, 30)) == -1  # step length must be positive
     assert call(batch=1, tracker=T(1, 0.0, 30)) == -1      # ADMM penalty must be positive
     assert call(batch=1, tracker=T(1, 1.0, 0)) == -1       # at least one ADMM iteration
     assert call(batch=2, tracker=T(1, 1.0, 30)) == -6      # the l1 fit moves U one column at a time
@@ -149,6 +152,47 @@ def test_sigma_mu_heldout_validation(lib):
     assert call(k_=7) == -2
     assert call(mu_rule=3) == -1
     assert call(stat=2) == -1
+
+
+def test_seeded_inputs_validation(lib):
+    """The generators and the end-to-end call's NULL inputs check their
+    arguments before any launch."""
+    from oracle import sampling as OS
+    for v, eta in ((250_000, 3500), (999_999, 1), (1_000_001, 1), (0, 5), (7, 1_000_000)):
+        assert lib.rpt_sample_count(v, eta) == OS.sample_count(v, eta)
+    assert lib.rpt_sample_count(-1, 5) == -1 and lib.rpt_sample_count(10, 1_000_001) == -1
+    d = C.c_void_p(256)
+    gl = lib.rpt_gen_relabellings
+    assert gl(1, 0, 10, 20, 20, d, None) == -1        # n1 = n
+    assert gl(1, 0, 10, 513, 100, d, None) == -1      # more than 512 subjects
+    assert gl(1, (1 << 32) - 5, 6, 20, 10, d, None) == -1  # rows past the counter range
+    assert gl(1, 0, 10, 20, 10, None, None) == -1     # no output
+    assert gl(1, 0, 0, 20, 10, None, None) == 0       # no rows: a no-op
+    gs = lib.rpt_gen_sampled_sets
+    assert gs(1, 0, 0, 5, 100, 101, d, None) == -1    # k > v
+    assert gs(1, 0, 0, 5, 100, 0, d, None) == -1      # empty set
+    assert gs(1, -1, 0, 5, 100, 10, d, None) == -1    # negative set id
+    assert gs(1, 0, 0, 5, 100_000, 4097, d, None) == -6  # above the LDS-resident shuffle
+    assert gs(1, 0, 0, 0, 100, 10, None, None) == 0
+    assert lib.rpt_gen_start_basis(1, 100, 0, d, None) == -1
+    assert lib.rpt_gen_start_basis(1, 100, 4, None, None) == -1
+    # the end-to-end call with NULL inputs needs the generated inputs' workspace
+    v, n, ell, L_rec, r, k, prec, passes = 5000, 20, 30, 70, 8, 40, 1, 2
+    base = lib.rpt_rapidpt_workspace(v, n, ell, L_rec, r, k, prec)
+    extra = lib.rpt_rapidpt_gen_workspace(n, ell, L_rec, k, passes)
+    assert extra >= (ell + L_rec) * n + 4 * k * (passes * ell + ell + L_rec)
+    ws = C.c_void_p(512)
+
+    def call(ws_bytes, k_=k, v_=v, labels=None, omegas=None):
+        return lib.rpt_rapidpt_maxnull(d, v_, n, n, n // 2, labels, ell, labels, L_rec, None, r, omegas, k_, passes,
+                                       1, 1.0, 0.0, omegas, omegas, 7, 0, prec, 0, None, d, d, d, d, d, d, d, ws,
+                                       ws_bytes, None)
+
+    assert call(base + extra - 1) == -4
+    assert call(base - 1, labels=d, omegas=d) == -4   # explicit labels and sets: the base workspace
+    big = 5000
+    assert call(1 << 40, k_=big, v_=250_000) == -6    # drawn sets above 4096 voxels
+    assert lib.rpt_rapidpt_gen_workspace(0, ell, L_rec, k, passes) == 0
 
 
 def test_autotune_table_roundtrip(lib, tmp_path):

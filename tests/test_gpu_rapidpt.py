@@ -291,6 +291,34 @@ def test_train_l1_tracker_matches_oracle(n, v, r, k, eta):
     assert abs(sigma - so) <= 1e-3 * so
 
 
+@pytest.mark.parametrize("n,v,r,k,batch", [(20, 3001, 12, 150, 8), (60, 6001, 40, 700, 1), (60, 6001, 40, 700, 30)])
+def test_train_gradient_tracker_matches_oracle(n, v, r, k, batch):
+    """Training driven by the masked loss of Eq. 1 (its backward, a step of
+    length 1e-3 and a QR retraction per mini-batch), three passes, against
+    the oracle on the training columns the GPU computed: basis, pass
+    objectives and sigma."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce(f"train gradient tracker n={n} v={v} r={r} k={k} batch={batch}")
+    passes, seed, alpha = 3, 2017, 1e-3
+    X, tl, U0, omt, oms = _train_inputs(n=n, v=v, ell=30, r=r, k=k, passes=passes)
+    out = rpt.train_subspace(_dev(torch, X), _dev(torch, tl), _dev(torch, U0), _dev(torch, omt), _dev(torch, oms),
+                             passes=passes, seed=seed, batch=batch, gamma=alpha, prec="fp32", return_T=True,
+                             tracker="gradient")
+    U = out["U"].cpu().numpy().astype(np.float64)
+    T_ex = out["T_ex"].cpu().numpy().astype(np.float64)
+    hist = []
+    Uo = OR.train_subspace_gradient(T_ex, U0.astype(np.float64), omt, passes, batch, alpha, history=hist)
+    so, _, _ = OR.sigma_mu(T_ex, Uo, oms, seed)
+    sigma = float(out["sigma_mu"][0].item())
+    dP = np.abs(U @ U.T - Uo @ Uo.T).max()
+    np.testing.assert_allclose(U.T @ U, np.eye(r), atol=5e-5)
+    assert dP < 2e-4
+    assert int(out["passes_used"].item()) == passes
+    np.testing.assert_allclose(out["objective"].cpu().numpy(), hist, rtol=1e-3)
+    assert abs(sigma - so) <= 1e-3 * so
+
+
 @pytest.mark.parametrize("mu_rule", ["mean_gap", "literal"])
 def test_sigma_mu_heldout_matches_oracle(mu_rule):
     """sigma and mu from held-out fully computed columns (rpt_sigma_mu): the
