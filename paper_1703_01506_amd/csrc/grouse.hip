@@ -107,16 +107,26 @@ __host__ __device__ constexpr int g_hld(int rb) { return 16 * rb + 1; }
 // quad_perm [2, 3, 0, 1] (0x4E), row_half_mirror (0x141), row_mirror
 // (0x140); row_bcast:15 (0x142) and row_bcast:31 (0x143) into the upper
 // rows for whole-wave sums
+// With every row enabled each lane reads a lane of its own row, so the
+// destination's old value is never kept and needs no zeroing first; with a
+// row mask the disabled rows keep 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ int dpp_mov_i(int x) {
+  if constexpr (ROWMASK == 0xF)
+    return __builtin_amdgcn_mov_dpp(x, CTRL, 0xF, 0xF, false);
+  else
+    return __builtin_amdgcn_update_dpp(0, x, CTRL, ROWMASK, 0xF, false);
+}
 template <int CTRL, int ROWMASK>
 __device__ __forceinline__ double dpp_mov_d(double s) {
   const long long b = __double_as_longlong(s);
-  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xFFFFFFFFll), CTRL, ROWMASK, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, ROWMASK, 0xF, false);
+  const int lo = dpp_mov_i<CTRL, ROWMASK>(static_cast<int>(b & 0xFFFFFFFFll));
+  const int hi = dpp_mov_i<CTRL, ROWMASK>(static_cast<int>(b >> 32));
   return __longlong_as_double((static_cast<long long>(static_cast<unsigned>(hi)) << 32) | static_cast<unsigned>(lo));
 }
 template <int CTRL>
 __device__ __forceinline__ float dpp_mov_f(float s) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(s), CTRL, 0xF, 0xF, false));
+  return __int_as_float(dpp_mov_i<CTRL, 0xF>(__float_as_int(s)));
 }
 // sum over the 64 lanes of one wave; the total ends in lane 63 and is read
 // back as a scalar, so every lane gets it
@@ -169,6 +179,27 @@ __device__ __forceinline__ double row16_reduce_scatter8(const double (&v)[8], in
   return k1;
 }
 
+// The same reduce-scatter without lane-dependent selects, for operands
+// stored in a lane-dependent order: v[m] holds value (c >> 1) ^ kRowX[m].
+// Then every exchange keeps the low half and sends the high half: the
+// mirror partner 15 - c holds value (c >> 1) ^ 7 ^ kRowX[m] in v[m], which is
+// what this lane holds in v[4 + m] (kRowX[4 + m] = 7 ^ kRowX[m]); the
+// half-mirror partner c ^ 7 likewise (kRowX[2 + m] = 3 ^ kRowX[m]), and the
+// partner c ^ 2 holds in v[0] this lane's v[1].  Lane c ends with the sum of
+// value c >> 1 (= row8_sel(c)).
+__device__ constexpr int kRowX[8] = {0, 1, 3, 2, 7, 6, 4, 5};
+__device__ __forceinline__ double row16_reduce_scatter8_px(const double (&v)[8]) {
+  double k4[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) k4[m] = v[m] + dpp_mov_d<0x140, 0xF>(v[4 + m]);
+  double k2[2];
+#pragma unroll
+  for (int m = 0; m < 2; ++m) k2[m] = k4[m] + dpp_mov_d<0x141, 0xF>(k4[2 + m]);
+  double k1 = k2[0] + dpp_mov_d<0x4E, 0xF>(k2[1]);
+  k1 += dpp_mov_d<0xB1, 0xF>(k1);
+  return k1;
+}
+
 // the lower 16 x 16 tiles (bi >= bj) of an RB-block Gram matrix, numbered
 // bi (bi + 1) / 2 + bj; tile group G of TG takes the tiles t = G mod TG.
 // One 16x16x4 FP32 matrix-core product per tile and group of four rows:
@@ -191,9 +222,11 @@ __device__ __forceinline__ void gram_products(f32x4 (&acc)[gram_ntw(RB, TG)], co
 // M r, M the inverse diagonal) and the vector m = M w that the next product
 // H m needs are written together.  The iteration stops when (r, M r) has
 // fallen by kCgTol^2.  H is held in registers in the matrix layout (lane (rq, cb) of
-// wave w: rows rbase .. rbase + 7, columns 8 cb .. 8 cb + 7; after a
+// wave w: rows rbase .. rbase + 7, in the lane-dependent order of
+// row16_reduce_scatter8_px, columns 8 cb .. 8 cb + 7; after the
 // reduce-scatter the lane holds row myrow, owned by the even lane of its
-// pair).  The right-hand side is row r of H, or with WARM the vector bvec
+// pair, and both lanes of the pair keep identical copies of every vector
+// entry, so inner products add half of every lane's term).  The right-hand side is row r of H, or with WARM the vector bvec
 // (FP64, in LDS) and the iteration starts from the z in sv.zv.  On return sv.zv and
 // sv.zf hold z (zero from r on); the result is 0, 1 (a non-positive diagonal
 // or curvature) or 2 (iteration cap).  Ends with a barrier.
@@ -206,7 +239,7 @@ __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, i
   for (int ii = 0; ii < 8; ++ii)
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int rr = rbase + ii, cc = 8 * cb + j;
+      const int rr = rbase + ((cb >> 1) ^ kRowX[ii]), cc = 8 * cb + j;
       const int hi = min(max(rr, cc), r - 1), lo = min(min(rr, cc), r - 1);
       const float hv = H[hi * hld + lo];
       h[ii][j] = (rr < r && cc < r) ? static_cast<double>(hv) : 0.0;
@@ -214,8 +247,7 @@ __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, i
   const int rowc = rowok ? myrow : 0;
   const double bq = rowok ? (WARM ? bvec[rowc] : static_cast<double>(H[r * hld + rowc])) : 0.0;
   const double dg = rowok ? static_cast<double>(H[rowc * hld + rowc]) : 1.0;
-  const double di = dg > 0.0 ? 1.0 / dg : 0.0;
-  const bool cnt = owner && rowok;
+  const double di = dg > 0.0 ? 1.0 / dg : 0.0;  // 1 where !rowok: every vector entry there is 0
   // H y at this lane's row for y given at every column through LDS
   auto hprod = [&](const double* y) -> double {
     double yc[8], ap[8];
@@ -223,15 +255,12 @@ __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, i
     for (int j = 0; j < 8; ++j) yc[j] = y[8 * cb + j];
 #pragma unroll
     for (int ii = 0; ii < 8; ++ii) {
-      double a0 = 0.0, a1 = 0.0;
+      double a = 0.0;
 #pragma unroll
-      for (int j = 0; j < 8; j += 2) {
-        a0 = fma(h[ii][j], yc[j], a0);
-        a1 = fma(h[ii][j + 1], yc[j + 1], a1);
-      }
-      ap[ii] = a0 + a1;
+      for (int j = 0; j < 8; ++j) a = fma(h[ii][j], yc[j], a);
+      ap[ii] = a;
     }
-    return row16_reduce_scatter8(ap, cb);
+    return row16_reduce_scatter8_px(ap);
   };
   // x_0 = 0 (or the previous solution in sv.zv), r_0 = b - H x_0,
   // u_0 = M r_0, w_0 = H u_0
@@ -242,7 +271,7 @@ __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, i
     rr_ = rowok ? bq - hx : 0.0;
   }
   double ur = di * rr_;
-  const double pb = wave_sum_dpp(cnt ? bq * di * bq : 0.0);  // (r_0, M r_0)
+  const double pb = wave_sum_dpp(0.5 * (bq * di * bq));  // (r_0, M r_0)
   const bool anybad = __ballot(rowok && !(dg > 0.0)) != 0ull;
   if (lane == 0) {
     sv.red[3][wave] = pb;
@@ -266,9 +295,9 @@ __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, i
 #pragma unroll 1
     for (; it < kCgMaxIt; ++it) {
       const int sl = it & 1;  // double-buffered exchange slots
-      const double mr = rowok ? di * wr : 0.0;
-      const double g0 = wave_sum_dpp(cnt ? rr_ * ur : 0.0);
-      const double g1 = wave_sum_dpp(cnt ? wr * ur : 0.0);
+      const double mr = di * wr;
+      const double g0 = wave_sum_dpp(0.5 * (rr_ * ur));
+      const double g1 = wave_sum_dpp(0.5 * (wr * ur));
       if (lane == 0) {
         sv.cgr[sl][wave][0] = g0;
         sv.cgr[sl][wave][1] = g1;
@@ -655,6 +684,19 @@ __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
     if (MODE == 0) {
       // ---------------------------------------------------------- 4. H z = b (every workgroup)
       cg_fail = grouse_cg<hld, false>(H, r, sv, lane, wave, rbase, cb, myrow, owner, rowok, nullptr);
+      // |e|^2 = x_O^T x_O - b^T z for the least-squares z, from H alone (row
+      // r of H is [b^T, x_O^T x_O]): the same in every workgroup, so no
+      // exchange is needed while the fit leaves at least a tenth of
+      // |x_O|^2 (then the cancellation costs at most one digit of H's
+      // FP32 sums); a closer fit sums the residuals across workgroups
+      double xx, eef;
+      {
+        double t = 0.0;
+        for (int j = lane; j < r; j += 64) t = fma(static_cast<double>(H[r * hld + j]), sv.zv[j], t);
+        xx = static_cast<double>(H[r * hld + r]);
+        eef = xx - wave_sum_dpp(t);
+      }
+      const bool exch = !(xx > 0.0 && eef >= 0.1 * xx);
       // ---------------------------------------------------------- 5. residuals of this slice
       {
         float zl[8];
@@ -685,19 +727,25 @@ __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
             ee += static_cast<double>(e) * e;
           }
         }
-        ee = wave_sum_dpp(ee);
-        if (lane == 0) sv.red[3][wave] = ee;
-        __syncthreads();
-        if (tid == 0) {
+        if (exch) {
+          ee = wave_sum_dpp(ee);
+          if (lane == 0) sv.red[3][wave] = ee;
+        }
+        __syncthreads();  // the residuals se[] are in
+        if (exch && tid == 0) {
           double t = 0.0;
   #pragma unroll
           for (int w = 0; w < kGWaves; ++w) t += sv.red[3][w];
           ca.epart[wg] = t;
         }
       }
-      target += nwg;
-      if (!(alive = coop_barrier(ctr, target, ca.abort, flag))) break;
-      for (int p = 0; p < nwg; ++p) ee += ca.epart[p];
+      if (exch) {
+        target += nwg;
+        if (!(alive = coop_barrier(ctr, target, ca.abort, flag))) break;
+        for (int p = 0; p < nwg; ++p) ee += ca.epart[p];
+      } else {
+        ee = eef;
+      }
       obj += ee;
     } else {
       // ---------------------------------------------------------- 4'. the l1 fit (ADMM)
