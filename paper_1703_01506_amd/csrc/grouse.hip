@@ -99,10 +99,10 @@ struct GrouseVec {
   float zf[kGR], qf[kGR];
 };
 
-// column blocks of 16 covering columns 0..r; H holds all 16 RB rows and the
-// columns the tiles write (row length 16 RB + 1 words)
+// column blocks of 16 covering columns 0..r; H holds all 16 RB rows and
+// columns of the symmetric matrix (row length 16 RB + 4 words)
 __host__ __device__ constexpr int g_rb(int r) { return (r + 1 + 15) / 16; }
-__host__ __device__ constexpr int g_hld(int rb) { return 16 * rb + 1; }
+__host__ __device__ constexpr int g_hld(int rb) { return 16 * rb + 4; }  // rows 16-byte aligned
 // DPP lane moves within rows of 16 lanes: quad_perm [1, 0, 3, 2] (0xB1),
 // quad_perm [2, 3, 0, 1] (0x4E), row_half_mirror (0x141), row_mirror
 // (0x140); row_bcast:15 (0x142) and row_bcast:31 (0x143) into the upper
@@ -234,16 +234,23 @@ template <int HLD, bool WARM>
 __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, int lane, int wave, int rbase, int cb,
                                          int myrow, bool owner, bool rowok, const double* bvec) {
   constexpr int hld = HLD;
+  // H is stored whole with 16-byte aligned rows: two 16-byte loads per row
+  // (row and column offsets clamped into the stored block, the entries
+  // outside the r x r matrix then zeroed)
   double h[8][8];
+  const int c0 = min(8 * cb, (hld & ~7) - 8);
 #pragma unroll
-  for (int ii = 0; ii < 8; ++ii)
+  for (int ii = 0; ii < 8; ++ii) {
+    const int rr = rbase + ((cb >> 1) ^ kRowX[ii]);
+    const float* hrow = H + min(rr, r - 1) * hld + c0;
+    const f32x4 a0 = *reinterpret_cast<const f32x4*>(hrow);
+    const f32x4 a1 = *reinterpret_cast<const f32x4*>(hrow + 4);
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int rr = rbase + ((cb >> 1) ^ kRowX[ii]), cc = 8 * cb + j;
-      const int hi = min(max(rr, cc), r - 1), lo = min(min(rr, cc), r - 1);
-      const float hv = H[hi * hld + lo];
-      h[ii][j] = (rr < r && cc < r) ? static_cast<double>(hv) : 0.0;
+      const int cc = 8 * cb + j;
+      h[ii][j] = (rr < r && cc < r) ? static_cast<double>(j < 4 ? a0[j] : a1[j - 4]) : 0.0;
     }
+  }
   const int rowc = rowok ? myrow : 0;
   const double bq = rowok ? (WARM ? bvec[rowc] : static_cast<double>(H[r * hld + rowc])) : 0.0;
   const double dg = rowok ? static_cast<double>(H[rowc * hld + rowc]) : 1.0;
@@ -673,6 +680,8 @@ __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
             const int bj = t - bi * (bi + 1) / 2;
 #pragma unroll
             for (int e = 0; e < 4; ++e) H[(16 * bi + 4 * (l >> 4) + e) * hld + 16 * bj + (l & 15)] = v4[m][e];
+            // and the mirrored entries, so that H is stored whole
+            if (bi != bj) *reinterpret_cast<f32x4*>(H + (16 * bj + (l & 15)) * hld + 16 * bi + 4 * (l >> 4)) = v4[m];
           }
         }
       }
