@@ -142,6 +142,16 @@ __device__ __forceinline__ double wave_sum_dpp(double s) {
   const unsigned hi = static_cast<unsigned>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), 63));
   return __longlong_as_double(static_cast<long long>((static_cast<unsigned long long>(hi) << 32) | lo));
 }
+// the same sum, left in lane 63 only (no broadcast back to the wave)
+__device__ __forceinline__ double wave_sum_l63(double s) {
+  s += dpp_mov_d<0xB1, 0xF>(s);
+  s += dpp_mov_d<0x4E, 0xF>(s);
+  s += dpp_mov_d<0x141, 0xF>(s);
+  s += dpp_mov_d<0x140, 0xF>(s);
+  s += dpp_mov_d<0x142, 0xA>(s);
+  s += dpp_mov_d<0x143, 0xC>(s);
+  return s;
+}
 // sum over the 16 lanes of a DPP row into every one of them
 __device__ __forceinline__ float row16_sum_f(float x) {
   x += dpp_mov_f<0xB1>(x);
@@ -256,10 +266,8 @@ __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, i
   const double dg = rowok ? static_cast<double>(H[rowc * hld + rowc]) : 1.0;
   const double di = dg > 0.0 ? 1.0 / dg : 0.0;  // 1 where !rowok: every vector entry there is 0
   // H y at this lane's row for y given at every column through LDS
-  auto hprod = [&](const double* y) -> double {
-    double yc[8], ap[8];
-#pragma unroll
-    for (int j = 0; j < 8; ++j) yc[j] = y[8 * cb + j];
+  auto hprod_r = [&](const double (&yc)[8]) -> double {
+    double ap[8];
 #pragma unroll
     for (int ii = 0; ii < 8; ++ii) {
       double a = 0.0;
@@ -268,6 +276,12 @@ __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, i
       ap[ii] = a;
     }
     return row16_reduce_scatter8_px(ap);
+  };
+  auto hprod = [&](const double* y) -> double {
+    double yc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) yc[j] = y[8 * cb + j];
+    return hprod_r(yc);
   };
   // x_0 = 0 (or the previous solution in sv.zv), r_0 = b - H x_0,
   // u_0 = M r_0, w_0 = H u_0
@@ -303,14 +317,18 @@ __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, i
     for (; it < kCgMaxIt; ++it) {
       const int sl = it & 1;  // double-buffered exchange slots
       const double mr = di * wr;
-      const double g0 = wave_sum_dpp(0.5 * (rr_ * ur));
-      const double g1 = wave_sum_dpp(0.5 * (wr * ur));
-      if (lane == 0) {
+      const double g0 = wave_sum_l63(0.5 * (rr_ * ur));
+      const double g1 = wave_sum_l63(0.5 * (wr * ur));
+      if (lane == 63) {
         sv.cgr[sl][wave][0] = g0;
         sv.cgr[sl][wave][1] = g1;
       }
       if (owner) sv.mv[sl][myrow] = mr;
       __syncthreads();  // the inner products and m = M w are in
+      // the next product's operand is read with the sums, before the test
+      double yc[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) yc[j] = sv.mv[sl][8 * cb + j];
       double gam = 0.0, del = 0.0;
 #pragma unroll
       for (int w = 0; w < kGWaves; ++w) {
@@ -318,7 +336,7 @@ __device__ __forceinline__ int grouse_cg(const float* H, int r, GrouseVec& sv, i
         del += sv.cgr[sl][w][1];
       }
       if (gam <= stop2) break;
-      const double nr = hprod(sv.mv[sl]);
+      const double nr = hprod_r(yc);
       // the step lengths with a hardware reciprocal and two Newton steps
       // (quadratic: relative error below 2^-52 from the rcp's 2^-22)
       auto rcp = [](double d) {
