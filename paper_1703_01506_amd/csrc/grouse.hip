@@ -94,7 +94,7 @@ struct GrouseVec {
   double gv[kGR];     // right-hand side of the l1 fit's solves
   double cgr[2][kGWaves][2];
   double red[4][kGWaves];
-  double nrm[2][kGWaves];  // per-wave |N|_F^2 and |N^{-1}|_F^2
+  double nf2[2];  // |N|_F^2, |N^{-1}|_F^2
   int badf[kGWaves];
   float zf[kGR], qf[kGR];
 };
@@ -482,6 +482,10 @@ __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
   // registers; the pass starts from N = I
   // (and of N^{-1}, nin)
   float nreg[8][8], nin[8][8];
+  // |N|_F^2 and |N^{-1}|_F^2 (sv.nf2 in LDS), followed through the rank-one
+  // updates: with |wh| = 1, N' = (I + a wh wh^T) N has
+  // |N'|^2 = |N|^2 + (2 a + a^2) |N^T wh|^2 and N^{-1}' = N^{-1} (I + (c - 1)
+  // wh wh^T) has |N^{-1}'|^2 = |N^{-1}|^2 + (c^2 - 1) |N^{-1} wh|^2
   auto identity = [&]() {
 #pragma unroll
     for (int i = 0; i < 8; ++i)
@@ -490,6 +494,7 @@ __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
         const int rr = 32 * wave + 8 * (lane >> 4) + i, cc = 8 * (lane & 15) + j;
         nreg[i][j] = nin[i][j] = (rr == cc && rr < r) ? 1.0f : 0.0f;
       }
+    if (tid == 0) sv.nf2[0] = sv.nf2[1] = static_cast<double>(r);
   };
   identity();
   double obj = 0.0;
@@ -517,13 +522,7 @@ __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
     // over all v rows (each workgroup a share) and N <- I: the subspace and
     // the step are unchanged.
     if (i > 0) {
-      double nf = 0.0, mf = 0.0;
-#pragma unroll
-      for (int w = 0; w < kGWaves; ++w) {
-        nf += sv.nrm[0][w];
-        mf += sv.nrm[1][w];
-      }
-      if (sqrt(nf * mf) > kRefresh * r) {
+      if (sqrt(sv.nf2[0] * sv.nf2[1]) > kRefresh * r) {
         float* Md = H;  // N^{-1}, r x r
 #pragma unroll
         for (int ii = 0; ii < 8; ++ii)
@@ -955,6 +954,20 @@ __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
         sv.qf[tid] = own ? static_cast<float>(t / cth) : 0.0f;
       }
       __syncthreads();
+      {
+        double u2 = 0.0, m2 = 0.0;
+        for (int j = lane; j < r; j += 64) {
+          u2 = fma(sv.uu[j], sv.uu[j], u2);
+          m2 = fma(sv.mw[j], sv.mw[j], m2);
+        }
+        u2 = wave_sum_dpp(u2);
+        m2 = wave_sum_dpp(m2);
+        const double a1 = 1.0 / cth - 1.0;
+        if (tid == 0) {
+          sv.nf2[0] += (2.0 * a1 + a1 * a1) * u2;
+          sv.nf2[1] += (cth * cth - 1.0) * m2;
+        }
+      }
       const float fi = static_cast<float>(1.0 / cth - 1.0);
 #pragma unroll
       for (int ii = 0; ii < 8; ++ii) {
@@ -1005,22 +1018,6 @@ __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
       }
     }
     if (wg == 0 && tid == 0) a.info[i] = cg_fail ? -cg_fail : 0;
-    {
-      double nf = 0.0, mf = 0.0;
-#pragma unroll
-      for (int ii = 0; ii < 8; ++ii)
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-          nf += static_cast<double>(nreg[ii][j]) * nreg[ii][j];
-          mf += static_cast<double>(nin[ii][j]) * nin[ii][j];
-        }
-      nf = wave_sum_dpp(nf);
-      mf = wave_sum_dpp(mf);
-      if (lane == 0) {
-        sv.nrm[0][wave] = nf;
-        sv.nrm[1][wave] = mf;
-      }
-    }
     target += nwg;
     if (!(alive = coop_barrier(ctr, target, ca.abort, flag))) break;
   }
