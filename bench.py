@@ -332,6 +332,86 @@ def studies(a):
         "stages_ms_per_call": stages}), flush=True)
 
 
+def masked_loss_bench(a):
+    """The differentiable path at its largest shape: the masked loss of Eq. 1
+    and its backward for U 500,000 x 400 FP32, batches of 512 relabellings
+    with 1,750 sampled voxels each (0.35%), the sampled values being the t
+    statistics of a 500,000 x 400 (200/200) data matrix at those voxels;
+    L = 100,000 relabellings make 196 batches.  W (400 x 512) is a fixed
+    Gaussian matrix: the kernels' work does not depend on its values.  A step
+    is one forward and one backward launch; the sampled t and the sets are
+    drawn before the timed region, four batches in turn."""
+    import torch
+    import paper_1703_01506_amd as rpt
+    from paper_1703_01506_amd import timing
+    v, n, r, B, k, L = 500_000, 400, 400, 512, 1750, 100_000
+    steps = (L + B - 1) // B
+    dev = torch.device("cuda:0")
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(1703)
+    X = torch.randn((v, n), generator=gen, device=dev, dtype=torch.float32)
+    U = torch.randn((v, r), generator=gen, device=dev, dtype=torch.float32) * (1.0 / v ** 0.5)
+    W = torch.randn((r, B), generator=gen, device=dev, dtype=torch.float32)
+    ptr = torch.arange(B + 1, device=dev, dtype=torch.int64) * k
+    batches = []
+    for q in range(4):
+        lab = rpt.gen_relabellings(2017, q * B, B, n, n // 2, device=dev)
+        om = rpt.gen_sampled_sets(2017, 0, q * B, B, v, k, device=dev)
+        t = rpt.sampled_tstat(X, lab, om)
+        batches.append((om.reshape(-1).contiguous(), t.reshape(-1).contiguous()))
+    del X
+    torch.cuda.synchronize()
+
+    def step(q):
+        idx, t = batches[q % 4]
+        loss, resid = rpt.masked_loss_fwd(U, W, ptr, idx, t)
+        return rpt.masked_loss_bwd(U, W, ptr, idx, resid)
+
+    for q in range(a.warmup + 2):
+        step(q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q in range(steps):
+        step(q)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    timing.reset()
+    timing.enable(True)
+    for q in range(8):
+        step(q)
+    torch.cuda.synchronize()
+    timing.enable(False)
+    st = timing.summary()
+    timing.reset()
+    nnz = B * k
+    row = 4.0 * r
+    # algorithmic bytes: the forward gathers every sampled row of U once and
+    # reads the index, value and W, writing the residual; the backward fills
+    # dU (v r), gathers the rows again for dW and adds each entry's row into
+    # dU (read and write)
+    fwd_bytes = nnz * (row + 8.0) + 4.0 * r * B + 4.0 * nnz
+    bwd_bytes = 4.0 * v * r + nnz * (row + 8.0) + nnz * 2 * row + 4.0 * r * B
+    roofs = {}
+    for name, byts in (("masked_loss_fwd", fwd_bytes), ("masked_loss_bwd", bwd_bytes)):
+        q_ = st.get(name)
+        if q_:
+            avg_s = q_[0] * 1e-3 / q_[1]
+            ach = byts / avg_s / 1e9
+            roofs[name] = {"kernel": name, "bound": "hbm", "achieved": ach, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                           "frac": ach / PEAK_HBM_GBS, "avg_launch_ms": avg_s * 1e3, "launches_per_step": 1,
+                           "algorithmic_bytes_per_launch": byts, "traffic": None}
+    dom = max(roofs, key=lambda k_: roofs[k_]["avg_launch_ms"]) if roofs else None
+    print(json.dumps({
+        "metric": "masked-loss forward + backward steps/s, U 500,000 x 400, batches of 512 x 1,750 sampled entries",
+        "value": 1.0 / wall, "unit": "steps/s", "n_gpus": 1, "steps": steps, "warmup": a.warmup,
+        "ms_per_step": 1e3 * wall, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32 (f64 loss)", "data": "synthetic (GPU-drawn Gaussian X, U, W; seeded relabellings and sets)",
+        "config": {"workload": "masked subspace loss fwd+bwd over L = 100,000 relabellings (196 batches)", "v": v,
+                   "n": n, "r": r, "batch": B, "sampled": k, "L": L},
+        "relabellings_per_s": B / wall, "roofline": roofs.get(dom),
+        "rooflines_other_stages": {k_: v_ for k_, v_ in roofs.items() if k_ != dom}}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -350,7 +430,15 @@ def main():
                     help="only run RapidPT against NaivePT on Simulation Data I and II (accuracy sweep)")
     ap.add_argument("--studies", action="store_true",
                     help="only run the 16-study batched recovery workload (one JSON line of its own)")
+    ap.add_argument("--masked-loss", action="store_true",
+                    help="only run the masked-loss forward and backward at U 500,000 x 400 (one JSON line)")
     a = ap.parse_args()
+    if a.masked_loss:
+        if a.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        masked_loss_bench(a)
+        return
     if a.simulations:
         simulations(a)
         return

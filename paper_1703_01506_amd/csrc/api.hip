@@ -321,7 +321,11 @@ rpt_status train_track(int64_t v, int32_t n, int32_t n1, int32_t ell, int32_t r,
     // 3. GROUSE column by column (the paper's mode), one cooperative launch
     // per pass; the rest of the chip is free for whatever at_step starts
     for (int pp = 0; pp < passes; ++pp) {
-      if (at_step) RPT_TRY(at_step(pp, passes));
+      // whatever at_step starts goes out with the first pass, which leaves
+      // all but a few dozen compute units free while it runs: the stopping
+      // rule may end tracking after any pass, and work released with the
+      // later passes would then hold up the launches that follow
+      if (at_step && pp == 0) RPT_TRY(at_step(0, 1));
       RPT_TRY(grouse_pass_launch(t.g, U_out, v, r, T, v, omega_train + static_cast<int64_t>(pp) * ell * k, k, ell,
                                  gamma, pp, tol, objective, passes_used, t.info, opt, s));
       // span(B) is the tracked subspace: its orthonormal basis starts the next pass
@@ -636,8 +640,8 @@ rpt_status rpt_rapidpt_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
   st = stream_wait(sd, sd->mid, sd->st, s);  // the basis is ready for the tracking passes
   if (st_side == RPT_OK && st == RPT_OK && L_rec > 0)
     st_side = prep_launch(w.p, X, ldx, RPT_TAIL_SIGNED, kPrepRows | stat_flags(stat), sd->st);
-  // the sampled t of the recovered columns in one chunk per tracking pass,
-  // each released as that pass starts
+  // the sampled t of the recovered columns, released in chunks as the
+  // tracking steps start (column by column tracking: all with the first pass)
   int64_t done = 0;
   const std::function<rpt_status(int, int)> at_step = [&](int j, int steps) -> rpt_status {
     if (st_side != RPT_OK || L_rec == 0) return RPT_OK;

@@ -245,3 +245,7 @@ def test_bench_refuses_more_than_one_gpu():
                          text=True, timeout=120)
     assert out.returncode == 2
     assert "one GPU only" in out.stderr
+    for mode in ("--studies", "--masked-loss"):
+        out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), mode, "--gpus", "2"],
+                             capture_output=True, text=True, timeout=120)
+        assert out.returncode == 2 and "one GPU only" in out.stderr, mode

@@ -412,7 +412,10 @@ def test_rapidpt_end_to_end_gates():
     t_ref, t_gpu = OM.threshold(href, 0.05), OM.threshold(h, 0.05)
     assert abs(t_gpu - t_ref) <= 0.01 * abs(t_ref)
     print(f"max |h - h_oracle| = {np.abs(h - href).max():.3e}", flush=True)
-    np.testing.assert_allclose(h, href, atol=5e-3, rtol=0)
+    # every maximum: the basis after several passes differs from the FP64
+    # oracle's by the drift of the FP32 / split-BF16 trajectory (observed
+    # 6e-5 on both designs), so the bar is 5e-4
+    np.testing.assert_allclose(h, href, atol=5e-4, rtol=0)
 
 
 def test_masked_loss_forward_backward():
@@ -604,7 +607,10 @@ def test_rapidpt_end_to_end_wide_subjects():
     t_ref, t_gpu = OM.threshold(href, 0.05), OM.threshold(h, 0.05)
     assert abs(t_gpu - t_ref) <= 0.01 * abs(t_ref)
     print(f"max |h - h_oracle| = {np.abs(h - href).max():.3e}", flush=True)
-    np.testing.assert_allclose(h, href, atol=5e-3, rtol=0)
+    # every maximum: the basis after several passes differs from the FP64
+    # oracle's by the drift of the FP32 / split-BF16 trajectory (observed
+    # 6e-5 on both designs), so the bar is 5e-4
+    np.testing.assert_allclose(h, href, atol=5e-4, rtol=0)
 
 
 def test_empty_inputs_through_every_entry_point():
