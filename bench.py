@@ -40,7 +40,7 @@ TOL = 1e-3                     # stopping tolerance of the tracking passes (Sec.
 GOLDEN = os.path.join(ROOT, "tests", "golden", "train_full_n100_v250k.txt")
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "rapidpt_step_n100_v250k_hbm_traffic.md")
 STAGE_KERNEL = {"track_grouse": "grouse_coop_kernel", "complete": "complete_kernel", "complete_gram": "complete_gram_kernel",
-                "complete_solve": "complete_solve_kernel", "recon_fused": "recon_fused_kernel",
+                "complete_solve": "complete_cg_kernel", "recon_fused": "recon_fused_kernel",
                 "naive_contract": "naive_max_kernel", "sampled_t": "sampled_kernel",
                 "track_update": "track_apply_kernel", "reorth_gram": "gram_partial_kernel",
                 "reorth_apply": "apply_rinv_kernel", "reorth_chol": "chol_rinv_kernel",
@@ -309,14 +309,16 @@ def studies(a):
             "normals_per_s": normals / rb[1] / avg_s, "traffic": None}
     cs = st.get("complete_solve")
     if cs:
-        # FP64 Cholesky (r^3/3 multiply-adds) and two triangular solves (r^2)
-        # per recovered column, one launch per study
+        # the work of a direct (Cholesky) solve per recovered column, r^3/3
+        # multiply-adds and two triangular solves, one launch per study; the
+        # kernel solves by conjugate gradients
         avg_s = cs[0] * 1e-3 / cs[1]
         ach = solve_flops / cs[1] / avg_s / 1e12
         roofs["complete_solve"] = {
             "kernel": "complete_solve", "bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS,
             "unit": "TFLOP/s (fp64)", "frac": ach / PEAK_FP64_TFLOPS, "avg_launch_ms": avg_s * 1e3,
-            "launches_per_step": cs[1], "algorithmic_flops_per_launch": solve_flops / cs[1], "traffic": None}
+            "launches_per_step": cs[1], "algorithmic_flops_per_launch": solve_flops / cs[1],
+            "work": "flops of a Cholesky solve per column", "traffic": None}
     dom = max((k_ for k_ in st if st[k_] and k_ in roofs), key=lambda k_: st[k_][0], default=None)
     roof = roofs.get(dom)
     print(json.dumps({
@@ -752,13 +754,16 @@ def roofline_for(stage, ms_per_step, launches_per_step, v, n, L, ell, r, k, P):
                     "frac": ach / PEAK_HBM_GBS, "algorithmic_bytes_per_launch": byts})
         return out
     if stage == "complete_solve":
-        # FP64 Cholesky (r^3/3 multiply-adds) and two triangular solves (r^2)
-        # per recovered column, 2 flops per multiply-add; bound in practice by
-        # the dependent chain of each panel, not by this peak
+        # the work of a direct solve of each recovered column's r x r normal
+        # equations: FP64 Cholesky (r^3/3 multiply-adds) and two triangular
+        # solves (r^2), 2 flops per multiply-add.  The kernel solves by
+        # conjugate gradients (about 2 r^2 flops per iteration, 10-20
+        # iterations), a dependent chain far below this peak
         flops = Lr * 2.0 * (r ** 3 / 3.0 + r * r) / launches_per_step
         ach = flops / avg_s / 1e12
         out.update({"bound": "alu", "achieved": ach, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s (fp64)",
-                    "frac": ach / PEAK_FP64_TFLOPS, "algorithmic_flops_per_launch": flops})
+                    "frac": ach / PEAK_FP64_TFLOPS, "algorithmic_flops_per_launch": flops,
+                    "work": "flops of a Cholesky solve per column"})
         return out
     if stage == "recon_fused":
         # U w for every voxel of every training and recovered column, one

@@ -354,7 +354,10 @@ rpt_status rpt_sigma_mu(const float* X, int64_t v, int32_t n, int64_t ldx, int32
  *   stat      the statistic sampled (as rpt_naive_maxnull)          (in)
  *   max_out   L_rec FP32                                            (out)
  *   W_out     NULL or L_rec x r FP32 (the fitted coefficients)      (out)
- *   info      L_rec int32 (as rpt_complete)                         (out)
+ *   info      L_rec int32: 0, or the size + 1 of a sampled set with
+ *             fewer than r voxels, or -1 / -2 when the fit's conjugate
+ *             gradients met a non-positive curvature (a singular Gram
+ *             matrix) / did not converge; a failed fit has w = 0      (out)
  * Requirements: balanced designs; 1 <= r <= 128; r <= k.
  * ------------------------------------------------------------------------- */
 size_t rpt_recover_workspace(int64_t v, int32_t n, int64_t L_rec, int32_t r, int32_t k);
@@ -389,7 +392,8 @@ rpt_status rpt_recover_maxnull(const float* X, int64_t v, int32_t n, int64_t ldx
  *   h_out         l + L_rec FP32                                        (out)
  *   U_out         v x r FP32 trained basis                              (out)
  *   sigma_mu      2 FP32 on the device {sigma, mu}                      (out)
- *   train_info    l int32;  rec_info  L_rec int32 (as rpt_complete)     (out)
+ *   train_info    l int32 (as rpt_train_subspace);  rec_info  L_rec int32
+ *                 (as rpt_recover_maxnull)                          (out)
  *   objective, passes_used: as rpt_train_subspace                       (out)
  *   ws            rpt_rapidpt_workspace(v, n, l, L_rec, r, k, prec) bytes,
  *                 plus rpt_rapidpt_gen_workspace(n, l, L_rec, k, passes)
@@ -471,8 +475,8 @@ rpt_status rpt_gen_start_basis(uint64_t seed, int64_t v, int32_t r, float* U, vo
  *             distinct voxel indices (at least r of them for a solvable fit)
  *     omega_idx  int32 [nnz] voxel indices; nnz = omega_ptr[L_rec] must be
  *             passed as the host value `nnz`
- *     max_out  [L_rec] FP32 recovered maxima + mu;  info  [L_rec] int32, 0 or
- *             the failing pivot + 1 (a row with fewer than r entries fails)
+ *     max_out  [L_rec] FP32 recovered maxima + mu;  info  [L_rec] int32 as
+ *             rpt_recover_maxnull (a row with fewer than r entries fails)
  * Launches are only stream-ordered kernels on `stream` (no host
  * synchronisation, allocation or host reads of device memory), so the call
  * can be captured into a HIP graph.  The sampled-t and Complete steps of the

@@ -12,11 +12,13 @@
 // lower triangle in LDS with b^T appended as row r, so that the blocked
 // Cholesky of that trapezoid leaves z = L^{-1} b in row r; one blocked back
 // substitution gives w.  A non-positive pivot j sets info[i] = j + 1 and
-// w_i = 0.  Optionally the residual y - U_O w is written, and optionally each
+// w_i = 0.  (Recovery, with many columns and no residuals, solves by
+// conjugate gradients instead: see the split form below.)  Optionally the residual y - U_O w is written, and optionally each
 // sampled entry (i, q) of a solved column is pushed onto the list of its voxel
 // (lhead / lnext), so that a later pass can apply all entries of one voxel
 // together without floating-point atomics.
 #include "lds_linalg.h"
+#include "pcg.h"
 #include "rpt_internal.h"
 
 namespace rpt {
@@ -257,26 +259,14 @@ __global__ __launch_bounds__(kNT, (RB >= 8 ? 1 : 2)) void complete_kernel(Comple
 }
 
 // ---------------------------------------------------------------- split form
-// For many columns without residuals the two steps run as two kernels, so
-// that the latency-bound Cholesky does not hold the Gram step's registers and
-// the Gram step does not hold the Cholesky's LDS: the Gram kernel writes
-// G (FP32, rounded once from its exact FP64 sum of the wave partials) and b
-// (FP64) of every column to global memory; the solve kernel needs about
-// 54 KB of LDS at r = 100, three columns per compute unit.
+// For many columns without residuals (recovery) the two steps run as two
+// kernels: the Gram kernel writes G (FP32, rounded once from its exact FP64
+// sum of the wave partials) and b (FP64) of every column to global memory,
+// and the solve kernel (below) fits each column by conjugate gradients.
 __host__ __device__ inline int ntri_r(int r) { return r * (r + 1) / 2; }
 __host__ __device__ inline size_t gb_stride(int r) {  // bytes per column: G floats, then b doubles
   return ((static_cast<size_t>(ntri_r(r)) * sizeof(float) + 7) & ~static_cast<size_t>(7)) +
          static_cast<size_t>(r) * sizeof(double);
-}
-// Panel rows of r + 1 - kCb doubles: the trailing update's 16 x 16 tiles read up
-// to 15 entries past the panel, which land in dinv (r >= 17 whenever there is
-// a trailing update) and only feed tile rows and columns that are discarded.
-// w takes the panel's place once the factorisation is done.  At r = 100 this
-// is 52,896 bytes: three columns per compute unit.
-__host__ __device__ inline int solve_pld(int r) { return r + 1 - kCb > 1 ? r + 1 - kCb : 1; }
-inline size_t solve_smem(int r) {
-  const size_t pw = static_cast<size_t>(kCb) * solve_pld(r) > static_cast<size_t>(r) ? kCb * solve_pld(r) : r;
-  return (static_cast<size_t>(gsize(r)) + pw + static_cast<size_t>(r) + 4) * sizeof(double);
 }
 inline size_t gram_smem(int r) {
   return static_cast<size_t>(gsize(r)) * sizeof(double) + kIdx * (sizeof(int) + sizeof(float));
@@ -299,24 +289,71 @@ __global__ __launch_bounds__(kNT, 2) void complete_gram_kernel(CompleteArgs a, c
   for (int c = threadIdx.x; c < r; c += kNT) bo[c] = G[nt + c];                  // row r
 }
 
+// The recovery solve by conjugate gradients: G (packed lower FP32) is
+// stored whole in LDS and b (FP64) is the right-hand side of the
+// Jacobi-preconditioned conjugate gradients that the tracking pass also uses
+// (pcg.h); a well-conditioned r x r system takes 10 to 20 iterations, a
+// fraction of a Cholesky factorisation's dependent chain.  A set with fewer
+// than r voxels fails as the factorisation would (info = its size + 1);
+// non-positive curvature gives -1 and no convergence -2, with w = 0.
+struct CgVec {
+  double zv[kGR];
+  double mv[2][kGR];
+  double gv[kGR];  // b
+  double cgr[2][kGWaves][2];
+  double red[4][kGWaves];
+  int badf[kGWaves];
+  float zf[kGR];
+};
+__host__ __device__ inline size_t cg_smem(int rb) {
+  return ((sizeof(CgVec) + 15) & ~static_cast<size_t>(15)) + sizeof(float) * 16 * rb * g_hld(rb);
+}
+
 template <int RB>
-__global__ __launch_bounds__(kNT, 3) void complete_solve_kernel(CompleteArgs a, const char* gb) {
+__global__ __launch_bounds__(kNT, 2) void complete_cg_kernel(CompleteArgs a, const char* gb) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const int r = a.r, nt = ntri_r(r), pld = solve_pld(r);
-  double* G = reinterpret_cast<double*>(smem);
-  double* P = G + gsize(r);
-  double* dinv = P + (kCb * pld > r ? kCb * pld : r);
-  double* wv = P;  // the panel is dead once the factorisation is done
+  static_assert(kNT == kGT, "the solver's layout takes four waves");
+  constexpr int hld = g_hld(RB);
+  CgVec& sv = *reinterpret_cast<CgVec*>(smem);
+  float* H = reinterpret_cast<float*>(smem + ((sizeof(CgVec) + 15) & ~static_cast<size_t>(15)));
+  const int r = a.r;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int64_t i = blockIdx.x;
-  const int64_t base = a.optr ? a.optr[i] : i * a.k;
-  const int k = a.optr ? static_cast<int>(a.optr[i + 1] - base) : a.k;
+  const int k = a.optr ? static_cast<int>(a.optr[i + 1] - a.optr[i]) : a.k;
+  float* Wi = a.W + i * r;
+  if (k < r) {
+    for (int c = tid; c < r; c += kNT) Wi[c] = 0.0f;
+    if (tid == 0) a.info[i] = k + 1;
+    return;
+  }
   const float* gi = reinterpret_cast<const float*>(gb + i * gb_stride(r));
   const double* bi = reinterpret_cast<const double*>(gb + i * gb_stride(r) + gb_stride(r) -
                                                      static_cast<size_t>(r) * sizeof(double));
-  for (int t = threadIdx.x; t < nt; t += kNT) G[t] = static_cast<double>(gi[t]);
-  for (int c = threadIdx.x; c < r; c += kNT) G[nt + c] = bi[c];
+  // row `row` of the packed triangle is contiguous: one wave per row
+  for (int row = wave; row < r; row += kNW) {
+    const float* gr = gi + (row * (row + 1)) / 2;
+    for (int col = lane; col <= row; col += 64) {
+      const float g = gr[col];
+      H[row * hld + col] = g;
+      H[col * hld + row] = g;
+    }
+  }
+  for (int c = tid; c < kGR; c += kNT) {
+    sv.gv[c] = c < r ? bi[c] : 0.0;
+    sv.zv[c] = 0.0;
+  }
   __syncthreads();
-  solve_phase<RB>(a, i, base, k, G, P, pld, dinv, wv);
+  const int rq = lane >> 4, cb = lane & 15, rbase = 32 * wave + 8 * rq, myrow = rbase + (cb >> 1);
+  const int fail = pcg_solve<hld, true>(H, r, sv, lane, wave, rbase, cb, myrow, (cb & 1) == 0, myrow < r, sv.gv);
+  for (int c = tid; c < r; c += kNT) Wi[c] = fail ? 0.0f : sv.zf[c];
+  if (tid == 0) {
+    a.info[i] = fail ? -fail : 0;
+    if (a.wnorm2) {
+      double t = 0.0;
+      for (int c = 0; c < r; ++c) t = fma(sv.zv[c], sv.zv[c], t);
+      a.wnorm2[i] = fail ? 0.0f : static_cast<float>(t);
+    }
+  }
 }
 
 }  // namespace
@@ -338,7 +375,7 @@ rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, 
     reinterpret_cast<void*>(&K<7>), reinterpret_cast<void*>(&K<8>) }
   static void* const fused[8] = RPT_FNS(complete_kernel);
   static void* const gram[8] = RPT_FNS(complete_gram_kernel);
-  static void* const solve[8] = RPT_FNS(complete_solve_kernel);
+  static void* const solve[8] = RPT_FNS(complete_cg_kernel);
 #undef RPT_FNS
   static bool attr_set[8] = {};
   if (!attr_set[RB - 1]) {
@@ -347,7 +384,7 @@ rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, 
     (void)hipFuncSetAttribute(gram[RB - 1], hipFuncAttributeMaxDynamicSharedMemorySize,
                               static_cast<int>(gram_smem(kRMax)));
     (void)hipFuncSetAttribute(solve[RB - 1], hipFuncAttributeMaxDynamicSharedMemorySize,
-                              static_cast<int>(solve_smem(kRMax)));
+                              static_cast<int>(cg_smem(RB)));
     attr_set[RB - 1] = true;
   }
   hipError_t e = hipSuccess;
@@ -362,7 +399,7 @@ rpt_status complete_run(const float* U, int64_t v, int r, const int32_t* omega, 
     }
     if (e == hipSuccess) {
       RPT_STAGE("complete_solve", s);
-      e = hipLaunchKernel(solve[RB - 1], dim3(static_cast<unsigned>(L)), dim3(kNT), sa, solve_smem(r), s);
+      e = hipLaunchKernel(solve[RB - 1], dim3(static_cast<unsigned>(L)), dim3(kNT), sa, cg_smem(RB), s);
     }
   } else {
     RPT_STAGE("complete", s);
