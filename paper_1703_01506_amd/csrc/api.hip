@@ -189,7 +189,7 @@ TrainWs train_carve(void* ws, int64_t v, int n, int n1, int ell, int r, int k, i
   t.recon_ws = c.take<char>(recon_bytes(v, ell, r));
   t.lhead = c.take<int32_t>(v);
   t.lnext = c.take<int32_t>(static_cast<size_t>(ell) * k);
-  t.g = grouse_carve(c.take<char>(grouse_bytes(r, k)), r, k);
+  t.g = grouse_carve(c.take<char>(grouse_bytes(r, k, ell)), r, k, ell);
   t.WT = c.take<float>(static_cast<size_t>(ell) * r);
   t.dW = c.take<float>(static_cast<size_t>(ell) * r);
   t.optr = c.take<int64_t>(static_cast<size_t>(ell) + 1);

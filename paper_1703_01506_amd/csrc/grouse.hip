@@ -68,6 +68,7 @@ struct GrouseArgs {
   const float* T;        // training columns, row i = t map of column i
   int64_t ldT;
   const int32_t* omega;  // this pass's sampled sets, ell x k
+  const float* xo;       // their sampled values T[i][omega[i][q]], ell x k
   int k;
   int ell;
   float gamma;
@@ -300,14 +301,17 @@ __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
     }
     // ---------------------------------------------------------- 1. gather
     // local row lq = 32 m + j is sampled row q = 32 (wg + nwg m) + j
+    // (the index and the value of a sampled row are read together: the
+    // values were gathered into set order before the pass)
     const int32_t* om = a.omega + static_cast<int64_t>(i) * k;
-    const float* Ti = a.T + static_cast<int64_t>(i) * a.ldT;
+    const float* xi = a.xo + static_cast<int64_t>(i) * k;
     for (int lq = tid; lq < kCoopSlice * nsl; lq += kGT) {
       const int q = kCoopSlice * (wg + nwg * (lq / kCoopSlice)) + lq % kCoopSlice;
       const int64_t vox = q < k ? om[q] : -1;
+      const float xv = q < k ? xi[q] : 0.0f;
       const int vx = (vox >= 0 && vox < a.v) ? static_cast<int>(vox) : -1;
       svox[lq] = vx;
-      se[lq] = vx >= 0 ? Ti[vx] : 0.0f;  // x_q, later the residual
+      se[lq] = vx >= 0 ? xv : 0.0f;  // x_q, later the residual
     }
     __syncthreads();
     // rows into LDS as [B_q | x_q | 0 ...] up to column 16 RB (rows out of
@@ -772,6 +776,20 @@ __global__ __launch_bounds__(kGT) void grouse_coop_kernel(CoopArgs ca) {
   }
 }
 
+// the sampled values of a pass in set order, xo[i][q] = T[i][omega[i][q]]
+// (0 for an index out of range); skipped once tracking has converged
+__global__ __launch_bounds__(kBlock) void grouse_xo_kernel(const float* __restrict__ T, int64_t ldT,
+                                                           const int32_t* __restrict__ omega, int64_t n,
+                                                           int k, int64_t v, float* __restrict__ xo,
+                                                           const int32_t* stop, int pass) {
+  if (*stop < pass) return;
+  for (int64_t t = blockIdx.x * static_cast<int64_t>(kBlock) + threadIdx.x; t < n;
+       t += static_cast<int64_t>(gridDim.x) * kBlock) {
+    const int64_t i = t / k, vox = omega[t];
+    xo[t] = (vox >= 0 && vox < v) ? T[i * ldT + vox] : 0.0f;
+  }
+}
+
 __global__ void grouse_init_kernel(int32_t* stop, int32_t* used, double* objr, double* obj_out, int passes,
                                    uint32_t* ctr, int32_t* abort) {
   if (threadIdx.x == 0) {
@@ -806,9 +824,9 @@ rpt_status launch_coop(const CoopArgs& ca, int mode, size_t smem, hipStream_t s)
 
 }  // namespace
 
-size_t grouse_bytes(int r, int k) {
+size_t grouse_bytes(int r, int k, int ell) {
   Carver c(nullptr);
-  (void)k;
+  c.take<float>(static_cast<size_t>(ell) * k);
   const size_t nt = static_cast<size_t>(g_rb(r)) * (g_rb(r) + 1) / 2;
   c.take<float>(static_cast<size_t>(kCoopMaxWg) * nt * 256);
   c.take<float>(nt * 256);
@@ -821,10 +839,10 @@ size_t grouse_bytes(int r, int k) {
   return c.off;
 }
 
-GrouseState grouse_carve(void* ws, int r, int k) {
+GrouseState grouse_carve(void* ws, int r, int k, int ell) {
   Carver c(ws);
   GrouseState g;
-  (void)k;
+  g.xo = c.take<float>(static_cast<size_t>(ell) * k);
   const size_t nt = static_cast<size_t>(g_rb(r)) * (g_rb(r) + 1) / 2;
   g.part = c.take<float>(static_cast<size_t>(kCoopMaxWg) * nt * 256);
   g.hred = c.take<float>(nt * 256);
@@ -863,6 +881,7 @@ rpt_status grouse_pass_launch(const GrouseState& g, float* B, int64_t v, int r, 
   a.T = T;
   a.ldT = ldT;
   a.omega = omega;
+  a.xo = g.xo;
   a.k = k;
   a.ell = ell;
   a.gamma = gamma;
@@ -885,6 +904,14 @@ rpt_status grouse_pass_launch(const GrouseState& g, float* B, int64_t v, int r, 
   ca.spw = (nslices + ca.nwg - 1) / ca.nwg;
   const size_t smem = coop_lds(r, ca.spw);
   if (smem > kLdsMax) return RPT_ERR_UNSUPPORTED;
+  {
+    const int64_t n = static_cast<int64_t>(ell) * k;
+    int64_t blocks = (n + kBlock - 1) / kBlock;
+    if (blocks > 1024) blocks = 1024;
+    hipLaunchKernelGGL(grouse_xo_kernel, dim3(static_cast<unsigned>(blocks > 0 ? blocks : 1)), dim3(kBlock), 0, s, T,
+                       ldT, omega, n, k, v, g.xo, g.stop, pass);
+    RPT_CHECK_LAUNCH();
+  }
   RPT_STAGE("track_grouse", s);
   switch (g_rb(r)) {
     case 1: return launch_coop<1>(ca, mode, smem, s);

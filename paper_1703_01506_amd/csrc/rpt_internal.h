@@ -315,9 +315,10 @@ struct GrouseState {
   int32_t* stop = nullptr;
   int32_t* used_ws = nullptr;
   int32_t* rinfo = nullptr;  // status of the end-of-pass orthonormalisation
+  float* xo = nullptr;       // [ell][k] the pass's sampled values in set order
 };
-size_t grouse_bytes(int r, int k);
-GrouseState grouse_carve(void* ws, int r, int k);
+size_t grouse_bytes(int r, int k, int ell);
+GrouseState grouse_carve(void* ws, int r, int k, int ell);
 // stop <- none, passes used <- 0 (used: caller's device int, or the workspace's),
 // obj_out[0 .. passes) <- 0 when given
 rpt_status grouse_init_launch(const GrouseState& g, int32_t* used, double* obj_out, int passes, hipStream_t s);
