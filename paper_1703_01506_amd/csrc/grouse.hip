@@ -35,8 +35,10 @@
 //     row and a reduce-scatter over the 16 lanes of a DPP row).  The solve
 //     and the r x r updates below are identical in every workgroup, so z, w,
 //     the angle and N agree bit for bit without being exchanged.
-//  4. The residuals e = x_O - B_O z of its rows (from LDS) give a partial
-//     |e|^2; grid barrier; every workgroup adds the partials in one order.
+//  4. The residuals e = x_O - B_O z of its rows (from LDS); |e|^2 follows
+//     from H itself (x_O^T x_O - b^T z) unless the fit leaves less than a
+//     tenth of |x_O|^2, when the rows' partial sums are exchanged (grid
+//     barrier; every workgroup adds them in one order).
 //  5. w = N z, the angle, u = N^T wh and the rank-one update of N (each
 //     lane keeps its 8 x 8 block of N, the layout of H, in registers); then
 //     each workgroup writes B[q] + (s / |e|) e_q (u / c)^T for its rows;
@@ -47,7 +49,7 @@
 // by the same rank-one updates).
 // A single workgroup would gather the 875 rows of a step at about 20 GB/s;
 // spread over 28 workgroups the gathers overlap and the step is bounded by
-// the solve and the four barriers.  The Eq. 1 objective of the pass, the
+// the solve and the three barriers.  The Eq. 1 objective of the pass, the
 // sum over its visits of |e|^2 before U moves, decides when tracking has
 // converged.
 #include <type_traits>
