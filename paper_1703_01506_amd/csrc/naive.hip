@@ -40,17 +40,27 @@ namespace {
 
 struct NaiveArgs {
   const uint16_t* kb16;
+  const uint16_t* kbm;
   const float* kb32;
   const float* kb32sq;
   const float2* cst;
   const float2* cstg;
   const uint8_t* labels;
   int64_t vpad, v, vt, L;
-  int n, n1, tpc, pg, abs_tail, store;
+  int n, n1, tpc, pg, abs_tail, store, mixr;
   float fs, tm;
   float* partial;
   float* T_out;
 };
+
+// label byte j of a relabelling row as a flag: 0 past n or for a row beyond
+// L.  The load itself is unconditional (clamped index, and a row beyond L
+// reads row 0), so that a lane's many label loads are issued back to back
+// instead of each waiting behind a branch of its own.
+__device__ __forceinline__ bool in_group1(const uint8_t* lab, int j, int n, bool valid) {
+  const uint8_t b = lab[j < n ? j : n - 1];
+  return valid && j < n && b != 0;
+}
 
 __device__ __forceinline__ void block_coords(const NaiveArgs& a, int pt, int& chunk, int64_t& pbase) {
   const int b = blockIdx.x, xcd = b & 7, j = b >> 3;
@@ -86,8 +96,8 @@ __global__ __launch_bounds__(kBlock) void naive_split_kernel(NaiveArgs a) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int j0 = 16 * s + 8 * h + 2 * q;
-        const unsigned b0 = (valid && j0 < a.n && lab[j0]) ? 0x3F80u : 0u;
-        const unsigned b1 = (valid && j0 + 1 < a.n && lab[j0 + 1]) ? 0x3F80u : 0u;
+        const unsigned b0 = in_group1(lab, j0, a.n, valid) ? 0x3F80u : 0u;
+        const unsigned b1 = in_group1(lab, j0 + 1, a.n, valid) ? 0x3F80u : 0u;
         w[q] = b0 | (b1 << 16);
       }
       I[p][s] = u32x4{w[0], w[1], w[2], w[3]};
@@ -175,7 +185,11 @@ __global__ __launch_bounds__(kBlock) void naive_split_kernel(NaiveArgs a) {
 // per tile) and every wave reads its fragments from there: the four waves
 // share one copy instead of fetching it four times through the vector memory
 // path.
-template <int KS, int PT, bool ABS>
+// MIX (R = n mod 16 in 1..8): the last, partial K step packs the hi and the
+// lo half of its R subjects into one 16-wide block (hi at positions 0..R-1,
+// lo at R..2R-1), paired with an indicator fragment that repeats the R
+// indicators, so that step takes one MFMA instead of two.
+template <int KS, int PT, bool ABS, bool MIX>
 __global__ __launch_bounds__(kBlock, 2) void naive_max_kernel(NaiveArgs a) {
   __shared__ __align__(16) uint16_t xs[2][KS][2][64 * 8];
   typedef __attribute__((address_space(3))) void lds_void;
@@ -185,38 +199,81 @@ __global__ __launch_bounds__(kBlock, 2) void naive_max_kernel(NaiveArgs a) {
   int64_t pbase;
   block_coords(a, PT, chunk, pbase);
 
-  // indicator fragments (B operand): lane supplies I[relabelling pbase + 32p + col][subject 16s + 8h + 0..7]
+  // indicator fragments (B operand): lane supplies I[relabelling pbase + 32p + col][subject 16s + 8h + 0..7].
+  // The label rows are staged through the data buffer (unused until the
+  // first tile), two relabelling tiles per wave at a time: a wave's 64 rows
+  // are n x 64 contiguous bytes, copied with 16-byte loads, after which each
+  // lane reads its flags in pairs (n is even on this path, so a pair is one
+  // aligned 2-byte read).  Reading them straight from global memory, one byte
+  // and one wait at a time, cost about a seventh of the launch.
+  static_assert(PT % 2 == 0, "labels are staged two relabelling tiles per wave at a time");
   u32x4 I[PT][KS];
+  {
+    uint8_t* st = reinterpret_cast<uint8_t*>(&xs[0][0][0][0]);  // 4096 KS bytes >= 256 n
+    const int64_t nbytes = a.L * a.n;
+    const int run = 64 * a.n;  // bytes per wave and round; a multiple of 16
+    const int64_t wg0 = pbase - static_cast<int64_t>(wave) * (PT * 32);
+    const bool al16 = (reinterpret_cast<uintptr_t>(a.labels) & 15) == 0;
 #pragma unroll
-  for (int p = 0; p < PT; ++p) {
-    const int64_t perm = pbase + p * 32 + col;
-    const bool valid = perm < a.L;
-    const uint8_t* lab = a.labels + (valid ? perm : 0) * a.n;
+    for (int rd = 0; rd < PT / 2; ++rd) {
+      if (rd > 0) __syncthreads();  // every wave has read the previous round
+      for (int c = threadIdx.x; c < 4 * (run / 16); c += kBlock) {
+        const int w = c / (run / 16), off = (c - w * (run / 16)) * 16;
+        const int64_t g = (wg0 + w * (PT * 32) + rd * 64) * a.n + off;
+        u32x4 v = u32x4{0u, 0u, 0u, 0u};
+        if (al16 && g + 16 <= nbytes) {
+          v = *reinterpret_cast<const u32x4*>(a.labels + g);
+        } else {
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      unsigned w[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int j0 = 16 * s + 8 * h + 2 * q;
-        const unsigned b0 = (valid && j0 < a.n && lab[j0]) ? 0x3F80u : 0u;
-        const unsigned b1 = (valid && j0 + 1 < a.n && lab[j0 + 1]) ? 0x3F80u : 0u;
-        w[q] = b0 | (b1 << 16);
+          for (int e = 0; e < 16; ++e)
+            if (g + e < nbytes) v[e >> 2] |= static_cast<unsigned>(a.labels[g + e]) << (8 * (e & 3));
+        }
+        *reinterpret_cast<u32x4*>(st + w * run + off) = v;
       }
-      I[p][s] = u32x4{w[0], w[1], w[2], w[3]};
+      __syncthreads();
+#pragma unroll
+      for (int pp = 0; pp < 2; ++pp) {
+        const int p = 2 * rd + pp;
+        const bool valid = pbase + p * 32 + col < a.L;
+        const uint8_t* row = st + (wave * 64 + pp * 32 + col) * a.n;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          unsigned w[4];
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            // block position kappa holds subject 16 s + kappa; under MIX the
+            // last step's position kappa holds subject 16 s + kappa (hi,
+            // kappa < R) or 16 s + kappa - R (lo, R <= kappa < 2 R); R is
+            // even, so a pair of positions is a pair of consecutive subjects
+            const int k0 = 8 * h + 2 * q;
+            int j0 = 16 * s + k0;
+            if (MIX && s == KS - 1) j0 = k0 < a.mixr ? 16 * s + k0 : (k0 < 2 * a.mixr ? 16 * s + k0 - a.mixr : a.n);
+            const unsigned pr = (valid && j0 < a.n) ? *reinterpret_cast<const uint16_t*>(row + j0) : 0u;
+            w[q] = ((pr & 0xFFu) ? 0x3F80u : 0u) | ((pr >> 8) ? 0x3F800000u : 0u);
+          }
+          I[p][s] = u32x4{w[0], w[1], w[2], w[3]};
+        }
+      }
     }
+    __syncthreads();  // every wave has its fragments before the tile copies reuse the buffer
   }
 
   const int64_t t0 = static_cast<int64_t>(chunk) * a.tpc;
   const int64_t t1 = t0 + a.tpc < a.vt ? t0 + a.tpc : a.vt;
   const size_t kstride = static_cast<size_t>(a.vpad) * 32;  // uint16 per K step
+  // 1 KB blocks per tile: hi and lo of every K step, or under MIX hi and lo
+  // of the KS - 1 full steps and the mixed block (into xs[b][KS - 1][0])
+  constexpr int NB = MIX ? 2 * KS - 1 : 2 * KS;
   // copy of tile t into buffer b: wave w moves the 1 KB blocks j = w, w + 4, ...
   auto issue = [&](int b, int64_t t) {
 #pragma unroll
-    for (int j = 0; j < 2 * KS; j += 4) {
+    for (int j = 0; j < NB; j += 4) {
       const int jj = j + wave;
-      if (jj < 2 * KS) {
+      if (jj < NB) {
         const int s = jj >> 1, hl = jj & 1;
-        const uint16_t* g = a.kb16 + s * kstride + static_cast<size_t>(t) * 32 * 32 + hl * 512 + lane * 8;
+        const uint16_t* g = (MIX && jj == NB - 1)
+                                ? a.kbm + static_cast<size_t>(t) * 32 * 16 + lane * 8
+                                : a.kb16 + s * kstride + static_cast<size_t>(t) * 32 * 32 + hl * 512 + lane * 8;
         __builtin_amdgcn_global_load_lds((gbl_void*)g, (lds_void*)&xs[b][s][hl][0], 16, 0, 0);
       }
     }
@@ -237,14 +294,25 @@ __global__ __launch_bounds__(kBlock, 2) void naive_max_kernel(NaiveArgs a) {
     f32x16 acc[PT];
 #pragma unroll
     for (int p = 0; p < PT; ++p) acc[p] = f32x16{};
+    // block j (hi / lo of step j / 2, or the mixed block) multiplies the
+    // indicator of step j / 2; block j + 1 is read from LDS while block j's
+    // MFMAs run
+    u32x4 cur = *reinterpret_cast<const u32x4*>(&xs[b][0][0][lane * 8]);
 #pragma unroll
-    for (int s = 0; s < KS; ++s) {
-      const u32x4 xh = *reinterpret_cast<const u32x4*>(&xs[b][s][0][lane * 8]);
-      const u32x4 xl = *reinterpret_cast<const u32x4*>(&xs[b][s][1][lane * 8]);
+    for (int j = 0; j < NB; ++j) {
+      u32x4 nxt;
+      if (j + 1 < NB) nxt = *reinterpret_cast<const u32x4*>(&xs[b][(j + 1) >> 1][(j + 1) & 1][lane * 8]);
 #pragma unroll
-      for (int p = 0; p < PT; ++p) acc[p] = mfma_bf16(xh, I[p][s], acc[p]);
+      for (int p = 0; p < PT; ++p) acc[p] = mfma_bf16(cur, I[p][j >> 1], acc[p]);
+      if (j + 1 < NB) cur = nxt;
+    }
+    // schedule: reads of blocks 0 and 1, then block j's MFMAs followed by
+    // the read of block j + 2
+    __builtin_amdgcn_sched_group_barrier(0x100, 2, 0);
 #pragma unroll
-      for (int p = 0; p < PT; ++p) acc[p] = mfma_bf16(xl, I[p][s], acc[p]);
+    for (int j = 0; j < NB; ++j) {
+      __builtin_amdgcn_sched_group_barrier(0x008, PT, 0);
+      if (j + 2 < NB) __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
 #pragma unroll
     for (int p = 0; p < PT; ++p) {
@@ -306,14 +374,11 @@ __global__ __launch_bounds__(kBlock, 2) void naive_wide_kernel(NaiveArgs a) {
     const int p = idx / (64 * ks), rem = idx - p * 64 * ks, c = rem / (2 * ks), g = rem - c * 2 * ks;
     const int64_t perm = pbase + p * 32 + c;
     unsigned bits = 0;
-    if (perm < a.L) {
-      const uint8_t* lab = a.labels + perm * a.n;
+    const bool valid = perm < a.L;
+    const uint8_t* lab = a.labels + (valid ? perm : 0) * a.n;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int j = 8 * g + i;
-        if (j < a.n && lab[j]) bits |= 1u << i;
-      }
-    }
+    for (int i = 0; i < 8; ++i)
+      if (in_group1(lab, 8 * g + i, a.n, valid)) bits |= 1u << i;
     lb[wave][p][c][g] = static_cast<uint8_t>(bits);
   }
 
@@ -429,7 +494,7 @@ __global__ __launch_bounds__(kBlock) void naive_f32_kernel(NaiveArgs a) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int j = 8 * s + 2 * q + h;
-        f[q] = (valid && j < a.n && lab[j]) ? 1.0f : 0.0f;
+        f[q] = in_group1(lab, j, a.n, valid) ? 1.0f : 0.0f;
       }
       A[p][s] = f32x4{f[0], f[1], f[2], f[3]};
     }
@@ -547,22 +612,24 @@ __global__ __launch_bounds__(kBlock) void naive_finalize_kernel(const float* __r
 // T-storing launches use naive_split_kernel (PT = 1), max-only launches
 // naive_max_kernel (PT = 4)
 template <int PT, int KS>
-void* split_ptr(int abs_tail, int store) {
+void* split_ptr(int abs_tail, int store, int mix) {
   if (store) return abs_tail ? reinterpret_cast<void*>(&naive_split_kernel<KS, 1, true, true>)
                              : reinterpret_cast<void*>(&naive_split_kernel<KS, 1, false, true>);
-  return abs_tail ? reinterpret_cast<void*>(&naive_max_kernel<KS, 4, true>)
-                  : reinterpret_cast<void*>(&naive_max_kernel<KS, 4, false>);
+  if (mix) return abs_tail ? reinterpret_cast<void*>(&naive_max_kernel<KS, 4, true, true>)
+                           : reinterpret_cast<void*>(&naive_max_kernel<KS, 4, false, true>);
+  return abs_tail ? reinterpret_cast<void*>(&naive_max_kernel<KS, 4, true, false>)
+                  : reinterpret_cast<void*>(&naive_max_kernel<KS, 4, false, false>);
 }
 template <int PT, int KSB, bool U>
 void* f32_ptr() { return reinterpret_cast<void*>(&naive_f32_kernel<KSB, PT, U>); }
 
 template <int PT>
-void* pick_split(int ks, int at, int st) {
+void* pick_split(int ks, int at, int st, int mx) {
   switch (ks) {
-    case 1: return split_ptr<PT, 1>(at, st); case 2: return split_ptr<PT, 2>(at, st);
-    case 3: return split_ptr<PT, 3>(at, st); case 4: return split_ptr<PT, 4>(at, st);
-    case 5: return split_ptr<PT, 5>(at, st); case 6: return split_ptr<PT, 6>(at, st);
-    case 7: return split_ptr<PT, 7>(at, st); case 8: return split_ptr<PT, 8>(at, st);
+    case 1: return split_ptr<PT, 1>(at, st, mx); case 2: return split_ptr<PT, 2>(at, st, mx);
+    case 3: return split_ptr<PT, 3>(at, st, mx); case 4: return split_ptr<PT, 4>(at, st, mx);
+    case 5: return split_ptr<PT, 5>(at, st, mx); case 6: return split_ptr<PT, 6>(at, st, mx);
+    case 7: return split_ptr<PT, 7>(at, st, mx); case 8: return split_ptr<PT, 8>(at, st, mx);
     default: return nullptr;
   }
 }
@@ -623,6 +690,8 @@ rpt_status naive_launch(const PrepX& p, const NaivePlan& pl, const uint8_t* labe
   if (L == 0) return RPT_OK;
   NaiveArgs a;
   a.kb16 = p.kb16;
+  a.kbm = nullptr;
+  a.mixr = 0;
   a.kb32 = p.kb32;
   a.kb32sq = p.kb32sq;
   a.cst = p.cst;
@@ -651,7 +720,12 @@ rpt_status naive_launch(const PrepX& p, const NaivePlan& pl, const uint8_t* labe
                  : (a.abs_tail ? reinterpret_cast<void*>(&naive_wide_kernel<2, true, false>)
                                : reinterpret_cast<void*>(&naive_wide_kernel<2, false, false>));
   } else if (prec == RPT_SPLIT_BF16) {
-    fn = pick_split<0>(p.ksteps, a.abs_tail, a.store);
+    // split designs are balanced, so n is even (the max-only kernel reads
+    // label flags in pairs)
+    if (p.n & 1) return RPT_ERR_UNSUPPORTED;
+    a.kbm = p.kbm;
+    a.mixr = p.mixr;
+    fn = pick_split<0>(p.ksteps, a.abs_tail, a.store, p.kbm != nullptr && !a.store);
   } else {
     fn = unbal ? pick_f32<2, true>(p.ksteps) : pick_f32<2, false>(p.ksteps);
   }

@@ -27,6 +27,10 @@
 //         hi block then the lo block, each in MFMA fragment order: lane
 //         L = 32 h + c holds x''[voxel 32 t + c][subject 16 s + 8 h + 0..7]
 //         (0 past n), so a wave's fragment is one contiguous 1 KB
+//   kbm   [vpad / 32][64][8] bf16, when R = n mod 16 is 1..8: the last K
+//         step as one mixed block, position kappa = hi of subject
+//         16 (ks - 1) + kappa for kappa < R, lo of subject 16 (ks - 1) +
+//         kappa - R for R <= kappa < 2 R, 0 beyond; same lane order
 //   kb32  [ks][vpad][2][4] f32 subject 8s+2q+h at [s][k][h][q]
 //   rows  [vpad][ldn] f32      standardised rows, for the sampled statistics
 //   cst   [vpad] (rinv, -S/2 * rinv)       cstg [vpad] (S, Q)
@@ -157,6 +161,38 @@ __global__ __launch_bounds__(kBlock) void prep_kernel(const float* __restrict__ 
       }
     }
   }
+  if (p.kbm) {
+    // the mixed K block: position kappa < R holds hi of subject 16 F + kappa,
+    // R <= kappa < 2 R lo of subject 16 F + kappa - R (F full steps), then 0;
+    // lane L = 32 h + c holds positions 8 h .. 8 h + 7 of voxel 32 t + c
+    const int R = p.mixr, F = n / 16;
+    for (int idx = tid; idx < 2 * TILE; idx += kBlock) {
+      const int rr = idx >> 1, h = idx & 1;
+      if (rr < nv) {
+        uint32_t w[4];
+#pragma unroll
+        for (int e2 = 0; e2 < 4; ++e2) {
+          uint32_t pr = 0;
+#pragma unroll
+          for (int hl = 0; hl < 2; ++hl) {
+            const int kap = 8 * h + 2 * e2 + hl;
+            uint16_t val = 0;
+            if (kap < 2 * R) {
+              const int j = 16 * F + (kap < R ? kap : kap - R);
+              const float f = static_cast<float>(static_cast<double>(xs[rr][j]) * fold_c[rr] + fold_d[rr]);
+              const uint16_t hi = f2bf(f);
+              val = kap < R ? hi : f2bf(f - bf2f(hi));
+            }
+            pr |= static_cast<uint32_t>(val) << (16 * hl);
+          }
+          w[e2] = pr;
+        }
+        const int64_t vx = v0 + rr;
+        u32x4* d = reinterpret_cast<u32x4*>(p.kbm + (vx & ~int64_t(31)) * 16 + (h * 32 + (vx & 31)) * 8);
+        *d = u32x4{w[0], w[1], w[2], w[3]};
+      }
+    }
+  }
   if (p.kb32) {
     // per K block: TILE voxels x 8 floats = 2 TILE chunks of 16 bytes
     for (int s = 0; s < p.ksteps; ++s) {
@@ -203,6 +239,10 @@ PrepX prep_carve(Carver& c, int64_t v, int n, int n1, int flags) {
   if (flags & kPrepSplit) {
     p.ksteps = static_cast<int>(ceil_div(n, 16));
     p.kb16 = c.take<uint16_t>(static_cast<size_t>(p.ksteps) * p.vpad * 32);
+    if (p.ksteps <= 8 && n % 16 >= 1 && n % 16 <= 8) {
+      p.mixr = n % 16;
+      p.kbm = c.take<uint16_t>(static_cast<size_t>(p.vpad) * 16);
+    }
   } else if (flags & kPrepF32) {
     p.ksteps = static_cast<int>(ceil_div(n, 8));
     p.kb32 = c.take<float>(static_cast<size_t>(p.ksteps) * p.vpad * 8);

@@ -157,6 +157,9 @@ struct PrepX {
   int n = 0, n1 = 0;
   int ksteps = 0;            // split: 16-wide K blocks; f32: 8-subject blocks
   uint16_t* kb16 = nullptr;  // split: [ksteps][vpad][2][16] bf16 (hi block, lo block)
+  uint16_t* kbm = nullptr;   // split, R = n mod 16 in 1..8: per 32-voxel tile the mixed
+                             // K block [hi of the last R subjects | their lo | 0]
+  int mixr = 0;              // R when kbm is written, else 0
   float* kb32 = nullptr;     // f32:   [ksteps][vpad][2][4]   (subject 8s+2q+h)
   float* kb32sq = nullptr;   // f32 unbalanced: same layout, squared values
   float* rows = nullptr;     // [vpad][ldn] standardised rows (sampled t)

@@ -100,6 +100,26 @@ def test_naive_tiny_edge_cases():
             assert_t_close(_run(torch, X, labels, n // 2, "signed", prec), ref, prec, f"max n={n} v={v}", m=n // 2)
 
 
+@pytest.mark.parametrize("n", [18, 24, 30, 32, 100, 120, 122])
+@pytest.mark.parametrize("tail", ["signed", "abs"])
+def test_naive_split_max_tail_step(n, tail):
+    """Max-only split-BF16 launch for every kind of last K step (balanced, so n
+    is even): R = n mod 16 of 2..8 packs hi and lo of the last R subjects into
+    one mixed block (n = 18, 24, 100, 120), R of 10..14 keeps two blocks
+    (n = 30, 122), R = 0 has no partial step (n = 32); ragged voxel and
+    relabelling tiles, maxima against the oracle's full T."""
+    torch = torch_cuda()
+    announce(f"naive split max n={n} tail={tail}")
+    rng = np.random.default_rng(100 + n)
+    v, L = 1531, 389
+    X = (rng.normal(size=(v, n)) * rng.uniform(0.5, 2.0, size=(v, 1)) + rng.normal(size=(v, 1)) * 3).astype(np.float32)
+    labels = S.relabellings(L, n, n // 2, seed=n + 7)
+    Tref = OT.tmatrix(X.astype(np.float64), labels)
+    ref = np.abs(Tref).max(axis=1) if tail == "abs" else Tref.max(axis=1)
+    got = _run(torch, X, labels, n // 2, tail, "split_bf16")
+    assert_t_close(got, ref, "split", f"max n={n}", m=n // 2)
+
+
 @pytest.mark.parametrize("prec", ["split_bf16", "fp32"])
 def test_naive_full_size_sampled(prec):
     """n = 100 (50/50), v = 250,000 smoothed (FWHM 3) volume, L = 10,000 in the
