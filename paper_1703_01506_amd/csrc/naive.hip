@@ -191,7 +191,11 @@ __global__ __launch_bounds__(kBlock) void naive_split_kernel(NaiveArgs a) {
 // indicators, so that step takes one MFMA instead of two.
 template <int KS, int PT, bool ABS, bool MIX>
 __global__ __launch_bounds__(kBlock, 2) void naive_max_kernel(NaiveArgs a) {
-  __shared__ __align__(16) uint16_t xs[2][KS][2][64 * 8];
+  // the label rows of the workgroup (n <= 16 KS bytes each), then the two
+  // data tile buffers, share one LDS allocation
+  constexpr int kLabBytes = 4 * PT * 32 * 16 * KS, kTileBytes = 2 * KS * 2 * 64 * 8 * 2;
+  __shared__ __align__(16) uint8_t smem[kLabBytes > kTileBytes ? kLabBytes : kTileBytes];
+  uint16_t (&xs)[2][KS][2][64 * 8] = *reinterpret_cast<uint16_t (*)[2][KS][2][64 * 8]>(smem);
   typedef __attribute__((address_space(3))) void lds_void;
   typedef const __attribute__((address_space(1))) void gbl_void;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, h = lane >> 5, col = lane & 31;
@@ -200,62 +204,54 @@ __global__ __launch_bounds__(kBlock, 2) void naive_max_kernel(NaiveArgs a) {
   block_coords(a, PT, chunk, pbase);
 
   // indicator fragments (B operand): lane supplies I[relabelling pbase + 32p + col][subject 16s + 8h + 0..7].
-  // The label rows are staged through the data buffer (unused until the
-  // first tile), two relabelling tiles per wave at a time: a wave's 64 rows
-  // are n x 64 contiguous bytes, copied with 16-byte loads, after which each
-  // lane reads its flags in pairs (n is even on this path, so a pair is one
-  // aligned 2-byte read).  Reading them straight from global memory, one byte
-  // and one wait at a time, cost about a seventh of the launch.
-  static_assert(PT % 2 == 0, "labels are staged two relabelling tiles per wave at a time");
+  // The workgroup's label rows (4 PT 32 relabellings, one contiguous range of
+  // 128 PT n bytes) are first copied into LDS with 16-byte loads, in the
+  // space the data tiles take afterwards; each lane then reads its flags in
+  // pairs (n is even on this path, so a pair is one aligned 2-byte read).
+  // Reading them straight from global memory, one byte and one wait at a
+  // time, cost about a seventh of the launch.
   u32x4 I[PT][KS];
   {
-    uint8_t* st = reinterpret_cast<uint8_t*>(&xs[0][0][0][0]);  // 4096 KS bytes >= 256 n
     const int64_t nbytes = a.L * a.n;
-    const int run = 64 * a.n;  // bytes per wave and round; a multiple of 16
-    const int64_t wg0 = pbase - static_cast<int64_t>(wave) * (PT * 32);
+    const int64_t g0 = (pbase - static_cast<int64_t>(wave) * (PT * 32)) * a.n;  // 16-byte multiple
+    const int span = 4 * PT * 32 * a.n;                                          // <= sizeof smem
     const bool al16 = (reinterpret_cast<uintptr_t>(a.labels) & 15) == 0;
+    for (int off = 16 * threadIdx.x; off < span; off += 16 * kBlock) {
+      const int64_t g = g0 + off;
+      u32x4 v = u32x4{0u, 0u, 0u, 0u};
+      if (al16 && g + 16 <= nbytes) {
+        v = *reinterpret_cast<const u32x4*>(a.labels + g);
+      } else {
 #pragma unroll
-    for (int rd = 0; rd < PT / 2; ++rd) {
-      if (rd > 0) __syncthreads();  // every wave has read the previous round
-      for (int c = threadIdx.x; c < 4 * (run / 16); c += kBlock) {
-        const int w = c / (run / 16), off = (c - w * (run / 16)) * 16;
-        const int64_t g = (wg0 + w * (PT * 32) + rd * 64) * a.n + off;
-        u32x4 v = u32x4{0u, 0u, 0u, 0u};
-        if (al16 && g + 16 <= nbytes) {
-          v = *reinterpret_cast<const u32x4*>(a.labels + g);
-        } else {
-#pragma unroll
-          for (int e = 0; e < 16; ++e)
-            if (g + e < nbytes) v[e >> 2] |= static_cast<unsigned>(a.labels[g + e]) << (8 * (e & 3));
-        }
-        *reinterpret_cast<u32x4*>(st + w * run + off) = v;
+        for (int e = 0; e < 16; ++e)
+          if (g + e < nbytes) v[e >> 2] |= static_cast<unsigned>(a.labels[g + e]) << (8 * (e & 3));
       }
-      __syncthreads();
+      *reinterpret_cast<u32x4*>(smem + off) = v;
+    }
+    __syncthreads();
 #pragma unroll
-      for (int pp = 0; pp < 2; ++pp) {
-        const int p = 2 * rd + pp;
-        const bool valid = pbase + p * 32 + col < a.L;
-        const uint8_t* row = st + (wave * 64 + pp * 32 + col) * a.n;
+    for (int p = 0; p < PT; ++p) {
+      const bool valid = pbase + p * 32 + col < a.L;
+      const uint8_t* row = smem + ((wave * PT + p) * 32 + col) * a.n;
 #pragma unroll
-        for (int s = 0; s < KS; ++s) {
-          unsigned w[4];
+      for (int s = 0; s < KS; ++s) {
+        unsigned w[4];
 #pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            // block position kappa holds subject 16 s + kappa; under MIX the
-            // last step's position kappa holds subject 16 s + kappa (hi,
-            // kappa < R) or 16 s + kappa - R (lo, R <= kappa < 2 R); R is
-            // even, so a pair of positions is a pair of consecutive subjects
-            const int k0 = 8 * h + 2 * q;
-            int j0 = 16 * s + k0;
-            if (MIX && s == KS - 1) j0 = k0 < a.mixr ? 16 * s + k0 : (k0 < 2 * a.mixr ? 16 * s + k0 - a.mixr : a.n);
-            const unsigned pr = (valid && j0 < a.n) ? *reinterpret_cast<const uint16_t*>(row + j0) : 0u;
-            w[q] = ((pr & 0xFFu) ? 0x3F80u : 0u) | ((pr >> 8) ? 0x3F800000u : 0u);
-          }
-          I[p][s] = u32x4{w[0], w[1], w[2], w[3]};
+        for (int q = 0; q < 4; ++q) {
+          // block position kappa holds subject 16 s + kappa; under MIX the
+          // last step's position kappa holds subject 16 s + kappa (hi,
+          // kappa < R) or 16 s + kappa - R (lo, R <= kappa < 2 R); R is even,
+          // so a pair of positions is a pair of consecutive subjects
+          const int k0 = 8 * h + 2 * q;
+          int j0 = 16 * s + k0;
+          if (MIX && s == KS - 1) j0 = k0 < a.mixr ? 16 * s + k0 : (k0 < 2 * a.mixr ? 16 * s + k0 - a.mixr : a.n);
+          const unsigned pr = (valid && j0 < a.n) ? *reinterpret_cast<const uint16_t*>(row + j0) : 0u;
+          w[q] = ((pr & 0xFFu) ? 0x3F80u : 0u) | ((pr >> 8) ? 0x3F800000u : 0u);
         }
+        I[p][s] = u32x4{w[0], w[1], w[2], w[3]};
       }
     }
-    __syncthreads();  // every wave has its fragments before the tile copies reuse the buffer
+    __syncthreads();  // every wave has its fragments before the tile copies reuse the space
   }
 
   const int64_t t0 = static_cast<int64_t>(chunk) * a.tpc;
