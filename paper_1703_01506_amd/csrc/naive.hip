@@ -650,9 +650,12 @@ NaivePlan naive_plan(int64_t v, int64_t L, int n, int prec, bool store, int forc
   NaivePlan pl;
   // split max-only path: 4 relabelling tiles per wave (data shared through
   // LDS, two waves per SIMD); the split T-writing path 1 (its data tiles
-  // stay in registers, so one tile keeps two waves per SIMD); the FP32 path
-  // and the wide-subject path 2.
-  pl.pt = (prec == RPT_SPLIT_BF16 && n <= 128) ? (store ? 1 : 4) : 2;
+  // stay in registers, so one tile keeps two waves per SIMD); the wide-subject
+  // path 2; the FP32 path 1 (its indicator, accumulators and per-row running
+  // maxima of two tiles took 288 registers, one wave per SIMD, and every
+  // data load then waited out its latency: 7.2 -> 5.0 ms balanced, 12.9 ->
+  // 10.5 ms unbalanced at n = 100, v = 250k, L = 10k).
+  pl.pt = (prec == RPT_SPLIT_BF16 && n <= 128) ? (store ? 1 : 4) : (prec == RPT_SPLIT_BF16 ? 2 : 1);
   pl.vt = round_up(v, 32) / 32;
   const int64_t group = 4 * pl.pt * 32;
   pl.pg = static_cast<int>(ceil_div(L > 0 ? L : 1, group));
@@ -723,7 +726,7 @@ rpt_status naive_launch(const PrepX& p, const NaivePlan& pl, const uint8_t* labe
     a.mixr = p.mixr;
     fn = pick_split<0>(p.ksteps, a.abs_tail, a.store, p.kbm != nullptr && !a.store);
   } else {
-    fn = unbal ? pick_f32<2, true>(p.ksteps) : pick_f32<2, false>(p.ksteps);
+    fn = unbal ? pick_f32<1, true>(p.ksteps) : pick_f32<1, false>(p.ksteps);
   }
   if (!fn) return RPT_ERR_UNSUPPORTED;
   const unsigned blocks = static_cast<unsigned>(pl.pg) * static_cast<unsigned>(pl.nc);
