@@ -331,15 +331,18 @@ __global__ __launch_bounds__(kBlock, 2) void naive_max_kernel(NaiveArgs a) {
 
 // ----------------------------------------------------------------------------
 // split-BF16, balanced, more than 128 subjects (up to 512: 32 K steps).  The
-// K steps are taken kWideKC at a time: each 32-voxel tile's chunk of K steps
-// (hi and lo, 2 KB per step) is copied once per workgroup into LDS with
-// global_load_lds, double-buffered over the (tile, chunk) sequence.  The
-// indicator of a wave's relabellings is kept in LDS as bits, eight subjects per
-// byte, and expanded to a BF16 fragment when it is used: two indicator bits
-// x become the 32-bit pair ((x | x << 15) & 0x10001) * 0x3F80.  Relabellings
+// K steps are taken kWideKC at a time for two consecutive 32-voxel tiles:
+// the chunk (hi and lo, 2 KB per step and tile) is copied once per workgroup
+// into LDS with global_load_lds, double-buffered over the (tile pair, chunk)
+// sequence.  The indicator of a wave's relabellings is kept in LDS as bits,
+// eight subjects per byte, and expanded to a BF16 fragment when it is used,
+// once for both tiles (expanding it per tile took more VALU issue than the
+// MFMAs it fed): two indicator bits x become the 32-bit pair
+// ((x | x << 15) & 0x10001) * 0x3F80.  Relabellings
 // are the MFMA rows (A operand), voxels the columns; the same kernel keeps
 // running maxima and, in STORE mode, writes t for every element.
-constexpr int kWideKC = 8;      // K steps per staged chunk
+constexpr int kWideNT = 2;      // voxel tiles per unit
+constexpr int kWideKC = 4;      // K steps per staged chunk
 constexpr int kWideNMax = 512;  // subjects
 
 __device__ __forceinline__ u32x4 indicator_frag(unsigned byte) {
@@ -354,7 +357,9 @@ __device__ __forceinline__ u32x4 indicator_frag(unsigned byte) {
 
 template <int PT, bool ABS, bool STORE>
 __global__ __launch_bounds__(kBlock, 2) void naive_wide_kernel(NaiveArgs a) {
-  __shared__ __align__(16) uint16_t xs[2][kWideKC][2][64 * 8];
+  // a unit is one K chunk of kWideNT voxel tiles, so that each indicator
+  // fragment expanded from its bits serves the MFMAs of all of them
+  __shared__ __align__(16) uint16_t xs[2][kWideNT][kWideKC][2][64 * 8];
   __shared__ uint8_t lb[4][PT][32][kWideNMax / 8];
   typedef __attribute__((address_space(3))) void lds_void;
   typedef const __attribute__((address_space(1))) void gbl_void;
@@ -381,17 +386,19 @@ __global__ __launch_bounds__(kBlock, 2) void naive_wide_kernel(NaiveArgs a) {
   const int64_t t0 = static_cast<int64_t>(chunk) * a.tpc;
   const int64_t t1 = t0 + a.tpc < a.vt ? t0 + a.tpc : a.vt;
   const size_t kstride = static_cast<size_t>(a.vpad) * 32;  // uint16 per K step
-  // copy of K chunk c of tile t into buffer b: wave w moves the 1 KB blocks
-  // j = w, w + 4, ... (block j: K step 8c + j / 2, hi or lo)
-  auto issue = [&](int b, int64_t t, int c) {
+  // copy of K chunk c of the tiles tp .. tp + kWideNT - 1 (those below t1)
+  // into buffer b: wave w moves the 1 KB blocks j = w, w + 4, ... (block j:
+  // tile j / (2 kWideKC), K step kWideKC c + (j / 2) mod kWideKC, hi or lo)
+  auto issue = [&](int b, int64_t tp, int c) {
     const int s0 = c * kWideKC, nks = ks - s0 < kWideKC ? ks - s0 : kWideKC;
+    const int ntl = t1 - tp < kWideNT ? static_cast<int>(t1 - tp) : kWideNT;
 #pragma unroll
-    for (int j = 0; j < 2 * kWideKC; j += 4) {
-      const int jj = j + wave;
-      if (jj < 2 * nks) {
-        const int s = jj >> 1, hl = jj & 1;
-        const uint16_t* g = a.kb16 + (s0 + s) * kstride + static_cast<size_t>(t) * 32 * 32 + hl * 512 + lane * 8;
-        __builtin_amdgcn_global_load_lds((gbl_void*)g, (lds_void*)&xs[b][s][hl][0], 16, 0, 0);
+    for (int j = 0; j < 2 * kWideNT * kWideKC; j += 4) {
+      const int jj = j + wave, tt = jj / (2 * kWideKC), s = (jj >> 1) % kWideKC, hl = jj & 1;
+      if (tt < ntl && s < nks) {
+        const uint16_t* g =
+            a.kb16 + (s0 + s) * kstride + static_cast<size_t>(tp + tt) * 32 * 32 + hl * 512 + lane * 8;
+        __builtin_amdgcn_global_load_lds((gbl_void*)g, (lds_void*)&xs[b][tt][s][hl][0], 16, 0, 0);
       }
     }
   };
@@ -402,50 +409,66 @@ __global__ __launch_bounds__(kBlock, 2) void naive_wide_kernel(NaiveArgs a) {
   for (int p = 0; p < PT; ++p)
 #pragma unroll
     for (int e = 0; e < 16; ++e) rm[p][e] = init;
-  f32x16 acc[PT];
+  f32x16 acc[kWideNT][PT];
 #pragma unroll
-  for (int p = 0; p < PT; ++p) acc[p] = f32x16{};
-  const int64_t npair = (t1 - t0) * nkc;
-  if (npair > 0) issue(0, t0, 0);
-  for (int64_t i = 0; i < npair; ++i) {
-    const int64_t t = t0 + i / nkc;
+  for (int tt = 0; tt < kWideNT; ++tt)
+#pragma unroll
+    for (int p = 0; p < PT; ++p) acc[tt][p] = f32x16{};
+  // running maxima (and t in STORE mode) of tile t from its accumulators
+  auto finish = [&](f32x16 (&ac)[PT], int64_t t) {
+    const int64_t vox = t * 32 + col;
+#pragma unroll
+    for (int p = 0; p < PT; ++p) {
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const float u = ac[p][e];
+        rm[p][e] = fmaxf(rm[p][e], ABS ? fabsf(u) : u);
+        if (STORE) {
+          const int64_t perm = pbase + p * 32 + mfma_row(e, h);
+          if (perm < a.L && vox < a.v) a.T_out[perm * a.v + vox] = t_from_u_f(u, a.fs, a.tm);
+        }
+      }
+      ac[p] = f32x16{};
+    }
+  };
+  const int64_t nunit = (t1 - t0 + kWideNT - 1) / kWideNT * nkc;
+  if (nunit > 0) issue(0, t0, 0);
+  for (int64_t i = 0; i < nunit; ++i) {
+    const int64_t tp = t0 + kWideNT * (i / nkc);
     const int c = static_cast<int>(i % nkc);
     const int b = static_cast<int>(i & 1);
+    const int ntl = t1 - tp < kWideNT ? static_cast<int>(t1 - tp) : kWideNT;
     // this wave's copies have landed; after the barrier every wave's have
     // (and the indicator bytes are written), and every wave is done with
     // the other buffer
     __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
-    if (i + 1 < npair) issue(b ^ 1, t0 + (i + 1) / nkc, static_cast<int>((i + 1) % nkc));
+    if (i + 1 < nunit) issue(b ^ 1, t0 + kWideNT * ((i + 1) / nkc), static_cast<int>((i + 1) % nkc));
     const int s0 = c * kWideKC, nks = ks - s0 < kWideKC ? ks - s0 : kWideKC;
 #pragma unroll
     for (int s = 0; s < kWideKC; ++s) {
       if (s < nks) {
-        const u32x4 xh = *reinterpret_cast<const u32x4*>(&xs[b][s][0][lane * 8]);
-        const u32x4 xl = *reinterpret_cast<const u32x4*>(&xs[b][s][1][lane * 8]);
+        u32x4 ind[PT];
 #pragma unroll
-        for (int p = 0; p < PT; ++p) {
-          const u32x4 ind = indicator_frag(lb[wave][p][col][2 * (s0 + s) + h]);
-          acc[p] = mfma_bf16(ind, xh, acc[p]);
-          acc[p] = mfma_bf16(ind, xl, acc[p]);
+        for (int p = 0; p < PT; ++p) ind[p] = indicator_frag(lb[wave][p][col][2 * (s0 + s) + h]);
+#pragma unroll
+        for (int tt = 0; tt < kWideNT; ++tt) {
+          if (tt < ntl) {
+            const u32x4 xh = *reinterpret_cast<const u32x4*>(&xs[b][tt][s][0][lane * 8]);
+            const u32x4 xl = *reinterpret_cast<const u32x4*>(&xs[b][tt][s][1][lane * 8]);
+#pragma unroll
+            for (int p = 0; p < PT; ++p) {
+              acc[tt][p] = mfma_bf16(ind[p], xh, acc[tt][p]);
+              acc[tt][p] = mfma_bf16(ind[p], xl, acc[tt][p]);
+            }
+          }
         }
       }
     }
     if (c == nkc - 1) {
-      const int64_t vox = t * 32 + col;
 #pragma unroll
-      for (int p = 0; p < PT; ++p) {
-#pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          const float u = acc[p][e];
-          rm[p][e] = fmaxf(rm[p][e], ABS ? fabsf(u) : u);
-          if (STORE) {
-            const int64_t perm = pbase + p * 32 + mfma_row(e, h);
-            if (perm < a.L && vox < a.v) a.T_out[perm * a.v + vox] = t_from_u_f(u, a.fs, a.tm);
-          }
-        }
-        acc[p] = f32x16{};
-      }
+      for (int tt = 0; tt < kWideNT; ++tt)
+        if (tt < ntl) finish(acc[tt], tp + tt);
     }
   }
 #pragma unroll
