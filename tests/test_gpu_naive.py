@@ -120,6 +120,31 @@ def test_naive_split_max_tail_step(n, tail):
     assert_t_close(got, ref, "split", f"max n={n}", m=n // 2)
 
 
+@pytest.mark.parametrize("n", [36, 100])
+def test_naive_labels_unaligned_view(n):
+    """Labels passed as a row-offset view (its first byte n bytes into the
+    allocation, not 16-byte aligned) take the bytewise staging path of the
+    max-only kernel; the maxima must equal, bit for bit, those of an aligned
+    copy, and both must match the oracle."""
+    torch = torch_cuda()
+    import paper_1703_01506_amd as rpt
+    announce(f"naive unaligned labels n={n}")
+    rng = np.random.default_rng(300 + n)
+    v, L = 1100, 700
+    X = (rng.normal(size=(v, n)) * rng.uniform(0.5, 2.0, size=(v, 1))).astype(np.float32)
+    labels = S.relabellings(L + 1, n, n // 2, seed=n + 3)
+    Xd = torch.from_numpy(X).cuda()
+    Lfull = torch.from_numpy(labels).cuda()
+    view = Lfull[1:]
+    assert view.data_ptr() % 16 != 0
+    got_view = rpt.naive_maxnull(Xd, view).cpu().numpy()
+    got_copy = rpt.naive_maxnull(Xd, view.clone()).cpu().numpy()
+    torch.cuda.synchronize()
+    assert np.array_equal(got_view, got_copy)
+    ref = OT.naive_maxnull(X.astype(np.float64), labels[1:])
+    assert_t_close(got_view, ref, "split", f"max n={n}", m=n // 2)
+
+
 @pytest.mark.parametrize("prec", ["split_bf16", "fp32"])
 def test_naive_full_size_sampled(prec):
     """n = 100 (50/50), v = 250,000 smoothed (FWHM 3) volume, L = 10,000 in the
