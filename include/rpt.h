@@ -51,7 +51,7 @@ typedef enum {
   RPT_ERR_NOT_SPD = -3,         /* (device info code) Gram not positive def. */
   RPT_ERR_WORKSPACE = -4,       /* ws NULL, misaligned or too small         */
   RPT_ERR_HIP = -5,             /* a HIP launch failed; see rpt_last_hip_error */
-  RPT_ERR_UNSUPPORTED = -6      /* valid request this build does not handle  */
+  RPT_ERR_UNSUPPORTED = -6      /* valid request the library does not handle */
 } rpt_status;
 
 /* Arithmetic of the dense contractions (indicator GEMM of NaivePT and the
